@@ -1,0 +1,220 @@
+"""Seeded tetrahedral meshes: a structured Kuhn base mesh and its graded
+refinement by tagged (Maubach) newest-vertex bisection.
+
+This module produces inputs only (vertex coordinates and tetrahedra). It
+holds no finite-element arithmetic: no basis functions, quadrature,
+assembly or prolongation. Both the CPU checker and the GPU library derive
+those from the arrays returned here.
+
+The paper discretises on shape-regular, conforming tetrahedral meshes whose
+coarsest level is a uniform mesh of 24576 tetrahedra (= 16^3 cubes x 6,
+Section 4) refined locally toward the nuclei (Section 2, AFEM). The graded
+meshes here follow that shape: a Kuhn cube mesh, then conforming bisection
+wherever the longest edge of a tetrahedron exceeds a target size that grows
+with the distance to the nearest nucleus. Every fine tetrahedron lies inside
+exactly one base tetrahedron, so the base mesh is a nested coarse mesh.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+# Kuhn subdivision of the unit cube: one tetrahedron per permutation of the
+# axes, x0 = corner (0,0,0), x_{k} = x_{k-1} + e_{perm[k-1]}, x3 = (1,1,1).
+_PERMS = list(itertools.permutations(range(3)))
+
+
+def kuhn_mesh(n, lo, hi):
+    """Structured Kuhn mesh of the box [lo,hi]^3 with n^3 cubes.
+
+    Returns (xyz float64 (V,3), tets int64 (6 n^3, 4)). Vertices are numbered
+    lexicographically, x fastest: id = i + (n+1) j + (n+1)^2 k. Every tet is
+    stored in Kuhn order (x0, x1, x2, x3) with x0-x3 the cube diagonal, which
+    is the tag-3 vertex order that tagged bisection starts from.
+    """
+    n = int(n)
+    g = np.linspace(lo, hi, n + 1)
+    k, j, i = np.meshgrid(np.arange(n + 1), np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    xyz = np.stack([g[i.ravel()], g[j.ravel()], g[k.ravel()]], axis=1)
+
+    def vid(ii, jj, kk):
+        return ii + (n + 1) * (jj + (n + 1) * kk)
+
+    ci, cj, ck = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ci, cj, ck = ci.ravel(), cj.ravel(), ck.ravel()
+    tets = []
+    for perm in _PERMS:
+        off = np.zeros((4, 3), dtype=np.int64)
+        for s in range(1, 4):
+            off[s] = off[s - 1]
+            off[s, perm[s - 1]] += 1
+        tets.append(np.stack([vid(ci + off[s, 0], cj + off[s, 1], ck + off[s, 2]) for s in range(4)], axis=1))
+    # order: cube-major, then permutation
+    tets = np.stack(tets, axis=1).reshape(-1, 4).astype(np.int64)
+    return xyz, tets
+
+
+class _Bisector:
+    """Conforming tagged bisection (Maubach) of a Kuhn mesh, vectorised.
+
+    A tagged tet (x0,x1,x2,x3; k) is cut at the midpoint z of edge x0-xk into
+      (x0..x_{k-1}, z, x_{k+1}..x3) and (x1..x_k, z, x_{k+1}..x3),
+    both tagged k-1 (or 3 after tag 1). Starting from Kuhn order with tag 3
+    the refinement of neighbouring tets is compatible, and closing every
+    hanging edge by further bisection yields a conforming mesh.
+    """
+
+    def __init__(self, xyz, tets):
+        self.xyz = [np.asarray(xyz, dtype=np.float64)]
+        self.nv = len(xyz)
+        self.tets = np.asarray(tets, dtype=np.int64).copy()
+        self.tags = np.full(len(tets), 3, dtype=np.int8)
+        self.mid_keys = np.zeros(0, dtype=np.int64)  # sorted edge keys
+        self.mid_ids = np.zeros(0, dtype=np.int64)
+        self.key_base = np.int64(1) << np.int64(31)
+
+    def _key(self, a, b):
+        lo = np.minimum(a, b)
+        hi = np.maximum(a, b)
+        return lo * self.key_base + hi
+
+    def coords(self):
+        if len(self.xyz) > 1:
+            self.xyz = [np.concatenate(self.xyz, axis=0)]
+        return self.xyz[0]
+
+    def bisect(self, mask):
+        idx = np.nonzero(mask)[0]
+        if len(idx) == 0:
+            return 0
+        T = self.tets[idx]
+        k = self.tags[idx].astype(np.int64)
+        a = T[:, 0]
+        b = T[np.arange(len(idx)), k]
+        keys = self._key(a, b)
+        # look up existing midpoints, create the missing ones
+        pos = np.searchsorted(self.mid_keys, keys)
+        pos_c = np.minimum(pos, max(len(self.mid_keys) - 1, 0))
+        found = (len(self.mid_keys) > 0) & (self.mid_keys[pos_c] == keys) if len(self.mid_keys) else np.zeros(len(keys), bool)
+        new_keys, inv = np.unique(keys[~found], return_inverse=True)
+        mids = np.empty(len(keys), dtype=np.int64)
+        if len(self.mid_keys):
+            mids[found] = self.mid_ids[pos_c[found]]
+        if len(new_keys):
+            lo = new_keys // self.key_base
+            hi = new_keys % self.key_base
+            X = self.coords()
+            newxyz = 0.5 * (X[lo] + X[hi])
+            new_ids = self.nv + np.arange(len(new_keys), dtype=np.int64)
+            self.nv += len(new_keys)
+            self.xyz.append(newxyz)
+            mids[~found] = new_ids[inv]
+            allk = np.concatenate([self.mid_keys, new_keys])
+            alli = np.concatenate([self.mid_ids, new_ids])
+            order = np.argsort(allk, kind="stable")
+            self.mid_keys = allk[order]
+            self.mid_ids = alli[order]
+        z = mids
+        c1 = np.empty_like(T)
+        c2 = np.empty_like(T)
+        for kk in (1, 2, 3):
+            s = k == kk
+            if not np.any(s):
+                continue
+            Ts = T[s]
+            zs = z[s]
+            # child 1: (x0..x_{k-1}, z, x_{k+1}..x3)
+            ch1 = Ts.copy()
+            ch1[:, kk] = zs
+            # child 2: (x1..x_k, z, x_{k+1}..x3)
+            ch2 = np.empty_like(Ts)
+            ch2[:, :kk] = Ts[:, 1:kk + 1]
+            ch2[:, kk] = zs
+            ch2[:, kk + 1:] = Ts[:, kk + 1:]
+            c1[s] = ch1
+            c2[s] = ch2
+        newtag = np.where(k > 1, k - 1, 3).astype(np.int8)
+        keep = np.ones(len(self.tets), dtype=bool)
+        keep[idx] = False
+        self.tets = np.concatenate([self.tets[keep], c1, c2], axis=0)
+        self.tags = np.concatenate([self.tags[keep], newtag, newtag])
+        return len(idx)
+
+    def hanging(self):
+        """Mask of tets that own an edge whose midpoint already exists."""
+        if len(self.mid_keys) == 0:
+            return np.zeros(len(self.tets), dtype=bool)
+        T = self.tets
+        hang = np.zeros(len(T), dtype=bool)
+        for (p, q) in ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)):
+            keys = self._key(T[:, p], T[:, q])
+            pos = np.searchsorted(self.mid_keys, keys)
+            pos = np.minimum(pos, len(self.mid_keys) - 1)
+            hang |= self.mid_keys[pos] == keys
+        return hang
+
+    def close(self, max_rounds=1000):
+        for _ in range(max_rounds):
+            h = self.hanging()
+            if not np.any(h):
+                return
+            self.bisect(h)
+        raise RuntimeError("bisection closure did not terminate")
+
+
+def _longest_edge(xyz, tets):
+    P = xyz[tets]
+    h2 = np.zeros(len(tets))
+    for (p, q) in ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)):
+        d = P[:, p] - P[:, q]
+        h2 = np.maximum(h2, np.einsum("ij,ij->i", d, d))
+    return np.sqrt(h2)
+
+
+def _refine_to(B, C, h0, kappa, h_min, h_max, max_levels=200):
+    for _ in range(max_levels):
+        X = B.coords()
+        cen = X[B.tets].mean(axis=1)
+        d = np.full(len(cen), np.inf)
+        for c in C:
+            d = np.minimum(d, np.linalg.norm(cen - c, axis=1))
+        target = np.clip(h0 + kappa * d, h_min, h_max)
+        mark = _longest_edge(X, B.tets) > target * (1.0 + 1e-12)
+        if not np.any(mark):
+            return
+        B.bisect(mark)
+        B.close()
+
+
+def graded_mesh(n_base, lo, hi, centres, h0, kappa, h_min, h_max=np.inf, coarse=None):
+    """Kuhn base mesh refined until every tet satisfies
+    longest_edge <= clip(h0 + kappa * d(centroid), h_min, h_max), d = distance
+    of the centroid to the nearest centre.
+
+    coarse: None (the coarse mesh is the Kuhn base) or a tuple
+    (h0, kappa, h_min, h_max) of a first, milder grading; the fine mesh then
+    refines that graded mesh further, so the two meshes stay nested.
+    Returns (xyz, tets, coarse_xyz, coarse_tets). Coarse vertices keep their
+    ids in the fine mesh.
+    """
+    bxyz, btets = kuhn_mesh(n_base, lo, hi)
+    B = _Bisector(bxyz, btets)
+    C = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
+    if coarse is not None:
+        _refine_to(B, C, *coarse)
+    cxyz = B.coords().copy()
+    ctets = B.tets.copy()
+    _refine_to(B, C, h0, kappa, h_min, h_max)
+    X = B.coords()
+    return X.copy(), B.tets.copy(), cxyz, ctets
+
+
+def boundary_mask(xyz, lo, hi, tol=1e-12):
+    """Vertices on the box boundary (where the homogeneous Dirichlet condition
+    applies). Pure geometry of the input box."""
+    on = np.zeros(len(xyz), dtype=bool)
+    for ax in range(3):
+        on |= np.abs(xyz[:, ax] - lo) <= tol * max(1.0, abs(lo))
+        on |= np.abs(xyz[:, ax] - hi) <= tol * max(1.0, abs(hi))
+    return on
