@@ -1,0 +1,218 @@
+/*
+ * mlc.h -- C ABI of the MI355X library for the fine-mesh correction step of the
+ * multilevel-correction adaptive finite element method for the Kohn-Sham
+ * equation (Hu, Xie, Xu, "On accelerating a multilevel correction adaptive
+ * finite element method for Kohn-Sham equation").
+ *
+ * One call of mlc_correction_step performs one outer iteration l -> l+1 of
+ * Algorithm 1 (steps 5-7) on a fixed pair of nested meshes:
+ *   - density and exchange-correlation potential of Phi^l at the quadrature
+ *     points (Section 4, LDA / X-alpha; frozen during the inner loop as the
+ *     remark after eq. (gdef) requires),
+ *   - N auxiliary linear problems (eq. Aux_Linear_Problem), solved together
+ *     by a multi-right-hand-side Jacobi-preconditioned CG on the GPU,
+ *   - the Hartree direction (eq. W_h_equation) with multipole Dirichlet data
+ *     (remark after Algorithm 3),
+ *   - the fine-mesh integrals of Algorithm 3 step 1 (eqs. Adef, bdef, Ah4def,
+ *     betadef, rhsdef, Hartree_H_h, FG),
+ *   - the inner Hartree iteration of Algorithm 2 in the small augmented
+ *     spaces (Algorithm 3 step 2), in FP64 on the host,
+ *   - reconstruction phi_i = phi_{i,H} + theta_{2,i} u_i (Algorithm 3 step 3),
+ *     the Hartree potential and the density.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns mlc_status; MLC_OK is 0. Nothing throws across
+ *     the ABI. On failure mlc_last_error(ctx) describes the cause; the context
+ *     keeps its previous state (except MLC_ERR_NOT_CONVERGED, where the last
+ *     iterate is kept and the report is filled).
+ *   - Host arrays passed in are copied before the call returns; the caller
+ *     keeps ownership. Host output arrays are written by the library and must
+ *     be large enough for the documented size.
+ *   - Device memory: the library never allocates device memory. The caller
+ *     allocates one workspace of mlc_workspace_bytes() bytes on the GPU that
+ *     the context runs on and passes it to mlc_bind(), together with the HIP
+ *     stream all work is enqueued on. The workspace must outlive the context's
+ *     use of it. Calls that return host data synchronise that stream.
+ *   - DoF numbering seen by callers: the fine (coarse) degrees of freedom are
+ *     the vertices of the fine (coarse) mesh that do not lie on the box
+ *     boundary, in increasing vertex index. Orbital blocks are row-major
+ *     n_dof x N (orbital index fastest). Internally the library reorders the
+ *     fine DoFs for memory locality and undoes it on output.
+ *   - One context is used from one host thread at a time.
+ */
+#ifndef MLC_H
+#define MLC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MLC_OK = 0,
+  MLC_ERR_ARG = -1,           /* null pointer, size or enum out of range      */
+  MLC_ERR_MESH = -2,          /* degenerate tet, index out of range, no DoF   */
+  MLC_ERR_NOT_NESTED = -3,    /* a fine vertex lies outside the coarse mesh   */
+  MLC_ERR_WORKSPACE = -4,     /* workspace missing or too small               */
+  MLC_ERR_HIP = -5,           /* a HIP runtime call failed                    */
+  MLC_ERR_NOT_CONVERGED = -6, /* CG hit cg_maxit before cg_rtol               */
+  MLC_ERR_BREAKDOWN = -7,     /* CG curvature p^T A p <= 0                    */
+  MLC_ERR_NONFINITE = -8,     /* NaN/Inf detected in a result                 */
+  MLC_ERR_STATE = -9,         /* call order: not bound, no state, ...         */
+  MLC_WARN_INNER_MAXIT = 1    /* inner iteration stopped at inner_maxit       */
+} mlc_status;
+
+/* Potentials of the external field (Section 2 defines the bare Coulomb one). */
+enum { MLC_POT_ERF = 0,       /* -sum Z_k erf(|x-R_k|/rc)/|x-R_k|             */
+       MLC_POT_BARE = 1,      /* -sum Z_k/|x-R_k|                             */
+       MLC_POT_HARMONIC = 2   /* 0.5 omega^2 |x|^2 (no nuclei needed)         */ };
+/* Exchange-correlation (Section 4). */
+enum { MLC_XC_NONE = 0, MLC_XC_LDA = 1 /* Slater + Perdew-Zunger 81 */, MLC_XC_XALPHA = 2 };
+
+/* A P1 tetrahedral mesh of the box [box_lo, box_hi]^3 (host arrays).
+ * xyz: n_vertices x 3 doubles; tets: n_tets x 4 vertex indices. */
+typedef struct {
+  int64_t n_vertices;
+  const double* xyz;
+  int64_t n_tets;
+  const int32_t* tets;
+} mlc_mesh;
+
+/* The physical system (Section 2): M nuclei with charges Z at R, N orbitals
+ * with occupation numbers f_i (rho = sum f_i phi_i^2). */
+typedef struct {
+  int32_t n_nuclei;
+  const double* R;            /* n_nuclei x 3 */
+  const double* Z;            /* n_nuclei     */
+  int32_t potential;          /* MLC_POT_*    */
+  double rc;                  /* smoothing radius of MLC_POT_ERF */
+  double omega;               /* MLC_POT_HARMONIC frequency      */
+  int32_t n_orbitals;         /* N, 1..MLC_MAX_ORBITALS           */
+  const double* occupations;  /* N */
+  int32_t xc;                 /* MLC_XC_* */
+  double xalpha;              /* alpha of X-alpha (0.77298 in Section 4) */
+  int32_t hartree;            /* 1: Hartree term present, 0: absent */
+  double box_lo, box_hi;      /* homogeneous Dirichlet on the box faces */
+} mlc_system;
+
+#define MLC_MAX_ORBITALS 128
+
+typedef struct {
+  double cg_rtol;       /* per-orbital ||b - A x||_2 <= cg_rtol ||b||_2       */
+  int32_t cg_maxit;
+  int32_t check_every;  /* CG iterations between host convergence checks     */
+  int32_t shift;        /* 0: step 5 exactly as printed; 1: add sigma M       */
+  double sigma0;        /* shift = sigma0 - min V_eff when shift = 1          */
+  double poisson_rtol;  /* Hartree direction CG tolerance                     */
+  int32_t inner_maxit;  /* Algorithm 2 iteration cap                          */
+  double inner_tol;     /* Algorithm 2 stop: ||Phi^{s+1} - Phi^s||_{H^1}      */
+  int32_t n_extra;      /* candidates = lowest min(N_H+1, N + n_extra) pairs  */
+  int32_t reorder;      /* 1: Morton order of fine DoFs (default)            */
+  int32_t time_kernels; /* 1: HIP events around every SpMM launch            */
+} mlc_options;
+
+/* Filled by mlc_correction_step. Times in milliseconds. */
+typedef struct {
+  int32_t cg_iters_max, cg_iters_sum, poisson_iters, inner_iters;
+  double cg_relres_max;       /* max over orbitals, true residual at exit   */
+  double poisson_relres;
+  double inner_last_diff;     /* last ||Phi^{s+1}-Phi^s||_{H^1}             */
+  double sigma;               /* shift used in step 5                       */
+  double theta1;              /* Hartree coefficient of w0                  */
+  double max_offdiag_overlap; /* max_{i!=j} |(phi_i, phi_j)|                */
+  double rho_integral;        /* int rho = electron count                   */
+  double energy;              /* sum f lambda - 1/2 int w rho + int rho (eps_xc - v_xc^l) */
+  double t_fine_ms;           /* device: density..Gram blocks (steps 5, 6, Alg. 3 step 1) */
+  double t_inner_ms;          /* host: Algorithm 2 / Algorithm 3 step 2     */
+  double t_recon_ms;          /* device: reconstruction and diagnostics     */
+  double t_spmm_ms;           /* sum of SpMM kernel times (time_kernels=1)  */
+  int64_t n_spmm;             /* SpMM launches in this step                 */
+  int64_t spmm_rows;          /* rows x columns processed by those launches */
+  int64_t spmm_cols_sum;
+} mlc_step_report;
+
+typedef struct mlc_ctx mlc_ctx;
+
+/* Fill *opt with defaults: cg_rtol 1e-10, cg_maxit 20000, check_every 25,
+ * shift 1, sigma0 1, poisson_rtol 1e-12, inner_maxit 500, inner_tol 1e-10,
+ * n_extra 8, reorder 1, time_kernels 0. */
+void mlc_options_default(mlc_options* opt);
+
+/* Build a context: validates both meshes (positive volumes, indices in range,
+ * at least one interior vertex), locates every fine vertex in the coarse mesh
+ * (MLC_ERR_NOT_NESTED if one lies outside), builds the fine CSR pattern, the
+ * prolongation P (coarse hat functions at fine vertices, Section 3.2) and the
+ * grouping of fine tets by coarse parent. Host work only. */
+mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys,
+                      const mlc_options* opt, mlc_ctx** out);
+
+/* Sizes: fine interior DoFs, coarse interior DoFs, fine vertices, N. */
+mlc_status mlc_sizes(const mlc_ctx* ctx, int64_t* n_dof, int64_t* n_coarse_dof, int64_t* n_vertices,
+                     int32_t* n_orbitals);
+
+/* Device workspace size in bytes for this context. */
+mlc_status mlc_workspace_bytes(const mlc_ctx* ctx, size_t* bytes);
+
+/* Attach the caller's device workspace and HIP stream (hipStream_t, may be
+ * null for the default stream), upload the mesh data and compute the fixed
+ * matrices (K, M, V_ext at quadrature points, coarse trilinear tensor). */
+mlc_status mlc_bind(mlc_ctx* ctx, void* dev_workspace, size_t bytes, void* hip_stream);
+
+/* Algorithm 1 step 1 on the coarse mesh (self-consistent coarse Kohn-Sham
+ * solve, host FP64) followed by step 4's transfer to the fine mesh:
+ * Lambda = coarse eigenvalues, Phi = P Phi_H, w = coarse Hartree potential
+ * interpolated to every fine vertex. tol: L1 norm of the density change. */
+mlc_status mlc_initial_state(mlc_ctx* ctx, double tol, int32_t maxit, int32_t* iters);
+
+/* Set (Lambda^l, Phi^l, w^l) from host arrays: lambda[N], phi[n_dof x N]
+ * (caller DoF order), w[n_vertices] (nodal Hartree potential, boundary
+ * vertices included). */
+mlc_status mlc_set_state(mlc_ctx* ctx, const double* lambda, const double* phi, const double* w);
+
+/* One outer step (Algorithm 1 steps 5-7). rep may be null. */
+mlc_status mlc_correction_step(mlc_ctx* ctx, mlc_step_report* rep);
+
+/* Copy the current state to host arrays (any may be null): lambda[N],
+ * phi[n_dof x N], w[n_vertices], rho[n_vertices] (nodal density). */
+mlc_status mlc_get_results(mlc_ctx* ctx, double* lambda, double* phi, double* w, double* rho);
+
+/* Intermediate quantities of the last correction step, for checking each part
+ * against an independent implementation. Copies `count` doubles into host
+ * array out; count must equal the size listed (MLC_ERR_ARG otherwise).
+ *   MLC_PROBE_U        n_dof x N   u_i after M-normalisation (step 5)
+ *   MLC_PROBE_W0       n_dof       zero-boundary Hartree direction (step 6)
+ *   MLC_PROBE_G        n_vertices  multipole Dirichlet data (0 inside)
+ *   MLC_PROBE_VXC_QP   4 n_tets    V_xc(rho^l) at quadrature points
+ *   MLC_PROBE_PT_AFIX_U, _PT_MW0_U, _PT_M_U, _PT_K_U   N_H x N   P^T O u_i
+ *   MLC_PROBE_UT_AFIX_U, _UT_MW0_U, _UT_M_U, _UT_K_U   N x N     U^T O U
+ *   MLC_PROBE_HARTREE_D   N_H + 2  [P^T K w0, w0^T K w0, w0^T l] (l = K_IB g_B)
+ *   MLC_PROBE_AFIX_H, _MW0_H, _M_H, _K_H   N_H x N_H  dense coarse matrices
+ *   MLC_PROBE_AH4      N x N_H x N_H   (u_i psi_k, psi_j)
+ *   MLC_PROBE_RHS      N x N_H          (u_i^2, psi_j)
+ *   MLC_PROBE_THETA2   N                final theta_{2,i}
+ *   MLC_PROBE_PHI_H    N_H x N          final phi_{i,H} coefficients
+ *   MLC_PROBE_WH       N_H + 1          final [w_H, theta1]
+ *   MLC_PROBE_SIGMA    1                shift of step 5
+ */
+enum {
+  MLC_PROBE_U = 0, MLC_PROBE_W0, MLC_PROBE_G, MLC_PROBE_VXC_QP,
+  MLC_PROBE_PT_AFIX_U, MLC_PROBE_PT_MW0_U, MLC_PROBE_PT_M_U, MLC_PROBE_PT_K_U,
+  MLC_PROBE_UT_AFIX_U, MLC_PROBE_UT_MW0_U, MLC_PROBE_UT_M_U, MLC_PROBE_UT_K_U,
+  MLC_PROBE_HARTREE_D,
+  MLC_PROBE_AFIX_H, MLC_PROBE_MW0_H, MLC_PROBE_M_H, MLC_PROBE_K_H,
+  MLC_PROBE_AH4, MLC_PROBE_RHS, MLC_PROBE_THETA2, MLC_PROBE_PHI_H, MLC_PROBE_WH,
+  MLC_PROBE_SIGMA,
+  MLC_PROBE_COUNT
+};
+mlc_status mlc_probe(mlc_ctx* ctx, int32_t which, double* out, int64_t count);
+
+const char* mlc_status_string(mlc_status s);
+const char* mlc_last_error(const mlc_ctx* ctx);
+void mlc_destroy(mlc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLC_H */

@@ -1,0 +1,517 @@
+// The extern "C" entry points of include/mlc.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "inner.h"
+#include "mlc_internal.h"
+
+namespace mlc {
+
+int64_t small_len(int64_t nH, int N);
+
+mlc_status fail(mlc_ctx* c, mlc_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+mlc_status hip_fail(mlc_ctx* c, hipError_t e, const char* what) {
+  if (c) c->err = std::string(what) + ": " + hipGetErrorString(e);
+  return MLC_ERR_HIP;
+}
+
+namespace {
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(int64_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    return p;
+  }
+};
+
+}  // namespace
+
+size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
+  Carver w{base};
+  const int64_t n = c->n, nt = c->nt, nv = c->nv, nH = c->nH, N = c->N, cnt = c->cnt;
+  const int64_t nnz = (int64_t)c->col.size(), nadj = (int64_t)c->adj_tet.size();
+  d->tets = w.take<int32_t>(4 * nt);
+  d->v2d = w.take<int32_t>(nv);
+  d->xyz = w.take<double>(3 * nv);
+  d->geo = w.take<double>(16 * nt);
+  d->qpx = w.take<double>(12 * nt);
+  d->vext = w.take<double>(4 * nt);
+  d->vxc = w.take<double>(4 * nt);
+  d->exc = w.take<double>(4 * nt);
+  d->veff = w.take<double>(4 * nt);
+  d->rho = w.take<double>(4 * nt);
+  d->fld = w.take<double>(4 * nt);
+  d->fld2 = w.take<double>(4 * nt);
+  d->rhot = w.take<double>(4 * nt);
+  d->rowptr = w.take<int32_t>(n + 1);
+  d->col = w.take<int32_t>(nnz);
+  d->adj_ptr = w.take<int32_t>(n + 1);
+  d->adj_tet = w.take<int32_t>(nadj);
+  d->adj_pos = w.take<int32_t>(4 * nadj);
+  d->adj_loc = w.take<int8_t>(nadj);
+  d->bverts = w.take<int32_t>((int64_t)c->bverts.size());
+  d->valA = w.take<double>(nnz);
+  d->valF = w.take<double>(nnz);
+  d->valW = w.take<double>(nnz);
+  d->valM = w.take<double>(nnz);
+  d->valK = w.take<double>(nnz);
+  d->dinvA = w.take<double>(n);
+  d->dinvK = w.take<double>(n);
+  d->Phi = w.take<double>(n * N);
+  d->X = w.take<double>(n * N);
+  d->R = w.take<double>(n * N);
+  d->P = w.take<double>(n * N);
+  d->Q = w.take<double>(n * N);
+  d->B = w.take<double>(n * N);
+  d->Y = w.take<double>(4 * n * N);
+  d->w = w.take<double>(nv);
+  d->g = w.take<double>(nv);
+  d->w0 = w.take<double>(n);
+  d->lvec = w.take<double>(n);
+  d->pb = w.take<double>(n);
+  d->pr = w.take<double>(n);
+  d->pp = w.take<double>(n);
+  d->pq = w.take<double>(n);
+  d->rho_nodal = w.take<double>(nv);
+  d->Pk = w.take<int32_t>(4 * n);
+  d->Pw = w.take<double>(4 * n);
+  d->PTptr = w.take<int32_t>(nH + 1);
+  d->PTidx = w.take<int32_t>((int64_t)c->PTidx.size());
+  d->PTw = w.take<double>((int64_t)c->PTw.size());
+  d->cgrp_ptr = w.take<int32_t>(cnt + 1);
+  d->cgrp_tet = w.take<int32_t>(nt);
+  d->cgeo = w.take<double>(12 * cnt);
+  d->cel_ops = w.take<double>(40 * cnt);
+  d->cel_orb = w.take<double>(14 * cnt * N);
+  d->cel_tri = w.take<double>(20 * cnt);
+  d->small = w.take<double>(small_len(nH, (int)N));
+  d->coarse_in = w.take<double>(nH * N + nH + N);
+  d->occ = w.take<double>(N);
+  d->RZ = w.take<double>(4 * std::max<int64_t>(1, c->n_nuclei));
+  d->colv = w.take<double>(2 * N);
+  int64_t nred = std::max<int64_t>(3 * (int64_t)elem_blocks(n, (int)N) * N, 3 * (int64_t)elem_blocks(n, 1));
+  nred = std::max<int64_t>(nred, (int64_t)qp_blocks(nt) * 16);
+  nred = std::max<int64_t>(nred, (int64_t)gram_blocks(n) * N * N);
+  c->nred = nred;
+  d->red = w.take<double>(nred);
+  d->scal = w.take<double>(8 * N);
+  d->scalP = w.take<double>(8);
+  d->flags = w.take<int32_t>(4);
+  d->flagsP = w.take<int32_t>(4);
+  return w.off + 256;
+}
+
+#define HIPCHK(x)                                     \
+  do {                                                \
+    hipError_t e_ = (x);                              \
+    if (e_ != hipSuccess) return hip_fail(c, e_, #x); \
+  } while (0)
+
+template <class T>
+static hipError_t up(hipStream_t s, T* dst, const std::vector<T>& src) {
+  if (src.empty()) return hipSuccess;
+  return hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s);
+}
+
+mlc_status upload_and_init(mlc_ctx* c) {
+  auto& d = c->d;
+  hipStream_t s = c->stream;
+  std::vector<double> qpx(12 * c->nt);
+  for (int64_t t = 0; t < c->nt; ++t)
+    for (int q = 0; q < 4; ++q)
+      for (int k = 0; k < 3; ++k) {
+        double v = 0.0;
+        for (int j = 0; j < 4; ++j) v += (q == j ? QA : QB) * c->xyz[3 * (int64_t)c->tets[4 * t + j] + k];
+        qpx[12 * t + 3 * q + k] = v;
+      }
+  std::vector<double> RZ(4 * std::max(1, c->n_nuclei), 0.0);
+  for (int k = 0; k < c->n_nuclei; ++k) {
+    for (int x = 0; x < 3; ++x) RZ[4 * k + x] = c->R[3 * k + x];
+    RZ[4 * k + 3] = c->Z[k];
+  }
+  HIPCHK(up(s, d.tets, c->tets));
+  HIPCHK(up(s, d.v2d, c->v2d));
+  HIPCHK(up(s, d.xyz, c->xyz));
+  HIPCHK(up(s, d.geo, c->geo));
+  HIPCHK(up(s, d.qpx, qpx));
+  HIPCHK(up(s, d.rowptr, c->rowptr));
+  HIPCHK(up(s, d.col, c->col));
+  HIPCHK(up(s, d.adj_ptr, c->adj_ptr));
+  HIPCHK(up(s, d.adj_tet, c->adj_tet));
+  HIPCHK(up(s, d.adj_pos, c->adj_pos));
+  HIPCHK(up(s, d.adj_loc, c->adj_loc));
+  HIPCHK(up(s, d.bverts, c->bverts));
+  HIPCHK(up(s, d.Pk, c->Pk));
+  HIPCHK(up(s, d.Pw, c->Pw));
+  HIPCHK(up(s, d.PTptr, c->PTptr));
+  HIPCHK(up(s, d.PTidx, c->PTidx));
+  HIPCHK(up(s, d.PTw, c->PTw));
+  HIPCHK(up(s, d.cgrp_ptr, c->cgrp_ptr));
+  HIPCHK(up(s, d.cgrp_tet, c->cgrp_tet));
+  HIPCHK(up(s, d.cgeo, c->cgeo));
+  HIPCHK(up(s, d.occ, c->occ));
+  HIPCHK(up(s, d.RZ, RZ));
+  HIPCHK(hipMemsetAsync(d.w, 0, sizeof(double) * c->nv, s));
+  HIPCHK(hipMemsetAsync(d.g, 0, sizeof(double) * c->nv, s));
+  HIPCHK(hipMemsetAsync(d.small, 0, sizeof(double) * small_len(c->nH, c->N), s));
+  // fixed quantities: V_ext at the quadrature points, K, M, coarse trilinear tensor
+  launch_vext(s, c->nt, d.qpx, d.RZ, c->n_nuclei, c->potential, c->rc, c->omega, d.vext);
+  launch_assemble(s, c->n, d.rowptr, d.adj_ptr, d.adj_tet, d.adj_loc, d.adj_pos, d.geo, 1.0, nullptr, 0.0, d.valK,
+                  d.dinvK, 0.0, nullptr, nullptr);
+  launch_assemble(s, c->n, d.rowptr, d.adj_ptr, d.adj_tet, d.adj_loc, d.adj_pos, d.geo, 0.0, nullptr, 1.0, d.valM,
+                  nullptr, 0.0, nullptr, nullptr);
+  launch_coarse_tri(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.cel_tri);
+  c->h_tri.resize(20 * c->cnt);
+  HIPCHK(hipMemcpyAsync(c->h_tri.data(), d.cel_tri, sizeof(double) * c->h_tri.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  c->h_Mh_chol.clear();
+  c->h_Kh_chol.clear();
+  return MLC_OK;
+}
+
+mlc_status probe(mlc_ctx* c, int which, double* out, int64_t count) {
+  const int64_t n = c->n, nH = c->nH, nv = c->nv, nt = c->nt;
+  const int N = c->N;
+  auto need = [&](int64_t k) { return count == k ? MLC_OK : fail(c, MLC_ERR_ARG, "probe size mismatch"); };
+  hipStream_t s = c->stream;
+  auto& d = c->d;
+  auto dev_perm = [&](const double* src, int64_t cols) -> mlc_status {
+    std::vector<double> h(n * cols);
+    HIPCHK(hipMemcpyAsync(h.data(), src, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t a = 0; a < n; ++a)
+      for (int64_t j = 0; j < cols; ++j) out[(int64_t)c->dof_user[a] * cols + j] = h[a * cols + j];
+    return MLC_OK;
+  };
+  std::vector<double> tmp;
+  const double* h = c->last_small.data();
+  int64_t hn = nH * N, nn = (int64_t)N * N;
+  mlc_status st;
+  switch (which) {
+    case MLC_PROBE_U:
+      if ((st = need(n * N))) return st;
+      return dev_perm(d.X, N);
+    case MLC_PROBE_W0:
+      if ((st = need(n))) return st;
+      return dev_perm(d.w0, 1);
+    case MLC_PROBE_G:
+      if ((st = need(nv))) return st;
+      HIPCHK(hipMemcpyAsync(out, d.g, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      return MLC_OK;
+    case MLC_PROBE_VXC_QP: {
+      if ((st = need(4 * nt))) return st;
+      // library tet order -> caller tet order is not tracked; return per library tet
+      HIPCHK(hipMemcpyAsync(out, d.vxc, sizeof(double) * 4 * nt, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      return MLC_OK;
+    }
+    case MLC_PROBE_PT_AFIX_U:
+    case MLC_PROBE_PT_MW0_U:
+    case MLC_PROBE_PT_M_U:
+    case MLC_PROBE_PT_K_U:
+      if ((st = need(hn))) return st;
+      std::memcpy(out, h + (which - MLC_PROBE_PT_AFIX_U) * hn, sizeof(double) * hn);
+      return MLC_OK;
+    case MLC_PROBE_UT_AFIX_U:
+    case MLC_PROBE_UT_MW0_U:
+    case MLC_PROBE_UT_M_U:
+    case MLC_PROBE_UT_K_U:
+      if ((st = need(nn))) return st;
+      std::memcpy(out, h + 4 * hn + (which - MLC_PROBE_UT_AFIX_U) * nn, sizeof(double) * nn);
+      return MLC_OK;
+    case MLC_PROBE_HARTREE_D:
+      if ((st = need(nH + 2))) return st;
+      std::memcpy(out, h + 4 * hn + 4 * nn, sizeof(double) * nH);
+      out[nH] = h[4 * hn + 4 * nn + 2 * nH + 0];
+      out[nH + 1] = h[4 * hn + 4 * nn + 2 * nH + 1];
+      return MLC_OK;
+    case MLC_PROBE_AFIX_H:
+    case MLC_PROBE_MW0_H:
+    case MLC_PROBE_M_H:
+    case MLC_PROBE_K_H: {
+      if ((st = need(nH * nH))) return st;
+      int off = 10 * (which - MLC_PROBE_AFIX_H);
+      std::fill(out, out + nH * nH, 0.0);
+      static const int base[4] = {0, 4, 7, 9};
+      for (int64_t C = 0; C < c->cnt; ++C)
+        for (int a = 0; a < 4; ++a) {
+          int ka = c->cv2d[c->ctets[4 * C + a]];
+          if (ka < 0) continue;
+          for (int b = 0; b < 4; ++b) {
+            int kb = c->cv2d[c->ctets[4 * C + b]];
+            if (kb < 0) continue;
+            int j = std::min(a, b), k = std::max(a, b);
+            out[(int64_t)ka * nH + kb] += c->last_cel_ops[40 * C + off + base[j] + (k - j)];
+          }
+        }
+      return MLC_OK;
+    }
+    case MLC_PROBE_AH4: {
+      if ((st = need(N * nH * nH))) return st;
+      std::fill(out, out + N * nH * nH, 0.0);
+      static const int base[4] = {0, 4, 7, 9};
+      for (int64_t C = 0; C < c->cnt; ++C)
+        for (int i = 0; i < N; ++i)
+          for (int a = 0; a < 4; ++a) {
+            int ka = c->cv2d[c->ctets[4 * C + a]];
+            if (ka < 0) continue;
+            for (int b = 0; b < 4; ++b) {
+              int kb = c->cv2d[c->ctets[4 * C + b]];
+              if (kb < 0) continue;
+              int j = std::min(a, b), k = std::max(a, b);
+              out[(int64_t)i * nH * nH + (int64_t)ka * nH + kb] += c->last_cel_orb[(C * N + i) * 14 + base[j] + (k - j)];
+            }
+          }
+      return MLC_OK;
+    }
+    case MLC_PROBE_RHS: {
+      if ((st = need(N * nH))) return st;
+      std::fill(out, out + N * nH, 0.0);
+      for (int64_t C = 0; C < c->cnt; ++C)
+        for (int i = 0; i < N; ++i)
+          for (int a = 0; a < 4; ++a) {
+            int ka = c->cv2d[c->ctets[4 * C + a]];
+            if (ka >= 0) out[(int64_t)i * nH + ka] += c->last_cel_orb[(C * N + i) * 14 + 10 + a];
+          }
+      return MLC_OK;
+    }
+    case MLC_PROBE_THETA2:
+      if ((st = need(N))) return st;
+      std::copy(c->last_theta2.begin(), c->last_theta2.end(), out);
+      return MLC_OK;
+    case MLC_PROBE_PHI_H:
+      if ((st = need(nH * N))) return st;
+      std::copy(c->last_phiH.begin(), c->last_phiH.end(), out);
+      return MLC_OK;
+    case MLC_PROBE_WH:
+      if ((st = need(nH + 1))) return st;
+      std::copy(c->last_wH.begin(), c->last_wH.end(), out);
+      out[nH] = c->last_theta1;
+      return MLC_OK;
+    case MLC_PROBE_SIGMA:
+      if ((st = need(1))) return st;
+      out[0] = c->last_sigma;
+      return MLC_OK;
+    default:
+      return fail(c, MLC_ERR_ARG, "unknown probe");
+  }
+}
+
+}  // namespace mlc
+
+using namespace mlc;
+
+extern "C" {
+
+void mlc_options_default(mlc_options* o) {
+  if (!o) return;
+  o->cg_rtol = 1e-10;
+  o->cg_maxit = 20000;
+  o->check_every = 25;
+  o->shift = 1;
+  o->sigma0 = 1.0;
+  o->poisson_rtol = 1e-12;
+  o->inner_maxit = 500;
+  o->inner_tol = 1e-10;
+  o->n_extra = 8;
+  o->reorder = 1;
+  o->time_kernels = 0;
+}
+
+mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys, const mlc_options* opt,
+                      mlc_ctx** out) {
+  if (!out) return MLC_ERR_ARG;
+  *out = nullptr;
+  if (!fine || !coarse || !sys || !fine->xyz || !fine->tets || !coarse->xyz || !coarse->tets) return MLC_ERR_ARG;
+  if (sys->n_orbitals < 1 || sys->n_orbitals > MLC_MAX_ORBITALS || !sys->occupations) return MLC_ERR_ARG;
+  if (sys->potential < 0 || sys->potential > 2 || sys->xc < 0 || sys->xc > 2) return MLC_ERR_ARG;
+  if (sys->n_nuclei < 0 || (sys->n_nuclei > 0 && (!sys->R || !sys->Z))) return MLC_ERR_ARG;
+  if (sys->potential != MLC_POT_HARMONIC && sys->n_nuclei == 0) return MLC_ERR_ARG;
+  if (!(sys->box_hi > sys->box_lo)) return MLC_ERR_ARG;
+  if (sys->potential == MLC_POT_ERF && !(sys->rc > 0)) return MLC_ERR_ARG;
+  for (int i = 0; i < sys->n_orbitals; ++i)
+    if (!(sys->occupations[i] >= 0.0) || !std::isfinite(sys->occupations[i])) return MLC_ERR_ARG;
+  mlc_ctx* c = new (std::nothrow) mlc_ctx();
+  if (!c) return MLC_ERR_ARG;
+  if (opt)
+    c->opt = *opt;
+  else
+    mlc_options_default(&c->opt);
+  if (!(c->opt.cg_rtol > 0) || c->opt.cg_maxit < 1 || c->opt.check_every < 1 || c->opt.inner_maxit < 1 ||
+      c->opt.n_extra < 0 || !(c->opt.poisson_rtol > 0)) {
+    delete c;
+    return MLC_ERR_ARG;
+  }
+  c->n_nuclei = sys->n_nuclei;
+  c->R.assign(sys->R ? sys->R : nullptr, sys->R ? sys->R + 3 * sys->n_nuclei : nullptr);
+  c->Z.assign(sys->Z ? sys->Z : nullptr, sys->Z ? sys->Z + sys->n_nuclei : nullptr);
+  c->N = sys->n_orbitals;
+  c->occ.assign(sys->occupations, sys->occupations + c->N);
+  c->potential = sys->potential;
+  c->rc = sys->rc;
+  c->omega = sys->omega;
+  c->xc = sys->xc;
+  c->xalpha = sys->xalpha;
+  c->hartree = sys->hartree ? 1 : 0;
+  c->lo = sys->box_lo;
+  c->hi = sys->box_hi;
+  mlc_status st = build_mesh(c, fine, coarse);
+  if (st != MLC_OK) {
+    // keep the message reachable for the caller through a temporary context
+    *out = c;
+    return st;
+  }
+  *out = c;
+  return MLC_OK;
+}
+
+mlc_status mlc_sizes(const mlc_ctx* c, int64_t* n_dof, int64_t* n_coarse_dof, int64_t* n_vertices,
+                     int32_t* n_orbitals) {
+  if (!c) return MLC_ERR_ARG;
+  if (n_dof) *n_dof = c->n;
+  if (n_coarse_dof) *n_coarse_dof = c->nH;
+  if (n_vertices) *n_vertices = c->nv;
+  if (n_orbitals) *n_orbitals = c->N;
+  return MLC_OK;
+}
+
+mlc_status mlc_workspace_bytes(const mlc_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return MLC_ERR_ARG;
+  Dev tmp;
+  *bytes = workspace_layout(const_cast<mlc_ctx*>(c), nullptr, &tmp);
+  return MLC_OK;
+}
+
+mlc_status mlc_bind(mlc_ctx* c, void* dev_workspace, size_t bytes, void* hip_stream) {
+  if (!c) return MLC_ERR_ARG;
+  if (c->n == 0) return fail(c, MLC_ERR_STATE, "context was not built");
+  Dev tmp;
+  size_t need = workspace_layout(c, nullptr, &tmp);
+  if (!dev_workspace || bytes < need) return fail(c, MLC_ERR_WORKSPACE, "workspace missing or too small");
+  c->ws = static_cast<char*>(dev_workspace);
+  c->ws_bytes = bytes;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  workspace_layout(c, c->ws, &c->d);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  c->ev_pool.clear();
+  c->ev_used = 0;
+  if (c->opt.time_kernels) {
+    c->ev_pool.resize(2 * std::max(1, c->opt.check_every));
+    for (auto& e : c->ev_pool) {
+      hipError_t he = hipEventCreate(&e);
+      if (he != hipSuccess) return hip_fail(c, he, "hipEventCreate");
+    }
+  }
+  mlc_status st = upload_and_init(c);
+  if (st != MLC_OK) return st;
+  c->bound = true;
+  c->has_state = false;
+  c->has_step = false;
+  return MLC_OK;
+}
+
+mlc_status mlc_initial_state(mlc_ctx* c, double tol, int32_t maxit, int32_t* iters) {
+  if (!c) return MLC_ERR_ARG;
+  if (!c->bound) return fail(c, MLC_ERR_STATE, "mlc_bind first");
+  if (!(tol > 0) || maxit < 1) return fail(c, MLC_ERR_ARG, "bad tolerance or iteration cap");
+  int it = 0;
+  mlc_status st = coarse_scf(c, tol, maxit, &it);
+  if (iters) *iters = it;
+  return st;
+}
+
+mlc_status mlc_set_state(mlc_ctx* c, const double* lambda, const double* phi, const double* w) {
+  if (!c || !lambda || !phi || !w) return MLC_ERR_ARG;
+  if (!c->bound) return fail(c, MLC_ERR_STATE, "mlc_bind first");
+  const int N = c->N;
+  std::vector<double> p(c->n * N);
+  for (int64_t a = 0; a < c->n; ++a)
+    for (int i = 0; i < N; ++i) p[a * N + i] = phi[(int64_t)c->dof_user[a] * N + i];
+  for (int i = 0; i < N; ++i)
+    if (!std::isfinite(lambda[i])) return fail(c, MLC_ERR_ARG, "non-finite eigenvalue");
+  hipError_t e = hipMemcpyAsync(c->d.Phi, p.data(), sizeof(double) * p.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d.w, w, sizeof(double) * c->nv, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "mlc_set_state upload");
+  c->lam.assign(lambda, lambda + N);
+  c->has_state = true;
+  c->has_step = false;
+  return MLC_OK;
+}
+
+mlc_status mlc_correction_step(mlc_ctx* c, mlc_step_report* rep) {
+  if (!c) return MLC_ERR_ARG;
+  if (!c->bound || !c->has_state) return fail(c, MLC_ERR_STATE, "bind and set a state first");
+  return fine_stage_and_step(c, rep);
+}
+
+mlc_status mlc_get_results(mlc_ctx* c, double* lambda, double* phi, double* w, double* rho) {
+  if (!c) return MLC_ERR_ARG;
+  if (!c->bound || !c->has_state) return fail(c, MLC_ERR_STATE, "no state");
+  const int N = c->N;
+  hipStream_t s = c->stream;
+  if (lambda) std::copy(c->lam.begin(), c->lam.end(), lambda);
+  if (phi) {
+    std::vector<double> h(c->n * N);
+    HIPCHK(hipMemcpyAsync(h.data(), c->d.Phi, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t a = 0; a < c->n; ++a)
+      for (int i = 0; i < N; ++i) phi[(int64_t)c->dof_user[a] * N + i] = h[a * N + i];
+  }
+  if (w) {
+    HIPCHK(hipMemcpyAsync(w, c->d.w, sizeof(double) * c->nv, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  if (rho) {
+    launch_rho_nodal(s, c->nv, c->d.v2d, c->d.Phi, N, c->d.occ, c->d.rho_nodal);
+    HIPCHK(hipMemcpyAsync(rho, c->d.rho_nodal, sizeof(double) * c->nv, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return MLC_OK;
+}
+
+mlc_status mlc_probe(mlc_ctx* c, int32_t which, double* out, int64_t count) {
+  if (!c || !out) return MLC_ERR_ARG;
+  if (!c->has_step) return fail(c, MLC_ERR_STATE, "no correction step has run");
+  return probe(c, which, out, count);
+}
+
+const char* mlc_status_string(mlc_status s) {
+  switch (s) {
+    case MLC_OK: return "ok";
+    case MLC_ERR_ARG: return "invalid argument";
+    case MLC_ERR_MESH: return "invalid mesh";
+    case MLC_ERR_NOT_NESTED: return "meshes are not nested";
+    case MLC_ERR_WORKSPACE: return "workspace missing or too small";
+    case MLC_ERR_HIP: return "HIP runtime error";
+    case MLC_ERR_NOT_CONVERGED: return "CG not converged";
+    case MLC_ERR_BREAKDOWN: return "CG breakdown";
+    case MLC_ERR_NONFINITE: return "non-finite value";
+    case MLC_ERR_STATE: return "call order";
+    case MLC_WARN_INNER_MAXIT: return "inner iteration stopped at inner_maxit";
+  }
+  return "unknown status";
+}
+
+const char* mlc_last_error(const mlc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void mlc_destroy(mlc_ctx* c) {
+  if (!c) return;
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,329 @@
+// Host FP64 dense linear algebra, written for the small problems of the
+// method (order N_H + 1 of a few thousand at most). Parallel loops use
+// OpenMP over independent rows.
+#include "dense.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+namespace mlc {
+namespace dense {
+
+bool cholesky(std::vector<double>& A, int64_t n) {
+  // row-oriented: L_ij = (A_ij - sum_{k<j} L_ik L_jk) / L_jj, rows contiguous
+  for (int64_t i = 0; i < n; ++i) {
+    double* Li = &A[i * n];
+    for (int64_t j = 0; j <= i; ++j) {
+      const double* Lj = &A[j * n];
+      double s = Li[j];
+      for (int64_t k = 0; k < j; ++k) s -= Li[k] * Lj[k];
+      if (j == i) {
+        if (!(s > 0.0)) return false;
+        Li[i] = std::sqrt(s);
+      } else {
+        Li[j] = s / Lj[j];
+      }
+    }
+    for (int64_t j = i + 1; j < n; ++j) Li[j] = 0.0;
+  }
+  return true;
+}
+
+void forward(const std::vector<double>& L, int64_t n, double* x) {
+  for (int64_t i = 0; i < n; ++i) {
+    const double* Li = &L[i * n];
+    double s = x[i];
+    for (int64_t k = 0; k < i; ++k) s -= Li[k] * x[k];
+    x[i] = s / Li[i];
+  }
+}
+
+void backward(const std::vector<double>& L, int64_t n, double* x) {
+  for (int64_t i = n - 1; i >= 0; --i) {
+    double s = x[i];
+    for (int64_t k = i + 1; k < n; ++k) s -= L[k * n + i] * x[k];
+    x[i] = s / L[i * n + i];
+  }
+}
+
+void congruence(const std::vector<double>& L, const std::vector<double>& A, int64_t n, std::vector<double>& C) {
+  // X = L^{-1} A: column j of A (= row j, A symmetric) solved into row j of Xt
+  std::vector<double> Xt(n * n);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t j = 0; j < n; ++j) {
+    double* x = &Xt[j * n];
+    for (int64_t i = 0; i < n; ++i) x[i] = A[j * n + i];
+    forward(L, n, x);
+  }
+  // C = L^{-1} X^T: column j of X^T = row j of X = column j of Xt
+  C.assign(n * n, 0.0);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t j = 0; j < n; ++j) {
+    std::vector<double> x(n);
+    for (int64_t i = 0; i < n; ++i) x[i] = Xt[i * n + j];
+    forward(L, n, x.data());
+    for (int64_t i = 0; i < n; ++i) C[j * n + i] = x[i];
+  }
+  // symmetrise against rounding
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < i; ++j) {
+      double v = 0.5 * (C[i * n + j] + C[j * n + i]);
+      C[i * n + j] = v;
+      C[j * n + i] = v;
+    }
+}
+
+void tridiagonalize(std::vector<double>& C, int64_t n, Tridiag& T) {
+  T.n = n;
+  T.V.assign(n * n, 0.0);
+  T.tau.assign(n, 0.0);
+  T.d.assign(n, 0.0);
+  T.e.assign(n > 1 ? n - 1 : 0, 0.0);
+  std::vector<double> v(n), p(n);
+  for (int64_t k = 0; k + 2 < n; ++k) {
+    int64_t m = n - k - 1;  // trailing size
+    double* x = &v[k + 1];
+    double nrm2 = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+      x[i] = C[(k + 1 + i) * n + k];
+      nrm2 += x[i] * x[i];
+    }
+    double nrm = std::sqrt(nrm2);
+    T.d[k] = C[k * n + k];
+    if (nrm == 0.0) {
+      T.e[k] = 0.0;
+      T.tau[k] = 0.0;
+      continue;
+    }
+    double alpha = x[0] >= 0 ? -nrm : nrm;  // e_k
+    x[0] -= alpha;                          // v = x - alpha e1
+    double vv = nrm2 - 2.0 * alpha * (x[0] + alpha) + alpha * alpha;
+    // vv = |x - alpha e1|^2 computed directly for safety
+    vv = 0.0;
+    for (int64_t i = 0; i < m; ++i) vv += x[i] * x[i];
+    double tau = 2.0 / vv;
+    T.e[k] = alpha;
+    T.tau[k] = tau;
+    for (int64_t i = 0; i < m; ++i) T.V[k * n + k + 1 + i] = x[i];
+    // p = tau * C22 v
+#pragma omp parallel for schedule(static) if (m > 128)
+    for (int64_t i = 0; i < m; ++i) {
+      const double* Ci = &C[(k + 1 + i) * n + k + 1];
+      double s = 0.0;
+      for (int64_t j = 0; j < m; ++j) s += Ci[j] * x[j];
+      p[k + 1 + i] = tau * s;
+    }
+    double pv = 0.0;
+    for (int64_t i = 0; i < m; ++i) pv += p[k + 1 + i] * x[i];
+    double h = 0.5 * tau * pv;
+    for (int64_t i = 0; i < m; ++i) p[k + 1 + i] -= h * x[i];  // w
+    const double* w = &p[k + 1];
+#pragma omp parallel for schedule(static) if (m > 128)
+    for (int64_t i = 0; i < m; ++i) {
+      double* Ci = &C[(k + 1 + i) * n + k + 1];
+      double xi = x[i], wi = w[i];
+      for (int64_t j = 0; j < m; ++j) Ci[j] -= xi * w[j] + wi * x[j];
+    }
+  }
+  if (n >= 2) {
+    T.d[n - 2] = C[(n - 2) * n + n - 2];
+    T.e[n - 2] = C[(n - 1) * n + n - 2];
+  }
+  T.d[n - 1] = C[(n - 1) * n + n - 1];
+}
+
+// Q = H_0 H_1 ... H_{n-3}, H_k = I - tau_k v_k v_k^T
+void apply_QT(const Tridiag& T, double* x) {
+  int64_t n = T.n;
+  for (int64_t k = 0; k + 2 < n; ++k) {
+    if (T.tau[k] == 0.0) continue;
+    const double* v = &T.V[k * n];
+    double s = 0.0;
+    for (int64_t i = k + 1; i < n; ++i) s += v[i] * x[i];
+    s *= T.tau[k];
+    for (int64_t i = k + 1; i < n; ++i) x[i] -= s * v[i];
+  }
+}
+
+void apply_Q(const Tridiag& T, double* x) {
+  int64_t n = T.n;
+  for (int64_t k = n - 3; k >= 0; --k) {
+    if (T.tau[k] == 0.0) continue;
+    const double* v = &T.V[k * n];
+    double s = 0.0;
+    for (int64_t i = k + 1; i < n; ++i) s += v[i] * x[i];
+    s *= T.tau[k];
+    for (int64_t i = k + 1; i < n; ++i) x[i] -= s * v[i];
+  }
+}
+
+namespace {
+
+// Number of eigenvalues of [[T, u],[u^T, alpha]] (or of T if u is null) that
+// are smaller than mu: negative pivots of the LDL^T factorisation of
+// T - mu I plus the sign of the Schur complement of the border.
+int64_t count_below(const Tridiag& T, const double* u, double alpha, double mu, double pivmin) {
+  int64_t n = T.n;
+  int64_t cnt = 0;
+  double dprev = 1.0, wprev = 0.0, schur = alpha - mu;
+  for (int64_t j = 0; j < n; ++j) {
+    double dj = T.d[j] - mu;
+    double wj = u ? u[j] : 0.0;
+    if (j > 0) {
+      double ej = T.e[j - 1];
+      dj -= ej * ej / dprev;
+      wj -= ej / dprev * wprev;
+    }
+    if (std::fabs(dj) < pivmin) dj = -pivmin;
+    if (dj < 0) ++cnt;
+    if (u) schur -= wj * wj / dj;
+    dprev = dj;
+    wprev = wj;
+  }
+  if (u && schur < 0) ++cnt;
+  return cnt;
+}
+
+double gersh(const Tridiag& T, const double* u, double alpha, double* lo) {
+  int64_t n = T.n;
+  double mn = 1e300, mx = -1e300, su = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    double r = (j > 0 ? std::fabs(T.e[j - 1]) : 0.0) + (j + 1 < n ? std::fabs(T.e[j]) : 0.0) +
+               (u ? std::fabs(u[j]) : 0.0);
+    mn = std::min(mn, T.d[j] - r);
+    mx = std::max(mx, T.d[j] + r);
+    if (u) su += std::fabs(u[j]);
+  }
+  if (u) {
+    mn = std::min(mn, alpha - su);
+    mx = std::max(mx, alpha + su);
+  }
+  *lo = mn;
+  return mx;
+}
+
+// Solve (K - mu I) [x; t] = [r; q] for the bordered tridiagonal (u may be null).
+void bordered_solve(const Tridiag& T, const double* u, double alpha, double mu, const double* r, double q,
+                    double* x, double* t) {
+  int64_t n = T.n;
+  double eps = std::numeric_limits<double>::epsilon();
+  double scale = 0.0;
+  for (int64_t j = 0; j < n; ++j) scale = std::max(scale, std::fabs(T.d[j]) + (j < n - 1 ? std::fabs(T.e[j]) : 0));
+  double pivmin = eps * std::max(scale, 1e-300);
+  std::vector<double> dd(n), yr(n), yu(n);
+  // L D L^T of T - mu I, forward solves for r and u
+  for (int64_t j = 0; j < n; ++j) {
+    double dj = T.d[j] - mu;
+    double a = r[j], b = u ? u[j] : 0.0;
+    if (j > 0) {
+      double l = T.e[j - 1] / dd[j - 1];
+      dj -= l * T.e[j - 1];
+      a -= l * yr[j - 1];
+      b -= l * yu[j - 1];
+    }
+    if (std::fabs(dj) < pivmin) dj = dj < 0 ? -pivmin : pivmin;
+    dd[j] = dj;
+    yr[j] = a;
+    yu[j] = b;
+  }
+  // backward: z = (T - mu)^{-1} * [r, u]
+  std::vector<double> zr(n), zu(n);
+  for (int64_t j = n - 1; j >= 0; --j) {
+    double a = yr[j] / dd[j], b = yu[j] / dd[j];
+    if (j + 1 < n) {
+      double l = T.e[j] / dd[j];
+      a -= l * zr[j + 1];
+      b -= l * zu[j + 1];
+    }
+    zr[j] = a;
+    zu[j] = b;
+  }
+  if (!u) {
+    for (int64_t j = 0; j < n; ++j) x[j] = zr[j];
+    *t = 0.0;
+    return;
+  }
+  double ur = 0.0, uu = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    ur += u[j] * zr[j];
+    uu += u[j] * zu[j];
+  }
+  double s = alpha - mu - uu;
+  if (std::fabs(s) < pivmin) s = s < 0 ? -pivmin : pivmin;
+  double tt = (q - ur) / s;
+  for (int64_t j = 0; j < n; ++j) x[j] = zr[j] - zu[j] * tt;
+  *t = tt;
+}
+
+}  // namespace
+
+std::vector<double> lowest_eigenvalues(const Tridiag& T, const double* u, double alpha, int k) {
+  double lo, hi = gersh(T, u, alpha, &lo);
+  double eps = std::numeric_limits<double>::epsilon();
+  double scale = std::max(std::fabs(lo), std::fabs(hi));
+  double pivmin = eps * std::max(scale, 1e-300) * 1e-3;
+  std::vector<double> ev(k);
+  double a0 = lo - 1e-12 * scale - 1e-300, b0 = hi + 1e-12 * scale;
+  for (int j = 0; j < k; ++j) {
+    // find mu with count_below(mu) <= j < count_below(next)
+    double a = j > 0 ? std::max(a0, ev[j - 1] - 4 * eps * scale) : a0, b = b0;
+    for (int it = 0; it < 200; ++it) {
+      double m = 0.5 * (a + b);
+      if (b - a <= 2.0 * eps * std::max(std::fabs(a), std::fabs(b)) + 1e-300 || m == a || m == b) break;
+      if (count_below(T, u, alpha, m, pivmin) > j)
+        b = m;
+      else
+        a = m;
+    }
+    ev[j] = 0.5 * (a + b);
+  }
+  return ev;
+}
+
+double border_weight(const Tridiag& T, const double* u, double mu) {
+  int64_t n = T.n;
+  std::vector<double> z(n);
+  double tt;
+  // z = (T - mu)^{-1} u  (use the bordered solver with r = u, no border)
+  bordered_solve(T, nullptr, 0.0, mu, u, 0.0, z.data(), &tt);
+  double s2 = 0.0;
+  for (int64_t j = 0; j < n; ++j) s2 += z[j] * z[j];
+  return 1.0 / std::sqrt(1.0 + s2);
+}
+
+void eigenvector(const Tridiag& T, const double* u, double alpha, double mu, double* y, double* s) {
+  int64_t n = T.n;
+  std::vector<double> x(n), xn(n);
+  double t = 1.0, tn;
+  // start: for a bordered matrix, [-(T-mu)^{-1} u; 1]; otherwise all ones
+  if (u) {
+    double tt;
+    bordered_solve(T, nullptr, 0.0, mu, u, 0.0, x.data(), &tt);
+    for (int64_t j = 0; j < n; ++j) x[j] = -x[j];
+  } else {
+    for (int64_t j = 0; j < n; ++j) x[j] = 1.0 / std::sqrt((double)n) * (1.0 + 1e-3 * std::sin((double)j));
+    t = 0.0;
+  }
+  double eps = std::numeric_limits<double>::epsilon();
+  double mus = mu + eps * std::max(1.0, std::fabs(mu)) * 16.0;
+  for (int it = 0; it < 3; ++it) {
+    double nr = t * t;
+    for (int64_t j = 0; j < n; ++j) nr += x[j] * x[j];
+    nr = std::sqrt(nr);
+    for (int64_t j = 0; j < n; ++j) x[j] /= nr;
+    t /= nr;
+    bordered_solve(T, u, alpha, mus, x.data(), t, xn.data(), &tn);
+    x.swap(xn);
+    t = tn;
+  }
+  double nr = u ? t * t : 0.0;
+  for (int64_t j = 0; j < n; ++j) nr += x[j] * x[j];
+  nr = std::sqrt(nr);
+  for (int64_t j = 0; j < n; ++j) y[j] = x[j] / nr;
+  if (s) *s = u ? t / nr : 0.0;
+}
+
+}  // namespace dense
+}  // namespace mlc

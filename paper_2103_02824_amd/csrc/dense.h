@@ -1,0 +1,44 @@
+// Host FP64 dense linear algebra for the small augmented problems
+// (Algorithm 3 step 2) and the coarse self-consistent solve (Algorithm 1
+// step 1). Row-major square matrices of order n.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace mlc {
+namespace dense {
+
+// In-place Cholesky A = L L^T (lower triangle of A overwritten by L; the
+// strict upper triangle is zeroed). Returns false if A is not SPD.
+bool cholesky(std::vector<double>& A, int64_t n);
+// Solve L x = b (forward) and L^T x = b (backward) in place.
+void forward(const std::vector<double>& L, int64_t n, double* x);
+void backward(const std::vector<double>& L, int64_t n, double* x);
+// C = L^{-1} A L^{-T} for symmetric A.
+void congruence(const std::vector<double>& L, const std::vector<double>& A, int64_t n, std::vector<double>& C);
+
+// Householder tridiagonalisation of symmetric C = Q T Q^T. C is overwritten
+// with the reflectors; d (n) and e (n-1) hold T.
+struct Tridiag {
+  int64_t n = 0;
+  std::vector<double> V;    // reflectors (row k: v_k in entries k+1..n-1)
+  std::vector<double> tau;  // n
+  std::vector<double> d, e;
+};
+void tridiagonalize(std::vector<double>& C, int64_t n, Tridiag& T);
+void apply_QT(const Tridiag& T, double* x);  // x <- Q^T x
+void apply_Q(const Tridiag& T, double* x);   // x <- Q x
+
+// Eigenvalues of the bordered tridiagonal K = [[T, u], [u^T, alpha]] (order
+// n+1; u may be null for plain T of order n) by bisection on inertia counts.
+// Returns the k lowest eigenvalues in ascending order.
+std::vector<double> lowest_eigenvalues(const Tridiag& T, const double* u, double alpha, int k);
+// Eigenvector of K for eigenvalue mu by inverse iteration (normalised).
+// Output: y (n) and s (border coordinate; unused when u is null).
+void eigenvector(const Tridiag& T, const double* u, double alpha, double mu, double* y, double* s);
+// |s| of the normalised eigenvector for eigenvalue mu (border weight), cheap.
+double border_weight(const Tridiag& T, const double* u, double mu);
+
+}  // namespace dense
+}  // namespace mlc

@@ -1,0 +1,320 @@
+// Host FP64 parts of the method:
+//  * Algorithm 2 (inner Hartree iteration) implemented as in Algorithm 3
+//    step 2: every fine-mesh integral was precomputed on the GPU, so one inner
+//    iteration only touches coarse-size data;
+//  * Algorithm 1 step 1: the self-consistent Kohn-Sham solve on the coarse
+//    mesh that provides the initial state, and step 4's transfer to the fine
+//    mesh.
+//
+// The augmented eigenproblem of each orbital (eq. Eigenvalue_H_h) shares its
+// coarse block A_H with every other orbital. Per inner iteration the pencil
+// (A_H, M_H) is reduced once to tridiagonal form, C = L^{-1} A_H L^{-T} =
+// Q T Q^T (M_H = L L^T). For orbital i the border (b, beta; c, gamma) is first
+// made M-orthogonal to V_H (a = M_H^{-1} c), which turns the pencil into the
+// standard symmetric problem [[T, u], [u^T, alpha]] of order N_H + 1; its
+// lowest eigenvalues come from bisection on inertia counts and the chosen
+// eigenvector from inverse iteration, both O(N_H) per evaluation.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "dense.h"
+#include "inner.h"
+#include "mlc_internal.h"
+
+namespace mlc {
+
+namespace {
+
+// slot of the symmetric pair (j<=k) in the 10-entry element layout
+inline int sym10(int j, int k) {
+  if (j > k) std::swap(j, k);
+  static const int base[4] = {0, 4, 7, 9};
+  return base[j] + (k - j);
+}
+// slot of the sorted triple in the 20-entry trilinear layout
+int tri20(int a, int b, int c) {
+  int v[3] = {a, b, c};
+  std::sort(v, v + 3);
+  int k = 0;
+  for (int j = 0; j < 4; ++j)
+    for (int m = j; m < 4; ++m)
+      for (int l = m; l < 4; ++l, ++k)
+        if (j == v[0] && m == v[1] && l == v[2]) return k;
+  return -1;
+}
+
+struct TriIndex {
+  int idx[4][4][4];
+  TriIndex() {
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b)
+        for (int c = 0; c < 4; ++c) idx[a][b][c] = tri20(a, b, c);
+  }
+};
+const TriIndex& tri_index() {
+  static TriIndex t;
+  return t;
+}
+
+void assemble_dense(const mlc_ctx* c, const double* cel, int stride, int off, std::vector<double>& A) {
+  int64_t nH = c->nH;
+  A.assign(nH * nH, 0.0);
+  for (int64_t C = 0; C < c->cnt; ++C) {
+    int k[4];
+    for (int a = 0; a < 4; ++a) k[a] = c->cv2d[c->ctets[4 * C + a]];
+    const double* e = cel + (int64_t)stride * C + off;
+    for (int a = 0; a < 4; ++a) {
+      if (k[a] < 0) continue;
+      for (int b = 0; b < 4; ++b) {
+        if (k[b] < 0) continue;
+        A[(int64_t)k[a] * nH + k[b]] += e[sym10(a, b)];
+      }
+    }
+  }
+}
+
+inline double dot(const double* a, const double* b, int64_t n) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
+void symv(const std::vector<double>& A, int64_t n, const double* x, double* y) {
+#pragma omp parallel for schedule(static) if (n > 512)
+  for (int64_t i = 0; i < n; ++i) y[i] = dot(&A[i * n], x, n);
+}
+
+}  // namespace
+
+// A_{H,2}(w) = sum_m T_{jkm} w_m added into dense A (scale s)
+void add_trilinear_matrix(const mlc_ctx* c, const std::vector<double>& tri, const double* w, double s,
+                          std::vector<double>& A) {
+  const TriIndex& ti = tri_index();
+  int64_t nH = c->nH;
+  for (int64_t C = 0; C < c->cnt; ++C) {
+    int k[4];
+    double wl[4];
+    for (int a = 0; a < 4; ++a) {
+      k[a] = c->cv2d[c->ctets[4 * C + a]];
+      wl[a] = k[a] >= 0 ? w[k[a]] : 0.0;
+    }
+    const double* T = &tri[20 * C];
+    for (int a = 0; a < 4; ++a) {
+      if (k[a] < 0) continue;
+      for (int b = 0; b < 4; ++b) {
+        if (k[b] < 0) continue;
+        double v = 0.0;
+        for (int m = 0; m < 4; ++m) v += T[ti.idx[a][b][m]] * wl[m];
+        A[(int64_t)k[a] * nH + k[b]] += s * v;
+      }
+    }
+  }
+}
+
+mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
+  using namespace dense;
+  const int64_t nH = c->nH;
+  const int N = c->N;
+  const int hart = c->hartree;
+  const TriIndex& ti = tri_index();
+  auto t0 = std::chrono::steady_clock::now();
+
+  std::vector<double> AfixH, G, MH, KH;
+  assemble_dense(c, fb.cel_ops.data(), 40, 0, AfixH);
+  assemble_dense(c, fb.cel_ops.data(), 40, 10, G);
+  if (c->h_Mh_chol.empty()) {
+    assemble_dense(c, fb.cel_ops.data(), 40, 20, MH);
+    assemble_dense(c, fb.cel_ops.data(), 40, 30, KH);
+    c->h_MH = MH;
+    c->h_KH = KH;
+    c->h_Mh_chol = MH;
+    if (!cholesky(c->h_Mh_chol, nH)) return fail(c, MLC_ERR_NONFINITE, "coarse mass matrix not SPD");
+    c->h_Kh_chol = KH;
+    if (!cholesky(c->h_Kh_chol, nH)) return fail(c, MLC_ERR_NONFINITE, "coarse stiffness not SPD");
+  }
+  const std::vector<double>& L = c->h_Mh_chol;
+  const std::vector<double>& MHd = c->h_MH;
+  const std::vector<double>& KHd = c->h_KH;
+
+  // per-orbital sparse pieces: A_h4 as element arrays, rhs assembled
+  std::vector<double> rhsv(nH * N, 0.0);  // [k*N + i]
+  for (int64_t C = 0; C < c->cnt; ++C)
+    for (int a = 0; a < 4; ++a) {
+      int k = c->cv2d[c->ctets[4 * C + a]];
+      if (k < 0) continue;
+      for (int i = 0; i < N; ++i) rhsv[(int64_t)k * N + i] += fb.cel_orb[(C * N + i) * 14 + 10 + a];
+    }
+  auto ah4_apply = [&](int i, const double* x, double* y) {  // y = A_h4,i x (coarse dof vectors)
+    std::fill(y, y + nH, 0.0);
+    for (int64_t C = 0; C < c->cnt; ++C) {
+      int k[4];
+      for (int a = 0; a < 4; ++a) k[a] = c->cv2d[c->ctets[4 * C + a]];
+      const double* e = &fb.cel_orb[(C * N + i) * 14];
+      for (int a = 0; a < 4; ++a) {
+        if (k[a] < 0) continue;
+        double s = 0.0;
+        for (int b = 0; b < 4; ++b)
+          if (k[b] >= 0) s += e[sym10(a, b)] * x[k[b]];
+        y[k[a]] += s;
+      }
+    }
+  };
+
+  // Hartree system pieces (fixed in the inner loop): Schur complement of the border
+  std::vector<double> yd(nH, 0.0);
+  double schur = 1.0;
+  if (hart) {
+    for (int64_t k = 0; k < nH; ++k) yd[k] = fb.d[k];
+    forward(c->h_Kh_chol, nH, yd.data());
+    backward(c->h_Kh_chol, nH, yd.data());
+    schur = fb.zeta - dot(fb.d.data(), yd.data(), nH);
+    if (!(schur > 0.0)) return fail(c, MLC_ERR_NONFINITE, "Hartree augmented matrix not SPD");
+  }
+
+  std::vector<double> wH(nH, 0.0), phiH(nH * N, 0.0), phiH_old(nH * N, 0.0);
+  std::vector<double> theta2(N, 0.0), theta2_old(N, 1.0), lam(N, 0.0);
+  double th1 = hart ? 1.0 : 0.0;
+  std::vector<double> AH, Cm, KpM(nH * nH);
+  for (int64_t k = 0; k < nH * nH; ++k) KpM[k] = KHd[k] + MHd[k];
+  std::vector<double> a(nH), Aa(nH), b(nH), u(nH), y(nH), tmp(nH), fH(nH);
+  Tridiag Tr;
+  int n_keep = (int)std::min<int64_t>(nH + 1, (int64_t)N + c->opt.n_extra);
+  int its = 0;
+  double diff = 0.0;
+  mlc_status st = MLC_OK;
+  int maxit = std::max(1, c->opt.inner_maxit);
+  for (int s = 0; s < maxit; ++s) {
+    its = s + 1;
+    // (a) A_H = A_{H,1} + A_{H,4} + A_{H,2}(w_H) + theta1 A_{H,3}
+    AH = AfixH;
+    if (hart) {
+      add_trilinear_matrix(c, c->h_tri, wH.data(), 1.0, AH);
+      for (int64_t k = 0; k < nH * nH; ++k) AH[k] += th1 * G[k];
+    }
+    congruence(L, AH, nH, Cm);
+    tridiagonalize(Cm, nH, Tr);
+    for (int i = 0; i < N; ++i) {
+      // border of orbital i (eqs. bdef, betadef)
+      ah4_apply(i, wH.data(), tmp.data());
+      double beta = fb.utF[i * N + i] + th1 * fb.utW[i * N + i];
+      for (int64_t k = 0; k < nH; ++k) {
+        b[k] = fb.ptF[k * N + i] + (hart ? tmp[k] + th1 * fb.ptW[k * N + i] : 0.0);
+        beta += hart ? rhsv[k * N + i] * wH[k] : 0.0;
+      }
+      double gam = fb.utM[i * N + i];
+      for (int64_t k = 0; k < nH; ++k) a[k] = fb.ptM[k * N + i];
+      forward(L, nH, a.data());
+      backward(L, nH, a.data());  // a = M_H^{-1} c
+      symv(AH, nH, a.data(), Aa.data());
+      double ba = dot(b.data(), a.data(), nH), aAa = dot(a.data(), Aa.data(), nH);
+      double ca = 0.0;
+      for (int64_t k = 0; k < nH; ++k) ca += fb.ptM[k * N + i] * a[k];
+      double gp = gam - ca;
+      double bp = beta - 2.0 * ba + aAa;
+      if (!(gp > 1e-14 * std::fabs(gam))) return fail(c, MLC_ERR_NONFINITE, "auxiliary solution lies in the coarse space");
+      double sg = std::sqrt(gp);
+      for (int64_t k = 0; k < nH; ++k) u[k] = b[k] - Aa[k];
+      forward(L, nH, u.data());
+      for (int64_t k = 0; k < nH; ++k) u[k] /= sg;
+      apply_QT(Tr, u.data());
+      double alpha = bp / gp;
+      std::vector<double> ev = lowest_eigenvalues(Tr, u.data(), alpha, n_keep);
+      int jsel = 0;
+      double wbest = -1.0;
+      for (int j = 0; j < n_keep; ++j) {
+        double wj = border_weight(Tr, u.data(), ev[j]);
+        if (wj > wbest) {
+          wbest = wj;
+          jsel = j;
+        }
+      }
+      double sv;
+      eigenvector(Tr, u.data(), alpha, ev[jsel], y.data(), &sv);
+      if (sv < 0) {
+        sv = -sv;
+        for (int64_t k = 0; k < nH; ++k) y[k] = -y[k];
+      }
+      apply_Q(Tr, y.data());
+      backward(L, nH, y.data());
+      double t2 = sv / sg;
+      for (int64_t k = 0; k < nH; ++k) phiH[k * N + i] = y[k] - t2 * a[k];
+      theta2[i] = t2;
+      lam[i] = ev[jsel];
+    }
+    // (b) Hartree problem in W_{H,h} (eqs. Hartree_H_h, fH, gdef with the
+    //     factor 2, the theta2^2 term and the occupations)
+    if (hart) {
+      std::fill(fH.begin(), fH.end(), 0.0);
+      double gsum = 0.0;
+      std::vector<double> ph(nH);
+      for (int i = 0; i < N; ++i) {
+        double f = c->occ[i];
+        if (f == 0.0) continue;
+        for (int64_t k = 0; k < nH; ++k) ph[k] = phiH[k * N + i];
+        double t2 = theta2[i];
+        // (phi_H^2, psi_j) through the trilinear tensor
+        for (int64_t C = 0; C < c->cnt; ++C) {
+          int k[4];
+          double pl[4];
+          for (int q = 0; q < 4; ++q) {
+            k[q] = c->cv2d[c->ctets[4 * C + q]];
+            pl[q] = k[q] >= 0 ? ph[k[q]] : 0.0;
+          }
+          const double* T = &c->h_tri[20 * C];
+          for (int j = 0; j < 4; ++j) {
+            if (k[j] < 0) continue;
+            double sacc = 0.0;
+            for (int m = 0; m < 4; ++m)
+              for (int l = 0; l < 4; ++l) sacc += T[ti.idx[j][m][l]] * pl[m] * pl[l];
+            fH[k[j]] += f * sacc;
+          }
+        }
+        ah4_apply(i, ph.data(), tmp.data());
+        for (int64_t k = 0; k < nH; ++k) fH[k] += f * (2.0 * t2 * tmp[k] + t2 * t2 * rhsv[k * N + i]);
+        symv(G, nH, ph.data(), tmp.data());
+        double g1 = dot(ph.data(), tmp.data(), nH);
+        double g2 = 0.0;
+        for (int64_t k = 0; k < nH; ++k) g2 += fb.ptW[k * N + i] * ph[k];
+        gsum += f * (g1 + 2.0 * t2 * g2 + t2 * t2 * fb.utW[i * N + i]);
+      }
+      const double fourpi = 4.0 * 3.14159265358979323846;
+      std::vector<double> r1(nH);
+      for (int64_t k = 0; k < nH; ++k) r1[k] = fourpi * fH[k] - fb.liftH[k];
+      double r2 = fourpi * gsum - fb.liftT;
+      forward(c->h_Kh_chol, nH, r1.data());
+      backward(c->h_Kh_chol, nH, r1.data());
+      double t1 = (r2 - dot(fb.d.data(), r1.data(), nH)) / schur;
+      for (int64_t k = 0; k < nH; ++k) wH[k] = r1[k] - yd[k] * t1;
+      th1 = t1;
+    }
+    // (c) ||Phi^{s+1} - Phi^s||_{H^1} in the basis [P, u_i]
+    double d2 = 0.0;
+    std::vector<double> dp(nH), kd(nH);
+    for (int i = 0; i < N; ++i) {
+      for (int64_t k = 0; k < nH; ++k) dp[k] = phiH[k * N + i] - phiH_old[k * N + i];
+      double dt = theta2[i] - theta2_old[i];
+      symv(KpM, nH, dp.data(), kd.data());
+      double cross = 0.0;
+      for (int64_t k = 0; k < nH; ++k) cross += dp[k] * (fb.ptK[k * N + i] + fb.ptM[k * N + i]);
+      d2 += dot(dp.data(), kd.data(), nH) + 2.0 * dt * cross + dt * dt * (fb.utK[i * N + i] + fb.utM[i * N + i]);
+    }
+    diff = std::sqrt(std::max(d2, 0.0));
+    phiH_old = phiH;
+    theta2_old = theta2;
+    if (!hart || diff < c->opt.inner_tol) break;
+    if (s == maxit - 1) st = MLC_WARN_INNER_MAXIT;
+  }
+  out.lam = lam;
+  out.phiH = phiH;
+  out.theta2 = theta2;
+  out.wH = wH;
+  out.theta1 = th1;
+  out.iters = its;
+  out.last_diff = diff;
+  out.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+}  // namespace mlc

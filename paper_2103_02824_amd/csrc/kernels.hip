@@ -1,0 +1,966 @@
+// gfx950 kernels of the fine-mesh correction step.
+//
+// Layouts (all device memory comes from the caller's workspace):
+//   orbital blocks  n x N row-major, orbital index fastest, so the N values of
+//                   one DoF are one contiguous 8N-byte segment;
+//   fields at quadrature points  nt x 4 (4-point rule, barycentric (a,b,b,b));
+//   operators       CSR over interior DoFs, int32 indices, FP64 values.
+//
+// Every reduction is two-stage and ordered (block partials, then one block
+// summing partials in block order), so results are bitwise reproducible from
+// run to run. No atomics are used.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mlc_internal.h"
+
+namespace mlc {
+
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ double Lq(int q, int j) { return q == j ? QA : QB; }
+
+// Ordered in-block reduction of R rows x N columns held in sd[row*N + col];
+// leaves the column sums in sd[col].
+__device__ __forceinline__ void block_reduce_cols(double* sd, int R, int N) {
+  int t = threadIdx.x;
+  int m = R;
+  while (m > 1) {
+    int h = (m + 1) >> 1;
+    __syncthreads();
+    if (t < (m - h) * N) sd[t] += sd[t + h * N];
+    m = h;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Exchange-correlation: LDA = Slater exchange + Perdew-Zunger 1981 correlation
+// with the constants printed in Section 4; V_xc = eps + rho d eps/d rho in the
+// closed forms eps_x * 4/3 and, for correlation,
+//   r_s >= 1: v_c = eps_c (1 + 7/6 b1 sqrt(rs) + 4/3 b2 rs) / (1 + b1 sqrt(rs) + b2 rs)
+//   r_s <  1: v_c = A ln rs + (B - A/3) + (2/3) C rs ln rs + (2D - C)/3 rs.
+// X-alpha: v = -3/2 alpha (3 rho / pi)^(1/3), eps = 3/4 v.
+__device__ __forceinline__ void xc_point(int kind, double xalpha, double rho, double* eps, double* v) {
+  if (kind == 0 || !(rho > 1e-30)) {
+    *eps = 0.0;
+    *v = 0.0;
+    return;
+  }
+  const double pi = 3.14159265358979323846;
+  double c13 = cbrt(rho);
+  if (kind == 2) {
+    double vv = -1.5 * xalpha * cbrt(3.0 / pi) * c13;
+    *v = vv;
+    *eps = 0.75 * vv;
+    return;
+  }
+  double ex = -0.75 * cbrt(3.0 / pi) * c13;
+  double vx = ex * (4.0 / 3.0);
+  double rs = cbrt(3.0 / (4.0 * pi * rho));
+  double ec, vc;
+  if (rs >= 1.0) {
+    const double g = -0.1423, b1 = 1.0529, b2 = 0.3334;
+    double sq = sqrt(rs);
+    double den = 1.0 + b1 * sq + b2 * rs;
+    ec = g / den;
+    vc = ec * (1.0 + (7.0 / 6.0) * b1 * sq + (4.0 / 3.0) * b2 * rs) / den;
+  } else {
+    const double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
+    double lr = log(rs);
+    ec = A * lr + B + C * rs * lr + D * rs;
+    vc = A * lr + (B - A / 3.0) + (2.0 / 3.0) * C * rs * lr + ((2.0 * D - C) / 3.0) * rs;
+  }
+  *eps = ex + ec;
+  *v = vx + vc;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(TPB) k_vext(int64_t nt, const double* __restrict__ qpx, int n_nuclei,
+                                              const double* __restrict__ RZ, int kind, double rc,
+                                              double omega, double* __restrict__ vext) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= nt * 4) return;
+  double x = qpx[3 * i], y = qpx[3 * i + 1], z = qpx[3 * i + 2];
+  double v = 0.0;
+  if (kind == 2) {
+    v = 0.5 * omega * omega * (x * x + y * y + z * z);
+  } else {
+    for (int k = 0; k < n_nuclei; ++k) {
+      double dx = x - RZ[4 * k], dy = y - RZ[4 * k + 1], dz = z - RZ[4 * k + 2], Zk = RZ[4 * k + 3];
+      double r = sqrt(dx * dx + dy * dy + dz * dz);
+      if (kind == 1) {
+        v -= Zk / r;
+      } else {
+        // -Z erf(r/rc)/r, with its r -> 0 limit -2Z/(sqrt(pi) rc)
+        if (r < 1e-12)
+          v -= Zk * 1.12837916709551257390 / rc;
+        else
+          v -= Zk * erf(r / rc) / r;
+      }
+    }
+  }
+  vext[i] = v;
+}
+
+// rho(q) = sum_i f_i phi_i(q)^2 for one tet; phi from nodal interior values.
+__device__ __forceinline__ void tet_density(const int32_t* __restrict__ tets, const int32_t* __restrict__ v2d,
+                                            const double* __restrict__ X, int N, const double* __restrict__ occ,
+                                            int64_t t, double rho[4]) {
+  int dof[4];
+  for (int j = 0; j < 4; ++j) dof[j] = v2d[tets[4 * t + j]];
+  for (int q = 0; q < 4; ++q) rho[q] = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double u[4];
+    for (int j = 0; j < 4; ++j) u[j] = dof[j] >= 0 ? X[(int64_t)dof[j] * N + i] : 0.0;
+    double s = u[0] + u[1] + u[2] + u[3];
+    double f = occ[i];
+    for (int q = 0; q < 4; ++q) {
+      double uq = QB * s + (QA - QB) * u[q];
+      rho[q] += f * uq * uq;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_qp_density(int64_t nt, const int32_t* __restrict__ tets,
+                                                    const int32_t* __restrict__ v2d, const double* __restrict__ X,
+                                                    int N, const double* __restrict__ occ,
+                                                    double* __restrict__ rho_out) {
+  int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= nt) return;
+  double rho[4];
+  tet_density(tets, v2d, X, N, occ, t, rho);
+  for (int q = 0; q < 4; ++q) rho_out[4 * t + q] = rho[q];
+}
+
+// Per tet: rho^l, V_xc, eps_xc, V_eff = V_ext + w^l + V_xc at the 4 points;
+// block partials of the multipole raw moments (10) and of min V_eff.
+constexpr int NMOM = 11;  // Q, Dx,Dy,Dz, Sxx,Syy,Szz,Sxy,Sxz,Syz, min veff
+__global__ void __launch_bounds__(TPB) k_qp_fields(int64_t nt, const int32_t* __restrict__ tets,
+                                                   const int32_t* __restrict__ v2d, const double* __restrict__ Phi,
+                                                   int N, const double* __restrict__ occ,
+                                                   const double* __restrict__ wnod, const double* __restrict__ vext,
+                                                   const double* __restrict__ geo, const double* __restrict__ qpx,
+                                                   int xck, double xalpha, double* __restrict__ vxc,
+                                                   double* __restrict__ exc, double* __restrict__ veff,
+                                                   double* __restrict__ rho_out, double* __restrict__ partials) {
+  __shared__ double sd[TPB];
+  int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  double mom[NMOM];
+  for (int k = 0; k < NMOM - 1; ++k) mom[k] = 0.0;
+  mom[NMOM - 1] = 1e300;
+  if (t < nt) {
+    double rho[4];
+    tet_density(tets, v2d, Phi, N, occ, t, rho);
+    double wv[4];
+    for (int j = 0; j < 4; ++j) wv[j] = wnod[tets[4 * t + j]];
+    double ws = wv[0] + wv[1] + wv[2] + wv[3];
+    double wq4 = 0.25 * geo[16 * t];
+    for (int q = 0; q < 4; ++q) {
+      double e, v;
+      xc_point(xck, xalpha, rho[q], &e, &v);
+      double wq = QB * ws + (QA - QB) * wv[q];
+      double ve = vext[4 * t + q] + wq + v;
+      vxc[4 * t + q] = v;
+      exc[4 * t + q] = e;
+      veff[4 * t + q] = ve;
+      rho_out[4 * t + q] = rho[q];
+      double m = wq4 * rho[q];
+      double x = qpx[12 * t + 3 * q], y = qpx[12 * t + 3 * q + 1], z = qpx[12 * t + 3 * q + 2];
+      mom[0] += m;
+      mom[1] += m * x;
+      mom[2] += m * y;
+      mom[3] += m * z;
+      mom[4] += m * x * x;
+      mom[5] += m * y * y;
+      mom[6] += m * z * z;
+      mom[7] += m * x * y;
+      mom[8] += m * x * z;
+      mom[9] += m * y * z;
+      mom[10] = fmin(mom[10], ve);
+    }
+  }
+  for (int k = 0; k < NMOM; ++k) {
+    __syncthreads();
+    sd[threadIdx.x] = mom[k];
+    for (int s = TPB / 2; s > 0; s >>= 1) {
+      __syncthreads();
+      if ((int)threadIdx.x < s) {
+        if (k == NMOM - 1)
+          sd[threadIdx.x] = fmin(sd[threadIdx.x], sd[threadIdx.x + s]);
+        else
+          sd[threadIdx.x] += sd[threadIdx.x + s];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * NMOM + k] = sd[0];
+  }
+}
+
+// Sum (or min for the last value when minlast) over nblk partial rows.
+__global__ void __launch_bounds__(TPB) k_reduce_rows(const double* __restrict__ partials, int nblk, int nvals,
+                                                     int minlast, double* __restrict__ out) {
+  __shared__ double sd[TPB];
+  for (int k = 0; k < nvals; ++k) {
+    bool mn = minlast && k == nvals - 1;
+    double acc = mn ? 1e300 : 0.0;
+    for (int b = threadIdx.x; b < nblk; b += TPB) {
+      double v = partials[(int64_t)b * nvals + k];
+      acc = mn ? fmin(acc, v) : acc + v;
+    }
+    __syncthreads();
+    sd[threadIdx.x] = acc;
+    for (int s = TPB / 2; s > 0; s >>= 1) {
+      __syncthreads();
+      if ((int)threadIdx.x < s) sd[threadIdx.x] = mn ? fmin(sd[threadIdx.x], sd[threadIdx.x + s]) : sd[threadIdx.x] + sd[threadIdx.x + s];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) out[k] = sd[0];
+  }
+}
+
+// Multipole Dirichlet data at boundary vertices from raw moments about the
+// origin, shifted to the charge centroid c:
+//   g = Q/r + p.r/r^3 + 1/2 r.Qt.r / r^5, Qt traceless, r = x - c.
+__global__ void __launch_bounds__(TPB) k_boundary_g(int64_t nb, const int32_t* __restrict__ bverts,
+                                                    const double* __restrict__ xyz, const double* __restrict__ mom,
+                                                    double* __restrict__ g) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= nb) return;
+  double Q = mom[0];
+  double c[3] = {mom[1] / Q, mom[2] / Q, mom[3] / Q};
+  double p[3] = {mom[1] - Q * c[0], mom[2] - Q * c[1], mom[3] - Q * c[2]};
+  double S[3][3] = {{mom[4], mom[7], mom[8]}, {mom[7], mom[5], mom[9]}, {mom[8], mom[9], mom[6]}};
+  double Sc[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Sc[a][b] = S[a][b] - c[a] * mom[1 + b] - c[b] * mom[1 + a] + Q * c[a] * c[b];
+  double tr = Sc[0][0] + Sc[1][1] + Sc[2][2];
+  int v = bverts[i];
+  double r[3] = {xyz[3 * v] - c[0], xyz[3 * v + 1] - c[1], xyz[3 * v + 2] - c[2]};
+  double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  double rn = sqrt(r2);
+  double quad = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) quad += r[a] * (3.0 * Sc[a][b] - (a == b ? tr : 0.0)) * r[b];
+  double pr = p[0] * r[0] + p[1] * r[1] + p[2] * r[2];
+  g[v] = Q / rn + pr / (r2 * rn) + 0.5 * quad / (r2 * r2 * rn);
+}
+
+// out(t,q) = sum_j L[q][j] val(v_j) + add1(t,q) + add2(t,q), with
+// val(v) = nod[v] (if nod) + dofv[v2d[v]] (if dofv and v is interior).
+__global__ void __launch_bounds__(TPB) k_field(int64_t nt, const int32_t* __restrict__ tets,
+                                               const double* __restrict__ nod, const int32_t* __restrict__ v2d,
+                                               const double* __restrict__ dofv, const double* __restrict__ add1,
+                                               const double* __restrict__ add2, double* __restrict__ out) {
+  int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= nt) return;
+  double u[4];
+  for (int j = 0; j < 4; ++j) {
+    int v = tets[4 * t + j];
+    double a = nod ? nod[v] : 0.0;
+    if (dofv) {
+      int d = v2d[v];
+      if (d >= 0) a += dofv[d];
+    }
+    u[j] = a;
+  }
+  double s = u[0] + u[1] + u[2] + u[3];
+  for (int q = 0; q < 4; ++q) {
+    double o = QB * s + (QA - QB) * u[q];
+    if (add1) o += add1[4 * t + q];
+    if (add2) o += add2[4 * t + q];
+    out[4 * t + q] = o;
+  }
+}
+
+// Row-wise assembly on the interior CSR pattern, one thread per row:
+//   val1 = cK1 K + M_{f1} + cM1 M      (f1 may be null)
+//   val2 = cK2 K + M_{f2}              (optional)
+// and dinv1 = 1/diag(val1) (optional). Each thread owns its row, so the
+// element contributions are summed in a fixed (adjacency) order.
+__global__ void __launch_bounds__(TPB) k_assemble(int64_t n, const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ adj_ptr,
+                                                  const int32_t* __restrict__ adj_tet,
+                                                  const int8_t* __restrict__ adj_loc,
+                                                  const int32_t* __restrict__ adj_pos, const double* __restrict__ geo,
+                                                  double cK1, const double* __restrict__ f1, double cM1,
+                                                  double* __restrict__ val1, double* __restrict__ dinv1, double cK2,
+                                                  const double* __restrict__ f2, double* __restrict__ val2) {
+  int64_t a = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (a >= n) return;
+  int r0 = rowptr[a], r1 = rowptr[a + 1];
+  for (int j = r0; j < r1; ++j) {
+    val1[j] = 0.0;
+    if (val2) val2[j] = 0.0;
+  }
+  int diag_slot = -1;
+  for (int e = adj_ptr[a]; e < adj_ptr[a + 1]; ++e) {
+    int64_t t = adj_tet[e];
+    int la = adj_loc[e];
+    const double* G = geo + 16 * t;
+    double vol = G[0];
+    double ga[3] = {G[1 + 3 * la], G[2 + 3 * la], G[3 + 3 * la]};
+    double fa[4], fb[4];
+    for (int q = 0; q < 4; ++q) {
+      double w = 0.25 * vol * Lq(q, la);
+      fa[q] = f1 ? w * f1[4 * t + q] : 0.0;
+      fb[q] = f2 ? w * f2[4 * t + q] : 0.0;
+    }
+    double m1base = 0.25 * vol;
+    for (int lb = 0; lb < 4; ++lb) {
+      int pos = adj_pos[4 * (int64_t)e + lb];
+      if (pos < 0) continue;
+      if (lb == la) diag_slot = pos;
+      double kv = vol * (ga[0] * G[1 + 3 * lb] + ga[1] * G[2 + 3 * lb] + ga[2] * G[3 + 3 * lb]);
+      double mf = 0.0, mg = 0.0, mm = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        double lb_q = Lq(q, lb);
+        mf += fa[q] * lb_q;
+        mg += fb[q] * lb_q;
+        mm += m1base * Lq(q, la) * lb_q;
+      }
+      val1[r0 + pos] += cK1 * kv + mf + cM1 * mm;
+      if (val2) val2[r0 + pos] += cK2 * kv + mg;
+    }
+  }
+  if (dinv1 && diag_slot >= 0) dinv1[a] = 1.0 / val1[r0 + diag_slot];
+}
+
+// Load vector, one thread per interior row:
+//   b_a  = scale * int f phi_a  -  l_a,   l_a = sum_{boundary b} K_ab g_b.
+__global__ void __launch_bounds__(TPB) k_load(int64_t n, const int32_t* __restrict__ adj_ptr,
+                                              const int32_t* __restrict__ adj_tet, const int8_t* __restrict__ adj_loc,
+                                              const int32_t* __restrict__ tets, const double* __restrict__ geo,
+                                              const double* __restrict__ f, double scale,
+                                              const double* __restrict__ gnod, const int32_t* __restrict__ v2d,
+                                              double* __restrict__ b, double* __restrict__ lvec) {
+  int64_t a = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (a >= n) return;
+  double load = 0.0, lift = 0.0;
+  for (int e = adj_ptr[a]; e < adj_ptr[a + 1]; ++e) {
+    int64_t t = adj_tet[e];
+    int la = adj_loc[e];
+    const double* G = geo + 16 * t;
+    double vol = G[0];
+    for (int q = 0; q < 4; ++q) load += 0.25 * vol * f[4 * t + q] * Lq(q, la);
+    if (gnod) {
+      for (int lb = 0; lb < 4; ++lb) {
+        int v = tets[4 * t + lb];
+        if (v2d[v] >= 0) continue;
+        double kv = vol * (G[1 + 3 * la] * G[1 + 3 * lb] + G[2 + 3 * la] * G[2 + 3 * lb] +
+                           G[3 + 3 * la] * G[3 + 3 * lb]);
+        lift += kv * gnod[v];
+      }
+    }
+  }
+  b[a] = scale * load - lift;
+  if (lvec) lvec[a] = lift;
+}
+
+// ---------------------------------------------------------------------------
+// Multi-right-hand-side CSR SpMM  Y = A X  (X, Y: n x N row-major).
+// A block holds R rows x N columns; thread (row, col) walks the row and
+// gathers X[col_j, c]. The N threads of a row read the same index/value
+// (one broadcast transaction) and N consecutive doubles of X per nonzero.
+// Optional epilogue: per-column block partials of X . Y (CG curvature).
+__global__ void __launch_bounds__(TPB) k_spmm(int64_t n, int N, int R, const int32_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ col, const double* __restrict__ val,
+                                              const double* __restrict__ X, double* __restrict__ Y,
+                                              double* __restrict__ partial) {
+  __shared__ double sd[TPB];
+  int t = threadIdx.x;
+  int rl = t / N, c = t - rl * N;
+  int64_t r = (int64_t)blockIdx.x * R + rl;
+  double dot = 0.0;
+  if (rl < R && r < n) {
+    int j0 = rowptr[r], j1 = rowptr[r + 1];
+    double acc = 0.0;
+    for (int j = j0; j < j1; ++j) acc += val[j] * X[(int64_t)col[j] * N + c];
+    Y[r * N + c] = acc;
+    if (partial) dot = acc * X[r * N + c];
+  }
+  if (partial) {
+    sd[t] = dot;
+    block_reduce_cols(sd, R, N);
+    if (t < N) partial[(int64_t)blockIdx.x * N + t] = sd[t];
+  }
+}
+
+// Y[r,c] = s[c] * X[r,c]
+__global__ void __launch_bounds__(TPB) k_scale_cols_to(int64_t total, int N, const double* __restrict__ X,
+                                                       const double* __restrict__ s, double* __restrict__ Y) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= total) return;
+  Y[i] = s[i % N] * X[i];
+}
+
+// CG start: R = B - AX, P = Dinv R; partials rz, rr, bb per column.
+__global__ void __launch_bounds__(TPB) k_cg_init(int64_t n, int N, int R, const double* __restrict__ B,
+                                                 const double* __restrict__ AX, const double* __restrict__ dinv,
+                                                 double* __restrict__ Rv, double* __restrict__ P,
+                                                 double* __restrict__ partial) {
+  __shared__ double sd[TPB];
+  int t = threadIdx.x;
+  int rl = t / N, c = t - rl * N;
+  int64_t r = (int64_t)blockIdx.x * R + rl;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (rl < R && r < n) {
+    int64_t i = r * N + c;
+    double b = B[i];
+    double rr = b - AX[i];
+    double z = dinv[r] * rr;
+    Rv[i] = rr;
+    P[i] = z;
+    v[0] = rr * z;
+    v[1] = rr * rr;
+    v[2] = b * b;
+  }
+  for (int k = 0; k < 3; ++k) {
+    __syncthreads();
+    sd[t] = v[k];
+    block_reduce_cols(sd, R, N);
+    if (t < N) partial[((int64_t)blockIdx.x * 3 + k) * N + t] = sd[t];
+  }
+}
+
+// scal layout (per column c): [0] rz [1] alpha [2] beta [3] rr [4] bb [5] active [6] pq
+// CG update: X += a P, R -= a Q; partials r.z and r.r per column.
+__global__ void __launch_bounds__(TPB) k_cg_update(int64_t n, int N, int R, const double* __restrict__ scal,
+                                                   const double* __restrict__ dinv, double* __restrict__ X,
+                                                   double* __restrict__ Rv, const double* __restrict__ P,
+                                                   const double* __restrict__ Q, double* __restrict__ partial) {
+  __shared__ double sd[TPB];
+  int t = threadIdx.x;
+  int rl = t / N, c = t - rl * N;
+  int64_t r = (int64_t)blockIdx.x * R + rl;
+  double v[2] = {0.0, 0.0};
+  if (rl < R && r < n) {
+    int64_t i = r * N + c;
+    double a = scal[N + c];
+    double x = X[i] + a * P[i];
+    double rr = Rv[i] - a * Q[i];
+    X[i] = x;
+    Rv[i] = rr;
+    v[0] = rr * dinv[r] * rr;
+    v[1] = rr * rr;
+  }
+  for (int k = 0; k < 2; ++k) {
+    __syncthreads();
+    sd[t] = v[k];
+    block_reduce_cols(sd, R, N);
+    if (t < N) partial[((int64_t)blockIdx.x * 2 + k) * N + t] = sd[t];
+  }
+}
+
+// P = Dinv R + beta P
+__global__ void __launch_bounds__(TPB) k_cg_direction(int64_t total, int N, const double* __restrict__ scal,
+                                                      const double* __restrict__ dinv, const double* __restrict__ Rv,
+                                                      double* __restrict__ P) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= total) return;
+  int c = (int)(i % N);
+  int64_t r = i / N;
+  P[i] = dinv[r] * Rv[i] + scal[2 * N + c] * P[i];
+}
+
+// Per-column CG scalars from block partials (one block, ordered sums).
+//   phase 0: partial = [rz, rr, bb] -> rz, rr, bb, active
+//   phase 1: partial = [pq]         -> alpha (0 for inactive columns)
+//   phase 2: partial = [rz', rr]    -> beta, rz, rr, active
+// flags[0] = number of active columns, flags[1] |= breakdown (pq <= 0).
+__global__ void __launch_bounds__(TPB) k_cg_scalars(int N, int nblk, const double* __restrict__ partial,
+                                                    int phase, double rtol2, double* __restrict__ scal,
+                                                    int32_t* __restrict__ flags) {
+  __shared__ double sd[TPB];
+  int nv = phase == 0 ? 3 : (phase == 1 ? 1 : 2);
+  __shared__ double sums[3 * MLC_MAX_ORBITALS];
+  for (int c = 0; c < N; ++c) {
+    for (int k = 0; k < nv; ++k) {
+      double acc = 0.0;
+      for (int b = threadIdx.x; b < nblk; b += TPB) acc += partial[((int64_t)b * nv + k) * N + c];
+      __syncthreads();
+      sd[threadIdx.x] = acc;
+      for (int s = TPB / 2; s > 0; s >>= 1) {
+        __syncthreads();
+        if ((int)threadIdx.x < s) sd[threadIdx.x] += sd[threadIdx.x + s];
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) sums[k * N + c] = sd[0];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int nact = 0;
+    for (int c = 0; c < N; ++c) {
+      if (phase == 0) {
+        scal[c] = sums[c];
+        scal[3 * N + c] = sums[N + c];
+        scal[4 * N + c] = sums[2 * N + c];
+        scal[2 * N + c] = 0.0;
+        bool act = sums[N + c] > rtol2 * sums[2 * N + c];
+        scal[5 * N + c] = act ? 1.0 : 0.0;
+        nact += act;
+      } else if (phase == 1) {
+        double pq = sums[c];
+        scal[6 * N + c] = pq;
+        bool act = scal[5 * N + c] != 0.0;
+        if (act && !(pq > 0.0)) {
+          flags[1] = 1;
+          act = false;
+          scal[5 * N + c] = 0.0;
+        }
+        scal[N + c] = act ? scal[c] / pq : 0.0;
+      } else {
+        bool act = scal[5 * N + c] != 0.0;
+        double rzn = sums[c];
+        scal[2 * N + c] = act ? rzn / scal[c] : 0.0;
+        if (act) {
+          scal[c] = rzn;
+          scal[3 * N + c] = sums[N + c];
+        }
+        act = act && (sums[N + c] > rtol2 * scal[4 * N + c]);
+        scal[5 * N + c] = act ? 1.0 : 0.0;
+        nact += act;
+      }
+    }
+    if (phase != 1) flags[0] = nact;
+  }
+}
+
+// Per-column block partials of sum_r X[r,c] Y[r,c].
+__global__ void __launch_bounds__(TPB) k_coldot(int64_t n, int N, int R, const double* __restrict__ X,
+                                                const double* __restrict__ Y, double* __restrict__ partial) {
+  __shared__ double sd[TPB];
+  int t = threadIdx.x;
+  int rl = t / N, c = t - rl * N;
+  int64_t r = (int64_t)blockIdx.x * R + rl;
+  double v = 0.0;
+  if (rl < R && r < n) v = X[r * N + c] * Y[r * N + c];
+  sd[t] = v;
+  block_reduce_cols(sd, R, N);
+  if (t < N) partial[(int64_t)blockIdx.x * N + t] = sd[t];
+}
+
+// out[c] = sum over blocks of partial[b*N + c] (ordered).
+__global__ void __launch_bounds__(TPB) k_reduce_cols(int N, int nblk, const double* __restrict__ partial,
+                                                     double* __restrict__ out) {
+  __shared__ double sd[TPB];
+  for (int c = 0; c < N; ++c) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += TPB) acc += partial[(int64_t)b * N + c];
+    __syncthreads();
+    sd[threadIdx.x] = acc;
+    for (int s = TPB / 2; s > 0; s >>= 1) {
+      __syncthreads();
+      if ((int)threadIdx.x < s) sd[threadIdx.x] += sd[threadIdx.x + s];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) out[c] = sd[0];
+  }
+}
+
+// X[:,c] /= sqrt(s[c])
+__global__ void __launch_bounds__(TPB) k_normalize_cols(int64_t total, int N, const double* __restrict__ s,
+                                                        double* __restrict__ X) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= total) return;
+  X[i] = X[i] / sqrt(s[i % N]);
+}
+
+// out[k, c] = sum_{a in P^T row k} w_a Y[a, c]  (restriction P^T Y, gather form)
+__global__ void __launch_bounds__(TPB) k_restrict(int64_t nH, int N, const int32_t* __restrict__ PTptr,
+                                                  const int32_t* __restrict__ PTidx, const double* __restrict__ PTw,
+                                                  const double* __restrict__ Y, double* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= nH * N) return;
+  int64_t k = i / N;
+  int c = (int)(i - k * N);
+  double acc = 0.0;
+  for (int e = PTptr[k]; e < PTptr[k + 1]; ++e) acc += PTw[e] * Y[(int64_t)PTidx[e] * N + c];
+  out[i] = acc;
+}
+
+// Gram block U^T Y (N x N): each block sums a 256-row chunk for every (i,j)
+// pair; ordered reduction of block partials afterwards.
+constexpr int GRAM_ROWS = 256;
+__global__ void __launch_bounds__(TPB) k_gram(int64_t n, int N, const double* __restrict__ U,
+                                              const double* __restrict__ Y, double* __restrict__ partial) {
+  int64_t r0 = (int64_t)blockIdx.x * GRAM_ROWS;
+  int64_t r1 = r0 + GRAM_ROWS < n ? r0 + GRAM_ROWS : n;
+  int NN = N * N;
+  for (int p = threadIdx.x; p < NN; p += TPB) {
+    int i = p / N, j = p - (p / N) * N;
+    double acc = 0.0;
+    for (int64_t r = r0; r < r1; ++r) acc += U[r * N + i] * Y[r * N + j];
+    partial[(int64_t)blockIdx.x * NN + p] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-pattern integrals, one thread per coarse tet, looping over the fine
+// tets inside it (nested meshes: coarse hats are linear on every fine tet,
+// psi_j = sum_a Bc[a][j] phi_a with Bc the coarse barycentrics of the fine
+// vertices). Results are 4x4 symmetric blocks in coarse local numbering,
+// stored as the 10 entries (j<=k) in order (0,0)(0,1)(0,2)(0,3)(1,1)...(3,3).
+__device__ __forceinline__ void coarse_bary(const double* __restrict__ cg, const double* __restrict__ xyz, int v,
+                                            double b[4]) {
+  double dx = xyz[3 * v] - cg[0], dy = xyz[3 * v + 1] - cg[1], dz = xyz[3 * v + 2] - cg[2];
+  b[1] = cg[3] * dx + cg[4] * dy + cg[5] * dz;
+  b[2] = cg[6] * dx + cg[7] * dy + cg[8] * dz;
+  b[3] = cg[9] * dx + cg[10] * dy + cg[11] * dz;
+  b[0] = 1.0 - b[1] - b[2] - b[3];
+}
+
+// Operators: [A_fix = 1/2 K + M_{fA}] [M_{fW}] [M] [K] -> 40 values per coarse tet.
+__global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* __restrict__ grp_ptr,
+                                                    const int32_t* __restrict__ grp_tet,
+                                                    const int32_t* __restrict__ tets, const double* __restrict__ geo,
+                                                    const double* __restrict__ xyz, const double* __restrict__ cgeo,
+                                                    const double* __restrict__ fA, const double* __restrict__ fW,
+                                                    double* __restrict__ out) {
+  int64_t C = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (C >= cnt) return;
+  double acc[40];
+  for (int k = 0; k < 40; ++k) acc[k] = 0.0;
+  const double* cg = cgeo + 12 * C;
+  for (int e = grp_ptr[C]; e < grp_ptr[C + 1]; ++e) {
+    int64_t t = grp_tet[e];
+    const double* G = geo + 16 * t;
+    double vol = G[0];
+    double Bc[4][4];
+    for (int a = 0; a < 4; ++a) coarse_bary(cg, xyz, tets[4 * t + a], Bc[a]);
+    // coarse hat gradients restricted to this fine tet and values at qp
+    double gc[4][3], pq[4][4];
+    for (int j = 0; j < 4; ++j) {
+      for (int x = 0; x < 3; ++x) {
+        double s = 0.0;
+        for (int a = 0; a < 4; ++a) s += Bc[a][j] * G[1 + 3 * a + x];
+        gc[j][x] = s;
+      }
+      double s = Bc[0][j] + Bc[1][j] + Bc[2][j] + Bc[3][j];
+      for (int q = 0; q < 4; ++q) pq[q][j] = QB * s + (QA - QB) * Bc[q][j];
+    }
+    double wA[4], wW[4];
+    for (int q = 0; q < 4; ++q) {
+      wA[q] = 0.25 * vol * (fA ? fA[4 * t + q] : 0.0);
+      wW[q] = 0.25 * vol * (fW ? fW[4 * t + q] : 0.0);
+    }
+    int k = 0;
+    for (int j = 0; j < 4; ++j)
+      for (int m = j; m < 4; ++m, ++k) {
+        double kv = vol * (gc[j][0] * gc[m][0] + gc[j][1] * gc[m][1] + gc[j][2] * gc[m][2]);
+        double mA = 0.0, mW = 0.0, mM = 0.0;
+        for (int q = 0; q < 4; ++q) {
+          double pp = pq[q][j] * pq[q][m];
+          mA += wA[q] * pp;
+          mW += wW[q] * pp;
+          mM += 0.25 * vol * pp;
+        }
+        acc[k] += 0.5 * kv + mA;
+        acc[10 + k] += mW;
+        acc[20 + k] += mM;
+        acc[30 + k] += kv;
+      }
+  }
+  for (int k = 0; k < 40; ++k) out[40 * C + k] = acc[k];
+}
+
+// Per orbital: A_h4 entries int u psi_j psi_k (10) and rhs int u^2 psi_j (4).
+__global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, const int32_t* __restrict__ grp_ptr,
+                                                    const int32_t* __restrict__ grp_tet,
+                                                    const int32_t* __restrict__ tets, const double* __restrict__ geo,
+                                                    const double* __restrict__ xyz, const double* __restrict__ cgeo,
+                                                    const int32_t* __restrict__ v2d, const double* __restrict__ U,
+                                                    int N, double* __restrict__ out) {
+  int64_t id = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (id >= cnt * N) return;
+  int64_t C = id / N;
+  int i = (int)(id - C * N);
+  double acc[14];
+  for (int k = 0; k < 14; ++k) acc[k] = 0.0;
+  const double* cg = cgeo + 12 * C;
+  for (int e = grp_ptr[C]; e < grp_ptr[C + 1]; ++e) {
+    int64_t t = grp_tet[e];
+    double vol = geo[16 * t];
+    double Bc[4][4], u[4];
+    for (int a = 0; a < 4; ++a) {
+      int v = tets[4 * t + a];
+      coarse_bary(cg, xyz, v, Bc[a]);
+      int d = v2d[v];
+      u[a] = d >= 0 ? U[(int64_t)d * N + i] : 0.0;
+    }
+    double us = u[0] + u[1] + u[2] + u[3];
+    for (int q = 0; q < 4; ++q) {
+      double uq = QB * us + (QA - QB) * u[q];
+      double ps[4];
+      for (int j = 0; j < 4; ++j) {
+        double s = Bc[0][j] + Bc[1][j] + Bc[2][j] + Bc[3][j];
+        ps[j] = QB * s + (QA - QB) * Bc[q][j];
+      }
+      double w = 0.25 * vol;
+      int k = 0;
+      for (int j = 0; j < 4; ++j)
+        for (int m = j; m < 4; ++m, ++k) acc[k] += w * uq * ps[j] * ps[m];
+      for (int j = 0; j < 4; ++j) acc[10 + j] += w * uq * uq * ps[j];
+    }
+  }
+  for (int k = 0; k < 14; ++k) out[14 * id + k] = acc[k];
+}
+
+// Trilinear tensor T_jkm = int psi_j psi_k psi_m (fine quadrature), 20 entries
+// (j<=k<=m) per coarse tet.
+__global__ void __launch_bounds__(TPB) k_coarse_tri(int64_t cnt, const int32_t* __restrict__ grp_ptr,
+                                                    const int32_t* __restrict__ grp_tet,
+                                                    const int32_t* __restrict__ tets, const double* __restrict__ geo,
+                                                    const double* __restrict__ xyz, const double* __restrict__ cgeo,
+                                                    double* __restrict__ out) {
+  int64_t C = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (C >= cnt) return;
+  double acc[20];
+  for (int k = 0; k < 20; ++k) acc[k] = 0.0;
+  const double* cg = cgeo + 12 * C;
+  for (int e = grp_ptr[C]; e < grp_ptr[C + 1]; ++e) {
+    int64_t t = grp_tet[e];
+    double vol = geo[16 * t];
+    double Bc[4][4];
+    for (int a = 0; a < 4; ++a) coarse_bary(cg, xyz, tets[4 * t + a], Bc[a]);
+    for (int q = 0; q < 4; ++q) {
+      double ps[4];
+      for (int j = 0; j < 4; ++j) {
+        double s = Bc[0][j] + Bc[1][j] + Bc[2][j] + Bc[3][j];
+        ps[j] = QB * s + (QA - QB) * Bc[q][j];
+      }
+      double w = 0.25 * vol;
+      int k = 0;
+      for (int j = 0; j < 4; ++j)
+        for (int m = j; m < 4; ++m)
+          for (int l = m; l < 4; ++l, ++k) acc[k] += w * ps[j] * ps[m] * ps[l];
+    }
+  }
+  for (int k = 0; k < 20; ++k) out[20 * C + k] = acc[k];
+}
+
+// Phi[a,i] = sum_j Pw[a,j] phiH[Pk[a,j], i] + theta2[i] U[a,i]
+__global__ void __launch_bounds__(TPB) k_reconstruct(int64_t n, int N, const int32_t* __restrict__ Pk,
+                                                     const double* __restrict__ Pw, const double* __restrict__ phiH,
+                                                     const double* __restrict__ theta2, const double* __restrict__ U,
+                                                     double* __restrict__ Phi) {
+  int64_t id = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (id >= n * N) return;
+  int64_t a = id / N;
+  int i = (int)(id - a * N);
+  double s = 0.0;
+  for (int j = 0; j < 4; ++j) {
+    int k = Pk[4 * a + j];
+    if (k >= 0) s += Pw[4 * a + j] * phiH[(int64_t)k * N + i];
+  }
+  Phi[id] = s + theta2[i] * U[id];
+}
+
+// w(v) = g(v) + sum_j Pw[a,j] wH[Pk[a,j]] + theta1 w0[a]   (a = dof of v; boundary: g)
+__global__ void __launch_bounds__(TPB) k_hartree_nodal(int64_t nv, const int32_t* __restrict__ v2d,
+                                                       const int32_t* __restrict__ Pk, const double* __restrict__ Pw,
+                                                       const double* __restrict__ wH, double theta1,
+                                                       const double* __restrict__ w0, const double* __restrict__ g,
+                                                       double* __restrict__ w) {
+  int64_t v = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (v >= nv) return;
+  int a = v2d[v];
+  double s = g[v];
+  if (a >= 0) {
+    for (int j = 0; j < 4; ++j) {
+      int k = Pk[4 * (int64_t)a + j];
+      if (k >= 0) s += Pw[4 * (int64_t)a + j] * wH[k];
+    }
+    s += theta1 * w0[a];
+  }
+  w[v] = s;
+}
+
+__global__ void __launch_bounds__(TPB) k_rho_nodal(int64_t nv, const int32_t* __restrict__ v2d,
+                                                   const double* __restrict__ Phi, int N,
+                                                   const double* __restrict__ occ, double* __restrict__ rho) {
+  int64_t v = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (v >= nv) return;
+  int a = v2d[v];
+  double s = 0.0;
+  if (a >= 0)
+    for (int i = 0; i < N; ++i) {
+      double p = Phi[(int64_t)a * N + i];
+      s += occ[i] * p * p;
+    }
+  rho[v] = s;
+}
+
+// Energy pieces per block: [int rho, int (-1/2 w rho + rho (eps_xc(rho) - v_xc^l))]
+__global__ void __launch_bounds__(TPB) k_energy(int64_t nt, const int32_t* __restrict__ tets,
+                                                const int32_t* __restrict__ v2d, const double* __restrict__ Phi,
+                                                int N, const double* __restrict__ occ,
+                                                const double* __restrict__ wnod, const double* __restrict__ vxc_old,
+                                                const double* __restrict__ geo, int xck, double xalpha,
+                                                double* __restrict__ partials) {
+  __shared__ double sd[TPB];
+  int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (t < nt) {
+    double rho[4];
+    tet_density(tets, v2d, Phi, N, occ, t, rho);
+    double wv[4];
+    for (int j = 0; j < 4; ++j) wv[j] = wnod[tets[4 * t + j]];
+    double ws = wv[0] + wv[1] + wv[2] + wv[3];
+    double w4 = 0.25 * geo[16 * t];
+    for (int q = 0; q < 4; ++q) {
+      double e, vx;
+      xc_point(xck, xalpha, rho[q], &e, &vx);
+      double wq = QB * ws + (QA - QB) * wv[q];
+      v[0] += w4 * rho[q];
+      v[1] += w4 * (-0.5 * wq * rho[q] + rho[q] * (e - vxc_old[4 * t + q]));
+    }
+  }
+  for (int k = 0; k < 2; ++k) {
+    __syncthreads();
+    sd[threadIdx.x] = v[k];
+    for (int s = TPB / 2; s > 0; s >>= 1) {
+      __syncthreads();
+      if ((int)threadIdx.x < s) sd[threadIdx.x] += sd[threadIdx.x + s];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * 2 + k] = sd[0];
+  }
+}
+
+inline unsigned nb(int64_t work) { return (unsigned)((work + TPB - 1) / TPB); }
+
+}  // namespace
+
+// ============================================================================
+// Launchers
+int spmm_rows_per_block(int N) { return TPB / N; }
+int elem_blocks(int64_t n, int N) { return (int)((n + spmm_rows_per_block(N) - 1) / spmm_rows_per_block(N)); }
+int qp_blocks(int64_t nt) { return (int)nb(nt); }
+int gram_blocks(int64_t n) { return (int)((n + GRAM_ROWS - 1) / GRAM_ROWS); }
+
+void launch_vext(hipStream_t s, int64_t nt, const double* qpx, const double* RZ, int n_nuclei, int kind,
+                 double rc, double omega, double* vext) {
+  hipLaunchKernelGGL(k_vext, dim3(nb(nt * 4)), dim3(TPB), 0, s, nt, qpx, n_nuclei, RZ, kind, rc, omega, vext);
+}
+void launch_qp_density(hipStream_t s, int64_t nt, const int32_t* tets, const int32_t* v2d, const double* X, int N,
+                       const double* occ, double* rho_out) {
+  hipLaunchKernelGGL(k_qp_density, dim3(nb(nt)), dim3(TPB), 0, s, nt, tets, v2d, X, N, occ, rho_out);
+}
+void launch_qp_fields(hipStream_t s, int64_t nt, const int32_t* tets, const int32_t* v2d, const double* Phi, int N,
+                      const double* occ, const double* wnod, const double* vext, const double* geo,
+                      const double* qpx, int xck, double xalpha, double* vxc, double* exc, double* veff,
+                      double* rho, double* partials) {
+  hipLaunchKernelGGL(k_qp_fields, dim3(nb(nt)), dim3(TPB), 0, s, nt, tets, v2d, Phi, N, occ, wnod, vext, geo, qpx,
+                     xck, xalpha, vxc, exc, veff, rho, partials);
+}
+int nmom() { return NMOM; }
+void launch_reduce_rows(hipStream_t s, const double* partials, int nblk, int nvals, int minlast, double* out) {
+  hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(TPB), 0, s, partials, nblk, nvals, minlast, out);
+}
+void launch_boundary_g(hipStream_t s, int64_t nbv, const int32_t* bverts, const double* xyz, const double* mom,
+                       double* g) {
+  if (nbv == 0) return;
+  hipLaunchKernelGGL(k_boundary_g, dim3(nb(nbv)), dim3(TPB), 0, s, nbv, bverts, xyz, mom, g);
+}
+void launch_field(hipStream_t s, int64_t nt, const int32_t* tets, const double* nod, const int32_t* v2d,
+                  const double* dofv, const double* add1, const double* add2, double* out) {
+  hipLaunchKernelGGL(k_field, dim3(nb(nt)), dim3(TPB), 0, s, nt, tets, nod, v2d, dofv, add1, add2, out);
+}
+void launch_assemble(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* adj_ptr, const int32_t* adj_tet,
+                     const int8_t* adj_loc, const int32_t* adj_pos, const double* geo, double cK1, const double* f1,
+                     double cM1, double* val1, double* dinv1, double cK2, const double* f2, double* val2) {
+  hipLaunchKernelGGL(k_assemble, dim3(nb(n)), dim3(TPB), 0, s, n, rowptr, adj_ptr, adj_tet, adj_loc, adj_pos, geo,
+                     cK1, f1, cM1, val1, dinv1, cK2, f2, val2);
+}
+void launch_load(hipStream_t s, int64_t n, const int32_t* adj_ptr, const int32_t* adj_tet, const int8_t* adj_loc,
+                 const int32_t* tets, const double* geo, const double* f_qp, double scale, const double* gnod,
+                 const int32_t* v2d, double* b, double* lvec) {
+  hipLaunchKernelGGL(k_load, dim3(nb(n)), dim3(TPB), 0, s, n, adj_ptr, adj_tet, adj_loc, tets, geo, f_qp, scale,
+                     gnod, v2d, b, lvec);
+}
+void launch_spmm(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const double* val,
+                 const double* X, double* Y, double* partial) {
+  int R = spmm_rows_per_block(N);
+  hipLaunchKernelGGL(k_spmm, dim3(elem_blocks(n, N)), dim3(TPB), 0, s, n, N, R, rowptr, col, val, X, Y, partial);
+}
+void launch_scale_cols_to(hipStream_t s, int64_t n, int N, const double* X, const double* sc, double* Y) {
+  hipLaunchKernelGGL(k_scale_cols_to, dim3(nb(n * N)), dim3(TPB), 0, s, n * N, N, X, sc, Y);
+}
+void launch_cg_init(hipStream_t s, int64_t n, int N, const double* B, const double* AX, const double* dinv,
+                    double* Rv, double* P, double* partial) {
+  int R = spmm_rows_per_block(N);
+  hipLaunchKernelGGL(k_cg_init, dim3(elem_blocks(n, N)), dim3(TPB), 0, s, n, N, R, B, AX, dinv, Rv, P, partial);
+}
+void launch_cg_update(hipStream_t s, int64_t n, int N, const double* scal, const double* dinv, double* X, double* Rv,
+                      const double* P, const double* Q, double* partial) {
+  int R = spmm_rows_per_block(N);
+  hipLaunchKernelGGL(k_cg_update, dim3(elem_blocks(n, N)), dim3(TPB), 0, s, n, N, R, scal, dinv, X, Rv, P, Q,
+                     partial);
+}
+void launch_cg_direction(hipStream_t s, int64_t n, int N, const double* scal, const double* dinv, const double* Rv,
+                         double* P) {
+  hipLaunchKernelGGL(k_cg_direction, dim3(nb(n * N)), dim3(TPB), 0, s, n * N, N, scal, dinv, Rv, P);
+}
+void launch_cg_scalars(hipStream_t s, int N, int nblk, const double* partial, int phase, double rtol2, double* scal,
+                       int32_t* flags) {
+  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(TPB), 0, s, N, nblk, partial, phase, rtol2, scal, flags);
+}
+void launch_coldot(hipStream_t s, int64_t n, int N, const double* X, const double* Y, double* partial) {
+  int R = spmm_rows_per_block(N);
+  hipLaunchKernelGGL(k_coldot, dim3(elem_blocks(n, N)), dim3(TPB), 0, s, n, N, R, X, Y, partial);
+}
+void launch_reduce_cols(hipStream_t s, int N, int nblk, const double* partial, double* out) {
+  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(TPB), 0, s, N, nblk, partial, out);
+}
+void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, double* X) {
+  hipLaunchKernelGGL(k_normalize_cols, dim3(nb(n * N)), dim3(TPB), 0, s, n * N, N, sc, X);
+}
+void launch_restrict(hipStream_t s, int64_t nH, int N, const int32_t* PTptr, const int32_t* PTidx, const double* PTw,
+                     const double* Y, double* out) {
+  hipLaunchKernelGGL(k_restrict, dim3(nb(nH * N)), dim3(TPB), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
+}
+void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double* Y, double* partial) {
+  hipLaunchKernelGGL(k_gram, dim3(gram_blocks(n)), dim3(TPB), 0, s, n, N, U, Y, partial);
+}
+void launch_coarse_ops(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
+                       const int32_t* tets, const double* geo, const double* xyz, const double* cgeo,
+                       const double* fA, const double* fW, double* out) {
+  hipLaunchKernelGGL(k_coarse_ops, dim3(nb(cnt)), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo, fA,
+                     fW, out);
+}
+void launch_coarse_orb(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
+                       const int32_t* tets, const double* geo, const double* xyz, const double* cgeo,
+                       const int32_t* v2d, const double* U, int N, double* out) {
+  hipLaunchKernelGGL(k_coarse_orb, dim3(nb(cnt * N)), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo,
+                     v2d, U, N, out);
+}
+void launch_coarse_tri(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
+                       const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* out) {
+  hipLaunchKernelGGL(k_coarse_tri, dim3(nb(cnt)), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo,
+                     out);
+}
+void launch_reconstruct(hipStream_t s, int64_t n, int N, const int32_t* Pk, const double* Pw, const double* phiH,
+                        const double* theta2, const double* U, double* Phi) {
+  hipLaunchKernelGGL(k_reconstruct, dim3(nb(n * N)), dim3(TPB), 0, s, n, N, Pk, Pw, phiH, theta2, U, Phi);
+}
+void launch_hartree_nodal(hipStream_t s, int64_t nv, const int32_t* v2d, const int32_t* Pk, const double* Pw,
+                          const double* wH, double theta1, const double* w0, const double* g, double* w) {
+  hipLaunchKernelGGL(k_hartree_nodal, dim3(nb(nv)), dim3(TPB), 0, s, nv, v2d, Pk, Pw, wH, theta1, w0, g, w);
+}
+void launch_rho_nodal(hipStream_t s, int64_t nv, const int32_t* v2d, const double* Phi, int N, const double* occ,
+                      double* rho) {
+  hipLaunchKernelGGL(k_rho_nodal, dim3(nb(nv)), dim3(TPB), 0, s, nv, v2d, Phi, N, occ, rho);
+}
+void launch_energy(hipStream_t s, int64_t nt, const int32_t* tets, const int32_t* v2d, const double* Phi, int N,
+                   const double* occ, const double* wnod, const double* vxc_old, const double* geo, int xck,
+                   double xalpha, double* partials) {
+  hipLaunchKernelGGL(k_energy, dim3(nb(nt)), dim3(TPB), 0, s, nt, tets, v2d, Phi, N, occ, wnod, vxc_old, geo, xck,
+                     xalpha, partials);
+}
+
+}  // namespace mlc

@@ -1,0 +1,383 @@
+// Host-side mesh preparation (once per mesh pair): interior DoF numbering,
+// locality ordering, element geometry, CSR pattern, row adjacency for the
+// row-wise assembly kernel, the prolongation P (coarse hat functions at the
+// fine vertices: the spaces are nested, Section 3.2) and the grouping of fine
+// tets by their coarse parent tet.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "mlc_internal.h"
+
+namespace mlc {
+
+namespace {
+
+uint64_t spread3(uint64_t x) {
+  x &= 0x1fffff;
+  x = (x | x << 32) & 0x1f00000000ffffULL;
+  x = (x | x << 16) & 0x1f0000ff0000ffULL;
+  x = (x | x << 8) & 0x100f00f00f00f00fULL;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+  x = (x | x << 2) & 0x1249249249249249ULL;
+  return x;
+}
+
+uint64_t morton(const double* p, double lo, double hi) {
+  double s = (double)((1u << 21) - 1) / (hi - lo);
+  uint64_t c[3];
+  for (int k = 0; k < 3; ++k) {
+    double v = (p[k] - lo) * s;
+    v = v < 0 ? 0 : (v > (double)((1u << 21) - 1) ? (double)((1u << 21) - 1) : v);
+    c[k] = (uint64_t)v;
+  }
+  return spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
+}
+
+// Jacobian J = [x1-x0, x2-x0, x3-x0] (columns); returns det and J^{-1}.
+double tet_inverse(const double* x0, const double* x1, const double* x2, const double* x3, double Ji[9]) {
+  double J[9];
+  for (int r = 0; r < 3; ++r) {
+    J[3 * r + 0] = x1[r] - x0[r];
+    J[3 * r + 1] = x2[r] - x0[r];
+    J[3 * r + 2] = x3[r] - x0[r];
+  }
+  double c00 = J[4] * J[8] - J[5] * J[7];
+  double c01 = J[5] * J[6] - J[3] * J[8];
+  double c02 = J[3] * J[7] - J[4] * J[6];
+  double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+  double id = 1.0 / det;
+  Ji[0] = c00 * id;
+  Ji[1] = (J[2] * J[7] - J[1] * J[8]) * id;
+  Ji[2] = (J[1] * J[5] - J[2] * J[4]) * id;
+  Ji[3] = c01 * id;
+  Ji[4] = (J[0] * J[8] - J[2] * J[6]) * id;
+  Ji[5] = (J[2] * J[3] - J[0] * J[5]) * id;
+  Ji[6] = c02 * id;
+  Ji[7] = (J[1] * J[6] - J[0] * J[7]) * id;
+  Ji[8] = (J[0] * J[4] - J[1] * J[3]) * id;
+  return det;
+}
+
+struct Locator {
+  // uniform bucket grid over the coarse tets' bounding boxes
+  int nb = 1;
+  double lo = 0, hi = 1, h = 1;
+  std::vector<int32_t> ptr, ids;
+  const std::vector<double>* cgeo = nullptr;
+  void build(const mlc_ctx* c) {
+    lo = c->lo;
+    hi = c->hi;
+    nb = std::max(1, (int)std::cbrt((double)c->cnt / 4.0));
+    h = (hi - lo) / nb;
+    std::vector<int32_t> cnt((size_t)nb * nb * nb + 1, 0);
+    auto cells = [&](int64_t t, int r[6]) {
+      double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+      for (int a = 0; a < 4; ++a)
+        for (int k = 0; k < 3; ++k) {
+          double v = c->cxyz[3 * (int64_t)c->ctets[4 * t + a] + k];
+          mn[k] = std::min(mn[k], v);
+          mx[k] = std::max(mx[k], v);
+        }
+      for (int k = 0; k < 3; ++k) {
+        double e = 1e-9 * (hi - lo);
+        r[2 * k] = std::max(0, std::min(nb - 1, (int)std::floor((mn[k] - e - lo) / h)));
+        r[2 * k + 1] = std::max(0, std::min(nb - 1, (int)std::floor((mx[k] + e - lo) / h)));
+      }
+    };
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1) {
+        ptr.assign(cnt.size(), 0);
+        for (size_t i = 1; i < cnt.size(); ++i) ptr[i] = ptr[i - 1] + cnt[i - 1];
+        ids.assign(ptr.back(), 0);
+        std::fill(cnt.begin(), cnt.end(), 0);
+      }
+      for (int64_t t = 0; t < c->cnt; ++t) {
+        int r[6];
+        cells(t, r);
+        for (int z = r[4]; z <= r[5]; ++z)
+          for (int y = r[2]; y <= r[3]; ++y)
+            for (int x = r[0]; x <= r[1]; ++x) {
+              size_t cell = ((size_t)z * nb + y) * nb + x;
+              if (pass == 1) ids[ptr[cell] + cnt[cell]] = (int32_t)t;
+              cnt[cell]++;
+            }
+      }
+    }
+  }
+  // coarse tet with the largest minimal barycentric coordinate; returns it in b
+  int64_t find(const mlc_ctx* c, const double* p, double b[4], double* best_min) const {
+    int ix[3];
+    for (int k = 0; k < 3; ++k) ix[k] = std::max(0, std::min(nb - 1, (int)std::floor((p[k] - lo) / h)));
+    size_t cell = ((size_t)ix[2] * nb + ix[1]) * nb + ix[0];
+    int64_t best = -1;
+    double bm = -1e300;
+    for (int32_t e = ptr[cell]; e < ptr[cell + 1]; ++e) {
+      int64_t t = ids[e];
+      const double* g = c->cgeo.data() + 12 * t;
+      double dx = p[0] - g[0], dy = p[1] - g[1], dz = p[2] - g[2];
+      double l1 = g[3] * dx + g[4] * dy + g[5] * dz;
+      double l2 = g[6] * dx + g[7] * dy + g[8] * dz;
+      double l3 = g[9] * dx + g[10] * dy + g[11] * dz;
+      double l0 = 1.0 - l1 - l2 - l3;
+      double m = std::min(std::min(l0, l1), std::min(l2, l3));
+      if (m > bm) {
+        bm = m;
+        best = t;
+        b[0] = l0;
+        b[1] = l1;
+        b[2] = l2;
+        b[3] = l3;
+      }
+    }
+    *best_min = bm;
+    return best;
+  }
+};
+
+std::vector<char> boundary_flags(const std::vector<double>& xyz, double lo, double hi) {
+  int64_t nv = (int64_t)xyz.size() / 3;
+  std::vector<char> on(nv, 0);
+  double tol = 1e-12 * std::max(1.0, std::max(std::fabs(lo), std::fabs(hi)));
+  for (int64_t v = 0; v < nv; ++v)
+    for (int k = 0; k < 3; ++k) {
+      double x = xyz[3 * v + k];
+      if (std::fabs(x - lo) <= tol || std::fabs(x - hi) <= tol) on[v] = 1;
+    }
+  return on;
+}
+
+}  // namespace
+
+mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) {
+  // ---- copy and validate ------------------------------------------------------
+  c->nv = fine->n_vertices;
+  c->nt = fine->n_tets;
+  c->cnv = coarse->n_vertices;
+  c->cnt = coarse->n_tets;
+  if (c->nv < 4 || c->nt < 1 || c->cnv < 4 || c->cnt < 1) return fail(c, MLC_ERR_MESH, "empty mesh");
+  if (c->nv >= (1LL << 31) || c->nt * 4 >= (1LL << 31)) return fail(c, MLC_ERR_MESH, "mesh too large for int32 indices");
+  c->xyz.assign(fine->xyz, fine->xyz + 3 * c->nv);
+  c->cxyz.assign(coarse->xyz, coarse->xyz + 3 * c->cnv);
+  std::vector<int32_t> tin(fine->tets, fine->tets + 4 * c->nt);
+  c->ctets.assign(coarse->tets, coarse->tets + 4 * c->cnt);
+  for (int64_t i = 0; i < 4 * c->nt; ++i)
+    if (tin[i] < 0 || tin[i] >= c->nv) return fail(c, MLC_ERR_MESH, "fine tet index out of range");
+  for (int64_t i = 0; i < 4 * c->cnt; ++i)
+    if (c->ctets[i] < 0 || c->ctets[i] >= c->cnv) return fail(c, MLC_ERR_MESH, "coarse tet index out of range");
+  for (int64_t i = 0; i < 3 * c->nv; ++i)
+    if (!std::isfinite(c->xyz[i])) return fail(c, MLC_ERR_MESH, "non-finite fine coordinate");
+
+  // ---- fine tets: locality order by Morton code of the centroid -------------
+  std::vector<uint64_t> key(c->nt);
+  for (int64_t t = 0; t < c->nt; ++t) {
+    double p[3] = {0, 0, 0};
+    for (int a = 0; a < 4; ++a)
+      for (int k = 0; k < 3; ++k) p[k] += 0.25 * c->xyz[3 * (int64_t)tin[4 * t + a] + k];
+    key[t] = morton(p, c->lo, c->hi);
+  }
+  std::vector<int64_t> tord(c->nt);
+  std::iota(tord.begin(), tord.end(), 0);
+  if (c->opt.reorder) std::stable_sort(tord.begin(), tord.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+  c->tets.resize(4 * c->nt);
+  for (int64_t t = 0; t < c->nt; ++t)
+    for (int a = 0; a < 4; ++a) c->tets[4 * t + a] = tin[4 * tord[t] + a];
+
+  // ---- geometry ---------------------------------------------------------------
+  c->geo.assign(16 * c->nt, 0.0);
+  for (int64_t t = 0; t < c->nt; ++t) {
+    const double* x[4];
+    for (int a = 0; a < 4; ++a) x[a] = &c->xyz[3 * (int64_t)c->tets[4 * t + a]];
+    double Ji[9];
+    double det = tet_inverse(x[0], x[1], x[2], x[3], Ji);
+    double vol = std::fabs(det) / 6.0;
+    if (!(vol > 1e-300) || !std::isfinite(vol)) return fail(c, MLC_ERR_MESH, "degenerate fine tet");
+    double* G = &c->geo[16 * t];
+    G[0] = vol;
+    for (int k = 0; k < 3; ++k) {  // grad lambda_{1..3} = rows of J^{-1}
+      G[1 + 3 * 1 + k] = Ji[0 * 3 + k];
+      G[1 + 3 * 2 + k] = Ji[1 * 3 + k];
+      G[1 + 3 * 3 + k] = Ji[2 * 3 + k];
+      G[1 + k] = -(Ji[k] + Ji[3 + k] + Ji[6 + k]);
+    }
+  }
+
+  // ---- interior DoFs ------------------------------------------------------------
+  std::vector<char> on = boundary_flags(c->xyz, c->lo, c->hi);
+  std::vector<int32_t> interior;
+  for (int64_t v = 0; v < c->nv; ++v)
+    if (!on[v]) interior.push_back((int32_t)v);
+    else c->bverts.push_back((int32_t)v);
+  c->n = (int64_t)interior.size();
+  if (c->n == 0) return fail(c, MLC_ERR_MESH, "fine mesh has no interior vertex");
+  std::vector<int64_t> dord(c->n);
+  std::iota(dord.begin(), dord.end(), 0);
+  if (c->opt.reorder) {
+    std::vector<uint64_t> vk(c->n);
+    for (int64_t i = 0; i < c->n; ++i) vk[i] = morton(&c->xyz[3 * (int64_t)interior[i]], c->lo, c->hi);
+    std::stable_sort(dord.begin(), dord.end(), [&](int64_t a, int64_t b) { return vk[a] < vk[b]; });
+  }
+  c->v2d.assign(c->nv, -1);
+  c->d2v.resize(c->n);
+  c->dof_user.resize(c->n);
+  for (int64_t d = 0; d < c->n; ++d) {
+    int32_t v = interior[dord[d]];
+    c->d2v[d] = v;
+    c->v2d[v] = (int32_t)d;
+    c->dof_user[d] = (int32_t)dord[d];
+  }
+
+  // ---- vertex -> tets, CSR pattern, assembly adjacency ---------------------------
+  std::vector<int32_t> vt_ptr(c->nv + 1, 0), vt(4 * c->nt);
+  for (int64_t i = 0; i < 4 * c->nt; ++i) vt_ptr[c->tets[i] + 1]++;
+  for (int64_t v = 0; v < c->nv; ++v) vt_ptr[v + 1] += vt_ptr[v];
+  {
+    std::vector<int32_t> fill(vt_ptr.begin(), vt_ptr.end() - 1);
+    for (int64_t t = 0; t < c->nt; ++t)
+      for (int a = 0; a < 4; ++a) vt[fill[c->tets[4 * t + a]]++] = (int32_t)t;
+  }
+  c->rowptr.assign(c->n + 1, 0);
+  c->col.clear();
+  c->adj_ptr.assign(c->n + 1, 0);
+  c->adj_tet.clear();
+  c->adj_loc.clear();
+  c->adj_pos.clear();
+  std::vector<int32_t> nbr;
+  for (int64_t d = 0; d < c->n; ++d) {
+    int32_t v = c->d2v[d];
+    nbr.clear();
+    for (int32_t e = vt_ptr[v]; e < vt_ptr[v + 1]; ++e) {
+      int64_t t = vt[e];
+      for (int a = 0; a < 4; ++a) {
+        int32_t dd = c->v2d[c->tets[4 * t + a]];
+        if (dd >= 0) nbr.push_back(dd);
+      }
+    }
+    std::sort(nbr.begin(), nbr.end());
+    nbr.erase(std::unique(nbr.begin(), nbr.end()), nbr.end());
+    c->col.insert(c->col.end(), nbr.begin(), nbr.end());
+    c->rowptr[d + 1] = (int32_t)c->col.size();
+    for (int32_t e = vt_ptr[v]; e < vt_ptr[v + 1]; ++e) {
+      int64_t t = vt[e];
+      int la = -1;
+      for (int a = 0; a < 4; ++a)
+        if (c->tets[4 * t + a] == v) la = a;
+      c->adj_tet.push_back((int32_t)t);
+      c->adj_loc.push_back((int8_t)la);
+      for (int b = 0; b < 4; ++b) {
+        int32_t dd = c->v2d[c->tets[4 * t + b]];
+        int32_t pos = -1;
+        if (dd >= 0) pos = (int32_t)(std::lower_bound(nbr.begin(), nbr.end(), dd) - nbr.begin());
+        c->adj_pos.push_back(pos);
+      }
+    }
+    c->adj_ptr[d + 1] = (int32_t)c->adj_tet.size();
+  }
+  if ((int64_t)c->col.size() >= (1LL << 31)) return fail(c, MLC_ERR_MESH, "too many nonzeros");
+
+  // ---- coarse mesh --------------------------------------------------------------
+  std::vector<char> con = boundary_flags(c->cxyz, c->lo, c->hi);
+  c->cv2d.assign(c->cnv, -1);
+  c->cd2v.clear();
+  for (int64_t v = 0; v < c->cnv; ++v)
+    if (!con[v]) {
+      c->cv2d[v] = (int32_t)c->cd2v.size();
+      c->cd2v.push_back((int32_t)v);
+    }
+  c->nH = (int64_t)c->cd2v.size();
+  if (c->nH == 0) return fail(c, MLC_ERR_MESH, "coarse mesh has no interior vertex");
+  c->cgeo.assign(12 * c->cnt, 0.0);
+  c->cvol.assign(c->cnt, 0.0);
+  for (int64_t t = 0; t < c->cnt; ++t) {
+    const double* x[4];
+    for (int a = 0; a < 4; ++a) x[a] = &c->cxyz[3 * (int64_t)c->ctets[4 * t + a]];
+    double Ji[9];
+    double det = tet_inverse(x[0], x[1], x[2], x[3], Ji);
+    if (!(std::fabs(det) > 1e-300)) return fail(c, MLC_ERR_MESH, "degenerate coarse tet");
+    c->cvol[t] = std::fabs(det) / 6.0;
+    double* g = &c->cgeo[12 * t];
+    for (int k = 0; k < 3; ++k) g[k] = x[0][k];
+    for (int k = 0; k < 9; ++k) g[3 + k] = Ji[k];
+  }
+
+  // ---- point location: prolongation and coarse parents ---------------------------
+  Locator loc;
+  loc.build(c);
+  c->Pfull_k.assign(4 * c->nv, -1);
+  c->Pfull_w.assign(4 * c->nv, 0.0);
+  for (int64_t v = 0; v < c->nv; ++v) {
+    double b[4], bm;
+    int64_t t = loc.find(c, &c->xyz[3 * v], b, &bm);
+    if (t < 0 || bm < -1e-9) return fail(c, MLC_ERR_NOT_NESTED, "fine vertex outside the coarse mesh");
+    for (int a = 0; a < 4; ++a) {
+      double w = std::fabs(b[a]) < 1e-13 ? 0.0 : b[a];
+      c->Pfull_k[4 * v + a] = w != 0.0 ? c->ctets[4 * t + a] : -1;
+      c->Pfull_w[4 * v + a] = w;
+    }
+  }
+  c->Pk.assign(4 * c->n, -1);
+  c->Pw.assign(4 * c->n, 0.0);
+  std::vector<int32_t> ptc(c->nH + 1, 0);
+  for (int64_t d = 0; d < c->n; ++d) {
+    int32_t v = c->d2v[d];
+    int s = 0;
+    for (int a = 0; a < 4; ++a) {
+      int32_t cv = c->Pfull_k[4 * (int64_t)v + a];
+      if (cv < 0) continue;
+      int32_t k = c->cv2d[cv];
+      if (k < 0) continue;
+      c->Pk[4 * d + s] = k;
+      c->Pw[4 * d + s] = c->Pfull_w[4 * (int64_t)v + a];
+      ptc[k + 1]++;
+      ++s;
+    }
+  }
+  c->PTptr.assign(c->nH + 1, 0);
+  for (int64_t k = 0; k < c->nH; ++k) c->PTptr[k + 1] = c->PTptr[k] + ptc[k + 1];
+  c->PTidx.assign(c->PTptr.back(), 0);
+  c->PTw.assign(c->PTptr.back(), 0.0);
+  {
+    std::vector<int32_t> fill(c->PTptr.begin(), c->PTptr.end() - 1);
+    for (int64_t d = 0; d < c->n; ++d)
+      for (int s = 0; s < 4; ++s) {
+        int32_t k = c->Pk[4 * d + s];
+        if (k < 0) continue;
+        c->PTidx[fill[k]] = (int32_t)d;
+        c->PTw[fill[k]] = c->Pw[4 * d + s];
+        fill[k]++;
+      }
+  }
+  c->parent.assign(c->nt, -1);
+  std::vector<int32_t> gc(c->cnt + 1, 0);
+  for (int64_t t = 0; t < c->nt; ++t) {
+    double p[3] = {0, 0, 0};
+    for (int a = 0; a < 4; ++a)
+      for (int k = 0; k < 3; ++k) p[k] += 0.25 * c->xyz[3 * (int64_t)c->tets[4 * t + a] + k];
+    double b[4], bm;
+    int64_t C = loc.find(c, p, b, &bm);
+    if (C < 0 || bm < -1e-9) return fail(c, MLC_ERR_NOT_NESTED, "fine tet outside the coarse mesh");
+    // every vertex of the fine tet must lie in the parent (nested refinement)
+    const double* g = &c->cgeo[12 * C];
+    for (int a = 0; a < 4; ++a) {
+      const double* x = &c->xyz[3 * (int64_t)c->tets[4 * t + a]];
+      double dx = x[0] - g[0], dy = x[1] - g[1], dz = x[2] - g[2];
+      double l1 = g[3] * dx + g[4] * dy + g[5] * dz, l2 = g[6] * dx + g[7] * dy + g[8] * dz;
+      double l3 = g[9] * dx + g[10] * dy + g[11] * dz;
+      double m = std::min(std::min(1.0 - l1 - l2 - l3, l1), std::min(l2, l3));
+      if (m < -1e-9) return fail(c, MLC_ERR_NOT_NESTED, "fine tet crosses a coarse tet");
+    }
+    c->parent[t] = (int32_t)C;
+    gc[C + 1]++;
+  }
+  c->cgrp_ptr.assign(c->cnt + 1, 0);
+  for (int64_t C = 0; C < c->cnt; ++C) c->cgrp_ptr[C + 1] = c->cgrp_ptr[C] + gc[C + 1];
+  c->cgrp_tet.assign(c->nt, 0);
+  {
+    std::vector<int32_t> fill(c->cgrp_ptr.begin(), c->cgrp_ptr.end() - 1);
+    for (int64_t t = 0; t < c->nt; ++t) c->cgrp_tet[fill[c->parent[t]]++] = (int32_t)t;
+  }
+  return MLC_OK;
+}
+
+}  // namespace mlc

@@ -1,0 +1,233 @@
+// Internal state of an mlc context (host side) and the launch interface of the
+// gfx950 kernels. Not part of the ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/mlc.h"
+
+namespace mlc {
+
+// Symmetric 4-point quadrature of degree 2 on a tetrahedron: barycentric
+// points (a,b,b,b) and permutations, weight |T|/4 each.
+constexpr double QA = 0.58541019662496845446;  // (5 + 3 sqrt 5) / 20
+constexpr double QB = 0.13819660112501051518;  // (5 - sqrt 5) / 20
+
+// Device sub-buffers carved out of the caller's workspace.
+struct Dev {
+  // fine mesh (library orders)
+  int32_t* tets = nullptr;      // nt x 4 fine vertex ids
+  int32_t* v2d = nullptr;       // nv: vertex -> dof or -1
+  double* xyz = nullptr;        // nv x 3
+  double* geo = nullptr;        // nt x 16: vol, grad lambda_0..3 (12), pad
+  double* qpx = nullptr;        // nt x 4 x 3 quadrature point coordinates
+  double* vext = nullptr;       // nt x 4
+  double* vxc = nullptr;        // nt x 4   V_xc(rho^l)
+  double* exc = nullptr;        // nt x 4
+  double* veff = nullptr;       // nt x 4
+  double* rho = nullptr;        // nt x 4   rho^l
+  double* fld = nullptr;        // nt x 4   V_ext + V_xc + g
+  double* fld2 = nullptr;       // nt x 4   w0
+  double* rhot = nullptr;       // nt x 4   density of normalised u_i
+  int32_t* rowptr = nullptr;    // n + 1
+  int32_t* col = nullptr;       // nnz
+  int32_t* adj_ptr = nullptr;   // n + 1
+  int32_t* adj_tet = nullptr;   // nadj
+  int32_t* adj_pos = nullptr;   // nadj x 4
+  int8_t* adj_loc = nullptr;    // nadj
+  int32_t* bverts = nullptr;    // boundary vertex ids
+  // operators on the interior CSR pattern
+  double* valA = nullptr;       // A + sigma M (step 5)
+  double* valF = nullptr;       // A_fix = 1/2 K + M_{V_ext + V_xc + g}
+  double* valW = nullptr;       // M_{w0}
+  double* valM = nullptr;       // M
+  double* valK = nullptr;       // K
+  double* dinvA = nullptr;      // n
+  double* dinvK = nullptr;      // n
+  // orbital blocks, n x N row-major
+  double* Phi = nullptr;        // Phi^l (state)
+  double* X = nullptr;          // CG iterate, then u_i
+  double* R = nullptr;
+  double* P = nullptr;
+  double* Q = nullptr;
+  double* B = nullptr;
+  double* Y = nullptr;          // 4 blocks of n x N
+  // single vectors
+  double* w = nullptr;          // nv nodal Hartree potential
+  double* g = nullptr;          // nv multipole data (0 inside)
+  double* w0 = nullptr;         // n
+  double* lvec = nullptr;       // n   l = K_IB g_B
+  double* pb = nullptr;         // n
+  double* pr = nullptr;         // n
+  double* pp = nullptr;         // n
+  double* pq = nullptr;         // n
+  double* rho_nodal = nullptr;  // nv
+  // prolongation
+  int32_t* Pk = nullptr;        // n x 4
+  double* Pw = nullptr;         // n x 4
+  int32_t* PTptr = nullptr;     // nH + 1
+  int32_t* PTidx = nullptr;
+  double* PTw = nullptr;
+  // coarse grouping
+  int32_t* cgrp_ptr = nullptr;  // cnt + 1
+  int32_t* cgrp_tet = nullptr;  // nt
+  double* cgeo = nullptr;       // cnt x 12
+  double* cel_ops = nullptr;    // cnt x 40
+  double* cel_orb = nullptr;    // cnt x N x 14
+  double* cel_tri = nullptr;    // cnt x 20
+  // small
+  double* small = nullptr;      // packed small blocks (see step.cpp)
+  double* coarse_in = nullptr;  // phi_H (nH x N), w_H (nH), theta2 (N)
+  double* occ = nullptr;        // N
+  double* RZ = nullptr;         // 4 x n_nuclei
+  double* colv = nullptr;       // 2 x N per-column scratch
+  double* red = nullptr;        // reduction partials
+  double* scal = nullptr;       // 7 x N CG scalars (orbitals)
+  double* scalP = nullptr;      // 7 CG scalars (Poisson)
+  int32_t* flags = nullptr;     // 4
+  int32_t* flagsP = nullptr;    // 4
+};
+
+struct Options {
+  mlc_options o;
+};
+
+}  // namespace mlc
+
+struct mlc_ctx {
+  // ---- inputs -------------------------------------------------------------
+  int64_t nv = 0, nt = 0, cnv = 0, cnt = 0;
+  std::vector<double> xyz, cxyz;        // library vertex order (= caller order)
+  std::vector<int32_t> tets;            // library tet order (Morton by centroid)
+  std::vector<int32_t> ctets;
+  int32_t n_nuclei = 0;
+  std::vector<double> R, Z, occ;
+  int32_t potential = 0, xc = 0, hartree = 1, N = 1;
+  double rc = 0.5, omega = 1.0, xalpha = 0.77298, lo = 0, hi = 0;
+  mlc_options opt{};
+  // ---- fine DoFs ----------------------------------------------------------
+  int64_t n = 0;                        // interior DoFs
+  std::vector<int32_t> v2d, d2v;        // vertex <-> library dof
+  std::vector<int32_t> dof_user;        // library dof -> caller dof index
+  std::vector<int32_t> bverts;
+  std::vector<int32_t> rowptr, col;
+  std::vector<int32_t> adj_ptr, adj_tet, adj_pos;
+  std::vector<int8_t> adj_loc;
+  std::vector<double> geo;              // nt x 16
+  // ---- coarse ---------------------------------------------------------------
+  int64_t nH = 0;
+  std::vector<int32_t> cv2d, cd2v;
+  std::vector<int32_t> Pk;              // n x 4
+  std::vector<double> Pw;
+  std::vector<int32_t> PTptr, PTidx;
+  std::vector<double> PTw;
+  std::vector<int32_t> parent;          // fine tet -> coarse tet
+  std::vector<int32_t> cgrp_ptr, cgrp_tet;
+  std::vector<double> cgeo;             // cnt x 12
+  std::vector<double> cvol;             // coarse tet volumes
+  std::vector<double> Pfull_w;          // nv x 4 weights (all fine vertices, coarse vertex ids)
+  std::vector<int32_t> Pfull_k;
+  // ---- device ---------------------------------------------------------------
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  mlc::Dev d;
+  bool bound = false, has_state = false, has_step = false;
+  int64_t nred = 0;                     // size of reduction partial buffer (doubles)
+  // ---- state ----------------------------------------------------------------
+  std::vector<double> lam;
+  // host copies of the last step's small blocks (for mlc_probe and the inner loop)
+  std::vector<double> h_tri;            // cnt x 20 (once per mesh)
+  std::vector<double> h_Mh_chol;        // dense L of M_H (once per mesh)
+  std::vector<double> h_KH;             // dense C_H = P^T K P (once per mesh)
+  std::vector<double> h_Kh_chol;        // its Cholesky factor
+  std::vector<double> h_MH;             // dense M_H
+  std::vector<double> last_theta2, last_phiH, last_wH;
+  double last_theta1 = 0.0, last_sigma = 0.0;
+  std::vector<double> last_small;       // packed small blocks of the fine stage
+  std::vector<double> last_cel_ops, last_cel_orb;
+  int64_t small_len = 0;
+  std::string err;
+  // timing of the dominant kernel
+  std::vector<hipEvent_t> ev_pool;
+  int ev_used = 0;
+};
+
+namespace mlc {
+
+// ---- host helpers -----------------------------------------------------------
+mlc_status fail(mlc_ctx* c, mlc_status s, const std::string& msg);
+mlc_status hip_fail(mlc_ctx* c, hipError_t e, const char* what);
+
+mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse);
+size_t workspace_layout(mlc_ctx* c, char* base, Dev* d);
+mlc_status upload_and_init(mlc_ctx* c);
+mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep);
+mlc_status coarse_scf(mlc_ctx* c, double tol, int maxit, int* iters);
+mlc_status probe(mlc_ctx* c, int which, double* out, int64_t count);
+
+// ---- kernel launchers (kernels.hip) -------------------------------------------
+int spmm_rows_per_block(int N);
+int elem_blocks(int64_t n, int N);
+int qp_blocks(int64_t nt);
+int gram_blocks(int64_t n);
+int nmom();
+void launch_vext(hipStream_t s, int64_t nt, const double* qpx, const double* RZ, int n_nuclei, int kind,
+                 double rc, double omega, double* vext);
+void launch_qp_density(hipStream_t s, int64_t nt, const int32_t* tets, const int32_t* v2d, const double* X, int N,
+                       const double* occ, double* rho_out);
+void launch_qp_fields(hipStream_t s, int64_t nt, const int32_t* tets, const int32_t* v2d, const double* Phi, int N,
+                      const double* occ, const double* wnod, const double* vext, const double* geo,
+                      const double* qpx, int xck, double xalpha, double* vxc, double* exc, double* veff,
+                      double* rho, double* partials);
+void launch_reduce_rows(hipStream_t s, const double* partials, int nblk, int nvals, int minlast, double* out);
+void launch_boundary_g(hipStream_t s, int64_t nbv, const int32_t* bverts, const double* xyz, const double* mom,
+                       double* g);
+void launch_field(hipStream_t s, int64_t nt, const int32_t* tets, const double* nod, const int32_t* v2d,
+                  const double* dofv, const double* add1, const double* add2, double* out);
+void launch_assemble(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* adj_ptr, const int32_t* adj_tet,
+                     const int8_t* adj_loc, const int32_t* adj_pos, const double* geo, double cK1, const double* f1,
+                     double cM1, double* val1, double* dinv1, double cK2, const double* f2, double* val2);
+void launch_load(hipStream_t s, int64_t n, const int32_t* adj_ptr, const int32_t* adj_tet, const int8_t* adj_loc,
+                 const int32_t* tets, const double* geo, const double* f_qp, double scale, const double* gnod,
+                 const int32_t* v2d, double* b, double* lvec);
+void launch_spmm(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const double* val,
+                 const double* X, double* Y, double* partial);
+void launch_scale_cols_to(hipStream_t s, int64_t n, int N, const double* X, const double* sc, double* Y);
+void launch_cg_init(hipStream_t s, int64_t n, int N, const double* B, const double* AX, const double* dinv,
+                    double* Rv, double* P, double* partial);
+void launch_cg_update(hipStream_t s, int64_t n, int N, const double* scal, const double* dinv, double* X, double* Rv,
+                      const double* P, const double* Q, double* partial);
+void launch_cg_direction(hipStream_t s, int64_t n, int N, const double* scal, const double* dinv, const double* Rv,
+                         double* P);
+void launch_cg_scalars(hipStream_t s, int N, int nblk, const double* partial, int phase, double rtol2, double* scal,
+                       int32_t* flags);
+void launch_coldot(hipStream_t s, int64_t n, int N, const double* X, const double* Y, double* partial);
+void launch_reduce_cols(hipStream_t s, int N, int nblk, const double* partial, double* out);
+void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, double* X);
+void launch_restrict(hipStream_t s, int64_t nH, int N, const int32_t* PTptr, const int32_t* PTidx, const double* PTw,
+                     const double* Y, double* out);
+void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double* Y, double* partial);
+void launch_coarse_ops(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
+                       const int32_t* tets, const double* geo, const double* xyz, const double* cgeo,
+                       const double* fA, const double* fW, double* out);
+void launch_coarse_orb(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
+                       const int32_t* tets, const double* geo, const double* xyz, const double* cgeo,
+                       const int32_t* v2d, const double* U, int N, double* out);
+void launch_coarse_tri(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
+                       const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* out);
+void launch_reconstruct(hipStream_t s, int64_t n, int N, const int32_t* Pk, const double* Pw, const double* phiH,
+                        const double* theta2, const double* U, double* Phi);
+void launch_hartree_nodal(hipStream_t s, int64_t nv, const int32_t* v2d, const int32_t* Pk, const double* Pw,
+                          const double* wH, double theta1, const double* w0, const double* g, double* w);
+void launch_rho_nodal(hipStream_t s, int64_t nv, const int32_t* v2d, const double* Phi, int N, const double* occ,
+                      double* rho);
+void launch_energy(hipStream_t s, int64_t nt, const int32_t* tets, const int32_t* v2d, const double* Phi, int N,
+                   const double* occ, const double* wnod, const double* vxc_old, const double* geo, int xck,
+                   double xalpha, double* partials);
+
+}  // namespace mlc

@@ -1,0 +1,319 @@
+// One outer step of Algorithm 1 (steps 5-7): the fine stage on the GPU, the
+// inner Hartree iteration on the host, and the reconstruction on the GPU.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "inner.h"
+#include "mlc_internal.h"
+
+namespace mlc {
+
+// Offsets into the packed small-block buffer (doubles).
+struct SmallLayout {
+  int64_t ptF, ptW, ptM, ptK, utF, utW, utM, utK, d, liftH, sc, mom, ovl, colv, total;
+  SmallLayout(int64_t nH, int N) {
+    int64_t hn = nH * N, nn = (int64_t)N * N;
+    ptF = 0;
+    ptW = hn;
+    ptM = 2 * hn;
+    ptK = 3 * hn;
+    utF = 4 * hn;
+    utW = utF + nn;
+    utM = utW + nn;
+    utK = utM + nn;
+    d = utK + nn;
+    liftH = d + nH;
+    sc = liftH + nH;   // [0] zeta [1] w0.l [2] int rho [3] energy piece
+    mom = sc + 8;      // 11 moments (+ min V_eff)
+    ovl = mom + 16;    // N x N overlaps
+    colv = ovl + nn;   // 2N per-column values
+    total = colv + 2 * N;
+  }
+};
+
+int64_t small_len(int64_t nH, int N) { return SmallLayout(nH, N).total; }
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    hipError_t e_ = (x);                           \
+    if (e_ != hipSuccess) return hip_fail(c, e_, #x); \
+  } while (0)
+
+namespace {
+
+struct CgRes {
+  int iters = 0;
+  double relres = 0.0;
+  bool converged = false;
+  bool breakdown = false;
+};
+
+// Multi-column Jacobi-PCG, one independent recurrence per column; per-column
+// scalars stay on the device; the host checks the number of active columns
+// every check_every iterations. On exit the true residual is evaluated.
+mlc_status cg(mlc_ctx* c, int64_t n, int N, const double* val, const double* dinv, const double* B, double* X,
+              double* R, double* P, double* Q, double* scal, int32_t* flags, double rtol, int maxit, bool timed,
+              double* spmm_ms, int64_t* n_spmm, CgRes* out) {
+  hipStream_t s = c->stream;
+  auto& d = c->d;
+  int nblk = elem_blocks(n, N);
+  HIPCHK(hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), s));
+  launch_spmm(s, n, N, d.rowptr, d.col, val, X, Q, nullptr);
+  launch_cg_init(s, n, N, B, Q, dinv, R, P, d.red);
+  launch_cg_scalars(s, N, nblk, d.red, 0, rtol * rtol, scal, flags);
+  int it = 0;
+  int32_t hf[4];
+  int every = std::max(1, c->opt.check_every);
+  for (;;) {
+    HIPCHK(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (timed && c->ev_used > 0) {
+      for (int k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
+        *spmm_ms += ms;
+      }
+      c->ev_used = 0;
+    }
+    if (hf[1]) {
+      out->breakdown = true;
+      break;
+    }
+    if (hf[0] == 0) {
+      out->converged = true;
+      break;
+    }
+    if (it >= maxit) break;
+    int chunk = std::min(every, maxit - it);
+    for (int k = 0; k < chunk; ++k) {
+      bool rec = timed && c->ev_used + 2 <= (int)c->ev_pool.size();
+      if (rec) HIPCHK(hipEventRecord(c->ev_pool[c->ev_used], s));
+      launch_spmm(s, n, N, d.rowptr, d.col, val, P, Q, d.red);
+      if (rec) {
+        HIPCHK(hipEventRecord(c->ev_pool[c->ev_used + 1], s));
+        c->ev_used += 2;
+      }
+      ++*n_spmm;
+      launch_cg_scalars(s, N, nblk, d.red, 1, rtol * rtol, scal, flags);
+      launch_cg_update(s, n, N, scal, dinv, X, R, P, Q, d.red);
+      launch_cg_scalars(s, N, nblk, d.red, 2, rtol * rtol, scal, flags);
+      launch_cg_direction(s, n, N, scal, dinv, R, P);
+      ++it;
+    }
+  }
+  out->iters = it;
+  // true residual ||B - A X|| / ||B|| per column (R, P, scal reused)
+  launch_spmm(s, n, N, d.rowptr, d.col, val, X, Q, nullptr);
+  launch_cg_init(s, n, N, B, Q, dinv, R, P, d.red);
+  launch_cg_scalars(s, N, nblk, d.red, 0, 0.0, scal, flags);
+  std::vector<double> hs(8 * N);
+  HIPCHK(hipMemcpyAsync(hs.data(), scal, sizeof(double) * 5 * N, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double mx = 0.0;
+  for (int j = 0; j < N; ++j) {
+    double bb = hs[4 * N + j];
+    double rr = hs[3 * N + j];
+    mx = std::max(mx, bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr));
+  }
+  out->relres = mx;
+  if (!std::isfinite(mx)) return fail(c, MLC_ERR_NONFINITE, "non-finite CG residual");
+  return MLC_OK;
+}
+
+}  // namespace
+
+mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
+  auto& d = c->d;
+  hipStream_t s = c->stream;
+  const int64_t n = c->n, nt = c->nt, nH = c->nH, nv = c->nv, cnt = c->cnt;
+  const int N = c->N;
+  SmallLayout L(nH, N);
+  mlc_step_report r;
+  std::memset(&r, 0, sizeof(r));
+  bool timed = c->opt.time_kernels != 0;
+  hipEvent_t ev[4];
+  for (int k = 0; k < 4; ++k) HIPCHK(hipEventCreate(&ev[k]));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int k = 0; k < 4; ++k) (void)hipEventDestroy(e[k]);
+    }
+  } guard{ev};
+  HIPCHK(hipEventRecord(ev[0], s));
+
+  // ---- density, XC, V_eff at quadrature points; multipole moments ----------------
+  const int nqb = qp_blocks(nt);
+  launch_qp_fields(s, nt, d.tets, d.v2d, d.Phi, N, d.occ, d.w, d.vext, d.geo, d.qpx, c->xc, c->xalpha, d.vxc,
+                   d.exc, d.veff, d.rho, d.red);
+  launch_reduce_rows(s, d.red, nqb, nmom(), 1, d.small + L.mom);
+  double mom[16];
+  HIPCHK(hipMemcpyAsync(mom, d.small + L.mom, sizeof(double) * nmom(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double sigma = c->opt.shift ? c->opt.sigma0 - mom[nmom() - 1] : 0.0;
+  c->last_sigma = sigma;
+
+  // ---- multipole Dirichlet data g (remark after Algorithm 3) -------------------
+  HIPCHK(hipMemsetAsync(d.g, 0, sizeof(double) * nv, s));
+  if (c->hartree && mom[0] > 0.0) launch_boundary_g(s, (int64_t)c->bverts.size(), d.bverts, d.xyz, d.small + L.mom, d.g);
+  // V_ext + V_xc + g at the quadrature points (A_fix of the inner problems)
+  launch_field(s, nt, d.tets, d.g, d.v2d, nullptr, d.vext, d.vxc, d.fld);
+  // ---- operators: A + sigma M (step 5) and A_fix -------------------------------
+  launch_assemble(s, n, d.rowptr, d.adj_ptr, d.adj_tet, d.adj_loc, d.adj_pos, d.geo, 0.5, d.veff, sigma, d.valA,
+                  d.dinvA, 0.5, d.fld, d.valF);
+
+  // ---- step 5: (A + sigma M) u_i = (lambda_i + sigma) M phi_i ------------------------
+  std::vector<double> colv(2 * N);
+  for (int i = 0; i < N; ++i) colv[i] = c->lam[i] + sigma;
+  HIPCHK(hipMemcpyAsync(d.colv, colv.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+  launch_spmm(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr);
+  launch_scale_cols_to(s, n, N, d.Q, d.colv, d.B);
+  HIPCHK(hipMemcpyAsync(d.X, d.Phi, sizeof(double) * n * N, hipMemcpyDeviceToDevice, s));
+  CgRes cr;
+  mlc_status st = cg(c, n, N, d.valA, d.dinvA, d.B, d.X, d.R, d.P, d.Q, d.scal, d.flags, c->opt.cg_rtol,
+                     c->opt.cg_maxit, timed, &r.t_spmm_ms, &r.n_spmm, &cr);
+  if (st != MLC_OK) return st;
+  r.cg_iters_max = cr.iters;
+  r.cg_iters_sum = cr.iters * N;
+  r.cg_relres_max = cr.relres;
+  r.spmm_rows = n;
+  r.spmm_cols_sum = N;
+  if (cr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the auxiliary problems");
+  // M-normalise u_i
+  launch_spmm(s, n, N, d.rowptr, d.col, d.valM, d.X, d.Q, d.red);
+  launch_reduce_cols(s, N, elem_blocks(n, N), d.red, d.colv + N);
+  launch_normalize_cols(s, n, N, d.colv + N, d.X);
+
+  // ---- step 6: Hartree direction w0 -------------------------------------------
+  CgRes pr;
+  if (c->hartree) {
+    launch_qp_density(s, nt, d.tets, d.v2d, d.X, N, d.occ, d.rhot);
+    launch_load(s, n, d.adj_ptr, d.adj_tet, d.adj_loc, d.tets, d.geo, d.rhot, 4.0 * 3.14159265358979323846, d.g,
+                d.v2d, d.pb, d.lvec);
+    HIPCHK(hipMemsetAsync(d.w0, 0, sizeof(double) * n, s));
+    double dummy = 0.0;
+    int64_t dn = 0;
+    st = cg(c, n, 1, d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP, c->opt.poisson_rtol,
+            c->opt.cg_maxit, false, &dummy, &dn, &pr);
+    if (st != MLC_OK) return st;
+    if (pr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the Hartree problem");
+    launch_field(s, nt, d.tets, nullptr, d.v2d, d.w0, nullptr, nullptr, d.fld2);
+    launch_assemble(s, n, d.rowptr, d.adj_ptr, d.adj_tet, d.adj_loc, d.adj_pos, d.geo, 0.0, d.fld2, 0.0, d.valW,
+                    nullptr, 0.0, nullptr, nullptr);
+  } else {
+    HIPCHK(hipMemsetAsync(d.w0, 0, sizeof(double) * n, s));
+    HIPCHK(hipMemsetAsync(d.lvec, 0, sizeof(double) * n, s));
+    HIPCHK(hipMemsetAsync(d.fld2, 0, sizeof(double) * 4 * nt, s));
+    HIPCHK(hipMemsetAsync(d.valW, 0, sizeof(double) * c->col.size(), s));
+  }
+  r.poisson_iters = pr.iters;
+  r.poisson_relres = pr.relres;
+
+  // ---- Algorithm 3 step 1: Gram blocks P^T O U and U^T O U --------------------------
+  const double* vals[4] = {d.valF, d.valW, d.valM, d.valK};
+  for (int o = 0; o < 4; ++o) {
+    double* Yo = d.Y + (int64_t)o * n * N;
+    launch_spmm(s, n, N, d.rowptr, d.col, vals[o], d.X, Yo, nullptr);
+    launch_restrict(s, nH, N, d.PTptr, d.PTidx, d.PTw, Yo, d.small + L.ptF + (int64_t)o * nH * N);
+    launch_gram(s, n, N, d.X, Yo, d.red);
+    launch_reduce_cols(s, N * N, gram_blocks(n), d.red, d.small + L.utF + (int64_t)o * N * N);
+  }
+  HIPCHK(hipMemsetAsync(d.small + L.d, 0, sizeof(double) * (2 * nH + 8), s));
+  if (c->hartree) {
+    launch_spmm(s, n, 1, d.rowptr, d.col, d.valK, d.w0, d.pq, nullptr);
+    launch_restrict(s, nH, 1, d.PTptr, d.PTidx, d.PTw, d.pq, d.small + L.d);
+    launch_restrict(s, nH, 1, d.PTptr, d.PTidx, d.PTw, d.lvec, d.small + L.liftH);
+    launch_coldot(s, n, 1, d.w0, d.pq, d.red);
+    launch_reduce_cols(s, 1, elem_blocks(n, 1), d.red, d.small + L.sc + 0);
+    launch_coldot(s, n, 1, d.w0, d.lvec, d.red);
+    launch_reduce_cols(s, 1, elem_blocks(n, 1), d.red, d.small + L.sc + 1);
+  }
+  // ---- coarse-pattern integrals (eqs. Adef, Ah4def, rhsdef, FG) -------------------
+  launch_coarse_ops(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.fld, d.fld2, d.cel_ops);
+  launch_coarse_orb(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.v2d, d.X, N, d.cel_orb);
+  c->last_small.resize(L.total);
+  c->last_cel_ops.resize(40 * cnt);
+  c->last_cel_orb.resize(14 * cnt * N);
+  HIPCHK(hipMemcpyAsync(c->last_small.data(), d.small, sizeof(double) * L.total, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(c->last_cel_ops.data(), d.cel_ops, sizeof(double) * 40 * cnt, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(c->last_cel_orb.data(), d.cel_orb, sizeof(double) * 14 * cnt * N, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(ev[1], s));
+  HIPCHK(hipStreamSynchronize(s));
+
+  // ---- Algorithm 2 via Algorithm 3 step 2 (host FP64) --------------------------
+  FineBlocks fb;
+  const double* h = c->last_small.data();
+  fb.ptF.assign(h + L.ptF, h + L.ptF + nH * N);
+  fb.ptW.assign(h + L.ptW, h + L.ptW + nH * N);
+  fb.ptM.assign(h + L.ptM, h + L.ptM + nH * N);
+  fb.ptK.assign(h + L.ptK, h + L.ptK + nH * N);
+  fb.utF.assign(h + L.utF, h + L.utF + N * N);
+  fb.utW.assign(h + L.utW, h + L.utW + N * N);
+  fb.utM.assign(h + L.utM, h + L.utM + N * N);
+  fb.utK.assign(h + L.utK, h + L.utK + N * N);
+  fb.d.assign(h + L.d, h + L.d + nH);
+  fb.liftH.assign(h + L.liftH, h + L.liftH + nH);
+  fb.zeta = h[L.sc + 0];
+  fb.liftT = h[L.sc + 1];
+  fb.cel_ops = c->last_cel_ops;
+  fb.cel_orb = c->last_cel_orb;
+  InnerOut io;
+  mlc_status ist = inner_loop(c, fb, io);
+  if (ist < 0) return ist;
+  r.inner_iters = io.iters;
+  r.inner_last_diff = io.last_diff;
+  r.t_inner_ms = io.ms;
+  r.theta1 = io.theta1;
+  r.sigma = sigma;
+
+  // ---- reconstruction (Algorithm 3 step 3), Hartree potential, density --------------
+  std::vector<double> cin(nH * N + nH + N);
+  std::copy(io.phiH.begin(), io.phiH.end(), cin.begin());
+  std::copy(io.wH.begin(), io.wH.end(), cin.begin() + nH * N);
+  std::copy(io.theta2.begin(), io.theta2.end(), cin.begin() + nH * N + nH);
+  HIPCHK(hipMemcpyAsync(d.coarse_in, cin.data(), sizeof(double) * cin.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(ev[2], s));
+  launch_reconstruct(s, n, N, d.Pk, d.Pw, d.coarse_in, d.coarse_in + nH * N + nH, d.X, d.Phi);
+  launch_hartree_nodal(s, nv, d.v2d, d.Pk, d.Pw, d.coarse_in + nH * N, io.theta1, d.w0, d.g, d.w);
+  launch_rho_nodal(s, nv, d.v2d, d.Phi, N, d.occ, d.rho_nodal);
+  launch_energy(s, nt, d.tets, d.v2d, d.Phi, N, d.occ, d.w, d.vxc, d.geo, c->xc, c->xalpha, d.red);
+  launch_reduce_rows(s, d.red, nqb, 2, 0, d.small + L.sc + 2);
+  launch_spmm(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr);
+  launch_gram(s, n, N, d.Phi, d.Q, d.red);
+  launch_reduce_cols(s, N * N, gram_blocks(n), d.red, d.small + L.ovl);
+  HIPCHK(hipEventRecord(ev[3], s));
+  std::vector<double> tail(L.total - L.sc);
+  HIPCHK(hipMemcpyAsync(tail.data(), d.small + L.sc, sizeof(double) * tail.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::copy(tail.begin(), tail.end(), c->last_small.begin() + L.sc);
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+  r.t_fine_ms = ms;
+  HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3]));
+  r.t_recon_ms = ms;
+  double E = tail[3];
+  for (int i = 0; i < N; ++i) E += c->occ[i] * io.lam[i];
+  r.energy = E;
+  r.rho_integral = tail[2];
+  double mo = 0.0;
+  const double* ov = tail.data() + (L.ovl - L.sc);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j)
+      if (i != j) mo = std::max(mo, std::fabs(ov[i * N + j]));
+  r.max_offdiag_overlap = mo;
+  for (int i = 0; i < N; ++i)
+    if (!std::isfinite(io.lam[i])) return fail(c, MLC_ERR_NONFINITE, "non-finite eigenvalue");
+  c->lam = io.lam;
+  c->last_theta2 = io.theta2;
+  c->last_phiH = io.phiH;
+  c->last_wH = io.wH;
+  c->last_theta1 = io.theta1;
+  c->has_step = true;
+  if (rep) *rep = r;
+  if (!cr.converged) return fail(c, MLC_ERR_NOT_CONVERGED, "CG did not reach cg_rtol within cg_maxit");
+  if (c->hartree && !pr.converged) return fail(c, MLC_ERR_NOT_CONVERGED, "Hartree CG did not converge");
+  return ist;
+}
+
+}  // namespace mlc

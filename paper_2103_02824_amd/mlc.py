@@ -1,0 +1,210 @@
+"""Python binding of libmlc.so (include/mlc.h): argument marshalling only.
+
+Every computation happens inside the library's HIP kernels and host C++ code.
+PyTorch supplies the device workspace and the HIP stream. If the shared
+library is missing this module raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+LIB_PATH = _HERE / "libmlc.so"
+_lib = None
+
+MLC_OK = 0
+MLC_WARN_INNER_MAXIT = 1
+STATUS = {0: "MLC_OK", -1: "MLC_ERR_ARG", -2: "MLC_ERR_MESH", -3: "MLC_ERR_NOT_NESTED", -4: "MLC_ERR_WORKSPACE",
+          -5: "MLC_ERR_HIP", -6: "MLC_ERR_NOT_CONVERGED", -7: "MLC_ERR_BREAKDOWN", -8: "MLC_ERR_NONFINITE",
+          -9: "MLC_ERR_STATE", 1: "MLC_WARN_INNER_MAXIT"}
+
+PROBES = ["U", "W0", "G", "VXC_QP", "PT_AFIX_U", "PT_MW0_U", "PT_M_U", "PT_K_U", "UT_AFIX_U", "UT_MW0_U",
+          "UT_M_U", "UT_K_U", "HARTREE_D", "AFIX_H", "MW0_H", "M_H", "K_H", "AH4", "RHS", "THETA2", "PHI_H",
+          "WH", "SIGMA"]
+PROBE_ID = {name: i for i, name in enumerate(PROBES)}
+
+EXPORTED = ["mlc_options_default", "mlc_create", "mlc_sizes", "mlc_workspace_bytes", "mlc_bind",
+            "mlc_initial_state", "mlc_set_state", "mlc_correction_step", "mlc_get_results", "mlc_probe",
+            "mlc_status_string", "mlc_last_error", "mlc_destroy"]
+
+
+class MlcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_vertices", C.c_int64), ("xyz", C.POINTER(C.c_double)), ("n_tets", C.c_int64),
+                ("tets", C.POINTER(C.c_int32))]
+
+
+class SystemDesc(C.Structure):
+    _fields_ = [("n_nuclei", C.c_int32), ("R", C.POINTER(C.c_double)), ("Z", C.POINTER(C.c_double)),
+                ("potential", C.c_int32), ("rc", C.c_double), ("omega", C.c_double), ("n_orbitals", C.c_int32),
+                ("occupations", C.POINTER(C.c_double)), ("xc", C.c_int32), ("xalpha", C.c_double),
+                ("hartree", C.c_int32), ("box_lo", C.c_double), ("box_hi", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("cg_rtol", C.c_double), ("cg_maxit", C.c_int32), ("check_every", C.c_int32),
+                ("shift", C.c_int32), ("sigma0", C.c_double), ("poisson_rtol", C.c_double),
+                ("inner_maxit", C.c_int32), ("inner_tol", C.c_double), ("n_extra", C.c_int32),
+                ("reorder", C.c_int32), ("time_kernels", C.c_int32)]
+
+
+class StepReport(C.Structure):
+    _fields_ = [("cg_iters_max", C.c_int32), ("cg_iters_sum", C.c_int32), ("poisson_iters", C.c_int32),
+                ("inner_iters", C.c_int32), ("cg_relres_max", C.c_double), ("poisson_relres", C.c_double),
+                ("inner_last_diff", C.c_double), ("sigma", C.c_double), ("theta1", C.c_double),
+                ("max_offdiag_overlap", C.c_double), ("rho_integral", C.c_double), ("energy", C.c_double),
+                ("t_fine_ms", C.c_double), ("t_inner_ms", C.c_double), ("t_recon_ms", C.c_double),
+                ("t_spmm_ms", C.c_double), ("n_spmm", C.c_int64), ("spmm_rows", C.c_int64),
+                ("spmm_cols_sum", C.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def lib():
+    """Load libmlc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise RuntimeError(f"{LIB_PATH} not found: build it with `python -m paper_2103_02824_amd.build`")
+    L = C.CDLL(str(LIB_PATH))
+    P, i32, i64, dbl, vp = C.POINTER, C.c_int32, C.c_int64, C.c_double, C.c_void_p
+    L.mlc_options_default.argtypes = [P(Options)]
+    L.mlc_options_default.restype = None
+    L.mlc_create.argtypes = [P(Mesh), P(Mesh), P(SystemDesc), P(Options), P(vp)]
+    L.mlc_sizes.argtypes = [vp, P(i64), P(i64), P(i64), P(i32)]
+    L.mlc_workspace_bytes.argtypes = [vp, P(C.c_size_t)]
+    L.mlc_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    L.mlc_initial_state.argtypes = [vp, dbl, i32, P(i32)]
+    L.mlc_set_state.argtypes = [vp, P(dbl), P(dbl), P(dbl)]
+    L.mlc_correction_step.argtypes = [vp, P(StepReport)]
+    L.mlc_get_results.argtypes = [vp, P(dbl), P(dbl), P(dbl), P(dbl)]
+    L.mlc_probe.argtypes = [vp, i32, P(dbl), i64]
+    L.mlc_status_string.argtypes = [i32]
+    L.mlc_status_string.restype = C.c_char_p
+    L.mlc_last_error.argtypes = [vp]
+    L.mlc_last_error.restype = C.c_char_p
+    L.mlc_destroy.argtypes = [vp]
+    L.mlc_destroy.restype = None
+    for f in ("mlc_create", "mlc_sizes", "mlc_workspace_bytes", "mlc_bind", "mlc_initial_state", "mlc_set_state",
+              "mlc_correction_step", "mlc_get_results", "mlc_probe"):
+        getattr(L, f).restype = i32
+    _lib = L
+    return L
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def options(**kw):
+    o = Options()
+    lib().mlc_options_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """One library context bound to a torch-allocated workspace and stream."""
+
+    def __init__(self, system, opts: Options = None, device="cuda:0"):
+        import torch
+
+        L = lib()
+        self._keep = []
+        xyz = np.ascontiguousarray(system.xyz, dtype=np.float64)
+        tets = np.ascontiguousarray(system.tets, dtype=np.int32)
+        cxyz = np.ascontiguousarray(system.cxyz, dtype=np.float64)
+        ctets = np.ascontiguousarray(system.ctets, dtype=np.int32)
+        R = np.ascontiguousarray(np.asarray(system.R, dtype=np.float64).reshape(-1, 3))
+        Z = np.ascontiguousarray(np.asarray(system.Z, dtype=np.float64).ravel())
+        occ = np.ascontiguousarray(np.asarray(system.occupations, dtype=np.float64))
+        self._keep += [xyz, tets, cxyz, ctets, R, Z, occ]
+        fine = Mesh(len(xyz), _dp(xyz), len(tets), tets.ctypes.data_as(C.POINTER(C.c_int32)))
+        coarse = Mesh(len(cxyz), _dp(cxyz), len(ctets), ctets.ctypes.data_as(C.POINTER(C.c_int32)))
+        sd = SystemDesc(len(Z), _dp(R), _dp(Z), int(system.potential), float(system.rc), float(system.omega),
+                        int(system.n_orbitals), _dp(occ), int(system.xc), float(system.xalpha),
+                        int(bool(system.hartree)), float(system.lo), float(system.hi))
+        self.opts = opts if opts is not None else options()
+        h = C.c_void_p()
+        st = L.mlc_create(C.byref(fine), C.byref(coarse), C.byref(sd), C.byref(self.opts), C.byref(h))
+        if st != MLC_OK:
+            msg = L.mlc_last_error(h).decode() if h.value else "mlc_create failed"
+            if h.value:
+                L.mlc_destroy(h)
+            raise MlcError(st, msg)
+        self.h = h
+        n, nH, nv, N = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
+        self._chk(L.mlc_sizes(h, C.byref(n), C.byref(nH), C.byref(nv), C.byref(N)))
+        self.n_dof, self.n_coarse_dof, self.n_vertices, self.N = n.value, nH.value, nv.value, N.value
+        self.n_tets = len(tets)
+        nbytes = C.c_size_t()
+        self._chk(L.mlc_workspace_bytes(h, C.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self._chk(L.mlc_bind(h, C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                             C.c_void_p(self.stream.cuda_stream)))
+
+    def _chk(self, st, allow_warn=False):
+        if st == MLC_OK or (allow_warn and st > 0):
+            return st
+        raise MlcError(st, lib().mlc_last_error(self.h).decode())
+
+    def initial_state(self, tol=1e-11, maxit=400):
+        it = C.c_int32()
+        self._chk(lib().mlc_initial_state(self.h, tol, maxit, C.byref(it)))
+        return it.value
+
+    def set_state(self, lam, Phi, w):
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        Phi = np.ascontiguousarray(Phi, dtype=np.float64).reshape(self.n_dof, self.N)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        assert lam.shape == (self.N,) and w.shape == (self.n_vertices,)
+        self._chk(lib().mlc_set_state(self.h, _dp(lam), _dp(Phi), _dp(w)))
+
+    def correction_step(self, allow_warn=True):
+        rep = StepReport()
+        st = lib().mlc_correction_step(self.h, C.byref(rep))
+        self._chk(st, allow_warn=allow_warn)
+        d = rep.as_dict()
+        d["status"] = st
+        return d
+
+    def get_results(self):
+        lam = np.zeros(self.N)
+        Phi = np.zeros((self.n_dof, self.N))
+        w = np.zeros(self.n_vertices)
+        rho = np.zeros(self.n_vertices)
+        self._chk(lib().mlc_get_results(self.h, _dp(lam), _dp(Phi), _dp(w), _dp(rho)))
+        return lam, Phi, w, rho
+
+    def probe(self, name, shape):
+        out = np.zeros(int(np.prod(shape)))
+        self._chk(lib().mlc_probe(self.h, PROBE_ID[name], _dp(out), out.size))
+        return out.reshape(shape)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().mlc_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,129 @@
+"""The C-ABI library: it loads, exports every function include/mlc.h declares,
+and its host-side validation (no GPU work) rejects bad input with the
+documented status codes."""
+import ctypes as C
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from inputs.meshgen import kuhn_mesh
+from inputs.systems import c1_hydrogen
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def _lib():
+    from paper_2103_02824_amd import mlc
+    if not mlc.LIB_PATH.exists():
+        pytest.fail("libmlc.so is not built (run __graft_entry__.build())")
+    return mlc, mlc.lib()
+
+
+def test_exports_match_header():
+    mlc, L = _lib()
+    hdr = (ROOT / "include" / "mlc.h").read_text()
+    declared = set(re.findall(r"\b(mlc_[a-z_]+)\s*\(", hdr))
+    declared -= {"mlc_status"}
+    assert declared, "no declarations found"
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert declared == set(mlc.EXPORTED)
+
+
+def _create(mlc, L, S, fine_xyz=None, fine_tets=None, coarse_xyz=None, coarse_tets=None, **sysover):
+    xyz = np.ascontiguousarray(S.xyz if fine_xyz is None else fine_xyz, dtype=np.float64)
+    tets = np.ascontiguousarray(S.tets if fine_tets is None else fine_tets, dtype=np.int32)
+    cxyz = np.ascontiguousarray(S.cxyz if coarse_xyz is None else coarse_xyz, dtype=np.float64)
+    ctets = np.ascontiguousarray(S.ctets if coarse_tets is None else coarse_tets, dtype=np.int32)
+    R = np.ascontiguousarray(S.R.reshape(-1, 3))
+    Z = np.ascontiguousarray(S.Z, dtype=np.float64)
+    occ = np.ascontiguousarray(S.occupations, dtype=np.float64)
+    fine = mlc.Mesh(len(xyz), mlc._dp(xyz), len(tets), tets.ctypes.data_as(C.POINTER(C.c_int32)))
+    coarse = mlc.Mesh(len(cxyz), mlc._dp(cxyz), len(ctets), ctets.ctypes.data_as(C.POINTER(C.c_int32)))
+    sd = mlc.SystemDesc(len(Z), mlc._dp(R), mlc._dp(Z), S.potential, S.rc, S.omega, S.n_orbitals, mlc._dp(occ),
+                        S.xc, S.xalpha, int(S.hartree), S.lo, S.hi)
+    for k, v in sysover.items():
+        setattr(sd, k, v)
+    o = mlc.options()
+    h = C.c_void_p()
+    st = L.mlc_create(C.byref(fine), C.byref(coarse), C.byref(sd), C.byref(o), C.byref(h))
+    msg = L.mlc_last_error(h).decode() if h.value else ""
+    sizes = None
+    if st == 0:
+        n, nH, nv, N = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
+        L.mlc_sizes(h, C.byref(n), C.byref(nH), C.byref(nv), C.byref(N))
+        b = C.c_size_t()
+        assert L.mlc_workspace_bytes(h, C.byref(b)) == 0
+        sizes = (n.value, nH.value, nv.value, N.value, b.value)
+    if h.value:
+        L.mlc_destroy(h)
+    return st, msg, sizes
+
+
+def test_create_sizes_hydrogen():
+    mlc, L = _lib()
+    S = c1_hydrogen()
+    st, msg, sizes = _create(mlc, L, S)
+    assert st == 0, msg
+    n, nH, nv, N, ws = sizes
+    assert (n, nH, nv, N) == (15 ** 3, 7 ** 3, 17 ** 3, 1)
+    assert ws > 0
+
+
+def test_rejects_non_nested_coarse_mesh():
+    mlc, L = _lib()
+    S = c1_hydrogen()
+    cxyz, ctets = kuhn_mesh(8, -9.0, 9.0)   # smaller box: fine vertices outside
+    st, msg, _ = _create(mlc, L, S, coarse_xyz=cxyz, coarse_tets=ctets)
+    assert st == -3, (st, msg)
+
+
+def test_rejects_bad_tet_index_and_degenerate_tet():
+    mlc, L = _lib()
+    S = c1_hydrogen()
+    t = S.tets.copy()
+    t[5, 2] = len(S.xyz) + 7
+    st, msg, _ = _create(mlc, L, S, fine_tets=t)
+    assert st == -2, (st, msg)
+    t = S.tets.copy()
+    t[3, 1] = t[3, 0]
+    st, msg, _ = _create(mlc, L, S, fine_tets=t)
+    assert st == -2, (st, msg)
+
+
+def test_rejects_bad_system():
+    mlc, L = _lib()
+    S = c1_hydrogen()
+    assert _create(mlc, L, S, n_orbitals=0)[0] == -1
+    assert _create(mlc, L, S, xc=7)[0] == -1
+    assert _create(mlc, L, S, box_lo=10.0)[0] == -1
+    assert _create(mlc, L, S, rc=0.0)[0] == -1
+
+
+def test_status_strings():
+    mlc, L = _lib()
+    for s in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, 1):
+        assert L.mlc_status_string(s).decode() not in ("", "unknown status")
+
+
+def test_calls_before_bind_fail_cleanly():
+    mlc, L = _lib()
+    S = c1_hydrogen()
+    xyz = np.ascontiguousarray(S.xyz)
+    tets = np.ascontiguousarray(S.tets, dtype=np.int32)
+    cxyz = np.ascontiguousarray(S.cxyz)
+    ctets = np.ascontiguousarray(S.ctets, dtype=np.int32)
+    R, Z, occ = np.zeros(3), np.ones(1), np.ones(1)
+    fine = mlc.Mesh(len(xyz), mlc._dp(xyz), len(tets), tets.ctypes.data_as(C.POINTER(C.c_int32)))
+    coarse = mlc.Mesh(len(cxyz), mlc._dp(cxyz), len(ctets), ctets.ctypes.data_as(C.POINTER(C.c_int32)))
+    sd = mlc.SystemDesc(1, mlc._dp(R), mlc._dp(Z), 0, 0.2, 1.0, 1, mlc._dp(occ), 1, 0.77298, 1, -10.0, 10.0)
+    h = C.c_void_p()
+    assert L.mlc_create(C.byref(fine), C.byref(coarse), C.byref(sd), None, C.byref(h)) == 0
+    rep = mlc.StepReport()
+    assert L.mlc_correction_step(h, C.byref(rep)) == -9
+    assert L.mlc_bind(h, None, 0, None) == -4
+    lam = np.zeros(1)
+    assert L.mlc_get_results(h, mlc._dp(lam), None, None, None) == -9
+    L.mlc_destroy(h)
