@@ -110,7 +110,9 @@ typedef struct {
   double inner_tol;     /* Algorithm 2 stop: ||Phi^{s+1} - Phi^s||_{H^1}      */
   int32_t n_extra;      /* candidates = lowest min(N_H+1, N + n_extra) pairs  */
   int32_t reorder;      /* 1: Morton order of fine DoFs (default)            */
-  int32_t time_kernels; /* 1: HIP events around every SpMM launch            */
+  int32_t time_kernels; /* 1: HIP events around every SpMM launch of step 5
+                           (that CG is then launched eagerly)                  */
+  int32_t use_graphs;   /* 1: CG iteration chunks replayed as HIP graphs      */
 } mlc_options;
 
 /* Filled by mlc_correction_step. Times in milliseconds. */
@@ -137,7 +139,7 @@ typedef struct mlc_ctx mlc_ctx;
 
 /* Fill *opt with defaults: cg_rtol 1e-10, cg_maxit 20000, check_every 25,
  * shift 1, sigma0 1, poisson_rtol 1e-12, inner_maxit 500, inner_tol 1e-10,
- * n_extra 8, reorder 1, time_kernels 0. */
+ * n_extra 8, reorder 1, time_kernels 0, use_graphs 1. */
 void mlc_options_default(mlc_options* opt);
 
 /* Build a context: validates both meshes (positive volumes, indices in range,

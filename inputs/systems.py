@@ -87,7 +87,7 @@ def c1_hydrogen():
 
 def cluster_system(seed, n_atoms=4, half_width=3.0, d_min=1.5, box=15.0, rc=0.5,
                    n_base=8, h0=0.12, kappa=0.12, h_min=0.12, h_max=None, name=None,
-                   n_orbitals=None, coarse=(1.0, 0.5, 1.0)):
+                   n_orbitals=None, coarse=(1.4, 0.6, 1.4)):
     """A seeded cluster with a graded P1 mesh refined toward the nuclei.
 
     Defaults give the 4-atom workload: positions in [-3,3]^3, separation

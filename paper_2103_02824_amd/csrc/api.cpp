@@ -101,14 +101,15 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->RZ = w.take<double>(4 * std::max<int64_t>(1, c->n_nuclei));
   d->colv = w.take<double>(2 * N);
   int64_t nred = std::max<int64_t>(3 * (int64_t)elem_blocks(n, (int)N) * N, 3 * (int64_t)elem_blocks(n, 1));
+  nred = std::max<int64_t>(nred, 2 * (int64_t)cg_max_blocks() * 3 * std::max<int64_t>(N, 1));
   nred = std::max<int64_t>(nred, (int64_t)qp_blocks(nt) * 16);
   nred = std::max<int64_t>(nred, (int64_t)gram_blocks(n) * N * N);
   c->nred = nred;
   d->red = w.take<double>(nred);
-  d->scal = w.take<double>(8 * N);
-  d->scalP = w.take<double>(8);
-  d->flags = w.take<int32_t>(4);
-  d->flagsP = w.take<int32_t>(4);
+  d->scal = w.take<double>(10 * N);
+  d->scalP = w.take<double>(10);
+  d->flags = w.take<int32_t>(8);
+  d->flagsP = w.take<int32_t>(8);
   return w.off + 256;
 }
 
@@ -165,6 +166,7 @@ mlc_status upload_and_init(mlc_ctx* c) {
   HIPCHK(hipMemsetAsync(d.w, 0, sizeof(double) * c->nv, s));
   HIPCHK(hipMemsetAsync(d.g, 0, sizeof(double) * c->nv, s));
   HIPCHK(hipMemsetAsync(d.small, 0, sizeof(double) * small_len(c->nH, c->N), s));
+  HIPCHK(hipMemsetAsync(d.w0, 0, sizeof(double) * c->n, s));
   // fixed quantities: V_ext at the quadrature points, K, M, coarse trilinear tensor
   launch_vext(s, c->nt, d.qpx, d.RZ, c->n_nuclei, c->potential, c->rc, c->omega, d.vext);
   launch_assemble(s, c->n, d.rowptr, d.adj_ptr, d.adj_tet, d.adj_loc, d.adj_pos, d.geo, 1.0, nullptr, 0.0, d.valK,
@@ -329,6 +331,7 @@ void mlc_options_default(mlc_options* o) {
   o->n_extra = 8;
   o->reorder = 1;
   o->time_kernels = 0;
+  o->use_graphs = 1;
 }
 
 mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys, const mlc_options* opt,
@@ -408,6 +411,15 @@ mlc_status mlc_bind(mlc_ctx* c, void* dev_workspace, size_t bytes, void* hip_str
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   c->ev_pool.clear();
   c->ev_used = 0;
+  for (int k = 0; k < 2; ++k) {
+    if (c->cg_graph[k]) (void)hipGraphExecDestroy(c->cg_graph[k]);
+    c->cg_graph[k] = nullptr;
+    c->cg_graph_chunk[k] = 0;
+  }
+  if (c->opt.use_graphs && !c->cap_stream) {
+    hipError_t he = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (he != hipSuccess) return hip_fail(c, he, "hipStreamCreateWithFlags");
+  }
   if (c->opt.time_kernels) {
     c->ev_pool.resize(2 * std::max(1, c->opt.check_every));
     for (auto& e : c->ev_pool) {
@@ -511,6 +523,9 @@ const char* mlc_last_error(const mlc_ctx* c) { return c ? c->err.c_str() : "null
 void mlc_destroy(mlc_ctx* c) {
   if (!c) return;
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (int k = 0; k < 2; ++k)
+    if (c->cg_graph[k]) (void)hipGraphExecDestroy(c->cg_graph[k]);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 

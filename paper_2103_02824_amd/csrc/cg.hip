@@ -1,0 +1,427 @@
+// Multi-right-hand-side CSR SpMM and the Jacobi-PCG vector kernels (gfx950).
+//
+// Orbital blocks are n x N row-major (orbital fastest). Every CG recurrence is
+// independent per column (the step-5 problems are independent per orbital,
+// Section 3.2): alpha, beta and the convergence flag are per column and live
+// on the device.
+//
+// One CG iteration is three kernels: SpMM q = A p (block partials of p.q),
+// update (alpha from the p.q partials; x, r; partials of r.Dr and r.r) and
+// direction (beta and the convergence test from those partials; p). Each
+// consumer kernel sums the producer's block partials itself, every block in
+// the same fixed order, so all blocks obtain bitwise identical scalars without
+// a separate reduction launch; grids are capped (rows visited grid-stride) to
+// keep those partial sets small. A last-arriving-block reduction would need a
+// device-scope fence in every block, which on this multi-die part means an L2
+// write-back per block and costs more than it saves. Scalars are double
+// buffered by iteration parity so that no kernel reads a value another block
+// of the same launch writes.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mlc_internal.h"
+
+namespace mlc {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int MAXBLK = 1024;       // plain SpMM / init grids
+constexpr int SPMM_BS = 1024;      // CG SpMM block size (16 waves per block)
+constexpr int SPMM_MAXBLK = 512;   // CG SpMM grid cap (number of p.q partials)
+constexpr int VEC_MAXBLK = 512;    // update / direction grid cap
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// In-block column sums for the (row, column) thread layout (R rows x N cols);
+// leaves column sums in sd[0..N).
+__device__ __forceinline__ void block_reduce_cols(double* sd, int R, int N) {
+  int t = threadIdx.x;
+  int m = R;
+  while (m > 1) {
+    int h = (m + 1) >> 1;
+    __syncthreads();
+    if (t < (m - h) * N) sd[t] += sd[t + h * N];
+    m = h;
+  }
+  __syncthreads();
+}
+
+inline int cap(int64_t needed, int mx) { return (int)(needed < mx ? (needed < 1 ? 1 : needed) : mx); }
+
+// ---------------------------------------------------------------------------
+// SpMM for small N (compile-time NT <= 8): G lanes share a row, each lane
+// takes every G-th nonzero and keeps all NT column sums in registers; the G
+// partial sums are combined with lane shuffles. Column indices and values are
+// read coalesced (G consecutive entries), X rows as NT consecutive doubles.
+// Optional CG epilogue: per-block column sums of P . Q.
+template <int NT, int G, int BS>
+__global__ void __launch_bounds__(BS) k_spmm_small(int64_t n, const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                   const double* __restrict__ X, double* __restrict__ Y,
+                                                   double* __restrict__ partial, const int32_t* __restrict__ flags) {
+  constexpr int RB = BS / G;  // rows per block pass
+  if (flags && flags[0] == 0) return;
+  __shared__ double sd[BS / 64][NT];
+  const int sub = threadIdx.x % G;
+  const int rl = threadIdx.x / G;
+  double dot[NT];
+#pragma unroll
+  for (int c = 0; c < NT; ++c) dot[c] = 0.0;
+  for (int64_t r0 = (int64_t)blockIdx.x * RB; r0 < n; r0 += (int64_t)gridDim.x * RB) {
+    int64_t r = r0 + rl;
+    double acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[c] = 0.0;
+    if (r < n) {
+      int j1 = rowptr[r + 1];
+      for (int j = rowptr[r] + sub; j < j1; j += G) {
+        double a = val[j];
+        const double* xr = X + (int64_t)col[j] * NT;
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[c] += a * xr[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, G);
+    if (r < n) {
+#pragma unroll
+      for (int c = 0; c < NT; ++c)
+        if (c % G == sub) {
+          Y[r * NT + c] = acc[c];
+          if (partial) dot[c] += acc[c] * X[r * NT + c];
+        }
+    }
+  }
+  if (!partial) return;
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    double v = wave_sum(dot[c]);
+    if (lane == 0) sd[wid][c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NT) {
+    int c = threadIdx.x;
+    double s = 0.0;
+    for (int w = 0; w < BS / 64; ++w) s += sd[w][c];
+    partial[(int64_t)blockIdx.x * NT + c] = s;
+  }
+}
+
+// SpMM for wider blocks (N > 8): thread (row, column), R = 256/N rows per pass,
+// the nonzero loop unrolled by 4 so that four gathers are in flight.
+__global__ void __launch_bounds__(TPB) k_spmm_wide(int64_t n, int N, const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                   const double* __restrict__ X, double* __restrict__ Y,
+                                                   double* __restrict__ partial, const int32_t* __restrict__ flags) {
+  if (flags && flags[0] == 0) return;
+  __shared__ double sd[TPB];
+  const int R = TPB / N;
+  const int t = threadIdx.x;
+  const int rl = t / N, c = t - rl * N;
+  double dot = 0.0;
+  for (int64_t r0 = (int64_t)blockIdx.x * R; r0 < n; r0 += (int64_t)gridDim.x * R) {
+    int64_t r = r0 + rl;
+    if (rl < R && r < n) {
+      int j = rowptr[r], j1 = rowptr[r + 1];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      for (; j + 3 < j1; j += 4) {
+        int k0 = col[j], k1 = col[j + 1], k2 = col[j + 2], k3 = col[j + 3];
+        a0 += val[j] * X[(int64_t)k0 * N + c];
+        a1 += val[j + 1] * X[(int64_t)k1 * N + c];
+        a2 += val[j + 2] * X[(int64_t)k2 * N + c];
+        a3 += val[j + 3] * X[(int64_t)k3 * N + c];
+      }
+      for (; j < j1; ++j) a0 += val[j] * X[(int64_t)col[j] * N + c];
+      double acc = (a0 + a1) + (a2 + a3);
+      Y[r * N + c] = acc;
+      if (partial) dot += acc * X[r * N + c];
+    }
+  }
+  if (!partial) return;
+  sd[t] = dot;
+  block_reduce_cols(sd, R, N);
+  if (t < N) partial[(int64_t)blockIdx.x * N + t] = sd[t];
+}
+
+// (row, column) thread layout of the vector kernels
+struct RC {
+  int R, rl, c;
+  __device__ RC(int N) {
+    R = TPB / N;
+    rl = threadIdx.x / N;
+    c = threadIdx.x - rl * N;
+  }
+};
+
+// CG start: R = B - AX, P = Dinv R; block partials of rz, rr, bb.
+__global__ void __launch_bounds__(TPB) k_cg_init(int64_t n, int N, const double* __restrict__ B,
+                                                 const double* __restrict__ AX, const double* __restrict__ dinv,
+                                                 double* __restrict__ Rv, double* __restrict__ P,
+                                                 double* __restrict__ partial) {
+  __shared__ double sd[TPB];
+  RC p(N);
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int64_t r0 = (int64_t)blockIdx.x * p.R; r0 < n; r0 += (int64_t)gridDim.x * p.R) {
+    int64_t r = r0 + p.rl;
+    if (p.rl < p.R && r < n) {
+      int64_t i = r * N + p.c;
+      double b = B[i];
+      double rr = b - AX[i];
+      double z = dinv[r] * rr;
+      Rv[i] = rr;
+      P[i] = z;
+      v[0] += rr * z;
+      v[1] += rr * rr;
+      v[2] += b * b;
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    __syncthreads();
+    sd[threadIdx.x] = v[k];
+    block_reduce_cols(sd, p.R, N);
+    if ((int)threadIdx.x < N) partial[((int64_t)blockIdx.x * 3 + k) * N + threadIdx.x] = sd[threadIdx.x];
+  }
+}
+
+// Column sums of nblk block partials (row b holds nvals values), computed by
+// every block of a consumer kernel in the same fixed order. out: shared array.
+__device__ void sum_partials(const double* __restrict__ partial, int nblk, int nvals, double* out) {
+  constexpr int CH = 16;
+  __shared__ double wsum[TPB / 64][CH];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int v0 = 0; v0 < nvals; v0 += CH) {
+    int nc = nvals - v0 < CH ? nvals - v0 : CH;
+    double acc[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) acc[q] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += TPB) {
+      const double* p = partial + (int64_t)b * nvals + v0;
+#pragma unroll
+      for (int q = 0; q < CH; ++q)
+        if (q < nc) acc[q] += p[q];
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      double v = wave_sum(acc[q]);
+      if (lane == 0) wsum[wid][q] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+      int q = threadIdx.x;
+      out[v0 + q] = (wsum[0][q] + wsum[1][q]) + (wsum[2][q] + wsum[3][q]);
+    }
+    __syncthreads();
+  }
+}
+
+// scal buffer per column c (two buffers, alternating by iteration parity):
+// [0] rz [1] rr [2] bb [3] active [4] iterations.  flags: [0] active count.
+enum { C_RZ = 0, C_RR, C_BB, C_ACT, C_IT };
+
+// CG start scalars from the k_cg_init partials [rz, rr, bb] (one block).
+__global__ void __launch_bounds__(TPB) k_cg_start(int N, int nblk, const double* __restrict__ partial, double rtol2,
+                                                 double* __restrict__ scal, int32_t* __restrict__ flags) {
+  __shared__ double sums[3 * MLC_MAX_ORBITALS];
+  sum_partials(partial, nblk, 3 * N, sums);
+  if (threadIdx.x != 0) return;
+  int nact = 0;
+  for (int c = 0; c < N; ++c) {
+    scal[C_RZ * N + c] = sums[c];
+    scal[C_RR * N + c] = sums[N + c];
+    scal[C_BB * N + c] = sums[2 * N + c];
+    scal[C_IT * N + c] = 0.0;
+    bool act = sums[N + c] > rtol2 * sums[2 * N + c];
+    scal[C_ACT * N + c] = act ? 1.0 : 0.0;
+    nact += act;
+  }
+  flags[0] = nact;
+}
+
+// alpha_c = rz_c / (p.q)_c from the SpMM partials; X += alpha P, R -= alpha Q;
+// block partials of r.Dr and r.r. A non-positive curvature on an active
+// column sets brk and freezes that column (alpha = 0).
+__global__ void __launch_bounds__(TPB) k_cg_update(int64_t n, int N, const double* __restrict__ dinv,
+                                                   double* __restrict__ X, double* __restrict__ Rv,
+                                                   const double* __restrict__ P, const double* __restrict__ Q,
+                                                   const double* __restrict__ pq_part, int nblk_pq,
+                                                   const double* __restrict__ scal, const int32_t* __restrict__ flags,
+                                                   double* __restrict__ partial, int32_t* __restrict__ brk) {
+  if (flags[0] == 0) return;
+  __shared__ double sd[TPB];
+  __shared__ double alpha[MLC_MAX_ORBITALS];
+  sum_partials(pq_part, nblk_pq, N, alpha);
+  if ((int)threadIdx.x < N) {
+    int c = threadIdx.x;
+    double pq = alpha[c];
+    bool act = scal[C_ACT * N + c] != 0.0;
+    if (act && !(pq > 0.0)) {
+      if (blockIdx.x == 0) brk[0] = 1;
+      act = false;
+    }
+    alpha[c] = act ? scal[C_RZ * N + c] / pq : 0.0;
+  }
+  __syncthreads();
+  RC p(N);
+  double a = p.rl < p.R ? alpha[p.c] : 0.0;
+  double v[2] = {0.0, 0.0};
+  for (int64_t r0 = (int64_t)blockIdx.x * p.R; r0 < n; r0 += (int64_t)gridDim.x * p.R) {
+    int64_t r = r0 + p.rl;
+    if (p.rl < p.R && r < n) {
+      int64_t i = r * N + p.c;
+      double x = X[i] + a * P[i];
+      double rr = Rv[i] - a * Q[i];
+      X[i] = x;
+      Rv[i] = rr;
+      v[0] += rr * dinv[r] * rr;
+      v[1] += rr * rr;
+    }
+  }
+  for (int k = 0; k < 2; ++k) {
+    __syncthreads();
+    sd[threadIdx.x] = v[k];
+    block_reduce_cols(sd, p.R, N);
+    if ((int)threadIdx.x < N) partial[((int64_t)blockIdx.x * 2 + k) * N + threadIdx.x] = sd[threadIdx.x];
+  }
+}
+
+// beta_c = rz'_c / rz_c and the test ||r||^2 <= rtol^2 ||b||^2 from the update
+// partials; P = Dinv R + beta P. Block 0 writes the next scalars (the other
+// buffer) and the active count.
+__global__ void __launch_bounds__(TPB) k_cg_direction(int64_t n, int N, const double* __restrict__ dinv,
+                                                      const double* __restrict__ Rv, double* __restrict__ P,
+                                                      const double* __restrict__ upd_part, int nblk_upd,
+                                                      const double* __restrict__ scal_in,
+                                                      const int32_t* __restrict__ flags_in,
+                                                      double* __restrict__ scal_out, int32_t* __restrict__ flags_out,
+                                                      double rtol2) {
+  if (flags_in[0] == 0) {
+    // converged: carry the scalars to the other buffer so that the parity
+    // alternation stays consistent, then do nothing else
+    if (blockIdx.x == 0) {
+      for (int i = threadIdx.x; i < 5 * N; i += TPB) scal_out[i] = scal_in[i];
+      if (threadIdx.x == 0) flags_out[0] = 0;
+    }
+    return;
+  }
+  __shared__ double sums[2 * MLC_MAX_ORBITALS];
+  __shared__ double beta[MLC_MAX_ORBITALS];
+  __shared__ double still[MLC_MAX_ORBITALS];
+  sum_partials(upd_part, nblk_upd, 2 * N, sums);
+  if ((int)threadIdx.x < N) {
+    int c = threadIdx.x;
+    bool act = scal_in[C_ACT * N + c] != 0.0;
+    double rzn = sums[c], rr = sums[N + c];
+    beta[c] = act ? rzn / scal_in[C_RZ * N + c] : 0.0;
+    double bb = scal_in[C_BB * N + c];
+    still[c] = (act && rr > rtol2 * bb) ? 1.0 : 0.0;
+    if (blockIdx.x == 0) {
+      scal_out[C_RZ * N + c] = act ? rzn : scal_in[C_RZ * N + c];
+      scal_out[C_RR * N + c] = act ? rr : scal_in[C_RR * N + c];
+      scal_out[C_BB * N + c] = bb;
+      scal_out[C_IT * N + c] = scal_in[C_IT * N + c] + (act ? 1.0 : 0.0);
+      scal_out[C_ACT * N + c] = still[c];
+    }
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int nact = 0;
+    for (int c = 0; c < N; ++c) nact += still[c] != 0.0;
+    flags_out[0] = nact;
+  }
+  int64_t total = n * N;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < total; i += (int64_t)gridDim.x * TPB) {
+    int64_t r = i / N;
+    int c = (int)(i - r * N);
+    P[i] = dinv[r] * Rv[i] + beta[c] * P[i];
+  }
+}
+
+template <int NT, int BS>
+void spmm_small(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                const double* X, double* Y, double* partial, const int32_t* flags, int maxblk) {
+  constexpr int G = NT == 1 ? 8 : 4;
+  int64_t needed = (n + (BS / G) - 1) / (BS / G);
+  hipLaunchKernelGGL((k_spmm_small<NT, G, BS>), dim3(cap(needed, maxblk)), dim3(BS), 0, s, n, rowptr, col, val, X, Y,
+                     partial, flags);
+}
+
+int vec_blocks(int64_t n, int N) {
+  int64_t R = TPB / N;
+  return cap((n + R - 1) / R, VEC_MAXBLK);
+}
+
+}  // namespace
+
+int cg_blocks(int64_t n, int N) {
+  int64_t R = TPB / N;
+  return cap((n + R - 1) / R, MAXBLK);
+}
+int spmm_blocks(int64_t n, int N) {
+  if (N <= 8) {
+    int G = N == 1 ? 8 : 4;
+    return cap((n + (SPMM_BS / G) - 1) / (SPMM_BS / G), SPMM_MAXBLK);
+  }
+  return cg_blocks(n, N);
+}
+int cg_max_blocks() { return MAXBLK; }
+
+// Y = A X (N columns); with partial: per-block column sums of X . Y (the CG
+// variant, 1024-thread blocks); with flags: early exit when no column is active.
+void launch_spmm2(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const double* val,
+                  const double* X, double* Y, double* partial, const int32_t* flags) {
+#define SPMM_CASE(K)                                                                     \
+  case K:                                                                                \
+    if (partial)                                                                         \
+      spmm_small<K, SPMM_BS>(s, n, rowptr, col, val, X, Y, partial, flags, SPMM_MAXBLK); \
+    else                                                                                 \
+      spmm_small<K, TPB>(s, n, rowptr, col, val, X, Y, partial, flags, MAXBLK);          \
+    return;
+  switch (N) {
+    SPMM_CASE(1)
+    SPMM_CASE(2)
+    SPMM_CASE(3)
+    SPMM_CASE(4)
+    SPMM_CASE(5)
+    SPMM_CASE(6)
+    SPMM_CASE(7)
+    SPMM_CASE(8)
+    default:
+      hipLaunchKernelGGL(k_spmm_wide, dim3(cg_blocks(n, N)), dim3(TPB), 0, s, n, N, rowptr, col, val, X, Y, partial,
+                         flags);
+  }
+#undef SPMM_CASE
+}
+
+void launch_cg_init2(hipStream_t s, int64_t n, int N, const double* B, const double* AX, const double* dinv,
+                     double* Rv, double* P, double* partial) {
+  hipLaunchKernelGGL(k_cg_init, dim3(cg_blocks(n, N)), dim3(TPB), 0, s, n, N, B, AX, dinv, Rv, P, partial);
+}
+
+void launch_cg_start(hipStream_t s, int64_t n, int N, const double* partial, double rtol2, double* scal,
+                     int32_t* flags) {
+  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(TPB), 0, s, N, cg_blocks(n, N), partial, rtol2, scal, flags);
+}
+
+void launch_cg_update_f(hipStream_t s, int64_t n, int N, const double* dinv, double* X, double* Rv, const double* P,
+                        const double* Q, const double* pq_part, const double* scal, const int32_t* flags,
+                        double* partial, int32_t* brk) {
+  hipLaunchKernelGGL(k_cg_update, dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, X, Rv, P, Q, pq_part,
+                     spmm_blocks(n, N), scal, flags, partial, brk);
+}
+
+void launch_cg_direction_f(hipStream_t s, int64_t n, int N, const double* dinv, const double* Rv, double* P,
+                           const double* upd_part, const double* scal_in, const int32_t* flags_in, double* scal_out,
+                           int32_t* flags_out, double rtol2) {
+  hipLaunchKernelGGL(k_cg_direction, dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, Rv, P, upd_part,
+                     vec_blocks(n, N), scal_in, flags_in, scal_out, flags_out, rtol2);
+}
+
+}  // namespace mlc

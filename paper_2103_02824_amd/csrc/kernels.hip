@@ -8,7 +8,7 @@
 //
 // Every reduction is two-stage and ordered (block partials, then one block
 // summing partials in block order), so results are bitwise reproducible from
-// run to run. No atomics are used.
+// run to run. The kernels of this file use no atomics.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -360,174 +360,12 @@ __global__ void __launch_bounds__(TPB) k_load(int64_t n, const int32_t* __restri
   if (lvec) lvec[a] = lift;
 }
 
-// ---------------------------------------------------------------------------
-// Multi-right-hand-side CSR SpMM  Y = A X  (X, Y: n x N row-major).
-// A block holds R rows x N columns; thread (row, col) walks the row and
-// gathers X[col_j, c]. The N threads of a row read the same index/value
-// (one broadcast transaction) and N consecutive doubles of X per nonzero.
-// Optional epilogue: per-column block partials of X . Y (CG curvature).
-__global__ void __launch_bounds__(TPB) k_spmm(int64_t n, int N, int R, const int32_t* __restrict__ rowptr,
-                                              const int32_t* __restrict__ col, const double* __restrict__ val,
-                                              const double* __restrict__ X, double* __restrict__ Y,
-                                              double* __restrict__ partial) {
-  __shared__ double sd[TPB];
-  int t = threadIdx.x;
-  int rl = t / N, c = t - rl * N;
-  int64_t r = (int64_t)blockIdx.x * R + rl;
-  double dot = 0.0;
-  if (rl < R && r < n) {
-    int j0 = rowptr[r], j1 = rowptr[r + 1];
-    double acc = 0.0;
-    for (int j = j0; j < j1; ++j) acc += val[j] * X[(int64_t)col[j] * N + c];
-    Y[r * N + c] = acc;
-    if (partial) dot = acc * X[r * N + c];
-  }
-  if (partial) {
-    sd[t] = dot;
-    block_reduce_cols(sd, R, N);
-    if (t < N) partial[(int64_t)blockIdx.x * N + t] = sd[t];
-  }
-}
-
 // Y[r,c] = s[c] * X[r,c]
 __global__ void __launch_bounds__(TPB) k_scale_cols_to(int64_t total, int N, const double* __restrict__ X,
                                                        const double* __restrict__ s, double* __restrict__ Y) {
   int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (i >= total) return;
   Y[i] = s[i % N] * X[i];
-}
-
-// CG start: R = B - AX, P = Dinv R; partials rz, rr, bb per column.
-__global__ void __launch_bounds__(TPB) k_cg_init(int64_t n, int N, int R, const double* __restrict__ B,
-                                                 const double* __restrict__ AX, const double* __restrict__ dinv,
-                                                 double* __restrict__ Rv, double* __restrict__ P,
-                                                 double* __restrict__ partial) {
-  __shared__ double sd[TPB];
-  int t = threadIdx.x;
-  int rl = t / N, c = t - rl * N;
-  int64_t r = (int64_t)blockIdx.x * R + rl;
-  double v[3] = {0.0, 0.0, 0.0};
-  if (rl < R && r < n) {
-    int64_t i = r * N + c;
-    double b = B[i];
-    double rr = b - AX[i];
-    double z = dinv[r] * rr;
-    Rv[i] = rr;
-    P[i] = z;
-    v[0] = rr * z;
-    v[1] = rr * rr;
-    v[2] = b * b;
-  }
-  for (int k = 0; k < 3; ++k) {
-    __syncthreads();
-    sd[t] = v[k];
-    block_reduce_cols(sd, R, N);
-    if (t < N) partial[((int64_t)blockIdx.x * 3 + k) * N + t] = sd[t];
-  }
-}
-
-// scal layout (per column c): [0] rz [1] alpha [2] beta [3] rr [4] bb [5] active [6] pq
-// CG update: X += a P, R -= a Q; partials r.z and r.r per column.
-__global__ void __launch_bounds__(TPB) k_cg_update(int64_t n, int N, int R, const double* __restrict__ scal,
-                                                   const double* __restrict__ dinv, double* __restrict__ X,
-                                                   double* __restrict__ Rv, const double* __restrict__ P,
-                                                   const double* __restrict__ Q, double* __restrict__ partial) {
-  __shared__ double sd[TPB];
-  int t = threadIdx.x;
-  int rl = t / N, c = t - rl * N;
-  int64_t r = (int64_t)blockIdx.x * R + rl;
-  double v[2] = {0.0, 0.0};
-  if (rl < R && r < n) {
-    int64_t i = r * N + c;
-    double a = scal[N + c];
-    double x = X[i] + a * P[i];
-    double rr = Rv[i] - a * Q[i];
-    X[i] = x;
-    Rv[i] = rr;
-    v[0] = rr * dinv[r] * rr;
-    v[1] = rr * rr;
-  }
-  for (int k = 0; k < 2; ++k) {
-    __syncthreads();
-    sd[t] = v[k];
-    block_reduce_cols(sd, R, N);
-    if (t < N) partial[((int64_t)blockIdx.x * 2 + k) * N + t] = sd[t];
-  }
-}
-
-// P = Dinv R + beta P
-__global__ void __launch_bounds__(TPB) k_cg_direction(int64_t total, int N, const double* __restrict__ scal,
-                                                      const double* __restrict__ dinv, const double* __restrict__ Rv,
-                                                      double* __restrict__ P) {
-  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (i >= total) return;
-  int c = (int)(i % N);
-  int64_t r = i / N;
-  P[i] = dinv[r] * Rv[i] + scal[2 * N + c] * P[i];
-}
-
-// Per-column CG scalars from block partials (one block, ordered sums).
-//   phase 0: partial = [rz, rr, bb] -> rz, rr, bb, active
-//   phase 1: partial = [pq]         -> alpha (0 for inactive columns)
-//   phase 2: partial = [rz', rr]    -> beta, rz, rr, active
-// flags[0] = number of active columns, flags[1] |= breakdown (pq <= 0).
-__global__ void __launch_bounds__(TPB) k_cg_scalars(int N, int nblk, const double* __restrict__ partial,
-                                                    int phase, double rtol2, double* __restrict__ scal,
-                                                    int32_t* __restrict__ flags) {
-  __shared__ double sd[TPB];
-  int nv = phase == 0 ? 3 : (phase == 1 ? 1 : 2);
-  __shared__ double sums[3 * MLC_MAX_ORBITALS];
-  for (int c = 0; c < N; ++c) {
-    for (int k = 0; k < nv; ++k) {
-      double acc = 0.0;
-      for (int b = threadIdx.x; b < nblk; b += TPB) acc += partial[((int64_t)b * nv + k) * N + c];
-      __syncthreads();
-      sd[threadIdx.x] = acc;
-      for (int s = TPB / 2; s > 0; s >>= 1) {
-        __syncthreads();
-        if ((int)threadIdx.x < s) sd[threadIdx.x] += sd[threadIdx.x + s];
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) sums[k * N + c] = sd[0];
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int nact = 0;
-    for (int c = 0; c < N; ++c) {
-      if (phase == 0) {
-        scal[c] = sums[c];
-        scal[3 * N + c] = sums[N + c];
-        scal[4 * N + c] = sums[2 * N + c];
-        scal[2 * N + c] = 0.0;
-        bool act = sums[N + c] > rtol2 * sums[2 * N + c];
-        scal[5 * N + c] = act ? 1.0 : 0.0;
-        nact += act;
-      } else if (phase == 1) {
-        double pq = sums[c];
-        scal[6 * N + c] = pq;
-        bool act = scal[5 * N + c] != 0.0;
-        if (act && !(pq > 0.0)) {
-          flags[1] = 1;
-          act = false;
-          scal[5 * N + c] = 0.0;
-        }
-        scal[N + c] = act ? scal[c] / pq : 0.0;
-      } else {
-        bool act = scal[5 * N + c] != 0.0;
-        double rzn = sums[c];
-        scal[2 * N + c] = act ? rzn / scal[c] : 0.0;
-        if (act) {
-          scal[c] = rzn;
-          scal[3 * N + c] = sums[N + c];
-        }
-        act = act && (sums[N + c] > rtol2 * scal[4 * N + c]);
-        scal[5 * N + c] = act ? 1.0 : 0.0;
-        nact += act;
-      }
-    }
-    if (phase != 1) flags[0] = nact;
-  }
 }
 
 // Per-column block partials of sum_r X[r,c] Y[r,c].
@@ -570,17 +408,31 @@ __global__ void __launch_bounds__(TPB) k_normalize_cols(int64_t total, int N, co
   X[i] = X[i] / sqrt(s[i % N]);
 }
 
-// out[k, c] = sum_{a in P^T row k} w_a Y[a, c]  (restriction P^T Y, gather form)
+// out[k, c] = sum_{a in P^T row k} w_a Y[a, c]  (restriction P^T Y, gather form).
+// One wavefront per coarse row: lanes stride over the row's fine entries and
+// the 64 partial sums are combined with shuffles (fixed order).
 __global__ void __launch_bounds__(TPB) k_restrict(int64_t nH, int N, const int32_t* __restrict__ PTptr,
                                                   const int32_t* __restrict__ PTidx, const double* __restrict__ PTw,
                                                   const double* __restrict__ Y, double* __restrict__ out) {
-  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (i >= nH * N) return;
-  int64_t k = i / N;
-  int c = (int)(i - k * N);
-  double acc = 0.0;
-  for (int e = PTptr[k]; e < PTptr[k + 1]; ++e) acc += PTw[e] * Y[(int64_t)PTidx[e] * N + c];
-  out[i] = acc;
+  int64_t k = (int64_t)blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (k >= nH) return;
+  int e0 = PTptr[k], e1 = PTptr[k + 1];
+  for (int c0 = 0; c0 < N; c0 += 8) {
+    double acc[8];
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    int nc = N - c0 < 8 ? N - c0 : 8;
+    for (int e = e0 + lane; e < e1; e += 64) {
+      double w = PTw[e];
+      const double* y = Y + (int64_t)PTidx[e] * N + c0;
+      for (int q = 0; q < nc; ++q) acc[q] += w * y[q];
+    }
+    for (int q = 0; q < nc; ++q) {
+      double v = acc[q];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0) out[k * N + c0 + q] = v;
+    }
+  }
 }
 
 // Gram block U^T Y (N x N): each block sums a 256-row chunk for every (i,j)
@@ -614,25 +466,34 @@ __device__ __forceinline__ void coarse_bary(const double* __restrict__ cg, const
   b[0] = 1.0 - b[1] - b[2] - b[3];
 }
 
-// Operators: [A_fix = 1/2 K + M_{fA}] [M_{fW}] [M] [K] -> 40 values per coarse tet.
+// Block-wide ordered sum of v over the 256 threads; result returned to all.
+__device__ __forceinline__ double block_sum(double v, double* ws) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+// Operators: [A_fix = 1/2 K + M_{fA}] [M_{fW}] [M] [K] -> 40 values per coarse
+// tet. One workgroup per coarse tet; threads stride over its fine tets.
 __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* __restrict__ grp_ptr,
                                                     const int32_t* __restrict__ grp_tet,
                                                     const int32_t* __restrict__ tets, const double* __restrict__ geo,
                                                     const double* __restrict__ xyz, const double* __restrict__ cgeo,
                                                     const double* __restrict__ fA, const double* __restrict__ fW,
                                                     double* __restrict__ out) {
-  int64_t C = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (C >= cnt) return;
+  __shared__ double ws[TPB / 64];
+  int64_t C = blockIdx.x;
   double acc[40];
   for (int k = 0; k < 40; ++k) acc[k] = 0.0;
   const double* cg = cgeo + 12 * C;
-  for (int e = grp_ptr[C]; e < grp_ptr[C + 1]; ++e) {
+  for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
     int64_t t = grp_tet[e];
     const double* G = geo + 16 * t;
     double vol = G[0];
     double Bc[4][4];
     for (int a = 0; a < 4; ++a) coarse_bary(cg, xyz, tets[4 * t + a], Bc[a]);
-    // coarse hat gradients restricted to this fine tet and values at qp
     double gc[4][3], pq[4][4];
     for (int j = 0; j < 4; ++j) {
       for (int x = 0; x < 3; ++x) {
@@ -665,64 +526,71 @@ __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* 
         acc[30 + k] += kv;
       }
   }
-  for (int k = 0; k < 40; ++k) out[40 * C + k] = acc[k];
+  for (int k = 0; k < 40; ++k) {
+    double v = block_sum(acc[k], ws);
+    if (threadIdx.x == 0) out[40 * C + k] = v;
+  }
 }
 
 // Per orbital: A_h4 entries int u psi_j psi_k (10) and rhs int u^2 psi_j (4).
+// One workgroup per coarse tet, orbitals in turn.
 __global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, const int32_t* __restrict__ grp_ptr,
                                                     const int32_t* __restrict__ grp_tet,
                                                     const int32_t* __restrict__ tets, const double* __restrict__ geo,
                                                     const double* __restrict__ xyz, const double* __restrict__ cgeo,
                                                     const int32_t* __restrict__ v2d, const double* __restrict__ U,
                                                     int N, double* __restrict__ out) {
-  int64_t id = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (id >= cnt * N) return;
-  int64_t C = id / N;
-  int i = (int)(id - C * N);
-  double acc[14];
-  for (int k = 0; k < 14; ++k) acc[k] = 0.0;
+  __shared__ double ws[TPB / 64];
+  int64_t C = blockIdx.x;
   const double* cg = cgeo + 12 * C;
-  for (int e = grp_ptr[C]; e < grp_ptr[C + 1]; ++e) {
-    int64_t t = grp_tet[e];
-    double vol = geo[16 * t];
-    double Bc[4][4], u[4];
-    for (int a = 0; a < 4; ++a) {
-      int v = tets[4 * t + a];
-      coarse_bary(cg, xyz, v, Bc[a]);
-      int d = v2d[v];
-      u[a] = d >= 0 ? U[(int64_t)d * N + i] : 0.0;
-    }
-    double us = u[0] + u[1] + u[2] + u[3];
-    for (int q = 0; q < 4; ++q) {
-      double uq = QB * us + (QA - QB) * u[q];
-      double ps[4];
-      for (int j = 0; j < 4; ++j) {
-        double s = Bc[0][j] + Bc[1][j] + Bc[2][j] + Bc[3][j];
-        ps[j] = QB * s + (QA - QB) * Bc[q][j];
+  for (int i = 0; i < N; ++i) {
+    double acc[14];
+    for (int k = 0; k < 14; ++k) acc[k] = 0.0;
+    for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
+      int64_t t = grp_tet[e];
+      double vol = geo[16 * t];
+      double Bc[4][4], u[4];
+      for (int a = 0; a < 4; ++a) {
+        int v = tets[4 * t + a];
+        coarse_bary(cg, xyz, v, Bc[a]);
+        int d = v2d[v];
+        u[a] = d >= 0 ? U[(int64_t)d * N + i] : 0.0;
       }
-      double w = 0.25 * vol;
-      int k = 0;
-      for (int j = 0; j < 4; ++j)
-        for (int m = j; m < 4; ++m, ++k) acc[k] += w * uq * ps[j] * ps[m];
-      for (int j = 0; j < 4; ++j) acc[10 + j] += w * uq * uq * ps[j];
+      double us = u[0] + u[1] + u[2] + u[3];
+      for (int q = 0; q < 4; ++q) {
+        double uq = QB * us + (QA - QB) * u[q];
+        double ps[4];
+        for (int j = 0; j < 4; ++j) {
+          double s = Bc[0][j] + Bc[1][j] + Bc[2][j] + Bc[3][j];
+          ps[j] = QB * s + (QA - QB) * Bc[q][j];
+        }
+        double w = 0.25 * vol;
+        int k = 0;
+        for (int j = 0; j < 4; ++j)
+          for (int m = j; m < 4; ++m, ++k) acc[k] += w * uq * ps[j] * ps[m];
+        for (int j = 0; j < 4; ++j) acc[10 + j] += w * uq * uq * ps[j];
+      }
+    }
+    for (int k = 0; k < 14; ++k) {
+      double v = block_sum(acc[k], ws);
+      if (threadIdx.x == 0) out[14 * (C * N + i) + k] = v;
     }
   }
-  for (int k = 0; k < 14; ++k) out[14 * id + k] = acc[k];
 }
 
 // Trilinear tensor T_jkm = int psi_j psi_k psi_m (fine quadrature), 20 entries
-// (j<=k<=m) per coarse tet.
+// (j<=k<=m) per coarse tet; one workgroup per coarse tet.
 __global__ void __launch_bounds__(TPB) k_coarse_tri(int64_t cnt, const int32_t* __restrict__ grp_ptr,
                                                     const int32_t* __restrict__ grp_tet,
                                                     const int32_t* __restrict__ tets, const double* __restrict__ geo,
                                                     const double* __restrict__ xyz, const double* __restrict__ cgeo,
                                                     double* __restrict__ out) {
-  int64_t C = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (C >= cnt) return;
+  __shared__ double ws[TPB / 64];
+  int64_t C = blockIdx.x;
   double acc[20];
   for (int k = 0; k < 20; ++k) acc[k] = 0.0;
   const double* cg = cgeo + 12 * C;
-  for (int e = grp_ptr[C]; e < grp_ptr[C + 1]; ++e) {
+  for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
     int64_t t = grp_tet[e];
     double vol = geo[16 * t];
     double Bc[4][4];
@@ -740,7 +608,10 @@ __global__ void __launch_bounds__(TPB) k_coarse_tri(int64_t cnt, const int32_t* 
           for (int l = m; l < 4; ++l, ++k) acc[k] += w * ps[j] * ps[m] * ps[l];
     }
   }
-  for (int k = 0; k < 20; ++k) out[20 * C + k] = acc[k];
+  for (int k = 0; k < 20; ++k) {
+    double v = block_sum(acc[k], ws);
+    if (threadIdx.x == 0) out[20 * C + k] = v;
+  }
 }
 
 // Phi[a,i] = sum_j Pw[a,j] phiH[Pk[a,j], i] + theta2[i] U[a,i]
@@ -883,32 +754,8 @@ void launch_load(hipStream_t s, int64_t n, const int32_t* adj_ptr, const int32_t
   hipLaunchKernelGGL(k_load, dim3(nb(n)), dim3(TPB), 0, s, n, adj_ptr, adj_tet, adj_loc, tets, geo, f_qp, scale,
                      gnod, v2d, b, lvec);
 }
-void launch_spmm(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const double* val,
-                 const double* X, double* Y, double* partial) {
-  int R = spmm_rows_per_block(N);
-  hipLaunchKernelGGL(k_spmm, dim3(elem_blocks(n, N)), dim3(TPB), 0, s, n, N, R, rowptr, col, val, X, Y, partial);
-}
 void launch_scale_cols_to(hipStream_t s, int64_t n, int N, const double* X, const double* sc, double* Y) {
   hipLaunchKernelGGL(k_scale_cols_to, dim3(nb(n * N)), dim3(TPB), 0, s, n * N, N, X, sc, Y);
-}
-void launch_cg_init(hipStream_t s, int64_t n, int N, const double* B, const double* AX, const double* dinv,
-                    double* Rv, double* P, double* partial) {
-  int R = spmm_rows_per_block(N);
-  hipLaunchKernelGGL(k_cg_init, dim3(elem_blocks(n, N)), dim3(TPB), 0, s, n, N, R, B, AX, dinv, Rv, P, partial);
-}
-void launch_cg_update(hipStream_t s, int64_t n, int N, const double* scal, const double* dinv, double* X, double* Rv,
-                      const double* P, const double* Q, double* partial) {
-  int R = spmm_rows_per_block(N);
-  hipLaunchKernelGGL(k_cg_update, dim3(elem_blocks(n, N)), dim3(TPB), 0, s, n, N, R, scal, dinv, X, Rv, P, Q,
-                     partial);
-}
-void launch_cg_direction(hipStream_t s, int64_t n, int N, const double* scal, const double* dinv, const double* Rv,
-                         double* P) {
-  hipLaunchKernelGGL(k_cg_direction, dim3(nb(n * N)), dim3(TPB), 0, s, n * N, N, scal, dinv, Rv, P);
-}
-void launch_cg_scalars(hipStream_t s, int N, int nblk, const double* partial, int phase, double rtol2, double* scal,
-                       int32_t* flags) {
-  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(TPB), 0, s, N, nblk, partial, phase, rtol2, scal, flags);
 }
 void launch_coldot(hipStream_t s, int64_t n, int N, const double* X, const double* Y, double* partial) {
   int R = spmm_rows_per_block(N);
@@ -922,7 +769,7 @@ void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, do
 }
 void launch_restrict(hipStream_t s, int64_t nH, int N, const int32_t* PTptr, const int32_t* PTidx, const double* PTw,
                      const double* Y, double* out) {
-  hipLaunchKernelGGL(k_restrict, dim3(nb(nH * N)), dim3(TPB), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
+  hipLaunchKernelGGL(k_restrict, dim3((unsigned)((nH + 3) / 4)), dim3(TPB), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
 }
 void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double* Y, double* partial) {
   hipLaunchKernelGGL(k_gram, dim3(gram_blocks(n)), dim3(TPB), 0, s, n, N, U, Y, partial);
@@ -930,18 +777,18 @@ void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double*
 void launch_coarse_ops(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
                        const int32_t* tets, const double* geo, const double* xyz, const double* cgeo,
                        const double* fA, const double* fW, double* out) {
-  hipLaunchKernelGGL(k_coarse_ops, dim3(nb(cnt)), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo, fA,
+  hipLaunchKernelGGL(k_coarse_ops, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo, fA,
                      fW, out);
 }
 void launch_coarse_orb(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
                        const int32_t* tets, const double* geo, const double* xyz, const double* cgeo,
                        const int32_t* v2d, const double* U, int N, double* out) {
-  hipLaunchKernelGGL(k_coarse_orb, dim3(nb(cnt * N)), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo,
+  hipLaunchKernelGGL(k_coarse_orb, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo,
                      v2d, U, N, out);
 }
 void launch_coarse_tri(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
                        const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* out) {
-  hipLaunchKernelGGL(k_coarse_tri, dim3(nb(cnt)), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo,
+  hipLaunchKernelGGL(k_coarse_tri, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo,
                      out);
 }
 void launch_reconstruct(hipStream_t s, int64_t n, int N, const int32_t* Pk, const double* Pw, const double* phiH,

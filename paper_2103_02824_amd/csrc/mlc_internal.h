@@ -86,10 +86,10 @@ struct Dev {
   double* RZ = nullptr;         // 4 x n_nuclei
   double* colv = nullptr;       // 2 x N per-column scratch
   double* red = nullptr;        // reduction partials
-  double* scal = nullptr;       // 7 x N CG scalars (orbitals)
-  double* scalP = nullptr;      // 7 CG scalars (Poisson)
-  int32_t* flags = nullptr;     // 4
-  int32_t* flagsP = nullptr;    // 4
+  double* scal = nullptr;       // 2 x 5N CG scalars (orbitals), two parity buffers
+  double* scalP = nullptr;      // 2 x 5 CG scalars (Hartree)
+  int32_t* flags = nullptr;     // [0] active (buffer 0) [2] active (buffer 1) [4] breakdown
+  int32_t* flagsP = nullptr;
 };
 
 struct Options {
@@ -155,6 +155,11 @@ struct mlc_ctx {
   // timing of the dominant kernel
   std::vector<hipEvent_t> ev_pool;
   int ev_used = 0;
+  // captured CG iteration chunks (one per solve kind: 0 orbitals, 1 Poisson)
+  hipGraphExec_t cg_graph[2] = {nullptr, nullptr};
+  int cg_graph_chunk[2] = {0, 0};
+  double cg_graph_rt2[2] = {0.0, 0.0};
+  hipStream_t cap_stream = nullptr;     // library-owned stream used only to record graphs
 };
 
 namespace mlc {
@@ -172,6 +177,23 @@ mlc_status probe(mlc_ctx* c, int which, double* out, int64_t count);
 
 // ---- kernel launchers (kernels.hip) -------------------------------------------
 int spmm_rows_per_block(int N);
+// cg.hip
+int cg_blocks(int64_t n, int N);
+int spmm_blocks(int64_t n, int N);
+int cg_max_blocks();
+void launch_spmm2(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const double* val,
+                  const double* X, double* Y, double* partial, const int32_t* flags);
+void launch_cg_init2(hipStream_t s, int64_t n, int N, const double* B, const double* AX, const double* dinv,
+                     double* Rv, double* P, double* partial);
+void launch_cg_start(hipStream_t s, int64_t n, int N, const double* partial, double rtol2, double* scal,
+                     int32_t* flags);
+void launch_cg_update_f(hipStream_t s, int64_t n, int N, const double* dinv, double* X, double* Rv, const double* P,
+                        const double* Q, const double* pq_part, const double* scal, const int32_t* flags,
+                        double* partial, int32_t* brk);
+void launch_cg_direction_f(hipStream_t s, int64_t n, int N, const double* dinv, const double* Rv, double* P,
+                           const double* upd_part, const double* scal_in, const int32_t* flags_in, double* scal_out,
+                           int32_t* flags_out, double rtol2);
+// kernels.hip
 int elem_blocks(int64_t n, int N);
 int qp_blocks(int64_t nt);
 int gram_blocks(int64_t n);
@@ -195,17 +217,7 @@ void launch_assemble(hipStream_t s, int64_t n, const int32_t* rowptr, const int3
 void launch_load(hipStream_t s, int64_t n, const int32_t* adj_ptr, const int32_t* adj_tet, const int8_t* adj_loc,
                  const int32_t* tets, const double* geo, const double* f_qp, double scale, const double* gnod,
                  const int32_t* v2d, double* b, double* lvec);
-void launch_spmm(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const double* val,
-                 const double* X, double* Y, double* partial);
 void launch_scale_cols_to(hipStream_t s, int64_t n, int N, const double* X, const double* sc, double* Y);
-void launch_cg_init(hipStream_t s, int64_t n, int N, const double* B, const double* AX, const double* dinv,
-                    double* Rv, double* P, double* partial);
-void launch_cg_update(hipStream_t s, int64_t n, int N, const double* scal, const double* dinv, double* X, double* Rv,
-                      const double* P, const double* Q, double* partial);
-void launch_cg_direction(hipStream_t s, int64_t n, int N, const double* scal, const double* dinv, const double* Rv,
-                         double* P);
-void launch_cg_scalars(hipStream_t s, int N, int nblk, const double* partial, int phase, double rtol2, double* scal,
-                       int32_t* flags);
 void launch_coldot(hipStream_t s, int64_t n, int N, const double* X, const double* Y, double* partial);
 void launch_reduce_cols(hipStream_t s, int N, int nblk, const double* partial, double* out);
 void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, double* X);

@@ -45,29 +45,70 @@ namespace {
 
 struct CgRes {
   int iters = 0;
+  int64_t iters_sum = 0;
   double relres = 0.0;
   bool converged = false;
   bool breakdown = false;
 };
 
+struct CgArgs {
+  const double* val;
+  const double* dinv;
+  const double* B;
+  double *X, *R, *P, *Q, *scal;
+  int32_t* flags;
+};
+
+// One CG iteration (three kernels) reading the scalars of parity p and
+// writing those of parity 1-p.
+void enqueue_iteration(mlc_ctx* c, hipStream_t s, int64_t n, int N, const CgArgs& a, double rt2, int p) {
+  auto& d = c->d;
+  double* red_pq = d.red;
+  double* red_upd = d.red + c->nred / 2;
+  double* sc_in = a.scal + (p ? 5 * N : 0);
+  double* sc_out = a.scal + (p ? 0 : 5 * N);
+  int32_t* fl_in = a.flags + (p ? 2 : 0);
+  int32_t* fl_out = a.flags + (p ? 0 : 2);
+  launch_spmm2(s, n, N, d.rowptr, d.col, a.val, a.P, a.Q, red_pq, fl_in);
+  launch_cg_update_f(s, n, N, a.dinv, a.X, a.R, a.P, a.Q, red_pq, sc_in, fl_in, red_upd, a.flags + 4);
+  launch_cg_direction_f(s, n, N, a.dinv, a.R, a.P, red_upd, sc_in, fl_in, sc_out, fl_out, rt2);
+}
+
 // Multi-column Jacobi-PCG, one independent recurrence per column; per-column
 // scalars stay on the device; the host checks the number of active columns
-// every check_every iterations. On exit the true residual is evaluated.
-mlc_status cg(mlc_ctx* c, int64_t n, int N, const double* val, const double* dinv, const double* B, double* X,
-              double* R, double* P, double* Q, double* scal, int32_t* flags, double rtol, int maxit, bool timed,
+// every chunk (an even number of iterations >= check_every). A chunk is
+// captured once into a HIP graph (kind 0: orbitals, 1: Hartree) and replayed;
+// with timed = true the chunk is launched eagerly and every SpMM launch is
+// bracketed by HIP events. On exit the true residual is evaluated.
+mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs& a, double rtol, int maxit, bool timed,
               double* spmm_ms, int64_t* n_spmm, CgRes* out) {
   hipStream_t s = c->stream;
   auto& d = c->d;
-  int nblk = elem_blocks(n, N);
-  HIPCHK(hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), s));
-  launch_spmm(s, n, N, d.rowptr, d.col, val, X, Q, nullptr);
-  launch_cg_init(s, n, N, B, Q, dinv, R, P, d.red);
-  launch_cg_scalars(s, N, nblk, d.red, 0, rtol * rtol, scal, flags);
+  const double rt2 = rtol * rtol;
+  double* red_upd = d.red + c->nred / 2;
+  HIPCHK(hipMemsetAsync(a.flags, 0, 8 * sizeof(int32_t), s));
+  launch_spmm2(s, n, N, d.rowptr, d.col, a.val, a.X, a.Q, nullptr, nullptr);
+  launch_cg_init2(s, n, N, a.B, a.Q, a.dinv, a.R, a.P, red_upd);
+  launch_cg_start(s, n, N, red_upd, rt2, a.scal, a.flags);
   int it = 0;
-  int32_t hf[4];
-  int every = std::max(1, c->opt.check_every);
+  int32_t hf[8];
+  const int every = 2 * ((std::max(1, c->opt.check_every) + 1) / 2);
+  const bool graph = c->opt.use_graphs && !timed && c->cap_stream;
+  if (graph && (!c->cg_graph[kind] || c->cg_graph_chunk[kind] != every || c->cg_graph_rt2[kind] != rt2)) {
+    if (c->cg_graph[kind]) HIPCHK(hipGraphExecDestroy(c->cg_graph[kind]));
+    c->cg_graph[kind] = nullptr;
+    hipGraph_t g;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < every; ++k) enqueue_iteration(c, c->cap_stream, n, N, a, rt2, k & 1);
+    HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
+    hipError_t e = hipGraphInstantiate(&c->cg_graph[kind], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+    c->cg_graph_chunk[kind] = every;
+    c->cg_graph_rt2[kind] = rt2;
+  }
   for (;;) {
-    HIPCHK(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hf, a.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (timed && c->ev_used > 0) {
       for (int k = 0; k + 1 < c->ev_used; k += 2) {
@@ -77,7 +118,7 @@ mlc_status cg(mlc_ctx* c, int64_t n, int N, const double* val, const double* din
       }
       c->ev_used = 0;
     }
-    if (hf[1]) {
+    if (hf[4]) {
       out->breakdown = true;
       break;
     }
@@ -86,35 +127,50 @@ mlc_status cg(mlc_ctx* c, int64_t n, int N, const double* val, const double* din
       break;
     }
     if (it >= maxit) break;
-    int chunk = std::min(every, maxit - it);
-    for (int k = 0; k < chunk; ++k) {
-      bool rec = timed && c->ev_used + 2 <= (int)c->ev_pool.size();
-      if (rec) HIPCHK(hipEventRecord(c->ev_pool[c->ev_used], s));
-      launch_spmm(s, n, N, d.rowptr, d.col, val, P, Q, d.red);
-      if (rec) {
-        HIPCHK(hipEventRecord(c->ev_pool[c->ev_used + 1], s));
-        c->ev_used += 2;
+    if (graph) {
+      HIPCHK(hipGraphLaunch(c->cg_graph[kind], s));
+    } else {
+      for (int k = 0; k < every; ++k) {
+        bool rec = timed && c->ev_used + 2 <= (int)c->ev_pool.size();
+        if (rec) HIPCHK(hipEventRecord(c->ev_pool[c->ev_used], s));
+        int p = k & 1;
+        double* red_pq = d.red;
+        launch_spmm2(s, n, N, d.rowptr, d.col, a.val, a.P, a.Q, red_pq, a.flags + (p ? 2 : 0));
+        if (rec) {
+          HIPCHK(hipEventRecord(c->ev_pool[c->ev_used + 1], s));
+          c->ev_used += 2;
+          ++*n_spmm;
+        }
+        launch_cg_update_f(s, n, N, a.dinv, a.X, a.R, a.P, a.Q, red_pq, a.scal + (p ? 5 * N : 0),
+                           a.flags + (p ? 2 : 0), red_upd, a.flags + 4);
+        launch_cg_direction_f(s, n, N, a.dinv, a.R, a.P, red_upd, a.scal + (p ? 5 * N : 0), a.flags + (p ? 2 : 0),
+                              a.scal + (p ? 0 : 5 * N), a.flags + (p ? 0 : 2), rt2);
       }
-      ++*n_spmm;
-      launch_cg_scalars(s, N, nblk, d.red, 1, rtol * rtol, scal, flags);
-      launch_cg_update(s, n, N, scal, dinv, X, R, P, Q, d.red);
-      launch_cg_scalars(s, N, nblk, d.red, 2, rtol * rtol, scal, flags);
-      launch_cg_direction(s, n, N, scal, dinv, R, P);
-      ++it;
     }
+    it += every;
   }
-  out->iters = it;
-  // true residual ||B - A X|| / ||B|| per column (R, P, scal reused)
-  launch_spmm(s, n, N, d.rowptr, d.col, val, X, Q, nullptr);
-  launch_cg_init(s, n, N, B, Q, dinv, R, P, d.red);
-  launch_cg_scalars(s, N, nblk, d.red, 0, 0.0, scal, flags);
-  std::vector<double> hs(8 * N);
-  HIPCHK(hipMemcpyAsync(hs.data(), scal, sizeof(double) * 5 * N, hipMemcpyDeviceToHost, s));
+  // per-column iteration counts, then the true residual ||B - A X|| / ||B||
+  std::vector<double> hs(5 * N);
+  HIPCHK(hipMemcpyAsync(hs.data(), a.scal, sizeof(double) * 5 * N, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int itmax = 0;
+  int64_t itsum = 0;
+  for (int j = 0; j < N; ++j) {
+    int ij = (int)hs[4 * N + j];
+    itmax = std::max(itmax, ij);
+    itsum += ij;
+  }
+  out->iters = itmax;
+  out->iters_sum = itsum;
+  launch_spmm2(s, n, N, d.rowptr, d.col, a.val, a.X, a.Q, nullptr, nullptr);
+  launch_cg_init2(s, n, N, a.B, a.Q, a.dinv, a.R, a.P, red_upd);
+  launch_cg_start(s, n, N, red_upd, 0.0, a.scal, a.flags);
+  HIPCHK(hipMemcpyAsync(hs.data(), a.scal, sizeof(double) * 5 * N, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   double mx = 0.0;
   for (int j = 0; j < N; ++j) {
-    double bb = hs[4 * N + j];
-    double rr = hs[3 * N + j];
+    double bb = hs[2 * N + j];
+    double rr = hs[1 * N + j];
     mx = std::max(mx, bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr));
   }
   out->relres = mx;
@@ -167,21 +223,22 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   std::vector<double> colv(2 * N);
   for (int i = 0; i < N; ++i) colv[i] = c->lam[i] + sigma;
   HIPCHK(hipMemcpyAsync(d.colv, colv.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
-  launch_spmm(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr);
+  launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr, nullptr);
   launch_scale_cols_to(s, n, N, d.Q, d.colv, d.B);
   HIPCHK(hipMemcpyAsync(d.X, d.Phi, sizeof(double) * n * N, hipMemcpyDeviceToDevice, s));
   CgRes cr;
-  mlc_status st = cg(c, n, N, d.valA, d.dinvA, d.B, d.X, d.R, d.P, d.Q, d.scal, d.flags, c->opt.cg_rtol,
-                     c->opt.cg_maxit, timed, &r.t_spmm_ms, &r.n_spmm, &cr);
+  CgArgs ca{d.valA, d.dinvA, d.B, d.X, d.R, d.P, d.Q, d.scal, d.flags};
+  mlc_status st = cg(c, 0, n, N, ca, c->opt.cg_rtol, c->opt.cg_maxit, timed, &r.t_spmm_ms, &r.n_spmm, &cr);
   if (st != MLC_OK) return st;
   r.cg_iters_max = cr.iters;
-  r.cg_iters_sum = cr.iters * N;
+  r.cg_iters_sum = (int32_t)cr.iters_sum;
   r.cg_relres_max = cr.relres;
   r.spmm_rows = n;
   r.spmm_cols_sum = N;
   if (cr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the auxiliary problems");
   // M-normalise u_i
-  launch_spmm(s, n, N, d.rowptr, d.col, d.valM, d.X, d.Q, d.red);
+  launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.X, d.Q, nullptr, nullptr);
+  launch_coldot(s, n, N, d.X, d.Q, d.red);
   launch_reduce_cols(s, N, elem_blocks(n, N), d.red, d.colv + N);
   launch_normalize_cols(s, n, N, d.colv + N, d.X);
 
@@ -191,11 +248,11 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
     launch_qp_density(s, nt, d.tets, d.v2d, d.X, N, d.occ, d.rhot);
     launch_load(s, n, d.adj_ptr, d.adj_tet, d.adj_loc, d.tets, d.geo, d.rhot, 4.0 * 3.14159265358979323846, d.g,
                 d.v2d, d.pb, d.lvec);
-    HIPCHK(hipMemsetAsync(d.w0, 0, sizeof(double) * n, s));
+    // warm start from the previous step's w0 (zero at bind)
     double dummy = 0.0;
     int64_t dn = 0;
-    st = cg(c, n, 1, d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP, c->opt.poisson_rtol,
-            c->opt.cg_maxit, false, &dummy, &dn, &pr);
+    CgArgs pa{d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP};
+    st = cg(c, 1, n, 1, pa, c->opt.poisson_rtol, c->opt.cg_maxit, false, &dummy, &dn, &pr);
     if (st != MLC_OK) return st;
     if (pr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the Hartree problem");
     launch_field(s, nt, d.tets, nullptr, d.v2d, d.w0, nullptr, nullptr, d.fld2);
@@ -214,14 +271,14 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   const double* vals[4] = {d.valF, d.valW, d.valM, d.valK};
   for (int o = 0; o < 4; ++o) {
     double* Yo = d.Y + (int64_t)o * n * N;
-    launch_spmm(s, n, N, d.rowptr, d.col, vals[o], d.X, Yo, nullptr);
+    launch_spmm2(s, n, N, d.rowptr, d.col, vals[o], d.X, Yo, nullptr, nullptr);
     launch_restrict(s, nH, N, d.PTptr, d.PTidx, d.PTw, Yo, d.small + L.ptF + (int64_t)o * nH * N);
     launch_gram(s, n, N, d.X, Yo, d.red);
     launch_reduce_cols(s, N * N, gram_blocks(n), d.red, d.small + L.utF + (int64_t)o * N * N);
   }
   HIPCHK(hipMemsetAsync(d.small + L.d, 0, sizeof(double) * (2 * nH + 8), s));
   if (c->hartree) {
-    launch_spmm(s, n, 1, d.rowptr, d.col, d.valK, d.w0, d.pq, nullptr);
+    launch_spmm2(s, n, 1, d.rowptr, d.col, d.valK, d.w0, d.pq, nullptr, nullptr);
     launch_restrict(s, nH, 1, d.PTptr, d.PTidx, d.PTw, d.pq, d.small + L.d);
     launch_restrict(s, nH, 1, d.PTptr, d.PTidx, d.PTw, d.lvec, d.small + L.liftH);
     launch_coldot(s, n, 1, d.w0, d.pq, d.red);
@@ -279,7 +336,7 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   launch_rho_nodal(s, nv, d.v2d, d.Phi, N, d.occ, d.rho_nodal);
   launch_energy(s, nt, d.tets, d.v2d, d.Phi, N, d.occ, d.w, d.vxc, d.geo, c->xc, c->xalpha, d.red);
   launch_reduce_rows(s, d.red, nqb, 2, 0, d.small + L.sc + 2);
-  launch_spmm(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr);
+  launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr, nullptr);
   launch_gram(s, n, N, d.Phi, d.Q, d.red);
   launch_reduce_cols(s, N * N, gram_blocks(n), d.red, d.small + L.ovl);
   HIPCHK(hipEventRecord(ev[3], s));

@@ -54,7 +54,7 @@ class Options(C.Structure):
     _fields_ = [("cg_rtol", C.c_double), ("cg_maxit", C.c_int32), ("check_every", C.c_int32),
                 ("shift", C.c_int32), ("sigma0", C.c_double), ("poisson_rtol", C.c_double),
                 ("inner_maxit", C.c_int32), ("inner_tol", C.c_double), ("n_extra", C.c_int32),
-                ("reorder", C.c_int32), ("time_kernels", C.c_int32)]
+                ("reorder", C.c_int32), ("time_kernels", C.c_int32), ("use_graphs", C.c_int32)]
 
 
 class StepReport(C.Structure):
