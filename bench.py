@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=100)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this size twice (hardware counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU sharding by orbitals "
@@ -129,6 +131,14 @@ def main():
             f"{rep['t_spmm_ms']:.2f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - tw0
+    if args.calib_copy_mib:
+        nb = args.calib_copy_mib * 2 ** 20
+        a = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nb} bytes read and written, 2 times")
     t_gpu = sum(r["t_fine_ms"] + r["t_recon_ms"] for r in reps) / 1e3
     value = n * N * len(reps) / t_gpu
     ms_per_step = 1e3 * t_gpu / len(reps)

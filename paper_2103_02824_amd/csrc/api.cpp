@@ -66,6 +66,10 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->valW = w.take<double>(nnz);
   d->valM = w.take<double>(nnz);
   d->valK = w.take<double>(nnz);
+  d->elem = w.take<double>(20 * nt);
+  d->slot_ptr = w.take<int32_t>(nnz + 1);
+  d->slot_src = w.take<int32_t>((int64_t)c->slot_src.size());
+  d->diag_slot = w.take<int32_t>(n);
   d->dinvA = w.take<double>(n);
   d->dinvK = w.take<double>(n);
   d->Phi = w.take<double>(n * N);
@@ -153,6 +157,9 @@ mlc_status upload_and_init(mlc_ctx* c) {
   HIPCHK(up(s, d.adj_pos, c->adj_pos));
   HIPCHK(up(s, d.adj_loc, c->adj_loc));
   HIPCHK(up(s, d.bverts, c->bverts));
+  HIPCHK(up(s, d.slot_ptr, c->slot_ptr));
+  HIPCHK(up(s, d.slot_src, c->slot_src));
+  HIPCHK(up(s, d.diag_slot, c->diag_slot));
   HIPCHK(up(s, d.Pk, c->Pk));
   HIPCHK(up(s, d.Pw, c->Pw));
   HIPCHK(up(s, d.PTptr, c->PTptr));
@@ -169,10 +176,11 @@ mlc_status upload_and_init(mlc_ctx* c) {
   HIPCHK(hipMemsetAsync(d.w0, 0, sizeof(double) * c->n, s));
   // fixed quantities: V_ext at the quadrature points, K, M, coarse trilinear tensor
   launch_vext(s, c->nt, d.qpx, d.RZ, c->n_nuclei, c->potential, c->rc, c->omega, d.vext);
-  launch_assemble(s, c->n, d.rowptr, d.adj_ptr, d.adj_tet, d.adj_loc, d.adj_pos, d.geo, 1.0, nullptr, 0.0, d.valK,
-                  d.dinvK, 0.0, nullptr, nullptr);
-  launch_assemble(s, c->n, d.rowptr, d.adj_ptr, d.adj_tet, d.adj_loc, d.adj_pos, d.geo, 0.0, nullptr, 1.0, d.valM,
-                  nullptr, 0.0, nullptr, nullptr);
+  const int64_t nnz = (int64_t)c->col.size();
+  launch_assemble2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 1.0, nullptr, 0.0, d.valK,
+                   d.dinvK, 0.0, nullptr, d.valM);
+  launch_assemble2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 0.0, nullptr, 1.0, d.valM,
+                   nullptr, 0.0, nullptr, nullptr);
   launch_coarse_tri(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.cel_tri);
   c->h_tri.resize(20 * c->cnt);
   HIPCHK(hipMemcpyAsync(c->h_tri.data(), d.cel_tri, sizeof(double) * c->h_tri.size(), hipMemcpyDeviceToHost, s));

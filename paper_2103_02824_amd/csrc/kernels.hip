@@ -276,57 +276,77 @@ __global__ void __launch_bounds__(TPB) k_field(int64_t nt, const int32_t* __rest
   }
 }
 
-// Row-wise assembly on the interior CSR pattern, one thread per row:
-//   val1 = cK1 K + M_{f1} + cM1 M      (f1 may be null)
-//   val2 = cK2 K + M_{f2}              (optional)
-// and dinv1 = 1/diag(val1) (optional). Each thread owns its row, so the
-// element contributions are summed in a fixed (adjacency) order.
-__global__ void __launch_bounds__(TPB) k_assemble(int64_t n, const int32_t* __restrict__ rowptr,
-                                                  const int32_t* __restrict__ adj_ptr,
-                                                  const int32_t* __restrict__ adj_tet,
-                                                  const int8_t* __restrict__ adj_loc,
-                                                  const int32_t* __restrict__ adj_pos, const double* __restrict__ geo,
-                                                  double cK1, const double* __restrict__ f1, double cM1,
-                                                  double* __restrict__ val1, double* __restrict__ dinv1, double cK2,
-                                                  const double* __restrict__ f2, double* __restrict__ val2) {
+// Element entries (10 symmetric local pairs, order (0,0)(0,1)..(3,3)) of
+//   op1 = cK1 K + M_{f1} + cM1 M  and  op2 = cK2 K + M_{f2}
+// for one tet per thread; the mass parts use the 4-point rule.
+__global__ void __launch_bounds__(TPB) k_elem(int64_t nt, const double* __restrict__ geo, double cK1,
+                                              const double* __restrict__ f1, double cM1, double cK2,
+                                              const double* __restrict__ f2, double* __restrict__ elem) {
+  int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= nt) return;
+  const double* G = geo + 16 * t;
+  double vol = G[0];
+  double g[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int x = 0; x < 3; ++x) g[a][x] = G[1 + 3 * a + x];
+  double w1[4], w2[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    w1[q] = 0.25 * vol * (f1 ? f1[4 * t + q] : 0.0);
+    w2[q] = 0.25 * vol * (f2 ? f2[4 * t + q] : 0.0);
+  }
+  double e1[10], e2[10];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a; b < 4; ++b) {
+      const int p = a * 4 - (a * (a - 1)) / 2 + (b - a);
+      double kv = vol * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2]);
+      double m1 = 0.0, m2 = 0.0, mm = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double ll = Lq(q, a) * Lq(q, b);
+        m1 += w1[q] * ll;
+        m2 += w2[q] * ll;
+        mm += 0.25 * vol * ll;
+      }
+      e1[p] = cK1 * kv + m1 + cM1 * mm;
+      e2[p] = cK2 * kv + m2;
+    }
+  double* o = elem + 20 * t;
+#pragma unroll
+  for (int p = 0; p < 10; ++p) {
+    o[p] = e1[p];
+    o[10 + p] = e2[p];
+  }
+}
+
+// One thread per CSR slot: the slot's element entries summed in tet order.
+__global__ void __launch_bounds__(TPB) k_slot_gather(int64_t nnz, const int32_t* __restrict__ slot_ptr,
+                                                     const int32_t* __restrict__ slot_src,
+                                                     const double* __restrict__ elem, double* __restrict__ val1,
+                                                     double* __restrict__ val2) {
+  int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (j >= nnz) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int e = slot_ptr[j]; e < slot_ptr[j + 1]; ++e) {
+    int src = slot_src[e];
+    int64_t t = src / 10;
+    int p = src - (int)t * 10;
+    s1 += elem[20 * t + p];
+    if (val2) s2 += elem[20 * t + 10 + p];
+  }
+  val1[j] = s1;
+  if (val2) val2[j] = s2;
+}
+
+__global__ void __launch_bounds__(TPB) k_diag_inv(int64_t n, const int32_t* __restrict__ diag_slot,
+                                                  const double* __restrict__ val, double* __restrict__ dinv) {
   int64_t a = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (a >= n) return;
-  int r0 = rowptr[a], r1 = rowptr[a + 1];
-  for (int j = r0; j < r1; ++j) {
-    val1[j] = 0.0;
-    if (val2) val2[j] = 0.0;
-  }
-  int diag_slot = -1;
-  for (int e = adj_ptr[a]; e < adj_ptr[a + 1]; ++e) {
-    int64_t t = adj_tet[e];
-    int la = adj_loc[e];
-    const double* G = geo + 16 * t;
-    double vol = G[0];
-    double ga[3] = {G[1 + 3 * la], G[2 + 3 * la], G[3 + 3 * la]};
-    double fa[4], fb[4];
-    for (int q = 0; q < 4; ++q) {
-      double w = 0.25 * vol * Lq(q, la);
-      fa[q] = f1 ? w * f1[4 * t + q] : 0.0;
-      fb[q] = f2 ? w * f2[4 * t + q] : 0.0;
-    }
-    double m1base = 0.25 * vol;
-    for (int lb = 0; lb < 4; ++lb) {
-      int pos = adj_pos[4 * (int64_t)e + lb];
-      if (pos < 0) continue;
-      if (lb == la) diag_slot = pos;
-      double kv = vol * (ga[0] * G[1 + 3 * lb] + ga[1] * G[2 + 3 * lb] + ga[2] * G[3 + 3 * lb]);
-      double mf = 0.0, mg = 0.0, mm = 0.0;
-      for (int q = 0; q < 4; ++q) {
-        double lb_q = Lq(q, lb);
-        mf += fa[q] * lb_q;
-        mg += fb[q] * lb_q;
-        mm += m1base * Lq(q, la) * lb_q;
-      }
-      val1[r0 + pos] += cK1 * kv + mf + cM1 * mm;
-      if (val2) val2[r0 + pos] += cK2 * kv + mg;
-    }
-  }
-  if (dinv1 && diag_slot >= 0) dinv1[a] = 1.0 / val1[r0 + diag_slot];
+  dinv[a] = 1.0 / val[diag_slot[a]];
 }
 
 // Load vector, one thread per interior row:
@@ -486,6 +506,7 @@ __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* 
   __shared__ double ws[TPB / 64];
   int64_t C = blockIdx.x;
   double acc[40];
+#pragma unroll
   for (int k = 0; k < 40; ++k) acc[k] = 0.0;
   const double* cg = cgeo + 12 * C;
   for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
@@ -509,9 +530,11 @@ __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* 
       wA[q] = 0.25 * vol * (fA ? fA[4 * t + q] : 0.0);
       wW[q] = 0.25 * vol * (fW ? fW[4 * t + q] : 0.0);
     }
-    int k = 0;
+#pragma unroll
     for (int j = 0; j < 4; ++j)
-      for (int m = j; m < 4; ++m, ++k) {
+#pragma unroll
+      for (int m = j; m < 4; ++m) {
+        const int k = j * 4 - (j * (j - 1)) / 2 + (m - j);
         double kv = vol * (gc[j][0] * gc[m][0] + gc[j][1] * gc[m][1] + gc[j][2] * gc[m][2]);
         double mA = 0.0, mW = 0.0, mM = 0.0;
         for (int q = 0; q < 4; ++q) {
@@ -526,6 +549,7 @@ __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* 
         acc[30 + k] += kv;
       }
   }
+#pragma unroll
   for (int k = 0; k < 40; ++k) {
     double v = block_sum(acc[k], ws);
     if (threadIdx.x == 0) out[40 * C + k] = v;
@@ -545,6 +569,7 @@ __global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, const int32_t* 
   const double* cg = cgeo + 12 * C;
   for (int i = 0; i < N; ++i) {
     double acc[14];
+#pragma unroll
     for (int k = 0; k < 14; ++k) acc[k] = 0.0;
     for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
       int64_t t = grp_tet[e];
@@ -565,12 +590,15 @@ __global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, const int32_t* 
           ps[j] = QB * s + (QA - QB) * Bc[q][j];
         }
         double w = 0.25 * vol;
-        int k = 0;
+#pragma unroll
         for (int j = 0; j < 4; ++j)
-          for (int m = j; m < 4; ++m, ++k) acc[k] += w * uq * ps[j] * ps[m];
+#pragma unroll
+          for (int m = j; m < 4; ++m) acc[j * 4 - (j * (j - 1)) / 2 + (m - j)] += w * uq * ps[j] * ps[m];
+#pragma unroll
         for (int j = 0; j < 4; ++j) acc[10 + j] += w * uq * uq * ps[j];
       }
     }
+#pragma unroll
     for (int k = 0; k < 14; ++k) {
       double v = block_sum(acc[k], ws);
       if (threadIdx.x == 0) out[14 * (C * N + i) + k] = v;
@@ -588,6 +616,7 @@ __global__ void __launch_bounds__(TPB) k_coarse_tri(int64_t cnt, const int32_t* 
   __shared__ double ws[TPB / 64];
   int64_t C = blockIdx.x;
   double acc[20];
+#pragma unroll
   for (int k = 0; k < 20; ++k) acc[k] = 0.0;
   const double* cg = cgeo + 12 * C;
   for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
@@ -603,11 +632,15 @@ __global__ void __launch_bounds__(TPB) k_coarse_tri(int64_t cnt, const int32_t* 
       }
       double w = 0.25 * vol;
       int k = 0;
+#pragma unroll
       for (int j = 0; j < 4; ++j)
+#pragma unroll
         for (int m = j; m < 4; ++m)
+#pragma unroll
           for (int l = m; l < 4; ++l, ++k) acc[k] += w * ps[j] * ps[m] * ps[l];
     }
   }
+#pragma unroll
   for (int k = 0; k < 20; ++k) {
     double v = block_sum(acc[k], ws);
     if (threadIdx.x == 0) out[20 * C + k] = v;
@@ -742,11 +775,12 @@ void launch_field(hipStream_t s, int64_t nt, const int32_t* tets, const double* 
                   const double* dofv, const double* add1, const double* add2, double* out) {
   hipLaunchKernelGGL(k_field, dim3(nb(nt)), dim3(TPB), 0, s, nt, tets, nod, v2d, dofv, add1, add2, out);
 }
-void launch_assemble(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* adj_ptr, const int32_t* adj_tet,
-                     const int8_t* adj_loc, const int32_t* adj_pos, const double* geo, double cK1, const double* f1,
-                     double cM1, double* val1, double* dinv1, double cK2, const double* f2, double* val2) {
-  hipLaunchKernelGGL(k_assemble, dim3(nb(n)), dim3(TPB), 0, s, n, rowptr, adj_ptr, adj_tet, adj_loc, adj_pos, geo,
-                     cK1, f1, cM1, val1, dinv1, cK2, f2, val2);
+void launch_assemble2(hipStream_t s, int64_t nt, int64_t n, int64_t nnz, const double* geo, const int32_t* slot_ptr,
+                      const int32_t* slot_src, const int32_t* diag_slot, double* elem, double cK1, const double* f1,
+                      double cM1, double* val1, double* dinv1, double cK2, const double* f2, double* val2) {
+  hipLaunchKernelGGL(k_elem, dim3(nb(nt)), dim3(TPB), 0, s, nt, geo, cK1, f1, cM1, cK2, f2, elem);
+  hipLaunchKernelGGL(k_slot_gather, dim3(nb(nnz)), dim3(TPB), 0, s, nnz, slot_ptr, slot_src, elem, val1, val2);
+  if (dinv1) hipLaunchKernelGGL(k_diag_inv, dim3(nb(n)), dim3(TPB), 0, s, n, diag_slot, val1, dinv1);
 }
 void launch_load(hipStream_t s, int64_t n, const int32_t* adj_ptr, const int32_t* adj_tet, const int8_t* adj_loc,
                  const int32_t* tets, const double* geo, const double* f_qp, double scale, const double* gnod,

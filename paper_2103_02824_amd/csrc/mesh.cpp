@@ -275,6 +275,40 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
     c->adj_ptr[d + 1] = (int32_t)c->adj_tet.size();
   }
   if ((int64_t)c->col.size() >= (1LL << 31)) return fail(c, MLC_ERR_MESH, "too many nonzeros");
+  if (c->nt * 10 >= (1LL << 31)) return fail(c, MLC_ERR_MESH, "too many tets for the slot list");
+  // For every CSR slot (a, b): the element entries (tet t, symmetric local pair
+  // p) that add into it, in increasing tet order. Assembly then sums them with
+  // one thread per slot in this fixed order.
+  {
+    static const int sym[4][4] = {{0, 1, 2, 3}, {1, 4, 5, 6}, {2, 5, 7, 8}, {3, 6, 8, 9}};
+    const int64_t nnz = (int64_t)c->col.size();
+    std::vector<int32_t> cnt(nnz + 1, 0);
+    c->diag_slot.assign(c->n, -1);
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1) {
+        c->slot_ptr.assign(nnz + 1, 0);
+        for (int64_t j = 0; j < nnz; ++j) c->slot_ptr[j + 1] = c->slot_ptr[j] + cnt[j];
+        c->slot_src.assign(c->slot_ptr.back(), 0);
+        std::fill(cnt.begin(), cnt.end(), 0);
+      }
+      for (int64_t t = 0; t < c->nt; ++t) {
+        int32_t dd[4];
+        for (int a = 0; a < 4; ++a) dd[a] = c->v2d[c->tets[4 * t + a]];
+        for (int a = 0; a < 4; ++a) {
+          if (dd[a] < 0) continue;
+          const int32_t* rb = &c->col[c->rowptr[dd[a]]];
+          const int32_t* re = &c->col[c->rowptr[dd[a] + 1]];
+          for (int b = 0; b < 4; ++b) {
+            if (dd[b] < 0) continue;
+            int64_t slot = c->rowptr[dd[a]] + (std::lower_bound(rb, re, dd[b]) - rb);
+            if (pass == 1) c->slot_src[c->slot_ptr[slot] + cnt[slot]] = (int32_t)(t * 10 + sym[a][b]);
+            cnt[slot]++;
+            if (a == b) c->diag_slot[dd[a]] = (int32_t)slot;
+          }
+        }
+      }
+    }
+  }
 
   // ---- coarse mesh --------------------------------------------------------------
   std::vector<char> con = boundary_flags(c->cxyz, c->lo, c->hi);

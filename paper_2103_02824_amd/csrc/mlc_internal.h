@@ -46,6 +46,10 @@ struct Dev {
   double* valW = nullptr;       // M_{w0}
   double* valM = nullptr;       // M
   double* valK = nullptr;       // K
+  double* elem = nullptr;       // nt x 20: element entries of two operators
+  int32_t* slot_ptr = nullptr;  // nnz + 1
+  int32_t* slot_src = nullptr;  // t * 10 + local pair
+  int32_t* diag_slot = nullptr; // n
   double* dinvA = nullptr;      // n
   double* dinvK = nullptr;      // n
   // orbital blocks, n x N row-major
@@ -118,6 +122,7 @@ struct mlc_ctx {
   std::vector<int32_t> adj_ptr, adj_tet, adj_pos;
   std::vector<int8_t> adj_loc;
   std::vector<double> geo;              // nt x 16
+  std::vector<int32_t> slot_ptr, slot_src, diag_slot;  // assembly gather lists
   // ---- coarse ---------------------------------------------------------------
   int64_t nH = 0;
   std::vector<int32_t> cv2d, cd2v;
@@ -211,9 +216,10 @@ void launch_boundary_g(hipStream_t s, int64_t nbv, const int32_t* bverts, const 
                        double* g);
 void launch_field(hipStream_t s, int64_t nt, const int32_t* tets, const double* nod, const int32_t* v2d,
                   const double* dofv, const double* add1, const double* add2, double* out);
-void launch_assemble(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* adj_ptr, const int32_t* adj_tet,
-                     const int8_t* adj_loc, const int32_t* adj_pos, const double* geo, double cK1, const double* f1,
-                     double cM1, double* val1, double* dinv1, double cK2, const double* f2, double* val2);
+// val1 = cK1 K + M_{f1} + cM1 M, val2 = cK2 K + M_{f2} (optional), dinv1 = 1/diag(val1) (optional)
+void launch_assemble2(hipStream_t s, int64_t nt, int64_t n, int64_t nnz, const double* geo, const int32_t* slot_ptr,
+                      const int32_t* slot_src, const int32_t* diag_slot, double* elem, double cK1, const double* f1,
+                      double cM1, double* val1, double* dinv1, double cK2, const double* f2, double* val2);
 void launch_load(hipStream_t s, int64_t n, const int32_t* adj_ptr, const int32_t* adj_tet, const int8_t* adj_loc,
                  const int32_t* tets, const double* geo, const double* f_qp, double scale, const double* gnod,
                  const int32_t* v2d, double* b, double* lvec);

@@ -216,8 +216,9 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   // V_ext + V_xc + g at the quadrature points (A_fix of the inner problems)
   launch_field(s, nt, d.tets, d.g, d.v2d, nullptr, d.vext, d.vxc, d.fld);
   // ---- operators: A + sigma M (step 5) and A_fix -------------------------------
-  launch_assemble(s, n, d.rowptr, d.adj_ptr, d.adj_tet, d.adj_loc, d.adj_pos, d.geo, 0.5, d.veff, sigma, d.valA,
-                  d.dinvA, 0.5, d.fld, d.valF);
+  const int64_t nnz = (int64_t)c->col.size();
+  launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 0.5, d.veff, sigma, d.valA,
+                   d.dinvA, 0.5, d.fld, d.valF);
 
   // ---- step 5: (A + sigma M) u_i = (lambda_i + sigma) M phi_i ------------------------
   std::vector<double> colv(2 * N);
@@ -256,8 +257,8 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
     if (st != MLC_OK) return st;
     if (pr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the Hartree problem");
     launch_field(s, nt, d.tets, nullptr, d.v2d, d.w0, nullptr, nullptr, d.fld2);
-    launch_assemble(s, n, d.rowptr, d.adj_ptr, d.adj_tet, d.adj_loc, d.adj_pos, d.geo, 0.0, d.fld2, 0.0, d.valW,
-                    nullptr, 0.0, nullptr, nullptr);
+    launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 0.0, d.fld2, 0.0, d.valW,
+                     nullptr, 0.0, nullptr, nullptr);
   } else {
     HIPCHK(hipMemsetAsync(d.w0, 0, sizeof(double) * n, s));
     HIPCHK(hipMemsetAsync(d.lvec, 0, sizeof(double) * n, s));
