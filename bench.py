@@ -50,11 +50,11 @@ def make_system(workload, seed):
     raise SystemExit(f"unknown workload {workload}")
 
 
-def spmm_bytes(n, nnz, N):
-    """Algorithmic bytes of one SpMM launch Y = A X: values (8 B) and column
-    indices (4 B) per nonzero, row pointers (4 B per row), X read once and Y
-    written once (8 B per DoF and orbital each)."""
-    return 12 * nnz + 4 * (n + 1) + 16 * n * N
+def spmm_bytes(n, nnz, N, word=8):
+    """Algorithmic bytes of one SpMM launch Y = A X: values (word bytes) and
+    column indices (4 B) per nonzero, row pointers (4 B per row), X read once
+    and Y written once (word bytes per DoF and orbital each)."""
+    return (word + 4) * nnz + 4 * (n + 1) + 2 * word * n * N
 
 
 def cpu_baseline(S, N, iters_per_step, sample_iters, sigma):
@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cg-rtol", type=float, default=1e-9)
+    ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64",
+                    help="step-5 arithmetic: plain FP64 CG, or FP32 CG inside FP64 iterative refinement")
     ap.add_argument("--inner-maxit", type=int, default=60)
     ap.add_argument("--inner-tol", type=float, default=1e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -105,8 +107,9 @@ def main():
     t_all = time.perf_counter()
     log(f"[bench] building workload {args.workload} seed {args.seed}")
     S = make_system(args.workload, args.seed)
+    prec = mlc.PREC_FP32_IR if args.precision == "fp32ir" else mlc.PREC_FP64
     opts = mlc.options(cg_rtol=args.cg_rtol, poisson_rtol=args.cg_rtol, inner_maxit=args.inner_maxit,
-                       inner_tol=args.inner_tol, time_kernels=1)
+                       inner_tol=args.inner_tol, time_kernels=1, precision=prec)
     ctx = mlc.Context(S, opts)
     n, N = ctx.n_dof, ctx.N
     nnz = None
@@ -128,7 +131,7 @@ def main():
         log(f"[bench] step {k}: fine {rep['t_fine_ms']:.2f} ms + recon {rep['t_recon_ms']:.2f} ms, "
             f"inner {rep['t_inner_ms']:.0f} ms ({rep['inner_iters']} it), cg {rep['cg_iters_max']} it "
             f"relres {rep['cg_relres_max']:.1e}, poisson {rep['poisson_iters']} it, spmm {rep['n_spmm']} launches "
-            f"{rep['t_spmm_ms']:.2f} ms")
+            f"{rep['t_spmm_ms']:.2f} ms, refinement passes {rep['ir_outer']}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - tw0
     if args.calib_copy_mib:
@@ -148,7 +151,7 @@ def main():
     n_spmm = sum(r["n_spmm"] for r in reps)
     t_spmm = sum(r["t_spmm_ms"] for r in reps) / 1e3
     per_launch = t_spmm / max(n_spmm, 1)
-    bytes_launch = spmm_bytes(n, nnz, N)
+    bytes_launch = spmm_bytes(n, nnz, N, 4 if args.precision == "fp32ir" else 8)
     achieved = bytes_launch / per_launch / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
@@ -163,11 +166,13 @@ def main():
         "metric": "fine-mesh SCF correction step: DoF*orbitals/s and % HBM roofline vs plain FP64",
         "value": value, "unit": "DoF*orbitals/s", "n_gpus": 1, "steps": len(reps), "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64-refinement", "data": "synthetic",
         "config": {"workload": f"4-atom seeded cluster (seed {args.seed}), graded P1 mesh" if args.workload == "c2"
                    else "hydrogen Z=1 rc=0.2, 16^3 Kuhn P1 mesh",
                    "n_dof": n, "orbitals": N, "n_tets": ctx.n_tets, "nnz": nnz, "n_coarse_dof": ctx.n_coarse_dof,
-                   "cg_rtol": args.cg_rtol, "precision": "plain FP64", "parallelism": "1 GPU"},
+                   "cg_rtol": args.cg_rtol,
+                   "precision": "plain FP64" if args.precision == "fp64" else "FP32 CG + FP64 refinement",
+                   "parallelism": "1 GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "detail": {"cg_iters_per_step": cg_its,

@@ -113,11 +113,19 @@ typedef struct {
   int32_t time_kernels; /* 1: HIP events around every SpMM launch of step 5
                            (that CG is then launched eagerly)                  */
   int32_t use_graphs;   /* 1: CG iteration chunks replayed as HIP graphs      */
+  int32_t precision;    /* MLC_PREC_FP64: plain FP64 CG for step 5;
+                           MLC_PREC_FP32_IR: FP32 SpMM/CG inside FP64 iterative
+                           refinement (residual, update and stopping test in
+                           FP64; cg_rtol applies to the FP64 residual)         */
+  double ir_inner_rtol; /* FP32 inner CG tolerance relative to ||R||          */
+  int32_t ir_max_outer; /* refinement passes cap                              */
 } mlc_options;
+
+enum { MLC_PREC_FP64 = 0, MLC_PREC_FP32_IR = 1 };
 
 /* Filled by mlc_correction_step. Times in milliseconds. */
 typedef struct {
-  int32_t cg_iters_max, cg_iters_sum, poisson_iters, inner_iters;
+  int32_t cg_iters_max, cg_iters_sum, poisson_iters, inner_iters;  /* FP32_IR: summed inner FP32 iterations */
   double cg_relres_max;       /* max over orbitals, true residual at exit   */
   double poisson_relres;
   double inner_last_diff;     /* last ||Phi^{s+1}-Phi^s||_{H^1}             */
@@ -133,13 +141,15 @@ typedef struct {
   int64_t n_spmm;             /* SpMM launches in this step                 */
   int64_t spmm_rows;          /* rows x columns processed by those launches */
   int64_t spmm_cols_sum;
+  int32_t ir_outer;           /* refinement passes (precision FP32_IR)      */
 } mlc_step_report;
 
 typedef struct mlc_ctx mlc_ctx;
 
 /* Fill *opt with defaults: cg_rtol 1e-10, cg_maxit 20000, check_every 25,
  * shift 1, sigma0 1, poisson_rtol 1e-12, inner_maxit 500, inner_tol 1e-10,
- * n_extra 8, reorder 1, time_kernels 0, use_graphs 1. */
+ * n_extra 8, reorder 1, time_kernels 0, use_graphs 1, precision FP64,
+ * ir_inner_rtol 1e-4, ir_max_outer 30. */
 void mlc_options_default(mlc_options* opt);
 
 /* Build a context: validates both meshes (positive volumes, indices in range,

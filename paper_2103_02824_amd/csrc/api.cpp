@@ -114,6 +114,17 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->scalP = w.take<double>(10);
   d->flags = w.take<int32_t>(8);
   d->flagsP = w.take<int32_t>(8);
+  if (c->opt.precision == MLC_PREC_FP32_IR) {
+    d->valA32 = w.take<float>(nnz);
+    d->dinvA32 = w.take<float>(n);
+    d->X32 = w.take<float>(n * N);
+    d->R32 = w.take<float>(n * N);
+    d->P32 = w.take<float>(n * N);
+    d->Q32 = w.take<float>(n * N);
+    d->B32 = w.take<float>(n * N);
+  }
+  d->scal32 = w.take<double>(10 * N);
+  d->flags32 = w.take<int32_t>(8);
   return w.off + 256;
 }
 
@@ -340,6 +351,9 @@ void mlc_options_default(mlc_options* o) {
   o->reorder = 1;
   o->time_kernels = 0;
   o->use_graphs = 1;
+  o->precision = MLC_PREC_FP64;
+  o->ir_inner_rtol = 1e-4;
+  o->ir_max_outer = 30;
 }
 
 mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys, const mlc_options* opt,
@@ -362,7 +376,9 @@ mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_sy
   else
     mlc_options_default(&c->opt);
   if (!(c->opt.cg_rtol > 0) || c->opt.cg_maxit < 1 || c->opt.check_every < 1 || c->opt.inner_maxit < 1 ||
-      c->opt.n_extra < 0 || !(c->opt.poisson_rtol > 0)) {
+      c->opt.n_extra < 0 || !(c->opt.poisson_rtol > 0) ||
+      (c->opt.precision != MLC_PREC_FP64 && c->opt.precision != MLC_PREC_FP32_IR) ||
+      (c->opt.precision == MLC_PREC_FP32_IR && (!(c->opt.ir_inner_rtol > 0) || c->opt.ir_max_outer < 1))) {
     delete c;
     return MLC_ERR_ARG;
   }
@@ -419,7 +435,7 @@ mlc_status mlc_bind(mlc_ctx* c, void* dev_workspace, size_t bytes, void* hip_str
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   c->ev_pool.clear();
   c->ev_used = 0;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 3; ++k) {
     if (c->cg_graph[k]) (void)hipGraphExecDestroy(c->cg_graph[k]);
     c->cg_graph[k] = nullptr;
     c->cg_graph_chunk[k] = 0;
@@ -531,7 +547,7 @@ const char* mlc_last_error(const mlc_ctx* c) { return c ? c->err.c_str() : "null
 void mlc_destroy(mlc_ctx* c) {
   if (!c) return;
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < 3; ++k)
     if (c->cg_graph[k]) (void)hipGraphExecDestroy(c->cg_graph[k]);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;

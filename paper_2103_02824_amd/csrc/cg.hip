@@ -59,10 +59,10 @@ inline int cap(int64_t needed, int mx) { return (int)(needed < mx ? (needed < 1 
 // partial sums are combined with lane shuffles. Column indices and values are
 // read coalesced (G consecutive entries), X rows as NT consecutive doubles.
 // Optional CG epilogue: per-block column sums of P . Q.
-template <int NT, int G, int BS>
+template <int NT, int G, int BS, typename T>
 __global__ void __launch_bounds__(BS) k_spmm_small(int64_t n, const int32_t* __restrict__ rowptr,
-                                                   const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                   const double* __restrict__ X, double* __restrict__ Y,
+                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ X, T* __restrict__ Y,
                                                    double* __restrict__ partial, const int32_t* __restrict__ flags) {
   constexpr int RB = BS / G;  // rows per block pass
   if (flags && flags[0] == 0) return;
@@ -74,14 +74,14 @@ __global__ void __launch_bounds__(BS) k_spmm_small(int64_t n, const int32_t* __r
   for (int c = 0; c < NT; ++c) dot[c] = 0.0;
   for (int64_t r0 = (int64_t)blockIdx.x * RB; r0 < n; r0 += (int64_t)gridDim.x * RB) {
     int64_t r = r0 + rl;
-    double acc[NT];
+    T acc[NT];
 #pragma unroll
-    for (int c = 0; c < NT; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NT; ++c) acc[c] = T(0);
     if (r < n) {
       int j1 = rowptr[r + 1];
       for (int j = rowptr[r] + sub; j < j1; j += G) {
-        double a = val[j];
-        const double* xr = X + (int64_t)col[j] * NT;
+        T a = val[j];
+        const T* xr = X + (int64_t)col[j] * NT;
 #pragma unroll
         for (int c = 0; c < NT; ++c) acc[c] += a * xr[c];
       }
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(BS) k_spmm_small(int64_t n, const int32_t* __r
       for (int c = 0; c < NT; ++c)
         if (c % G == sub) {
           Y[r * NT + c] = acc[c];
-          if (partial) dot[c] += acc[c] * X[r * NT + c];
+          if (partial) dot[c] += (double)acc[c] * (double)X[r * NT + c];
         }
     }
   }
@@ -117,9 +117,10 @@ __global__ void __launch_bounds__(BS) k_spmm_small(int64_t n, const int32_t* __r
 
 // SpMM for wider blocks (N > 8): thread (row, column), R = 256/N rows per pass,
 // the nonzero loop unrolled by 4 so that four gathers are in flight.
+template <typename T>
 __global__ void __launch_bounds__(TPB) k_spmm_wide(int64_t n, int N, const int32_t* __restrict__ rowptr,
-                                                   const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                   const double* __restrict__ X, double* __restrict__ Y,
+                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ X, T* __restrict__ Y,
                                                    double* __restrict__ partial, const int32_t* __restrict__ flags) {
   if (flags && flags[0] == 0) return;
   __shared__ double sd[TPB];
@@ -131,7 +132,7 @@ __global__ void __launch_bounds__(TPB) k_spmm_wide(int64_t n, int N, const int32
     int64_t r = r0 + rl;
     if (rl < R && r < n) {
       int j = rowptr[r], j1 = rowptr[r + 1];
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
       for (; j + 3 < j1; j += 4) {
         int k0 = col[j], k1 = col[j + 1], k2 = col[j + 2], k3 = col[j + 3];
         a0 += val[j] * X[(int64_t)k0 * N + c];
@@ -140,9 +141,9 @@ __global__ void __launch_bounds__(TPB) k_spmm_wide(int64_t n, int N, const int32
         a3 += val[j + 3] * X[(int64_t)k3 * N + c];
       }
       for (; j < j1; ++j) a0 += val[j] * X[(int64_t)col[j] * N + c];
-      double acc = (a0 + a1) + (a2 + a3);
+      T acc = (a0 + a1) + (a2 + a3);
       Y[r * N + c] = acc;
-      if (partial) dot += acc * X[r * N + c];
+      if (partial) dot += (double)acc * (double)X[r * N + c];
     }
   }
   if (!partial) return;
@@ -162,9 +163,10 @@ struct RC {
 };
 
 // CG start: R = B - AX, P = Dinv R; block partials of rz, rr, bb.
-__global__ void __launch_bounds__(TPB) k_cg_init(int64_t n, int N, const double* __restrict__ B,
-                                                 const double* __restrict__ AX, const double* __restrict__ dinv,
-                                                 double* __restrict__ Rv, double* __restrict__ P,
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_cg_init(int64_t n, int N, const T* __restrict__ B,
+                                                 const T* __restrict__ AX, const T* __restrict__ dinv,
+                                                 T* __restrict__ Rv, T* __restrict__ P,
                                                  double* __restrict__ partial) {
   __shared__ double sd[TPB];
   RC p(N);
@@ -173,14 +175,14 @@ __global__ void __launch_bounds__(TPB) k_cg_init(int64_t n, int N, const double*
     int64_t r = r0 + p.rl;
     if (p.rl < p.R && r < n) {
       int64_t i = r * N + p.c;
-      double b = B[i];
-      double rr = b - AX[i];
-      double z = dinv[r] * rr;
+      T b = B[i];
+      T rr = b - AX[i];
+      T z = dinv[r] * rr;
       Rv[i] = rr;
       P[i] = z;
-      v[0] += rr * z;
-      v[1] += rr * rr;
-      v[2] += b * b;
+      v[0] += (double)rr * (double)z;
+      v[1] += (double)rr * (double)rr;
+      v[2] += (double)b * (double)b;
     }
   }
   for (int k = 0; k < 3; ++k) {
@@ -228,7 +230,8 @@ enum { C_RZ = 0, C_RR, C_BB, C_ACT, C_IT };
 
 // CG start scalars from the k_cg_init partials [rz, rr, bb] (one block).
 __global__ void __launch_bounds__(TPB) k_cg_start(int N, int nblk, const double* __restrict__ partial, double rtol2,
-                                                 double* __restrict__ scal, int32_t* __restrict__ flags) {
+                                                 const double* __restrict__ mask, double* __restrict__ scal,
+                                                 int32_t* __restrict__ flags) {
   __shared__ double sums[3 * MLC_MAX_ORBITALS];
   sum_partials(partial, nblk, 3 * N, sums);
   if (threadIdx.x != 0) return;
@@ -239,6 +242,7 @@ __global__ void __launch_bounds__(TPB) k_cg_start(int N, int nblk, const double*
     scal[C_BB * N + c] = sums[2 * N + c];
     scal[C_IT * N + c] = 0.0;
     bool act = sums[N + c] > rtol2 * sums[2 * N + c];
+    if (mask) act = act && mask[C_ACT * N + c] != 0.0;
     scal[C_ACT * N + c] = act ? 1.0 : 0.0;
     nact += act;
   }
@@ -248,9 +252,10 @@ __global__ void __launch_bounds__(TPB) k_cg_start(int N, int nblk, const double*
 // alpha_c = rz_c / (p.q)_c from the SpMM partials; X += alpha P, R -= alpha Q;
 // block partials of r.Dr and r.r. A non-positive curvature on an active
 // column sets brk and freezes that column (alpha = 0).
-__global__ void __launch_bounds__(TPB) k_cg_update(int64_t n, int N, const double* __restrict__ dinv,
-                                                   double* __restrict__ X, double* __restrict__ Rv,
-                                                   const double* __restrict__ P, const double* __restrict__ Q,
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_cg_update(int64_t n, int N, const T* __restrict__ dinv,
+                                                   T* __restrict__ X, T* __restrict__ Rv,
+                                                   const T* __restrict__ P, const T* __restrict__ Q,
                                                    const double* __restrict__ pq_part, int nblk_pq,
                                                    const double* __restrict__ scal, const int32_t* __restrict__ flags,
                                                    double* __restrict__ partial, int32_t* __restrict__ brk) {
@@ -270,18 +275,18 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int64_t n, int N, const doubl
   }
   __syncthreads();
   RC p(N);
-  double a = p.rl < p.R ? alpha[p.c] : 0.0;
+  T a = p.rl < p.R ? (T)alpha[p.c] : T(0);
   double v[2] = {0.0, 0.0};
   for (int64_t r0 = (int64_t)blockIdx.x * p.R; r0 < n; r0 += (int64_t)gridDim.x * p.R) {
     int64_t r = r0 + p.rl;
     if (p.rl < p.R && r < n) {
       int64_t i = r * N + p.c;
-      double x = X[i] + a * P[i];
-      double rr = Rv[i] - a * Q[i];
+      T x = X[i] + a * P[i];
+      T rr = Rv[i] - a * Q[i];
       X[i] = x;
       Rv[i] = rr;
-      v[0] += rr * dinv[r] * rr;
-      v[1] += rr * rr;
+      v[0] += (double)rr * (double)dinv[r] * (double)rr;
+      v[1] += (double)rr * (double)rr;
     }
   }
   for (int k = 0; k < 2; ++k) {
@@ -295,8 +300,9 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int64_t n, int N, const doubl
 // beta_c = rz'_c / rz_c and the test ||r||^2 <= rtol^2 ||b||^2 from the update
 // partials; P = Dinv R + beta P. Block 0 writes the next scalars (the other
 // buffer) and the active count.
-__global__ void __launch_bounds__(TPB) k_cg_direction(int64_t n, int N, const double* __restrict__ dinv,
-                                                      const double* __restrict__ Rv, double* __restrict__ P,
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_cg_direction(int64_t n, int N, const T* __restrict__ dinv,
+                                                      const T* __restrict__ Rv, T* __restrict__ P,
                                                       const double* __restrict__ upd_part, int nblk_upd,
                                                       const double* __restrict__ scal_in,
                                                       const int32_t* __restrict__ flags_in,
@@ -340,22 +346,60 @@ __global__ void __launch_bounds__(TPB) k_cg_direction(int64_t n, int N, const do
   for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < total; i += (int64_t)gridDim.x * TPB) {
     int64_t r = i / N;
     int c = (int)(i - r * N);
-    P[i] = dinv[r] * Rv[i] + beta[c] * P[i];
+    P[i] = dinv[r] * Rv[i] + (T)beta[c] * P[i];
   }
 }
 
-template <int NT, int BS>
-void spmm_small(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
-                const double* X, double* Y, double* partial, const int32_t* flags, int maxblk) {
+template <int NT, int BS, typename T>
+void spmm_small(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* col, const T* val, const T* X, T* Y,
+                double* partial, const int32_t* flags, int maxblk) {
   constexpr int G = NT == 1 ? 8 : 4;
   int64_t needed = (n + (BS / G) - 1) / (BS / G);
-  hipLaunchKernelGGL((k_spmm_small<NT, G, BS>), dim3(cap(needed, maxblk)), dim3(BS), 0, s, n, rowptr, col, val, X, Y,
-                     partial, flags);
+  hipLaunchKernelGGL((k_spmm_small<NT, G, BS, T>), dim3(cap(needed, maxblk)), dim3(BS), 0, s, n, rowptr, col, val, X,
+                     Y, partial, flags);
 }
 
 int vec_blocks(int64_t n, int N) {
   int64_t R = TPB / N;
   return cap((n + R - 1) / R, VEC_MAXBLK);
+}
+
+// FP32 <-> FP64 helpers of the iterative refinement
+__global__ void __launch_bounds__(TPB) k_to_f32(int64_t m, const double* __restrict__ a, float* __restrict__ b) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < m) b[i] = (float)a[i];
+}
+__global__ void __launch_bounds__(TPB) k_add_f32(int64_t m, const float* __restrict__ d, double* __restrict__ x) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < m) x[i] += (double)d[i];
+}
+
+template <typename T>
+void spmm_any(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val, const T* X,
+              T* Y, double* partial, const int32_t* flags) {
+#define SPMM_CASE(K)                                                                        \
+  case K:                                                                                   \
+    if (partial)                                                                            \
+      spmm_small<K, SPMM_BS, T>(s, n, rowptr, col, val, X, Y, partial, flags, SPMM_MAXBLK); \
+    else                                                                                    \
+      spmm_small<K, TPB, T>(s, n, rowptr, col, val, X, Y, partial, flags, MAXBLK);          \
+    return;
+  switch (N) {
+    SPMM_CASE(1)
+    SPMM_CASE(2)
+    SPMM_CASE(3)
+    SPMM_CASE(4)
+    SPMM_CASE(5)
+    SPMM_CASE(6)
+    SPMM_CASE(7)
+    SPMM_CASE(8)
+    default: {
+      int64_t R = TPB / N;
+      hipLaunchKernelGGL((k_spmm_wide<T>), dim3(cap((n + R - 1) / R, MAXBLK)), dim3(TPB), 0, s, n, N, rowptr, col,
+                         val, X, Y, partial, flags);
+    }
+  }
+#undef SPMM_CASE
 }
 
 }  // namespace
@@ -377,51 +421,62 @@ int cg_max_blocks() { return MAXBLK; }
 // variant, 1024-thread blocks); with flags: early exit when no column is active.
 void launch_spmm2(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const double* val,
                   const double* X, double* Y, double* partial, const int32_t* flags) {
-#define SPMM_CASE(K)                                                                     \
-  case K:                                                                                \
-    if (partial)                                                                         \
-      spmm_small<K, SPMM_BS>(s, n, rowptr, col, val, X, Y, partial, flags, SPMM_MAXBLK); \
-    else                                                                                 \
-      spmm_small<K, TPB>(s, n, rowptr, col, val, X, Y, partial, flags, MAXBLK);          \
-    return;
-  switch (N) {
-    SPMM_CASE(1)
-    SPMM_CASE(2)
-    SPMM_CASE(3)
-    SPMM_CASE(4)
-    SPMM_CASE(5)
-    SPMM_CASE(6)
-    SPMM_CASE(7)
-    SPMM_CASE(8)
-    default:
-      hipLaunchKernelGGL(k_spmm_wide, dim3(cg_blocks(n, N)), dim3(TPB), 0, s, n, N, rowptr, col, val, X, Y, partial,
-                         flags);
-  }
-#undef SPMM_CASE
+  spmm_any<double>(s, n, N, rowptr, col, val, X, Y, partial, flags);
+}
+void launch_spmm2_f32(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const float* val,
+                      const float* X, float* Y, double* partial, const int32_t* flags) {
+  spmm_any<float>(s, n, N, rowptr, col, val, X, Y, partial, flags);
 }
 
+template <typename T>
+void cg_init_t(hipStream_t s, int64_t n, int N, const T* B, const T* AX, const T* dinv, T* Rv, T* P, double* partial) {
+  hipLaunchKernelGGL((k_cg_init<T>), dim3(cg_blocks(n, N)), dim3(TPB), 0, s, n, N, B, AX, dinv, Rv, P, partial);
+}
 void launch_cg_init2(hipStream_t s, int64_t n, int N, const double* B, const double* AX, const double* dinv,
                      double* Rv, double* P, double* partial) {
-  hipLaunchKernelGGL(k_cg_init, dim3(cg_blocks(n, N)), dim3(TPB), 0, s, n, N, B, AX, dinv, Rv, P, partial);
+  cg_init_t<double>(s, n, N, B, AX, dinv, Rv, P, partial);
+}
+void launch_cg_init2_f32(hipStream_t s, int64_t n, int N, const float* B, const float* AX, const float* dinv,
+                         float* Rv, float* P, double* partial) {
+  cg_init_t<float>(s, n, N, B, AX, dinv, Rv, P, partial);
 }
 
-void launch_cg_start(hipStream_t s, int64_t n, int N, const double* partial, double rtol2, double* scal,
-                     int32_t* flags) {
-  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(TPB), 0, s, N, cg_blocks(n, N), partial, rtol2, scal, flags);
+void launch_cg_start(hipStream_t s, int64_t n, int N, const double* partial, double rtol2, const double* mask,
+                     double* scal, int32_t* flags) {
+  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(TPB), 0, s, N, cg_blocks(n, N), partial, rtol2, mask, scal, flags);
 }
 
 void launch_cg_update_f(hipStream_t s, int64_t n, int N, const double* dinv, double* X, double* Rv, const double* P,
                         const double* Q, const double* pq_part, const double* scal, const int32_t* flags,
                         double* partial, int32_t* brk) {
-  hipLaunchKernelGGL(k_cg_update, dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, X, Rv, P, Q, pq_part,
+  hipLaunchKernelGGL((k_cg_update<double>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, X, Rv, P, Q,
+                     pq_part, spmm_blocks(n, N), scal, flags, partial, brk);
+}
+void launch_cg_update_f32(hipStream_t s, int64_t n, int N, const float* dinv, float* X, float* Rv, const float* P,
+                          const float* Q, const double* pq_part, const double* scal, const int32_t* flags,
+                          double* partial, int32_t* brk) {
+  hipLaunchKernelGGL((k_cg_update<float>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, X, Rv, P, Q, pq_part,
                      spmm_blocks(n, N), scal, flags, partial, brk);
 }
 
 void launch_cg_direction_f(hipStream_t s, int64_t n, int N, const double* dinv, const double* Rv, double* P,
                            const double* upd_part, const double* scal_in, const int32_t* flags_in, double* scal_out,
                            int32_t* flags_out, double rtol2) {
-  hipLaunchKernelGGL(k_cg_direction, dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, Rv, P, upd_part,
+  hipLaunchKernelGGL((k_cg_direction<double>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, Rv, P, upd_part,
                      vec_blocks(n, N), scal_in, flags_in, scal_out, flags_out, rtol2);
+}
+void launch_cg_direction_f32(hipStream_t s, int64_t n, int N, const float* dinv, const float* Rv, float* P,
+                             const double* upd_part, const double* scal_in, const int32_t* flags_in, double* scal_out,
+                             int32_t* flags_out, double rtol2) {
+  hipLaunchKernelGGL((k_cg_direction<float>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, Rv, P, upd_part,
+                     vec_blocks(n, N), scal_in, flags_in, scal_out, flags_out, rtol2);
+}
+
+void launch_to_f32(hipStream_t s, int64_t m, const double* a, float* b) {
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((m + TPB - 1) / TPB)), dim3(TPB), 0, s, m, a, b);
+}
+void launch_add_f32(hipStream_t s, int64_t m, const float* d, double* x) {
+  hipLaunchKernelGGL(k_add_f32, dim3((unsigned)((m + TPB - 1) / TPB)), dim3(TPB), 0, s, m, d, x);
 }
 
 }  // namespace mlc

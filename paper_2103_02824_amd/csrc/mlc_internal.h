@@ -94,6 +94,12 @@ struct Dev {
   double* scalP = nullptr;      // 2 x 5 CG scalars (Hartree)
   int32_t* flags = nullptr;     // [0] active (buffer 0) [2] active (buffer 1) [4] breakdown
   int32_t* flagsP = nullptr;
+  // FP32 inner solve of the iterative refinement
+  float* valA32 = nullptr;      // nnz
+  float* dinvA32 = nullptr;     // n
+  float *X32 = nullptr, *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr, *B32 = nullptr;  // n x N
+  double* scal32 = nullptr;     // 2 x 5N
+  int32_t* flags32 = nullptr;   // 8
 };
 
 struct Options {
@@ -161,9 +167,9 @@ struct mlc_ctx {
   std::vector<hipEvent_t> ev_pool;
   int ev_used = 0;
   // captured CG iteration chunks (one per solve kind: 0 orbitals, 1 Poisson)
-  hipGraphExec_t cg_graph[2] = {nullptr, nullptr};
-  int cg_graph_chunk[2] = {0, 0};
-  double cg_graph_rt2[2] = {0.0, 0.0};
+  hipGraphExec_t cg_graph[3] = {nullptr, nullptr, nullptr};  // 0 orbitals, 1 Hartree, 2 orbitals FP32
+  int cg_graph_chunk[3] = {0, 0, 0};
+  double cg_graph_rt2[3] = {0.0, 0.0, 0.0};
   hipStream_t cap_stream = nullptr;     // library-owned stream used only to record graphs
 };
 
@@ -190,8 +196,20 @@ void launch_spmm2(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const 
                   const double* X, double* Y, double* partial, const int32_t* flags);
 void launch_cg_init2(hipStream_t s, int64_t n, int N, const double* B, const double* AX, const double* dinv,
                      double* Rv, double* P, double* partial);
-void launch_cg_start(hipStream_t s, int64_t n, int N, const double* partial, double rtol2, double* scal,
-                     int32_t* flags);
+void launch_cg_start(hipStream_t s, int64_t n, int N, const double* partial, double rtol2, const double* mask,
+                     double* scal, int32_t* flags);
+void launch_spmm2_f32(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const float* val,
+                      const float* X, float* Y, double* partial, const int32_t* flags);
+void launch_cg_init2_f32(hipStream_t s, int64_t n, int N, const float* B, const float* AX, const float* dinv,
+                         float* Rv, float* P, double* partial);
+void launch_cg_update_f32(hipStream_t s, int64_t n, int N, const float* dinv, float* X, float* Rv, const float* P,
+                          const float* Q, const double* pq_part, const double* scal, const int32_t* flags,
+                          double* partial, int32_t* brk);
+void launch_cg_direction_f32(hipStream_t s, int64_t n, int N, const float* dinv, const float* Rv, float* P,
+                             const double* upd_part, const double* scal_in, const int32_t* flags_in, double* scal_out,
+                             int32_t* flags_out, double rtol2);
+void launch_to_f32(hipStream_t s, int64_t m, const double* a, float* b);
+void launch_add_f32(hipStream_t s, int64_t m, const float* d, double* x);
 void launch_cg_update_f(hipStream_t s, int64_t n, int N, const double* dinv, double* X, double* Rv, const double* P,
                         const double* Q, const double* pq_part, const double* scal, const int32_t* flags,
                         double* partial, int32_t* brk);

@@ -51,17 +51,57 @@ struct CgRes {
   bool breakdown = false;
 };
 
+template <typename T>
 struct CgArgs {
-  const double* val;
-  const double* dinv;
-  const double* B;
-  double *X, *R, *P, *Q, *scal;
+  const T* val;
+  const T* dinv;
+  const T* B;
+  T *X, *R, *P, *Q;
+  double* scal;
   int32_t* flags;
+  const double* mask;  // optional: column c may be active only if mask[active c] != 0
 };
+
+// type-dispatched launchers
+inline void L_spmm(hipStream_t s, int64_t n, int N, const int32_t* rp, const int32_t* ci, const double* v,
+                   const double* X, double* Y, double* part, const int32_t* fl) {
+  launch_spmm2(s, n, N, rp, ci, v, X, Y, part, fl);
+}
+inline void L_spmm(hipStream_t s, int64_t n, int N, const int32_t* rp, const int32_t* ci, const float* v,
+                   const float* X, float* Y, double* part, const int32_t* fl) {
+  launch_spmm2_f32(s, n, N, rp, ci, v, X, Y, part, fl);
+}
+inline void L_init(hipStream_t s, int64_t n, int N, const double* B, const double* AX, const double* dinv, double* R,
+                   double* P, double* part) {
+  launch_cg_init2(s, n, N, B, AX, dinv, R, P, part);
+}
+inline void L_init(hipStream_t s, int64_t n, int N, const float* B, const float* AX, const float* dinv, float* R,
+                   float* P, double* part) {
+  launch_cg_init2_f32(s, n, N, B, AX, dinv, R, P, part);
+}
+inline void L_update(hipStream_t s, int64_t n, int N, const double* dinv, double* X, double* R, const double* P,
+                     const double* Q, const double* pq, const double* sc, const int32_t* fl, double* part,
+                     int32_t* brk) {
+  launch_cg_update_f(s, n, N, dinv, X, R, P, Q, pq, sc, fl, part, brk);
+}
+inline void L_update(hipStream_t s, int64_t n, int N, const float* dinv, float* X, float* R, const float* P,
+                     const float* Q, const double* pq, const double* sc, const int32_t* fl, double* part,
+                     int32_t* brk) {
+  launch_cg_update_f32(s, n, N, dinv, X, R, P, Q, pq, sc, fl, part, brk);
+}
+inline void L_dir(hipStream_t s, int64_t n, int N, const double* dinv, const double* R, double* P, const double* up,
+                  const double* si, const int32_t* fi, double* so, int32_t* fo, double rt2) {
+  launch_cg_direction_f(s, n, N, dinv, R, P, up, si, fi, so, fo, rt2);
+}
+inline void L_dir(hipStream_t s, int64_t n, int N, const float* dinv, const float* R, float* P, const double* up,
+                  const double* si, const int32_t* fi, double* so, int32_t* fo, double rt2) {
+  launch_cg_direction_f32(s, n, N, dinv, R, P, up, si, fi, so, fo, rt2);
+}
 
 // One CG iteration (three kernels) reading the scalars of parity p and
 // writing those of parity 1-p.
-void enqueue_iteration(mlc_ctx* c, hipStream_t s, int64_t n, int N, const CgArgs& a, double rt2, int p) {
+template <typename T>
+void enqueue_iteration(mlc_ctx* c, hipStream_t s, int64_t n, int N, const CgArgs<T>& a, double rt2, int p) {
   auto& d = c->d;
   double* red_pq = d.red;
   double* red_upd = d.red + c->nred / 2;
@@ -69,27 +109,28 @@ void enqueue_iteration(mlc_ctx* c, hipStream_t s, int64_t n, int N, const CgArgs
   double* sc_out = a.scal + (p ? 0 : 5 * N);
   int32_t* fl_in = a.flags + (p ? 2 : 0);
   int32_t* fl_out = a.flags + (p ? 0 : 2);
-  launch_spmm2(s, n, N, d.rowptr, d.col, a.val, a.P, a.Q, red_pq, fl_in);
-  launch_cg_update_f(s, n, N, a.dinv, a.X, a.R, a.P, a.Q, red_pq, sc_in, fl_in, red_upd, a.flags + 4);
-  launch_cg_direction_f(s, n, N, a.dinv, a.R, a.P, red_upd, sc_in, fl_in, sc_out, fl_out, rt2);
+  L_spmm(s, n, N, d.rowptr, d.col, a.val, a.P, a.Q, red_pq, fl_in);
+  L_update(s, n, N, a.dinv, a.X, a.R, a.P, a.Q, red_pq, sc_in, fl_in, red_upd, a.flags + 4);
+  L_dir(s, n, N, a.dinv, a.R, a.P, red_upd, sc_in, fl_in, sc_out, fl_out, rt2);
 }
 
 // Multi-column Jacobi-PCG, one independent recurrence per column; per-column
 // scalars stay on the device; the host checks the number of active columns
 // every chunk (an even number of iterations >= check_every). A chunk is
-// captured once into a HIP graph (kind 0: orbitals, 1: Hartree) and replayed;
+// captured once into a HIP graph (one graph per solve kind) and replayed;
 // with timed = true the chunk is launched eagerly and every SpMM launch is
-// bracketed by HIP events. On exit the true residual is evaluated.
-mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs& a, double rtol, int maxit, bool timed,
+// bracketed by HIP events. On exit the true residual is evaluated in T.
+template <typename T>
+mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs<T>& a, double rtol, int maxit, bool timed,
               double* spmm_ms, int64_t* n_spmm, CgRes* out) {
   hipStream_t s = c->stream;
   auto& d = c->d;
   const double rt2 = rtol * rtol;
   double* red_upd = d.red + c->nred / 2;
   HIPCHK(hipMemsetAsync(a.flags, 0, 8 * sizeof(int32_t), s));
-  launch_spmm2(s, n, N, d.rowptr, d.col, a.val, a.X, a.Q, nullptr, nullptr);
-  launch_cg_init2(s, n, N, a.B, a.Q, a.dinv, a.R, a.P, red_upd);
-  launch_cg_start(s, n, N, red_upd, rt2, a.scal, a.flags);
+  L_spmm(s, n, N, d.rowptr, d.col, a.val, a.X, a.Q, nullptr, nullptr);
+  L_init(s, n, N, a.B, a.Q, a.dinv, a.R, a.P, red_upd);
+  launch_cg_start(s, n, N, red_upd, rt2, a.mask, a.scal, a.flags);
   int it = 0;
   int32_t hf[8];
   const int every = 2 * ((std::max(1, c->opt.check_every) + 1) / 2);
@@ -132,19 +173,19 @@ mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs& a, double rt
     } else {
       for (int k = 0; k < every; ++k) {
         bool rec = timed && c->ev_used + 2 <= (int)c->ev_pool.size();
-        if (rec) HIPCHK(hipEventRecord(c->ev_pool[c->ev_used], s));
         int p = k & 1;
         double* red_pq = d.red;
-        launch_spmm2(s, n, N, d.rowptr, d.col, a.val, a.P, a.Q, red_pq, a.flags + (p ? 2 : 0));
+        if (rec) HIPCHK(hipEventRecord(c->ev_pool[c->ev_used], s));
+        L_spmm(s, n, N, d.rowptr, d.col, a.val, a.P, a.Q, red_pq, a.flags + (p ? 2 : 0));
         if (rec) {
           HIPCHK(hipEventRecord(c->ev_pool[c->ev_used + 1], s));
           c->ev_used += 2;
           ++*n_spmm;
         }
-        launch_cg_update_f(s, n, N, a.dinv, a.X, a.R, a.P, a.Q, red_pq, a.scal + (p ? 5 * N : 0),
-                           a.flags + (p ? 2 : 0), red_upd, a.flags + 4);
-        launch_cg_direction_f(s, n, N, a.dinv, a.R, a.P, red_upd, a.scal + (p ? 5 * N : 0), a.flags + (p ? 2 : 0),
-                              a.scal + (p ? 0 : 5 * N), a.flags + (p ? 0 : 2), rt2);
+        L_update(s, n, N, a.dinv, a.X, a.R, a.P, a.Q, red_pq, a.scal + (p ? 5 * N : 0), a.flags + (p ? 2 : 0),
+                 red_upd, a.flags + 4);
+        L_dir(s, n, N, a.dinv, a.R, a.P, red_upd, a.scal + (p ? 5 * N : 0), a.flags + (p ? 2 : 0),
+              a.scal + (p ? 0 : 5 * N), a.flags + (p ? 0 : 2), rt2);
       }
     }
     it += every;
@@ -162,9 +203,9 @@ mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs& a, double rt
   }
   out->iters = itmax;
   out->iters_sum = itsum;
-  launch_spmm2(s, n, N, d.rowptr, d.col, a.val, a.X, a.Q, nullptr, nullptr);
-  launch_cg_init2(s, n, N, a.B, a.Q, a.dinv, a.R, a.P, red_upd);
-  launch_cg_start(s, n, N, red_upd, 0.0, a.scal, a.flags);
+  L_spmm(s, n, N, d.rowptr, d.col, a.val, a.X, a.Q, nullptr, nullptr);
+  L_init(s, n, N, a.B, a.Q, a.dinv, a.R, a.P, red_upd);
+  launch_cg_start(s, n, N, red_upd, 0.0, nullptr, a.scal, a.flags);
   HIPCHK(hipMemcpyAsync(hs.data(), a.scal, sizeof(double) * 5 * N, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   double mx = 0.0;
@@ -174,6 +215,69 @@ mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs& a, double rt
     mx = std::max(mx, bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr));
   }
   out->relres = mx;
+  if (!std::isfinite(mx)) return fail(c, MLC_ERR_NONFINITE, "non-finite CG residual");
+  return MLC_OK;
+}
+
+// Step 5 with FP32 CG inside FP64 iterative refinement: the residual
+// R = B - A X is formed in FP64, the correction D solves A D = R in FP32 (CG
+// to ir_inner_rtol relative to ||R|| for the columns not yet converged in
+// FP64), and X += D in FP64; until ||B - A X||_2 <= cg_rtol ||B||_2 per column.
+mlc_status solve_ir(mlc_ctx* c, int64_t n, int N, bool timed, double* spmm_ms, int64_t* n_spmm, CgRes* out,
+                    int* outer_iters) {
+  hipStream_t s = c->stream;
+  auto& d = c->d;
+  const int64_t nnz = (int64_t)c->col.size();
+  double* red_upd = d.red + c->nred / 2;
+  launch_to_f32(s, nnz, d.valA, d.valA32);
+  launch_to_f32(s, n, d.dinvA, d.dinvA32);
+  const double rt2 = c->opt.cg_rtol * c->opt.cg_rtol;
+  int total = 0;
+  int64_t total_sum = 0;
+  int outer = 0;
+  int32_t hf[8];
+  bool converged = false;
+  for (; outer < c->opt.ir_max_outer; ++outer) {
+    launch_spmm2(s, n, N, d.rowptr, d.col, d.valA, d.X, d.Q, nullptr, nullptr);
+    launch_cg_init2(s, n, N, d.B, d.Q, d.dinvA, d.R, d.P, red_upd);
+    launch_cg_start(s, n, N, red_upd, rt2, nullptr, d.scal, d.flags);
+    HIPCHK(hipMemcpyAsync(hf, d.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hf[0] == 0) {
+      converged = true;
+      break;
+    }
+    launch_to_f32(s, n * N, d.R, d.B32);
+    HIPCHK(hipMemsetAsync(d.X32, 0, sizeof(float) * n * N, s));
+    CgArgs<float> fa{d.valA32, d.dinvA32, d.B32, d.X32, d.R32, d.P32, d.Q32, d.scal32, d.flags32, d.scal};
+    CgRes ir;
+    mlc_status st = cg<float>(c, 2, n, N, fa, c->opt.ir_inner_rtol, c->opt.cg_maxit, timed, spmm_ms, n_spmm, &ir);
+    if (st != MLC_OK) return st;
+    if (ir.breakdown) {
+      out->breakdown = true;
+      return MLC_OK;
+    }
+    launch_add_f32(s, n * N, d.X32, d.X);
+    total += ir.iters;
+    total_sum += ir.iters_sum;
+  }
+  out->converged = converged;
+  out->iters = total;
+  out->iters_sum = total_sum;
+  // true FP64 residual
+  launch_spmm2(s, n, N, d.rowptr, d.col, d.valA, d.X, d.Q, nullptr, nullptr);
+  launch_cg_init2(s, n, N, d.B, d.Q, d.dinvA, d.R, d.P, red_upd);
+  launch_cg_start(s, n, N, red_upd, 0.0, nullptr, d.scal, d.flags);
+  std::vector<double> hs(5 * N);
+  HIPCHK(hipMemcpyAsync(hs.data(), d.scal, sizeof(double) * 5 * N, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double mx = 0.0;
+  for (int j = 0; j < N; ++j) {
+    double bb = hs[2 * N + j], rr = hs[N + j];
+    mx = std::max(mx, bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr));
+  }
+  out->relres = mx;
+  *outer_iters = outer;
   if (!std::isfinite(mx)) return fail(c, MLC_ERR_NONFINITE, "non-finite CG residual");
   return MLC_OK;
 }
@@ -228,8 +332,15 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   launch_scale_cols_to(s, n, N, d.Q, d.colv, d.B);
   HIPCHK(hipMemcpyAsync(d.X, d.Phi, sizeof(double) * n * N, hipMemcpyDeviceToDevice, s));
   CgRes cr;
-  CgArgs ca{d.valA, d.dinvA, d.B, d.X, d.R, d.P, d.Q, d.scal, d.flags};
-  mlc_status st = cg(c, 0, n, N, ca, c->opt.cg_rtol, c->opt.cg_maxit, timed, &r.t_spmm_ms, &r.n_spmm, &cr);
+  mlc_status st;
+  int outer_iters = 0;
+  if (c->opt.precision == MLC_PREC_FP32_IR) {
+    st = solve_ir(c, n, N, timed, &r.t_spmm_ms, &r.n_spmm, &cr, &outer_iters);
+  } else {
+    CgArgs<double> ca{d.valA, d.dinvA, d.B, d.X, d.R, d.P, d.Q, d.scal, d.flags, nullptr};
+    st = cg<double>(c, 0, n, N, ca, c->opt.cg_rtol, c->opt.cg_maxit, timed, &r.t_spmm_ms, &r.n_spmm, &cr);
+  }
+  r.ir_outer = outer_iters;
   if (st != MLC_OK) return st;
   r.cg_iters_max = cr.iters;
   r.cg_iters_sum = (int32_t)cr.iters_sum;
@@ -252,8 +363,8 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
     // warm start from the previous step's w0 (zero at bind)
     double dummy = 0.0;
     int64_t dn = 0;
-    CgArgs pa{d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP};
-    st = cg(c, 1, n, 1, pa, c->opt.poisson_rtol, c->opt.cg_maxit, false, &dummy, &dn, &pr);
+    CgArgs<double> pa{d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP, nullptr};
+    st = cg<double>(c, 1, n, 1, pa, c->opt.poisson_rtol, c->opt.cg_maxit, false, &dummy, &dn, &pr);
     if (st != MLC_OK) return st;
     if (pr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the Hartree problem");
     launch_field(s, nt, d.tets, nullptr, d.v2d, d.w0, nullptr, nullptr, d.fld2);

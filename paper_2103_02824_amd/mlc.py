@@ -54,7 +54,10 @@ class Options(C.Structure):
     _fields_ = [("cg_rtol", C.c_double), ("cg_maxit", C.c_int32), ("check_every", C.c_int32),
                 ("shift", C.c_int32), ("sigma0", C.c_double), ("poisson_rtol", C.c_double),
                 ("inner_maxit", C.c_int32), ("inner_tol", C.c_double), ("n_extra", C.c_int32),
-                ("reorder", C.c_int32), ("time_kernels", C.c_int32), ("use_graphs", C.c_int32)]
+                ("reorder", C.c_int32), ("time_kernels", C.c_int32), ("use_graphs", C.c_int32),
+                ("precision", C.c_int32), ("ir_inner_rtol", C.c_double), ("ir_max_outer", C.c_int32)]
+
+PREC_FP64, PREC_FP32_IR = 0, 1
 
 
 class StepReport(C.Structure):
@@ -64,7 +67,7 @@ class StepReport(C.Structure):
                 ("max_offdiag_overlap", C.c_double), ("rho_integral", C.c_double), ("energy", C.c_double),
                 ("t_fine_ms", C.c_double), ("t_inner_ms", C.c_double), ("t_recon_ms", C.c_double),
                 ("t_spmm_ms", C.c_double), ("n_spmm", C.c_int64), ("spmm_rows", C.c_int64),
-                ("spmm_cols_sum", C.c_int64)]
+                ("spmm_cols_sum", C.c_int64), ("ir_outer", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

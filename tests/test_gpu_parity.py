@@ -187,3 +187,28 @@ def test_graph_replay_matches_eager(gpu):
         ctx.close()
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("case", ["c1", "tiny2"])
+def test_fp32_refinement_matches_fp64_checker(gpu, case):
+    """Step 5 with FP32 SpMM/CG inside FP64 iterative refinement reaches the
+    same results as the FP64 checker (residual tested in FP64)."""
+    from inputs.systems import tiny_system
+    from paper_2103_02824_amd import mlc
+    if case == "c1":
+        S = c1_hydrogen()
+    else:
+        S = tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=True, n_orbitals=2, seed=7)
+    print(f"case {case} precision FP32_IR", flush=True)
+    prob = Problem(S)
+    st0, _ = initial_state(prob)
+    ctx = mlc.Context(S, mlc.options(**dict(LIB_OPTS, precision=mlc.PREC_FP32_IR, ir_inner_rtol=1e-4)))
+    ctx.set_state(st0.lam, st0.Phi, st0.w)
+    rep = ctx.correction_step()
+    assert rep["ir_outer"] >= 2 and rep["cg_relres_max"] <= 1e-12
+    ref = correction_step(prob, st0, ORA_OPTS)
+    assert relerr(ctx.probe("U", (ctx.n_dof, ctx.N)), ref.inter["fine"]["U"]) < 1e-8
+    lam, Phi, w, rho = ctx.get_results()
+    assert np.max(np.abs(lam - ref.state.lam)) < 1e-8, (lam, ref.state.lam)
+    assert relerr(rho, ref.rho_nodal) < 1e-6
+    ctx.close()
