@@ -220,6 +220,68 @@ enum {
 };
 mlc_status mlc_probe(mlc_ctx* ctx, int32_t which, double* out, int64_t count);
 
+/* Kernel timing for roofline accounting: replays the SpMM of step 5's CG
+ * (Y = (A + sigma M) P over all N orbital columns, with the per-block P.Y
+ * partials the CG consumes; FP32 values when options.precision is
+ * MLC_PREC_FP32_IR) `reps` times back to back on the bound stream, between
+ * two HIP events, and returns the mean duration per launch in microseconds.
+ * It overwrites only CG scratch (the Q block and the partials); the state and
+ * the results of the last step are untouched. Requires a completed
+ * correction step (MLC_ERR_STATE otherwise); reps must lie in 1..100000. */
+mlc_status mlc_time_spmm(mlc_ctx* ctx, int32_t reps, double* avg_us);
+
+/* ---- Batches of independent systems ---------------------------------------
+ * Batching extension of steps 5-6 (the paper steps systems one at a time; its
+ * step-5 problems are independent per orbital, Section 3.2, and so are the
+ * problems of independent systems). A batch steps several bound contexts with
+ * a state together: the step-5 CG solves of all systems run as one set of
+ * launches per CG phase over a table of row tiles (tile -> system), replayed
+ * from a captured HIP graph, and likewise their Hartree solves; every other
+ * phase runs per system on the batch stream; the host inner iterations
+ * (Algorithm 3 step 2) run in parallel over the systems. An autotuner times
+ * the batched SpMM on the first step for rows per tile {128, 256, 512, 1024}
+ * x lanes per row {2, 4, 8} and keeps the fastest (mlc_batch_set_shape fixes
+ * either instead).
+ *
+ * mlc_batch_create: ctxs[0..count) distinct, bound contexts with the same
+ * options.precision; the batch keeps the pointers (the caller keeps the
+ * contexts alive, does not re-bind them and does not step them concurrently
+ * with the batch). Systems may differ in mesh and orbital count.
+ * mlc_batch_bind: device workspace of mlc_batch_workspace_bytes (256-byte
+ * aligned, owned by the caller) and the stream every call enqueues on.
+ * mlc_batch_step: one correction step of every system (same results, to
+ * rounding order, as mlc_correction_step on each); reports[0..count) as in
+ * mlc_correction_step (t_fine_ms and t_recon_ms of a system span the batch's
+ * phases); br may be NULL. On error the message names the system. */
+typedef struct mlc_batch mlc_batch;
+
+typedef struct {
+  int32_t n_systems;
+  int32_t tile_rows;      /* rows per tile in use */
+  int32_t spmm_lanes;     /* lanes per row in use (systems with N <= 8) */
+  int32_t n_tiles;        /* step-5 tiles over all systems */
+  int32_t cg_iters;       /* step-5 CG iterations (max over systems; FP32 total under refinement) */
+  int32_t poisson_iters;  /* Hartree CG iterations (max over systems) */
+  int32_t ir_outer;       /* refinement passes (MLC_PREC_FP32_IR) */
+  int32_t pad;
+  int64_t dof_orbitals;   /* sum over systems of n_dof x N */
+  double t_gpu_ms;        /* HIP events: fine stage of all systems, density through coarse integrals */
+  double t_solve_ms;      /* of which the batched step-5 solve */
+  double t_poisson_ms;    /* of which the batched Hartree solve */
+  double t_inner_ms;      /* host inner iterations, wall time */
+  double t_recon_ms;      /* HIP events: reconstruction of all systems */
+  double t_tune_ms;       /* autotuning wall time (first step only, not in t_gpu_ms) */
+} mlc_batch_report;
+
+mlc_status mlc_batch_create(mlc_ctx* const* ctxs, int32_t count, mlc_batch** out);
+mlc_status mlc_batch_workspace_bytes(const mlc_batch* b, size_t* bytes);
+mlc_status mlc_batch_bind(mlc_batch* b, void* workspace, size_t bytes, void* stream);
+/* tile_rows in {0, 128, 256, 512, 1024}, lanes in {0, 2, 4, 8}; 0 = autotune. */
+mlc_status mlc_batch_set_shape(mlc_batch* b, int32_t tile_rows, int32_t lanes);
+mlc_status mlc_batch_step(mlc_batch* b, mlc_step_report* reports, mlc_batch_report* br);
+const char* mlc_batch_last_error(const mlc_batch* b);
+void mlc_batch_destroy(mlc_batch* b);
+
 const char* mlc_status_string(mlc_status s);
 const char* mlc_last_error(const mlc_ctx* ctx);
 void mlc_destroy(mlc_ctx* ctx);

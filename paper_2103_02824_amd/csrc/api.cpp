@@ -525,6 +525,38 @@ mlc_status mlc_probe(mlc_ctx* c, int32_t which, double* out, int64_t count) {
   return probe(c, which, out, count);
 }
 
+mlc_status mlc_time_spmm(mlc_ctx* c, int32_t reps, double* avg_us) {
+  if (!c || !avg_us || reps < 1 || reps > 100000) return MLC_ERR_ARG;
+  if (!c->has_step) return fail(c, MLC_ERR_STATE, "no correction step has run");
+  auto& d = c->d;
+  hipStream_t s = c->stream;
+  const int64_t n = c->n;
+  const int N = c->N;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, MLC_ERR_HIP, "hipEventCreate");
+  }
+  hipError_t err = hipEventRecord(e0, s);
+  for (int k = 0; k < reps && err == hipSuccess; ++k) {
+    if (c->opt.precision == MLC_PREC_FP32_IR)
+      launch_spmm2_f32(s, n, N, d.rowptr, d.col, d.valA32, d.P32, d.Q32, d.red, nullptr);
+    else
+      launch_spmm2(s, n, N, d.rowptr, d.col, d.valA, d.P, d.Q, d.red, nullptr);
+    err = hipGetLastError();
+  }
+  if (err == hipSuccess) err = hipEventRecord(e1, s);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return hip_fail(c, err, "mlc_time_spmm");
+  *avg_us = 1e3 * (double)ms / reps;
+  return MLC_OK;
+}
+
 const char* mlc_status_string(mlc_status s) {
   switch (s) {
     case MLC_OK: return "ok";

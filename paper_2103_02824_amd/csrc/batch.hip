@@ -1,0 +1,470 @@
+// Batched multi-column Jacobi-PCG over many independent systems (gfx950).
+//
+// A batch holds K problems of different sizes n_p and column counts N_p (the
+// step-5 problems of several systems, or their Hartree problems). Rows of
+// every problem are cut into tiles of TR rows; one launch covers the tiles of
+// all problems, a table maps tile -> problem. One CG iteration is five
+// launches: SpMM (per-tile partials of p.q), alpha (one block per problem sums
+// its partials in tile order), update (x, r; partials of r.Dr and r.r), beta
+// (one block per problem: beta, the convergence test, the active count) and
+// direction. Problems whose columns have all converged skip their tiles.
+// Scalars per problem and column live on the device:
+//   bs[p * 8 * NB + k * NB + c], k = RZ, RR, BB, ACT, IT, ALPHA, BETA, MASK
+// and the active-column count of problem p in flags[p]; flags[K] is set on a
+// breakdown (non-positive curvature on an active column, which freezes it).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "batch.h"
+
+namespace mlc {
+
+namespace {
+
+constexpr int BS = 256;  // threads per block for every batched kernel
+
+__device__ __forceinline__ double wsum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Column sums over the (rl, c) layout: sd holds R x N values, row-major.
+__device__ __forceinline__ void reduce_rc(double* sd, int R, int N) {
+  int t = threadIdx.x;
+  int m = R;
+  while (m > 1) {
+    int h = (m + 1) >> 1;
+    __syncthreads();
+    if (t < (m - h) * N) sd[t] += sd[t + h * N];
+    m = h;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double* sc(double* bs, int p, int NB, int k) { return bs + ((int64_t)p * 8 + k) * NB; }
+__device__ __forceinline__ const double* sc(const double* bs, int p, int NB, int k) {
+  return bs + ((int64_t)p * 8 + k) * NB;
+}
+
+// Rows [r0, r1) of Y = A S for NT <= 8 columns: G lanes per row, every lane
+// strides the row's nonzeros by G and keeps the NT sums in registers. With
+// dot: per-block column sums of S . Y into sd[0..NT).
+template <int NT, int G, typename T>
+__device__ void tile_spmm_small(int64_t r0, int64_t r1, const int32_t* __restrict__ rowptr,
+                                const int32_t* __restrict__ col, const T* __restrict__ val, const T* __restrict__ S,
+                                T* __restrict__ Y, bool dot, double* sd) {
+  constexpr int RB = BS / G;
+  const int sub = threadIdx.x % G;
+  const int rl = threadIdx.x / G;
+  double dp[NT];
+#pragma unroll
+  for (int c = 0; c < NT; ++c) dp[c] = 0.0;
+  for (int64_t rb = r0; rb < r1; rb += RB) {
+    int64_t r = rb + rl;
+    T acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[c] = T(0);
+    if (r < r1) {
+      int j1 = rowptr[r + 1];
+      for (int j = rowptr[r] + sub; j < j1; j += G) {
+        T a = val[j];
+        const T* xr = S + (int64_t)col[j] * NT;
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[c] += a * xr[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, G);
+    if (r < r1) {
+#pragma unroll
+      for (int c = 0; c < NT; ++c)
+        if (c % G == sub) {
+          Y[r * NT + c] = acc[c];
+          if (dot) dp[c] += (double)acc[c] * (double)S[r * NT + c];
+        }
+    }
+  }
+  if (!dot) return;
+  __shared__ double wpart[BS / 64][8];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    double v = wsum(dp[c]);
+    if (lane == 0) wpart[wid][c] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NT) {
+    int c = threadIdx.x;
+    double s = 0.0;
+    for (int w = 0; w < BS / 64; ++w) s += wpart[w][c];
+    sd[c] = s;
+  }
+  __syncthreads();
+}
+
+// Rows [r0, r1) of Y = A S for any N: thread (row, column), R = BS / N rows
+// per pass, four gathers in flight. With dot: column sums into sd[0..N).
+template <typename T>
+__device__ void tile_spmm_wide(int64_t r0, int64_t r1, int N, const int32_t* __restrict__ rowptr,
+                               const int32_t* __restrict__ col, const T* __restrict__ val, const T* __restrict__ S,
+                               T* __restrict__ Y, bool dot, double* sd) {
+  const int R = BS / N;
+  const int rl = threadIdx.x / N, c = threadIdx.x - rl * N;
+  double dp = 0.0;
+  for (int64_t rb = r0; rb < r1; rb += R) {
+    int64_t r = rb + rl;
+    if (rl < R && r < r1) {
+      int j = rowptr[r], j1 = rowptr[r + 1];
+      T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+      for (; j + 3 < j1; j += 4) {
+        int k0 = col[j], k1 = col[j + 1], k2 = col[j + 2], k3 = col[j + 3];
+        a0 += val[j] * S[(int64_t)k0 * N + c];
+        a1 += val[j + 1] * S[(int64_t)k1 * N + c];
+        a2 += val[j + 2] * S[(int64_t)k2 * N + c];
+        a3 += val[j + 3] * S[(int64_t)k3 * N + c];
+      }
+      for (; j < j1; ++j) a0 += val[j] * S[(int64_t)col[j] * N + c];
+      T acc = (a0 + a1) + (a2 + a3);
+      Y[r * N + c] = acc;
+      if (dot) dp += (double)acc * (double)S[r * N + c];
+    }
+  }
+  if (!dot) return;
+  sd[threadIdx.x] = (rl < R) ? dp : 0.0;
+  reduce_rc(sd, R, N);
+}
+
+// SpMM over all tiles. mode 0 (CG): Q = A P with partials of P.Q, tiles of
+// problems without active columns skip; mode 1: Q = A X, no partials.
+template <int G, typename T>
+__global__ void __launch_bounds__(BS) kb_spmm(const BProb<T>* __restrict__ probs, const int32_t* __restrict__ tile_prob,
+                                              int TR, int NB, int mode, double* __restrict__ part,
+                                              const int32_t* __restrict__ flags) {
+  __shared__ double sd[BS];
+  const int t = blockIdx.x;
+  const int p = tile_prob[t];
+  if (mode == 0 && flags[p] == 0) return;
+  const BProb<T> D = probs[p];
+  const int64_t r0 = (int64_t)(t - D.tile0) * TR;
+  const int64_t r1 = r0 + TR < D.n ? r0 + TR : D.n;
+  const T* S = mode == 0 ? D.P : D.X;
+  const bool dot = mode == 0;
+  switch (D.N) {
+#define SMALL(K)                                                                            \
+  case K:                                                                                   \
+    tile_spmm_small<K, (K == 1 ? 8 : G), T>(r0, r1, D.rowptr, D.col, D.val, S, D.Q, dot, sd); \
+    break;
+    SMALL(1)
+    SMALL(2)
+    SMALL(3)
+    SMALL(4)
+    SMALL(5)
+    SMALL(6)
+    SMALL(7)
+    SMALL(8)
+#undef SMALL
+    default:
+      tile_spmm_wide<T>(r0, r1, D.N, D.rowptr, D.col, D.val, S, D.Q, dot, sd);
+  }
+  if (dot && (int)threadIdx.x < D.N) part[(int64_t)t * NB + threadIdx.x] = sd[threadIdx.x];
+}
+
+// Sum over the tiles of problem p of nv partial values per tile (stride
+// `stride` per tile), in tile order; one block; result in out[0..nv).
+__device__ void sum_tiles(const double* __restrict__ part, int tile0, int ntiles, int stride, int nv, double* out) {
+  constexpr int CH = 16;
+  __shared__ double ws[BS / 64][CH];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int v0 = 0; v0 < nv; v0 += CH) {
+    int nc = nv - v0 < CH ? nv - v0 : CH;
+    double acc[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) acc[q] = 0.0;
+    for (int b = threadIdx.x; b < ntiles; b += BS) {
+      const double* pp = part + (int64_t)(tile0 + b) * stride + v0;
+#pragma unroll
+      for (int q = 0; q < CH; ++q)
+        if (q < nc) acc[q] += pp[q];
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      double v = wsum(acc[q]);
+      if (lane == 0) ws[wid][q] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+      int q = threadIdx.x;
+      out[v0 + q] = (ws[0][q] + ws[1][q]) + (ws[2][q] + ws[3][q]);
+    }
+    __syncthreads();
+  }
+}
+
+// One block per problem: alpha_c = rz_c / (p.q)_c on active columns.
+template <typename T>
+__global__ void __launch_bounds__(BS) kb_alpha(const BProb<T>* __restrict__ probs, int NB,
+                                               const double* __restrict__ part, double* __restrict__ bs,
+                                               int32_t* __restrict__ flags, int K) {
+  const int p = blockIdx.x;
+  if (flags[p] == 0) return;
+  __shared__ double pq[MLC_MAX_ORBITALS];
+  const BProb<T> D = probs[p];
+  sum_tiles(part, D.tile0, D.ntiles, NB, D.N, pq);
+  for (int c = threadIdx.x; c < D.N; c += BS) {
+    double* act = sc(bs, p, NB, 3) + c;
+    double a = 0.0;
+    if (*act != 0.0) {
+      if (pq[c] > 0.0) {
+        a = sc(bs, p, NB, 0)[c] / pq[c];
+      } else {
+        *act = 0.0;
+        flags[K] = 1;
+      }
+    }
+    sc(bs, p, NB, 5)[c] = a;
+  }
+}
+
+// X += alpha P, R -= alpha Q over a tile; partials of r.Dr and r.r.
+template <typename T>
+__global__ void __launch_bounds__(BS) kb_update(const BProb<T>* __restrict__ probs, const int32_t* __restrict__ tile_prob,
+                                                int TR, int NB, const double* __restrict__ bs,
+                                                const int32_t* __restrict__ flags, double* __restrict__ part) {
+  __shared__ double sd[BS];
+  const int t = blockIdx.x;
+  const int p = tile_prob[t];
+  if (flags[p] == 0) return;
+  const BProb<T> D = probs[p];
+  const int N = D.N;
+  const int64_t r0 = (int64_t)(t - D.tile0) * TR;
+  const int64_t r1 = r0 + TR < D.n ? r0 + TR : D.n;
+  double v0 = 0.0, v1 = 0.0;
+  if (N <= BS) {
+    const int R = BS / N;
+    const int rl = threadIdx.x / N, c = threadIdx.x - rl * N;
+    const T a = rl < R ? (T)sc(bs, p, NB, 5)[c] : T(0);
+    for (int64_t rb = r0; rb < r1; rb += R) {
+      int64_t r = rb + rl;
+      if (rl < R && r < r1) {
+        int64_t i = r * N + c;
+        T x = D.X[i] + a * D.P[i];
+        T rr = D.R[i] - a * D.Q[i];
+        D.X[i] = x;
+        D.R[i] = rr;
+        v0 += (double)rr * (double)D.dinv[r] * (double)rr;
+        v1 += (double)rr * (double)rr;
+      }
+    }
+    sd[threadIdx.x] = rl < R ? v0 : 0.0;
+    reduce_rc(sd, R, N);
+    if ((int)threadIdx.x < N) part[(int64_t)t * 3 * NB + threadIdx.x] = sd[threadIdx.x];
+    __syncthreads();
+    sd[threadIdx.x] = rl < R ? v1 : 0.0;
+    reduce_rc(sd, R, N);
+    if ((int)threadIdx.x < N) part[(int64_t)t * 3 * NB + NB + threadIdx.x] = sd[threadIdx.x];
+  }
+}
+
+// One block per problem: beta, convergence ||r||^2 <= rtol^2 ||b||^2, counts.
+template <typename T>
+__global__ void __launch_bounds__(BS) kb_beta(const BProb<T>* __restrict__ probs, int NB,
+                                              const double* __restrict__ part, double* __restrict__ bs,
+                                              int32_t* __restrict__ flags, double rtol2) {
+  const int p = blockIdx.x;
+  if (flags[p] == 0) return;
+  __shared__ double s2[2 * MLC_MAX_ORBITALS];
+  __shared__ int cnt;
+  const BProb<T> D = probs[p];
+  const int N = D.N;
+  // the two partial sets (r.Dr, r.r) sit at offsets 0 and NB of each tile row
+  sum_tiles(part, D.tile0, D.ntiles, 3 * NB, N, s2);
+  sum_tiles(part + NB, D.tile0, D.ntiles, 3 * NB, N, s2 + MLC_MAX_ORBITALS);
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < N; c += BS) {
+    double* act = sc(bs, p, NB, 3) + c;
+    bool a = *act != 0.0;
+    double rzn = s2[c], rr = s2[MLC_MAX_ORBITALS + c];
+    double* rz = sc(bs, p, NB, 0) + c;
+    sc(bs, p, NB, 6)[c] = a ? rzn / *rz : 0.0;
+    if (a) {
+      *rz = rzn;
+      sc(bs, p, NB, 1)[c] = rr;
+      sc(bs, p, NB, 4)[c] += 1.0;
+    }
+    bool still = a && rr > rtol2 * sc(bs, p, NB, 2)[c];
+    *act = still ? 1.0 : 0.0;
+    if (still) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) flags[p] = cnt;
+}
+
+// P = Dinv R + beta P over a tile.
+template <typename T>
+__global__ void __launch_bounds__(BS) kb_direction(const BProb<T>* __restrict__ probs,
+                                                   const int32_t* __restrict__ tile_prob, int TR, int NB,
+                                                   const double* __restrict__ bs, const int32_t* __restrict__ flags) {
+  const int t = blockIdx.x;
+  const int p = tile_prob[t];
+  if (flags[p] == 0) return;
+  __shared__ T beta[MLC_MAX_ORBITALS];
+  const BProb<T> D = probs[p];
+  const int N = D.N;
+  for (int c = threadIdx.x; c < N; c += BS) beta[c] = (T)sc(bs, p, NB, 6)[c];
+  __syncthreads();
+  const int64_t r0 = (int64_t)(t - D.tile0) * TR;
+  const int64_t r1 = r0 + TR < D.n ? r0 + TR : D.n;
+  for (int64_t i = r0 * N + threadIdx.x; i < r1 * N; i += BS) {
+    int64_t r = i / N;
+    int c = (int)(i - r * N);
+    D.P[i] = D.dinv[r] * D.R[i] + beta[c] * D.P[i];
+  }
+}
+
+// CG start over a tile: R = B - Q (Q = A X from a mode-1 SpMM), P = Dinv R;
+// partials of r.Dr, r.r, b.b.
+template <typename T>
+__global__ void __launch_bounds__(BS) kb_init(const BProb<T>* __restrict__ probs, const int32_t* __restrict__ tile_prob,
+                                              int TR, int NB, double* __restrict__ part) {
+  __shared__ double sd[BS];
+  const int t = blockIdx.x;
+  const int p = tile_prob[t];
+  const BProb<T> D = probs[p];
+  const int N = D.N;
+  const int64_t r0 = (int64_t)(t - D.tile0) * TR;
+  const int64_t r1 = r0 + TR < D.n ? r0 + TR : D.n;
+  const int R = BS / N;
+  const int rl = threadIdx.x / N, c = threadIdx.x - rl * N;
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int64_t rb = r0; rb < r1; rb += R) {
+    int64_t r = rb + rl;
+    if (rl < R && r < r1) {
+      int64_t i = r * N + c;
+      T b = D.B[i];
+      T rr = b - D.Q[i];
+      T z = D.dinv[r] * rr;
+      D.R[i] = rr;
+      D.P[i] = z;
+      v[0] += (double)rr * (double)z;
+      v[1] += (double)rr * (double)rr;
+      v[2] += (double)b * (double)b;
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    __syncthreads();
+    sd[threadIdx.x] = rl < R ? v[k] : 0.0;
+    reduce_rc(sd, R, N);
+    if ((int)threadIdx.x < N) part[(int64_t)t * 3 * NB + k * NB + threadIdx.x] = sd[threadIdx.x];
+  }
+}
+
+// One block per problem: start scalars; a column is active when
+// ||r||^2 > rtol^2 ||b||^2 and, with mask_bs, when it is active there.
+template <typename T>
+__global__ void __launch_bounds__(BS) kb_start(const BProb<T>* __restrict__ probs, int NB,
+                                               const double* __restrict__ part, double* __restrict__ bs,
+                                               const double* __restrict__ mask_bs, int32_t* __restrict__ flags,
+                                               double rtol2) {
+  const int p = blockIdx.x;
+  __shared__ double s3[3 * MLC_MAX_ORBITALS];
+  __shared__ int cnt;
+  const BProb<T> D = probs[p];
+  const int N = D.N;
+  for (int k = 0; k < 3; ++k)
+    sum_tiles(part + k * NB, D.tile0, D.ntiles, 3 * NB, N, s3 + k * MLC_MAX_ORBITALS);
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < N; c += BS) {
+    double rz = s3[c], rr = s3[MLC_MAX_ORBITALS + c], bb = s3[2 * MLC_MAX_ORBITALS + c];
+    sc(bs, p, NB, 0)[c] = rz;
+    sc(bs, p, NB, 1)[c] = rr;
+    sc(bs, p, NB, 2)[c] = bb;
+    sc(bs, p, NB, 4)[c] = 0.0;
+    bool act = rr > rtol2 * bb;
+    if (mask_bs) act = act && sc(mask_bs, p, NB, 3)[c] != 0.0;
+    sc(bs, p, NB, 3)[c] = act ? 1.0 : 0.0;
+    if (act) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) flags[p] = cnt;
+}
+
+// Iterative refinement helpers over a tile: op 0: B32 = R64, X32 = 0;
+// op 1: X64 += X32.
+__global__ void __launch_bounds__(BS) kb_ir(const BProb<double>* __restrict__ p64, const BProb<float>* __restrict__ p32,
+                                            const int32_t* __restrict__ tile_prob, int TR, int op) {
+  const int t = blockIdx.x;
+  const int p = tile_prob[t];
+  const BProb<double> D = p64[p];
+  const BProb<float> F = p32[p];
+  const int N = D.N;
+  const int64_t r0 = (int64_t)(t - D.tile0) * TR;
+  const int64_t r1 = r0 + TR < D.n ? r0 + TR : D.n;
+  for (int64_t i = r0 * N + threadIdx.x; i < r1 * N; i += BS) {
+    if (op == 0) {
+      const_cast<float*>(F.B)[i] = (float)D.R[i];
+      F.X[i] = 0.0f;
+    } else {
+      D.X[i] += (double)F.X[i];
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_b_spmm(hipStream_t s, const BProb<T>* probs, const int32_t* tile_prob, int ntiles, int TR, int G, int NB,
+                   int mode, double* part, const int32_t* flags) {
+  switch (G) {
+    case 2:
+      hipLaunchKernelGGL((kb_spmm<2, T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, mode, part, flags);
+      break;
+    case 8:
+      hipLaunchKernelGGL((kb_spmm<8, T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, mode, part, flags);
+      break;
+    default:
+      hipLaunchKernelGGL((kb_spmm<4, T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, mode, part, flags);
+  }
+}
+
+template <typename T>
+void launch_b_iteration(hipStream_t s, const BProb<T>* probs, const int32_t* tile_prob, int ntiles, int K, int TR,
+                        int G, int NB, double* part, double* bs, int32_t* flags, double rtol2) {
+  launch_b_spmm<T>(s, probs, tile_prob, ntiles, TR, G, NB, 0, part, flags);
+  hipLaunchKernelGGL((kb_alpha<T>), dim3(K), dim3(BS), 0, s, probs, NB, part, bs, flags, K);
+  hipLaunchKernelGGL((kb_update<T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, bs, flags, part);
+  hipLaunchKernelGGL((kb_beta<T>), dim3(K), dim3(BS), 0, s, probs, NB, part, bs, flags, rtol2);
+  hipLaunchKernelGGL((kb_direction<T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, bs, flags);
+}
+
+template <typename T>
+void launch_b_start(hipStream_t s, const BProb<T>* probs, const int32_t* tile_prob, int ntiles, int K, int TR, int G,
+                    int NB, double* part, double* bs, const double* mask_bs, int32_t* flags, double rtol2) {
+  launch_b_spmm<T>(s, probs, tile_prob, ntiles, TR, G, NB, 1, part, flags);
+  hipLaunchKernelGGL((kb_init<T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, part);
+  hipLaunchKernelGGL((kb_start<T>), dim3(K), dim3(BS), 0, s, probs, NB, part, bs, mask_bs, flags, rtol2);
+}
+
+void launch_b_ir(hipStream_t s, const BProb<double>* p64, const BProb<float>* p32, const int32_t* tile_prob,
+                 int ntiles, int TR, int op) {
+  hipLaunchKernelGGL(kb_ir, dim3(ntiles), dim3(BS), 0, s, p64, p32, tile_prob, TR, op);
+}
+
+template void launch_b_spmm<double>(hipStream_t, const BProb<double>*, const int32_t*, int, int, int, int, int,
+                                    double*, const int32_t*);
+template void launch_b_spmm<float>(hipStream_t, const BProb<float>*, const int32_t*, int, int, int, int, int, double*,
+                                   const int32_t*);
+template void launch_b_iteration<double>(hipStream_t, const BProb<double>*, const int32_t*, int, int, int, int, int,
+                                         double*, double*, int32_t*, double);
+template void launch_b_iteration<float>(hipStream_t, const BProb<float>*, const int32_t*, int, int, int, int, int,
+                                        double*, double*, int32_t*, double);
+template void launch_b_start<double>(hipStream_t, const BProb<double>*, const int32_t*, int, int, int, int, int,
+                                     double*, double*, const double*, int32_t*, double);
+template void launch_b_start<float>(hipStream_t, const BProb<float>*, const int32_t*, int, int, int, int, int, double*,
+                                    double*, const double*, int32_t*, double);
+
+}  // namespace mlc

@@ -1,0 +1,46 @@
+// The phases of one correction step (Algorithm 1 steps 5-7), shared by the
+// single-system step and the batched step. Not part of the ABI.
+#pragma once
+
+#include "inner.h"
+#include "mlc_internal.h"
+
+namespace mlc {
+
+struct CgRes {
+  int iters = 0;
+  int64_t iters_sum = 0;
+  double relres = 0.0;
+  bool converged = false;
+  bool breakdown = false;
+};
+
+struct StepRun {
+  mlc_ctx* c;
+  mlc_step_report r;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  double mom[16] = {};
+  double colv[2 * MLC_MAX_ORBITALS] = {};
+  double sigma = 0.0;
+  CgRes cr, pr;  // step-5 and Hartree solves
+  InnerOut io;
+  mlc_status ist = MLC_OK;
+  std::vector<double> cin, tail;
+  explicit StepRun(mlc_ctx* ctx);
+  ~StepRun();
+  StepRun(const StepRun&) = delete;
+  StepRun& operator=(const StepRun&) = delete;
+};
+
+// Enqueue on c->stream; phase_fields and phase_gram end with device-to-host
+// copies that the caller must synchronise before phase_operators and
+// phase_inner; phase_recon likewise before phase_finish.
+mlc_status phase_fields(StepRun& S);
+mlc_status phase_operators(StepRun& S);
+mlc_status phase_after_solve(StepRun& S);
+mlc_status phase_gram(StepRun& S);
+mlc_status phase_inner(StepRun& S);
+mlc_status phase_recon(StepRun& S);
+mlc_status phase_finish(StepRun& S, mlc_step_report* rep);
+
+}  // namespace mlc

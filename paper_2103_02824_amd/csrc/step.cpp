@@ -5,8 +5,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "inner.h"
-#include "mlc_internal.h"
+#include "phases.h"
 
 namespace mlc {
 
@@ -42,14 +41,6 @@ int64_t small_len(int64_t nH, int N) { return SmallLayout(nH, N).total; }
   } while (0)
 
 namespace {
-
-struct CgRes {
-  int iters = 0;
-  int64_t iters_sum = 0;
-  double relres = 0.0;
-  bool converged = false;
-  bool breakdown = false;
-};
 
 template <typename T>
 struct CgArgs {
@@ -227,10 +218,7 @@ mlc_status solve_ir(mlc_ctx* c, int64_t n, int N, bool timed, double* spmm_ms, i
                     int* outer_iters) {
   hipStream_t s = c->stream;
   auto& d = c->d;
-  const int64_t nnz = (int64_t)c->col.size();
   double* red_upd = d.red + c->nred / 2;
-  launch_to_f32(s, nnz, d.valA, d.valA32);
-  launch_to_f32(s, n, d.dinvA, d.dinvA32);
   const double rt2 = c->opt.cg_rtol * c->opt.cg_rtol;
   int total = 0;
   int64_t total_sum = 0;
@@ -284,89 +272,103 @@ mlc_status solve_ir(mlc_ctx* c, int64_t n, int N, bool timed, double* spmm_ms, i
 
 }  // namespace
 
-mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
+// ---- phases of one correction step ---------------------------------------------
+// The single-system step runs them in order with its own CG solves; a batch runs
+// each phase for every system and replaces the two solves by batched launches.
+
+StepRun::StepRun(mlc_ctx* ctx) : c(ctx) { std::memset(&r, 0, sizeof(r)); }
+StepRun::~StepRun() {
+  for (int k = 0; k < 4; ++k)
+    if (ev[k]) (void)hipEventDestroy(ev[k]);
+}
+
+// Density, XC and V_eff at the quadrature points; multipole moments and
+// min V_eff copied to the host (the caller synchronises before phase_operators).
+mlc_status phase_fields(StepRun& S) {
+  mlc_ctx* c = S.c;
   auto& d = c->d;
   hipStream_t s = c->stream;
-  const int64_t n = c->n, nt = c->nt, nH = c->nH, nv = c->nv, cnt = c->cnt;
-  const int N = c->N;
-  SmallLayout L(nH, N);
-  mlc_step_report r;
-  std::memset(&r, 0, sizeof(r));
-  bool timed = c->opt.time_kernels != 0;
-  hipEvent_t ev[4];
-  for (int k = 0; k < 4; ++k) HIPCHK(hipEventCreate(&ev[k]));
-  struct EvGuard {
-    hipEvent_t* e;
-    ~EvGuard() {
-      for (int k = 0; k < 4; ++k) (void)hipEventDestroy(e[k]);
-    }
-  } guard{ev};
-  HIPCHK(hipEventRecord(ev[0], s));
-
-  // ---- density, XC, V_eff at quadrature points; multipole moments ----------------
-  const int nqb = qp_blocks(nt);
-  launch_qp_fields(s, nt, d.tets, d.v2d, d.Phi, N, d.occ, d.w, d.vext, d.geo, d.qpx, c->xc, c->xalpha, d.vxc,
+  SmallLayout L(c->nH, c->N);
+  for (int k = 0; k < 4; ++k) HIPCHK(hipEventCreate(&S.ev[k]));
+  HIPCHK(hipEventRecord(S.ev[0], s));
+  launch_qp_fields(s, c->nt, d.tets, d.v2d, d.Phi, c->N, d.occ, d.w, d.vext, d.geo, d.qpx, c->xc, c->xalpha, d.vxc,
                    d.exc, d.veff, d.rho, d.red);
-  launch_reduce_rows(s, d.red, nqb, nmom(), 1, d.small + L.mom);
-  double mom[16];
-  HIPCHK(hipMemcpyAsync(mom, d.small + L.mom, sizeof(double) * nmom(), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const double sigma = c->opt.shift ? c->opt.sigma0 - mom[nmom() - 1] : 0.0;
-  c->last_sigma = sigma;
+  launch_reduce_rows(s, d.red, qp_blocks(c->nt), nmom(), 1, d.small + L.mom);
+  HIPCHK(hipMemcpyAsync(S.mom, d.small + L.mom, sizeof(double) * nmom(), hipMemcpyDeviceToHost, s));
+  return MLC_OK;
+}
 
-  // ---- multipole Dirichlet data g (remark after Algorithm 3) -------------------
+// Boundary data g, the operators A + sigma M and A_fix, the right-hand sides
+// B = (lambda_i + sigma) M phi_i and the initial iterate X = Phi (step 5).
+mlc_status phase_operators(StepRun& S) {
+  mlc_ctx* c = S.c;
+  auto& d = c->d;
+  hipStream_t s = c->stream;
+  const int64_t n = c->n, nt = c->nt, nv = c->nv;
+  const int N = c->N;
+  SmallLayout L(c->nH, N);
+  S.sigma = c->opt.shift ? c->opt.sigma0 - S.mom[nmom() - 1] : 0.0;
+  c->last_sigma = S.sigma;
+  // multipole Dirichlet data g (remark after Algorithm 3)
   HIPCHK(hipMemsetAsync(d.g, 0, sizeof(double) * nv, s));
-  if (c->hartree && mom[0] > 0.0) launch_boundary_g(s, (int64_t)c->bverts.size(), d.bverts, d.xyz, d.small + L.mom, d.g);
+  if (c->hartree && S.mom[0] > 0.0)
+    launch_boundary_g(s, (int64_t)c->bverts.size(), d.bverts, d.xyz, d.small + L.mom, d.g);
   // V_ext + V_xc + g at the quadrature points (A_fix of the inner problems)
   launch_field(s, nt, d.tets, d.g, d.v2d, nullptr, d.vext, d.vxc, d.fld);
-  // ---- operators: A + sigma M (step 5) and A_fix -------------------------------
   const int64_t nnz = (int64_t)c->col.size();
-  launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 0.5, d.veff, sigma, d.valA,
+  launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 0.5, d.veff, S.sigma, d.valA,
                    d.dinvA, 0.5, d.fld, d.valF);
-
-  // ---- step 5: (A + sigma M) u_i = (lambda_i + sigma) M phi_i ------------------------
-  std::vector<double> colv(2 * N);
-  for (int i = 0; i < N; ++i) colv[i] = c->lam[i] + sigma;
-  HIPCHK(hipMemcpyAsync(d.colv, colv.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+  for (int i = 0; i < N; ++i) S.colv[i] = c->lam[i] + S.sigma;
+  HIPCHK(hipMemcpyAsync(d.colv, S.colv, sizeof(double) * N, hipMemcpyHostToDevice, s));
   launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr, nullptr);
   launch_scale_cols_to(s, n, N, d.Q, d.colv, d.B);
   HIPCHK(hipMemcpyAsync(d.X, d.Phi, sizeof(double) * n * N, hipMemcpyDeviceToDevice, s));
-  CgRes cr;
-  mlc_status st;
-  int outer_iters = 0;
   if (c->opt.precision == MLC_PREC_FP32_IR) {
-    st = solve_ir(c, n, N, timed, &r.t_spmm_ms, &r.n_spmm, &cr, &outer_iters);
-  } else {
-    CgArgs<double> ca{d.valA, d.dinvA, d.B, d.X, d.R, d.P, d.Q, d.scal, d.flags, nullptr};
-    st = cg<double>(c, 0, n, N, ca, c->opt.cg_rtol, c->opt.cg_maxit, timed, &r.t_spmm_ms, &r.n_spmm, &cr);
+    launch_to_f32(s, nnz, d.valA, d.valA32);
+    launch_to_f32(s, n, d.dinvA, d.dinvA32);
   }
-  r.ir_outer = outer_iters;
-  if (st != MLC_OK) return st;
-  r.cg_iters_max = cr.iters;
-  r.cg_iters_sum = (int32_t)cr.iters_sum;
-  r.cg_relres_max = cr.relres;
-  r.spmm_rows = n;
-  r.spmm_cols_sum = N;
-  if (cr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the auxiliary problems");
-  // M-normalise u_i
+  return MLC_OK;
+}
+
+// After step 5: M-normalise u_i; density of the u_i and the Hartree load
+// vector (the caller then solves K w0 = b with zero boundary values).
+mlc_status phase_after_solve(StepRun& S) {
+  mlc_ctx* c = S.c;
+  auto& d = c->d;
+  hipStream_t s = c->stream;
+  const int64_t n = c->n, nt = c->nt;
+  const int N = c->N;
+  S.r.cg_iters_max = S.cr.iters;
+  S.r.cg_iters_sum = (int32_t)S.cr.iters_sum;
+  S.r.cg_relres_max = S.cr.relres;
+  S.r.spmm_rows = n;
+  S.r.spmm_cols_sum = N;
+  if (S.cr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the auxiliary problems");
   launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.X, d.Q, nullptr, nullptr);
   launch_coldot(s, n, N, d.X, d.Q, d.red);
   launch_reduce_cols(s, N, elem_blocks(n, N), d.red, d.colv + N);
   launch_normalize_cols(s, n, N, d.colv + N, d.X);
-
-  // ---- step 6: Hartree direction w0 -------------------------------------------
-  CgRes pr;
   if (c->hartree) {
     launch_qp_density(s, nt, d.tets, d.v2d, d.X, N, d.occ, d.rhot);
     launch_load(s, n, d.adj_ptr, d.adj_tet, d.adj_loc, d.tets, d.geo, d.rhot, 4.0 * 3.14159265358979323846, d.g,
                 d.v2d, d.pb, d.lvec);
-    // warm start from the previous step's w0 (zero at bind)
-    double dummy = 0.0;
-    int64_t dn = 0;
-    CgArgs<double> pa{d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP, nullptr};
-    st = cg<double>(c, 1, n, 1, pa, c->opt.poisson_rtol, c->opt.cg_maxit, false, &dummy, &dn, &pr);
-    if (st != MLC_OK) return st;
-    if (pr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the Hartree problem");
+  }
+  return MLC_OK;
+}
+
+// Step 6 continued and Algorithm 3 step 1: M_{w0}, the Gram blocks P^T O U and
+// U^T O U, the Hartree pieces and the coarse-pattern integrals, copied to the
+// host (the caller synchronises before phase_inner).
+mlc_status phase_gram(StepRun& S) {
+  mlc_ctx* c = S.c;
+  auto& d = c->d;
+  hipStream_t s = c->stream;
+  const int64_t n = c->n, nt = c->nt, nH = c->nH, cnt = c->cnt;
+  const int N = c->N;
+  SmallLayout L(nH, N);
+  const int64_t nnz = (int64_t)c->col.size();
+  if (c->hartree) {
+    if (S.pr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the Hartree problem");
     launch_field(s, nt, d.tets, nullptr, d.v2d, d.w0, nullptr, nullptr, d.fld2);
     launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 0.0, d.fld2, 0.0, d.valW,
                      nullptr, 0.0, nullptr, nullptr);
@@ -374,12 +376,10 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
     HIPCHK(hipMemsetAsync(d.w0, 0, sizeof(double) * n, s));
     HIPCHK(hipMemsetAsync(d.lvec, 0, sizeof(double) * n, s));
     HIPCHK(hipMemsetAsync(d.fld2, 0, sizeof(double) * 4 * nt, s));
-    HIPCHK(hipMemsetAsync(d.valW, 0, sizeof(double) * c->col.size(), s));
+    HIPCHK(hipMemsetAsync(d.valW, 0, sizeof(double) * nnz, s));
   }
-  r.poisson_iters = pr.iters;
-  r.poisson_relres = pr.relres;
-
-  // ---- Algorithm 3 step 1: Gram blocks P^T O U and U^T O U --------------------------
+  S.r.poisson_iters = S.pr.iters;
+  S.r.poisson_relres = S.pr.relres;
   const double* vals[4] = {d.valF, d.valW, d.valM, d.valK};
   for (int o = 0; o < 4; ++o) {
     double* Yo = d.Y + (int64_t)o * n * N;
@@ -398,7 +398,7 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
     launch_coldot(s, n, 1, d.w0, d.lvec, d.red);
     launch_reduce_cols(s, 1, elem_blocks(n, 1), d.red, d.small + L.sc + 1);
   }
-  // ---- coarse-pattern integrals (eqs. Adef, Ah4def, rhsdef, FG) -------------------
+  // coarse-pattern integrals (eqs. Adef, Ah4def, rhsdef, FG)
   launch_coarse_ops(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.fld, d.fld2, d.cel_ops);
   launch_coarse_orb(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.v2d, d.X, N, d.cel_orb);
   c->last_small.resize(L.total);
@@ -407,10 +407,16 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   HIPCHK(hipMemcpyAsync(c->last_small.data(), d.small, sizeof(double) * L.total, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(c->last_cel_ops.data(), d.cel_ops, sizeof(double) * 40 * cnt, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(c->last_cel_orb.data(), d.cel_orb, sizeof(double) * 14 * cnt * N, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipEventRecord(ev[1], s));
-  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipEventRecord(S.ev[1], s));
+  return MLC_OK;
+}
 
-  // ---- Algorithm 2 via Algorithm 3 step 2 (host FP64) --------------------------
+// Algorithm 2 via Algorithm 3 step 2 on the host (FP64). Touches no device memory.
+mlc_status phase_inner(StepRun& S) {
+  mlc_ctx* c = S.c;
+  const int64_t nH = c->nH;
+  const int N = c->N;
+  SmallLayout L(nH, N);
   FineBlocks fb;
   const double* h = c->last_small.data();
   fb.ptF.assign(h + L.ptF, h + L.ptF + nH * N);
@@ -427,62 +433,119 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   fb.liftT = h[L.sc + 1];
   fb.cel_ops = c->last_cel_ops;
   fb.cel_orb = c->last_cel_orb;
-  InnerOut io;
-  mlc_status ist = inner_loop(c, fb, io);
-  if (ist < 0) return ist;
-  r.inner_iters = io.iters;
-  r.inner_last_diff = io.last_diff;
-  r.t_inner_ms = io.ms;
-  r.theta1 = io.theta1;
-  r.sigma = sigma;
+  S.ist = inner_loop(c, fb, S.io);
+  if (S.ist < 0) return S.ist;
+  S.r.inner_iters = S.io.iters;
+  S.r.inner_last_diff = S.io.last_diff;
+  S.r.t_inner_ms = S.io.ms;
+  S.r.theta1 = S.io.theta1;
+  S.r.sigma = S.sigma;
+  return MLC_OK;
+}
 
-  // ---- reconstruction (Algorithm 3 step 3), Hartree potential, density --------------
-  std::vector<double> cin(nH * N + nH + N);
-  std::copy(io.phiH.begin(), io.phiH.end(), cin.begin());
-  std::copy(io.wH.begin(), io.wH.end(), cin.begin() + nH * N);
-  std::copy(io.theta2.begin(), io.theta2.end(), cin.begin() + nH * N + nH);
-  HIPCHK(hipMemcpyAsync(d.coarse_in, cin.data(), sizeof(double) * cin.size(), hipMemcpyHostToDevice, s));
-  HIPCHK(hipEventRecord(ev[2], s));
+// Algorithm 3 step 3: phi_i = phi_{i,H} + theta2_i u_i, w = g + w_H + theta1 w0,
+// the density, the energy pieces and the overlaps, copied to the host.
+mlc_status phase_recon(StepRun& S) {
+  mlc_ctx* c = S.c;
+  auto& d = c->d;
+  hipStream_t s = c->stream;
+  const int64_t n = c->n, nt = c->nt, nH = c->nH, nv = c->nv;
+  const int N = c->N;
+  SmallLayout L(nH, N);
+  S.cin.assign(nH * N + nH + N, 0.0);
+  std::copy(S.io.phiH.begin(), S.io.phiH.end(), S.cin.begin());
+  std::copy(S.io.wH.begin(), S.io.wH.end(), S.cin.begin() + nH * N);
+  std::copy(S.io.theta2.begin(), S.io.theta2.end(), S.cin.begin() + nH * N + nH);
+  HIPCHK(hipMemcpyAsync(d.coarse_in, S.cin.data(), sizeof(double) * S.cin.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(S.ev[2], s));
   launch_reconstruct(s, n, N, d.Pk, d.Pw, d.coarse_in, d.coarse_in + nH * N + nH, d.X, d.Phi);
-  launch_hartree_nodal(s, nv, d.v2d, d.Pk, d.Pw, d.coarse_in + nH * N, io.theta1, d.w0, d.g, d.w);
+  launch_hartree_nodal(s, nv, d.v2d, d.Pk, d.Pw, d.coarse_in + nH * N, S.io.theta1, d.w0, d.g, d.w);
   launch_rho_nodal(s, nv, d.v2d, d.Phi, N, d.occ, d.rho_nodal);
   launch_energy(s, nt, d.tets, d.v2d, d.Phi, N, d.occ, d.w, d.vxc, d.geo, c->xc, c->xalpha, d.red);
-  launch_reduce_rows(s, d.red, nqb, 2, 0, d.small + L.sc + 2);
+  launch_reduce_rows(s, d.red, qp_blocks(nt), 2, 0, d.small + L.sc + 2);
   launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr, nullptr);
   launch_gram(s, n, N, d.Phi, d.Q, d.red);
   launch_reduce_cols(s, N * N, gram_blocks(n), d.red, d.small + L.ovl);
-  HIPCHK(hipEventRecord(ev[3], s));
-  std::vector<double> tail(L.total - L.sc);
-  HIPCHK(hipMemcpyAsync(tail.data(), d.small + L.sc, sizeof(double) * tail.size(), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  std::copy(tail.begin(), tail.end(), c->last_small.begin() + L.sc);
+  HIPCHK(hipEventRecord(S.ev[3], s));
+  S.tail.assign(L.total - L.sc, 0.0);
+  HIPCHK(hipMemcpyAsync(S.tail.data(), d.small + L.sc, sizeof(double) * S.tail.size(), hipMemcpyDeviceToHost, s));
+  return MLC_OK;
+}
+
+// After the caller synchronised: timings, energy, overlaps, state update.
+mlc_status phase_finish(StepRun& S, mlc_step_report* rep) {
+  mlc_ctx* c = S.c;
+  const int N = c->N;
+  SmallLayout L(c->nH, N);
+  std::copy(S.tail.begin(), S.tail.end(), c->last_small.begin() + L.sc);
   float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
-  r.t_fine_ms = ms;
-  HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3]));
-  r.t_recon_ms = ms;
-  double E = tail[3];
-  for (int i = 0; i < N; ++i) E += c->occ[i] * io.lam[i];
-  r.energy = E;
-  r.rho_integral = tail[2];
+  HIPCHK(hipEventElapsedTime(&ms, S.ev[0], S.ev[1]));
+  S.r.t_fine_ms = ms;
+  HIPCHK(hipEventElapsedTime(&ms, S.ev[2], S.ev[3]));
+  S.r.t_recon_ms = ms;
+  double E = S.tail[3];
+  for (int i = 0; i < N; ++i) E += c->occ[i] * S.io.lam[i];
+  S.r.energy = E;
+  S.r.rho_integral = S.tail[2];
   double mo = 0.0;
-  const double* ov = tail.data() + (L.ovl - L.sc);
+  const double* ov = S.tail.data() + (L.ovl - L.sc);
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j)
       if (i != j) mo = std::max(mo, std::fabs(ov[i * N + j]));
-  r.max_offdiag_overlap = mo;
+  S.r.max_offdiag_overlap = mo;
   for (int i = 0; i < N; ++i)
-    if (!std::isfinite(io.lam[i])) return fail(c, MLC_ERR_NONFINITE, "non-finite eigenvalue");
-  c->lam = io.lam;
-  c->last_theta2 = io.theta2;
-  c->last_phiH = io.phiH;
-  c->last_wH = io.wH;
-  c->last_theta1 = io.theta1;
+    if (!std::isfinite(S.io.lam[i])) return fail(c, MLC_ERR_NONFINITE, "non-finite eigenvalue");
+  c->lam = S.io.lam;
+  c->last_theta2 = S.io.theta2;
+  c->last_phiH = S.io.phiH;
+  c->last_wH = S.io.wH;
+  c->last_theta1 = S.io.theta1;
   c->has_step = true;
-  if (rep) *rep = r;
-  if (!cr.converged) return fail(c, MLC_ERR_NOT_CONVERGED, "CG did not reach cg_rtol within cg_maxit");
-  if (c->hartree && !pr.converged) return fail(c, MLC_ERR_NOT_CONVERGED, "Hartree CG did not converge");
-  return ist;
+  if (rep) *rep = S.r;
+  if (!S.cr.converged) return fail(c, MLC_ERR_NOT_CONVERGED, "CG did not reach cg_rtol within cg_maxit");
+  if (c->hartree && !S.pr.converged) return fail(c, MLC_ERR_NOT_CONVERGED, "Hartree CG did not converge");
+  return S.ist;
+}
+
+#define PHASE(x)                      \
+  do {                                \
+    mlc_status st_ = (x);             \
+    if (st_ != MLC_OK) return st_;    \
+  } while (0)
+
+mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
+  auto& d = c->d;
+  hipStream_t s = c->stream;
+  const int64_t n = c->n;
+  const int N = c->N;
+  const bool timed = c->opt.time_kernels != 0;
+  StepRun S(c);
+  PHASE(phase_fields(S));
+  HIPCHK(hipStreamSynchronize(s));
+  PHASE(phase_operators(S));
+  // step 5: (A + sigma M) u_i = (lambda_i + sigma) M phi_i
+  int outer_iters = 0;
+  if (c->opt.precision == MLC_PREC_FP32_IR) {
+    PHASE(solve_ir(c, n, N, timed, &S.r.t_spmm_ms, &S.r.n_spmm, &S.cr, &outer_iters));
+  } else {
+    CgArgs<double> ca{d.valA, d.dinvA, d.B, d.X, d.R, d.P, d.Q, d.scal, d.flags, nullptr};
+    PHASE(cg<double>(c, 0, n, N, ca, c->opt.cg_rtol, c->opt.cg_maxit, timed, &S.r.t_spmm_ms, &S.r.n_spmm, &S.cr));
+  }
+  S.r.ir_outer = outer_iters;
+  PHASE(phase_after_solve(S));
+  // step 6: Hartree direction w0, warm-started from the previous step's w0 (zero at bind)
+  if (c->hartree) {
+    double dummy = 0.0;
+    int64_t dn = 0;
+    CgArgs<double> pa{d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP, nullptr};
+    PHASE(cg<double>(c, 1, n, 1, pa, c->opt.poisson_rtol, c->opt.cg_maxit, false, &dummy, &dn, &S.pr));
+  }
+  PHASE(phase_gram(S));
+  HIPCHK(hipStreamSynchronize(s));
+  PHASE(phase_inner(S));
+  PHASE(phase_recon(S));
+  HIPCHK(hipStreamSynchronize(s));
+  return phase_finish(S, rep);
 }
 
 }  // namespace mlc

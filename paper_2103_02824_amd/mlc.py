@@ -29,7 +29,9 @@ PROBE_ID = {name: i for i, name in enumerate(PROBES)}
 
 EXPORTED = ["mlc_options_default", "mlc_create", "mlc_sizes", "mlc_workspace_bytes", "mlc_bind",
             "mlc_initial_state", "mlc_set_state", "mlc_correction_step", "mlc_get_results", "mlc_probe",
-            "mlc_status_string", "mlc_last_error", "mlc_destroy"]
+            "mlc_time_spmm", "mlc_status_string", "mlc_last_error", "mlc_destroy", "mlc_batch_create",
+            "mlc_batch_workspace_bytes", "mlc_batch_bind", "mlc_batch_set_shape", "mlc_batch_step",
+            "mlc_batch_last_error", "mlc_batch_destroy"]
 
 
 class MlcError(RuntimeError):
@@ -73,6 +75,17 @@ class StepReport(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class BatchReport(C.Structure):
+    _fields_ = [("n_systems", C.c_int32), ("tile_rows", C.c_int32), ("spmm_lanes", C.c_int32),
+                ("n_tiles", C.c_int32), ("cg_iters", C.c_int32), ("poisson_iters", C.c_int32),
+                ("ir_outer", C.c_int32), ("pad", C.c_int32), ("dof_orbitals", C.c_int64),
+                ("t_gpu_ms", C.c_double), ("t_solve_ms", C.c_double), ("t_poisson_ms", C.c_double),
+                ("t_inner_ms", C.c_double), ("t_recon_ms", C.c_double), ("t_tune_ms", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+
+
 def lib():
     """Load libmlc.so (raises if it has not been built)."""
     global _lib
@@ -93,12 +106,26 @@ def lib():
     L.mlc_correction_step.argtypes = [vp, P(StepReport)]
     L.mlc_get_results.argtypes = [vp, P(dbl), P(dbl), P(dbl), P(dbl)]
     L.mlc_probe.argtypes = [vp, i32, P(dbl), i64]
+    L.mlc_time_spmm.argtypes = [vp, i32, P(dbl)]
+    L.mlc_time_spmm.restype = i32
     L.mlc_status_string.argtypes = [i32]
     L.mlc_status_string.restype = C.c_char_p
     L.mlc_last_error.argtypes = [vp]
     L.mlc_last_error.restype = C.c_char_p
     L.mlc_destroy.argtypes = [vp]
     L.mlc_destroy.restype = None
+    L.mlc_batch_create.argtypes = [P(vp), i32, P(vp)]
+    L.mlc_batch_workspace_bytes.argtypes = [vp, P(C.c_size_t)]
+    L.mlc_batch_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    L.mlc_batch_set_shape.argtypes = [vp, i32, i32]
+    L.mlc_batch_step.argtypes = [vp, P(StepReport), P(BatchReport)]
+    L.mlc_batch_last_error.argtypes = [vp]
+    L.mlc_batch_last_error.restype = C.c_char_p
+    L.mlc_batch_destroy.argtypes = [vp]
+    L.mlc_batch_destroy.restype = None
+    for f in ("mlc_batch_create", "mlc_batch_workspace_bytes", "mlc_batch_bind", "mlc_batch_set_shape",
+              "mlc_batch_step"):
+        getattr(L, f).restype = i32
     for f in ("mlc_create", "mlc_sizes", "mlc_workspace_bytes", "mlc_bind", "mlc_initial_state", "mlc_set_state",
               "mlc_correction_step", "mlc_get_results", "mlc_probe"):
         getattr(L, f).restype = i32
@@ -201,9 +228,64 @@ class Context:
         self._chk(lib().mlc_probe(self.h, PROBE_ID[name], _dp(out), out.size))
         return out.reshape(shape)
 
+    def time_spmm(self, reps=50):
+        us = C.c_double()
+        self._chk(lib().mlc_time_spmm(self.h, int(reps), C.byref(us)))
+        return us.value
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             lib().mlc_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several contexts stepped together (mlc_batch_*): batched CG launches for
+    the step-5 and Hartree solves of every system, on one stream."""
+
+    def __init__(self, contexts, tile_rows=0, lanes=0):
+        import torch
+
+        L = lib()
+        self.contexts = list(contexts)
+        arr = (C.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
+        h = C.c_void_p()
+        st = L.mlc_batch_create(arr, len(self.contexts), C.byref(h))
+        if st != MLC_OK:
+            raise MlcError(st, "mlc_batch_create failed")
+        self.h = h
+        nbytes = C.c_size_t()
+        self._chk(L.mlc_batch_workspace_bytes(h, C.byref(nbytes)))
+        dev = self.contexts[0].device
+        self.workspace = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.current_stream(dev)
+        self._chk(L.mlc_batch_bind(h, C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                   C.c_void_p(self.stream.cuda_stream)))
+        if tile_rows or lanes:
+            self._chk(L.mlc_batch_set_shape(h, int(tile_rows), int(lanes)))
+
+    def _chk(self, st, allow_warn=False):
+        if st == MLC_OK or (allow_warn and st > 0):
+            return st
+        raise MlcError(st, lib().mlc_batch_last_error(self.h).decode())
+
+    def step(self, allow_warn=True):
+        reps = (StepReport * len(self.contexts))()
+        br = BatchReport()
+        st = lib().mlc_batch_step(self.h, reps, C.byref(br))
+        self._chk(st, allow_warn=allow_warn)
+        out = [r.as_dict() for r in reps]
+        return out, br.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().mlc_batch_destroy(self.h)
             self.h = C.c_void_p()
 
     def __del__(self):

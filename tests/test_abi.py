@@ -127,3 +127,32 @@ def test_calls_before_bind_fail_cleanly():
     lam = np.zeros(1)
     assert L.mlc_get_results(h, mlc._dp(lam), None, None, None) == -9
     L.mlc_destroy(h)
+
+
+def test_batch_argument_checks():
+    """mlc_batch_create rejects empty, null, duplicate and unbound contexts,
+    and mlc_batch_set_shape rejects shapes outside its lists (no GPU needed:
+    the context is created but not bound)."""
+    mlc, L = _lib()
+    S = c1_hydrogen()
+    keep = [np.ascontiguousarray(a, dtype=t) for a, t in
+            ((S.xyz, np.float64), (S.tets, np.int32), (S.cxyz, np.float64), (S.ctets, np.int32),
+             (S.R.reshape(-1, 3), np.float64), (S.Z, np.float64), (S.occupations, np.float64))]
+    xyz, tets, cxyz, ctets, R, Z, occ = keep
+    fine = mlc.Mesh(len(xyz), mlc._dp(xyz), len(tets), tets.ctypes.data_as(C.POINTER(C.c_int32)))
+    coarse = mlc.Mesh(len(cxyz), mlc._dp(cxyz), len(ctets), ctets.ctypes.data_as(C.POINTER(C.c_int32)))
+    sd = mlc.SystemDesc(len(Z), mlc._dp(R), mlc._dp(Z), S.potential, S.rc, S.omega, S.n_orbitals, mlc._dp(occ),
+                        S.xc, S.xalpha, int(S.hartree), S.lo, S.hi)
+    o = mlc.options()
+    h = C.c_void_p()
+    assert L.mlc_create(C.byref(fine), C.byref(coarse), C.byref(sd), C.byref(o), C.byref(h)) == 0
+    b = C.c_void_p()
+    two = (C.c_void_p * 2)(h.value, h.value)
+    one = (C.c_void_p * 1)(h.value)
+    assert L.mlc_batch_create(two, 2, C.byref(b)) == -1     # the same context twice
+    assert L.mlc_batch_create(one, 0, C.byref(b)) == -1     # empty
+    assert L.mlc_batch_create(None, 1, C.byref(b)) == -1    # null list
+    assert L.mlc_batch_create(one, 1, C.byref(b)) == -9     # not bound
+    assert not b.value
+    assert L.mlc_batch_set_shape(None, 128, 2) == -1
+    L.mlc_destroy(h)

@@ -212,3 +212,18 @@ def test_fp32_refinement_matches_fp64_checker(gpu, case):
     assert np.max(np.abs(lam - ref.state.lam)) < 1e-8, (lam, ref.state.lam)
     assert relerr(rho, ref.rho_nodal) < 1e-6
     ctx.close()
+
+
+def test_time_spmm_leaves_results_untouched(c1):
+    S, prob, st0, ctx = c1
+    print("case c1_hydrogen mlc_time_spmm", flush=True)
+    ctx.set_state(st0.lam, st0.Phi, st0.w)
+    ctx.correction_step()
+    before = ctx.get_results()
+    u_before = ctx.probe("U", (ctx.n_dof, ctx.N))
+    us = ctx.time_spmm(20)
+    assert 0.0 < us < 1e5
+    after = ctx.get_results()
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    assert np.array_equal(u_before, ctx.probe("U", (ctx.n_dof, ctx.N)))
