@@ -142,6 +142,8 @@ typedef struct {
   int64_t spmm_rows;          /* rows x columns processed by those launches */
   int64_t spmm_cols_sum;
   int32_t ir_outer;           /* refinement passes (precision FP32_IR)      */
+  int32_t guess_learned_cols; /* columns started from the learned guess (mlc_set_guess) */
+  double guess_resid_ratio;   /* max over columns of |b - A x0| / |b - A phi| (x0 = start used) */
 } mlc_step_report;
 
 typedef struct mlc_ctx mlc_ctx;
@@ -207,6 +209,9 @@ mlc_status mlc_get_results(mlc_ctx* ctx, double* lambda, double* phi, double* w,
  *   MLC_PROBE_PHI_H    N_H x N          final phi_{i,H} coefficients
  *   MLC_PROBE_WH       N_H + 1          final [w_H, theta1]
  *   MLC_PROBE_SIGMA    1                shift of step 5
+ *   MLC_PROBE_FEATURES n_dof x N x 6   learned-guess features (row dof, orbital)
+ *   MLC_PROBE_NN_OUT   n_dof x N       network outputs of the last guess
+ *   MLC_PROBE_GUESS_SCALE N            s_c = max |phi_c| of the last guess
  */
 enum {
   MLC_PROBE_U = 0, MLC_PROBE_W0, MLC_PROBE_G, MLC_PROBE_VXC_QP,
@@ -216,6 +221,7 @@ enum {
   MLC_PROBE_AFIX_H, MLC_PROBE_MW0_H, MLC_PROBE_M_H, MLC_PROBE_K_H,
   MLC_PROBE_AH4, MLC_PROBE_RHS, MLC_PROBE_THETA2, MLC_PROBE_PHI_H, MLC_PROBE_WH,
   MLC_PROBE_SIGMA,
+  MLC_PROBE_FEATURES, MLC_PROBE_NN_OUT, MLC_PROBE_GUESS_SCALE,
   MLC_PROBE_COUNT
 };
 mlc_status mlc_probe(mlc_ctx* ctx, int32_t which, double* out, int64_t count);
@@ -229,6 +235,66 @@ mlc_status mlc_probe(mlc_ctx* ctx, int32_t which, double* out, int64_t count);
  * the results of the last step are untouched. Requires a completed
  * correction step (MLC_ERR_STATE otherwise); reps must lie in 1..100000. */
 mlc_status mlc_time_spmm(mlc_ctx* ctx, int32_t reps, double* avg_us);
+
+/* ---- Learned initial guess of step 5 ----------------------------------------
+ * Extension of the method (the paper starts every step-5 problem from the
+ * current orbital phi_i, Algorithm 1 step 5). A network of 8833 parameters,
+ * 6 -> 64 -> 64 -> 64 -> 1 with GELU (erf form) after each hidden layer,
+ * maps per-(DoF, orbital) features to a correction direction
+ *   delta_i = s_i NN(features),  s_i = max |phi_i|,
+ *   features = [V_eff at the vertex clipped to +-50, phi/s, D^-1 (b - A phi)/s,
+ *               distances to the three nearest nuclei / 10 (box diagonal when
+ *               fewer nuclei)],
+ * with A, b, D the step-5 operator, right-hand side and diagonal. Step 5
+ * then starts from x0_i = a phi_i + b delta_i, the minimiser of the energy
+ * J(x) = 1/2 x.Ax - b.x over span{phi_i, delta_i} (a 2 x 2 solve per
+ * column), which is never farther from the solution in the A-norm than
+ * phi_i; phi_i stays the fallback where the 2 x 2 system is singular or J
+ * does not drop. Products run in BF16 on the matrix cores with FP32 accumulation;
+ * master weights, Adam moments and the loss are FP32/FP64.
+ * Parameter packing (floats): W1 (64 x 6, out x in), b1 (64), W2 (64 x 64),
+ * b2, W3 (64 x 64), b3, W4 (64), b4 (1).
+ *
+ * A network object owns no memory: mlc_nn_bind hands it a device workspace
+ * of mlc_nn_workspace_bytes (256-byte aligned) and the stream it runs on.
+ * Device pointers (x: rows x 6 floats, t and y: rows floats) stay owned by
+ * the caller. mlc_nn_forward is asynchronous on the stream; the other calls
+ * return after the device finished. mlc_nn_loss_grad: loss = mean (y - t)^2
+ * and its gradient (host array of 8833). mlc_nn_adam: one Adam step (bias
+ * corrected) with a host gradient. mlc_nn_train: `steps` Adam steps (lr,
+ * beta1 0.9, beta2 0.999, eps 1e-8) on minibatches of `batch` rows visiting
+ * the rows in a fixed scattered order (row (g * k) mod rows for sample g of
+ * the run, k coprime with rows); loss_history (host, steps floats) may be
+ * NULL. Errors: MLC_ERR_ARG (bad sizes or pointers), MLC_ERR_STATE (not bound
+ * or no parameters), MLC_ERR_NONFINITE (non-finite parameters). */
+typedef struct mlc_nn mlc_nn;
+#define MLC_NN_N_PARAMS 8833
+
+mlc_status mlc_nn_create(mlc_nn** out);
+mlc_status mlc_nn_workspace_bytes(const mlc_nn* nn, size_t* bytes);
+mlc_status mlc_nn_bind(mlc_nn* nn, void* workspace, size_t bytes, void* stream);
+mlc_status mlc_nn_set_params(mlc_nn* nn, const float* theta);
+mlc_status mlc_nn_get_params(mlc_nn* nn, float* theta);
+mlc_status mlc_nn_forward(mlc_nn* nn, const float* x, int64_t rows, float* y);
+mlc_status mlc_nn_loss_grad(mlc_nn* nn, const float* x, const float* t, int64_t rows, double* loss, float* grad);
+mlc_status mlc_nn_adam(mlc_nn* nn, const float* grad, double lr, double beta1, double beta2, double eps);
+mlc_status mlc_nn_train(mlc_nn* nn, const float* x, const float* t, int64_t rows, int32_t steps, int32_t batch,
+                        double lr, float* loss_history);
+const char* mlc_nn_last_error(const mlc_nn* nn);
+void mlc_nn_destroy(mlc_nn* nn);
+
+/* Start step 5 of this context from the network's guess (nn bound, with
+ * parameters, on the context's device; the context keeps the pointer until
+ * the next call), or from phi again with nn = NULL. */
+mlc_status mlc_set_guess(mlc_ctx* ctx, const mlc_nn* nn);
+/* Training samples: every correction step from now on appends, while room is
+ * left, the features and targets (u_i - phi_i)/s_i (u_i the step-5 solution
+ * before its normalisation) of every stride-th DoF and all orbitals to the
+ * device arrays x (capacity x 6 floats) and t (capacity floats), owned by
+ * the caller. capacity 0 switches the sink off. mlc_sample_count: rows
+ * written since the sink was set. */
+mlc_status mlc_set_sample_sink(mlc_ctx* ctx, float* x, float* t, int64_t capacity, int32_t stride);
+mlc_status mlc_sample_count(const mlc_ctx* ctx, int64_t* rows);
 
 /* ---- Batches of independent systems ---------------------------------------
  * Batching extension of steps 5-6 (the paper steps systems one at a time; its

@@ -148,3 +148,21 @@ def tiny_system(n_fine=4, n_coarse=2, box=4.0, nonlinear=True, n_orbitals=2, see
                   n_orbitals=n_orbitals, occupations=aufbau(ne, n_orbitals),
                   xc=XC_LDA if nonlinear else XC_NONE, hartree=nonlinear,
                   xyz=xyz, tets=tets, cxyz=cxyz, ctets=ctets)
+
+
+def batch_clusters(count, seed0=2000, atoms=(2, 8), h_range=(0.12, 0.24)):
+    """Uneven independent clusters for batching: system k (seed seed0 + k)
+    draws its atom count uniformly from atoms, its half-width 3 (n/4)^(1/3)
+    bohr (the 4-atom value scaled to constant density), and its mesh size
+    parameter h (h0 = kappa = h_min) uniformly from h_range, which spreads the
+    meshes over roughly 3e4-2e5 vertices; N = ceil(sum Z / 2)."""
+    out = []
+    for k in range(count):
+        seed = seed0 + k
+        rng = np.random.default_rng(seed)
+        na = int(rng.integers(atoms[0], atoms[1] + 1))
+        h = float(rng.uniform(*h_range))
+        hw = 3.0 * (na / 4.0) ** (1.0 / 3.0)
+        out.append(cluster_system(seed, n_atoms=na, half_width=hw, d_min=1.5, h0=h, kappa=h, h_min=h,
+                                  name=f"batch{k}_cluster{na}_s{seed}"))
+    return out

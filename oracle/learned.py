@@ -3,11 +3,16 @@
 TEST INFRASTRUCTURE ONLY (see the package header).
 
 The method starts each auxiliary problem of step 5 (Algorithm 1) from the
-current orbital phi_i. The extension replaces that start by
-    x0 = phi_i + s_i * NN(features),   s_i = max |phi_i| over the DoFs,
-where NN is one small network applied to every (DoF, orbital) row and
-trained on solutions the method itself produced; the plain start phi_i stays
-the fallback (per column, whichever start has the smaller residual).
+current orbital phi_i. The extension proposes a correction direction
+    delta_i = s_i * NN(features),   s_i = max |phi_i| over the DoFs,
+with NN one small network applied to every (DoF, orbital) row and trained on
+solutions the method itself produced, and starts from the best point of
+span{phi_i, delta_i} for the energy J(x) = 1/2 x^T A x - b^T x of the SPD
+step-5 problem (a 2 x 2 Galerkin solve per column): x0 = a phi_i + b delta_i.
+J(x) - J(u) = 1/2 |x - u|_A^2, so this start is never farther from the
+solution in the A-norm than phi_i itself (a = 1, b = 0 is in the span); the
+plain start phi_i stays the fallback and the judge (kept where
+J(x0) >= J(phi_i), or where the 2 x 2 system is singular).
 
 Network: 6 -> 64 -> 64 -> 64 -> 1, GELU (erf form) after each hidden layer,
 linear output. Parameters are packed in one vector, in this order:
@@ -29,7 +34,8 @@ Features of row (i, c) (DoF i, orbital c), all from the state before the
 step and the step-5 operator A = A_l + sigma M, right-hand side
 b_c = (lambda_c + sigma) M phi_c and its diagonal D:
     0  V_eff at the vertex: V_ext(x_i) + w(x_i) + V_xc(rho(x_i)),
-       rho(x_i) = sum_c f_c phi_c(x_i)^2 (nodal values)
+       rho(x_i) = sum_c f_c phi_c(x_i)^2 (nodal values), clipped to
+       [-50, 50] hartree (a bare Coulomb nucleus on a vertex is infinite)
     1  phi_ic / s_c
     2  r0_ic / s_c,  r0 = D^{-1} (b - A phi)  (Jacobi-scaled initial residual)
     3-5  distances from x_i to the three nearest nuclei, ascending, divided
@@ -144,6 +150,20 @@ class Adam:
         return self.theta
 
 
+VEFF_CLIP = 50.0
+
+
+def veff_nodal(system, pts, w, Phi):
+    """Feature 0 at the points pts (DoF coordinates): clipped V_ext + w + V_xc(rho)."""
+    from .potentials import v_ext
+    from .xc import evaluate
+    rho = (np.asarray(Phi) ** 2) @ np.asarray(system.occupations, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        v = v_ext(pts, system.R, system.Z, system.potential, system.rc, system.omega)
+    v = v + np.asarray(w) + evaluate(system.xc, rho, system.xalpha)[1]
+    return np.clip(v, -VEFF_CLIP, VEFF_CLIP)
+
+
 def nearest_distances(pts, R, diag):
     """Three smallest distances from each point to the nuclei R, ascending;
     missing ones are diag."""
@@ -179,7 +199,34 @@ def targets(U, Phi, s):
     return ((np.asarray(U) - np.asarray(Phi)) / s).reshape(-1)
 
 
-def guess(theta, F, Phi, s, bf=False):
-    """x0 = phi + s * NN(features), n x N."""
+def galerkin_start(A, B, Phi, D):
+    """Per column the minimiser of J over span{phi, delta}; returns x0, the
+    per-column flags (True where the combination is used) and the
+    coefficients (a, b)."""
+    Phi, D, B = np.asarray(Phi), np.asarray(D), np.asarray(B)
+    AP, AD = A @ Phi, A @ D
+    X = Phi.copy()
+    used = np.zeros(Phi.shape[1], dtype=bool)
+    coef = np.tile([1.0, 0.0], (Phi.shape[1], 1))
+    for c in range(Phi.shape[1]):
+        G = np.array([[Phi[:, c] @ AP[:, c], Phi[:, c] @ AD[:, c]], [D[:, c] @ AP[:, c], D[:, c] @ AD[:, c]]])
+        r = np.array([B[:, c] @ Phi[:, c], B[:, c] @ D[:, c]])
+        det = G[0, 0] * G[1, 1] - G[0, 1] * G[1, 0]
+        if not det > 1e-12 * G[0, 0] * G[1, 1]:
+            continue
+        a = (r[0] * G[1, 1] - r[1] * G[0, 1]) / det
+        b = (G[0, 0] * r[1] - G[1, 0] * r[0]) / det
+        j_phi = 0.5 * G[0, 0] - r[0]
+        j_new = 0.5 * (a * a * G[0, 0] + 2 * a * b * G[0, 1] + b * b * G[1, 1]) - (a * r[0] + b * r[1])
+        if j_new < j_phi:
+            X[:, c] = a * Phi[:, c] + b * D[:, c]
+            used[c] = True
+            coef[c] = (a, b)
+    return X, used, coef
+
+
+def guess(theta, F, Phi, s, A, B, bf=False):
+    """The learned start: delta = s * NN(features), then the Galerkin start."""
     n, N = np.asarray(Phi).shape
-    return np.asarray(Phi) + forward(theta, F, bf=bf).reshape(n, N) * s
+    D = forward(theta, F, bf=bf).reshape(n, N) * s
+    return galerkin_start(A, B, Phi, D)

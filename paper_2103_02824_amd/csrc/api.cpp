@@ -104,7 +104,8 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->occ = w.take<double>(N);
   d->RZ = w.take<double>(4 * std::max<int64_t>(1, c->n_nuclei));
   d->colv = w.take<double>(2 * N);
-  int64_t nred = std::max<int64_t>(3 * (int64_t)elem_blocks(n, (int)N) * N, 3 * (int64_t)elem_blocks(n, 1));
+  // 5 per-block column sums per orbital: the Galerkin dots of the learned start (the most of any user)
+  int64_t nred = std::max<int64_t>(5 * (int64_t)elem_blocks(n, (int)N) * N, 3 * (int64_t)elem_blocks(n, 1));
   nred = std::max<int64_t>(nred, 2 * (int64_t)cg_max_blocks() * 3 * std::max<int64_t>(N, 1));
   nred = std::max<int64_t>(nred, (int64_t)qp_blocks(nt) * 16);
   nred = std::max<int64_t>(nred, (int64_t)gram_blocks(n) * N * N);
@@ -125,6 +126,13 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   }
   d->scal32 = w.take<double>(10 * N);
   d->flags32 = w.take<int32_t>(8);
+  // learned initial guess: features, network outputs, column scales, choices
+  d->F = w.take<float>(6 * n * N);
+  d->Ynn = w.take<float>(n * N);
+  d->gscale = w.take<double>(N);
+  d->gsel = w.take<double>(4 * N);
+  d->gdots = w.take<double>(5 * N);
+  d->d2v = w.take<int32_t>(n);
   return w.off + 256;
 }
 
@@ -181,6 +189,7 @@ mlc_status upload_and_init(mlc_ctx* c) {
   HIPCHK(up(s, d.cgeo, c->cgeo));
   HIPCHK(up(s, d.occ, c->occ));
   HIPCHK(up(s, d.RZ, RZ));
+  HIPCHK(up(s, d.d2v, c->d2v));
   HIPCHK(hipMemsetAsync(d.w, 0, sizeof(double) * c->nv, s));
   HIPCHK(hipMemsetAsync(d.g, 0, sizeof(double) * c->nv, s));
   HIPCHK(hipMemsetAsync(d.small, 0, sizeof(double) * small_len(c->nH, c->N), s));
@@ -325,6 +334,24 @@ mlc_status probe(mlc_ctx* c, int which, double* out, int64_t count) {
     case MLC_PROBE_SIGMA:
       if ((st = need(1))) return st;
       out[0] = c->last_sigma;
+      return MLC_OK;
+    case MLC_PROBE_FEATURES:
+    case MLC_PROBE_NN_OUT: {
+      const int per = which == MLC_PROBE_FEATURES ? 6 : 1;
+      if ((st = need(n * N * per))) return st;
+      std::vector<float> h(n * N * per);
+      HIPCHK(hipMemcpyAsync(h.data(), which == MLC_PROBE_FEATURES ? d.F : d.Ynn, sizeof(float) * h.size(),
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int64_t a = 0; a < n; ++a)
+        for (int64_t j = 0; j < (int64_t)N * per; ++j)
+          out[(int64_t)c->dof_user[a] * N * per + j] = h[a * N * per + j];
+      return MLC_OK;
+    }
+    case MLC_PROBE_GUESS_SCALE:
+      if ((st = need(N))) return st;
+      HIPCHK(hipMemcpyAsync(out, d.gscale, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
       return MLC_OK;
     default:
       return fail(c, MLC_ERR_ARG, "unknown probe");
@@ -554,6 +581,30 @@ mlc_status mlc_time_spmm(mlc_ctx* c, int32_t reps, double* avg_us) {
   (void)hipEventDestroy(e1);
   if (err != hipSuccess) return hip_fail(c, err, "mlc_time_spmm");
   *avg_us = 1e3 * (double)ms / reps;
+  return MLC_OK;
+}
+
+mlc_status mlc_set_guess(mlc_ctx* c, const mlc_nn* nn) {
+  if (!c) return MLC_ERR_ARG;
+  if (nn && !nn_device(nn)) return fail(c, MLC_ERR_STATE, "network not bound or without parameters");
+  c->nn = nn;
+  return MLC_OK;
+}
+
+mlc_status mlc_set_sample_sink(mlc_ctx* c, float* x, float* t, int64_t capacity, int32_t stride) {
+  if (!c || capacity < 0) return MLC_ERR_ARG;
+  if (capacity > 0 && (!x || !t || stride < 1)) return fail(c, MLC_ERR_ARG, "sink needs x, t and stride >= 1");
+  c->sink_x = capacity > 0 ? x : nullptr;
+  c->sink_t = capacity > 0 ? t : nullptr;
+  c->sink_cap = capacity;
+  c->sink_stride = capacity > 0 ? stride : 1;
+  c->sink_count = 0;
+  return MLC_OK;
+}
+
+mlc_status mlc_sample_count(const mlc_ctx* c, int64_t* rows) {
+  if (!c || !rows) return MLC_ERR_ARG;
+  *rows = c->sink_count;
   return MLC_OK;
 }
 

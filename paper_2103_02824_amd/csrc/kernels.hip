@@ -79,31 +79,33 @@ __device__ __forceinline__ void xc_point(int kind, double xalpha, double rho, do
 }
 
 // ---------------------------------------------------------------------------
+// V_ext at a point: -sum Z erf(r/rc)/r (its r -> 0 limit -2Z/(sqrt(pi) rc)),
+// the bare -sum Z/r, or the harmonic 1/2 omega^2 |x|^2.
+__device__ __forceinline__ double vext_point(double x, double y, double z, int n_nuclei, const double* __restrict__ RZ,
+                                             int kind, double rc, double omega) {
+  if (kind == 2) return 0.5 * omega * omega * (x * x + y * y + z * z);
+  double v = 0.0;
+  for (int k = 0; k < n_nuclei; ++k) {
+    double dx = x - RZ[4 * k], dy = y - RZ[4 * k + 1], dz = z - RZ[4 * k + 2], Zk = RZ[4 * k + 3];
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (kind == 1) {
+      v -= Zk / r;
+    } else {
+      if (r < 1e-12)
+        v -= Zk * 1.12837916709551257390 / rc;
+      else
+        v -= Zk * erf(r / rc) / r;
+    }
+  }
+  return v;
+}
+
 __global__ void __launch_bounds__(TPB) k_vext(int64_t nt, const double* __restrict__ qpx, int n_nuclei,
                                               const double* __restrict__ RZ, int kind, double rc,
                                               double omega, double* __restrict__ vext) {
   int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (i >= nt * 4) return;
-  double x = qpx[3 * i], y = qpx[3 * i + 1], z = qpx[3 * i + 2];
-  double v = 0.0;
-  if (kind == 2) {
-    v = 0.5 * omega * omega * (x * x + y * y + z * z);
-  } else {
-    for (int k = 0; k < n_nuclei; ++k) {
-      double dx = x - RZ[4 * k], dy = y - RZ[4 * k + 1], dz = z - RZ[4 * k + 2], Zk = RZ[4 * k + 3];
-      double r = sqrt(dx * dx + dy * dy + dz * dz);
-      if (kind == 1) {
-        v -= Zk / r;
-      } else {
-        // -Z erf(r/rc)/r, with its r -> 0 limit -2Z/(sqrt(pi) rc)
-        if (r < 1e-12)
-          v -= Zk * 1.12837916709551257390 / rc;
-        else
-          v -= Zk * erf(r / rc) / r;
-      }
-    }
-  }
-  vext[i] = v;
+  vext[i] = vext_point(qpx[3 * i], qpx[3 * i + 1], qpx[3 * i + 2], n_nuclei, RZ, kind, rc, omega);
 }
 
 // rho(q) = sum_i f_i phi_i(q)^2 for one tet; phi from nodal interior values.
@@ -738,6 +740,192 @@ __global__ void __launch_bounds__(TPB) k_energy(int64_t nt, const int32_t* __res
 
 inline unsigned nb(int64_t work) { return (unsigned)((work + TPB - 1) / TPB); }
 
+// ---------------------------------------------------------------------------
+// Learned initial guess of step 5 (the features, the start x0 = phi + s y, the
+// per-column residual judge and the training-sample sink).
+
+// Per-block column maxima of |X| (thread (row, column) layout).
+__global__ void __launch_bounds__(TPB) k_colmax_abs(int64_t n, int N, int R, const double* __restrict__ X,
+                                                    double* __restrict__ partial) {
+  __shared__ double sd[TPB];
+  int t = threadIdx.x;
+  int rl = t / N, c = t - rl * N;
+  double v = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * R + rl; rl < R && r < n; r += (int64_t)gridDim.x * R)
+    v = fmax(v, fabs(X[r * N + c]));
+  sd[t] = v;
+  int m = R;
+  while (m > 1) {
+    int h = (m + 1) >> 1;
+    __syncthreads();
+    if (t < (m - h) * N) sd[t] = fmax(sd[t], sd[t + h * N]);
+    m = h;
+  }
+  __syncthreads();
+  if (t < N) partial[(int64_t)blockIdx.x * N + t] = sd[t];
+}
+
+// out[c] = max over blocks (1 where the column is zero).
+__global__ void __launch_bounds__(TPB) k_colmax_final(int N, int nblk, const double* __restrict__ partial,
+                                                      double* __restrict__ out) {
+  for (int c = threadIdx.x; c < N; c += TPB) {
+    double v = 0.0;
+    for (int b = 0; b < nblk; ++b) v = fmax(v, partial[(int64_t)b * N + c]);
+    out[c] = v > 0.0 ? v : 1.0;
+  }
+}
+
+// Row (i N + c): [V_eff (clipped to +-50), phi/s, D^-1 (b - A phi)/s, d1/10, d2/10, d3/10].
+__global__ void __launch_bounds__(TPB) k_features(int64_t n, int N, const int32_t* __restrict__ d2v,
+                                                  const double* __restrict__ xyz, const double* __restrict__ w,
+                                                  const double* __restrict__ Phi, const double* __restrict__ AX,
+                                                  const double* __restrict__ B, const double* __restrict__ dinv,
+                                                  const double* __restrict__ occ, const double* __restrict__ RZ,
+                                                  int n_nuclei, int pot, double rc, double omega, int xck,
+                                                  double xalpha, double diag, const double* __restrict__ scale,
+                                                  float* __restrict__ F) {
+  int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (q >= n * N) return;
+  int64_t i = q / N;
+  int c = (int)(q - i * N);
+  int v = d2v[i];
+  double x = xyz[3 * v], y = xyz[3 * v + 1], z = xyz[3 * v + 2];
+  double rho = 0.0;
+  for (int k = 0; k < N; ++k) rho += occ[k] * Phi[i * N + k] * Phi[i * N + k];
+  double eps = 0.0, vxc = 0.0;
+  xc_point(xck, xalpha, rho, &eps, &vxc);
+  double ve = vext_point(x, y, z, n_nuclei, RZ, pot, rc, omega) + w[v] + vxc;
+  ve = fmin(50.0, fmax(-50.0, ve));
+  double d1 = diag, d2 = diag, d3 = diag;
+  if (pot != 2) {
+    for (int k = 0; k < n_nuclei; ++k) {
+      double dx = x - RZ[4 * k], dy = y - RZ[4 * k + 1], dz = z - RZ[4 * k + 2];
+      double r = sqrt(dx * dx + dy * dy + dz * dz);
+      if (r < d1) {
+        d3 = d2;
+        d2 = d1;
+        d1 = r;
+      } else if (r < d2) {
+        d3 = d2;
+        d2 = r;
+      } else if (r < d3) {
+        d3 = r;
+      }
+    }
+  }
+  double sc = scale[c];
+  float* f = F + q * 6;
+  f[0] = (float)ve;
+  f[1] = (float)(Phi[q] / sc);
+  f[2] = (float)(dinv[i] * (B[q] - AX[q]) / sc);
+  f[3] = (float)(d1 / 10.0);
+  f[4] = (float)(d2 / 10.0);
+  f[5] = (float)(d3 / 10.0);
+}
+
+// delta = s * y (the network's correction direction).
+__global__ void __launch_bounds__(TPB) k_guess_delta(int64_t total, int N, const double* __restrict__ scale,
+                                                     const float* __restrict__ Y, double* __restrict__ D) {
+  int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (q >= total) return;
+  D[q] = scale[q % N] * (double)Y[q];
+}
+
+// Per-block column sums of [phi.A phi, phi.A delta, delta.A delta, b.phi, b.delta].
+__global__ void __launch_bounds__(TPB) k_guess_dots(int64_t n, int N, int R, const double* __restrict__ Phi,
+                                                    const double* __restrict__ D, const double* __restrict__ AP,
+                                                    const double* __restrict__ AD, const double* __restrict__ B,
+                                                    double* __restrict__ partial) {
+  __shared__ double sd[TPB];
+  int t = threadIdx.x;
+  int rl = t / N, c = t - rl * N;
+  int64_t r = (int64_t)blockIdx.x * R + rl;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (rl < R && r < n) {
+    int64_t q = r * N + c;
+    v[0] = Phi[q] * AP[q];
+    v[1] = Phi[q] * AD[q];
+    v[2] = D[q] * AD[q];
+    v[3] = B[q] * Phi[q];
+    v[4] = B[q] * D[q];
+  }
+  for (int k = 0; k < 5; ++k) {
+    __syncthreads();
+    sd[t] = v[k];
+    block_reduce_cols(sd, R, N);
+    if (t < N) partial[(int64_t)blockIdx.x * 5 * N + k * N + t] = sd[t];
+  }
+}
+
+// Minimiser of J(x) = 1/2 x.Ax - b.x over span{phi, delta} for column c
+// from the five sums g = [phi.A phi, phi.A delta, delta.A delta, b.phi,
+// b.delta]; (1, 0) where the 2 x 2 system is singular or J does not drop.
+__device__ __forceinline__ bool galerkin_coef(const double* g, int N, int c, double* a, double* b) {
+  double g00 = g[c], g01 = g[N + c], g11 = g[2 * N + c], r0 = g[3 * N + c], r1 = g[4 * N + c];
+  double det = g00 * g11 - g01 * g01;
+  *a = 1.0;
+  *b = 0.0;
+  if (!(det > 1e-12 * g00 * g11)) return false;
+  double aa = (r0 * g11 - r1 * g01) / det, bb = (g00 * r1 - g01 * r0) / det;
+  double jphi = 0.5 * g00 - r0;
+  double jnew = 0.5 * (aa * aa * g00 + 2.0 * aa * bb * g01 + bb * bb * g11) - (aa * r0 + bb * r1);
+  if (!(jnew < jphi)) return false;
+  *a = aa;
+  *b = bb;
+  return true;
+}
+
+// X = a phi + b delta per column (X holds delta on entry); per-block column
+// sums of |b - A x0|^2 and |b - A phi|^2 (A x0 = a A phi + b A delta).
+__global__ void __launch_bounds__(TPB) k_guess_combine(int64_t n, int N, int R, const double* __restrict__ Phi,
+                                                       const double* __restrict__ AP, const double* __restrict__ AD,
+                                                       const double* __restrict__ B, const double* __restrict__ g,
+                                                       double* __restrict__ X, double* __restrict__ used,
+                                                       double* __restrict__ partial) {
+  __shared__ double sd[TPB];
+  int t = threadIdx.x;
+  int rl = t / N, c = t - rl * N;
+  int64_t r = (int64_t)blockIdx.x * R + rl;
+  double v[2] = {0.0, 0.0};
+  if (rl < R) {
+    double a, b;
+    bool u = galerkin_coef(g, N, c, &a, &b);
+    if (blockIdx.x == 0 && rl == 0) used[c] = u ? 1.0 : 0.0;
+    if (r < n) {
+      int64_t q = r * N + c;
+      X[q] = u ? a * Phi[q] + b * X[q] : Phi[q];
+      double el = B[q] - (a * AP[q] + b * AD[q]);
+      double ep = B[q] - AP[q];
+      v[0] = el * el;
+      v[1] = ep * ep;
+    }
+  }
+  for (int k = 0; k < 2; ++k) {
+    __syncthreads();
+    sd[t] = v[k];
+    block_reduce_cols(sd, R, N);
+    if (t < N) partial[(int64_t)blockIdx.x * 2 * N + k * N + t] = sd[t];
+  }
+}
+
+// Sample rows of every stride-th DoF: features and (u - phi)/s.
+__global__ void __launch_bounds__(TPB) k_collect(int64_t n, int N, int stride, const float* __restrict__ F,
+                                                 const double* __restrict__ U, const double* __restrict__ Phi,
+                                                 const double* __restrict__ scale, int64_t offset, int64_t cap,
+                                                 float* __restrict__ ox, float* __restrict__ ot) {
+  int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;  // sample index over (selected DoF, column)
+  int64_t nsel = (n + stride - 1) / stride;
+  if (k >= nsel * N) return;
+  int64_t is = k / N;
+  int c = (int)(k - is * N);
+  int64_t i = is * stride;
+  int64_t row = offset + k;
+  if (row >= cap) return;
+  int64_t q = i * N + c;
+  for (int a = 0; a < 6; ++a) ox[row * 6 + a] = F[q * 6 + a];
+  ot[row] = (float)((U[q] - Phi[q]) / scale[c]);
+}
+
 }  // namespace
 
 // ============================================================================
@@ -842,6 +1030,40 @@ void launch_energy(hipStream_t s, int64_t nt, const int32_t* tets, const int32_t
                    double xalpha, double* partials) {
   hipLaunchKernelGGL(k_energy, dim3(nb(nt)), dim3(TPB), 0, s, nt, tets, v2d, Phi, N, occ, wnod, vxc_old, geo, xck,
                      xalpha, partials);
+}
+
+void launch_colmax_abs(hipStream_t s, int64_t n, int N, const double* X, double* partial, double* out) {
+  int R = spmm_rows_per_block(N);
+  int nbk = elem_blocks(n, N);
+  if (nbk > 1024) nbk = 1024;
+  hipLaunchKernelGGL(k_colmax_abs, dim3(nbk), dim3(TPB), 0, s, n, N, R, X, partial);
+  hipLaunchKernelGGL(k_colmax_final, dim3(1), dim3(TPB), 0, s, N, nbk, partial, out);
+}
+void launch_features(hipStream_t s, int64_t n, int N, const int32_t* d2v, const double* xyz, const double* w,
+                     const double* Phi, const double* AX, const double* B, const double* dinv, const double* occ,
+                     const double* RZ, int n_nuclei, int pot, double rc, double omega, int xck, double xalpha,
+                     double diag, const double* scale, float* F) {
+  hipLaunchKernelGGL(k_features, dim3(nb(n * N)), dim3(TPB), 0, s, n, N, d2v, xyz, w, Phi, AX, B, dinv, occ, RZ,
+                     n_nuclei, pot, rc, omega, xck, xalpha, diag, scale, F);
+}
+void launch_guess_delta(hipStream_t s, int64_t n, int N, const double* scale, const float* Y, double* D) {
+  hipLaunchKernelGGL(k_guess_delta, dim3(nb(n * N)), dim3(TPB), 0, s, n * N, N, scale, Y, D);
+}
+void launch_guess_galerkin(hipStream_t s, int64_t n, int N, const double* Phi, const double* AP, const double* AD,
+                           const double* B, double* X, double* partial, double* gdots, double* gsel) {
+  int R = spmm_rows_per_block(N);
+  int nbk = elem_blocks(n, N);
+  hipLaunchKernelGGL(k_guess_dots, dim3(nbk), dim3(TPB), 0, s, n, N, R, Phi, X, AP, AD, B, partial);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(TPB), 0, s, 5 * N, nbk, partial, gdots);
+  hipLaunchKernelGGL(k_guess_combine, dim3(nbk), dim3(TPB), 0, s, n, N, R, Phi, AP, AD, B, gdots, X, gsel, partial);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(TPB), 0, s, 2 * N, nbk, partial, gsel + N);
+}
+void launch_collect(hipStream_t s, int64_t n, int N, int stride, const float* F, const double* U,
+                    const double* Phi, const double* scale, int64_t offset, int64_t cap, float* out_x,
+                    float* out_t) {
+  int64_t nsel = (n + stride - 1) / stride;
+  hipLaunchKernelGGL(k_collect, dim3(nb(nsel * N)), dim3(TPB), 0, s, n, N, stride, F, U, Phi, scale, offset, cap,
+                     out_x, out_t);
 }
 
 }  // namespace mlc

@@ -100,6 +100,13 @@ struct Dev {
   float *X32 = nullptr, *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr, *B32 = nullptr;  // n x N
   double* scal32 = nullptr;     // 2 x 5N
   int32_t* flags32 = nullptr;   // 8
+  // learned initial guess of step 5
+  float* F = nullptr;           // n N x 6 features (row i N + c)
+  float* Ynn = nullptr;         // n N network outputs
+  double* gscale = nullptr;     // N: max |phi_c|
+  double* gsel = nullptr;       // 4N: [learned start used, |r|^2 learned, |r|^2 plain, -]
+  double* gdots = nullptr;      // 5N: Galerkin sums of the learned start
+  int32_t* d2v = nullptr;       // n: library dof -> vertex
 };
 
 struct Options {
@@ -171,9 +178,18 @@ struct mlc_ctx {
   int cg_graph_chunk[3] = {0, 0, 0};
   double cg_graph_rt2[3] = {0.0, 0.0, 0.0};
   hipStream_t cap_stream = nullptr;     // library-owned stream used only to record graphs
+  // learned initial guess of step 5 and the sample sink that feeds its training
+  const mlc_nn* nn = nullptr;
+  float* sink_x = nullptr;
+  float* sink_t = nullptr;
+  int64_t sink_cap = 0, sink_count = 0;
+  int32_t sink_stride = 1;
 };
 
 namespace mlc {
+
+struct NnDev;
+const NnDev* nn_device(const mlc_nn* nn);
 
 // ---- host helpers -----------------------------------------------------------
 mlc_status fail(mlc_ctx* c, mlc_status s, const std::string& msg);
@@ -262,6 +278,20 @@ void launch_hartree_nodal(hipStream_t s, int64_t nv, const int32_t* v2d, const i
                           const double* wH, double theta1, const double* w0, const double* g, double* w);
 void launch_rho_nodal(hipStream_t s, int64_t nv, const int32_t* v2d, const double* Phi, int N, const double* occ,
                       double* rho);
+// learned initial guess (kernels.hip)
+void launch_colmax_abs(hipStream_t s, int64_t n, int N, const double* X, double* partial, double* out);
+void launch_features(hipStream_t s, int64_t n, int N, const int32_t* d2v, const double* xyz, const double* w,
+                     const double* Phi, const double* AX, const double* B, const double* dinv, const double* occ,
+                     const double* RZ, int n_nuclei, int pot, double rc, double omega, int xck, double xalpha,
+                     double diag, const double* scale, float* F);
+void launch_guess_delta(hipStream_t s, int64_t n, int N, const double* scale, const float* Y, double* D);
+// X (= delta on entry) <- Galerkin start in span{Phi, delta}; gdots: 5N sums;
+// gsel: [used (N), |b - A x0|^2 (N), |b - A phi|^2 (N)].
+void launch_guess_galerkin(hipStream_t s, int64_t n, int N, const double* Phi, const double* AP, const double* AD,
+                           const double* B, double* X, double* partial, double* gdots, double* gsel);
+void launch_collect(hipStream_t s, int64_t n, int N, int stride, const float* F, const double* U,
+                    const double* Phi, const double* scale, int64_t offset, int64_t cap, float* out_x,
+                    float* out_t);
 void launch_energy(hipStream_t s, int64_t nt, const int32_t* tets, const int32_t* v2d, const double* Phi, int N,
                    const double* occ, const double* wnod, const double* vxc_old, const double* geo, int xck,
                    double xalpha, double* partials);

@@ -26,6 +26,8 @@ struct StepRun {
   InnerOut io;
   mlc_status ist = MLC_OK;
   std::vector<double> cin, tail;
+  bool guess = false;                     // learned start evaluated this step
+  double gsel[4 * MLC_MAX_ORBITALS] = {};  // its per-column choices and residuals
   explicit StepRun(mlc_ctx* ctx);
   ~StepRun();
   StepRun(const StepRun&) = delete;

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "nn.h"
 #include "phases.h"
 
 namespace mlc {
@@ -323,6 +324,24 @@ mlc_status phase_operators(StepRun& S) {
   launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr, nullptr);
   launch_scale_cols_to(s, n, N, d.Q, d.colv, d.B);
   HIPCHK(hipMemcpyAsync(d.X, d.Phi, sizeof(double) * n * N, hipMemcpyDeviceToDevice, s));
+  // learned start: direction delta = s NN(features), start = minimiser of the
+  // energy 1/2 x.Ax - b.x over span{phi, delta} (phi where J does not drop)
+  const NnDev* nd = c->nn ? nn_device(c->nn) : nullptr;
+  if (c->nn && !nd) return fail(c, MLC_ERR_STATE, "the guess network lost its parameters or binding");
+  const bool sink = c->sink_cap > 0 && c->sink_count < c->sink_cap;
+  S.guess = nd != nullptr;
+  if (nd || sink) {
+    launch_spmm2(s, n, N, d.rowptr, d.col, d.valA, d.Phi, d.Q, nullptr, nullptr);
+    launch_colmax_abs(s, n, N, d.Phi, d.red, d.gscale);
+    launch_features(s, n, N, d.d2v, d.xyz, d.w, d.Phi, d.Q, d.B, d.dinvA, d.occ, d.RZ, c->n_nuclei, c->potential,
+                    c->rc, c->omega, c->xc, c->xalpha, std::sqrt(3.0) * (c->hi - c->lo), d.gscale, d.F);
+  }
+  if (nd) {
+    launch_nn_forward(s, *nd, d.F, n * N, 0, 1, n * N, d.Ynn);
+    launch_guess_delta(s, n, N, d.gscale, d.Ynn, d.X);
+    launch_spmm2(s, n, N, d.rowptr, d.col, d.valA, d.X, d.R, nullptr, nullptr);
+    launch_guess_galerkin(s, n, N, d.Phi, d.Q, d.R, d.B, d.X, d.red, d.gdots, d.gsel);
+  }
   if (c->opt.precision == MLC_PREC_FP32_IR) {
     launch_to_f32(s, nnz, d.valA, d.valA32);
     launch_to_f32(s, n, d.dinvA, d.dinvA32);
@@ -344,6 +363,12 @@ mlc_status phase_after_solve(StepRun& S) {
   S.r.spmm_rows = n;
   S.r.spmm_cols_sum = N;
   if (S.cr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the auxiliary problems");
+  // training samples from this solve (before the M-normalisation)
+  if (c->sink_cap > 0 && c->sink_count < c->sink_cap) {
+    const int st = c->sink_stride;
+    launch_collect(s, n, N, st, d.F, d.X, d.Phi, d.gscale, c->sink_count, c->sink_cap, c->sink_x, c->sink_t);
+    c->sink_count = std::min<int64_t>(c->sink_cap, c->sink_count + ((n + st - 1) / st) * N);
+  }
   launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.X, d.Q, nullptr, nullptr);
   launch_coldot(s, n, N, d.X, d.Q, d.red);
   launch_reduce_cols(s, N, elem_blocks(n, N), d.red, d.colv + N);
@@ -407,6 +432,7 @@ mlc_status phase_gram(StepRun& S) {
   HIPCHK(hipMemcpyAsync(c->last_small.data(), d.small, sizeof(double) * L.total, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(c->last_cel_ops.data(), d.cel_ops, sizeof(double) * 40 * cnt, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(c->last_cel_orb.data(), d.cel_orb, sizeof(double) * 14 * cnt * N, hipMemcpyDeviceToHost, s));
+  if (S.guess) HIPCHK(hipMemcpyAsync(S.gsel, d.gsel, sizeof(double) * 4 * N, hipMemcpyDeviceToHost, s));
   HIPCHK(hipEventRecord(S.ev[1], s));
   return MLC_OK;
 }
@@ -493,6 +519,17 @@ mlc_status phase_finish(StepRun& S, mlc_step_report* rep) {
     for (int j = 0; j < N; ++j)
       if (i != j) mo = std::max(mo, std::fabs(ov[i * N + j]));
   S.r.max_offdiag_overlap = mo;
+  if (S.guess) {
+    double worst = 0.0;
+    int used = 0;
+    for (int i = 0; i < N; ++i) {
+      used += S.gsel[i] != 0.0;
+      double l = S.gsel[N + i], p = S.gsel[2 * N + i];
+      worst = std::max(worst, p > 0.0 ? std::sqrt(l / p) : (l > 0.0 ? 1e300 : 1.0));
+    }
+    S.r.guess_learned_cols = used;
+    S.r.guess_resid_ratio = worst;
+  }
   for (int i = 0; i < N; ++i)
     if (!std::isfinite(S.io.lam[i])) return fail(c, MLC_ERR_NONFINITE, "non-finite eigenvalue");
   c->lam = S.io.lam;

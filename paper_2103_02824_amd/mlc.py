@@ -24,14 +24,18 @@ STATUS = {0: "MLC_OK", -1: "MLC_ERR_ARG", -2: "MLC_ERR_MESH", -3: "MLC_ERR_NOT_N
 
 PROBES = ["U", "W0", "G", "VXC_QP", "PT_AFIX_U", "PT_MW0_U", "PT_M_U", "PT_K_U", "UT_AFIX_U", "UT_MW0_U",
           "UT_M_U", "UT_K_U", "HARTREE_D", "AFIX_H", "MW0_H", "M_H", "K_H", "AH4", "RHS", "THETA2", "PHI_H",
-          "WH", "SIGMA"]
+          "WH", "SIGMA", "FEATURES", "NN_OUT", "GUESS_SCALE"]
 PROBE_ID = {name: i for i, name in enumerate(PROBES)}
 
 EXPORTED = ["mlc_options_default", "mlc_create", "mlc_sizes", "mlc_workspace_bytes", "mlc_bind",
             "mlc_initial_state", "mlc_set_state", "mlc_correction_step", "mlc_get_results", "mlc_probe",
             "mlc_time_spmm", "mlc_status_string", "mlc_last_error", "mlc_destroy", "mlc_batch_create",
             "mlc_batch_workspace_bytes", "mlc_batch_bind", "mlc_batch_set_shape", "mlc_batch_step",
-            "mlc_batch_last_error", "mlc_batch_destroy"]
+            "mlc_batch_last_error", "mlc_batch_destroy", "mlc_nn_create", "mlc_nn_workspace_bytes", "mlc_nn_bind",
+            "mlc_nn_set_params", "mlc_nn_get_params", "mlc_nn_forward", "mlc_nn_loss_grad", "mlc_nn_adam",
+            "mlc_nn_train", "mlc_nn_last_error", "mlc_nn_destroy", "mlc_set_guess", "mlc_set_sample_sink",
+            "mlc_sample_count"]
+N_PARAMS = 8833
 
 
 class MlcError(RuntimeError):
@@ -69,7 +73,8 @@ class StepReport(C.Structure):
                 ("max_offdiag_overlap", C.c_double), ("rho_integral", C.c_double), ("energy", C.c_double),
                 ("t_fine_ms", C.c_double), ("t_inner_ms", C.c_double), ("t_recon_ms", C.c_double),
                 ("t_spmm_ms", C.c_double), ("n_spmm", C.c_int64), ("spmm_rows", C.c_int64),
-                ("spmm_cols_sum", C.c_int64), ("ir_outer", C.c_int32)]
+                ("spmm_cols_sum", C.c_int64), ("ir_outer", C.c_int32), ("guess_learned_cols", C.c_int32),
+                ("guess_resid_ratio", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -123,6 +128,27 @@ def lib():
     L.mlc_batch_last_error.restype = C.c_char_p
     L.mlc_batch_destroy.argtypes = [vp]
     L.mlc_batch_destroy.restype = None
+    fp = P(C.c_float)
+    L.mlc_nn_create.argtypes = [P(vp)]
+    L.mlc_nn_workspace_bytes.argtypes = [vp, P(C.c_size_t)]
+    L.mlc_nn_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    L.mlc_nn_set_params.argtypes = [vp, fp]
+    L.mlc_nn_get_params.argtypes = [vp, fp]
+    L.mlc_nn_forward.argtypes = [vp, vp, i64, vp]
+    L.mlc_nn_loss_grad.argtypes = [vp, vp, vp, i64, P(dbl), fp]
+    L.mlc_nn_adam.argtypes = [vp, fp, dbl, dbl, dbl, dbl]
+    L.mlc_nn_train.argtypes = [vp, vp, vp, i64, i32, i32, dbl, fp]
+    L.mlc_nn_last_error.argtypes = [vp]
+    L.mlc_nn_last_error.restype = C.c_char_p
+    L.mlc_nn_destroy.argtypes = [vp]
+    L.mlc_nn_destroy.restype = None
+    L.mlc_set_guess.argtypes = [vp, vp]
+    L.mlc_set_sample_sink.argtypes = [vp, vp, vp, i64, i32]
+    L.mlc_sample_count.argtypes = [vp, P(i64)]
+    for f in ("mlc_nn_create", "mlc_nn_workspace_bytes", "mlc_nn_bind", "mlc_nn_set_params", "mlc_nn_get_params",
+              "mlc_nn_forward", "mlc_nn_loss_grad", "mlc_nn_adam", "mlc_nn_train", "mlc_set_guess",
+              "mlc_set_sample_sink", "mlc_sample_count"):
+        getattr(L, f).restype = i32
     for f in ("mlc_batch_create", "mlc_batch_workspace_bytes", "mlc_batch_bind", "mlc_batch_set_shape",
               "mlc_batch_step"):
         getattr(L, f).restype = i32
@@ -228,6 +254,27 @@ class Context:
         self._chk(lib().mlc_probe(self.h, PROBE_ID[name], _dp(out), out.size))
         return out.reshape(shape)
 
+    def set_guess(self, nn):
+        """Start step 5 from the network's guess (None: from phi)."""
+        self._chk(lib().mlc_set_guess(self.h, nn.h if nn is not None else None))
+        self._guess = nn
+
+    def set_sample_sink(self, x, t, stride=1):
+        """x: torch float32 (capacity, 6), t: torch float32 (capacity,) on the device; None switches off."""
+        if x is None:
+            self._chk(lib().mlc_set_sample_sink(self.h, None, None, 0, 1))
+            self._sink = None
+            return
+        assert x.dtype == t.dtype and x.shape[1] == 6 and x.shape[0] == t.shape[0] and x.is_contiguous()
+        self._sink = (x, t)
+        self._chk(lib().mlc_set_sample_sink(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                            int(x.shape[0]), int(stride)))
+
+    def sample_count(self):
+        r = C.c_int64()
+        self._chk(lib().mlc_sample_count(self.h, C.byref(r)))
+        return r.value
+
     def time_spmm(self, reps=50):
         us = C.c_double()
         self._chk(lib().mlc_time_spmm(self.h, int(reps), C.byref(us)))
@@ -286,6 +333,83 @@ class Batch:
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             lib().mlc_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Network:
+    """The learned-guess network (mlc_nn_*): parameters, forward, loss and
+    gradient, Adam, training, all on the device through the library."""
+
+    def __init__(self, device="cuda:0"):
+        import torch
+
+        L = lib()
+        h = C.c_void_p()
+        st = L.mlc_nn_create(C.byref(h))
+        if st != MLC_OK:
+            raise MlcError(st, "mlc_nn_create failed")
+        self.h = h
+        nbytes = C.c_size_t()
+        self._chk(L.mlc_nn_workspace_bytes(h, C.byref(nbytes)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self._chk(L.mlc_nn_bind(h, C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                C.c_void_p(self.stream.cuda_stream)))
+
+    def _chk(self, st):
+        if st != MLC_OK:
+            raise MlcError(st, lib().mlc_nn_last_error(self.h).decode())
+
+    @staticmethod
+    def _fp(a):
+        return a.ctypes.data_as(C.POINTER(C.c_float))
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        assert th.size == N_PARAMS
+        self._chk(lib().mlc_nn_set_params(self.h, self._fp(th)))
+
+    def get_params(self):
+        th = np.zeros(N_PARAMS, dtype=np.float32)
+        self._chk(lib().mlc_nn_get_params(self.h, self._fp(th)))
+        return th
+
+    def forward(self, x):
+        """x: torch float32 (rows, 6) on the device -> torch float32 (rows,)."""
+        import torch
+        assert x.dtype == torch.float32 and x.is_contiguous() and x.shape[1] == 6
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        self._chk(lib().mlc_nn_forward(self.h, C.c_void_p(x.data_ptr()), int(x.shape[0]),
+                                       C.c_void_p(y.data_ptr())))
+        return y
+
+    def loss_grad(self, x, t):
+        g = np.zeros(N_PARAMS, dtype=np.float32)
+        loss = C.c_double()
+        self._chk(lib().mlc_nn_loss_grad(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                         int(x.shape[0]), C.byref(loss), self._fp(g)))
+        return loss.value, g
+
+    def adam(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        g = np.ascontiguousarray(grad, dtype=np.float32)
+        self._chk(lib().mlc_nn_adam(self.h, self._fp(g), lr, beta1, beta2, eps))
+
+    def train(self, x, t, steps, batch=4096, lr=1e-3):
+        hist = np.zeros(steps, dtype=np.float32)
+        self._chk(lib().mlc_nn_train(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                     int(x.shape[0]), int(steps), int(batch), float(lr), self._fp(hist)))
+        return hist
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().mlc_nn_destroy(self.h)
             self.h = C.c_void_p()
 
     def __del__(self):

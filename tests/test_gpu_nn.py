@@ -1,0 +1,207 @@
+"""The learned initial guess (mlc_nn_*, mlc_set_guess, mlc_set_sample_sink)
+vs the FP64 checker (oracle/learned.py), through the C ABI.
+
+Tolerances. The kernels round the operands of their matrix products to
+bfloat16 (unit roundoff 2^-8 = 3.9e-3) and accumulate in FP32. Against the
+checker with the same roundings (bf=True) the remaining differences are FP32
+accumulation and the rare operand that lands on the other side of a bfloat16
+rounding boundary (one ulp, 2^-8 relative, in one term of a 64-term sum):
+relative L2 error <= 2e-3 for outputs and gradients. Against the pure FP64
+network the bfloat16 roundings themselves count: <= 3e-2 (outputs) and
+<= 5e-2 (gradients), about 8 u for sums of 64 products through three layers.
+Adam is elementwise FP32: 1e-6 relative. Features are FP32 copies of FP64
+values: 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+from inputs.nn_init import init_params, random_features
+from oracle import learned as Lr
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def net(gpu):
+    from paper_2103_02824_amd import mlc
+    return mlc.Network()
+
+
+@pytest.mark.parametrize("rows", [1, 16, 1007, 70001])
+def test_forward_matches_checker(net, rows):
+    import torch
+    print(f"case nn forward rows={rows}", flush=True)
+    th = init_params(1)
+    X, _ = random_features(2, rows)
+    net.set_params(th)
+    y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    th64 = th.astype(np.float64)
+    yb = Lr.forward(th64, X.astype(np.float64), bf=True)
+    y64 = Lr.forward(th64, X.astype(np.float64))
+    assert relerr(y, yb) < 2e-3, relerr(y, yb)
+    assert relerr(y, y64) < 3e-2, relerr(y, y64)
+
+
+def test_forward_empty_is_a_no_op(net):
+    import torch
+    net.set_params(init_params(1))
+    assert net.forward(torch.zeros((0, 6), dtype=torch.float32, device="cuda")).numel() == 0
+
+
+@pytest.mark.parametrize("rows", [5, 1007, 20000])
+def test_loss_and_gradient_match_checker(net, rows):
+    import torch
+    print(f"case nn loss/grad rows={rows}", flush=True)
+    th = init_params(3)
+    X, t = random_features(4, rows)
+    net.set_params(th)
+    loss, g = net.loss_grad(torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda())
+    lb, gb = Lr.loss_grad(th.astype(np.float64), X.astype(np.float64), t.astype(np.float64), bf=True)
+    l64, g64 = Lr.loss_grad(th.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - lb) / lb < 2e-3, (loss, lb)
+    assert relerr(g, gb) < 2e-3, relerr(g, gb)
+    assert relerr(g, g64) < 5e-2, relerr(g, g64)
+    # every parameter group separately (a transposed or misplaced block fails here)
+    starts = np.cumsum([0] + [int(np.prod(s)) for s in Lr.SIZES])
+    for a, b in zip(starts[:-1], starts[1:]):
+        assert relerr(g[a:b], gb[a:b]) < 5e-3, (a, b, relerr(g[a:b], gb[a:b]))
+
+
+def test_adam_steps_match_checker(net):
+    print("case nn adam two steps", flush=True)
+    th = init_params(5)
+    rng = np.random.default_rng(6)
+    g1 = rng.normal(0, 1e-2, th.size).astype(np.float32)
+    g2 = rng.normal(0, 1e-2, th.size).astype(np.float32)
+    net.set_params(th)
+    opt = Lr.Adam(th.astype(np.float64), lr=1e-3)
+    for g in (g1, g2):
+        net.adam(g, lr=1e-3)
+        ref = opt.step(g.astype(np.float64))
+        got = net.get_params()
+        assert np.max(np.abs(got - ref) / (1.0 + np.abs(ref))) < 1e-6
+
+
+def ctx_N(S):
+    return int(S.n_orbitals)
+
+
+def _tiny():
+    from inputs.systems import tiny_system
+    return tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=True, n_orbitals=2, seed=7)
+
+
+def test_features_guess_and_sink_match_checker(net):
+    """One step with the guess attached and the sample sink on: the features
+    (V_eff, phi/s, D^-1 r0/s, distances) and the network outputs against the
+    checker, the Galerkin start and its judge against the checker's, and the
+    sink rows against the features and (u - phi)/s."""
+    import scipy.sparse.linalg as spla
+    import torch
+    from oracle.mlc import Options, Problem, fine_stage
+    from oracle.scf import initial_state
+    from paper_2103_02824_amd import mlc
+    print("case tiny2 features + guess + sink", flush=True)
+    S = _tiny()
+    prob = Problem(S)
+    st0, _ = initial_state(prob)
+    fs = fine_stage(prob, st0, Options())
+    fine = prob.fine
+    Ash = (fs["A"] + fs["sigma"] * prob.M).tocsc()
+    Phi = st0.Phi
+    veff = Lr.veff_nodal(S, fine.xyz[fine.interior], st0.w[fine.interior], Phi)
+    diag = np.sqrt(3.0) * (S.hi - S.lo)
+    F, s = Lr.features(Phi, Ash @ Phi, fs["B"], 1.0 / Ash.diagonal(), veff, fine.xyz[fine.interior], S.R, diag)
+    Uraw = spla.splu(Ash).solve(fs["B"])
+    T = Lr.targets(Uraw, Phi, s)
+    th = init_params(7, out_scale=0.02)
+    net.set_params(th)
+    ctx = mlc.Context(S, mlc.options(cg_rtol=1e-12, poisson_rtol=1e-13, inner_tol=1e-11))
+    n, N = ctx.n_dof, ctx.N
+    cap = n * N + 5
+    sx = torch.zeros((cap, 6), dtype=torch.float32, device="cuda")
+    st = torch.zeros(cap, dtype=torch.float32, device="cuda")
+    ctx.set_state(st0.lam, st0.Phi, st0.w)
+    ctx.set_guess(net)
+    ctx.set_sample_sink(sx, st, stride=1)
+    rep = ctx.correction_step()
+    assert ctx.sample_count() == n * N
+    Fg = ctx.probe("FEATURES", (n * N, 6))
+    assert relerr(Fg[:, 0], F[:, 0]) < 1e-6 and relerr(Fg[:, 1], F[:, 1]) < 1e-6
+    assert relerr(Fg[:, 3:], F[:, 3:]) < 1e-6
+    # r0 is a small difference of large terms: compare on the scale of the features
+    assert np.max(np.abs(Fg[:, 2] - F[:, 2])) < 1e-6 * max(1.0, np.abs(F[:, 2]).max()) + 1e-9
+    assert np.allclose(ctx.probe("GUESS_SCALE", (N,)), s, rtol=1e-14)
+    yb = Lr.forward(th.astype(np.float64), Fg.astype(np.float64), bf=True)
+    assert relerr(ctx.probe("NN_OUT", (n * N,)), yb) < 2e-3
+    # the Galerkin start in span{phi, s y} and its judge, against the checker
+    x0, used, coef = Lr.guess(th.astype(np.float64), Fg.astype(np.float64), Phi, s, Ash, fs["B"], bf=True)
+    assert rep["guess_learned_cols"] == int(used.sum()), (rep, used, coef)
+    ratio = np.max(np.linalg.norm(fs["B"] - Ash @ x0, axis=0) / np.linalg.norm(fs["B"] - Ash @ Phi, axis=0))
+    assert abs(rep["guess_resid_ratio"] - ratio) < 1e-3 * ratio, (rep["guess_resid_ratio"], ratio)
+    # the step still reaches the checker's solution
+    assert relerr(ctx.probe("U", (n, N)), fs["U"]) < 1e-8
+    # sink rows: the same features (bitwise, in library order) and (u - phi)/s
+    X = sx[: n * N].cpu().numpy()
+    t = st[: n * N].cpu().numpy()
+    assert not st[n * N:].any()
+    ka = np.lexsort(X.T[::-1])
+    kb = np.lexsort(Fg.astype(np.float32).T[::-1])
+    assert np.array_equal(X[ka], Fg.astype(np.float32)[kb])
+    assert relerr(t[ka], T[kb]) < 1e-6
+    ctx.close()
+
+
+def test_training_lowers_loss_and_guess_gain_on_unseen_cluster(net):
+    """Samples from the library's own steps on three small clusters of the
+    4-atom distribution, GPU training by the library's kernels, then one
+    unseen cluster stepped from the same state with and without the learned
+    start. Reported: loss decrease, CG iterations and the initial residual
+    ratio; required: the loss falls, the solves reach the same answer, and
+    CG from the learned start (never farther from the solution in the A-norm)
+    needs at most two iterations more per orbital."""
+    import torch
+    from inputs.systems import c2_small
+    from paper_2103_02824_amd import mlc
+    print("case training on c2small seeds 1-3, evaluation on seed 0", flush=True)
+    opts = dict(cg_rtol=1e-9, poisson_rtol=1e-9, inner_maxit=30, inner_tol=1e-8)
+    cap = 400000
+    sx = torch.zeros((cap, 6), dtype=torch.float32, device="cuda")
+    st = torch.zeros(cap, dtype=torch.float32, device="cuda")
+    rows = 0
+    for seed in (1, 2, 3):
+        ctx = mlc.Context(c2_small(seed), mlc.options(**opts))
+        ctx.initial_state(tol=1e-9, maxit=200)
+        ctx.set_sample_sink(sx[rows:], st[rows:], stride=1)
+        for _ in range(3):
+            ctx.correction_step()
+        rows += ctx.sample_count()
+        ctx.close()
+    assert rows > 0
+    net.set_params(init_params(11, out_scale=0.01))
+    hist = net.train(sx[:rows].contiguous(), st[:rows].contiguous(), steps=600, batch=4096, lr=2e-3)
+    first, last = float(np.mean(hist[:20])), float(np.mean(hist[-20:]))
+    print(f"training rows {rows}: loss {first:.3e} -> {last:.3e}", flush=True)
+    assert np.all(np.isfinite(hist)) and last < first
+    S = c2_small(0)
+    res = {}
+    for use in (False, True):
+        ctx = mlc.Context(S, mlc.options(**opts))
+        ctx.initial_state(tol=1e-9, maxit=200)
+        if use:
+            ctx.set_guess(net)
+        rep = ctx.correction_step()
+        res[use] = (rep, ctx.probe("U", (ctx.n_dof, ctx.N)))
+        ctx.close()
+    plain, learned = res[False][0], res[True][0]
+    print(f"eval c2small seed 0: CG iterations plain {plain['cg_iters_max']} (sum {plain['cg_iters_sum']}), "
+          f"learned {learned['cg_iters_max']} (sum {learned['cg_iters_sum']}), learned columns "
+          f"{learned['guess_learned_cols']}, residual ratio {learned['guess_resid_ratio']:.3f}", flush=True)
+    assert relerr(res[True][1], res[False][1]) < 1e-6
+    # the start is the energy minimiser over a span containing phi: never worse in the A-norm, so CG from
+    # it needs at most a few iterations more (the residual test is not the A-norm) and usually fewer
+    assert learned["cg_iters_sum"] <= plain["cg_iters_sum"] + 2 * ctx_N(S)

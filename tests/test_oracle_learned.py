@@ -150,3 +150,31 @@ def test_nearest_distances_brute_force():
         assert np.allclose(row, ds, rtol=0, atol=1e-14)
     one = Lr.nearest_distances(pts, R[:1], 99.0)
     assert np.all(one[:, 1:] == 99.0)
+
+
+def test_galerkin_start_recovers_the_solution_and_never_loses_energy():
+    """A perfect direction (delta = u - phi) gives x0 = u exactly; any
+    direction gives J(x0) <= J(phi) and J(x0) <= J at other points of the
+    span; a direction parallel to phi is rejected (singular 2 x 2)."""
+    rng = np.random.default_rng(12)
+    n = 40
+    Bm = rng.normal(size=(n, n))
+    A = Bm @ Bm.T + n * np.eye(n)
+    U = rng.normal(size=(n, 3))
+    B = A @ U
+    Phi = U + 0.1 * rng.normal(size=(n, 3))
+    X, used, coef = Lr.galerkin_start(A, B, Phi, U - Phi)
+    assert used.all() and np.allclose(X, U, rtol=0, atol=1e-10) and np.allclose(coef, [[1, 1]] * 3)
+
+    def J(x, c):
+        return 0.5 * x @ A @ x - B[:, c] @ x
+
+    D = rng.normal(size=(n, 3))
+    X, used, coef = Lr.galerkin_start(A, B, Phi, D)
+    for c in range(3):
+        assert J(X[:, c], c) <= J(Phi[:, c], c) + 1e-9
+        for da, db in rng.normal(scale=0.05, size=(5, 2)):
+            a, b = coef[c]
+            assert J(X[:, c], c) <= J((a + da) * Phi[:, c] + (b + db) * D[:, c], c) + 1e-9
+    X, used, _ = Lr.galerkin_start(A, B, Phi, 2.0 * Phi)
+    assert not used.any() and np.array_equal(X, Phi)
