@@ -12,12 +12,14 @@ plus the reconstruction, measured with HIP events on the library's stream.
 The host inner Hartree iteration (small augmented problems) is timed and
 reported separately, and so is the wall time of the whole step.
 
-The dominant kernel is the multi-column CSR SpMM inside CG. After the timed
-steps the library replays that launch back to back between two HIP events on
-its own stream (mlc_time_spmm); its algorithmic bytes per launch (matrix once,
-X once, Y once) over that mean duration give the roofline fraction. The
-measured HBM traffic per launch comes from the committed counter summary in
-profiles/ and is reported only while the kernel source matches it.
+After the timed steps the library replays each solver kernel back to back
+between two HIP events on its own stream (mlc_time_kernel): the CG SpMM and,
+with the polynomial preconditioner, the fused Chebyshev step, for step 5 and
+for the Hartree problem. The dominant kernel is the one with the largest time
+per step (mean launch time x launches per step); its algorithmic bytes per
+launch over its mean duration give the roofline fraction. The measured HBM
+traffic per launch comes from the committed counter summary in profiles/ and
+is reported only while the kernel source matches it.
 
 cpu_baseline: the CPU checker's Jacobi-PCG (SciPy sparse, FP64) run for a
 bounded number of iterations on the same-size operator, scaled to one step
@@ -52,6 +54,24 @@ def make_system(workload, seed):
     if workload == "c2":
         return c2_cluster(seed)
     raise SystemExit(f"unknown workload {workload}")
+
+
+def cheb_bytes(n, nnz, N, word=8):
+    """Algorithmic bytes of one fused Chebyshev step: the SpMM's matrix and
+    row pointers, the inverse diagonal, Z read once (gathered), R read, the
+    step difference d read and written, Z written."""
+    return (word + 4) * nnz + 4 * (n + 1) + word * n + 5 * word * n * N
+
+
+def _kernel_name(which, N, word):
+    t = "float" if word == 4 else "double"
+    if which == "cg_spmm":
+        return f"k_spmm_small<{N}, {8 if N == 1 else 4}, 1024, {t}>" if N <= 8 else f"k_spmm_wide<{t}>"
+    if which == "hartree_spmm":
+        return "k_spmm_small<1, 8, 1024, double>"
+    if which == "cheb_step":
+        return f"k_cheb_small<{N}, {8 if N == 1 else 4}, 1024, {t}>" if N <= 8 else f"k_cheb_wide<{t}>"
+    return "k_cheb_small<1, 8, 1024, double>"
 
 
 def spmm_bytes(n, nnz, N, word=8):
@@ -91,10 +111,15 @@ def main():
     ap.add_argument("--cg-rtol", type=float, default=1e-9)
     ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64",
                     help="step-5 arithmetic: plain FP64 CG, or FP32 CG inside FP64 iterative refinement")
+    ap.add_argument("--precond", choices=["jacobi", "chebyshev"], default="chebyshev",
+                    help="CG preconditioner of the step-5 and Hartree solves")
+    ap.add_argument("--cheb-degree", type=int, default=8)
+    ap.add_argument("--cheb-ratio", type=float, default=100.0)
     ap.add_argument("--inner-maxit", type=int, default=60)
     ap.add_argument("--inner-tol", type=float, default=1e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=100)
+    ap.add_argument("--cpu-iters", type=int, default=800,
+                    help="checker PCG iterations timed for cpu_baseline (about 10 s on one core)")
     ap.add_argument("--batch-systems", type=int, default=12,
                     help="--workload batch: number of uneven clusters stepped together")
     ap.add_argument("--batch-inner-maxit", type=int, default=4,
@@ -121,7 +146,9 @@ def main():
     S = make_system(args.workload, args.seed)
     prec = mlc.PREC_FP32_IR if args.precision == "fp32ir" else mlc.PREC_FP64
     opts = mlc.options(cg_rtol=args.cg_rtol, poisson_rtol=args.cg_rtol, inner_maxit=args.inner_maxit,
-                       inner_tol=args.inner_tol, time_kernels=0, precision=prec)
+                       inner_tol=args.inner_tol, time_kernels=0, precision=prec,
+                       precond=mlc.PC_CHEBYSHEV if args.precond == "chebyshev" else mlc.PC_JACOBI,
+                       cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio)
     ctx = mlc.Context(S, opts)
     n, N = ctx.n_dof, ctx.N
     nnz = None
@@ -156,22 +183,36 @@ def main():
     t_gpu = sum(r["t_fine_ms"] + r["t_recon_ms"] for r in reps) / 1e3
     value = n * N * len(reps) / t_gpu
     ms_per_step = 1e3 * t_gpu / len(reps)
-    # roofline of the dominant kernel: the SpMM of step 5's CG, replayed back to back on the
-    # library stream between two HIP events (per-launch events inside CG would add dispatch
-    # overhead to every launch)
+    # roofline of the dominant kernel: each solver kernel is replayed back to back on the library
+    # stream between two HIP events (per-launch events inside the solve would add dispatch overhead
+    # to every launch); the one with the largest time per step (mean launch time x launches per
+    # step) is the dominant kernel
     nnz = int(np.sum(_row_nnz(S, ctx)))
     word = 4 if args.precision == "fp32ir" else 8
     n_replay = 200
-    avg_us = ctx.time_spmm(n_replay)
-    bytes_launch = spmm_bytes(n, nnz, N, word)
-    achieved = bytes_launch / (avg_us * 1e-6) / 1e9
-    kname = f"k_spmm_small<{N}, {8 if N == 1 else 4}, 1024, {'float' if word == 4 else 'double'}>" if N <= 8 \
-        else f"k_spmm_wide<{'float' if word == 4 else 'double'}>"
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    cheb = args.precond == "chebyshev"
+    deg = args.cheb_degree if cheb else 1
+    it5 = float(np.mean([r["cg_iters_max"] for r in reps]))
+    itp = float(np.mean([r["poisson_iters"] for r in reps]))
+    kern = {}
+    cands = [("cg_spmm", N, word, it5 + 2), ("hartree_spmm", 1, 8, itp + 2)]
+    if cheb:
+        cands += [("cheb_step", N, word, (deg - 1) * (it5 + 1)), ("hartree_cheb_step", 1, 8, (deg - 1) * (itp + 1))]
+    for which, ncol, w, launches in cands:
+        us = ctx.time_kernel(which, n_replay)
+        nbytes = spmm_bytes(n, nnz, ncol, w) if "spmm" in which else cheb_bytes(n, nnz, ncol, w)
+        kern[which] = {"avg_launch_us": round(us, 2), "bytes_per_launch": nbytes,
+                       "achieved_GBs": round(nbytes / (us * 1e-6) / 1e9, 1), "launches_per_step": round(launches, 1),
+                       "ms_per_step": round(us * launches / 1e3, 3)}
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    kd = kern[dom]
+    kname = _kernel_name(dom, N, word)
+    achieved = kd["achieved_GBs"]
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": _traffic(kname, args.workload, args.seed, args.precision),
-            "kernel": kname + " (Y = A X over all orbitals in CG)", "bytes_per_launch": bytes_launch,
-            "avg_launch_us": round(avg_us, 2), "launches_timed": n_replay}
+            "kernel": kname, "bytes_per_launch": kd["bytes_per_launch"], "avg_launch_us": kd["avg_launch_us"],
+            "launches_timed": n_replay, "all_kernels": kern}
     cg_its = int(np.mean([r["cg_iters_max"] for r in reps]))
     cpu = None
     if not args.no_cpu_baseline:
@@ -187,6 +228,8 @@ def main():
                    "n_dof": n, "orbitals": N, "n_tets": ctx.n_tets, "nnz": nnz, "n_coarse_dof": ctx.n_coarse_dof,
                    "cg_rtol": args.cg_rtol,
                    "precision": "plain FP64" if args.precision == "fp64" else "FP32 CG + FP64 refinement",
+                   "preconditioner": "Jacobi" if args.precond == "jacobi" else
+                   f"Chebyshev degree {args.cheb_degree} over [lmax/{args.cheb_ratio:g}, lmax]",
                    "parallelism": "1 GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -257,6 +300,8 @@ def run_batch(args):
         f"orbitals {[S.n_orbitals for S in systems]}")
     base = dict(cg_rtol=args.cg_rtol, poisson_rtol=args.cg_rtol, inner_maxit=args.batch_inner_maxit,
                 inner_tol=args.inner_tol)
+    pcopt = dict(precond=mlc.PC_CHEBYSHEV if args.precond == "chebyshev" else mlc.PC_JACOBI,
+                 cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio)
     out = {}
     states = []
     # plain FP64, one system at a time
@@ -277,8 +322,10 @@ def run_batch(args):
         c.close()
     net, rows, l0, l1 = train_guess_network(mlc, args, base)
     for name, kw, learned in (("batched_fp64", {}, False),
-                              ("batched_fp32ir", dict(precision=mlc.PREC_FP32_IR), False),
-                              ("batched_fp32ir_learned", dict(precision=mlc.PREC_FP32_IR), True)):
+                              (f"batched_fp64_{args.precond}", pcopt, False),
+                              (f"batched_fp32ir_{args.precond}", dict(pcopt, precision=mlc.PREC_FP32_IR), False),
+                              (f"batched_fp32ir_{args.precond}_learned", dict(pcopt, precision=mlc.PREC_FP32_IR),
+                               True)):
         ctxs = _batch_contexts(systems, mlc, states, **dict(base, **kw))
         if learned:
             for c in ctxs:
@@ -297,14 +344,15 @@ def run_batch(args):
         b.close()
         for c in ctxs:
             c.close()
-    best = out["batched_fp32ir_learned"]["gpu_ms"]
+    best = out[f"batched_fp32ir_{args.precond}_learned"]["gpu_ms"]
     res = {
         "metric": "fine-mesh SCF correction step: DoF*orbitals/s and % HBM roofline vs plain FP64",
         "value": dof_orb / (best / 1e3), "unit": "DoF*orbitals/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": best, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64-refinement", "data": "synthetic",
         "config": {"workload": f"batch of {len(systems)} uneven seeded clusters (2-8 atoms, graded P1 meshes)",
-                   "dof_orbitals": dof_orb, "cg_rtol": args.cg_rtol, "parallelism": "1 GPU"},
+                   "dof_orbitals": dof_orb, "cg_rtol": args.cg_rtol, "parallelism": "1 GPU",
+                   "timed_path": f"batched, FP32 CG + FP64 refinement, {args.precond} preconditioner, learned start"},
         "roofline": None, "cpu_baseline": None,
         "detail": dict(out, speedup_vs_plain_fp64=out["plain_fp64_sequential"]["gpu_ms"] / best,
                        training_rows=rows, training_loss=[l0, l1], total_wall_s=time.perf_counter() - t_all),
@@ -325,8 +373,10 @@ def _traffic(kname, workload, seed, precision):
     for line in prof.read_text().splitlines():
         if line.startswith("traffic-record:"):
             rec = json.loads(line.split(":", 1)[1])
+            if rec["kernel"] != kname:
+                continue
             src = Path(ROOT) / rec["source"]
-            if rec["kernel"] != kname or hashlib.sha256(src.read_bytes()).hexdigest() != rec["source_sha256"]:
+            if hashlib.sha256(src.read_bytes()).hexdigest() != rec["source_sha256"]:
                 return None
             return rec["bytes_per_launch"]
     return None

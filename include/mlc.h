@@ -119,7 +119,18 @@ typedef struct {
                            FP64; cg_rtol applies to the FP64 residual)         */
   double ir_inner_rtol; /* FP32 inner CG tolerance relative to ||R||          */
   int32_t ir_max_outer; /* refinement passes cap                              */
+  int32_t precond;      /* CG preconditioner of the single-system solves (steps 5 and 6):
+                           MLC_PC_JACOBI, or MLC_PC_CHEBYSHEV = the Chebyshev
+                           polynomial of degree cheb_degree in D^-1 A over
+                           [lmax / cheb_ratio, lmax], lmax a Gershgorin bound
+                           (same solution, fewer iterations and reductions);
+                           a batch uses the setting of its contexts, which
+                           must agree                                          */
+  int32_t cheb_degree;  /* 2..16                                               */
+  double cheb_ratio;    /* > 1                                                 */
 } mlc_options;
+
+enum { MLC_PC_JACOBI = 0, MLC_PC_CHEBYSHEV = 1 };
 
 enum { MLC_PREC_FP64 = 0, MLC_PREC_FP32_IR = 1 };
 
@@ -226,15 +237,24 @@ enum {
 };
 mlc_status mlc_probe(mlc_ctx* ctx, int32_t which, double* out, int64_t count);
 
-/* Kernel timing for roofline accounting: replays the SpMM of step 5's CG
- * (Y = (A + sigma M) P over all N orbital columns, with the per-block P.Y
- * partials the CG consumes; FP32 values when options.precision is
- * MLC_PREC_FP32_IR) `reps` times back to back on the bound stream, between
- * two HIP events, and returns the mean duration per launch in microseconds.
- * It overwrites only CG scratch (the Q block and the partials); the state and
- * the results of the last step are untouched. Requires a completed
- * correction step (MLC_ERR_STATE otherwise); reps must lie in 1..100000. */
-mlc_status mlc_time_spmm(mlc_ctx* ctx, int32_t reps, double* avg_us);
+/* Kernel timing for roofline accounting: replays one kernel of the solves
+ * `reps` times back to back on the bound stream, between two HIP events, and
+ * returns the mean duration per launch in microseconds (dispatch gaps
+ * between the launches included):
+ *   MLC_KERNEL_CG_SPMM            step 5: Y = (A + sigma M) P over all N
+ *                                 columns with the P.Y partials CG consumes
+ *                                 (FP32 values under MLC_PREC_FP32_IR)
+ *   MLC_KERNEL_CHEB_STEP          step 5: one Chebyshev step of the polynomial
+ *                                 preconditioner (SpMM fused with the update)
+ *   MLC_KERNEL_HARTREE_SPMM       step 6: the same SpMM with K, one column
+ *   MLC_KERNEL_HARTREE_CHEB_STEP  step 6: one Chebyshev step with K
+ * It overwrites only solver scratch (Q, the Gram blocks, the partials); the
+ * state and the results of the last step are untouched. Requires a completed
+ * correction step (MLC_ERR_STATE otherwise), options.precond =
+ * MLC_PC_CHEBYSHEV for the Chebyshev kernels and a Hartree problem for the
+ * step-6 kernels (MLC_ERR_ARG otherwise); reps in 1..100000. */
+enum { MLC_KERNEL_CG_SPMM = 0, MLC_KERNEL_CHEB_STEP, MLC_KERNEL_HARTREE_SPMM, MLC_KERNEL_HARTREE_CHEB_STEP };
+mlc_status mlc_time_kernel(mlc_ctx* ctx, int32_t which, int32_t reps, double* avg_us);
 
 /* ---- Learned initial guess of step 5 ----------------------------------------
  * Extension of the method (the paper starts every step-5 problem from the
@@ -310,7 +330,8 @@ mlc_status mlc_sample_count(const mlc_ctx* ctx, int64_t* rows);
  * either instead).
  *
  * mlc_batch_create: ctxs[0..count) distinct, bound contexts with the same
- * options.precision; the batch keeps the pointers (the caller keeps the
+ * options.precision, precond, cheb_degree and cheb_ratio (MLC_ERR_ARG
+ * otherwise); the batch keeps the pointers (the caller keeps the
  * contexts alive, does not re-bind them and does not step them concurrently
  * with the batch). Systems may differ in mesh and orbital count.
  * mlc_batch_bind: device workspace of mlc_batch_workspace_bytes (256-byte

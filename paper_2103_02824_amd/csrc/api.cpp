@@ -133,6 +133,7 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->gsel = w.take<double>(4 * N);
   d->gdots = w.take<double>(5 * N);
   d->d2v = w.take<int32_t>(n);
+  d->lmax = w.take<double>(2);
   return w.off + 256;
 }
 
@@ -201,6 +202,7 @@ mlc_status upload_and_init(mlc_ctx* c) {
                    d.dinvK, 0.0, nullptr, d.valM);
   launch_assemble2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 0.0, nullptr, 1.0, d.valM,
                    nullptr, 0.0, nullptr, nullptr);
+  launch_gershgorin(s, c->n, d.rowptr, d.valK, d.dinvK, d.red, d.lmax + 1);
   launch_coarse_tri(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.cel_tri);
   c->h_tri.resize(20 * c->cnt);
   HIPCHK(hipMemcpyAsync(c->h_tri.data(), d.cel_tri, sizeof(double) * c->h_tri.size(), hipMemcpyDeviceToHost, s));
@@ -381,6 +383,9 @@ void mlc_options_default(mlc_options* o) {
   o->precision = MLC_PREC_FP64;
   o->ir_inner_rtol = 1e-4;
   o->ir_max_outer = 30;
+  o->precond = MLC_PC_JACOBI;
+  o->cheb_degree = 4;
+  o->cheb_ratio = 30.0;
 }
 
 mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys, const mlc_options* opt,
@@ -405,7 +410,10 @@ mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_sy
   if (!(c->opt.cg_rtol > 0) || c->opt.cg_maxit < 1 || c->opt.check_every < 1 || c->opt.inner_maxit < 1 ||
       c->opt.n_extra < 0 || !(c->opt.poisson_rtol > 0) ||
       (c->opt.precision != MLC_PREC_FP64 && c->opt.precision != MLC_PREC_FP32_IR) ||
-      (c->opt.precision == MLC_PREC_FP32_IR && (!(c->opt.ir_inner_rtol > 0) || c->opt.ir_max_outer < 1))) {
+      (c->opt.precision == MLC_PREC_FP32_IR && (!(c->opt.ir_inner_rtol > 0) || c->opt.ir_max_outer < 1)) ||
+      (c->opt.precond != MLC_PC_JACOBI && c->opt.precond != MLC_PC_CHEBYSHEV) ||
+      (c->opt.precond == MLC_PC_CHEBYSHEV && (c->opt.cheb_degree < 2 || c->opt.cheb_degree > 16 ||
+                                              !(c->opt.cheb_ratio > 1.0)))) {
     delete c;
     return MLC_ERR_ARG;
   }
@@ -552,25 +560,52 @@ mlc_status mlc_probe(mlc_ctx* c, int32_t which, double* out, int64_t count) {
   return probe(c, which, out, count);
 }
 
-mlc_status mlc_time_spmm(mlc_ctx* c, int32_t reps, double* avg_us) {
-  if (!c || !avg_us || reps < 1 || reps > 100000) return MLC_ERR_ARG;
+mlc_status mlc_time_kernel(mlc_ctx* c, int32_t which, int32_t reps, double* avg_us) {
+  if (!c || !avg_us || reps < 1 || reps > 100000 || which < MLC_KERNEL_CG_SPMM ||
+      which > MLC_KERNEL_HARTREE_CHEB_STEP)
+    return MLC_ERR_ARG;
   if (!c->has_step) return fail(c, MLC_ERR_STATE, "no correction step has run");
+  const bool cheb = which == MLC_KERNEL_CHEB_STEP || which == MLC_KERNEL_HARTREE_CHEB_STEP;
+  const bool hart = which >= MLC_KERNEL_HARTREE_SPMM;
+  if (cheb && c->opt.precond != MLC_PC_CHEBYSHEV) return fail(c, MLC_ERR_ARG, "no polynomial preconditioner");
+  if (hart && !c->hartree) return fail(c, MLC_ERR_ARG, "no Hartree problem");
   auto& d = c->d;
   hipStream_t s = c->stream;
   const int64_t n = c->n;
-  const int N = c->N;
+  const int N = hart ? 1 : c->N;
+  const bool f32 = !hart && c->opt.precision == MLC_PREC_FP32_IR;
+  double* rz = d.red + (int64_t)cg_max_blocks() * N;
+  float* Yf = reinterpret_cast<float*>(d.Y);
+  // one Chebyshev step = a polynomial of degree 2 (its single step is the last one)
+  PolyPC<double> pd{hart ? d.lmax + 1 : d.lmax, c->opt.cheb_ratio, 2, {d.Y, d.Y + n * N}, d.Y + 2 * n * N, rz};
+  PolyPC<float> pf{d.lmax, c->opt.cheb_ratio, 2, {Yf, Yf + n * N}, Yf + 2 * n * N, rz};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return fail(c, MLC_ERR_HIP, "hipEventCreate");
   }
+  auto one = [&]() {
+    if (hart) {
+      if (cheb)
+        launch_cheb_steps_t<double>(s, n, 1, d.rowptr, d.col, d.valK, d.dinvK, d.pr, pd, nullptr, nullptr);
+      else
+        launch_spmm2(s, n, 1, d.rowptr, d.col, d.valK, d.pp, d.pq, d.red, nullptr);
+    } else if (f32) {
+      if (cheb)
+        launch_cheb_steps_t<float>(s, n, N, d.rowptr, d.col, d.valA32, d.dinvA32, d.R32, pf, nullptr, nullptr);
+      else
+        launch_spmm2_f32(s, n, N, d.rowptr, d.col, d.valA32, d.P32, d.Q32, d.red, nullptr);
+    } else {
+      if (cheb)
+        launch_cheb_steps_t<double>(s, n, N, d.rowptr, d.col, d.valA, d.dinvA, d.R, pd, nullptr, nullptr);
+      else
+        launch_spmm2(s, n, N, d.rowptr, d.col, d.valA, d.P, d.Q, d.red, nullptr);
+    }
+  };
   hipError_t err = hipEventRecord(e0, s);
   for (int k = 0; k < reps && err == hipSuccess; ++k) {
-    if (c->opt.precision == MLC_PREC_FP32_IR)
-      launch_spmm2_f32(s, n, N, d.rowptr, d.col, d.valA32, d.P32, d.Q32, d.red, nullptr);
-    else
-      launch_spmm2(s, n, N, d.rowptr, d.col, d.valA, d.P, d.Q, d.red, nullptr);
+    one();
     err = hipGetLastError();
   }
   if (err == hipSuccess) err = hipEventRecord(e1, s);
@@ -579,7 +614,7 @@ mlc_status mlc_time_spmm(mlc_ctx* c, int32_t reps, double* avg_us) {
   if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (err != hipSuccess) return hip_fail(c, err, "mlc_time_spmm");
+  if (err != hipSuccess) return hip_fail(c, err, "mlc_time_kernel");
   *avg_us = 1e3 * (double)ms / reps;
   return MLC_OK;
 }

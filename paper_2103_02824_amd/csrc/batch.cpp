@@ -40,6 +40,7 @@ struct mlc_batch {
   int32_t* tile_prob = nullptr;  // step-5 tile table
   int32_t* tile_probP = nullptr; // Hartree tile table
   double* part = nullptr;
+  double* part_rz = nullptr;     // r.z partials of the polynomial preconditioner
   double *bsA = nullptr, *bsA32 = nullptr, *bsP = nullptr;
   int32_t *flA = nullptr, *flA32 = nullptr, *flP = nullptr;
   // graphs: 0 step-5 FP64, 1 Hartree, 2 step-5 FP32
@@ -93,6 +94,7 @@ size_t layout(mlc_batch* b, char* base) {
   b->tile_prob = cv.take<int32_t>(b->max_tiles);
   b->tile_probP = cv.take<int32_t>(b->max_tiles);
   b->part = cv.take<double>(b->max_tiles * 3 * NB);
+  b->part_rz = cv.take<double>(b->max_tiles * NB);
   b->bsA = cv.take<double>((size_t)K * 8 * NB);
   b->bsA32 = cv.take<double>((size_t)K * 8 * NB);
   b->bsP = cv.take<double>((size_t)KP * 8 * NB);
@@ -112,14 +114,20 @@ mlc_status upload_shape(mlc_batch* b, int TR) {
     mlc_ctx* c = b->ctx[s];
     auto& d = c->d;
     int nt = (int)((c->n + TR - 1) / TR);
-    BProb<double> a{d.rowptr, d.col, d.valA, d.dinvA, d.B, d.X, d.R, d.P, d.Q, c->n, c->N, (int32_t)tp.size(), nt, 0};
-    BProb<float> f{d.rowptr, d.col, d.valA32, d.dinvA32, d.B32, d.X32, d.R32, d.P32, d.Q32, c->n, c->N,
-                   (int32_t)tp.size(), nt, 0};
+    // polynomial preconditioner scratch: the context's Gram blocks, free during the solves
+    const bool pc = c->opt.precond == MLC_PC_CHEBYSHEV;
+    const int64_t nN = c->n * c->N;
+    float* Yf = reinterpret_cast<float*>(d.Y);
+    BProb<double> a{d.rowptr, d.col, d.valA, d.dinvA, d.B, d.X, d.R, d.P, d.Q,
+                    d.Y, d.Y + nN, d.Y + 2 * nN, pc ? d.lmax : nullptr, c->n, c->N, (int32_t)tp.size(), nt, 0};
+    BProb<float> f{d.rowptr, d.col, d.valA32, d.dinvA32, d.B32, d.X32, d.R32, d.P32, d.Q32,
+                   Yf, Yf + nN, Yf + 2 * nN, pc ? d.lmax : nullptr, c->n, c->N, (int32_t)tp.size(), nt, 0};
     hA.push_back(a);
     hA32.push_back(f);
     for (int k = 0; k < nt; ++k) tp.push_back(s);
     if (c->hartree) {
-      BProb<double> pp{d.rowptr, d.col, d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, c->n, 1, (int32_t)tpP.size(),
+      BProb<double> pp{d.rowptr, d.col, d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq,
+                       d.Y, d.Y + c->n, d.Y + 2 * c->n, pc ? d.lmax + 1 : nullptr, c->n, 1, (int32_t)tpP.size(),
                        nt, 0};
       hP.push_back(pp);
       for (int k = 0; k < nt; ++k) tpP.push_back(kp);
@@ -215,16 +223,23 @@ struct BRes {
 
 // Batched CG from the current X of every problem; scalars in bs, counts in fl.
 // Ns[p] = columns of problem p. Accumulates iteration counts into out.
+BPoly batch_poly(const mlc_batch* b) {
+  const mlc_options& o = b->ctx[0]->opt;
+  if (o.precond != MLC_PC_CHEBYSHEV) return BPoly{0, 1.0, nullptr};
+  return BPoly{o.cheb_degree, o.cheb_ratio, b->part_rz};
+}
+
 template <typename T>
 mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* tile_prob, int ntiles,
                const std::vector<int>& Ns, double* bs, int32_t* fl, const double* mask_bs, double rtol, int maxit,
                BRes* out) {
+  const BPoly poly = batch_poly(b);
   hipStream_t s = b->stream;
   const int K = (int)Ns.size();
   const double rt2 = rtol * rtol;
   const int NB = b->NB;
   BCHK(hipMemsetAsync(fl + K, 0, sizeof(int32_t), s));
-  launch_b_start<T>(s, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, mask_bs, fl, rt2);
+  launch_b_start<T>(s, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, mask_bs, fl, rt2, poly);
   const int every = 2 * ((std::max(1, b->ctx[0]->opt.check_every) + 1) / 2);
   const bool graph = b->ctx[0]->opt.use_graphs != 0;
   if (graph && (!b->graph[kind] || b->graph_chunk[kind] != every || b->graph_rt2[kind] != rt2)) {
@@ -233,7 +248,7 @@ mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* til
     hipGraph_t g;
     BCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < every; ++k)
-      launch_b_iteration<T>(b->cap_stream, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, fl, rt2);
+      launch_b_iteration<T>(b->cap_stream, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, fl, rt2, poly);
     BCHK(hipStreamEndCapture(b->cap_stream, &g));
     hipError_t e = hipGraphInstantiate(&b->graph[kind], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -257,7 +272,7 @@ mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* til
       BCHK(hipGraphLaunch(b->graph[kind], s));
     } else {
       for (int k = 0; k < every; ++k)
-        launch_b_iteration<T>(s, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, fl, rt2);
+        launch_b_iteration<T>(s, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, fl, rt2, poly);
     }
     it += every;
   }
@@ -289,7 +304,8 @@ mlc_status residuals(mlc_batch* b, const BProb<double>* probs, const int32_t* ti
                      std::vector<int>* active) {
   hipStream_t s = b->stream;
   const int K = (int)Ns.size(), NB = b->NB;
-  launch_b_start<double>(s, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, nullptr, fl, rtol * rtol);
+  launch_b_start<double>(s, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, nullptr, fl, rtol * rtol,
+                         BPoly{0, 1.0, nullptr});
   std::vector<double> hs((size_t)K * 8 * NB);
   std::vector<int32_t> hf(K);
   BCHK(hipMemcpyAsync(hs.data(), bs, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, s));
@@ -407,6 +423,10 @@ mlc_status mlc_batch_create(mlc_ctx* const* ctxs, int32_t count, mlc_batch** out
   for (mlc_ctx* c : b->ctx) {
     if (!c->bound) return MLC_ERR_STATE;
     if (c->opt.precision != b->prec) return MLC_ERR_ARG;
+    if (c->opt.precond != ctxs[0]->opt.precond ||
+        (c->opt.precond == MLC_PC_CHEBYSHEV &&
+         (c->opt.cheb_degree != ctxs[0]->opt.cheb_degree || c->opt.cheb_ratio != ctxs[0]->opt.cheb_ratio)))
+      return MLC_ERR_ARG;
     b->NB = std::max(b->NB, (int)c->N);
     b->KP += c->hartree ? 1 : 0;
   }

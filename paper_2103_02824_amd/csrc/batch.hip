@@ -47,6 +47,23 @@ __device__ __forceinline__ const double* sc(const double* bs, int p, int NB, int
   return bs + ((int64_t)p * 8 + k) * NB;
 }
 
+// Chebyshev polynomial preconditioner (the same recurrence as the single-
+// system solves: Y. Saad, Iterative Methods for Sparse Linear Systems,
+// Algorithm 12.1, over [lmax / ratio, lmax]).
+__device__ __forceinline__ double cheb_theta(double lmax, double ratio) { return 0.5 * (lmax + lmax / ratio); }
+__device__ __forceinline__ void cheb_coef(double lmax, double ratio, int j, double* cd, double* cr) {
+  const double b = lmax, a = lmax / ratio;
+  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a);
+  const double s1 = theta / delta;
+  double rho_prev = 1.0 / s1, rho = rho_prev;
+  for (int k = 1; k <= j; ++k) {
+    rho_prev = rho;
+    rho = 1.0 / (2.0 * s1 - rho_prev);
+  }
+  *cd = rho * rho_prev;
+  *cr = 2.0 * rho / delta;
+}
+
 // Rows [r0, r1) of Y = A S for NT <= 8 columns: G lanes per row, every lane
 // strides the row's nonzeros by G and keeps the NT sums in registers. With
 // dot: per-block column sums of S . Y into sd[0..NT).
@@ -135,6 +152,144 @@ __device__ void tile_spmm_wide(int64_t r0, int64_t r1, int N, const int32_t* __r
   if (!dot) return;
   sd[threadIdx.x] = (rl < R) ? dp : 0.0;
   reduce_rc(sd, R, N);
+}
+
+// One Chebyshev step over rows [r0, r1): w = A Zin; d = cd d + cr D^-1 (R - w);
+// Zout = Zin + d; with dot, column sums of R . Zout into sd[0..N).
+template <int NT, int G, typename T>
+__device__ void tile_cheb_small(int64_t r0, int64_t r1, const BProb<T>& D, const T* __restrict__ Zin,
+                                T* __restrict__ Zout, T cd, T cr, bool dot, double* sd) {
+  constexpr int RB = BS / G;
+  const int sub = threadIdx.x % G;
+  const int rl = threadIdx.x / G;
+  double dp[NT];
+#pragma unroll
+  for (int c = 0; c < NT; ++c) dp[c] = 0.0;
+  for (int64_t rb = r0; rb < r1; rb += RB) {
+    int64_t r = rb + rl;
+    T acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[c] = T(0);
+    if (r < r1) {
+      int j1 = D.rowptr[r + 1];
+      for (int j = D.rowptr[r] + sub; j < j1; j += G) {
+        T a = D.val[j];
+        const T* zr = Zin + (int64_t)D.col[j] * NT;
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[c] += a * zr[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, G);
+    if (r < r1) {
+      const T di = D.dinv[r];
+#pragma unroll
+      for (int c = 0; c < NT; ++c)
+        if (c % G == sub) {
+          const int64_t i = r * NT + c;
+          const T rv = D.R[i];
+          const T dn = cd * D.Dd[i] + cr * (di * (rv - acc[c]));
+          D.Dd[i] = dn;
+          const T z = Zin[i] + dn;
+          Zout[i] = z;
+          if (dot) dp[c] += (double)rv * (double)z;
+        }
+    }
+  }
+  if (!dot) return;
+  __shared__ double wpart[BS / 64][8];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    double v = wsum(dp[c]);
+    if (lane == 0) wpart[wid][c] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NT) {
+    int c = threadIdx.x;
+    double s = 0.0;
+    for (int w = 0; w < BS / 64; ++w) s += wpart[w][c];
+    sd[c] = s;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void tile_cheb_wide(int64_t r0, int64_t r1, const BProb<T>& D, const T* __restrict__ Zin,
+                               T* __restrict__ Zout, T cd, T cr, bool dot, double* sd) {
+  const int N = D.N;
+  const int R = BS / N;
+  const int rl = threadIdx.x / N, c = threadIdx.x - rl * N;
+  double dp = 0.0;
+  for (int64_t rb = r0; rb < r1; rb += R) {
+    int64_t r = rb + rl;
+    if (rl < R && r < r1) {
+      int j = D.rowptr[r], j1 = D.rowptr[r + 1];
+      T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+      for (; j + 3 < j1; j += 4) {
+        int k0 = D.col[j], k1 = D.col[j + 1], k2 = D.col[j + 2], k3 = D.col[j + 3];
+        a0 += D.val[j] * Zin[(int64_t)k0 * N + c];
+        a1 += D.val[j + 1] * Zin[(int64_t)k1 * N + c];
+        a2 += D.val[j + 2] * Zin[(int64_t)k2 * N + c];
+        a3 += D.val[j + 3] * Zin[(int64_t)k3 * N + c];
+      }
+      for (; j < j1; ++j) a0 += D.val[j] * Zin[(int64_t)D.col[j] * N + c];
+      const T w = (a0 + a1) + (a2 + a3);
+      const int64_t i = r * N + c;
+      const T rv = D.R[i];
+      const T dn = cd * D.Dd[i] + cr * (D.dinv[r] * (rv - w));
+      D.Dd[i] = dn;
+      const T z = Zin[i] + dn;
+      Zout[i] = z;
+      if (dot) dp += (double)rv * (double)z;
+    }
+  }
+  if (!dot) return;
+  sd[threadIdx.x] = (rl < R) ? dp : 0.0;
+  reduce_rc(sd, R, N);
+}
+
+// Chebyshev step j >= 1 over all tiles. Step j reads Z[(j-1)&1] and writes
+// Z[j&1]; the last step writes P instead when to_p (start of a solve) and the
+// per-tile r.z partials. In iterations (to_p false) problems without active
+// columns skip their tiles.
+template <int G, typename T>
+__global__ void __launch_bounds__(BS) kb_cheb(const BProb<T>* __restrict__ probs, const int32_t* __restrict__ tile_prob,
+                                              int TR, int NB, int j, int last, int to_p, double ratio,
+                                              double* __restrict__ rz_part, const int32_t* __restrict__ flags) {
+  __shared__ double sd[BS];
+  const int t = blockIdx.x;
+  const int p = tile_prob[t];
+  if (!to_p && flags[p] == 0) return;
+  const BProb<T> D = probs[p];
+  const int64_t r0 = (int64_t)(t - D.tile0) * TR;
+  const int64_t r1 = r0 + TR < D.n ? r0 + TR : D.n;
+  double cdd, crr;
+  cheb_coef(*D.lmax, ratio, j, &cdd, &crr);
+  const T cd = (T)cdd, cr = (T)crr;
+  const T* zin = ((j - 1) & 1) ? D.Z1 : D.Z0;
+  T* zout = (last && to_p) ? D.P : ((j & 1) ? D.Z1 : D.Z0);
+  const bool dot = last != 0;
+  switch (D.N) {
+#define CHEB(K)                                                                       \
+  case K:                                                                             \
+    tile_cheb_small<K, (K == 1 ? 8 : G), T>(r0, r1, D, zin, zout, cd, cr, dot, sd);   \
+    break;
+    CHEB(1)
+    CHEB(2)
+    CHEB(3)
+    CHEB(4)
+    CHEB(5)
+    CHEB(6)
+    CHEB(7)
+    CHEB(8)
+#undef CHEB
+    default:
+      tile_cheb_wide<T>(r0, r1, D, zin, zout, cd, cr, dot, sd);
+  }
+  if (dot && (int)threadIdx.x < D.N) rz_part[(int64_t)t * NB + threadIdx.x] = sd[threadIdx.x];
 }
 
 // SpMM over all tiles. mode 0 (CG): Q = A P with partials of P.Q, tiles of
@@ -232,7 +387,8 @@ __global__ void __launch_bounds__(BS) kb_alpha(const BProb<T>* __restrict__ prob
 template <typename T>
 __global__ void __launch_bounds__(BS) kb_update(const BProb<T>* __restrict__ probs, const int32_t* __restrict__ tile_prob,
                                                 int TR, int NB, const double* __restrict__ bs,
-                                                const int32_t* __restrict__ flags, double* __restrict__ part) {
+                                                const int32_t* __restrict__ flags, double* __restrict__ part,
+                                                double ratio) {
   __shared__ double sd[BS];
   const int t = blockIdx.x;
   const int p = tile_prob[t];
@@ -246,6 +402,7 @@ __global__ void __launch_bounds__(BS) kb_update(const BProb<T>* __restrict__ pro
     const int R = BS / N;
     const int rl = threadIdx.x / N, c = threadIdx.x - rl * N;
     const T a = rl < R ? (T)sc(bs, p, NB, 5)[c] : T(0);
+    const T ith = D.lmax ? (T)(1.0 / cheb_theta(*D.lmax, ratio)) : T(0);
     for (int64_t rb = r0; rb < r1; rb += R) {
       int64_t r = rb + rl;
       if (rl < R && r < r1) {
@@ -254,6 +411,11 @@ __global__ void __launch_bounds__(BS) kb_update(const BProb<T>* __restrict__ pro
         T rr = D.R[i] - a * D.Q[i];
         D.X[i] = x;
         D.R[i] = rr;
+        if (D.lmax) {
+          T z = D.dinv[r] * rr * ith;
+          D.Z0[i] = z;
+          D.Dd[i] = z;
+        }
         v0 += (double)rr * (double)D.dinv[r] * (double)rr;
         v1 += (double)rr * (double)rr;
       }
@@ -272,7 +434,8 @@ __global__ void __launch_bounds__(BS) kb_update(const BProb<T>* __restrict__ pro
 template <typename T>
 __global__ void __launch_bounds__(BS) kb_beta(const BProb<T>* __restrict__ probs, int NB,
                                               const double* __restrict__ part, double* __restrict__ bs,
-                                              int32_t* __restrict__ flags, double rtol2) {
+                                              int32_t* __restrict__ flags, double rtol2,
+                                              const double* __restrict__ rz_part) {
   const int p = blockIdx.x;
   if (flags[p] == 0) return;
   __shared__ double s2[2 * MLC_MAX_ORBITALS];
@@ -280,7 +443,10 @@ __global__ void __launch_bounds__(BS) kb_beta(const BProb<T>* __restrict__ probs
   const BProb<T> D = probs[p];
   const int N = D.N;
   // the two partial sets (r.Dr, r.r) sit at offsets 0 and NB of each tile row
-  sum_tiles(part, D.tile0, D.ntiles, 3 * NB, N, s2);
+  if (rz_part)
+    sum_tiles(rz_part, D.tile0, D.ntiles, NB, N, s2);  // r.z of the polynomial preconditioner
+  else
+    sum_tiles(part, D.tile0, D.ntiles, 3 * NB, N, s2);
   sum_tiles(part + NB, D.tile0, D.ntiles, 3 * NB, N, s2 + MLC_MAX_ORBITALS);
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
@@ -307,7 +473,8 @@ __global__ void __launch_bounds__(BS) kb_beta(const BProb<T>* __restrict__ probs
 template <typename T>
 __global__ void __launch_bounds__(BS) kb_direction(const BProb<T>* __restrict__ probs,
                                                    const int32_t* __restrict__ tile_prob, int TR, int NB,
-                                                   const double* __restrict__ bs, const int32_t* __restrict__ flags) {
+                                                   const double* __restrict__ bs, const int32_t* __restrict__ flags,
+                                                   int degree) {
   const int t = blockIdx.x;
   const int p = tile_prob[t];
   if (flags[p] == 0) return;
@@ -318,10 +485,11 @@ __global__ void __launch_bounds__(BS) kb_direction(const BProb<T>* __restrict__ 
   __syncthreads();
   const int64_t r0 = (int64_t)(t - D.tile0) * TR;
   const int64_t r1 = r0 + TR < D.n ? r0 + TR : D.n;
+  const T* Zl = degree >= 2 ? (((degree - 1) & 1) ? D.Z1 : D.Z0) : nullptr;
   for (int64_t i = r0 * N + threadIdx.x; i < r1 * N; i += BS) {
     int64_t r = i / N;
     int c = (int)(i - r * N);
-    D.P[i] = D.dinv[r] * D.R[i] + beta[c] * D.P[i];
+    D.P[i] = (Zl ? Zl[i] : D.dinv[r] * D.R[i]) + beta[c] * D.P[i];
   }
 }
 
@@ -329,7 +497,7 @@ __global__ void __launch_bounds__(BS) kb_direction(const BProb<T>* __restrict__ 
 // partials of r.Dr, r.r, b.b.
 template <typename T>
 __global__ void __launch_bounds__(BS) kb_init(const BProb<T>* __restrict__ probs, const int32_t* __restrict__ tile_prob,
-                                              int TR, int NB, double* __restrict__ part) {
+                                              int TR, int NB, double* __restrict__ part, int poly, double ratio) {
   __shared__ double sd[BS];
   const int t = blockIdx.x;
   const int p = tile_prob[t];
@@ -349,6 +517,11 @@ __global__ void __launch_bounds__(BS) kb_init(const BProb<T>* __restrict__ probs
       T z = D.dinv[r] * rr;
       D.R[i] = rr;
       D.P[i] = z;
+      if (poly && D.lmax) {
+        T z0 = z * (T)(1.0 / cheb_theta(*D.lmax, ratio));
+        D.Z0[i] = z0;
+        D.Dd[i] = z0;
+      }
       v[0] += (double)rr * (double)z;
       v[1] += (double)rr * (double)rr;
       v[2] += (double)b * (double)b;
@@ -368,7 +541,7 @@ template <typename T>
 __global__ void __launch_bounds__(BS) kb_start(const BProb<T>* __restrict__ probs, int NB,
                                                const double* __restrict__ part, double* __restrict__ bs,
                                                const double* __restrict__ mask_bs, int32_t* __restrict__ flags,
-                                               double rtol2) {
+                                               double rtol2, const double* __restrict__ rz_part) {
   const int p = blockIdx.x;
   __shared__ double s3[3 * MLC_MAX_ORBITALS];
   __shared__ int cnt;
@@ -376,6 +549,7 @@ __global__ void __launch_bounds__(BS) kb_start(const BProb<T>* __restrict__ prob
   const int N = D.N;
   for (int k = 0; k < 3; ++k)
     sum_tiles(part + k * NB, D.tile0, D.ntiles, 3 * NB, N, s3 + k * MLC_MAX_ORBITALS);
+  if (rz_part) sum_tiles(rz_part, D.tile0, D.ntiles, NB, N, s3);  // r.z of the polynomial preconditioner
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
   for (int c = threadIdx.x; c < N; c += BS) {
@@ -432,21 +606,52 @@ void launch_b_spmm(hipStream_t s, const BProb<T>* probs, const int32_t* tile_pro
 }
 
 template <typename T>
+void launch_b_cheb(hipStream_t s, const BProb<T>* probs, const int32_t* tile_prob, int ntiles, int TR, int G, int NB,
+                   const BPoly& poly, int to_p, const int32_t* flags) {
+  for (int j = 1; j < poly.degree; ++j) {
+    const int last = j == poly.degree - 1;
+    switch (G) {
+      case 2:
+        hipLaunchKernelGGL((kb_cheb<2, T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, j, last, to_p,
+                           poly.ratio, poly.rz_part, flags);
+        break;
+      case 8:
+        hipLaunchKernelGGL((kb_cheb<8, T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, j, last, to_p,
+                           poly.ratio, poly.rz_part, flags);
+        break;
+      default:
+        hipLaunchKernelGGL((kb_cheb<4, T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, j, last, to_p,
+                           poly.ratio, poly.rz_part, flags);
+    }
+  }
+}
+
+template <typename T>
 void launch_b_iteration(hipStream_t s, const BProb<T>* probs, const int32_t* tile_prob, int ntiles, int K, int TR,
-                        int G, int NB, double* part, double* bs, int32_t* flags, double rtol2) {
+                        int G, int NB, double* part, double* bs, int32_t* flags, double rtol2, const BPoly& poly) {
+  const bool pc = poly.degree >= 2;
   launch_b_spmm<T>(s, probs, tile_prob, ntiles, TR, G, NB, 0, part, flags);
   hipLaunchKernelGGL((kb_alpha<T>), dim3(K), dim3(BS), 0, s, probs, NB, part, bs, flags, K);
-  hipLaunchKernelGGL((kb_update<T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, bs, flags, part);
-  hipLaunchKernelGGL((kb_beta<T>), dim3(K), dim3(BS), 0, s, probs, NB, part, bs, flags, rtol2);
-  hipLaunchKernelGGL((kb_direction<T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, bs, flags);
+  hipLaunchKernelGGL((kb_update<T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, bs, flags, part,
+                     poly.ratio);
+  if (pc) launch_b_cheb<T>(s, probs, tile_prob, ntiles, TR, G, NB, poly, 0, flags);
+  hipLaunchKernelGGL((kb_beta<T>), dim3(K), dim3(BS), 0, s, probs, NB, part, bs, flags, rtol2,
+                     pc ? poly.rz_part : nullptr);
+  hipLaunchKernelGGL((kb_direction<T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, bs, flags,
+                     pc ? poly.degree : 0);
 }
 
 template <typename T>
 void launch_b_start(hipStream_t s, const BProb<T>* probs, const int32_t* tile_prob, int ntiles, int K, int TR, int G,
-                    int NB, double* part, double* bs, const double* mask_bs, int32_t* flags, double rtol2) {
+                    int NB, double* part, double* bs, const double* mask_bs, int32_t* flags, double rtol2,
+                    const BPoly& poly) {
+  const bool pc = poly.degree >= 2;
   launch_b_spmm<T>(s, probs, tile_prob, ntiles, TR, G, NB, 1, part, flags);
-  hipLaunchKernelGGL((kb_init<T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, part);
-  hipLaunchKernelGGL((kb_start<T>), dim3(K), dim3(BS), 0, s, probs, NB, part, bs, mask_bs, flags, rtol2);
+  hipLaunchKernelGGL((kb_init<T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, part, pc ? 1 : 0,
+                     poly.ratio);
+  if (pc) launch_b_cheb<T>(s, probs, tile_prob, ntiles, TR, G, NB, poly, 1, flags);
+  hipLaunchKernelGGL((kb_start<T>), dim3(K), dim3(BS), 0, s, probs, NB, part, bs, mask_bs, flags, rtol2,
+                     pc ? poly.rz_part : nullptr);
 }
 
 void launch_b_ir(hipStream_t s, const BProb<double>* p64, const BProb<float>* p32, const int32_t* tile_prob,
@@ -459,12 +664,12 @@ template void launch_b_spmm<double>(hipStream_t, const BProb<double>*, const int
 template void launch_b_spmm<float>(hipStream_t, const BProb<float>*, const int32_t*, int, int, int, int, int, double*,
                                    const int32_t*);
 template void launch_b_iteration<double>(hipStream_t, const BProb<double>*, const int32_t*, int, int, int, int, int,
-                                         double*, double*, int32_t*, double);
+                                         double*, double*, int32_t*, double, const BPoly&);
 template void launch_b_iteration<float>(hipStream_t, const BProb<float>*, const int32_t*, int, int, int, int, int,
-                                        double*, double*, int32_t*, double);
+                                        double*, double*, int32_t*, double, const BPoly&);
 template void launch_b_start<double>(hipStream_t, const BProb<double>*, const int32_t*, int, int, int, int, int,
-                                     double*, double*, const double*, int32_t*, double);
+                                     double*, double*, const double*, int32_t*, double, const BPoly&);
 template void launch_b_start<float>(hipStream_t, const BProb<float>*, const int32_t*, int, int, int, int, int, double*,
-                                    double*, const double*, int32_t*, double);
+                                    double*, const double*, int32_t*, double, const BPoly&);
 
 }  // namespace mlc

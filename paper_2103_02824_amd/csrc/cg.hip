@@ -29,7 +29,10 @@ namespace {
 constexpr int TPB = 256;
 constexpr int MAXBLK = 1024;       // plain SpMM / init grids
 constexpr int SPMM_BS = 1024;      // CG SpMM block size (16 waves per block)
-constexpr int SPMM_MAXBLK = 512;   // CG SpMM grid cap (number of p.q partials)
+// CG SpMM grid cap (number of p.q partials): 512 blocks of 16 waves fill the
+// resident wave slots of the chip once; more blocks (one pass each) measured
+// slower, because the blocks past the first round run on a half-empty chip.
+constexpr int SPMM_MAXBLK = 512;
 constexpr int VEC_MAXBLK = 512;    // update / direction grid cap
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -52,6 +55,32 @@ __device__ __forceinline__ void block_reduce_cols(double* sd, int R, int N) {
 }
 
 inline int cap(int64_t needed, int mx) { return (int)(needed < mx ? (needed < 1 ? 1 : needed) : mx); }
+
+// ---------------------------------------------------------------------------
+// Chebyshev polynomial preconditioner z = p(D^-1 A) D^-1 r: the first m steps
+// of the Chebyshev iteration for A z = r from z = 0 with the Jacobi splitting,
+// for eigenvalues of D^-1 A in [lmax / ratio, lmax] (Y. Saad, Iterative
+// Methods for Sparse Linear Systems, 2nd ed., Algorithm 12.1):
+//   theta = (b + a)/2, delta = (b - a)/2, s1 = theta/delta, rho_0 = 1/s1,
+//   step 0:  d = D^-1 r / theta,  z = d
+//   step j:  rho_j = 1/(2 s1 - rho_{j-1}),
+//            d = rho_j rho_{j-1} d + (2 rho_j / delta) D^-1 (r - A z),  z += d.
+// Its residual polynomial is positive and below one on (0, b], so p is
+// positive there and p(D^-1 A) D^-1 is symmetric positive definite for CG.
+// lmax is a Gershgorin bound of D^-1 A computed on the device.
+__device__ __forceinline__ double cheb_theta(double lmax, double ratio) { return 0.5 * (lmax + lmax / ratio); }
+__device__ __forceinline__ void cheb_coef(double lmax, double ratio, int j, double* cd, double* cr) {
+  const double b = lmax, a = lmax / ratio;
+  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a);
+  const double s1 = theta / delta;
+  double rho_prev = 1.0 / s1, rho = rho_prev;
+  for (int k = 1; k <= j; ++k) {
+    rho_prev = rho;
+    rho = 1.0 / (2.0 * s1 - rho_prev);
+  }
+  *cd = rho * rho_prev;
+  *cr = 2.0 * rho / delta;
+}
 
 // ---------------------------------------------------------------------------
 // SpMM for small N (compile-time NT <= 8): G lanes share a row, each lane
@@ -152,6 +181,154 @@ __global__ void __launch_bounds__(TPB) k_spmm_wide(int64_t n, int N, const int32
   if (t < N) partial[(int64_t)blockIdx.x * N + t] = sd[t];
 }
 
+// One Chebyshev step j >= 1 fused with its SpMM (NT <= 8, G lanes per row):
+// w = A Zin; d = cd d + cr D^-1 (R - w); Zout = Zin + d; optional per-block
+// column sums of R . Zout (the r.z of CG after the last step).
+template <int NT, int G, int BS, typename T>
+__global__ void __launch_bounds__(BS) k_cheb_small(int64_t n, const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ dinv, const T* __restrict__ R,
+                                                   const T* __restrict__ Zin, T* __restrict__ Zout, T* __restrict__ Dd,
+                                                   const double* __restrict__ lmax, double ratio, int j,
+                                                   double* __restrict__ partial, const int32_t* __restrict__ flags) {
+  constexpr int RB = BS / G;
+  if (flags && flags[0] == 0) return;
+  __shared__ double sd[BS / 64][NT];
+  double cdd, crr;
+  cheb_coef(*lmax, ratio, j, &cdd, &crr);
+  const T cd = (T)cdd, cr = (T)crr;
+  const int sub = threadIdx.x % G;
+  const int rl = threadIdx.x / G;
+  double dot[NT];
+#pragma unroll
+  for (int c = 0; c < NT; ++c) dot[c] = 0.0;
+  for (int64_t r0 = (int64_t)blockIdx.x * RB; r0 < n; r0 += (int64_t)gridDim.x * RB) {
+    int64_t r = r0 + rl;
+    T acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[c] = T(0);
+    if (r < n) {
+      int j1 = rowptr[r + 1];
+      for (int e = rowptr[r] + sub; e < j1; e += G) {
+        T a = val[e];
+        const T* zr = Zin + (int64_t)col[e] * NT;
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[c] += a * zr[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, G);
+    if (r < n) {
+      const T di = dinv[r];
+#pragma unroll
+      for (int c = 0; c < NT; ++c)
+        if (c % G == sub) {
+          const int64_t i = r * NT + c;
+          const T rv = R[i];
+          const T dn = cd * Dd[i] + cr * (di * (rv - acc[c]));
+          Dd[i] = dn;
+          const T z = Zin[i] + dn;
+          Zout[i] = z;
+          if (partial) dot[c] += (double)rv * (double)z;
+        }
+    }
+  }
+  if (!partial) return;
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    double v = wave_sum(dot[c]);
+    if (lane == 0) sd[wid][c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NT) {
+    int c = threadIdx.x;
+    double s = 0.0;
+    for (int w = 0; w < BS / 64; ++w) s += sd[w][c];
+    partial[(int64_t)blockIdx.x * NT + c] = s;
+  }
+}
+
+// The same for N > 8: thread (row, column), R = 256/N rows per pass.
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_cheb_wide(int64_t n, int N, const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ dinv, const T* __restrict__ R,
+                                                   const T* __restrict__ Zin, T* __restrict__ Zout, T* __restrict__ Dd,
+                                                   const double* __restrict__ lmax, double ratio, int j,
+                                                   double* __restrict__ partial, const int32_t* __restrict__ flags) {
+  if (flags && flags[0] == 0) return;
+  __shared__ double sd[TPB];
+  double cdd, crr;
+  cheb_coef(*lmax, ratio, j, &cdd, &crr);
+  const T cd = (T)cdd, cr = (T)crr;
+  const int Rr = TPB / N;
+  const int t = threadIdx.x;
+  const int rl = t / N, c = t - rl * N;
+  double dot = 0.0;
+  for (int64_t r0 = (int64_t)blockIdx.x * Rr; r0 < n; r0 += (int64_t)gridDim.x * Rr) {
+    int64_t r = r0 + rl;
+    if (rl < Rr && r < n) {
+      int e = rowptr[r], e1 = rowptr[r + 1];
+      T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+      for (; e + 3 < e1; e += 4) {
+        int k0 = col[e], k1 = col[e + 1], k2 = col[e + 2], k3 = col[e + 3];
+        a0 += val[e] * Zin[(int64_t)k0 * N + c];
+        a1 += val[e + 1] * Zin[(int64_t)k1 * N + c];
+        a2 += val[e + 2] * Zin[(int64_t)k2 * N + c];
+        a3 += val[e + 3] * Zin[(int64_t)k3 * N + c];
+      }
+      for (; e < e1; ++e) a0 += val[e] * Zin[(int64_t)col[e] * N + c];
+      const T w = (a0 + a1) + (a2 + a3);
+      const int64_t i = r * N + c;
+      const T rv = R[i];
+      const T dn = cd * Dd[i] + cr * (dinv[r] * (rv - w));
+      Dd[i] = dn;
+      const T z = Zin[i] + dn;
+      Zout[i] = z;
+      if (partial) dot += (double)rv * (double)z;
+    }
+  }
+  if (!partial) return;
+  sd[t] = rl < Rr ? dot : 0.0;
+  block_reduce_cols(sd, Rr, N);
+  if (t < N) partial[(int64_t)blockIdx.x * N + t] = sd[t];
+}
+
+// Gershgorin bound of D^-1 A: per-block maxima of dinv_i sum_j |a_ij|, then
+// the maximum over blocks (times 1 + 1e-6) into out[0].
+__global__ void __launch_bounds__(TPB) k_gersh(int64_t n, const int32_t* __restrict__ rowptr,
+                                               const double* __restrict__ val, const double* __restrict__ dinv,
+                                               double* __restrict__ partial) {
+  __shared__ double sd[TPB];
+  double m = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x; r < n; r += (int64_t)gridDim.x * TPB) {
+    double s = 0.0;
+    for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) s += fabs(val[e]);
+    m = fmax(m, s * fabs(dinv[r]));
+  }
+  sd[threadIdx.x] = m;
+  for (int h = TPB / 2; h > 0; h >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < h) sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + h]);
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sd[0];
+}
+__global__ void __launch_bounds__(TPB) k_gersh_final(int nblk, const double* __restrict__ partial,
+                                                     double* __restrict__ out) {
+  __shared__ double sd[TPB];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += TPB) m = fmax(m, partial[b]);
+  sd[threadIdx.x] = m;
+  for (int h = TPB / 2; h > 0; h >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < h) sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + h]);
+  }
+  if (threadIdx.x == 0) out[0] = sd[0] * (1.0 + 1e-6);
+}
+
 // (row, column) thread layout of the vector kernels
 struct RC {
   int R, rl, c;
@@ -167,8 +344,10 @@ template <typename T>
 __global__ void __launch_bounds__(TPB) k_cg_init(int64_t n, int N, const T* __restrict__ B,
                                                  const T* __restrict__ AX, const T* __restrict__ dinv,
                                                  T* __restrict__ Rv, T* __restrict__ P,
-                                                 double* __restrict__ partial) {
+                                                 double* __restrict__ partial, T* __restrict__ Z0,
+                                                 T* __restrict__ Dd, const double* __restrict__ lmax, double ratio) {
   __shared__ double sd[TPB];
+  const T ith = Z0 ? (T)(1.0 / cheb_theta(*lmax, ratio)) : T(0);
   RC p(N);
   double v[3] = {0.0, 0.0, 0.0};
   for (int64_t r0 = (int64_t)blockIdx.x * p.R; r0 < n; r0 += (int64_t)gridDim.x * p.R) {
@@ -180,6 +359,10 @@ __global__ void __launch_bounds__(TPB) k_cg_init(int64_t n, int N, const T* __re
       T z = dinv[r] * rr;
       Rv[i] = rr;
       P[i] = z;
+      if (Z0) {
+        Z0[i] = z * ith;
+        Dd[i] = z * ith;
+      }
       v[0] += (double)rr * (double)z;
       v[1] += (double)rr * (double)rr;
       v[2] += (double)b * (double)b;
@@ -231,9 +414,11 @@ enum { C_RZ = 0, C_RR, C_BB, C_ACT, C_IT };
 // CG start scalars from the k_cg_init partials [rz, rr, bb] (one block).
 __global__ void __launch_bounds__(TPB) k_cg_start(int N, int nblk, const double* __restrict__ partial, double rtol2,
                                                  const double* __restrict__ mask, double* __restrict__ scal,
-                                                 int32_t* __restrict__ flags) {
+                                                 int32_t* __restrict__ flags, const double* __restrict__ rz_part,
+                                                 int nblk_rz) {
   __shared__ double sums[3 * MLC_MAX_ORBITALS];
   sum_partials(partial, nblk, 3 * N, sums);
+  if (rz_part) sum_partials(rz_part, nblk_rz, N, sums);  // r.z of the polynomial preconditioner
   if (threadIdx.x != 0) return;
   int nact = 0;
   for (int c = 0; c < N; ++c) {
@@ -258,10 +443,13 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int64_t n, int N, const T* __
                                                    const T* __restrict__ P, const T* __restrict__ Q,
                                                    const double* __restrict__ pq_part, int nblk_pq,
                                                    const double* __restrict__ scal, const int32_t* __restrict__ flags,
-                                                   double* __restrict__ partial, int32_t* __restrict__ brk) {
+                                                   double* __restrict__ partial, int32_t* __restrict__ brk,
+                                                   T* __restrict__ Z0, T* __restrict__ Dd,
+                                                   const double* __restrict__ lmax, double ratio) {
   if (flags[0] == 0) return;
   __shared__ double sd[TPB];
   __shared__ double alpha[MLC_MAX_ORBITALS];
+  const T ith = Z0 ? (T)(1.0 / cheb_theta(*lmax, ratio)) : T(0);
   sum_partials(pq_part, nblk_pq, N, alpha);
   if ((int)threadIdx.x < N) {
     int c = threadIdx.x;
@@ -285,6 +473,11 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int64_t n, int N, const T* __
       T rr = Rv[i] - a * Q[i];
       X[i] = x;
       Rv[i] = rr;
+      if (Z0) {
+        T z = dinv[r] * rr * ith;
+        Z0[i] = z;
+        Dd[i] = z;
+      }
       v[0] += (double)rr * (double)dinv[r] * (double)rr;
       v[1] += (double)rr * (double)rr;
     }
@@ -307,7 +500,8 @@ __global__ void __launch_bounds__(TPB) k_cg_direction(int64_t n, int N, const T*
                                                       const double* __restrict__ scal_in,
                                                       const int32_t* __restrict__ flags_in,
                                                       double* __restrict__ scal_out, int32_t* __restrict__ flags_out,
-                                                      double rtol2) {
+                                                      double rtol2, const double* __restrict__ rz_part, int nblk_rz,
+                                                      const T* __restrict__ Zl) {
   if (flags_in[0] == 0) {
     // converged: carry the scalars to the other buffer so that the parity
     // alternation stays consistent, then do nothing else
@@ -321,6 +515,7 @@ __global__ void __launch_bounds__(TPB) k_cg_direction(int64_t n, int N, const T*
   __shared__ double beta[MLC_MAX_ORBITALS];
   __shared__ double still[MLC_MAX_ORBITALS];
   sum_partials(upd_part, nblk_upd, 2 * N, sums);
+  if (rz_part) sum_partials(rz_part, nblk_rz, N, sums);  // r.z of the polynomial preconditioner
   if ((int)threadIdx.x < N) {
     int c = threadIdx.x;
     bool act = scal_in[C_ACT * N + c] != 0.0;
@@ -346,7 +541,7 @@ __global__ void __launch_bounds__(TPB) k_cg_direction(int64_t n, int N, const T*
   for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < total; i += (int64_t)gridDim.x * TPB) {
     int64_t r = i / N;
     int c = (int)(i - r * N);
-    P[i] = dinv[r] * Rv[i] + (T)beta[c] * P[i];
+    P[i] = (Zl ? Zl[i] : dinv[r] * Rv[i]) + (T)beta[c] * P[i];
   }
 }
 
@@ -429,48 +624,139 @@ void launch_spmm2_f32(hipStream_t s, int64_t n, int N, const int32_t* rowptr, co
 }
 
 template <typename T>
-void cg_init_t(hipStream_t s, int64_t n, int N, const T* B, const T* AX, const T* dinv, T* Rv, T* P, double* partial) {
-  hipLaunchKernelGGL((k_cg_init<T>), dim3(cg_blocks(n, N)), dim3(TPB), 0, s, n, N, B, AX, dinv, Rv, P, partial);
+void launch_cg_init_t(hipStream_t s, int64_t n, int N, const T* B, const T* AX, const T* dinv, T* Rv, T* P,
+                      double* partial, const PolyPC<T>* pc) {
+  hipLaunchKernelGGL((k_cg_init<T>), dim3(cg_blocks(n, N)), dim3(TPB), 0, s, n, N, B, AX, dinv, Rv, P, partial,
+                     pc ? pc->Z[0] : (T*)nullptr, pc ? pc->Dd : (T*)nullptr, pc ? pc->lmax : nullptr,
+                     pc ? pc->ratio : 1.0);
 }
 void launch_cg_init2(hipStream_t s, int64_t n, int N, const double* B, const double* AX, const double* dinv,
                      double* Rv, double* P, double* partial) {
-  cg_init_t<double>(s, n, N, B, AX, dinv, Rv, P, partial);
+  launch_cg_init_t<double>(s, n, N, B, AX, dinv, Rv, P, partial, nullptr);
 }
 void launch_cg_init2_f32(hipStream_t s, int64_t n, int N, const float* B, const float* AX, const float* dinv,
                          float* Rv, float* P, double* partial) {
-  cg_init_t<float>(s, n, N, B, AX, dinv, Rv, P, partial);
+  launch_cg_init_t<float>(s, n, N, B, AX, dinv, Rv, P, partial, nullptr);
 }
 
+void launch_cg_start2(hipStream_t s, int64_t n, int N, const double* partial, double rtol2, const double* mask,
+                      double* scal, int32_t* flags, const double* rz_part) {
+  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(TPB), 0, s, N, cg_blocks(n, N), partial, rtol2, mask, scal, flags,
+                     rz_part, spmm_blocks(n, N));
+}
 void launch_cg_start(hipStream_t s, int64_t n, int N, const double* partial, double rtol2, const double* mask,
                      double* scal, int32_t* flags) {
-  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(TPB), 0, s, N, cg_blocks(n, N), partial, rtol2, mask, scal, flags);
+  launch_cg_start2(s, n, N, partial, rtol2, mask, scal, flags, nullptr);
 }
 
+template <typename T>
+void launch_cg_update_t(hipStream_t s, int64_t n, int N, const T* dinv, T* X, T* Rv, const T* P, const T* Q,
+                        const double* pq_part, const double* scal, const int32_t* flags, double* partial,
+                        int32_t* brk, const PolyPC<T>* pc) {
+  hipLaunchKernelGGL((k_cg_update<T>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, X, Rv, P, Q, pq_part,
+                     spmm_blocks(n, N), scal, flags, partial, brk, pc ? pc->Z[0] : (T*)nullptr,
+                     pc ? pc->Dd : (T*)nullptr, pc ? pc->lmax : nullptr, pc ? pc->ratio : 1.0);
+}
 void launch_cg_update_f(hipStream_t s, int64_t n, int N, const double* dinv, double* X, double* Rv, const double* P,
                         const double* Q, const double* pq_part, const double* scal, const int32_t* flags,
                         double* partial, int32_t* brk) {
-  hipLaunchKernelGGL((k_cg_update<double>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, X, Rv, P, Q,
-                     pq_part, spmm_blocks(n, N), scal, flags, partial, brk);
+  launch_cg_update_t<double>(s, n, N, dinv, X, Rv, P, Q, pq_part, scal, flags, partial, brk, nullptr);
 }
 void launch_cg_update_f32(hipStream_t s, int64_t n, int N, const float* dinv, float* X, float* Rv, const float* P,
                           const float* Q, const double* pq_part, const double* scal, const int32_t* flags,
                           double* partial, int32_t* brk) {
-  hipLaunchKernelGGL((k_cg_update<float>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, X, Rv, P, Q, pq_part,
-                     spmm_blocks(n, N), scal, flags, partial, brk);
+  launch_cg_update_t<float>(s, n, N, dinv, X, Rv, P, Q, pq_part, scal, flags, partial, brk, nullptr);
 }
 
+template <typename T>
+void launch_cg_direction_t(hipStream_t s, int64_t n, int N, const T* dinv, const T* Rv, T* P, const double* upd_part,
+                           const double* scal_in, const int32_t* flags_in, double* scal_out, int32_t* flags_out,
+                           double rtol2, const PolyPC<T>* pc) {
+  const T* Zl = pc ? pc->Z[(pc->degree - 1) & 1] : nullptr;
+  hipLaunchKernelGGL((k_cg_direction<T>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, Rv, P, upd_part,
+                     vec_blocks(n, N), scal_in, flags_in, scal_out, flags_out, rtol2, pc ? pc->rz_part : nullptr,
+                     spmm_blocks(n, N), Zl);
+}
 void launch_cg_direction_f(hipStream_t s, int64_t n, int N, const double* dinv, const double* Rv, double* P,
                            const double* upd_part, const double* scal_in, const int32_t* flags_in, double* scal_out,
                            int32_t* flags_out, double rtol2) {
-  hipLaunchKernelGGL((k_cg_direction<double>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, Rv, P, upd_part,
-                     vec_blocks(n, N), scal_in, flags_in, scal_out, flags_out, rtol2);
+  launch_cg_direction_t<double>(s, n, N, dinv, Rv, P, upd_part, scal_in, flags_in, scal_out, flags_out, rtol2,
+                                nullptr);
 }
 void launch_cg_direction_f32(hipStream_t s, int64_t n, int N, const float* dinv, const float* Rv, float* P,
                              const double* upd_part, const double* scal_in, const int32_t* flags_in, double* scal_out,
                              int32_t* flags_out, double rtol2) {
-  hipLaunchKernelGGL((k_cg_direction<float>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, Rv, P, upd_part,
-                     vec_blocks(n, N), scal_in, flags_in, scal_out, flags_out, rtol2);
+  launch_cg_direction_t<float>(s, n, N, dinv, Rv, P, upd_part, scal_in, flags_in, scal_out, flags_out, rtol2, nullptr);
 }
+
+// Chebyshev steps 1..degree-1 from Z[0] and Dd (written by the init or update
+// kernel). Step j reads Z[(j-1)&1] and writes Z[j&1]; the last step writes
+// last_out instead when given, and the r.z partials.
+template <typename T>
+void launch_cheb_steps_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val,
+                         const T* dinv, const T* Rv, const PolyPC<T>& pc, T* last_out, const int32_t* flags) {
+  for (int j = 1; j < pc.degree; ++j) {
+    const bool last = j == pc.degree - 1;
+    const T* zin = pc.Z[(j - 1) & 1];
+    T* zout = last && last_out ? last_out : pc.Z[j & 1];
+    double* part = last ? pc.rz_part : nullptr;
+    if (N <= 8) {
+#define CHEB_CASE(K)                                                                                              \
+  case K: {                                                                                                       \
+    constexpr int G = K == 1 ? 8 : 4;                                                                             \
+    int64_t needed = (n + (SPMM_BS / G) - 1) / (SPMM_BS / G);                                                     \
+    hipLaunchKernelGGL((k_cheb_small<K, G, SPMM_BS, T>), dim3(cap(needed, SPMM_MAXBLK)), dim3(SPMM_BS),         \
+                       0, s, n, rowptr, col, val, dinv, Rv, zin, zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags); \
+    break;                                                                                                        \
+  }
+      switch (N) {
+        CHEB_CASE(1)
+        CHEB_CASE(2)
+        CHEB_CASE(3)
+        CHEB_CASE(4)
+        CHEB_CASE(5)
+        CHEB_CASE(6)
+        CHEB_CASE(7)
+        CHEB_CASE(8)
+      }
+#undef CHEB_CASE
+    } else {
+      hipLaunchKernelGGL((k_cheb_wide<T>), dim3(cg_blocks(n, N)), dim3(TPB), 0, s, n, N, rowptr, col, val, dinv, Rv,
+                         zin, zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags);
+    }
+  }
+}
+
+void launch_gershgorin(hipStream_t s, int64_t n, const int32_t* rowptr, const double* val, const double* dinv,
+                       double* partial, double* out) {
+  int nbk = (int)((n + TPB - 1) / TPB);
+  if (nbk > 1024) nbk = 1024;
+  if (nbk < 1) nbk = 1;
+  hipLaunchKernelGGL(k_gersh, dim3(nbk), dim3(TPB), 0, s, n, rowptr, val, dinv, partial);
+  hipLaunchKernelGGL(k_gersh_final, dim3(1), dim3(TPB), 0, s, nbk, partial, out);
+}
+
+template void launch_cg_init_t<double>(hipStream_t, int64_t, int, const double*, const double*, const double*, double*,
+                                       double*, double*, const PolyPC<double>*);
+template void launch_cg_init_t<float>(hipStream_t, int64_t, int, const float*, const float*, const float*, float*,
+                                      float*, double*, const PolyPC<float>*);
+template void launch_cg_update_t<double>(hipStream_t, int64_t, int, const double*, double*, double*, const double*,
+                                         const double*, const double*, const double*, const int32_t*, double*,
+                                         int32_t*, const PolyPC<double>*);
+template void launch_cg_update_t<float>(hipStream_t, int64_t, int, const float*, float*, float*, const float*,
+                                        const float*, const double*, const double*, const int32_t*, double*, int32_t*,
+                                        const PolyPC<float>*);
+template void launch_cg_direction_t<double>(hipStream_t, int64_t, int, const double*, const double*, double*,
+                                            const double*, const double*, const int32_t*, double*, int32_t*, double,
+                                            const PolyPC<double>*);
+template void launch_cg_direction_t<float>(hipStream_t, int64_t, int, const float*, const float*, float*,
+                                           const double*, const double*, const int32_t*, double*, int32_t*, double,
+                                           const PolyPC<float>*);
+template void launch_cheb_steps_t<double>(hipStream_t, int64_t, int, const int32_t*, const int32_t*, const double*,
+                                          const double*, const double*, const PolyPC<double>&, double*,
+                                          const int32_t*);
+template void launch_cheb_steps_t<float>(hipStream_t, int64_t, int, const int32_t*, const int32_t*, const float*,
+                                         const float*, const float*, const PolyPC<float>&, float*, const int32_t*);
 
 void launch_to_f32(hipStream_t s, int64_t m, const double* a, float* b) {
   hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((m + TPB - 1) / TPB)), dim3(TPB), 0, s, m, a, b);

@@ -351,34 +351,59 @@ __global__ void __launch_bounds__(TPB) k_diag_inv(int64_t n, const int32_t* __re
   dinv[a] = 1.0 / val[diag_slot[a]];
 }
 
-// Load vector, one thread per interior row:
-//   b_a  = scale * int f phi_a  -  l_a,   l_a = sum_{boundary b} K_ab g_b.
-__global__ void __launch_bounds__(TPB) k_load(int64_t n, const int32_t* __restrict__ adj_ptr,
-                                              const int32_t* __restrict__ adj_tet, const int8_t* __restrict__ adj_loc,
-                                              const int32_t* __restrict__ tets, const double* __restrict__ geo,
-                                              const double* __restrict__ f, double scale,
-                                              const double* __restrict__ gnod, const int32_t* __restrict__ v2d,
-                                              double* __restrict__ b, double* __restrict__ lvec) {
+// Load vector in two passes. Per tet (one thread): the local load
+//   L_a = scale * |T|/4 sum_q f(q) lambda_a(q)
+// and the lift of the boundary data, l_a = sum_{boundary vertices b of T} K^T_ab g_b,
+// into e[8t + a] and e[8t + 4 + a]. Per interior DoF (one thread): the sums
+// over its adjacent tets in tet order, b = L - l and lvec = l.
+__global__ void __launch_bounds__(TPB) k_load_elem(int64_t nt, const int32_t* __restrict__ tets,
+                                                   const double* __restrict__ geo, const double* __restrict__ f,
+                                                   double scale, const double* __restrict__ gnod,
+                                                   const int32_t* __restrict__ v2d, double* __restrict__ e) {
+  int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= nt) return;
+  const double* G = geo + 16 * t;
+  const double vol = G[0];
+  double fq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) fq[q] = f[4 * t + q];
+  bool bnd[4];
+  double gv[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    int v = tets[4 * t + b];
+    bnd[b] = gnod && v2d[v] < 0;
+    gv[b] = bnd[b] ? gnod[v] : 0.0;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double load = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) load += 0.25 * vol * fq[q] * Lq(q, a);
+    double lift = 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (bnd[b])
+        lift += vol * (G[1 + 3 * a] * G[1 + 3 * b] + G[2 + 3 * a] * G[2 + 3 * b] + G[3 + 3 * a] * G[3 + 3 * b]) *
+                gv[b];
+    e[8 * t + a] = scale * load;
+    e[8 * t + 4 + a] = lift;
+  }
+}
+
+__global__ void __launch_bounds__(TPB) k_load_gather(int64_t n, const int32_t* __restrict__ adj_ptr,
+                                                     const int32_t* __restrict__ adj_tet,
+                                                     const int8_t* __restrict__ adj_loc, const double* __restrict__ e,
+                                                     double* __restrict__ b, double* __restrict__ lvec) {
   int64_t a = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (a >= n) return;
   double load = 0.0, lift = 0.0;
-  for (int e = adj_ptr[a]; e < adj_ptr[a + 1]; ++e) {
-    int64_t t = adj_tet[e];
-    int la = adj_loc[e];
-    const double* G = geo + 16 * t;
-    double vol = G[0];
-    for (int q = 0; q < 4; ++q) load += 0.25 * vol * f[4 * t + q] * Lq(q, la);
-    if (gnod) {
-      for (int lb = 0; lb < 4; ++lb) {
-        int v = tets[4 * t + lb];
-        if (v2d[v] >= 0) continue;
-        double kv = vol * (G[1 + 3 * la] * G[1 + 3 * lb] + G[2 + 3 * la] * G[2 + 3 * lb] +
-                           G[3 + 3 * la] * G[3 + 3 * lb]);
-        lift += kv * gnod[v];
-      }
-    }
+  for (int k = adj_ptr[a]; k < adj_ptr[a + 1]; ++k) {
+    int64_t o = 8 * (int64_t)adj_tet[k] + adj_loc[k];
+    load += e[o];
+    lift += e[o + 4];
   }
-  b[a] = scale * load - lift;
+  b[a] = load - lift;
   if (lvec) lvec[a] = lift;
 }
 
@@ -404,22 +429,19 @@ __global__ void __launch_bounds__(TPB) k_coldot(int64_t n, int N, int R, const d
   if (t < N) partial[(int64_t)blockIdx.x * N + t] = sd[t];
 }
 
-// out[c] = sum over blocks of partial[b*N + c] (ordered).
+// out[c] = sum over blocks of partial[b*N + c] (ordered); one block per column.
 __global__ void __launch_bounds__(TPB) k_reduce_cols(int N, int nblk, const double* __restrict__ partial,
                                                      double* __restrict__ out) {
   __shared__ double sd[TPB];
-  for (int c = 0; c < N; ++c) {
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += TPB) acc += partial[(int64_t)b * N + c];
+  const int c = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += TPB) acc += partial[(int64_t)b * N + c];
+  sd[threadIdx.x] = acc;
+  for (int s = TPB / 2; s > 0; s >>= 1) {
     __syncthreads();
-    sd[threadIdx.x] = acc;
-    for (int s = TPB / 2; s > 0; s >>= 1) {
-      __syncthreads();
-      if ((int)threadIdx.x < s) sd[threadIdx.x] += sd[threadIdx.x + s];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) out[c] = sd[0];
+    if ((int)threadIdx.x < s) sd[threadIdx.x] += sd[threadIdx.x + s];
   }
+  if (threadIdx.x == 0) out[c] = sd[0];
 }
 
 // X[:,c] /= sqrt(s[c])
@@ -431,45 +453,99 @@ __global__ void __launch_bounds__(TPB) k_normalize_cols(int64_t total, int N, co
 }
 
 // out[k, c] = sum_{a in P^T row k} w_a Y[a, c]  (restriction P^T Y, gather form).
-// One wavefront per coarse row: lanes stride over the row's fine entries and
-// the 64 partial sums are combined with shuffles (fixed order).
+// One block per coarse row: the threads stride over the row's fine entries,
+// then wavefront shuffles and a fixed-order sum of the four waves.
 __global__ void __launch_bounds__(TPB) k_restrict(int64_t nH, int N, const int32_t* __restrict__ PTptr,
                                                   const int32_t* __restrict__ PTidx, const double* __restrict__ PTw,
                                                   const double* __restrict__ Y, double* __restrict__ out) {
-  int64_t k = (int64_t)blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
-  int lane = threadIdx.x & 63;
-  if (k >= nH) return;
-  int e0 = PTptr[k], e1 = PTptr[k + 1];
+  __shared__ double ws[TPB / 64][8];
+  const int64_t k = blockIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int e0 = PTptr[k], e1 = PTptr[k + 1];
   for (int c0 = 0; c0 < N; c0 += 8) {
+    const int nc = N - c0 < 8 ? N - c0 : 8;
     double acc[8];
+#pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    int nc = N - c0 < 8 ? N - c0 : 8;
-    for (int e = e0 + lane; e < e1; e += 64) {
-      double w = PTw[e];
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += TPB) {
+      const double w = PTw[e];
       const double* y = Y + (int64_t)PTidx[e] * N + c0;
-      for (int q = 0; q < nc; ++q) acc[q] += w * y[q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nc) acc[q] += w * y[q];
     }
-    for (int q = 0; q < nc; ++q) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
       double v = acc[q];
       for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-      if (lane == 0) out[k * N + c0 + q] = v;
+      if (lane == 0) ws[wid][q] = v;
     }
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+      const int q = threadIdx.x;
+      out[k * N + c0 + q] = (ws[0][q] + ws[1][q]) + (ws[2][q] + ws[3][q]);
+    }
+    __syncthreads();
   }
 }
 
-// Gram block U^T Y (N x N): each block sums a 256-row chunk for every (i,j)
-// pair; ordered reduction of block partials afterwards.
-constexpr int GRAM_ROWS = 256;
-__global__ void __launch_bounds__(TPB) k_gram(int64_t n, int N, const double* __restrict__ U,
-                                              const double* __restrict__ Y, double* __restrict__ partial) {
-  int64_t r0 = (int64_t)blockIdx.x * GRAM_ROWS;
-  int64_t r1 = r0 + GRAM_ROWS < n ? r0 + GRAM_ROWS : n;
-  int NN = N * N;
-  for (int p = threadIdx.x; p < NN; p += TPB) {
-    int i = p / N, j = p - (p / N) * N;
+// Gram block U^T Y (N x N) on the FP64 matrix cores (N <= 16): orbitals are
+// padded to 16, rows are the reduction index. One v_mfma_f64_16x16x4f64 per 4
+// rows: lane l feeds U[row 4q + l/16][orbital l%16] as A (16 x 4, orbital x
+// row) and Y[row 4q + l/16][orbital l%16] as B (4 x 16, row x orbital), and
+// accumulates D[l/16 + 4 v][l%16] in its register v = 0..3 (the rows of the
+// FP64 16x16 result interleave by four across the lane groups, unlike the
+// 16-bit 16x16 forms, whose lane groups hold four consecutive rows; measured
+// with a one-wave layout probe). Each block sums GRAM_ROWS rows
+// (its four waves take interleaved groups of four rows) and writes its N x N
+// partial; the partials are summed in block order afterwards.
+constexpr int GRAM_ROWS = 1024;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(TPB) k_gram_mfma(int64_t n, int N, const double* __restrict__ U,
+                                                   const double* __restrict__ Y, double* __restrict__ partial) {
+  __shared__ double sd[TPB / 64][16 * 16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int col = lane & 15, rq = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * GRAM_ROWS;
+  const int64_t r1 = r0 + GRAM_ROWS < n ? r0 + GRAM_ROWS : n;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t rb = r0 + 4 * wid; rb < r1; rb += 16) {
+    const int64_t r = rb + rq;
+    double a = 0.0, b = 0.0;
+    if (r < r1 && col < N) {
+      a = U[r * N + col];
+      b = Y[r * N + col];
+    }
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sd[wid][(rq + 4 * v) * 16 + col] = acc[v];
+  __syncthreads();
+  for (int p = threadIdx.x; p < N * N; p += TPB) {
+    const int i = p / N, j = p - i * N;
+    const int o = i * 16 + j;
+    partial[(int64_t)blockIdx.x * N * N + p] = (sd[0][o] + sd[1][o]) + (sd[2][o] + sd[3][o]);
+  }
+}
+
+// Gram block for N > 16: thread (row, j) with the N products per row in a
+// loop, per-block partials by an in-block column reduction per i.
+__global__ void __launch_bounds__(TPB) k_gram_wide(int64_t n, int N, const double* __restrict__ U,
+                                                   const double* __restrict__ Y, double* __restrict__ partial) {
+  __shared__ double sd[TPB];
+  const int R = TPB / N;
+  const int t = threadIdx.x;
+  const int rl = t / N, j = t - rl * N;
+  const int64_t r0 = (int64_t)blockIdx.x * GRAM_ROWS;
+  const int64_t r1 = r0 + GRAM_ROWS < n ? r0 + GRAM_ROWS : n;
+  for (int i = 0; i < N; ++i) {
     double acc = 0.0;
-    for (int64_t r = r0; r < r1; ++r) acc += U[r * N + i] * Y[r * N + j];
-    partial[(int64_t)blockIdx.x * NN + p] = acc;
+    if (rl < R)
+      for (int64_t r = r0 + rl; r < r1; r += R) acc += U[r * N + i] * Y[r * N + j];
+    __syncthreads();
+    sd[t] = rl < R ? acc : 0.0;
+    block_reduce_cols(sd, R, N);
+    if (t < N) partial[(int64_t)blockIdx.x * N * N + i * N + t] = sd[t];
   }
 }
 
@@ -560,6 +636,9 @@ __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* 
 
 // Per orbital: A_h4 entries int u psi_j psi_k (10) and rhs int u^2 psi_j (4).
 // One workgroup per coarse tet, orbitals in turn.
+// Orbitals are taken four at a time, so that the geometry and coarse
+// barycentrics of a fine tet are gathered once per group of four orbitals.
+constexpr int ORB_CHUNK = 4;
 __global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, const int32_t* __restrict__ grp_ptr,
                                                     const int32_t* __restrict__ grp_tet,
                                                     const int32_t* __restrict__ tets, const double* __restrict__ geo,
@@ -569,41 +648,58 @@ __global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, const int32_t* 
   __shared__ double ws[TPB / 64];
   int64_t C = blockIdx.x;
   const double* cg = cgeo + 12 * C;
-  for (int i = 0; i < N; ++i) {
-    double acc[14];
+  for (int i0 = 0; i0 < N; i0 += ORB_CHUNK) {
+    const int nc = N - i0 < ORB_CHUNK ? N - i0 : ORB_CHUNK;
+    double acc[ORB_CHUNK][14];
 #pragma unroll
-    for (int k = 0; k < 14; ++k) acc[k] = 0.0;
+    for (int o = 0; o < ORB_CHUNK; ++o)
+#pragma unroll
+      for (int k = 0; k < 14; ++k) acc[o][k] = 0.0;
     for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
       int64_t t = grp_tet[e];
-      double vol = geo[16 * t];
-      double Bc[4][4], u[4];
+      double w = 0.25 * geo[16 * t];
+      double Bc[4][4];
+      int dof[4];
+#pragma unroll
       for (int a = 0; a < 4; ++a) {
         int v = tets[4 * t + a];
         coarse_bary(cg, xyz, v, Bc[a]);
-        int d = v2d[v];
-        u[a] = d >= 0 ? U[(int64_t)d * N + i] : 0.0;
+        dof[a] = v2d[v];
       }
-      double us = u[0] + u[1] + u[2] + u[3];
-      for (int q = 0; q < 4; ++q) {
-        double uq = QB * us + (QA - QB) * u[q];
-        double ps[4];
-        for (int j = 0; j < 4; ++j) {
-          double s = Bc[0][j] + Bc[1][j] + Bc[2][j] + Bc[3][j];
-          ps[j] = QB * s + (QA - QB) * Bc[q][j];
+      double ps[4][4];  // coarse hats at the four quadrature points
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double sj = Bc[0][j] + Bc[1][j] + Bc[2][j] + Bc[3][j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ps[q][j] = QB * sj + (QA - QB) * Bc[q][j];
+      }
+#pragma unroll
+      for (int o = 0; o < ORB_CHUNK; ++o) {
+        if (o >= nc) continue;
+        double u[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) u[a] = dof[a] >= 0 ? U[(int64_t)dof[a] * N + i0 + o] : 0.0;
+        double us = u[0] + u[1] + u[2] + u[3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double uq = QB * us + (QA - QB) * u[q];
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int m = j; m < 4; ++m) acc[o][j * 4 - (j * (j - 1)) / 2 + (m - j)] += w * uq * ps[q][j] * ps[q][m];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[o][10 + j] += w * uq * uq * ps[q][j];
         }
-        double w = 0.25 * vol;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int m = j; m < 4; ++m) acc[j * 4 - (j * (j - 1)) / 2 + (m - j)] += w * uq * ps[j] * ps[m];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[10 + j] += w * uq * uq * ps[j];
       }
     }
 #pragma unroll
-    for (int k = 0; k < 14; ++k) {
-      double v = block_sum(acc[k], ws);
-      if (threadIdx.x == 0) out[14 * (C * N + i) + k] = v;
+    for (int o = 0; o < ORB_CHUNK; ++o) {
+      if (o >= nc) continue;
+#pragma unroll
+      for (int k = 0; k < 14; ++k) {
+        double v = block_sum(acc[o][k], ws);
+        if (threadIdx.x == 0) out[14 * (C * N + i0 + o) + k] = v;
+      }
     }
   }
 }
@@ -970,11 +1066,11 @@ void launch_assemble2(hipStream_t s, int64_t nt, int64_t n, int64_t nnz, const d
   hipLaunchKernelGGL(k_slot_gather, dim3(nb(nnz)), dim3(TPB), 0, s, nnz, slot_ptr, slot_src, elem, val1, val2);
   if (dinv1) hipLaunchKernelGGL(k_diag_inv, dim3(nb(n)), dim3(TPB), 0, s, n, diag_slot, val1, dinv1);
 }
-void launch_load(hipStream_t s, int64_t n, const int32_t* adj_ptr, const int32_t* adj_tet, const int8_t* adj_loc,
-                 const int32_t* tets, const double* geo, const double* f_qp, double scale, const double* gnod,
-                 const int32_t* v2d, double* b, double* lvec) {
-  hipLaunchKernelGGL(k_load, dim3(nb(n)), dim3(TPB), 0, s, n, adj_ptr, adj_tet, adj_loc, tets, geo, f_qp, scale,
-                     gnod, v2d, b, lvec);
+void launch_load(hipStream_t s, int64_t n, int64_t nt, const int32_t* adj_ptr, const int32_t* adj_tet,
+                 const int8_t* adj_loc, const int32_t* tets, const double* geo, const double* f_qp, double scale,
+                 const double* gnod, const int32_t* v2d, double* scratch, double* b, double* lvec) {
+  hipLaunchKernelGGL(k_load_elem, dim3(nb(nt)), dim3(TPB), 0, s, nt, tets, geo, f_qp, scale, gnod, v2d, scratch);
+  hipLaunchKernelGGL(k_load_gather, dim3(nb(n)), dim3(TPB), 0, s, n, adj_ptr, adj_tet, adj_loc, scratch, b, lvec);
 }
 void launch_scale_cols_to(hipStream_t s, int64_t n, int N, const double* X, const double* sc, double* Y) {
   hipLaunchKernelGGL(k_scale_cols_to, dim3(nb(n * N)), dim3(TPB), 0, s, n * N, N, X, sc, Y);
@@ -984,17 +1080,20 @@ void launch_coldot(hipStream_t s, int64_t n, int N, const double* X, const doubl
   hipLaunchKernelGGL(k_coldot, dim3(elem_blocks(n, N)), dim3(TPB), 0, s, n, N, R, X, Y, partial);
 }
 void launch_reduce_cols(hipStream_t s, int N, int nblk, const double* partial, double* out) {
-  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(TPB), 0, s, N, nblk, partial, out);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(N), dim3(TPB), 0, s, N, nblk, partial, out);
 }
 void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, double* X) {
   hipLaunchKernelGGL(k_normalize_cols, dim3(nb(n * N)), dim3(TPB), 0, s, n * N, N, sc, X);
 }
 void launch_restrict(hipStream_t s, int64_t nH, int N, const int32_t* PTptr, const int32_t* PTidx, const double* PTw,
                      const double* Y, double* out) {
-  hipLaunchKernelGGL(k_restrict, dim3((unsigned)((nH + 3) / 4)), dim3(TPB), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
+  hipLaunchKernelGGL(k_restrict, dim3((unsigned)nH), dim3(TPB), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
 }
 void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double* Y, double* partial) {
-  hipLaunchKernelGGL(k_gram, dim3(gram_blocks(n)), dim3(TPB), 0, s, n, N, U, Y, partial);
+  if (N <= 16)
+    hipLaunchKernelGGL(k_gram_mfma, dim3(gram_blocks(n)), dim3(TPB), 0, s, n, N, U, Y, partial);
+  else
+    hipLaunchKernelGGL(k_gram_wide, dim3(gram_blocks(n)), dim3(TPB), 0, s, n, N, U, Y, partial);
 }
 void launch_coarse_ops(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
                        const int32_t* tets, const double* geo, const double* xyz, const double* cgeo,
@@ -1054,9 +1153,9 @@ void launch_guess_galerkin(hipStream_t s, int64_t n, int N, const double* Phi, c
   int R = spmm_rows_per_block(N);
   int nbk = elem_blocks(n, N);
   hipLaunchKernelGGL(k_guess_dots, dim3(nbk), dim3(TPB), 0, s, n, N, R, Phi, X, AP, AD, B, partial);
-  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(TPB), 0, s, 5 * N, nbk, partial, gdots);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(5 * N), dim3(TPB), 0, s, 5 * N, nbk, partial, gdots);
   hipLaunchKernelGGL(k_guess_combine, dim3(nbk), dim3(TPB), 0, s, n, N, R, Phi, AP, AD, B, gdots, X, gsel, partial);
-  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(TPB), 0, s, 2 * N, nbk, partial, gsel + N);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(2 * N), dim3(TPB), 0, s, 2 * N, nbk, partial, gsel + N);
 }
 void launch_collect(hipStream_t s, int64_t n, int N, int stride, const float* F, const double* U,
                     const double* Phi, const double* scale, int64_t offset, int64_t cap, float* out_x,

@@ -107,6 +107,7 @@ struct Dev {
   double* gsel = nullptr;       // 4N: [learned start used, |r|^2 learned, |r|^2 plain, -]
   double* gdots = nullptr;      // 5N: Galerkin sums of the learned start
   int32_t* d2v = nullptr;       // n: library dof -> vertex
+  double* lmax = nullptr;       // 2: Gershgorin bounds of D^-1 A (step 5) and D^-1 K (Hartree)
 };
 
 struct Options {
@@ -177,6 +178,7 @@ struct mlc_ctx {
   hipGraphExec_t cg_graph[3] = {nullptr, nullptr, nullptr};  // 0 orbitals, 1 Hartree, 2 orbitals FP32
   int cg_graph_chunk[3] = {0, 0, 0};
   double cg_graph_rt2[3] = {0.0, 0.0, 0.0};
+  int cg_graph_pc[3] = {0, 0, 0};      // polynomial degree the graph was captured with (0: Jacobi)
   hipStream_t cap_stream = nullptr;     // library-owned stream used only to record graphs
   // learned initial guess of step 5 and the sample sink that feeds its training
   const mlc_nn* nn = nullptr;
@@ -204,6 +206,35 @@ mlc_status probe(mlc_ctx* c, int which, double* out, int64_t count);
 
 // ---- kernel launchers (kernels.hip) -------------------------------------------
 int spmm_rows_per_block(int N);
+
+// Chebyshev polynomial preconditioner of one CG solve (null pointer: Jacobi).
+template <typename T>
+struct PolyPC {
+  const double* lmax;  // device scalar: Gershgorin bound of D^-1 A
+  double ratio;        // interval [lmax / ratio, lmax]
+  int degree;          // >= 2
+  T* Z[2];             // ping-pong blocks, n x N each
+  T* Dd;               // n x N
+  double* rz_part;     // per-block r.z partials of the last step (spmm_blocks(n, N) x N)
+};
+template <typename T>
+void launch_cg_init_t(hipStream_t s, int64_t n, int N, const T* B, const T* AX, const T* dinv, T* Rv, T* P,
+                      double* partial, const PolyPC<T>* pc);
+template <typename T>
+void launch_cg_update_t(hipStream_t s, int64_t n, int N, const T* dinv, T* X, T* Rv, const T* P, const T* Q,
+                        const double* pq_part, const double* scal, const int32_t* flags, double* partial,
+                        int32_t* brk, const PolyPC<T>* pc);
+template <typename T>
+void launch_cg_direction_t(hipStream_t s, int64_t n, int N, const T* dinv, const T* Rv, T* P, const double* upd_part,
+                           const double* scal_in, const int32_t* flags_in, double* scal_out, int32_t* flags_out,
+                           double rtol2, const PolyPC<T>* pc);
+template <typename T>
+void launch_cheb_steps_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val,
+                         const T* dinv, const T* Rv, const PolyPC<T>& pc, T* last_out, const int32_t* flags);
+void launch_cg_start2(hipStream_t s, int64_t n, int N, const double* partial, double rtol2, const double* mask,
+                      double* scal, int32_t* flags, const double* rz_part);
+void launch_gershgorin(hipStream_t s, int64_t n, const int32_t* rowptr, const double* val, const double* dinv,
+                       double* partial, double* out);
 // cg.hip
 int cg_blocks(int64_t n, int N);
 int spmm_blocks(int64_t n, int N);
@@ -254,9 +285,11 @@ void launch_field(hipStream_t s, int64_t nt, const int32_t* tets, const double* 
 void launch_assemble2(hipStream_t s, int64_t nt, int64_t n, int64_t nnz, const double* geo, const int32_t* slot_ptr,
                       const int32_t* slot_src, const int32_t* diag_slot, double* elem, double cK1, const double* f1,
                       double cM1, double* val1, double* dinv1, double cK2, const double* f2, double* val2);
-void launch_load(hipStream_t s, int64_t n, const int32_t* adj_ptr, const int32_t* adj_tet, const int8_t* adj_loc,
-                 const int32_t* tets, const double* geo, const double* f_qp, double scale, const double* gnod,
-                 const int32_t* v2d, double* b, double* lvec);
+// b = scale * int f phi_a - l_a, l_a = sum over boundary b of K_ab g_b (gnod may be null);
+// scratch: 8 nt doubles.
+void launch_load(hipStream_t s, int64_t n, int64_t nt, const int32_t* adj_ptr, const int32_t* adj_tet,
+                 const int8_t* adj_loc, const int32_t* tets, const double* geo, const double* f_qp, double scale,
+                 const double* gnod, const int32_t* v2d, double* scratch, double* b, double* lvec);
 void launch_scale_cols_to(hipStream_t s, int64_t n, int N, const double* X, const double* sc, double* Y);
 void launch_coldot(hipStream_t s, int64_t n, int N, const double* X, const double* Y, double* partial);
 void launch_reduce_cols(hipStream_t s, int N, int nblk, const double* partial, double* out);

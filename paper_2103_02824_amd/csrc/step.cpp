@@ -52,6 +52,7 @@ struct CgArgs {
   double* scal;
   int32_t* flags;
   const double* mask;  // optional: column c may be active only if mask[active c] != 0
+  const PolyPC<T>* pc = nullptr;  // Chebyshev polynomial preconditioner (null: Jacobi)
 };
 
 // type-dispatched launchers
@@ -71,29 +72,9 @@ inline void L_init(hipStream_t s, int64_t n, int N, const float* B, const float*
                    float* P, double* part) {
   launch_cg_init2_f32(s, n, N, B, AX, dinv, R, P, part);
 }
-inline void L_update(hipStream_t s, int64_t n, int N, const double* dinv, double* X, double* R, const double* P,
-                     const double* Q, const double* pq, const double* sc, const int32_t* fl, double* part,
-                     int32_t* brk) {
-  launch_cg_update_f(s, n, N, dinv, X, R, P, Q, pq, sc, fl, part, brk);
-}
-inline void L_update(hipStream_t s, int64_t n, int N, const float* dinv, float* X, float* R, const float* P,
-                     const float* Q, const double* pq, const double* sc, const int32_t* fl, double* part,
-                     int32_t* brk) {
-  launch_cg_update_f32(s, n, N, dinv, X, R, P, Q, pq, sc, fl, part, brk);
-}
-inline void L_dir(hipStream_t s, int64_t n, int N, const double* dinv, const double* R, double* P, const double* up,
-                  const double* si, const int32_t* fi, double* so, int32_t* fo, double rt2) {
-  launch_cg_direction_f(s, n, N, dinv, R, P, up, si, fi, so, fo, rt2);
-}
-inline void L_dir(hipStream_t s, int64_t n, int N, const float* dinv, const float* R, float* P, const double* up,
-                  const double* si, const int32_t* fi, double* so, int32_t* fo, double rt2) {
-  launch_cg_direction_f32(s, n, N, dinv, R, P, up, si, fi, so, fo, rt2);
-}
-
-// One CG iteration (three kernels) reading the scalars of parity p and
-// writing those of parity 1-p.
 template <typename T>
-void enqueue_iteration(mlc_ctx* c, hipStream_t s, int64_t n, int N, const CgArgs<T>& a, double rt2, int p) {
+mlc_status enqueue_iteration(mlc_ctx* c, hipStream_t s, int64_t n, int N, const CgArgs<T>& a, double rt2, int p,
+                             hipEvent_t* ev = nullptr) {
   auto& d = c->d;
   double* red_pq = d.red;
   double* red_upd = d.red + c->nred / 2;
@@ -101,17 +82,34 @@ void enqueue_iteration(mlc_ctx* c, hipStream_t s, int64_t n, int N, const CgArgs
   double* sc_out = a.scal + (p ? 0 : 5 * N);
   int32_t* fl_in = a.flags + (p ? 2 : 0);
   int32_t* fl_out = a.flags + (p ? 0 : 2);
+  if (ev) HIPCHK(hipEventRecord(ev[0], s));
   L_spmm(s, n, N, d.rowptr, d.col, a.val, a.P, a.Q, red_pq, fl_in);
-  L_update(s, n, N, a.dinv, a.X, a.R, a.P, a.Q, red_pq, sc_in, fl_in, red_upd, a.flags + 4);
-  L_dir(s, n, N, a.dinv, a.R, a.P, red_upd, sc_in, fl_in, sc_out, fl_out, rt2);
+  if (ev) HIPCHK(hipEventRecord(ev[1], s));
+  launch_cg_update_t<T>(s, n, N, a.dinv, a.X, a.R, a.P, a.Q, red_pq, sc_in, fl_in, red_upd, a.flags + 4, a.pc);
+  if (a.pc) launch_cheb_steps_t<T>(s, n, N, d.rowptr, d.col, a.val, a.dinv, a.R, *a.pc, nullptr, fl_in);
+  launch_cg_direction_t<T>(s, n, N, a.dinv, a.R, a.P, red_upd, sc_in, fl_in, sc_out, fl_out, rt2, a.pc);
+  return MLC_OK;
 }
 
-// Multi-column Jacobi-PCG, one independent recurrence per column; per-column
-// scalars stay on the device; the host checks the number of active columns
-// every chunk (an even number of iterations >= check_every). A chunk is
-// captured once into a HIP graph (one graph per solve kind) and replayed;
-// with timed = true the chunk is launched eagerly and every SpMM launch is
-// bracketed by HIP events. On exit the true residual is evaluated in T.
+// Start of a solve: R = B - A X, P = M^-1 R (Jacobi, or the polynomial with
+// its last step written into P), scalars and active flags.
+template <typename T>
+void enqueue_start(mlc_ctx* c, hipStream_t s, int64_t n, int N, const CgArgs<T>& a, double rt2) {
+  auto& d = c->d;
+  double* red_upd = d.red + c->nred / 2;
+  L_spmm(s, n, N, d.rowptr, d.col, a.val, a.X, a.Q, nullptr, nullptr);
+  launch_cg_init_t<T>(s, n, N, a.B, a.Q, a.dinv, a.R, a.P, red_upd, a.pc);
+  if (a.pc) launch_cheb_steps_t<T>(s, n, N, d.rowptr, d.col, a.val, a.dinv, a.R, *a.pc, a.P, nullptr);
+  launch_cg_start2(s, n, N, red_upd, rt2, a.mask, a.scal, a.flags, a.pc ? a.pc->rz_part : nullptr);
+}
+
+// Multi-column preconditioned CG, one independent recurrence per column;
+// per-column scalars stay on the device; the host checks the number of
+// active columns every chunk (an even number of iterations >= check_every).
+// A chunk is captured once into a HIP graph (one graph per solve kind) and
+// replayed; with timed = true the chunk is launched eagerly and every SpMM
+// launch is bracketed by HIP events. On exit the true residual is evaluated
+// in T.
 template <typename T>
 mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs<T>& a, double rtol, int maxit, bool timed,
               double* spmm_ms, int64_t* n_spmm, CgRes* out) {
@@ -120,25 +118,26 @@ mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs<T>& a, double
   const double rt2 = rtol * rtol;
   double* red_upd = d.red + c->nred / 2;
   HIPCHK(hipMemsetAsync(a.flags, 0, 8 * sizeof(int32_t), s));
-  L_spmm(s, n, N, d.rowptr, d.col, a.val, a.X, a.Q, nullptr, nullptr);
-  L_init(s, n, N, a.B, a.Q, a.dinv, a.R, a.P, red_upd);
-  launch_cg_start(s, n, N, red_upd, rt2, a.mask, a.scal, a.flags);
+  enqueue_start<T>(c, s, n, N, a, rt2);
   int it = 0;
   int32_t hf[8];
   const int every = 2 * ((std::max(1, c->opt.check_every) + 1) / 2);
   const bool graph = c->opt.use_graphs && !timed && c->cap_stream;
-  if (graph && (!c->cg_graph[kind] || c->cg_graph_chunk[kind] != every || c->cg_graph_rt2[kind] != rt2)) {
+  const int pcdeg = a.pc ? a.pc->degree : 0;
+  if (graph && (!c->cg_graph[kind] || c->cg_graph_chunk[kind] != every || c->cg_graph_rt2[kind] != rt2 ||
+                c->cg_graph_pc[kind] != pcdeg)) {
     if (c->cg_graph[kind]) HIPCHK(hipGraphExecDestroy(c->cg_graph[kind]));
     c->cg_graph[kind] = nullptr;
     hipGraph_t g;
     HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < every; ++k) enqueue_iteration(c, c->cap_stream, n, N, a, rt2, k & 1);
+    for (int k = 0; k < every; ++k) (void)enqueue_iteration<T>(c, c->cap_stream, n, N, a, rt2, k & 1);
     HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
     hipError_t e = hipGraphInstantiate(&c->cg_graph[kind], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
     c->cg_graph_chunk[kind] = every;
     c->cg_graph_rt2[kind] = rt2;
+    c->cg_graph_pc[kind] = pcdeg;
   }
   for (;;) {
     HIPCHK(hipMemcpyAsync(hf, a.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
@@ -165,19 +164,12 @@ mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs<T>& a, double
     } else {
       for (int k = 0; k < every; ++k) {
         bool rec = timed && c->ev_used + 2 <= (int)c->ev_pool.size();
-        int p = k & 1;
-        double* red_pq = d.red;
-        if (rec) HIPCHK(hipEventRecord(c->ev_pool[c->ev_used], s));
-        L_spmm(s, n, N, d.rowptr, d.col, a.val, a.P, a.Q, red_pq, a.flags + (p ? 2 : 0));
+        mlc_status st = enqueue_iteration<T>(c, s, n, N, a, rt2, k & 1, rec ? &c->ev_pool[c->ev_used] : nullptr);
+        if (st != MLC_OK) return st;
         if (rec) {
-          HIPCHK(hipEventRecord(c->ev_pool[c->ev_used + 1], s));
           c->ev_used += 2;
           ++*n_spmm;
         }
-        L_update(s, n, N, a.dinv, a.X, a.R, a.P, a.Q, red_pq, a.scal + (p ? 5 * N : 0), a.flags + (p ? 2 : 0),
-                 red_upd, a.flags + 4);
-        L_dir(s, n, N, a.dinv, a.R, a.P, red_upd, a.scal + (p ? 5 * N : 0), a.flags + (p ? 2 : 0),
-              a.scal + (p ? 0 : 5 * N), a.flags + (p ? 0 : 2), rt2);
       }
     }
     it += every;
@@ -238,7 +230,11 @@ mlc_status solve_ir(mlc_ctx* c, int64_t n, int N, bool timed, double* spmm_ms, i
     }
     launch_to_f32(s, n * N, d.R, d.B32);
     HIPCHK(hipMemsetAsync(d.X32, 0, sizeof(float) * n * N, s));
-    CgArgs<float> fa{d.valA32, d.dinvA32, d.B32, d.X32, d.R32, d.P32, d.Q32, d.scal32, d.flags32, d.scal};
+    float* Yf = reinterpret_cast<float*>(d.Y);
+    PolyPC<float> pcF{d.lmax, c->opt.cheb_ratio, c->opt.cheb_degree, {Yf, Yf + n * N}, Yf + 2 * n * N,
+                      d.red + (int64_t)cg_max_blocks() * N};
+    CgArgs<float> fa{d.valA32, d.dinvA32, d.B32, d.X32, d.R32, d.P32, d.Q32, d.scal32, d.flags32, d.scal,
+                     c->opt.precond == MLC_PC_CHEBYSHEV ? &pcF : nullptr};
     CgRes ir;
     mlc_status st = cg<float>(c, 2, n, N, fa, c->opt.ir_inner_rtol, c->opt.cg_maxit, timed, spmm_ms, n_spmm, &ir);
     if (st != MLC_OK) return st;
@@ -319,6 +315,7 @@ mlc_status phase_operators(StepRun& S) {
   const int64_t nnz = (int64_t)c->col.size();
   launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 0.5, d.veff, S.sigma, d.valA,
                    d.dinvA, 0.5, d.fld, d.valF);
+  if (c->opt.precond == MLC_PC_CHEBYSHEV) launch_gershgorin(s, n, d.rowptr, d.valA, d.dinvA, d.red, d.lmax);
   for (int i = 0; i < N; ++i) S.colv[i] = c->lam[i] + S.sigma;
   HIPCHK(hipMemcpyAsync(d.colv, S.colv, sizeof(double) * N, hipMemcpyHostToDevice, s));
   launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr, nullptr);
@@ -375,8 +372,8 @@ mlc_status phase_after_solve(StepRun& S) {
   launch_normalize_cols(s, n, N, d.colv + N, d.X);
   if (c->hartree) {
     launch_qp_density(s, nt, d.tets, d.v2d, d.X, N, d.occ, d.rhot);
-    launch_load(s, n, d.adj_ptr, d.adj_tet, d.adj_loc, d.tets, d.geo, d.rhot, 4.0 * 3.14159265358979323846, d.g,
-                d.v2d, d.pb, d.lvec);
+    launch_load(s, n, nt, d.adj_ptr, d.adj_tet, d.adj_loc, d.tets, d.geo, d.rhot, 4.0 * 3.14159265358979323846, d.g,
+                d.v2d, d.elem, d.pb, d.lvec);
   }
   return MLC_OK;
 }
@@ -562,10 +559,13 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   PHASE(phase_operators(S));
   // step 5: (A + sigma M) u_i = (lambda_i + sigma) M phi_i
   int outer_iters = 0;
+  const bool cheb = c->opt.precond == MLC_PC_CHEBYSHEV;
+  double* rz_part = d.red + (int64_t)cg_max_blocks() * N;
+  PolyPC<double> pcA{d.lmax, c->opt.cheb_ratio, c->opt.cheb_degree, {d.Y, d.Y + n * N}, d.Y + 2 * n * N, rz_part};
   if (c->opt.precision == MLC_PREC_FP32_IR) {
     PHASE(solve_ir(c, n, N, timed, &S.r.t_spmm_ms, &S.r.n_spmm, &S.cr, &outer_iters));
   } else {
-    CgArgs<double> ca{d.valA, d.dinvA, d.B, d.X, d.R, d.P, d.Q, d.scal, d.flags, nullptr};
+    CgArgs<double> ca{d.valA, d.dinvA, d.B, d.X, d.R, d.P, d.Q, d.scal, d.flags, nullptr, cheb ? &pcA : nullptr};
     PHASE(cg<double>(c, 0, n, N, ca, c->opt.cg_rtol, c->opt.cg_maxit, timed, &S.r.t_spmm_ms, &S.r.n_spmm, &S.cr));
   }
   S.r.ir_outer = outer_iters;
@@ -574,7 +574,10 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   if (c->hartree) {
     double dummy = 0.0;
     int64_t dn = 0;
-    CgArgs<double> pa{d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP, nullptr};
+    PolyPC<double> pcK{d.lmax + 1, c->opt.cheb_ratio, c->opt.cheb_degree, {d.Y, d.Y + n}, d.Y + 2 * n,
+                       d.red + cg_max_blocks()};
+    CgArgs<double> pa{d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP, nullptr,
+                      c->opt.precond == MLC_PC_CHEBYSHEV ? &pcK : nullptr};
     PHASE(cg<double>(c, 1, n, 1, pa, c->opt.poisson_rtol, c->opt.cg_maxit, false, &dummy, &dn, &S.pr));
   }
   PHASE(phase_gram(S));

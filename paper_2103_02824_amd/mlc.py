@@ -29,7 +29,7 @@ PROBE_ID = {name: i for i, name in enumerate(PROBES)}
 
 EXPORTED = ["mlc_options_default", "mlc_create", "mlc_sizes", "mlc_workspace_bytes", "mlc_bind",
             "mlc_initial_state", "mlc_set_state", "mlc_correction_step", "mlc_get_results", "mlc_probe",
-            "mlc_time_spmm", "mlc_status_string", "mlc_last_error", "mlc_destroy", "mlc_batch_create",
+            "mlc_time_kernel", "mlc_status_string", "mlc_last_error", "mlc_destroy", "mlc_batch_create",
             "mlc_batch_workspace_bytes", "mlc_batch_bind", "mlc_batch_set_shape", "mlc_batch_step",
             "mlc_batch_last_error", "mlc_batch_destroy", "mlc_nn_create", "mlc_nn_workspace_bytes", "mlc_nn_bind",
             "mlc_nn_set_params", "mlc_nn_get_params", "mlc_nn_forward", "mlc_nn_loss_grad", "mlc_nn_adam",
@@ -61,9 +61,12 @@ class Options(C.Structure):
                 ("shift", C.c_int32), ("sigma0", C.c_double), ("poisson_rtol", C.c_double),
                 ("inner_maxit", C.c_int32), ("inner_tol", C.c_double), ("n_extra", C.c_int32),
                 ("reorder", C.c_int32), ("time_kernels", C.c_int32), ("use_graphs", C.c_int32),
-                ("precision", C.c_int32), ("ir_inner_rtol", C.c_double), ("ir_max_outer", C.c_int32)]
+                ("precision", C.c_int32), ("ir_inner_rtol", C.c_double), ("ir_max_outer", C.c_int32),
+                ("precond", C.c_int32), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double)]
 
 PREC_FP64, PREC_FP32_IR = 0, 1
+PC_JACOBI, PC_CHEBYSHEV = 0, 1
+KERNELS = {"cg_spmm": 0, "cheb_step": 1, "hartree_spmm": 2, "hartree_cheb_step": 3}
 
 
 class StepReport(C.Structure):
@@ -111,8 +114,8 @@ def lib():
     L.mlc_correction_step.argtypes = [vp, P(StepReport)]
     L.mlc_get_results.argtypes = [vp, P(dbl), P(dbl), P(dbl), P(dbl)]
     L.mlc_probe.argtypes = [vp, i32, P(dbl), i64]
-    L.mlc_time_spmm.argtypes = [vp, i32, P(dbl)]
-    L.mlc_time_spmm.restype = i32
+    L.mlc_time_kernel.argtypes = [vp, i32, i32, P(dbl)]
+    L.mlc_time_kernel.restype = i32
     L.mlc_status_string.argtypes = [i32]
     L.mlc_status_string.restype = C.c_char_p
     L.mlc_last_error.argtypes = [vp]
@@ -275,9 +278,11 @@ class Context:
         self._chk(lib().mlc_sample_count(self.h, C.byref(r)))
         return r.value
 
-    def time_spmm(self, reps=50):
+    def time_kernel(self, which="cg_spmm", reps=50):
+        """Mean launch time (us) of one solver kernel replayed back to back:
+        cg_spmm, cheb_step, hartree_spmm, hartree_cheb_step."""
         us = C.c_double()
-        self._chk(lib().mlc_time_spmm(self.h, int(reps), C.byref(us)))
+        self._chk(lib().mlc_time_kernel(self.h, KERNELS[which], int(reps), C.byref(us)))
         return us.value
 
     def close(self):

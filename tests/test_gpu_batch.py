@@ -55,11 +55,14 @@ def _contexts(cases, **kw):
     return ctxs
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
-def test_batch_step_matches_checker(cases, prec):
+@pytest.mark.parametrize("prec,pc", [("fp64", "jacobi"), ("fp32ir", "jacobi"), ("fp64", "chebyshev"),
+                                     ("fp32ir", "chebyshev")])
+def test_batch_step_matches_checker(cases, prec, pc):
     from paper_2103_02824_amd import mlc
     kw = {} if prec == "fp64" else dict(precision=mlc.PREC_FP32_IR, ir_inner_rtol=1e-4)
-    print(f"case batch of {[c[0] for c in cases]} precision {prec}", flush=True)
+    if pc == "chebyshev":
+        kw.update(precond=mlc.PC_CHEBYSHEV, cheb_degree=6, cheb_ratio=100.0)
+    print(f"case batch of {[c[0] for c in cases]} precision {prec} preconditioner {pc}", flush=True)
     ctxs = _contexts(cases, **kw)
     batch = mlc.Batch(ctxs)
     reps, br = batch.step()

@@ -214,16 +214,88 @@ def test_fp32_refinement_matches_fp64_checker(gpu, case):
     ctx.close()
 
 
-def test_time_spmm_leaves_results_untouched(c1):
-    S, prob, st0, ctx = c1
-    print("case c1_hydrogen mlc_time_spmm", flush=True)
+def test_time_kernel_leaves_results_untouched(gpu):
+    from paper_2103_02824_amd import mlc
+    S = c1_hydrogen()
+    prob = Problem(S)
+    st0, _ = initial_state(prob)
+    ctx = mlc.Context(S, mlc.options(**dict(LIB_OPTS, precond=mlc.PC_CHEBYSHEV)))
+    print("case c1_hydrogen mlc_time_kernel", flush=True)
     ctx.set_state(st0.lam, st0.Phi, st0.w)
     ctx.correction_step()
     before = ctx.get_results()
     u_before = ctx.probe("U", (ctx.n_dof, ctx.N))
-    us = ctx.time_spmm(20)
-    assert 0.0 < us < 1e5
+    for which in mlc.KERNELS:
+        us = ctx.time_kernel(which, 20)
+        assert 0.0 < us < 1e5, which
     after = ctx.get_results()
     for a, b in zip(before, after):
         assert np.array_equal(a, b)
     assert np.array_equal(u_before, ctx.probe("U", (ctx.n_dof, ctx.N)))
+
+
+@pytest.mark.parametrize("case", ["c1", "tiny2", "tiny12", "tiny2_fp32"])
+def test_chebyshev_preconditioner_reaches_the_checker(gpu, case):
+    """CG with the Chebyshev polynomial preconditioner (degree 4 in D^-1 A
+    over [lmax/30, lmax], Gershgorin lmax) gives the checker's step-5
+    solutions, Hartree direction and step results, in fewer CG iterations
+    than Jacobi over the step-5 and Hartree solves together where there is a
+    Hartree solve (a well-conditioned shifted step-5 problem on a tiny mesh
+    may take one or two more)."""
+    from inputs.systems import tiny_system
+    from oracle.mlc import fine_stage
+    from paper_2103_02824_amd import mlc
+    if case == "c1":
+        S = c1_hydrogen()
+    elif case == "tiny12":
+        S = tiny_system(n_fine=10, n_coarse=5, box=6.0, nonlinear=False, n_orbitals=12, seed=3)
+        S.occupations = np.ones(12)
+    else:
+        S = tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=True, n_orbitals=2, seed=7)
+    print(f"case {case} Chebyshev preconditioner", flush=True)
+    prob = Problem(S)
+    st0, _ = initial_state(prob)
+    extra = dict(precision=mlc.PREC_FP32_IR) if case.endswith("fp32") else {}
+    its = {}
+    for pc in (mlc.PC_JACOBI, mlc.PC_CHEBYSHEV):
+        ctx = mlc.Context(S, mlc.options(**dict(LIB_OPTS, precond=pc, cheb_degree=4, cheb_ratio=30.0, **extra)))
+        ctx.set_state(st0.lam, st0.Phi, st0.w)
+        rep = ctx.correction_step()
+        its[pc] = (rep["cg_iters_max"], rep["poisson_iters"])
+        if pc == mlc.PC_CHEBYSHEV:
+            fs = fine_stage(prob, st0, ORA_OPTS)
+            assert relerr(ctx.probe("U", (ctx.n_dof, ctx.N)), fs["U"]) < 1e-8
+            if S.hartree:
+                assert relerr(ctx.probe("W0", (ctx.n_dof,)), fs["w0"]) < 1e-8
+            if case != "tiny12":
+                ref = correction_step(prob, st0, ORA_OPTS)
+                lam, Phi, w, rho = ctx.get_results()
+                assert np.max(np.abs(lam - ref.state.lam)) < 1e-8, (lam, ref.state.lam)
+                assert relerr(rho, ref.rho_nodal) < 1e-6
+        ctx.close()
+    print(f"CG iterations (step 5, Hartree): Jacobi {its[mlc.PC_JACOBI]}, Chebyshev {its[mlc.PC_CHEBYSHEV]}",
+          flush=True)
+    if S.hartree:
+        assert sum(its[mlc.PC_CHEBYSHEV]) < sum(its[mlc.PC_JACOBI])
+
+
+def test_chebyshev_graph_replay_matches_eager(gpu):
+    from inputs.systems import tiny_system
+    from paper_2103_02824_amd import mlc
+    S = tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=True, n_orbitals=2, seed=7)
+    prob = Problem(S)
+    st0, _ = initial_state(prob)
+    outs = []
+    for graphs in (0, 1):
+        ctx = mlc.Context(S, mlc.options(**dict(LIB_OPTS, use_graphs=graphs, check_every=3,
+                                                precond=mlc.PC_CHEBYSHEV)))
+        ctx.set_state(st0.lam, st0.Phi, st0.w)
+        us = []
+        for _ in range(2):
+            ctx.correction_step()
+            us.append(ctx.probe("U", (ctx.n_dof, ctx.N)))
+            us.append(ctx.probe("W0", (ctx.n_dof,)))
+        outs.append(us)
+        ctx.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
