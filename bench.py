@@ -21,9 +21,9 @@ launch over its mean duration give the roofline fraction. The measured HBM
 traffic per launch comes from the committed counter summary in profiles/ and
 is reported only while the kernel source matches it.
 
-cpu_baseline: the CPU checker's Jacobi-PCG (SciPy sparse, FP64) run for a
-bounded number of iterations on the same-size operator, scaled to one step
-by the GPU's CG iteration count.
+cpu_baseline: the CPU checker's fine stage of one step at the library's state
+(XC, multipole data, assembly, step-5 and Hartree solves by the checker's
+Jacobi-PCG to the same tolerance; SciPy sparse, FP64).
 """
 from __future__ import annotations
 
@@ -81,168 +81,44 @@ def spmm_bytes(n, nnz, N, word=8):
     return (word + 4) * nnz + 4 * (n + 1) + 2 * word * n * N
 
 
-def cpu_baseline(S, N, iters_per_step, sample_iters, sigma):
-    """Time the checker's Jacobi-PCG on the same-size operator."""
-    from oracle.fem import Mesh
+def cpu_baseline(S, ctx, rtol):
+    """The checker's fine stage of one correction step at the library's current state, with the
+    checker's own Jacobi-PCG for both linear solves (its default sparse LU for the Hartree problem
+    takes minutes at this size): density and XC at the quadrature points, multipole boundary data,
+    assembly, the step-5 solves to rtol from phi, M-normalisation, the Hartree load and solve to
+    rtol. Setting up the checker's problem (meshes, prolongation, matrices) is not timed."""
+    import os
+    from oracle import hartree as har
+    from oracle import xc as xcmod
+    from oracle.mlc import Problem
     from oracle.pcg import jacobi_pcg
-    from oracle.potentials import v_ext
-    m = Mesh(S.xyz, S.tets, S.lo, S.hi)
-    A = 0.5 * m.ii(m.stiffness()) + m.ii(m.mass(v_ext(m.qp, S.R, S.Z, S.potential, S.rc)))
-    A = (A + sigma * m.ii(m.mass())).tocsr()
-    B = np.random.default_rng(0).standard_normal((m.n_dof, N))
+    prob = Problem(S)
+    lam, Phi, w, _ = ctx.get_results()
+    fine = prob.fine
     t0 = time.perf_counter()
-    jacobi_pcg(A, B, rtol=1e-30, max_iters_total=sample_iters)
+    rho = prob.density_qp(Phi)
+    exc, vxc = xcmod.evaluate(S.xc, rho, S.xalpha)
+    g = har.boundary_data(fine, rho) if prob.hartree else np.zeros(fine.nv)
+    veff = prob.vext_qp + fine.at_qp(w) + vxc
+    sigma = 1.0 - float(veff.min())
+    A = (0.5 * prob.K + prob.mass_ii(veff) + sigma * prob.M).tocsr()
+    B = (prob.M @ Phi) * (lam + sigma)[None, :]
+    U, it5 = jacobi_pcg(A, B, x0=Phi, rtol=rtol, maxit=100000)
+    U = U / np.sqrt(np.einsum("ai,ai->i", U, prob.M @ U))[None, :]
+    itp = 0
+    if prob.hartree:
+        rho_t = prob.density_qp(U)
+        b = 4.0 * np.pi * fine.load(rho_t)[fine.interior] - fine.ib(prob.Kfull) @ g[fine.bverts]
+        _, itp = jacobi_pcg(prob.K.tocsr(), b, rtol=rtol, maxit=100000)
     t = time.perf_counter() - t0
-    per_iter = t / sample_iters
-    step_s = per_iter * iters_per_step
-    return {"value": m.n_dof * N / step_s, "unit": "DoF*orbitals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample_iters} Jacobi-PCG iterations of the checker (SciPy CSR, FP64, one thread) on the "
-                      f"{m.n_dof}-DoF x {N}-orbital operator ({t:.1f} s), scaled to {iters_per_step} CG iterations "
-                      f"per step; assembly, Hartree solve and Gram blocks not included"}
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "batch"])
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cg-rtol", type=float, default=1e-9)
-    ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64",
-                    help="step-5 arithmetic: plain FP64 CG, or FP32 CG inside FP64 iterative refinement")
-    ap.add_argument("--precond", choices=["jacobi", "chebyshev"], default="chebyshev",
-                    help="CG preconditioner of the step-5 and Hartree solves")
-    ap.add_argument("--cheb-degree", type=int, default=8)
-    ap.add_argument("--cheb-ratio", type=float, default=100.0)
-    ap.add_argument("--inner-maxit", type=int, default=60)
-    ap.add_argument("--inner-tol", type=float, default=1e-9)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=800,
-                    help="checker PCG iterations timed for cpu_baseline (about 10 s on one core)")
-    ap.add_argument("--batch-systems", type=int, default=12,
-                    help="--workload batch: number of uneven clusters stepped together")
-    ap.add_argument("--batch-inner-maxit", type=int, default=4,
-                    help="--workload batch: inner iterations per step (host, reported apart from the GPU time)")
-    ap.add_argument("--train-steps", type=int, default=800,
-                    help="--workload batch: Adam steps of the learned-guess network")
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="after the timed steps, copy a buffer of this size twice (hardware counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU sharding by orbitals "
-              f"is described in DESIGN.md and not run here.", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2103_02824_amd import mlc
-
-    if not torch.cuda.is_available():
-        raise SystemExit("bench.py needs a GPU")
-    if args.workload == "batch":
-        return run_batch(args)
-    t_all = time.perf_counter()
-    log(f"[bench] building workload {args.workload} seed {args.seed}")
-    S = make_system(args.workload, args.seed)
-    prec = mlc.PREC_FP32_IR if args.precision == "fp32ir" else mlc.PREC_FP64
-    opts = mlc.options(cg_rtol=args.cg_rtol, poisson_rtol=args.cg_rtol, inner_maxit=args.inner_maxit,
-                       inner_tol=args.inner_tol, time_kernels=0, precision=prec,
-                       precond=mlc.PC_CHEBYSHEV if args.precond == "chebyshev" else mlc.PC_JACOBI,
-                       cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio)
-    ctx = mlc.Context(S, opts)
-    n, N = ctx.n_dof, ctx.N
-    nnz = None
-    log(f"[bench] n_dof={n} N={N} n_coarse={ctx.n_coarse_dof} tets={ctx.n_tets} workspace={ctx.workspace_bytes/1e6:.0f} MB")
-    t0 = time.perf_counter()
-    it = ctx.initial_state(tol=1e-10, maxit=300)
-    log(f"[bench] coarse SCF (initial state): {it} iterations, {time.perf_counter()-t0:.1f} s")
-    for w in range(args.warmup):
-        rep = ctx.correction_step()
-        log(f"[bench] warmup {w}: fine {rep['t_fine_ms']:.2f} ms, inner {rep['t_inner_ms']:.0f} ms "
-            f"({rep['inner_iters']} it), cg {rep['cg_iters_max']} it")
-    torch.cuda.synchronize()
-    reps = []
-    tw0 = time.perf_counter()
-    for k in range(args.steps):
-        rep = ctx.correction_step()
-        reps.append(rep)
-        lam = ctx.get_results()[0] if k == args.steps - 1 else None
-        log(f"[bench] step {k}: fine {rep['t_fine_ms']:.2f} ms + recon {rep['t_recon_ms']:.2f} ms, "
-            f"inner {rep['t_inner_ms']:.0f} ms ({rep['inner_iters']} it), cg {rep['cg_iters_max']} it "
-            f"relres {rep['cg_relres_max']:.1e}, poisson {rep['poisson_iters']} it, refinement passes {rep['ir_outer']}")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - tw0
-    if args.calib_copy_mib:
-        nb = args.calib_copy_mib * 2 ** 20
-        a = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(2):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy: {nb} bytes read and written, 2 times")
-    t_gpu = sum(r["t_fine_ms"] + r["t_recon_ms"] for r in reps) / 1e3
-    value = n * N * len(reps) / t_gpu
-    ms_per_step = 1e3 * t_gpu / len(reps)
-    # roofline of the dominant kernel: each solver kernel is replayed back to back on the library
-    # stream between two HIP events (per-launch events inside the solve would add dispatch overhead
-    # to every launch); the one with the largest time per step (mean launch time x launches per
-    # step) is the dominant kernel
-    nnz = int(np.sum(_row_nnz(S, ctx)))
-    word = 4 if args.precision == "fp32ir" else 8
-    n_replay = 200
-    cheb = args.precond == "chebyshev"
-    deg = args.cheb_degree if cheb else 1
-    it5 = float(np.mean([r["cg_iters_max"] for r in reps]))
-    itp = float(np.mean([r["poisson_iters"] for r in reps]))
-    kern = {}
-    cands = [("cg_spmm", N, word, it5 + 2), ("hartree_spmm", 1, 8, itp + 2)]
-    if cheb:
-        cands += [("cheb_step", N, word, (deg - 1) * (it5 + 1)), ("hartree_cheb_step", 1, 8, (deg - 1) * (itp + 1))]
-    for which, ncol, w, launches in cands:
-        us = ctx.time_kernel(which, n_replay)
-        nbytes = spmm_bytes(n, nnz, ncol, w) if "spmm" in which else cheb_bytes(n, nnz, ncol, w)
-        kern[which] = {"avg_launch_us": round(us, 2), "bytes_per_launch": nbytes,
-                       "achieved_GBs": round(nbytes / (us * 1e-6) / 1e9, 1), "launches_per_step": round(launches, 1),
-                       "ms_per_step": round(us * launches / 1e3, 3)}
-    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
-    kd = kern[dom]
-    kname = _kernel_name(dom, N, word)
-    achieved = kd["achieved_GBs"]
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": _traffic(kname, args.workload, args.seed, args.precision),
-            "kernel": kname, "bytes_per_launch": kd["bytes_per_launch"], "avg_launch_us": kd["avg_launch_us"],
-            "launches_timed": n_replay, "all_kernels": kern}
-    cg_its = int(np.mean([r["cg_iters_max"] for r in reps]))
-    cpu = None
-    if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline: {args.cpu_iters} checker PCG iterations")
-        cpu = cpu_baseline(S, N, cg_its, args.cpu_iters, reps[-1]["sigma"])
-    out = {
-        "metric": "fine-mesh SCF correction step: DoF*orbitals/s and % HBM roofline vs plain FP64",
-        "value": value, "unit": "DoF*orbitals/s", "n_gpus": 1, "steps": len(reps), "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64-refinement", "data": "synthetic",
-        "config": {"workload": f"4-atom seeded cluster (seed {args.seed}), graded P1 mesh" if args.workload == "c2"
-                   else "hydrogen Z=1 rc=0.2, 16^3 Kuhn P1 mesh",
-                   "n_dof": n, "orbitals": N, "n_tets": ctx.n_tets, "nnz": nnz, "n_coarse_dof": ctx.n_coarse_dof,
-                   "cg_rtol": args.cg_rtol,
-                   "precision": "plain FP64" if args.precision == "fp64" else "FP32 CG + FP64 refinement",
-                   "preconditioner": "Jacobi" if args.precond == "jacobi" else
-                   f"Chebyshev degree {args.cheb_degree} over [lmax/{args.cheb_ratio:g}, lmax]",
-                   "parallelism": "1 GPU"},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "detail": {"cg_iters_per_step": cg_its,
-                   "poisson_iters_per_step": int(np.mean([r["poisson_iters"] for r in reps])),
-                   "inner_ms_per_step": float(np.mean([r["t_inner_ms"] for r in reps])),
-                   "inner_iters_per_step": float(np.mean([r["inner_iters"] for r in reps])),
-                   "wall_ms_per_step_incl_host_inner": 1e3 * wall / len(reps),
-                   "energy": reps[-1]["energy"], "rho_integral": reps[-1]["rho_integral"],
-                   "eigenvalues": [float(x) for x in lam],
-                   "total_wall_s": time.perf_counter() - t_all},
-    }
-    print(json.dumps(out), flush=True)
+    it5 = int(np.max(it5)) if np.ndim(it5) else int(it5)
+    itp = int(np.max(itp)) if np.ndim(itp) else int(itp)
+    threads = os.environ.get("OMP_NUM_THREADS", "all")
+    return {"value": fine.n_dof * Phi.shape[1] / t, "unit": "DoF*orbitals/s", "cores": 1, "kind": "oracle",
+            "sample": f"one fine stage of the checker at the library's state after the timed steps: XC, "
+                      f"multipole data, assembly, step-5 Jacobi-PCG ({it5} iterations) and Hartree Jacobi-PCG "
+                      f"({itp} iterations) to {rtol:g}, {t:.1f} s; SciPy sparse products run on one thread "
+                      f"(BLAS threads: {threads}); problem setup not timed"}
 
 
 def _batch_contexts(systems, mlc, states, **kw):

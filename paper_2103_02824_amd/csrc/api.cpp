@@ -99,6 +99,7 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->cel_ops = w.take<double>(40 * cnt);
   d->cel_orb = w.take<double>(14 * cnt * N);
   d->cel_tri = w.take<double>(20 * cnt);
+  d->chat = w.take<double>(17 * nt);
   d->small = w.take<double>(small_len(nH, (int)N));
   d->coarse_in = w.take<double>(nH * N + nH + N);
   d->occ = w.take<double>(N);
@@ -204,6 +205,7 @@ mlc_status upload_and_init(mlc_ctx* c) {
                    nullptr, 0.0, nullptr, nullptr);
   launch_gershgorin(s, c->n, d.rowptr, d.valK, d.dinvK, d.red, d.lmax + 1);
   launch_coarse_tri(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.cel_tri);
+  launch_coarse_hats(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.chat);
   c->h_tri.resize(20 * c->cnt);
   HIPCHK(hipMemcpyAsync(c->h_tri.data(), d.cel_tri, sizeof(double) * c->h_tri.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));

@@ -24,6 +24,8 @@ struct mlc_batch {
   int prec = MLC_PREC_FP64;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
+  std::vector<hipStream_t> sys_stream;  // per-system streams of the non-solver phases
+  std::vector<hipEvent_t> sys_event;    // their join events (+ one fork event at the end)
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool bound = false;
@@ -382,19 +384,37 @@ mlc_status solve_hartree(mlc_batch* b, BRes* res) {
   return MLC_OK;
 }
 
-struct StreamSwap {
+struct StreamRestore {
   mlc_batch* b;
   std::vector<hipStream_t> saved;
-  explicit StreamSwap(mlc_batch* bb) : b(bb) {
-    for (mlc_ctx* c : b->ctx) {
-      saved.push_back(c->stream);
-      c->stream = b->stream;
-    }
+  explicit StreamRestore(mlc_batch* bb) : b(bb) {
+    for (mlc_ctx* c : b->ctx) saved.push_back(c->stream);
   }
-  ~StreamSwap() {
+  ~StreamRestore() {
     for (size_t i = 0; i < saved.size(); ++i) b->ctx[i]->stream = saved[i];
   }
 };
+
+// The systems' phases run concurrently on their own streams, which start
+// after the work already on the batch stream (fork) and which the batch
+// stream waits for before it goes on (join).
+mlc_status fork(mlc_batch* b) {
+  hipEvent_t ev = b->sys_event.back();
+  BCHK(hipEventRecord(ev, b->stream));
+  for (int i = 0; i < b->K; ++i) {
+    BCHK(hipStreamWaitEvent(b->sys_stream[i], ev, 0));
+    b->ctx[i]->stream = b->sys_stream[i];
+  }
+  return MLC_OK;
+}
+mlc_status join(mlc_batch* b) {
+  for (int i = 0; i < b->K; ++i) {
+    BCHK(hipEventRecord(b->sys_event[i], b->sys_stream[i]));
+    BCHK(hipStreamWaitEvent(b->stream, b->sys_event[i], 0));
+    b->ctx[i]->stream = b->stream;
+  }
+  return MLC_OK;
+}
 
 mlc_status sys_fail(mlc_batch* b, int s, mlc_status st) {
   return bfail(b, st, "system " + std::to_string(s) + ": " + b->ctx[s]->err);
@@ -453,6 +473,16 @@ mlc_status mlc_batch_bind(mlc_batch* b, void* workspace, size_t bytes, void* str
       g = nullptr;
     }
   if (!b->cap_stream) BCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  while ((int)b->sys_stream.size() < b->K) {
+    hipStream_t st;
+    BCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    b->sys_stream.push_back(st);
+  }
+  while ((int)b->sys_event.size() < b->K + 1) {
+    hipEvent_t ev;
+    BCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    b->sys_event.push_back(ev);
+  }
   b->ws = static_cast<char*>(workspace);
   b->stream = static_cast<hipStream_t>(stream);
   layout(b, b->ws);
@@ -481,11 +511,15 @@ mlc_status mlc_batch_step(mlc_batch* b, mlc_step_report* reports, mlc_batch_repo
     if (!c->bound || !c->has_state) return bfail(b, MLC_ERR_STATE, "system " + std::to_string(s) + " has no state");
     if (c->opt.precision != b->prec) return bfail(b, MLC_ERR_ARG, "precision changed since mlc_batch_create");
   }
-  StreamSwap swap(b);
+  StreamRestore restore(b);
+  for (mlc_ctx* c : b->ctx) c->stream = b->stream;
   hipStream_t s = b->stream;
   const int K = b->K;
   std::vector<std::unique_ptr<StepRun>> runs;
-  for (int i = 0; i < K; ++i) runs.emplace_back(new StepRun(b->ctx[i]));
+  for (int i = 0; i < K; ++i) {
+    runs.emplace_back(new StepRun(b->ctx[i]));
+    runs.back()->defer_copies = true;
+  }
   hipEvent_t ev[8];
   for (auto& e : ev) e = nullptr;
   struct EvGuard {
@@ -498,11 +532,17 @@ mlc_status mlc_batch_step(mlc_batch* b, mlc_step_report* reports, mlc_batch_repo
   for (auto& e : ev) BCHK(hipEventCreate(&e));
   mlc_status st;
   BCHK(hipEventRecord(ev[0], s));
+  if ((st = fork(b)) != MLC_OK) return st;
   for (int i = 0; i < K; ++i)
     if ((st = phase_fields(*runs[i])) != MLC_OK) return sys_fail(b, i, st);
+  if ((st = join(b)) != MLC_OK) return st;
+  for (int i = 0; i < K; ++i)
+    if ((st = phase_fields_copy(*runs[i])) != MLC_OK) return sys_fail(b, i, st);
   BCHK(hipStreamSynchronize(s));
+  if ((st = fork(b)) != MLC_OK) return st;
   for (int i = 0; i < K; ++i)
     if ((st = phase_operators(*runs[i])) != MLC_OK) return sys_fail(b, i, st);
+  if ((st = join(b)) != MLC_OK) return st;
   if (!b->tuned) {
     BCHK(hipStreamSynchronize(s));
     BCHK(hipEventRecord(ev[0], s));  // the tuning is reported on its own
@@ -521,8 +561,11 @@ mlc_status mlc_batch_step(mlc_batch* b, mlc_step_report* reports, mlc_batch_repo
     cr.breakdown = r5.breakdown;
     cr.converged = r5.done[i] != 0;
     runs[i]->r.ir_outer = outer;
-    if ((st = phase_after_solve(*runs[i])) != MLC_OK) return sys_fail(b, i, st);
   }
+  if ((st = fork(b)) != MLC_OK) return st;
+  for (int i = 0; i < K; ++i)
+    if ((st = phase_after_solve(*runs[i])) != MLC_OK) return sys_fail(b, i, st);
+  if ((st = join(b)) != MLC_OK) return st;
   BCHK(hipEventRecord(ev[3], s));
   BRes rp;
   if (b->KP > 0) {
@@ -540,9 +583,14 @@ mlc_status mlc_batch_step(mlc_batch* b, mlc_step_report* reports, mlc_batch_repo
       pr.converged = rp.done[kp] != 0;
       ++kp;
     }
-    if ((st = phase_gram(*runs[i])) != MLC_OK) return sys_fail(b, i, st);
   }
+  if ((st = fork(b)) != MLC_OK) return st;
+  for (int i = 0; i < K; ++i)
+    if ((st = phase_gram(*runs[i])) != MLC_OK) return sys_fail(b, i, st);
+  if ((st = join(b)) != MLC_OK) return st;
   BCHK(hipEventRecord(ev[5], s));
+  for (int i = 0; i < K; ++i)
+    if ((st = phase_gram_copy(*runs[i])) != MLC_OK) return sys_fail(b, i, st);
   BCHK(hipStreamSynchronize(s));
   auto ti0 = std::chrono::steady_clock::now();
   std::vector<mlc_status> ist(K, MLC_OK);
@@ -552,9 +600,13 @@ mlc_status mlc_batch_step(mlc_batch* b, mlc_step_report* reports, mlc_batch_repo
   for (int i = 0; i < K; ++i)
     if (ist[i] < 0) return sys_fail(b, i, ist[i]);
   BCHK(hipEventRecord(ev[6], s));
+  if ((st = fork(b)) != MLC_OK) return st;
   for (int i = 0; i < K; ++i)
     if ((st = phase_recon(*runs[i])) != MLC_OK) return sys_fail(b, i, st);
+  if ((st = join(b)) != MLC_OK) return st;
   BCHK(hipEventRecord(ev[7], s));
+  for (int i = 0; i < K; ++i)
+    if ((st = phase_recon_copy(*runs[i])) != MLC_OK) return sys_fail(b, i, st);
   BCHK(hipStreamSynchronize(s));
   mlc_status worst = MLC_OK;
   for (int i = 0; i < K; ++i) {
@@ -598,6 +650,8 @@ void mlc_batch_destroy(mlc_batch* b) {
   for (auto& g : b->graph)
     if (g) (void)hipGraphExecDestroy(g);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  for (hipStream_t st : b->sys_stream) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : b->sys_event) (void)hipEventDestroy(ev);
   delete b;
 }
 

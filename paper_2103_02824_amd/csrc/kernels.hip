@@ -575,10 +575,47 @@ __device__ __forceinline__ double block_sum(double v, double* ws) {
 
 // Operators: [A_fix = 1/2 K + M_{fA}] [M_{fW}] [M] [K] -> 40 values per coarse
 // tet. One workgroup per coarse tet; threads stride over its fine tets.
+// Per fine tet, in coarse-group order e (fixed per mesh): the four coarse
+// hats of its parent at its four quadrature points, chat[17 e + 4 q + j],
+// and its volume, chat[17 e + 16].
+constexpr int CHAT = 17;
+__global__ void __launch_bounds__(TPB) k_coarse_hats(int64_t cnt, const int32_t* __restrict__ grp_ptr,
+                                                     const int32_t* __restrict__ grp_tet,
+                                                     const int32_t* __restrict__ tets, const double* __restrict__ geo,
+                                                     const double* __restrict__ xyz, const double* __restrict__ cgeo,
+                                                     double* __restrict__ chat) {
+  const int64_t C = blockIdx.x;
+  const double* cg = cgeo + 12 * C;
+  for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
+    const int64_t t = grp_tet[e];
+    double Bc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) coarse_bary(cg, xyz, tets[4 * t + a], Bc[a]);
+    double* o = chat + (int64_t)CHAT * e;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double sj = Bc[0][j] + Bc[1][j] + Bc[2][j] + Bc[3][j];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[4 * q + j] = QB * sj + (QA - QB) * Bc[q][j];
+    }
+    o[16] = geo[16 * t];
+  }
+}
+
+// Gradients of the coarse hats on coarse tet C (constant there).
+__device__ __forceinline__ void coarse_grads(const double* __restrict__ cg, double g[4][3]) {
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    g[1][x] = cg[3 + x];
+    g[2][x] = cg[6 + x];
+    g[3][x] = cg[9 + x];
+    g[0][x] = -(g[1][x] + g[2][x] + g[3][x]);
+  }
+}
+
 __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* __restrict__ grp_ptr,
                                                     const int32_t* __restrict__ grp_tet,
-                                                    const int32_t* __restrict__ tets, const double* __restrict__ geo,
-                                                    const double* __restrict__ xyz, const double* __restrict__ cgeo,
+                                                    const double* __restrict__ chat, const double* __restrict__ cgeo,
                                                     const double* __restrict__ fA, const double* __restrict__ fW,
                                                     double* __restrict__ out) {
   __shared__ double ws[TPB / 64];
@@ -586,24 +623,19 @@ __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* 
   double acc[40];
 #pragma unroll
   for (int k = 0; k < 40; ++k) acc[k] = 0.0;
-  const double* cg = cgeo + 12 * C;
+  double gc[4][3];
+  coarse_grads(cgeo + 12 * C, gc);
   for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
-    int64_t t = grp_tet[e];
-    const double* G = geo + 16 * t;
-    double vol = G[0];
-    double Bc[4][4];
-    for (int a = 0; a < 4; ++a) coarse_bary(cg, xyz, tets[4 * t + a], Bc[a]);
-    double gc[4][3], pq[4][4];
-    for (int j = 0; j < 4; ++j) {
-      for (int x = 0; x < 3; ++x) {
-        double s = 0.0;
-        for (int a = 0; a < 4; ++a) s += Bc[a][j] * G[1 + 3 * a + x];
-        gc[j][x] = s;
-      }
-      double s = Bc[0][j] + Bc[1][j] + Bc[2][j] + Bc[3][j];
-      for (int q = 0; q < 4; ++q) pq[q][j] = QB * s + (QA - QB) * Bc[q][j];
-    }
+    const int64_t t = grp_tet[e];
+    const double* h = chat + (int64_t)CHAT * e;
+    const double vol = h[16];
+    double pq[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) pq[q][j] = h[4 * q + j];
     double wA[4], wW[4];
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
       wA[q] = 0.25 * vol * (fA ? fA[4 * t + q] : 0.0);
       wW[q] = 0.25 * vol * (fW ? fW[4 * t + q] : 0.0);
@@ -615,6 +647,7 @@ __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* 
         const int k = j * 4 - (j * (j - 1)) / 2 + (m - j);
         double kv = vol * (gc[j][0] * gc[m][0] + gc[j][1] * gc[m][1] + gc[j][2] * gc[m][2]);
         double mA = 0.0, mW = 0.0, mM = 0.0;
+#pragma unroll
         for (int q = 0; q < 4; ++q) {
           double pp = pq[q][j] * pq[q][m];
           mA += wA[q] * pp;
@@ -634,20 +667,16 @@ __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* 
   }
 }
 
-// Per orbital: A_h4 entries int u psi_j psi_k (10) and rhs int u^2 psi_j (4).
-// One workgroup per coarse tet, orbitals in turn.
-// Orbitals are taken four at a time, so that the geometry and coarse
-// barycentrics of a fine tet are gathered once per group of four orbitals.
-constexpr int ORB_CHUNK = 4;
+// Per orbital i and coarse tet: the 10 entries (u_i psi_j, psi_m) and the 4
+// entries (u_i^2, psi_j); orbitals two at a time per pass over the fine tets.
+constexpr int ORB_CHUNK = 2;
 __global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, const int32_t* __restrict__ grp_ptr,
                                                     const int32_t* __restrict__ grp_tet,
-                                                    const int32_t* __restrict__ tets, const double* __restrict__ geo,
-                                                    const double* __restrict__ xyz, const double* __restrict__ cgeo,
+                                                    const int32_t* __restrict__ tets, const double* __restrict__ chat,
                                                     const int32_t* __restrict__ v2d, const double* __restrict__ U,
                                                     int N, double* __restrict__ out) {
   __shared__ double ws[TPB / 64];
   int64_t C = blockIdx.x;
-  const double* cg = cgeo + 12 * C;
   for (int i0 = 0; i0 < N; i0 += ORB_CHUNK) {
     const int nc = N - i0 < ORB_CHUNK ? N - i0 : ORB_CHUNK;
     double acc[ORB_CHUNK][14];
@@ -656,39 +685,31 @@ __global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, const int32_t* 
 #pragma unroll
       for (int k = 0; k < 14; ++k) acc[o][k] = 0.0;
     for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
-      int64_t t = grp_tet[e];
-      double w = 0.25 * geo[16 * t];
-      double Bc[4][4];
+      const int64_t t = grp_tet[e];
+      const double* h = chat + (int64_t)CHAT * e;
+      const double w = 0.25 * h[16];
       int dof[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        int v = tets[4 * t + a];
-        coarse_bary(cg, xyz, v, Bc[a]);
-        dof[a] = v2d[v];
-      }
-      double ps[4][4];  // coarse hats at the four quadrature points
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        double sj = Bc[0][j] + Bc[1][j] + Bc[2][j] + Bc[3][j];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ps[q][j] = QB * sj + (QA - QB) * Bc[q][j];
-      }
+      for (int a = 0; a < 4; ++a) dof[a] = v2d[tets[4 * t + a]];
 #pragma unroll
       for (int o = 0; o < ORB_CHUNK; ++o) {
         if (o >= nc) continue;
         double u[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) u[a] = dof[a] >= 0 ? U[(int64_t)dof[a] * N + i0 + o] : 0.0;
-        double us = u[0] + u[1] + u[2] + u[3];
+        const double us = u[0] + u[1] + u[2] + u[3];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          double uq = QB * us + (QA - QB) * u[q];
+          const double uq = QB * us + (QA - QB) * u[q];
+          double ps[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) ps[j] = h[4 * q + j];
 #pragma unroll
           for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int m = j; m < 4; ++m) acc[o][j * 4 - (j * (j - 1)) / 2 + (m - j)] += w * uq * ps[q][j] * ps[q][m];
+            for (int m = j; m < 4; ++m) acc[o][j * 4 - (j * (j - 1)) / 2 + (m - j)] += w * uq * ps[j] * ps[m];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[o][10 + j] += w * uq * uq * ps[q][j];
+          for (int j = 0; j < 4; ++j) acc[o][10 + j] += w * uq * uq * ps[j];
         }
       }
     }
@@ -1095,17 +1116,21 @@ void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double*
   else
     hipLaunchKernelGGL(k_gram_wide, dim3(gram_blocks(n)), dim3(TPB), 0, s, n, N, U, Y, partial);
 }
+void launch_coarse_hats(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
+                        const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* chat) {
+  hipLaunchKernelGGL(k_coarse_hats, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo,
+                     chat);
+}
 void launch_coarse_ops(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
-                       const int32_t* tets, const double* geo, const double* xyz, const double* cgeo,
-                       const double* fA, const double* fW, double* out) {
-  hipLaunchKernelGGL(k_coarse_ops, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo, fA,
-                     fW, out);
+                       const double* chat, const double* cgeo, const double* fA, const double* fW, double* out) {
+  hipLaunchKernelGGL(k_coarse_ops, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, chat, cgeo, fA, fW,
+                     out);
 }
 void launch_coarse_orb(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
-                       const int32_t* tets, const double* geo, const double* xyz, const double* cgeo,
-                       const int32_t* v2d, const double* U, int N, double* out) {
-  hipLaunchKernelGGL(k_coarse_orb, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo,
-                     v2d, U, N, out);
+                       const int32_t* tets, const double* chat, const int32_t* v2d, const double* U, int N,
+                       double* out) {
+  hipLaunchKernelGGL(k_coarse_orb, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, chat, v2d, U, N,
+                     out);
 }
 void launch_coarse_tri(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
                        const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* out) {

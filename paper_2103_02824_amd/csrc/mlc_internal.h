@@ -83,6 +83,7 @@ struct Dev {
   double* cel_ops = nullptr;    // cnt x 40
   double* cel_orb = nullptr;    // cnt x N x 14
   double* cel_tri = nullptr;    // cnt x 20
+  double* chat = nullptr;       // nt x 17: coarse hats at fine quadrature points, fine volume
   // small
   double* small = nullptr;      // packed small blocks (see step.cpp)
   double* coarse_in = nullptr;  // phi_H (nH x N), w_H (nH), theta2 (N)
@@ -297,12 +298,15 @@ void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, do
 void launch_restrict(hipStream_t s, int64_t nH, int N, const int32_t* PTptr, const int32_t* PTidx, const double* PTw,
                      const double* Y, double* out);
 void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double* Y, double* partial);
+// chat: per fine tet in coarse-group order, the parent's coarse hats at its
+// quadrature points (16) and its volume (17 doubles; fixed per mesh).
+void launch_coarse_hats(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
+                        const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* chat);
 void launch_coarse_ops(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
-                       const int32_t* tets, const double* geo, const double* xyz, const double* cgeo,
-                       const double* fA, const double* fW, double* out);
+                       const double* chat, const double* cgeo, const double* fA, const double* fW, double* out);
 void launch_coarse_orb(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
-                       const int32_t* tets, const double* geo, const double* xyz, const double* cgeo,
-                       const int32_t* v2d, const double* U, int N, double* out);
+                       const int32_t* tets, const double* chat, const int32_t* v2d, const double* U, int N,
+                       double* out);
 void launch_coarse_tri(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
                        const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* out);
 void launch_reconstruct(hipStream_t s, int64_t n, int N, const int32_t* Pk, const double* Pw, const double* phiH,

@@ -27,6 +27,7 @@ struct StepRun {
   mlc_status ist = MLC_OK;
   std::vector<double> cin, tail;
   bool guess = false;                     // learned start evaluated this step
+  bool defer_copies = false;              // the caller enqueues the *_copy phases itself
   double gsel[4 * MLC_MAX_ORBITALS] = {};  // its per-column choices and residuals
   explicit StepRun(mlc_ctx* ctx);
   ~StepRun();
@@ -36,7 +37,8 @@ struct StepRun {
 
 // Enqueue on c->stream; phase_fields and phase_gram end with device-to-host
 // copies that the caller must synchronise before phase_operators and
-// phase_inner; phase_recon likewise before phase_finish.
+// phase_inner; phase_recon likewise before phase_finish. Host-to-device
+// copies come first in their phases (phase_operators, phase_recon).
 mlc_status phase_fields(StepRun& S);
 mlc_status phase_operators(StepRun& S);
 mlc_status phase_after_solve(StepRun& S);
@@ -44,5 +46,11 @@ mlc_status phase_gram(StepRun& S);
 mlc_status phase_inner(StepRun& S);
 mlc_status phase_recon(StepRun& S);
 mlc_status phase_finish(StepRun& S, mlc_step_report* rep);
+// The device-to-host copies that end phase_fields, phase_gram and phase_recon;
+// called by those phases unless defer_copies is set (a batch runs the phases
+// of its systems on separate streams and copies after joining them).
+mlc_status phase_fields_copy(StepRun& S);
+mlc_status phase_gram_copy(StepRun& S);
+mlc_status phase_recon_copy(StepRun& S);
 
 }  // namespace mlc

@@ -291,7 +291,13 @@ mlc_status phase_fields(StepRun& S) {
   launch_qp_fields(s, c->nt, d.tets, d.v2d, d.Phi, c->N, d.occ, d.w, d.vext, d.geo, d.qpx, c->xc, c->xalpha, d.vxc,
                    d.exc, d.veff, d.rho, d.red);
   launch_reduce_rows(s, d.red, qp_blocks(c->nt), nmom(), 1, d.small + L.mom);
-  HIPCHK(hipMemcpyAsync(S.mom, d.small + L.mom, sizeof(double) * nmom(), hipMemcpyDeviceToHost, s));
+  return S.defer_copies ? MLC_OK : phase_fields_copy(S);
+}
+
+mlc_status phase_fields_copy(StepRun& S) {
+  mlc_ctx* c = S.c;
+  SmallLayout L(c->nH, c->N);
+  HIPCHK(hipMemcpyAsync(S.mom, c->d.small + L.mom, sizeof(double) * nmom(), hipMemcpyDeviceToHost, c->stream));
   return MLC_OK;
 }
 
@@ -306,6 +312,8 @@ mlc_status phase_operators(StepRun& S) {
   SmallLayout L(c->nH, N);
   S.sigma = c->opt.shift ? c->opt.sigma0 - S.mom[nmom() - 1] : 0.0;
   c->last_sigma = S.sigma;
+  for (int i = 0; i < N; ++i) S.colv[i] = c->lam[i] + S.sigma;
+  HIPCHK(hipMemcpyAsync(d.colv, S.colv, sizeof(double) * N, hipMemcpyHostToDevice, s));
   // multipole Dirichlet data g (remark after Algorithm 3)
   HIPCHK(hipMemsetAsync(d.g, 0, sizeof(double) * nv, s));
   if (c->hartree && S.mom[0] > 0.0)
@@ -316,8 +324,6 @@ mlc_status phase_operators(StepRun& S) {
   launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 0.5, d.veff, S.sigma, d.valA,
                    d.dinvA, 0.5, d.fld, d.valF);
   if (c->opt.precond == MLC_PC_CHEBYSHEV) launch_gershgorin(s, n, d.rowptr, d.valA, d.dinvA, d.red, d.lmax);
-  for (int i = 0; i < N; ++i) S.colv[i] = c->lam[i] + S.sigma;
-  HIPCHK(hipMemcpyAsync(d.colv, S.colv, sizeof(double) * N, hipMemcpyHostToDevice, s));
   launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr, nullptr);
   launch_scale_cols_to(s, n, N, d.Q, d.colv, d.B);
   HIPCHK(hipMemcpyAsync(d.X, d.Phi, sizeof(double) * n * N, hipMemcpyDeviceToDevice, s));
@@ -421,8 +427,19 @@ mlc_status phase_gram(StepRun& S) {
     launch_reduce_cols(s, 1, elem_blocks(n, 1), d.red, d.small + L.sc + 1);
   }
   // coarse-pattern integrals (eqs. Adef, Ah4def, rhsdef, FG)
-  launch_coarse_ops(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.fld, d.fld2, d.cel_ops);
-  launch_coarse_orb(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.v2d, d.X, N, d.cel_orb);
+  launch_coarse_ops(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.chat, d.cgeo, d.fld, d.fld2, d.cel_ops);
+  launch_coarse_orb(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.chat, d.v2d, d.X, N, d.cel_orb);
+  HIPCHK(hipEventRecord(S.ev[1], s));
+  return S.defer_copies ? MLC_OK : phase_gram_copy(S);
+}
+
+mlc_status phase_gram_copy(StepRun& S) {
+  mlc_ctx* c = S.c;
+  auto& d = c->d;
+  hipStream_t s = c->stream;
+  const int64_t cnt = c->cnt;
+  const int N = c->N;
+  SmallLayout L(c->nH, N);
   c->last_small.resize(L.total);
   c->last_cel_ops.resize(40 * cnt);
   c->last_cel_orb.resize(14 * cnt * N);
@@ -430,7 +447,6 @@ mlc_status phase_gram(StepRun& S) {
   HIPCHK(hipMemcpyAsync(c->last_cel_ops.data(), d.cel_ops, sizeof(double) * 40 * cnt, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(c->last_cel_orb.data(), d.cel_orb, sizeof(double) * 14 * cnt * N, hipMemcpyDeviceToHost, s));
   if (S.guess) HIPCHK(hipMemcpyAsync(S.gsel, d.gsel, sizeof(double) * 4 * N, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipEventRecord(S.ev[1], s));
   return MLC_OK;
 }
 
@@ -490,8 +506,15 @@ mlc_status phase_recon(StepRun& S) {
   launch_gram(s, n, N, d.Phi, d.Q, d.red);
   launch_reduce_cols(s, N * N, gram_blocks(n), d.red, d.small + L.ovl);
   HIPCHK(hipEventRecord(S.ev[3], s));
+  return S.defer_copies ? MLC_OK : phase_recon_copy(S);
+}
+
+mlc_status phase_recon_copy(StepRun& S) {
+  mlc_ctx* c = S.c;
+  SmallLayout L(c->nH, c->N);
   S.tail.assign(L.total - L.sc, 0.0);
-  HIPCHK(hipMemcpyAsync(S.tail.data(), d.small + L.sc, sizeof(double) * S.tail.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(S.tail.data(), c->d.small + L.sc, sizeof(double) * S.tail.size(), hipMemcpyDeviceToHost,
+                        c->stream));
   return MLC_OK;
 }
 
