@@ -121,6 +121,153 @@ def cpu_baseline(S, ctx, rtol):
                       f"(BLAS threads: {threads}); problem setup not timed"}
 
 
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "batch"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cg-rtol", type=float, default=1e-9)
+    ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64",
+                    help="step-5 arithmetic: plain FP64 CG, or FP32 CG inside FP64 iterative refinement")
+    ap.add_argument("--precond", choices=["jacobi", "chebyshev"], default="chebyshev",
+                    help="CG preconditioner of the step-5 and Hartree solves")
+    ap.add_argument("--cheb-degree", type=int, default=8)
+    ap.add_argument("--cheb-ratio", type=float, default=100.0)
+    ap.add_argument("--hartree-coarse", type=int, default=0, choices=[0, 1],
+                    help="add the exact coarse-space correction to the Hartree CG preconditioner")
+    ap.add_argument("--inner-maxit", type=int, default=60)
+    ap.add_argument("--inner-tol", type=float, default=1e-9)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-systems", type=int, default=12,
+                    help="--workload batch: number of uneven clusters stepped together")
+    ap.add_argument("--batch-inner-maxit", type=int, default=4,
+                    help="--workload batch: inner iterations per step (host, reported apart from the GPU time)")
+    ap.add_argument("--train-steps", type=int, default=800,
+                    help="--workload batch: Adam steps of the learned-guess network")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this size twice (hardware counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the path shards by orbitals "
+              f"across GPUs, which is not run here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2103_02824_amd import mlc
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    if args.workload == "batch":
+        return run_batch(args)
+    t_all = time.perf_counter()
+    log(f"[bench] building workload {args.workload} seed {args.seed}")
+    S = make_system(args.workload, args.seed)
+    prec = mlc.PREC_FP32_IR if args.precision == "fp32ir" else mlc.PREC_FP64
+    opts = mlc.options(cg_rtol=args.cg_rtol, poisson_rtol=args.cg_rtol, inner_maxit=args.inner_maxit,
+                       inner_tol=args.inner_tol, time_kernels=0, precision=prec,
+                       precond=mlc.PC_CHEBYSHEV if args.precond == "chebyshev" else mlc.PC_JACOBI,
+                       cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio,
+                       hartree_coarse=args.hartree_coarse)
+    ctx = mlc.Context(S, opts)
+    n, N = ctx.n_dof, ctx.N
+    nnz = None
+    log(f"[bench] n_dof={n} N={N} n_coarse={ctx.n_coarse_dof} tets={ctx.n_tets} workspace={ctx.workspace_bytes/1e6:.0f} MB")
+    t0 = time.perf_counter()
+    it = ctx.initial_state(tol=1e-10, maxit=300)
+    log(f"[bench] coarse SCF (initial state): {it} iterations, {time.perf_counter()-t0:.1f} s")
+    for w in range(args.warmup):
+        rep = ctx.correction_step()
+        log(f"[bench] warmup {w}: fine {rep['t_fine_ms']:.2f} ms, inner {rep['t_inner_ms']:.0f} ms "
+            f"({rep['inner_iters']} it), cg {rep['cg_iters_max']} it")
+    torch.cuda.synchronize()
+    reps = []
+    tw0 = time.perf_counter()
+    for k in range(args.steps):
+        rep = ctx.correction_step()
+        reps.append(rep)
+        lam = ctx.get_results()[0] if k == args.steps - 1 else None
+        log(f"[bench] step {k}: fine {rep['t_fine_ms']:.2f} ms + recon {rep['t_recon_ms']:.2f} ms, "
+            f"inner {rep['t_inner_ms']:.0f} ms ({rep['inner_iters']} it), cg {rep['cg_iters_max']} it "
+            f"relres {rep['cg_relres_max']:.1e}, poisson {rep['poisson_iters']} it, refinement passes {rep['ir_outer']}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tw0
+    if args.calib_copy_mib:
+        nb = args.calib_copy_mib * 2 ** 20
+        a = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nb} bytes read and written, 2 times")
+    t_gpu = sum(r["t_fine_ms"] + r["t_recon_ms"] for r in reps) / 1e3
+    value = n * N * len(reps) / t_gpu
+    ms_per_step = 1e3 * t_gpu / len(reps)
+    # roofline of the dominant kernel: each solver kernel is replayed back to back on the library
+    # stream between two HIP events (per-launch events inside the solve would add dispatch overhead
+    # to every launch); the one with the largest time per step (mean launch time x launches per
+    # step) is the dominant kernel
+    nnz = int(np.sum(_row_nnz(S, ctx)))
+    word = 4 if args.precision == "fp32ir" else 8
+    n_replay = 200
+    cheb = args.precond == "chebyshev"
+    deg = args.cheb_degree if cheb else 1
+    it5 = float(np.mean([r["cg_iters_max"] for r in reps]))
+    itp = float(np.mean([r["poisson_iters"] for r in reps]))
+    kern = {}
+    cands = [("cg_spmm", N, word, it5 + 2), ("hartree_spmm", 1, 8, itp + 2)]
+    if cheb:
+        cands += [("cheb_step", N, word, (deg - 1) * (it5 + 1)), ("hartree_cheb_step", 1, 8, (deg - 1) * (itp + 1))]
+    for which, ncol, w, launches in cands:
+        us = ctx.time_kernel(which, n_replay)
+        nbytes = spmm_bytes(n, nnz, ncol, w) if "spmm" in which else cheb_bytes(n, nnz, ncol, w)
+        kern[which] = {"avg_launch_us": round(us, 2), "bytes_per_launch": nbytes,
+                       "achieved_GBs": round(nbytes / (us * 1e-6) / 1e9, 1), "launches_per_step": round(launches, 1),
+                       "ms_per_step": round(us * launches / 1e3, 3)}
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    kd = kern[dom]
+    kname = _kernel_name(dom, N, word)
+    achieved = kd["achieved_GBs"]
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": _traffic(kname, args.workload, args.seed, args.precision),
+            "kernel": kname, "bytes_per_launch": kd["bytes_per_launch"], "avg_launch_us": kd["avg_launch_us"],
+            "launches_timed": n_replay, "all_kernels": kern}
+    cg_its = int(np.mean([r["cg_iters_max"] for r in reps]))
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline: the checker's fine stage with Jacobi-PCG")
+        cpu = cpu_baseline(S, ctx, args.cg_rtol)
+        log(f"[bench] cpu baseline: {cpu['sample']}")
+    out = {
+        "metric": "fine-mesh SCF correction step: DoF*orbitals/s and % HBM roofline vs plain FP64",
+        "value": value, "unit": "DoF*orbitals/s", "n_gpus": 1, "steps": len(reps), "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64-refinement", "data": "synthetic",
+        "config": {"workload": f"4-atom seeded cluster (seed {args.seed}), graded P1 mesh" if args.workload == "c2"
+                   else "hydrogen Z=1 rc=0.2, 16^3 Kuhn P1 mesh",
+                   "n_dof": n, "orbitals": N, "n_tets": ctx.n_tets, "nnz": nnz, "n_coarse_dof": ctx.n_coarse_dof,
+                   "cg_rtol": args.cg_rtol,
+                   "precision": "plain FP64" if args.precision == "fp64" else "FP32 CG + FP64 refinement",
+                   "preconditioner": ("Jacobi" if args.precond == "jacobi" else
+                                      f"Chebyshev degree {args.cheb_degree} over [lmax/{args.cheb_ratio:g}, lmax]")
+                   + (" + coarse-space correction (Hartree)" if args.hartree_coarse else ""),
+                   "parallelism": "1 GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "detail": {"cg_iters_per_step": cg_its,
+                   "poisson_iters_per_step": int(np.mean([r["poisson_iters"] for r in reps])),
+                   "inner_ms_per_step": float(np.mean([r["t_inner_ms"] for r in reps])),
+                   "inner_iters_per_step": float(np.mean([r["inner_iters"] for r in reps])),
+                   "wall_ms_per_step_incl_host_inner": 1e3 * wall / len(reps),
+                   "energy": reps[-1]["energy"], "rho_integral": reps[-1]["rho_integral"],
+                   "eigenvalues": [float(x) for x in lam],
+                   "total_wall_s": time.perf_counter() - t_all},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def _batch_contexts(systems, mlc, states, **kw):
     """Contexts from the shared initial states (computed once, by the first call)."""
     ctxs = []
