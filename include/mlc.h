@@ -128,6 +128,12 @@ typedef struct {
                            must agree                                          */
   int32_t cheb_degree;  /* 2..16                                               */
   double cheb_ratio;    /* > 1                                                 */
+  int32_t hartree_coarse; /* 1: the Hartree CG adds the exact coarse-space
+                           correction P K_H^-1 P^T (additive two-level
+                           preconditioner over the nested coarse space; K_H =
+                           P^T K P factorised on the host once per mesh, its
+                           inverse applied on the device) to the preconditioner
+                           chosen by precond; single-system solves only        */
 } mlc_options;
 
 enum { MLC_PC_JACOBI = 0, MLC_PC_CHEBYSHEV = 1 };

@@ -5,6 +5,7 @@
 #include <new>
 
 #include "inner.h"
+#include "dense.h"
 #include "mlc_internal.h"
 
 namespace mlc {
@@ -135,6 +136,11 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->gdots = w.take<double>(5 * N);
   d->d2v = w.take<int32_t>(n);
   d->lmax = w.take<double>(2);
+  if (c->opt.hartree_coarse && c->hartree) {
+    d->KHinv = w.take<double>(nH * nH);
+    d->rH = w.take<double>(nH);
+    d->eH = w.take<double>(nH);
+  }
   return w.off + 256;
 }
 
@@ -206,6 +212,40 @@ mlc_status upload_and_init(mlc_ctx* c) {
   launch_gershgorin(s, c->n, d.rowptr, d.valK, d.dinvK, d.red, d.lmax + 1);
   launch_coarse_tri(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.cel_tri);
   launch_coarse_hats(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.chat);
+  if (d.KHinv) {
+    // coarse stiffness K_H = P^T K P of the nested P1 spaces (element by element: the coarse hat
+    // gradients are constant on a coarse tet), its Cholesky factor and explicit inverse
+    const int64_t nH = c->nH;
+    c->h_KHinv.assign(nH * nH, 0.0);
+    std::vector<double> L(nH * nH, 0.0);
+    for (int64_t C = 0; C < c->cnt; ++C) {
+      const double* g = &c->cgeo[12 * C];
+      double gr[4][3];
+      for (int x = 0; x < 3; ++x) {
+        gr[1][x] = g[3 + x];
+        gr[2][x] = g[6 + x];
+        gr[3][x] = g[9 + x];
+        gr[0][x] = -(gr[1][x] + gr[2][x] + gr[3][x]);
+      }
+      int k[4];
+      for (int a = 0; a < 4; ++a) k[a] = c->cv2d[c->ctets[4 * C + a]];
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+          if (k[a] >= 0 && k[b] >= 0)
+            L[(int64_t)k[a] * nH + k[b]] +=
+                c->cvol[C] * (gr[a][0] * gr[b][0] + gr[a][1] * gr[b][1] + gr[a][2] * gr[b][2]);
+    }
+    if (!dense::cholesky(L, nH)) return fail(c, MLC_ERR_NONFINITE, "coarse stiffness not SPD");
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < nH; ++j) {
+      std::vector<double> e(nH, 0.0);
+      e[j] = 1.0;
+      dense::forward(L, nH, e.data());
+      dense::backward(L, nH, e.data());
+      for (int64_t i = 0; i < nH; ++i) c->h_KHinv[i * nH + j] = e[i];
+    }
+    HIPCHK(up(s, d.KHinv, c->h_KHinv));
+  }
   c->h_tri.resize(20 * c->cnt);
   HIPCHK(hipMemcpyAsync(c->h_tri.data(), d.cel_tri, sizeof(double) * c->h_tri.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -388,6 +428,7 @@ void mlc_options_default(mlc_options* o) {
   o->precond = MLC_PC_JACOBI;
   o->cheb_degree = 4;
   o->cheb_ratio = 30.0;
+  o->hartree_coarse = 0;
 }
 
 mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys, const mlc_options* opt,

@@ -329,6 +329,45 @@ __global__ void __launch_bounds__(TPB) k_gersh_final(int nblk, const double* __r
   if (threadIdx.x == 0) out[0] = sd[0] * (1.0 + 1e-6);
 }
 
+// y = A x for a dense m x m matrix (row-major), one wavefront per row.
+__global__ void __launch_bounds__(TPB) k_dense_mv(int64_t m, const double* __restrict__ A,
+                                                  const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t r = (int64_t)blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= m) return;
+  const double* a = A + r * m;
+  double s = 0.0;
+  for (int64_t k = lane; k < m; k += 64) s += a[k] * x[k];
+  s = wave_sum(s);
+  if (lane == 0) y[r] = s;
+}
+
+// Zout = (Zin or D^-1 R) + P eH (four coarse weights per fine DoF), and the
+// per-block partials of R . Zout.
+__global__ void __launch_bounds__(TPB) k_zcoarse(int64_t n, const double* __restrict__ dinv,
+                                                 const double* __restrict__ R, const double* __restrict__ Zin,
+                                                 const int32_t* __restrict__ Pk, const double* __restrict__ Pw,
+                                                 const double* __restrict__ eH, double* __restrict__ Zout,
+                                                 double* __restrict__ partial) {
+  __shared__ double ws[TPB / 64];
+  double dot = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    double z = Zin ? Zin[i] : dinv[i] * R[i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = Pk[4 * i + j];
+      if (k >= 0) z += Pw[4 * i + j] * eH[k];
+    }
+    Zout[i] = z;
+    dot += R[i] * z;
+  }
+  dot = wave_sum(dot);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) ws[wid] = dot;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
 // (row, column) thread layout of the vector kernels
 struct RC {
   int R, rl, c;
@@ -669,13 +708,26 @@ void launch_cg_update_f32(hipStream_t s, int64_t n, int N, const float* dinv, fl
 }
 
 template <typename T>
+void launch_cg_direction_z(hipStream_t s, int64_t n, int N, const T* dinv, const T* Rv, T* P, const double* upd_part,
+                           const double* scal_in, const int32_t* flags_in, double* scal_out, int32_t* flags_out,
+                           double rtol2, const double* rz_part, const T* Zl) {
+  hipLaunchKernelGGL((k_cg_direction<T>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, Rv, P, upd_part,
+                     vec_blocks(n, N), scal_in, flags_in, scal_out, flags_out, rtol2, rz_part, spmm_blocks(n, N), Zl);
+}
+template <typename T>
 void launch_cg_direction_t(hipStream_t s, int64_t n, int N, const T* dinv, const T* Rv, T* P, const double* upd_part,
                            const double* scal_in, const int32_t* flags_in, double* scal_out, int32_t* flags_out,
                            double rtol2, const PolyPC<T>* pc) {
-  const T* Zl = pc ? pc->Z[(pc->degree - 1) & 1] : nullptr;
-  hipLaunchKernelGGL((k_cg_direction<T>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, Rv, P, upd_part,
-                     vec_blocks(n, N), scal_in, flags_in, scal_out, flags_out, rtol2, pc ? pc->rz_part : nullptr,
-                     spmm_blocks(n, N), Zl);
+  launch_cg_direction_z<T>(s, n, N, dinv, Rv, P, upd_part, scal_in, flags_in, scal_out, flags_out, rtol2,
+                           pc ? pc->rz_part : nullptr, pc ? pc->Z[(pc->degree - 1) & 1] : nullptr);
+}
+
+void launch_dense_mv(hipStream_t s, int64_t m, const double* Ainv, const double* x, double* y) {
+  hipLaunchKernelGGL(k_dense_mv, dim3((unsigned)((m + 3) / 4)), dim3(TPB), 0, s, m, Ainv, x, y);
+}
+void launch_zcoarse(hipStream_t s, int64_t n, const double* dinv, const double* R, const double* Zin,
+                    const int32_t* Pk, const double* Pw, const double* eH, double* Zout, double* rz_part) {
+  hipLaunchKernelGGL(k_zcoarse, dim3(spmm_blocks(n, 1)), dim3(TPB), 0, s, n, dinv, R, Zin, Pk, Pw, eH, Zout, rz_part);
 }
 void launch_cg_direction_f(hipStream_t s, int64_t n, int N, const double* dinv, const double* Rv, double* P,
                            const double* upd_part, const double* scal_in, const int32_t* flags_in, double* scal_out,
@@ -752,6 +804,12 @@ template void launch_cg_direction_t<double>(hipStream_t, int64_t, int, const dou
 template void launch_cg_direction_t<float>(hipStream_t, int64_t, int, const float*, const float*, float*,
                                            const double*, const double*, const int32_t*, double*, int32_t*, double,
                                            const PolyPC<float>*);
+template void launch_cg_direction_z<double>(hipStream_t, int64_t, int, const double*, const double*, double*,
+                                            const double*, const double*, const int32_t*, double*, int32_t*, double,
+                                            const double*, const double*);
+template void launch_cg_direction_z<float>(hipStream_t, int64_t, int, const float*, const float*, float*,
+                                           const double*, const double*, const int32_t*, double*, int32_t*, double,
+                                           const double*, const float*);
 template void launch_cheb_steps_t<double>(hipStream_t, int64_t, int, const int32_t*, const int32_t*, const double*,
                                           const double*, const double*, const PolyPC<double>&, double*,
                                           const int32_t*);

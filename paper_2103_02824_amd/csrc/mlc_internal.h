@@ -109,6 +109,9 @@ struct Dev {
   double* gdots = nullptr;      // 5N: Galerkin sums of the learned start
   int32_t* d2v = nullptr;       // n: library dof -> vertex
   double* lmax = nullptr;       // 2: Gershgorin bounds of D^-1 A (step 5) and D^-1 K (Hartree)
+  double* KHinv = nullptr;      // nH x nH: inverse of the coarse stiffness (two-level Hartree CG)
+  double* rH = nullptr;         // nH: restricted residual
+  double* eH = nullptr;         // nH: coarse correction
 };
 
 struct Options {
@@ -166,6 +169,7 @@ struct mlc_ctx {
   std::vector<double> h_KH;             // dense C_H = P^T K P (once per mesh)
   std::vector<double> h_Kh_chol;        // its Cholesky factor
   std::vector<double> h_MH;             // dense M_H
+  std::vector<double> h_KHinv;          // K_H^-1 (two-level Hartree CG; once per mesh)
   std::vector<double> last_theta2, last_phiH, last_wH;
   double last_theta1 = 0.0, last_sigma = 0.0;
   std::vector<double> last_small;       // packed small blocks of the fine stage
@@ -234,6 +238,18 @@ void launch_cheb_steps_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr,
                          const T* dinv, const T* Rv, const PolyPC<T>& pc, T* last_out, const int32_t* flags);
 void launch_cg_start2(hipStream_t s, int64_t n, int N, const double* partial, double rtol2, const double* mask,
                       double* scal, int32_t* flags, const double* rz_part);
+// Direction with an explicit preconditioned residual Zl and its r.z partials
+// (spmm_blocks(n, N) of them); null pointers: Jacobi on the fly.
+template <typename T>
+void launch_cg_direction_z(hipStream_t s, int64_t n, int N, const T* dinv, const T* Rv, T* P, const double* upd_part,
+                           const double* scal_in, const int32_t* flags_in, double* scal_out, int32_t* flags_out,
+                           double rtol2, const double* rz_part, const T* Zl);
+// Two-level correction (one column): eH = KHinv rH (dense); then
+// Zout = (Zin or D^-1 R) + P eH and per-block partials of R . Zout
+// (spmm_blocks(n, 1) blocks).
+void launch_dense_mv(hipStream_t s, int64_t m, const double* Ainv, const double* x, double* y);
+void launch_zcoarse(hipStream_t s, int64_t n, const double* dinv, const double* R, const double* Zin,
+                    const int32_t* Pk, const double* Pw, const double* eH, double* Zout, double* rz_part);
 void launch_gershgorin(hipStream_t s, int64_t n, const int32_t* rowptr, const double* val, const double* dinv,
                        double* partial, double* out);
 // cg.hip

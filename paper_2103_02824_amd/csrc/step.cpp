@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "nn.h"
 #include "phases.h"
@@ -43,6 +44,22 @@ int64_t small_len(int64_t nH, int N) { return SmallLayout(nH, N).total; }
 
 namespace {
 
+// Exact correction over the nested coarse space, added to the preconditioner:
+// z += P K_H^-1 P^T r (additive two-level preconditioner).
+struct CoarsePC {
+  const double* KHinv;
+  int64_t nH;
+  const int32_t* PTptr;
+  const int32_t* PTidx;
+  const double* PTw;
+  const int32_t* Pk;
+  const double* Pw;
+  double* rH;
+  double* eH;
+  double* Z;        // z without the polynomial preconditioner
+  double* rz_part;  // per-block r.z partials
+};
+
 template <typename T>
 struct CgArgs {
   const T* val;
@@ -53,7 +70,33 @@ struct CgArgs {
   int32_t* flags;
   const double* mask;  // optional: column c may be active only if mask[active c] != 0
   const PolyPC<T>* pc = nullptr;  // Chebyshev polynomial preconditioner (null: Jacobi)
+  const CoarsePC* cc = nullptr;  // additive coarse-space correction (one FP64 column only)
 };
+
+// The preconditioned residual of the iteration (or of the start, into P).
+template <typename T>
+void enqueue_precond(mlc_ctx* c, hipStream_t s, int64_t n, int N, const CgArgs<T>& a, const int32_t* flags,
+                     bool start, const double** rz_part, const T** Zl) {
+  auto& d = c->d;
+  *rz_part = nullptr;
+  *Zl = nullptr;
+  if (a.pc) {
+    launch_cheb_steps_t<T>(s, n, N, d.rowptr, d.col, a.val, a.dinv, a.R, *a.pc, start ? a.P : nullptr, flags);
+    *rz_part = a.pc->rz_part;
+    *Zl = start ? a.P : a.pc->Z[(a.pc->degree - 1) & 1];
+  }
+  if constexpr (std::is_same<T, double>::value) {
+    if (a.cc) {
+      const CoarsePC& cc = *a.cc;
+      launch_restrict(s, cc.nH, 1, cc.PTptr, cc.PTidx, cc.PTw, a.R, cc.rH);
+      launch_dense_mv(s, cc.nH, cc.KHinv, cc.rH, cc.eH);
+      double* zout = start ? a.P : (a.pc ? const_cast<double*>(*Zl) : cc.Z);
+      launch_zcoarse(s, n, a.dinv, a.R, a.pc ? *Zl : nullptr, cc.Pk, cc.Pw, cc.eH, zout, cc.rz_part);
+      *rz_part = cc.rz_part;
+      *Zl = zout;
+    }
+  }
+}
 
 // type-dispatched launchers
 inline void L_spmm(hipStream_t s, int64_t n, int N, const int32_t* rp, const int32_t* ci, const double* v,
@@ -86,8 +129,10 @@ mlc_status enqueue_iteration(mlc_ctx* c, hipStream_t s, int64_t n, int N, const 
   L_spmm(s, n, N, d.rowptr, d.col, a.val, a.P, a.Q, red_pq, fl_in);
   if (ev) HIPCHK(hipEventRecord(ev[1], s));
   launch_cg_update_t<T>(s, n, N, a.dinv, a.X, a.R, a.P, a.Q, red_pq, sc_in, fl_in, red_upd, a.flags + 4, a.pc);
-  if (a.pc) launch_cheb_steps_t<T>(s, n, N, d.rowptr, d.col, a.val, a.dinv, a.R, *a.pc, nullptr, fl_in);
-  launch_cg_direction_t<T>(s, n, N, a.dinv, a.R, a.P, red_upd, sc_in, fl_in, sc_out, fl_out, rt2, a.pc);
+  const double* rz_part;
+  const T* Zl;
+  enqueue_precond<T>(c, s, n, N, a, fl_in, false, &rz_part, &Zl);
+  launch_cg_direction_z<T>(s, n, N, a.dinv, a.R, a.P, red_upd, sc_in, fl_in, sc_out, fl_out, rt2, rz_part, Zl);
   return MLC_OK;
 }
 
@@ -99,8 +144,10 @@ void enqueue_start(mlc_ctx* c, hipStream_t s, int64_t n, int N, const CgArgs<T>&
   double* red_upd = d.red + c->nred / 2;
   L_spmm(s, n, N, d.rowptr, d.col, a.val, a.X, a.Q, nullptr, nullptr);
   launch_cg_init_t<T>(s, n, N, a.B, a.Q, a.dinv, a.R, a.P, red_upd, a.pc);
-  if (a.pc) launch_cheb_steps_t<T>(s, n, N, d.rowptr, d.col, a.val, a.dinv, a.R, *a.pc, a.P, nullptr);
-  launch_cg_start2(s, n, N, red_upd, rt2, a.mask, a.scal, a.flags, a.pc ? a.pc->rz_part : nullptr);
+  const double* rz_part;
+  const T* Zl;
+  enqueue_precond<T>(c, s, n, N, a, nullptr, true, &rz_part, &Zl);
+  launch_cg_start2(s, n, N, red_upd, rt2, a.mask, a.scal, a.flags, rz_part);
 }
 
 // Multi-column preconditioned CG, one independent recurrence per column;
@@ -123,7 +170,7 @@ mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs<T>& a, double
   int32_t hf[8];
   const int every = 2 * ((std::max(1, c->opt.check_every) + 1) / 2);
   const bool graph = c->opt.use_graphs && !timed && c->cap_stream;
-  const int pcdeg = a.pc ? a.pc->degree : 0;
+  const int pcdeg = (a.pc ? a.pc->degree : 0) + (a.cc ? 100 : 0);
   if (graph && (!c->cg_graph[kind] || c->cg_graph_chunk[kind] != every || c->cg_graph_rt2[kind] != rt2 ||
                 c->cg_graph_pc[kind] != pcdeg)) {
     if (c->cg_graph[kind]) HIPCHK(hipGraphExecDestroy(c->cg_graph[kind]));
@@ -599,8 +646,10 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
     int64_t dn = 0;
     PolyPC<double> pcK{d.lmax + 1, c->opt.cheb_ratio, c->opt.cheb_degree, {d.Y, d.Y + n}, d.Y + 2 * n,
                        d.red + cg_max_blocks()};
+    CoarsePC ccK{d.KHinv, c->nH, d.PTptr, d.PTidx, d.PTw, d.Pk, d.Pw, d.rH, d.eH, d.Y + 3 * n, d.red + cg_max_blocks()};
     CgArgs<double> pa{d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP, nullptr,
-                      c->opt.precond == MLC_PC_CHEBYSHEV ? &pcK : nullptr};
+                      c->opt.precond == MLC_PC_CHEBYSHEV ? &pcK : nullptr,
+                      c->opt.hartree_coarse && d.KHinv ? &ccK : nullptr};
     PHASE(cg<double>(c, 1, n, 1, pa, c->opt.poisson_rtol, c->opt.cg_maxit, false, &dummy, &dn, &S.pr));
   }
   PHASE(phase_gram(S));

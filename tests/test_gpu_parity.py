@@ -299,3 +299,39 @@ def test_chebyshev_graph_replay_matches_eager(gpu):
         ctx.close()
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("case,pc", [("c1", "jacobi"), ("c1", "chebyshev"), ("tiny2", "chebyshev")])
+def test_two_level_hartree_reaches_the_checker(gpu, case, pc):
+    """The Hartree CG with the additive coarse-space correction P K_H^-1 P^T
+    (on top of Jacobi or of the Chebyshev polynomial) gives the checker's
+    Hartree direction and step results; on top of Jacobi it also takes fewer
+    Hartree iterations (the polynomial already damps most of the spectrum,
+    and the sum of the two can take more)."""
+    from inputs.systems import tiny_system
+    from paper_2103_02824_amd import mlc
+    S = c1_hydrogen() if case == "c1" else tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=True,
+                                                        n_orbitals=2, seed=7)
+    print(f"case {case} two-level Hartree CG, preconditioner {pc}", flush=True)
+    prob = Problem(S)
+    st0, _ = initial_state(prob)
+    ref = correction_step(prob, st0, ORA_OPTS)
+    fs = ref.inter["fine"]
+    its = {}
+    for coarse in (0, 1):
+        opts = dict(LIB_OPTS, hartree_coarse=coarse,
+                    precond=mlc.PC_CHEBYSHEV if pc == "chebyshev" else mlc.PC_JACOBI)
+        ctx = mlc.Context(S, mlc.options(**opts))
+        ctx.set_state(st0.lam, st0.Phi, st0.w)
+        rep = ctx.correction_step()
+        its[coarse] = rep["poisson_iters"]
+        if coarse:
+            assert relerr(ctx.probe("W0", (ctx.n_dof,)), fs["w0"]) < 1e-8
+            lam, Phi, w, rho = ctx.get_results()
+            assert np.max(np.abs(lam - ref.state.lam)) < 1e-8, (lam, ref.state.lam)
+            assert relerr(rho, ref.rho_nodal) < 1e-6
+            assert rep["poisson_relres"] < 1e-12
+        ctx.close()
+    print(f"Hartree CG iterations: without coarse correction {its[0]}, with {its[1]}", flush=True)
+    if pc == "jacobi":
+        assert its[1] < its[0]
