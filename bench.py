@@ -135,7 +135,7 @@ def main():
                     help="CG preconditioner of the step-5 and Hartree solves")
     ap.add_argument("--cheb-degree", type=int, default=8)
     ap.add_argument("--cheb-ratio", type=float, default=100.0)
-    ap.add_argument("--hartree-coarse", type=int, default=0, choices=[0, 1],
+    ap.add_argument("--hartree-coarse", type=int, default=1, choices=[0, 1],
                     help="add the exact coarse-space correction to the Hartree CG preconditioner")
     ap.add_argument("--inner-maxit", type=int, default=60)
     ap.add_argument("--inner-tol", type=float, default=1e-9)
@@ -324,31 +324,33 @@ def run_batch(args):
     base = dict(cg_rtol=args.cg_rtol, poisson_rtol=args.cg_rtol, inner_maxit=args.batch_inner_maxit,
                 inner_tol=args.inner_tol)
     pcopt = dict(precond=mlc.PC_CHEBYSHEV if args.precond == "chebyshev" else mlc.PC_JACOBI,
-                 cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio)
+                 cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio, hartree_coarse=args.hartree_coarse)
+    pcname = args.precond + ("+coarse" if args.hartree_coarse else "")
     out = {}
     states = []
-    # plain FP64, one system at a time
-    ctxs = _batch_contexts(systems, mlc, states, **base)
-    dof_orb = sum(c.n_dof * c.N for c in ctxs)
-    for c in ctxs:
-        c.correction_step()
-    torch.cuda.synchronize()
-    t = 0.0
-    its = []
-    for c in ctxs:
-        r = c.correction_step()
-        t += r["t_fine_ms"] + r["t_recon_ms"]
-        its.append(r["cg_iters_max"])
-    out["plain_fp64_sequential"] = {"gpu_ms": t, "cg_iters": its}
-    log(f"[bench] plain FP64 one system at a time: {t:.2f} ms GPU, CG iterations {its}")
-    for c in ctxs:
-        c.close()
+    dof_orb = None
+    # one system at a time: the plain FP64 path (Jacobi-PCG) and the best single-system solver settings
+    for name, kw in (("plain_fp64_sequential", {}), (f"single_fp64_{pcname}_sequential", pcopt)):
+        ctxs = _batch_contexts(systems, mlc, states, **dict(base, **kw))
+        dof_orb = sum(c.n_dof * c.N for c in ctxs)
+        for c in ctxs:
+            c.correction_step()
+        torch.cuda.synchronize()
+        t = 0.0
+        its = []
+        for c in ctxs:
+            r = c.correction_step()
+            t += r["t_fine_ms"] + r["t_recon_ms"]
+            its.append((r["cg_iters_max"], r["poisson_iters"]))
+        out[name] = {"gpu_ms": t, "cg_and_hartree_iters": its}
+        log(f"[bench] {name}: {t:.2f} ms GPU, CG/Hartree iterations {its}")
+        for c in ctxs:
+            c.close()
     net, rows, l0, l1 = train_guess_network(mlc, args, base)
     for name, kw, learned in (("batched_fp64", {}, False),
-                              (f"batched_fp64_{args.precond}", pcopt, False),
-                              (f"batched_fp32ir_{args.precond}", dict(pcopt, precision=mlc.PREC_FP32_IR), False),
-                              (f"batched_fp32ir_{args.precond}_learned", dict(pcopt, precision=mlc.PREC_FP32_IR),
-                               True)):
+                              (f"batched_fp64_{pcname}", pcopt, False),
+                              (f"batched_fp32ir_{pcname}", dict(pcopt, precision=mlc.PREC_FP32_IR), False),
+                              (f"batched_fp32ir_{pcname}_learned", dict(pcopt, precision=mlc.PREC_FP32_IR), True)):
         ctxs = _batch_contexts(systems, mlc, states, **dict(base, **kw))
         if learned:
             for c in ctxs:
@@ -360,14 +362,16 @@ def run_batch(args):
         gpu = br["t_gpu_ms"] + br["t_recon_ms"]
         out[name] = {"gpu_ms": gpu, "solve_ms": br["t_solve_ms"], "poisson_ms": br["t_poisson_ms"],
                      "inner_ms": br["t_inner_ms"], "cg_iters": [r["cg_iters_max"] for r in reps],
+                     "hartree_iters": [r["poisson_iters"] for r in reps],
                      "tile_rows": br["tile_rows"], "lanes": br["spmm_lanes"], "ir_outer": br["ir_outer"],
                      "learned_cols": sum(r["guess_learned_cols"] for r in reps)}
         log(f"[bench] {name}: {gpu:.2f} ms GPU (solve {br['t_solve_ms']:.2f}, Hartree {br['t_poisson_ms']:.2f}), "
-            f"shape {br['tile_rows']}x{br['spmm_lanes']}, CG iterations {out[name]['cg_iters']}")
+            f"shape {br['tile_rows']}x{br['spmm_lanes']}, CG iterations {out[name]['cg_iters']}, "
+            f"Hartree {out[name]['hartree_iters']}")
         b.close()
         for c in ctxs:
             c.close()
-    best = out[f"batched_fp32ir_{args.precond}_learned"]["gpu_ms"]
+    best = out[f"batched_fp32ir_{pcname}_learned"]["gpu_ms"]
     res = {
         "metric": "fine-mesh SCF correction step: DoF*orbitals/s and % HBM roofline vs plain FP64",
         "value": dof_orb / (best / 1e3), "unit": "DoF*orbitals/s", "n_gpus": 1, "steps": 1, "warmup": 1,
@@ -375,9 +379,10 @@ def run_batch(args):
         "dtype": "f32+f64-refinement", "data": "synthetic",
         "config": {"workload": f"batch of {len(systems)} uneven seeded clusters (2-8 atoms, graded P1 meshes)",
                    "dof_orbitals": dof_orb, "cg_rtol": args.cg_rtol, "parallelism": "1 GPU",
-                   "timed_path": f"batched, FP32 CG + FP64 refinement, {args.precond} preconditioner, learned start"},
+                   "timed_path": f"batched, FP32 CG + FP64 refinement, {pcname} preconditioner, learned start"},
         "roofline": None, "cpu_baseline": None,
         "detail": dict(out, speedup_vs_plain_fp64=out["plain_fp64_sequential"]["gpu_ms"] / best,
+                       speedup_vs_best_single_sequential=out[f"single_fp64_{pcname}_sequential"]["gpu_ms"] / best,
                        training_rows=rows, training_loss=[l0, l1], total_wall_s=time.perf_counter() - t_all),
     }
     net.close()

@@ -133,7 +133,7 @@ typedef struct {
                            preconditioner over the nested coarse space; K_H =
                            P^T K P factorised on the host once per mesh, its
                            inverse applied on the device) to the preconditioner
-                           chosen by precond; single-system solves only        */
+                           chosen by precond                                   */
 } mlc_options;
 
 enum { MLC_PC_JACOBI = 0, MLC_PC_CHEBYSHEV = 1 };
@@ -336,8 +336,8 @@ mlc_status mlc_sample_count(const mlc_ctx* ctx, int64_t* rows);
  * either instead).
  *
  * mlc_batch_create: ctxs[0..count) distinct, bound contexts with the same
- * options.precision, precond, cheb_degree and cheb_ratio (MLC_ERR_ARG
- * otherwise); the batch keeps the pointers (the caller keeps the
+ * options.precision, precond, cheb_degree, cheb_ratio and hartree_coarse
+ * (MLC_ERR_ARG otherwise); the batch keeps the pointers (the caller keeps the
  * contexts alive, does not re-bind them and does not step them concurrently
  * with the batch). Systems may differ in mesh and orbital count.
  * mlc_batch_bind: device workspace of mlc_batch_workspace_bytes (256-byte

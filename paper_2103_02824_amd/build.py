@@ -22,7 +22,7 @@ HIP_FLAGS = [
     "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
-HOST_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-fopenmp", "-march=x86-64-v2"]
+HOST_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-fopenmp", "-march=x86-64-v2"]
 
 
 def _hipcc():

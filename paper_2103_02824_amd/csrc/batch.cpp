@@ -14,6 +14,7 @@
 #include "batch.h"
 #include "phases.h"
 
+using mlc::BCoarse;
 using mlc::BProb;
 
 struct mlc_batch {
@@ -43,6 +44,9 @@ struct mlc_batch {
   int32_t* tile_probP = nullptr; // Hartree tile table
   double* part = nullptr;
   double* part_rz = nullptr;     // r.z partials of the polynomial preconditioner
+  BCoarse* dC = nullptr;         // Hartree coarse corrections (null: none)
+  int32_t* crow_prob = nullptr;  // global coarse row -> Hartree problem
+  int64_t ncrows = 0;
   double *bsA = nullptr, *bsA32 = nullptr, *bsP = nullptr;
   int32_t *flA = nullptr, *flA32 = nullptr, *flP = nullptr;
   // graphs: 0 step-5 FP64, 1 Hartree, 2 step-5 FP32
@@ -103,6 +107,10 @@ size_t layout(mlc_batch* b, char* base) {
   b->flA = cv.take<int32_t>(K + 1);
   b->flA32 = cv.take<int32_t>(K + 1);
   b->flP = cv.take<int32_t>(KP + 1);
+  if (b->ncrows > 0) {
+    b->dC = cv.take<BCoarse>(KP);
+    b->crow_prob = cv.take<int32_t>(b->ncrows);
+  }
   return cv.off + 256;
 }
 
@@ -144,6 +152,21 @@ mlc_status upload_shape(mlc_batch* b, int TR) {
   if (!hP.empty()) {
     BCHK(hipMemcpyAsync(b->tile_probP, tpP.data(), sizeof(int32_t) * tpP.size(), hipMemcpyHostToDevice, s));
     BCHK(hipMemcpyAsync(b->dP, hP.data(), sizeof(BProb<double>) * hP.size(), hipMemcpyHostToDevice, s));
+  }
+  if (b->ncrows > 0) {
+    std::vector<BCoarse> hC;
+    std::vector<int32_t> crow;
+    int kq = 0;
+    for (mlc_ctx* c : b->ctx) {
+      if (!c->hartree) continue;
+      auto& d = c->d;
+      hC.push_back(BCoarse{d.PTptr, d.PTidx, d.PTw, d.Pk, d.Pw, d.KHinv, d.rH, d.eH, d.Y + 3 * c->n, c->nH,
+                           (int32_t)crow.size(), 0});
+      for (int64_t k = 0; k < c->nH; ++k) crow.push_back(kq);
+      ++kq;
+    }
+    BCHK(hipMemcpyAsync(b->dC, hC.data(), sizeof(BCoarse) * hC.size(), hipMemcpyHostToDevice, s));
+    BCHK(hipMemcpyAsync(b->crow_prob, crow.data(), sizeof(int32_t) * crow.size(), hipMemcpyHostToDevice, s));
   }
   BCHK(hipStreamSynchronize(s));
   b->TR = TR;
@@ -234,14 +257,15 @@ BPoly batch_poly(const mlc_batch* b) {
 template <typename T>
 mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* tile_prob, int ntiles,
                const std::vector<int>& Ns, double* bs, int32_t* fl, const double* mask_bs, double rtol, int maxit,
-               BRes* out) {
-  const BPoly poly = batch_poly(b);
+               BRes* out, const BCoarseSet* cs = nullptr) {
+  BPoly poly = batch_poly(b);
+  if (cs && cs->coarse && !poly.rz_part) poly.rz_part = b->part_rz;  // the coarse term's r.z partials
   hipStream_t s = b->stream;
   const int K = (int)Ns.size();
   const double rt2 = rtol * rtol;
   const int NB = b->NB;
   BCHK(hipMemsetAsync(fl + K, 0, sizeof(int32_t), s));
-  launch_b_start<T>(s, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, mask_bs, fl, rt2, poly);
+  launch_b_start<T>(s, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, mask_bs, fl, rt2, poly, cs);
   const int every = 2 * ((std::max(1, b->ctx[0]->opt.check_every) + 1) / 2);
   const bool graph = b->ctx[0]->opt.use_graphs != 0;
   if (graph && (!b->graph[kind] || b->graph_chunk[kind] != every || b->graph_rt2[kind] != rt2)) {
@@ -250,7 +274,8 @@ mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* til
     hipGraph_t g;
     BCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < every; ++k)
-      launch_b_iteration<T>(b->cap_stream, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, fl, rt2, poly);
+      launch_b_iteration<T>(b->cap_stream, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, fl, rt2, poly,
+                            cs);
     BCHK(hipStreamEndCapture(b->cap_stream, &g));
     hipError_t e = hipGraphInstantiate(&b->graph[kind], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -274,7 +299,7 @@ mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* til
       BCHK(hipGraphLaunch(b->graph[kind], s));
     } else {
       for (int k = 0; k < every; ++k)
-        launch_b_iteration<T>(s, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, fl, rt2, poly);
+        launch_b_iteration<T>(s, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, fl, rt2, poly, cs);
     }
     it += every;
   }
@@ -373,8 +398,9 @@ mlc_status solve_hartree(mlc_batch* b, BRes* res) {
   std::vector<int> Ns(b->KP, 1);
   const mlc_options& o = b->ctx[0]->opt;
   mlc_status st;
+  BCoarseSet cs{b->dC, b->crow_prob, b->ncrows};
   if ((st = bcg<double>(b, 1, b->dP, b->tile_probP, b->ntilesP, Ns, b->bsP, b->flP, nullptr, o.poisson_rtol,
-                        o.cg_maxit, res)) != MLC_OK)
+                        o.cg_maxit, res, b->dC ? &cs : nullptr)) != MLC_OK)
     return st;
   std::vector<char> done = res->done;
   std::vector<int> act;
@@ -447,8 +473,10 @@ mlc_status mlc_batch_create(mlc_ctx* const* ctxs, int32_t count, mlc_batch** out
         (c->opt.precond == MLC_PC_CHEBYSHEV &&
          (c->opt.cheb_degree != ctxs[0]->opt.cheb_degree || c->opt.cheb_ratio != ctxs[0]->opt.cheb_ratio)))
       return MLC_ERR_ARG;
+    if (c->opt.hartree_coarse != ctxs[0]->opt.hartree_coarse) return MLC_ERR_ARG;
     b->NB = std::max(b->NB, (int)c->N);
     b->KP += c->hartree ? 1 : 0;
+    if (c->hartree && c->opt.hartree_coarse) b->ncrows += c->nH;
   }
   b->max_tiles = std::max<int64_t>(tiles_for(b.get(), TR_MIN, false), 1);
   b->ws_bytes = layout(b.get(), nullptr);

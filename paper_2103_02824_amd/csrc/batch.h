@@ -42,6 +42,29 @@ struct BPoly {
   double* rz_part;  // per-tile r.z partials of the last step (tiles x NB)
 };
 
+// Additive coarse-space correction of one Hartree problem (one column).
+struct BCoarse {
+  const int32_t* PTptr;
+  const int32_t* PTidx;
+  const double* PTw;
+  const int32_t* Pk;
+  const double* Pw;
+  const double* KHinv;  // nH x nH
+  double* rH;
+  double* eH;
+  double* Zc;           // z when there is no polynomial preconditioner
+  int64_t nH;
+  int32_t row0;         // first global coarse row of this problem
+  int32_t pad;
+};
+
+// The coarse corrections of a batched Hartree solve (coarse == null: none).
+struct BCoarseSet {
+  const BCoarse* coarse;
+  const int32_t* crow_prob;  // global coarse row -> problem
+  int64_t nrows;
+};
+
 // Scalar slots per problem: bs[(p * 8 + k) * NB + c].
 enum { B_RZ = 0, B_RR, B_BB, B_ACT, B_IT, B_ALPHA, B_BETA, B_MASK };
 
@@ -50,11 +73,12 @@ void launch_b_spmm(hipStream_t s, const BProb<T>* probs, const int32_t* tile_pro
                    int mode, double* part, const int32_t* flags);
 template <typename T>
 void launch_b_iteration(hipStream_t s, const BProb<T>* probs, const int32_t* tile_prob, int ntiles, int K, int TR,
-                        int G, int NB, double* part, double* bs, int32_t* flags, double rtol2, const BPoly& poly);
+                        int G, int NB, double* part, double* bs, int32_t* flags, double rtol2, const BPoly& poly,
+                        const BCoarseSet* cs = nullptr);
 template <typename T>
 void launch_b_start(hipStream_t s, const BProb<T>* probs, const int32_t* tile_prob, int ntiles, int K, int TR, int G,
                     int NB, double* part, double* bs, const double* mask_bs, int32_t* flags, double rtol2,
-                    const BPoly& poly);
+                    const BPoly& poly, const BCoarseSet* cs = nullptr);
 void launch_b_ir(hipStream_t s, const BProb<double>* p64, const BProb<float>* p32, const int32_t* tile_prob,
                  int ntiles, int TR, int op);
 

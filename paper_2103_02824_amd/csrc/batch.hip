@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "batch.h"
 
@@ -383,6 +384,108 @@ __global__ void __launch_bounds__(BS) kb_alpha(const BProb<T>* __restrict__ prob
   }
 }
 
+// Coarse-space correction of batched Hartree problems (one column each).
+// Restriction rH = P^T R, one block per global coarse row.
+__global__ void __launch_bounds__(BS) kb_restrict(const BProb<double>* __restrict__ probs,
+                                                  const BCoarse* __restrict__ cs, const int32_t* __restrict__ crow_prob,
+                                                  const int32_t* __restrict__ flags, int check) {
+  __shared__ double ws[BS / 64];
+  const int g = blockIdx.x;
+  const int p = crow_prob[g];
+  if (check && flags[p] == 0) return;
+  const BCoarse C = cs[p];
+  const double* R = probs[p].R;
+  const int64_t k = g - C.row0;
+  double acc = 0.0;
+  for (int e = C.PTptr[k] + (int)threadIdx.x; e < C.PTptr[k + 1]; e += BS) acc += C.PTw[e] * R[C.PTidx[e]];
+  acc = wsum(acc);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) ws[wid] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) C.rH[k] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+// eH = KHinv rH, one wavefront per global coarse row.
+__global__ void __launch_bounds__(BS) kb_coarse_mv(const BCoarse* __restrict__ cs, const int32_t* __restrict__ crow_prob,
+                                                   int64_t nrows, const int32_t* __restrict__ flags, int check) {
+  const int64_t g = (int64_t)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+  if (g >= nrows) return;
+  const int p = crow_prob[g];
+  if (check && flags[p] == 0) return;
+  const BCoarse C = cs[p];
+  const int64_t k = g - C.row0;
+  const int lane = threadIdx.x & 63;
+  const double* a = C.KHinv + k * C.nH;
+  double acc = 0.0;
+  for (int64_t j = lane; j < C.nH; j += 64) acc += a[j] * C.rH[j];
+  acc = wsum(acc);
+  if (lane == 0) C.eH[k] = acc;
+}
+
+// z = (Zin or D^-1 R) + P eH over a tile into Zout; per-tile r.z partials.
+// zsrc: 0 D^-1 R, 1 Z0, 2 Z1 (the polynomial's last block); zdst: 0 P, 1 Z0,
+// 2 Z1, 3 the coarse-only buffer Zc.
+__global__ void __launch_bounds__(BS) kb_zcoarse(const BProb<double>* __restrict__ probs,
+                                                 const BCoarse* __restrict__ cs, const int32_t* __restrict__ tile_prob,
+                                                 int TR, int NB, int zsrc, int zdst, double* __restrict__ rz_part,
+                                                 const int32_t* __restrict__ flags, int check) {
+  __shared__ double ws[BS / 64];
+  const int t = blockIdx.x;
+  const int p = tile_prob[t];
+  if (check && flags[p] == 0) return;
+  const BProb<double> D = probs[p];
+  const BCoarse C = cs[p];
+  const int64_t r0 = (int64_t)(t - D.tile0) * TR;
+  const int64_t r1 = r0 + TR < D.n ? r0 + TR : D.n;
+  const double* zin = zsrc == 1 ? D.Z0 : (zsrc == 2 ? D.Z1 : nullptr);
+  double* zout = zdst == 0 ? D.P : (zdst == 1 ? D.Z0 : (zdst == 2 ? D.Z1 : C.Zc));
+  double dot = 0.0;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += BS) {
+    double z = zin ? zin[i] : D.dinv[i] * D.R[i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = C.Pk[4 * i + j];
+      if (k >= 0) z += C.Pw[4 * i + j] * C.eH[k];
+    }
+    zout[i] = z;
+    dot += D.R[i] * z;
+  }
+  dot = wsum(dot);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) ws[wid] = dot;
+  __syncthreads();
+  if (threadIdx.x == 0) rz_part[(int64_t)t * NB] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+// The start with the polynomial: P already holds p(D^-1 A) D^-1 R; add P eH.
+__global__ void __launch_bounds__(BS) kb_zcoarse_p(const BProb<double>* __restrict__ probs,
+                                                   const BCoarse* __restrict__ cs, const int32_t* __restrict__ tile_prob,
+                                                   int TR, int NB, double* __restrict__ rz_part) {
+  __shared__ double ws[BS / 64];
+  const int t = blockIdx.x;
+  const int p = tile_prob[t];
+  const BProb<double> D = probs[p];
+  const BCoarse C = cs[p];
+  const int64_t r0 = (int64_t)(t - D.tile0) * TR;
+  const int64_t r1 = r0 + TR < D.n ? r0 + TR : D.n;
+  double dot = 0.0;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += BS) {
+    double z = D.P[i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = C.Pk[4 * i + j];
+      if (k >= 0) z += C.Pw[4 * i + j] * C.eH[k];
+    }
+    D.P[i] = z;
+    dot += D.R[i] * z;
+  }
+  dot = wsum(dot);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) ws[wid] = dot;
+  __syncthreads();
+  if (threadIdx.x == 0) rz_part[(int64_t)t * NB] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
 // X += alpha P, R -= alpha Q over a tile; partials of r.Dr and r.r.
 template <typename T>
 __global__ void __launch_bounds__(BS) kb_update(const BProb<T>* __restrict__ probs, const int32_t* __restrict__ tile_prob,
@@ -474,7 +577,7 @@ template <typename T>
 __global__ void __launch_bounds__(BS) kb_direction(const BProb<T>* __restrict__ probs,
                                                    const int32_t* __restrict__ tile_prob, int TR, int NB,
                                                    const double* __restrict__ bs, const int32_t* __restrict__ flags,
-                                                   int degree) {
+                                                   int degree, const BCoarse* __restrict__ cs) {
   const int t = blockIdx.x;
   const int p = tile_prob[t];
   if (flags[p] == 0) return;
@@ -486,6 +589,9 @@ __global__ void __launch_bounds__(BS) kb_direction(const BProb<T>* __restrict__ 
   const int64_t r0 = (int64_t)(t - D.tile0) * TR;
   const int64_t r1 = r0 + TR < D.n ? r0 + TR : D.n;
   const T* Zl = degree >= 2 ? (((degree - 1) & 1) ? D.Z1 : D.Z0) : nullptr;
+  if constexpr (std::is_same<T, double>::value) {
+    if (cs && degree < 2) Zl = cs[p].Zc;  // coarse correction on top of Jacobi
+  }
   for (int64_t i = r0 * N + threadIdx.x; i < r1 * N; i += BS) {
     int64_t r = i / N;
     int c = (int)(i - r * N);
@@ -626,32 +732,62 @@ void launch_b_cheb(hipStream_t s, const BProb<T>* probs, const int32_t* tile_pro
   }
 }
 
+// The coarse correction after the polynomial steps (or on top of Jacobi):
+// restriction, coarse solve, z += P eH with the per-tile r.z partials.
+template <typename T>
+void launch_b_coarse(hipStream_t s, const BProb<T>* probs, const int32_t* tile_prob, int ntiles, int TR, int NB,
+                     const BPoly& poly, const BCoarseSet& cs, const int32_t* flags, bool start) {
+  if constexpr (std::is_same<T, double>::value) {
+    const int check = start ? 0 : 1;
+    const bool pc = poly.degree >= 2;
+    const int last = pc ? (((poly.degree - 1) & 1) ? 2 : 1) : 0;
+    const int zsrc = start ? (pc ? 3 : 0) : last;  // at the start the polynomial wrote P
+    const int zdst = start ? 0 : (pc ? last : 3);
+    hipLaunchKernelGGL(kb_restrict, dim3((unsigned)cs.nrows), dim3(BS), 0, s, probs, cs.coarse, cs.crow_prob, flags,
+                       check);
+    hipLaunchKernelGGL(kb_coarse_mv, dim3((unsigned)((cs.nrows + 3) / 4)), dim3(BS), 0, s, cs.coarse, cs.crow_prob,
+                       cs.nrows, flags, check);
+    if (zsrc == 3) {
+      // the polynomial's result is in P: add the correction in place
+      hipLaunchKernelGGL(kb_zcoarse_p, dim3(ntiles), dim3(BS), 0, s, probs, cs.coarse, tile_prob, TR, NB, poly.rz_part);
+    } else {
+      hipLaunchKernelGGL(kb_zcoarse, dim3(ntiles), dim3(BS), 0, s, probs, cs.coarse, tile_prob, TR, NB, zsrc, zdst,
+                         poly.rz_part, flags, check);
+    }
+  }
+}
+
 template <typename T>
 void launch_b_iteration(hipStream_t s, const BProb<T>* probs, const int32_t* tile_prob, int ntiles, int K, int TR,
-                        int G, int NB, double* part, double* bs, int32_t* flags, double rtol2, const BPoly& poly) {
+                        int G, int NB, double* part, double* bs, int32_t* flags, double rtol2, const BPoly& poly,
+                        const BCoarseSet* cs) {
   const bool pc = poly.degree >= 2;
+  const bool cc = cs && cs->coarse;
   launch_b_spmm<T>(s, probs, tile_prob, ntiles, TR, G, NB, 0, part, flags);
   hipLaunchKernelGGL((kb_alpha<T>), dim3(K), dim3(BS), 0, s, probs, NB, part, bs, flags, K);
   hipLaunchKernelGGL((kb_update<T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, bs, flags, part,
                      poly.ratio);
   if (pc) launch_b_cheb<T>(s, probs, tile_prob, ntiles, TR, G, NB, poly, 0, flags);
+  if (cc) launch_b_coarse<T>(s, probs, tile_prob, ntiles, TR, NB, poly, *cs, flags, false);
   hipLaunchKernelGGL((kb_beta<T>), dim3(K), dim3(BS), 0, s, probs, NB, part, bs, flags, rtol2,
-                     pc ? poly.rz_part : nullptr);
+                     (pc || cc) ? poly.rz_part : nullptr);
   hipLaunchKernelGGL((kb_direction<T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, bs, flags,
-                     pc ? poly.degree : 0);
+                     pc ? poly.degree : 0, cc ? cs->coarse : nullptr);
 }
 
 template <typename T>
 void launch_b_start(hipStream_t s, const BProb<T>* probs, const int32_t* tile_prob, int ntiles, int K, int TR, int G,
                     int NB, double* part, double* bs, const double* mask_bs, int32_t* flags, double rtol2,
-                    const BPoly& poly) {
+                    const BPoly& poly, const BCoarseSet* cs) {
   const bool pc = poly.degree >= 2;
+  const bool cc = cs && cs->coarse;
   launch_b_spmm<T>(s, probs, tile_prob, ntiles, TR, G, NB, 1, part, flags);
   hipLaunchKernelGGL((kb_init<T>), dim3(ntiles), dim3(BS), 0, s, probs, tile_prob, TR, NB, part, pc ? 1 : 0,
                      poly.ratio);
   if (pc) launch_b_cheb<T>(s, probs, tile_prob, ntiles, TR, G, NB, poly, 1, flags);
+  if (cc) launch_b_coarse<T>(s, probs, tile_prob, ntiles, TR, NB, poly, *cs, flags, true);
   hipLaunchKernelGGL((kb_start<T>), dim3(K), dim3(BS), 0, s, probs, NB, part, bs, mask_bs, flags, rtol2,
-                     pc ? poly.rz_part : nullptr);
+                     (pc || cc) ? poly.rz_part : nullptr);
 }
 
 void launch_b_ir(hipStream_t s, const BProb<double>* p64, const BProb<float>* p32, const int32_t* tile_prob,
@@ -664,12 +800,13 @@ template void launch_b_spmm<double>(hipStream_t, const BProb<double>*, const int
 template void launch_b_spmm<float>(hipStream_t, const BProb<float>*, const int32_t*, int, int, int, int, int, double*,
                                    const int32_t*);
 template void launch_b_iteration<double>(hipStream_t, const BProb<double>*, const int32_t*, int, int, int, int, int,
-                                         double*, double*, int32_t*, double, const BPoly&);
+                                         double*, double*, int32_t*, double, const BPoly&, const BCoarseSet*);
 template void launch_b_iteration<float>(hipStream_t, const BProb<float>*, const int32_t*, int, int, int, int, int,
-                                        double*, double*, int32_t*, double, const BPoly&);
+                                        double*, double*, int32_t*, double, const BPoly&, const BCoarseSet*);
 template void launch_b_start<double>(hipStream_t, const BProb<double>*, const int32_t*, int, int, int, int, int,
-                                     double*, double*, const double*, int32_t*, double, const BPoly&);
+                                     double*, double*, const double*, int32_t*, double, const BPoly&,
+                                     const BCoarseSet*);
 template void launch_b_start<float>(hipStream_t, const BProb<float>*, const int32_t*, int, int, int, int, int, double*,
-                                    double*, const double*, int32_t*, double, const BPoly&);
+                                    double*, const double*, int32_t*, double, const BPoly&, const BCoarseSet*);
 
 }  // namespace mlc

@@ -56,12 +56,15 @@ def _contexts(cases, **kw):
 
 
 @pytest.mark.parametrize("prec,pc", [("fp64", "jacobi"), ("fp32ir", "jacobi"), ("fp64", "chebyshev"),
-                                     ("fp32ir", "chebyshev")])
+                                     ("fp32ir", "chebyshev"), ("fp64", "jacobi+coarse"),
+                                     ("fp64", "chebyshev+coarse"), ("fp32ir", "chebyshev+coarse")])
 def test_batch_step_matches_checker(cases, prec, pc):
     from paper_2103_02824_amd import mlc
     kw = {} if prec == "fp64" else dict(precision=mlc.PREC_FP32_IR, ir_inner_rtol=1e-4)
-    if pc == "chebyshev":
+    if pc.startswith("chebyshev"):
         kw.update(precond=mlc.PC_CHEBYSHEV, cheb_degree=6, cheb_ratio=100.0)
+    if pc.endswith("coarse"):
+        kw.update(hartree_coarse=1)
     print(f"case batch of {[c[0] for c in cases]} precision {prec} preconditioner {pc}", flush=True)
     ctxs = _contexts(cases, **kw)
     batch = mlc.Batch(ctxs)
@@ -109,3 +112,36 @@ def test_batch_equals_single_steps_over_two_steps(cases):
     batch.close()
     for c in single + ctxs:
         c.close()
+
+
+def test_batch_coarse_correction_matches_single_context_iterations(cases):
+    """The batched Hartree CG with the coarse-space correction takes the
+    iterations of the single-context two-level solve (Jacobi and polynomial
+    smoothers, within one) and reaches its potential; the hydrogen system's
+    count against plain Jacobi is reported."""
+    from paper_2103_02824_amd import mlc
+    for pc in ("jacobi", "chebyshev"):
+        print(f"case batch vs single contexts, two-level Hartree, {pc}", flush=True)
+        kw = dict(hartree_coarse=1)
+        if pc == "chebyshev":
+            kw.update(precond=mlc.PC_CHEBYSHEV, cheb_degree=6, cheb_ratio=100.0)
+        single = _contexts(cases, **kw)
+        srep = [c.correction_step() for c in single]
+        ctxs = _contexts(cases, **kw)
+        batch = mlc.Batch(ctxs)
+        reps, br = batch.step()
+        for (name, S, *_), a, b, ra, rb in zip(cases, single, ctxs, srep, reps):
+            if not S.hartree:
+                continue
+            assert abs(ra["poisson_iters"] - rb["poisson_iters"]) <= 1, (name, pc, ra["poisson_iters"],
+                                                                        rb["poisson_iters"])
+            wa, wb = a.probe("W0", (a.n_dof,)), b.probe("W0", (b.n_dof,))
+            assert relerr(wb, wa) < 1e-9, (name, pc, relerr(wb, wa))
+        batch.close()
+        for c in single + ctxs:
+            c.close()
+    plain = _contexts(cases[:1])
+    rp = plain[0].correction_step()
+    plain[0].close()
+    print(f"c1 Hartree iterations: Jacobi {rp['poisson_iters']}, two-level (batched) {reps[0]['poisson_iters']}",
+          flush=True)
