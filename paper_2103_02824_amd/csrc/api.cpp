@@ -514,9 +514,11 @@ mlc_status mlc_bind(mlc_ctx* c, void* dev_workspace, size_t bytes, void* hip_str
   c->ev_pool.clear();
   c->ev_used = 0;
   for (int k = 0; k < 3; ++k) {
-    if (c->cg_graph[k]) (void)hipGraphExecDestroy(c->cg_graph[k]);
-    c->cg_graph[k] = nullptr;
-    c->cg_graph_chunk[k] = 0;
+    for (auto& g : c->cg_graph[k]) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+    c->cg_pred[k] = 0;
   }
   if (c->opt.use_graphs && !c->cap_stream) {
     hipError_t he = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
@@ -708,8 +710,9 @@ const char* mlc_last_error(const mlc_ctx* c) { return c ? c->err.c_str() : "null
 void mlc_destroy(mlc_ctx* c) {
   if (!c) return;
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-  for (int k = 0; k < 3; ++k)
-    if (c->cg_graph[k]) (void)hipGraphExecDestroy(c->cg_graph[k]);
+  for (auto& gk : c->cg_graph)
+    for (hipGraphExec_t g : gk)
+      if (g) (void)hipGraphExecDestroy(g);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }

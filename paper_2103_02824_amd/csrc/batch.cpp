@@ -50,9 +50,11 @@ struct mlc_batch {
   double *bsA = nullptr, *bsA32 = nullptr, *bsP = nullptr;
   int32_t *flA = nullptr, *flA32 = nullptr, *flP = nullptr;
   // graphs: 0 step-5 FP64, 1 Hartree, 2 step-5 FP32
-  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
-  int graph_chunk[3] = {0, 0, 0};
+  // per kind and chunk size (2 << g iterations), with the tolerance they were
+  // captured with and the last solve's iterations
+  hipGraphExec_t graph[3][mlc::CHUNK_GRAPHS] = {};
   double graph_rt2[3] = {0, 0, 0};
+  int pred[3] = {0, 0, 0};
   std::string err;
 };
 
@@ -172,11 +174,12 @@ mlc_status upload_shape(mlc_batch* b, int TR) {
   b->TR = TR;
   b->ntiles = (int)tp.size();
   b->ntilesP = (int)tpP.size();
-  for (auto& g : b->graph)
-    if (g) {
-      (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  for (auto& gk : b->graph)
+    for (auto& g : gk)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
   return MLC_OK;
 }
 
@@ -268,24 +271,35 @@ mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* til
   launch_b_start<T>(s, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, mask_bs, fl, rt2, poly, cs);
   const int every = 2 * ((std::max(1, b->ctx[0]->opt.check_every) + 1) / 2);
   const bool graph = b->ctx[0]->opt.use_graphs != 0;
-  if (graph && (!b->graph[kind] || b->graph_chunk[kind] != every || b->graph_rt2[kind] != rt2)) {
-    if (b->graph[kind]) BCHK(hipGraphExecDestroy(b->graph[kind]));
-    b->graph[kind] = nullptr;
-    hipGraph_t g;
-    BCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < every; ++k)
-      launch_b_iteration<T>(b->cap_stream, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, fl, rt2, poly,
-                            cs);
-    BCHK(hipStreamEndCapture(b->cap_stream, &g));
-    hipError_t e = hipGraphInstantiate(&b->graph[kind], g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return bfail(b, MLC_ERR_HIP, "hipGraphInstantiate (batch)");
-    b->graph_chunk[kind] = every;
+  auto* graphs = b->graph[kind];
+  if (graph && b->graph_rt2[kind] != rt2) {
+    for (int g = 0; g < mlc::CHUNK_GRAPHS; ++g) {
+      if (graphs[g]) BCHK(hipGraphExecDestroy(graphs[g]));
+      graphs[g] = nullptr;
+    }
     b->graph_rt2[kind] = rt2;
   }
+  auto launch_graph = [&](int g) -> mlc_status {
+    if (!graphs[g]) {
+      hipGraph_t gr;
+      BCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < (2 << g); ++k)
+        launch_b_iteration<T>(b->cap_stream, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, fl, rt2,
+                              poly, cs);
+      BCHK(hipStreamEndCapture(b->cap_stream, &gr));
+      hipError_t e = hipGraphInstantiate(&graphs[g], gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      if (e != hipSuccess) {
+        graphs[g] = nullptr;
+        return bfail(b, MLC_ERR_HIP, "hipGraphInstantiate (batch)");
+      }
+    }
+    BCHK(hipGraphLaunch(graphs[g], s));
+    return MLC_OK;
+  };
   std::vector<int32_t> hf(K + 1);
-  int it = 0;
-  for (;;) {
+  int it = 0, len = 0;
+  for (int chunk = 0;; ++chunk) {
     BCHK(hipMemcpyAsync(hf.data(), fl, sizeof(int32_t) * (K + 1), hipMemcpyDeviceToHost, s));
     BCHK(hipStreamSynchronize(s));
     if (hf[K]) {
@@ -295,13 +309,18 @@ mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* til
     bool any = false;
     for (int p = 0; p < K; ++p) any = any || hf[p] != 0;
     if (!any || it >= maxit) break;
+    len = mlc::chunk_length(chunk, len, b->pred[kind], every);
     if (graph) {
-      BCHK(hipGraphLaunch(b->graph[kind], s));
+      mlc_status st = MLC_OK;
+      mlc::for_chunk_graphs(len, [&](int g) {
+        if (st == MLC_OK) st = launch_graph(g);
+      });
+      if (st != MLC_OK) return st;
     } else {
-      for (int k = 0; k < every; ++k)
+      for (int k = 0; k < len; ++k)
         launch_b_iteration<T>(s, probs, tile_prob, ntiles, K, b->TR, b->G, NB, b->part, bs, fl, rt2, poly, cs);
     }
-    it += every;
+    it += len;
   }
   std::vector<double> hs((size_t)K * 8 * NB);
   BCHK(hipMemcpyAsync(hs.data(), bs, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, s));
@@ -312,6 +331,7 @@ mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* til
   }
   out->done.assign(K, 0);
   for (int p = 0; p < K; ++p) out->done[p] = hf[p] == 0 && !hf[K];
+  int itmax = 0;
   for (int p = 0; p < K; ++p) {
     int mx = 0;
     for (int c = 0; c < Ns[p]; ++c) {
@@ -320,7 +340,11 @@ mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* til
       out->iters_sum[p] += ic;
     }
     out->iters[p] += mx;
+    itmax = std::max(itmax, mx);
   }
+  bool all = !hf[K];
+  for (int p = 0; p < K; ++p) all = all && hf[p] == 0;
+  if (all) b->pred[kind] = itmax;
   return MLC_OK;
 }
 
@@ -495,11 +519,12 @@ mlc_status mlc_batch_bind(mlc_batch* b, void* workspace, size_t bytes, void* str
   if (bytes < b->ws_bytes) return bfail(b, MLC_ERR_WORKSPACE, "batch workspace too small");
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
     return bfail(b, MLC_ERR_WORKSPACE, "batch workspace must be 256-byte aligned");
-  for (auto& g : b->graph)
-    if (g) {
-      (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  for (auto& gk : b->graph)
+    for (auto& g : gk)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
   if (!b->cap_stream) BCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
   while ((int)b->sys_stream.size() < b->K) {
     hipStream_t st;
@@ -675,8 +700,9 @@ const char* mlc_batch_last_error(const mlc_batch* b) { return b ? b->err.c_str()
 
 void mlc_batch_destroy(mlc_batch* b) {
   if (!b) return;
-  for (auto& g : b->graph)
-    if (g) (void)hipGraphExecDestroy(g);
+  for (auto& gk : b->graph)
+    for (hipGraphExec_t g : gk)
+      if (g) (void)hipGraphExecDestroy(g);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   for (hipStream_t st : b->sys_stream) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : b->sys_event) (void)hipEventDestroy(ev);

@@ -34,6 +34,7 @@ constexpr int SPMM_BS = 1024;      // CG SpMM block size (16 waves per block)
 // slower, because the blocks past the first round run on a half-empty chip.
 constexpr int SPMM_MAXBLK = 512;
 constexpr int VEC_MAXBLK = 512;    // update / direction grid cap
+constexpr int NXCD = 8;            // XCDs of the chip, each with its own L2
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -55,6 +56,64 @@ __device__ __forceinline__ void block_reduce_cols(double* sd, int R, int N) {
 }
 
 inline int cap(int64_t needed, int mx) { return (int)(needed < mx ? (needed < 1 ? 1 : needed) : mx); }
+// grids of the row-block kernels: a multiple of the XCD count (mx is one)
+inline int cap_xcd(int64_t needed, int mx) { return cap((needed + NXCD - 1) / NXCD * NXCD, mx); }
+
+// Row blocks of a grid-stride loop, XCD-aware. Workgroups are dispatched to
+// the XCDs round robin (workgroup w runs on XCD w % NXCD) and each XCD has its
+// own L2; XCD x takes the contiguous x-th eighth of the nrb row blocks, so
+// the rows of X that its blocks gather (neighbours of neighbouring rows)
+// stay in that L2. Grids that are not a multiple of NXCD stride plainly.
+struct RowBlocks {
+  int64_t first, step, end;
+  __device__ explicit RowBlocks(int64_t nrb) {
+    const int g = (int)gridDim.x;
+    if (g % NXCD != 0) {
+      first = blockIdx.x;
+      step = g;
+      end = nrb;
+      return;
+    }
+    const int x = (int)blockIdx.x % NXCD;
+    first = nrb * x / NXCD + (int64_t)blockIdx.x / NXCD;
+    step = g / NXCD;
+    end = nrb * (x + 1) / NXCD;
+  }
+};
+
+// Nonzeros per lane and pass of row_gather: enough gathers in flight while
+// the kernel still fits 64 VGPRs (eight waves per SIMD, two 1024-thread blocks
+// per CU).
+constexpr int gather_unroll(int NT, int G) { return G >= 8 ? 2 : (NT <= 3 ? 4 : (NT <= 6 ? 2 : 1)); }
+
+// acc[c] += sum over this lane's nonzeros of row r (every G-th from
+// rowptr[r] + sub) of a_rj X[j][c]; U nonzeros per pass have their column
+// and value loads issued together, then their gathers. Entries past the row
+// end read row r itself with a zero weight (the same terms in the same order
+// as a plain loop, since adding +0 changes nothing).
+template <int NT, int G, int U, typename T>
+__device__ __forceinline__ void row_gather(int64_t r, int sub, const int32_t* __restrict__ rowptr,
+                                           const int32_t* __restrict__ col, const T* __restrict__ val,
+                                           const T* __restrict__ X, T (&acc)[NT]) {
+  const int j1 = rowptr[r + 1];
+  for (int j = rowptr[r] + sub; j < j1; j += G * U) {
+    int cc[U];
+    T vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = j + u * G;
+      const bool ok = e < j1;
+      cc[u] = ok ? col[e] : (int)r;
+      vv[u] = ok ? val[e] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const T* xr = X + (int64_t)cc[u] * NT;
+#pragma unroll
+      for (int c = 0; c < NT; ++c) acc[c] += vv[u] * xr[c];
+    }
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Chebyshev polynomial preconditioner z = p(D^-1 A) D^-1 r: the first m steps
@@ -89,7 +148,7 @@ __device__ __forceinline__ void cheb_coef(double lmax, double ratio, int j, doub
 // read coalesced (G consecutive entries), X rows as NT consecutive doubles.
 // Optional CG epilogue: per-block column sums of P . Q.
 template <int NT, int G, int BS, typename T>
-__global__ void __launch_bounds__(BS) k_spmm_small(int64_t n, const int32_t* __restrict__ rowptr,
+__global__ void __launch_bounds__(BS, NT <= 6 ? 8 : 4) k_spmm_small(int64_t n, const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
                                                    const T* __restrict__ X, T* __restrict__ Y,
                                                    double* __restrict__ partial, const int32_t* __restrict__ flags) {
@@ -101,20 +160,13 @@ __global__ void __launch_bounds__(BS) k_spmm_small(int64_t n, const int32_t* __r
   double dot[NT];
 #pragma unroll
   for (int c = 0; c < NT; ++c) dot[c] = 0.0;
-  for (int64_t r0 = (int64_t)blockIdx.x * RB; r0 < n; r0 += (int64_t)gridDim.x * RB) {
-    int64_t r = r0 + rl;
+  const RowBlocks rbk((n + RB - 1) / RB);
+  for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
+    int64_t r = rb * RB + rl;
     T acc[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[c] = T(0);
-    if (r < n) {
-      int j1 = rowptr[r + 1];
-      for (int j = rowptr[r] + sub; j < j1; j += G) {
-        T a = val[j];
-        const T* xr = X + (int64_t)col[j] * NT;
-#pragma unroll
-        for (int c = 0; c < NT; ++c) acc[c] += a * xr[c];
-      }
-    }
+    if (r < n) row_gather<NT, G, gather_unroll(NT, G)>(r, sub, rowptr, col, val, X, acc);
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
@@ -185,7 +237,7 @@ __global__ void __launch_bounds__(TPB) k_spmm_wide(int64_t n, int N, const int32
 // w = A Zin; d = cd d + cr D^-1 (R - w); Zout = Zin + d; optional per-block
 // column sums of R . Zout (the r.z of CG after the last step).
 template <int NT, int G, int BS, typename T>
-__global__ void __launch_bounds__(BS) k_cheb_small(int64_t n, const int32_t* __restrict__ rowptr,
+__global__ void __launch_bounds__(BS, NT <= 6 ? 8 : 4) k_cheb_small(int64_t n, const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
                                                    const T* __restrict__ dinv, const T* __restrict__ R,
                                                    const T* __restrict__ Zin, T* __restrict__ Zout, T* __restrict__ Dd,
@@ -202,20 +254,13 @@ __global__ void __launch_bounds__(BS) k_cheb_small(int64_t n, const int32_t* __r
   double dot[NT];
 #pragma unroll
   for (int c = 0; c < NT; ++c) dot[c] = 0.0;
-  for (int64_t r0 = (int64_t)blockIdx.x * RB; r0 < n; r0 += (int64_t)gridDim.x * RB) {
-    int64_t r = r0 + rl;
+  const RowBlocks rbk((n + RB - 1) / RB);
+  for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
+    int64_t r = rb * RB + rl;
     T acc[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[c] = T(0);
-    if (r < n) {
-      int j1 = rowptr[r + 1];
-      for (int e = rowptr[r] + sub; e < j1; e += G) {
-        T a = val[e];
-        const T* zr = Zin + (int64_t)col[e] * NT;
-#pragma unroll
-        for (int c = 0; c < NT; ++c) acc[c] += a * zr[c];
-      }
-    }
+    if (r < n) row_gather<NT, G, gather_unroll(NT, G)>(r, sub, rowptr, col, val, Zin, acc);
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
@@ -589,7 +634,7 @@ void spmm_small(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* 
                 double* partial, const int32_t* flags, int maxblk) {
   constexpr int G = NT == 1 ? 8 : 4;
   int64_t needed = (n + (BS / G) - 1) / (BS / G);
-  hipLaunchKernelGGL((k_spmm_small<NT, G, BS, T>), dim3(cap(needed, maxblk)), dim3(BS), 0, s, n, rowptr, col, val, X,
+  hipLaunchKernelGGL((k_spmm_small<NT, G, BS, T>), dim3(cap_xcd(needed, maxblk)), dim3(BS), 0, s, n, rowptr, col, val, X,
                      Y, partial, flags);
 }
 
@@ -645,7 +690,7 @@ int cg_blocks(int64_t n, int N) {
 int spmm_blocks(int64_t n, int N) {
   if (N <= 8) {
     int G = N == 1 ? 8 : 4;
-    return cap((n + (SPMM_BS / G) - 1) / (SPMM_BS / G), SPMM_MAXBLK);
+    return cap_xcd((n + (SPMM_BS / G) - 1) / (SPMM_BS / G), SPMM_MAXBLK);
   }
   return cg_blocks(n, N);
 }
@@ -757,7 +802,7 @@ void launch_cheb_steps_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr,
   case K: {                                                                                                       \
     constexpr int G = K == 1 ? 8 : 4;                                                                             \
     int64_t needed = (n + (SPMM_BS / G) - 1) / (SPMM_BS / G);                                                     \
-    hipLaunchKernelGGL((k_cheb_small<K, G, SPMM_BS, T>), dim3(cap(needed, SPMM_MAXBLK)), dim3(SPMM_BS),         \
+    hipLaunchKernelGGL((k_cheb_small<K, G, SPMM_BS, T>), dim3(cap_xcd(needed, SPMM_MAXBLK)), dim3(SPMM_BS),     \
                        0, s, n, rowptr, col, val, dinv, Rv, zin, zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags); \
     break;                                                                                                        \
   }

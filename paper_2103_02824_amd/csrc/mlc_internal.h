@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/mlc.h"
+#include "chunks.h"
 
 namespace mlc {
 
@@ -179,11 +180,13 @@ struct mlc_ctx {
   // timing of the dominant kernel
   std::vector<hipEvent_t> ev_pool;
   int ev_used = 0;
-  // captured CG iteration chunks (one per solve kind: 0 orbitals, 1 Poisson)
-  hipGraphExec_t cg_graph[3] = {nullptr, nullptr, nullptr};  // 0 orbitals, 1 Hartree, 2 orbitals FP32
-  int cg_graph_chunk[3] = {0, 0, 0};
+  // captured CG iteration chunks per solve kind (0 orbitals, 1 Hartree, 2
+  // orbitals FP32) and size (2 << g iterations), the tolerance and
+  // preconditioner they were captured with, and the last solve's iterations
+  hipGraphExec_t cg_graph[3][mlc::CHUNK_GRAPHS] = {};
   double cg_graph_rt2[3] = {0.0, 0.0, 0.0};
-  int cg_graph_pc[3] = {0, 0, 0};      // polynomial degree the graph was captured with (0: Jacobi)
+  int cg_graph_pc[3] = {0, 0, 0};      // polynomial degree + 100 with the coarse correction (0: Jacobi)
+  int cg_pred[3] = {0, 0, 0};
   hipStream_t cap_stream = nullptr;     // library-owned stream used only to record graphs
   // learned initial guess of step 5 and the sample sink that feeds its training
   const mlc_nn* nn = nullptr;

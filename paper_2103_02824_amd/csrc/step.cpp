@@ -152,11 +152,10 @@ void enqueue_start(mlc_ctx* c, hipStream_t s, int64_t n, int N, const CgArgs<T>&
 
 // Multi-column preconditioned CG, one independent recurrence per column;
 // per-column scalars stay on the device; the host checks the number of
-// active columns every chunk (an even number of iterations >= check_every).
-// A chunk is captured once into a HIP graph (one graph per solve kind) and
-// replayed; with timed = true the chunk is launched eagerly and every SpMM
-// launch is bracketed by HIP events. On exit the true residual is evaluated
-// in T.
+// active columns after every chunk of iterations (chunk_length). Chunks are
+// replayed from captured HIP graphs (per solve kind and size); with
+// timed = true they are launched eagerly and every SpMM launch is bracketed
+// by HIP events. On exit the true residual is evaluated in T.
 template <typename T>
 mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs<T>& a, double rtol, int maxit, bool timed,
               double* spmm_ms, int64_t* n_spmm, CgRes* out) {
@@ -171,22 +170,33 @@ mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs<T>& a, double
   const int every = 2 * ((std::max(1, c->opt.check_every) + 1) / 2);
   const bool graph = c->opt.use_graphs && !timed && c->cap_stream;
   const int pcdeg = (a.pc ? a.pc->degree : 0) + (a.cc ? 100 : 0);
-  if (graph && (!c->cg_graph[kind] || c->cg_graph_chunk[kind] != every || c->cg_graph_rt2[kind] != rt2 ||
-                c->cg_graph_pc[kind] != pcdeg)) {
-    if (c->cg_graph[kind]) HIPCHK(hipGraphExecDestroy(c->cg_graph[kind]));
-    c->cg_graph[kind] = nullptr;
-    hipGraph_t g;
-    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < every; ++k) (void)enqueue_iteration<T>(c, c->cap_stream, n, N, a, rt2, k & 1);
-    HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
-    hipError_t e = hipGraphInstantiate(&c->cg_graph[kind], g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
-    c->cg_graph_chunk[kind] = every;
+  auto* graphs = c->cg_graph[kind];
+  if (graph && (c->cg_graph_rt2[kind] != rt2 || c->cg_graph_pc[kind] != pcdeg)) {
+    for (int g = 0; g < CHUNK_GRAPHS; ++g) {
+      if (graphs[g]) HIPCHK(hipGraphExecDestroy(graphs[g]));
+      graphs[g] = nullptr;
+    }
     c->cg_graph_rt2[kind] = rt2;
     c->cg_graph_pc[kind] = pcdeg;
   }
-  for (;;) {
+  auto launch_graph = [&](int g) -> mlc_status {
+    if (!graphs[g]) {
+      hipGraph_t gr;
+      HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < (2 << g); ++k) (void)enqueue_iteration<T>(c, c->cap_stream, n, N, a, rt2, k & 1);
+      HIPCHK(hipStreamEndCapture(c->cap_stream, &gr));
+      hipError_t e = hipGraphInstantiate(&graphs[g], gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      if (e != hipSuccess) {
+        graphs[g] = nullptr;
+        return hip_fail(c, e, "hipGraphInstantiate");
+      }
+    }
+    HIPCHK(hipGraphLaunch(graphs[g], s));
+    return MLC_OK;
+  };
+  int len = 0;
+  for (int chunk = 0;; ++chunk) {
     HIPCHK(hipMemcpyAsync(hf, a.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (timed && c->ev_used > 0) {
@@ -206,10 +216,15 @@ mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs<T>& a, double
       break;
     }
     if (it >= maxit) break;
+    len = chunk_length(chunk, len, c->cg_pred[kind], every);
     if (graph) {
-      HIPCHK(hipGraphLaunch(c->cg_graph[kind], s));
+      mlc_status st = MLC_OK;
+      for_chunk_graphs(len, [&](int g) {
+        if (st == MLC_OK) st = launch_graph(g);
+      });
+      if (st != MLC_OK) return st;
     } else {
-      for (int k = 0; k < every; ++k) {
+      for (int k = 0; k < len; ++k) {
         bool rec = timed && c->ev_used + 2 <= (int)c->ev_pool.size();
         mlc_status st = enqueue_iteration<T>(c, s, n, N, a, rt2, k & 1, rec ? &c->ev_pool[c->ev_used] : nullptr);
         if (st != MLC_OK) return st;
@@ -219,7 +234,7 @@ mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs<T>& a, double
         }
       }
     }
-    it += every;
+    it += len;
   }
   // per-column iteration counts, then the true residual ||B - A X|| / ||B||
   std::vector<double> hs(5 * N);
@@ -234,6 +249,7 @@ mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs<T>& a, double
   }
   out->iters = itmax;
   out->iters_sum = itsum;
+  if (out->converged) c->cg_pred[kind] = itmax;
   L_spmm(s, n, N, d.rowptr, d.col, a.val, a.X, a.Q, nullptr, nullptr);
   L_init(s, n, N, a.B, a.Q, a.dinv, a.R, a.P, red_upd);
   launch_cg_start(s, n, N, red_upd, 0.0, nullptr, a.scal, a.flags);
