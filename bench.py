@@ -64,14 +64,18 @@ def cheb_bytes(n, nnz, N, word=8):
 
 
 def _kernel_name(which, N, word):
+    """Profiler name of the kernel mlc_time_kernel replays: the CG SpMM and
+    the Hartree SpMM run the partial-sum shape (1024-thread blocks), the
+    polynomial steps the 256-thread shape of the steps before the last."""
     t = "float" if word == 4 else "double"
-    if which == "cg_spmm":
-        return f"k_spmm_small<{N}, {8 if N == 1 else 4}, 1024, {t}>" if N <= 8 else f"k_spmm_wide<{t}>"
-    if which == "hartree_spmm":
-        return "k_spmm_small<1, 8, 1024, double>"
-    if which == "cheb_step":
-        return f"k_cheb_small<{N}, {8 if N == 1 else 4}, 1024, {t}>" if N <= 8 else f"k_cheb_wide<{t}>"
-    return "k_cheb_small<1, 8, 1024, double>"
+    if which in ("hartree_spmm", "hartree_cheb_step"):
+        N, t = 1, "double"
+    if N > 8:
+        return f"k_spmm_wide<{t}>" if "spmm" in which else f"k_cheb_wide<{t}>"
+    if "spmm" in which:
+        unroll = 4 if N <= 3 else (2 if N <= 6 else 1)
+        return f"k_spmm_small<{N}, 4, {unroll}, 1024, {8 if N <= 6 else 4}, {t}>"
+    return f"k_cheb_small<{N}, 4, {4 if N <= 6 else 2}, 256, {8 if N <= 2 else 4}, {t}>"
 
 
 def spmm_bytes(n, nnz, N, word=8):

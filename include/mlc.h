@@ -245,13 +245,17 @@ mlc_status mlc_probe(mlc_ctx* ctx, int32_t which, double* out, int64_t count);
 
 /* Kernel timing for roofline accounting: replays one kernel of the solves
  * `reps` times back to back on the bound stream, between two HIP events, and
- * returns the mean duration per launch in microseconds (dispatch gaps
- * between the launches included):
+ * returns the mean duration per launch in microseconds, dispatch gaps
+ * between the launches included (the launches are replayed from one captured
+ * HIP graph, as the solver replays them, when options.use_graphs is set and
+ * reps <= 4096; eagerly otherwise):
  *   MLC_KERNEL_CG_SPMM            step 5: Y = (A + sigma M) P over all N
  *                                 columns with the P.Y partials CG consumes
  *                                 (FP32 values under MLC_PREC_FP32_IR)
  *   MLC_KERNEL_CHEB_STEP          step 5: one Chebyshev step of the polynomial
- *                                 preconditioner (SpMM fused with the update)
+ *                                 preconditioner (SpMM fused with the update),
+ *                                 in the launch shape of all steps but the
+ *                                 last (which adds the r.z partials)
  *   MLC_KERNEL_HARTREE_SPMM       step 6: the same SpMM with K, one column
  *   MLC_KERNEL_HARTREE_CHEB_STEP  step 6: one Chebyshev step with K
  * It overwrites only solver scratch (Q, the Gram blocks, the partials); the

@@ -67,9 +67,9 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->valW = w.take<double>(nnz);
   d->valM = w.take<double>(nnz);
   d->valK = w.take<double>(nnz);
-  d->elem = w.take<double>(20 * nt);
+  d->elem = w.take<double>(std::max<int64_t>(2 * (int64_t)c->slot_ptr.back(), 8 * nt));
   d->slot_ptr = w.take<int32_t>(nnz + 1);
-  d->slot_src = w.take<int32_t>((int64_t)c->slot_src.size());
+  d->slot_of = w.take<int32_t>(16 * nt);
   d->diag_slot = w.take<int32_t>(n);
   d->dinvA = w.take<double>(n);
   d->dinvK = w.take<double>(n);
@@ -80,6 +80,7 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->Q = w.take<double>(n * N);
   d->B = w.take<double>(n * N);
   d->Y = w.take<double>(4 * n * N);
+  d->Yh = w.take<double>(c->hartree ? 4 * n : 1);
   d->w = w.take<double>(nv);
   d->g = w.take<double>(nv);
   d->w0 = w.take<double>(n);
@@ -113,6 +114,7 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   nred = std::max<int64_t>(nred, (int64_t)gram_blocks(n) * N * N);
   c->nred = nred;
   d->red = w.take<double>(nred);
+  d->red2 = w.take<double>((int64_t)gram_blocks(n) * N * N);
   d->scal = w.take<double>(10 * N);
   d->scalP = w.take<double>(10);
   d->flags = w.take<int32_t>(8);
@@ -185,7 +187,7 @@ mlc_status upload_and_init(mlc_ctx* c) {
   HIPCHK(up(s, d.adj_loc, c->adj_loc));
   HIPCHK(up(s, d.bverts, c->bverts));
   HIPCHK(up(s, d.slot_ptr, c->slot_ptr));
-  HIPCHK(up(s, d.slot_src, c->slot_src));
+  HIPCHK(up(s, d.slot_of, c->slot_of));
   HIPCHK(up(s, d.diag_slot, c->diag_slot));
   HIPCHK(up(s, d.Pk, c->Pk));
   HIPCHK(up(s, d.Pw, c->Pw));
@@ -205,10 +207,11 @@ mlc_status upload_and_init(mlc_ctx* c) {
   // fixed quantities: V_ext at the quadrature points, K, M, coarse trilinear tensor
   launch_vext(s, c->nt, d.qpx, d.RZ, c->n_nuclei, c->potential, c->rc, c->omega, d.vext);
   const int64_t nnz = (int64_t)c->col.size();
-  launch_assemble2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 1.0, nullptr, 0.0, d.valK,
-                   d.dinvK, 0.0, nullptr, d.valM);
-  launch_assemble2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 0.0, nullptr, 1.0, d.valM,
-                   nullptr, 0.0, nullptr, nullptr);
+  const int64_t ns = c->slot_ptr.back();
+  launch_assemble2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_of, ns, d.diag_slot, d.elem, 1.0, nullptr, 0.0,
+                   d.valK, d.dinvK, 0.0, nullptr, d.valM);
+  launch_assemble2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_of, ns, d.diag_slot, d.elem, 0.0, nullptr, 1.0,
+                   d.valM, nullptr, 0.0, nullptr, nullptr);
   launch_gershgorin(s, c->n, d.rowptr, d.valK, d.dinvK, d.red, d.lmax + 1);
   launch_coarse_tri(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.cel_tri);
   launch_coarse_hats(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.chat);
@@ -520,6 +523,12 @@ mlc_status mlc_bind(mlc_ctx* c, void* dev_workspace, size_t bytes, void* hip_str
     }
     c->cg_pred[k] = 0;
   }
+  if (!c->side) {
+    hipError_t he = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (he != hipSuccess) return hip_fail(c, he, "side stream");
+  }
   if (c->opt.use_graphs && !c->cap_stream) {
     hipError_t he = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
     if (he != hipSuccess) return hip_fail(c, he, "hipStreamCreateWithFlags");
@@ -619,11 +628,12 @@ mlc_status mlc_time_kernel(mlc_ctx* c, int32_t which, int32_t reps, double* avg_
   const int64_t n = c->n;
   const int N = hart ? 1 : c->N;
   const bool f32 = !hart && c->opt.precision == MLC_PREC_FP32_IR;
-  double* rz = d.red + (int64_t)cg_max_blocks() * N;
   float* Yf = reinterpret_cast<float*>(d.Y);
-  // one Chebyshev step = a polynomial of degree 2 (its single step is the last one)
-  PolyPC<double> pd{hart ? d.lmax + 1 : d.lmax, c->opt.cheb_ratio, 2, {d.Y, d.Y + n * N}, d.Y + 2 * n * N, rz};
-  PolyPC<float> pf{d.lmax, c->opt.cheb_ratio, 2, {Yf, Yf + n * N}, Yf + 2 * n * N, rz};
+  // one Chebyshev step = a polynomial of degree 2 without the r.z partials:
+  // the launch shape of every step but the last
+  double* Yd = hart ? d.Yh : d.Y;
+  PolyPC<double> pd{hart ? d.lmax + 1 : d.lmax, c->opt.cheb_ratio, 2, {Yd, Yd + n * N}, Yd + 2 * n * N, nullptr};
+  PolyPC<float> pf{d.lmax, c->opt.cheb_ratio, 2, {Yf, Yf + n * N}, Yf + 2 * n * N, nullptr};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -648,13 +658,36 @@ mlc_status mlc_time_kernel(mlc_ctx* c, int32_t which, int32_t reps, double* avg_
         launch_spmm2(s, n, N, d.rowptr, d.col, d.valA, d.P, d.Q, d.red, nullptr);
     }
   };
-  hipError_t err = hipEventRecord(e0, s);
-  for (int k = 0; k < reps && err == hipSuccess; ++k) {
-    one();
-    err = hipGetLastError();
+  hipError_t err = hipSuccess;
+  if (c->opt.use_graphs && c->cap_stream && reps <= 4096) {
+    // the launches back to back in one graph, as the solver replays its chunks
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipStream_t keep = s;
+    err = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) {
+      s = c->cap_stream;
+      for (int k = 0; k < reps; ++k) one();
+      s = keep;
+      err = hipStreamEndCapture(c->cap_stream, &g);
+    }
+    if (err == hipSuccess) err = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (err == hipSuccess) err = hipGraphLaunch(ge, s);  // warm-up replay
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    if (err == hipSuccess) err = hipGraphLaunch(ge, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    if (ge) (void)hipGraphExecDestroy(ge);
+  } else {
+    err = hipEventRecord(e0, s);
+    for (int k = 0; k < reps && err == hipSuccess; ++k) {
+      one();
+      err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
   }
-  if (err == hipSuccess) err = hipEventRecord(e1, s);
-  if (err == hipSuccess) err = hipEventSynchronize(e1);
   float ms = 0.f;
   if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
   (void)hipEventDestroy(e0);
@@ -714,6 +747,9 @@ void mlc_destroy(mlc_ctx* c) {
     for (hipGraphExec_t g : gk)
       if (g) (void)hipGraphExecDestroy(g);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->side) (void)hipStreamDestroy(c->side);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   delete c;
 }
 

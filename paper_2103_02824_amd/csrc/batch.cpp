@@ -139,7 +139,7 @@ mlc_status upload_shape(mlc_batch* b, int TR) {
     for (int k = 0; k < nt; ++k) tp.push_back(s);
     if (c->hartree) {
       BProb<double> pp{d.rowptr, d.col, d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq,
-                       d.Y, d.Y + c->n, d.Y + 2 * c->n, pc ? d.lmax + 1 : nullptr, c->n, 1, (int32_t)tpP.size(),
+                       d.Yh, d.Yh + c->n, d.Yh + 2 * c->n, pc ? d.lmax + 1 : nullptr, c->n, 1, (int32_t)tpP.size(),
                        nt, 0};
       hP.push_back(pp);
       for (int k = 0; k < nt; ++k) tpP.push_back(kp);
@@ -162,7 +162,7 @@ mlc_status upload_shape(mlc_batch* b, int TR) {
     for (mlc_ctx* c : b->ctx) {
       if (!c->hartree) continue;
       auto& d = c->d;
-      hC.push_back(BCoarse{d.PTptr, d.PTidx, d.PTw, d.Pk, d.Pw, d.KHinv, d.rH, d.eH, d.Y + 3 * c->n, c->nH,
+      hC.push_back(BCoarse{d.PTptr, d.PTidx, d.PTw, d.Pk, d.Pw, d.KHinv, d.rH, d.eH, d.Yh + 3 * c->n, c->nH,
                            (int32_t)crow.size(), 0});
       for (int64_t k = 0; k < c->nH; ++k) crow.push_back(kq);
       ++kq;
@@ -620,11 +620,17 @@ mlc_status mlc_batch_step(mlc_batch* b, mlc_step_report* reports, mlc_batch_repo
     if ((st = phase_after_solve(*runs[i])) != MLC_OK) return sys_fail(b, i, st);
   if ((st = join(b)) != MLC_OK) return st;
   BCHK(hipEventRecord(ev[3], s));
+  // the w0-independent Gram blocks on the systems' streams, beside the
+  // batched Hartree solve on the batch stream
+  if ((st = fork(b)) != MLC_OK) return st;
+  for (int i = 0; i < K; ++i)
+    if ((st = phase_gram_fixed(*runs[i], b->sys_stream[i], b->ctx[i]->d.red)) != MLC_OK) return sys_fail(b, i, st);
   BRes rp;
   if (b->KP > 0) {
     if ((st = solve_hartree(b, &rp)) != MLC_OK) return st;
   }
   BCHK(hipEventRecord(ev[4], s));
+  if ((st = join(b)) != MLC_OK) return st;
   int kp = 0;
   for (int i = 0; i < K; ++i) {
     if (b->ctx[i]->hartree) {

@@ -81,11 +81,6 @@ struct RowBlocks {
   }
 };
 
-// Nonzeros per lane and pass of row_gather: enough gathers in flight while
-// the kernel still fits 64 VGPRs (eight waves per SIMD, two 1024-thread blocks
-// per CU).
-constexpr int gather_unroll(int NT, int G) { return G >= 8 ? 2 : (NT <= 3 ? 4 : (NT <= 6 ? 2 : 1)); }
-
 // acc[c] += sum over this lane's nonzeros of row r (every G-th from
 // rowptr[r] + sub) of a_rj X[j][c]; U nonzeros per pass have their column
 // and value loads issued together, then their gathers. Entries past the row
@@ -147,11 +142,11 @@ __device__ __forceinline__ void cheb_coef(double lmax, double ratio, int j, doub
 // partial sums are combined with lane shuffles. Column indices and values are
 // read coalesced (G consecutive entries), X rows as NT consecutive doubles.
 // Optional CG epilogue: per-block column sums of P . Q.
-template <int NT, int G, int BS, typename T>
-__global__ void __launch_bounds__(BS, NT <= 6 ? 8 : 4) k_spmm_small(int64_t n, const int32_t* __restrict__ rowptr,
-                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                   const T* __restrict__ X, T* __restrict__ Y,
-                                                   double* __restrict__ partial, const int32_t* __restrict__ flags) {
+template <int NT, int G, int U, int BS, int W, typename T>
+__global__ void __launch_bounds__(BS, W) k_spmm_small(int64_t n, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                      const T* __restrict__ X, T* __restrict__ Y,
+                                                      double* __restrict__ partial, const int32_t* __restrict__ flags) {
   constexpr int RB = BS / G;  // rows per block pass
   if (flags && flags[0] == 0) return;
   __shared__ double sd[BS / 64][NT];
@@ -166,7 +161,7 @@ __global__ void __launch_bounds__(BS, NT <= 6 ? 8 : 4) k_spmm_small(int64_t n, c
     T acc[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[c] = T(0);
-    if (r < n) row_gather<NT, G, gather_unroll(NT, G)>(r, sub, rowptr, col, val, X, acc);
+    if (r < n) row_gather<NT, G, U>(r, sub, rowptr, col, val, X, acc);
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
@@ -235,15 +230,19 @@ __global__ void __launch_bounds__(TPB) k_spmm_wide(int64_t n, int N, const int32
 
 // One Chebyshev step j >= 1 fused with its SpMM (NT <= 8, G lanes per row):
 // w = A Zin; d = cd d + cr D^-1 (R - w); Zout = Zin + d; optional per-block
-// column sums of R . Zout (the r.z of CG after the last step).
-template <int NT, int G, int BS, typename T>
-__global__ void __launch_bounds__(BS, NT <= 6 ? 8 : 4) k_cheb_small(int64_t n, const int32_t* __restrict__ rowptr,
-                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                   const T* __restrict__ dinv, const T* __restrict__ R,
-                                                   const T* __restrict__ Zin, T* __restrict__ Zout, T* __restrict__ Dd,
-                                                   const double* __restrict__ lmax, double ratio, int j,
-                                                   double* __restrict__ partial, const int32_t* __restrict__ flags) {
+// column sums of R . Zout (the r.z of CG after the last step). The row's own
+// entries of R, d and Zin are loaded before the gather, so that their
+// latency overlaps it.
+template <int NT, int G, int U, int BS, int W, typename T>
+__global__ void __launch_bounds__(BS, W) k_cheb_small(int64_t n, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                      const T* __restrict__ dinv, const T* __restrict__ R,
+                                                      const T* __restrict__ Zin, T* __restrict__ Zout,
+                                                      T* __restrict__ Dd, const double* __restrict__ lmax,
+                                                      double ratio, int j, double* __restrict__ partial,
+                                                      const int32_t* __restrict__ flags) {
   constexpr int RB = BS / G;
+  constexpr int NO = (NT + G - 1) / G;  // columns owned by a lane (c = sub + o G)
   if (flags && flags[0] == 0) return;
   __shared__ double sd[BS / 64][NT];
   double cdd, crr;
@@ -256,28 +255,37 @@ __global__ void __launch_bounds__(BS, NT <= 6 ? 8 : 4) k_cheb_small(int64_t n, c
   for (int c = 0; c < NT; ++c) dot[c] = 0.0;
   const RowBlocks rbk((n + RB - 1) / RB);
   for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
-    int64_t r = rb * RB + rl;
+    const int64_t r = rb * RB + rl;
+    if (r >= n) continue;  // whole lane groups: the shuffles below stay within the group
+    T rv[NO], dv[NO], zv[NO];
+    const T di = dinv[r];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      const int c = sub + o * G;
+      if (c < NT) {
+        rv[o] = R[r * NT + c];
+        dv[o] = Dd[r * NT + c];
+        zv[o] = Zin[r * NT + c];
+      }
+    }
     T acc[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[c] = T(0);
-    if (r < n) row_gather<NT, G, gather_unroll(NT, G)>(r, sub, rowptr, col, val, Zin, acc);
+    row_gather<NT, G, U>(r, sub, rowptr, col, val, Zin, acc);
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
       for (int off = G / 2; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, G);
-    if (r < n) {
-      const T di = dinv[r];
 #pragma unroll
-      for (int c = 0; c < NT; ++c)
-        if (c % G == sub) {
-          const int64_t i = r * NT + c;
-          const T rv = R[i];
-          const T dn = cd * Dd[i] + cr * (di * (rv - acc[c]));
-          Dd[i] = dn;
-          const T z = Zin[i] + dn;
-          Zout[i] = z;
-          if (partial) dot[c] += (double)rv * (double)z;
-        }
+    for (int o = 0; o < NO; ++o) {
+      const int c = sub + o * G;
+      if (c < NT) {
+        const T dn = cd * dv[o] + cr * (di * (rv[o] - acc[c]));
+        Dd[r * NT + c] = dn;
+        const T z = zv[o] + dn;
+        Zout[r * NT + c] = z;
+        if (partial) dot[c] += (double)rv[o] * (double)z;
+      }
     }
   }
   if (!partial) return;
@@ -629,13 +637,36 @@ __global__ void __launch_bounds__(TPB) k_cg_direction(int64_t n, int N, const T*
   }
 }
 
-template <int NT, int BS, typename T>
+// Launch shapes of the row-gather kernels (NT <= 8 columns, four lanes per
+// row), from measurements on the 4-atom cluster matrix (2.7M nonzeros):
+// - producers of per-block partial sums (the CG SpMM and the last polynomial
+//   step) run 1024-thread blocks on a grid capped at SPMM_MAXBLK, because
+//   every consumer block re-reads all partials;
+// - the other polynomial steps and plain products run 256-thread blocks, one
+//   per row block (finer load balance), with deeper unrolling.
+constexpr int ROW_G = 4;
+constexpr int unroll_wide(int NT) { return NT <= 6 ? 4 : 2; }   // 256-thread shape
+constexpr int unroll_part(int NT) { return NT <= 3 ? 4 : (NT <= 6 ? 2 : 1); }  // partial producers
+// the last polynomial step also holds the row's R, d and Z entries: beyond
+// three columns it needs more than 64 VGPRs (one 1024-thread block per CU)
+constexpr int unroll_cheb_part(int NT) { return NT <= 3 ? 4 : 2; }
+constexpr int waves_cheb_part(int NT) { return NT <= 3 ? 8 : 4; }
+constexpr int waves_wide(int NT) { return NT <= 2 ? 8 : 4; }
+constexpr int waves_part(int NT) { return NT <= 6 ? 8 : 4; }
+
+template <int NT, typename T>
 void spmm_small(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* col, const T* val, const T* X, T* Y,
-                double* partial, const int32_t* flags, int maxblk) {
-  constexpr int G = NT == 1 ? 8 : 4;
-  int64_t needed = (n + (BS / G) - 1) / (BS / G);
-  hipLaunchKernelGGL((k_spmm_small<NT, G, BS, T>), dim3(cap_xcd(needed, maxblk)), dim3(BS), 0, s, n, rowptr, col, val, X,
-                     Y, partial, flags);
+                double* partial, const int32_t* flags) {
+  if (partial) {
+    const int64_t needed = (n + (SPMM_BS / ROW_G) - 1) / (SPMM_BS / ROW_G);
+    hipLaunchKernelGGL((k_spmm_small<NT, ROW_G, unroll_part(NT), SPMM_BS, waves_part(NT), T>),
+                       dim3(cap_xcd(needed, SPMM_MAXBLK)), dim3(SPMM_BS), 0, s, n, rowptr, col, val, X, Y, partial,
+                       flags);
+  } else {
+    const int64_t needed = (n + (TPB / ROW_G) - 1) / (TPB / ROW_G);
+    hipLaunchKernelGGL((k_spmm_small<NT, ROW_G, unroll_wide(NT), TPB, waves_wide(NT), T>),
+                       dim3(cap_xcd(needed, 1 << 30)), dim3(TPB), 0, s, n, rowptr, col, val, X, Y, partial, flags);
+  }
 }
 
 int vec_blocks(int64_t n, int N) {
@@ -656,12 +687,9 @@ __global__ void __launch_bounds__(TPB) k_add_f32(int64_t m, const float* __restr
 template <typename T>
 void spmm_any(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val, const T* X,
               T* Y, double* partial, const int32_t* flags) {
-#define SPMM_CASE(K)                                                                        \
-  case K:                                                                                   \
-    if (partial)                                                                            \
-      spmm_small<K, SPMM_BS, T>(s, n, rowptr, col, val, X, Y, partial, flags, SPMM_MAXBLK); \
-    else                                                                                    \
-      spmm_small<K, TPB, T>(s, n, rowptr, col, val, X, Y, partial, flags, MAXBLK);          \
+#define SPMM_CASE(K)                                                  \
+  case K:                                                             \
+    spmm_small<K, T>(s, n, rowptr, col, val, X, Y, partial, flags); \
     return;
   switch (N) {
     SPMM_CASE(1)
@@ -688,10 +716,7 @@ int cg_blocks(int64_t n, int N) {
   return cap((n + R - 1) / R, MAXBLK);
 }
 int spmm_blocks(int64_t n, int N) {
-  if (N <= 8) {
-    int G = N == 1 ? 8 : 4;
-    return cap_xcd((n + (SPMM_BS / G) - 1) / (SPMM_BS / G), SPMM_MAXBLK);
-  }
+  if (N <= 8) return cap_xcd((n + (SPMM_BS / ROW_G) - 1) / (SPMM_BS / ROW_G), SPMM_MAXBLK);
   return cg_blocks(n, N);
 }
 int cg_max_blocks() { return MAXBLK; }
@@ -798,14 +823,20 @@ void launch_cheb_steps_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr,
     T* zout = last && last_out ? last_out : pc.Z[j & 1];
     double* part = last ? pc.rz_part : nullptr;
     if (N <= 8) {
-#define CHEB_CASE(K)                                                                                              \
-  case K: {                                                                                                       \
-    constexpr int G = K == 1 ? 8 : 4;                                                                             \
-    int64_t needed = (n + (SPMM_BS / G) - 1) / (SPMM_BS / G);                                                     \
-    hipLaunchKernelGGL((k_cheb_small<K, G, SPMM_BS, T>), dim3(cap_xcd(needed, SPMM_MAXBLK)), dim3(SPMM_BS),     \
-                       0, s, n, rowptr, col, val, dinv, Rv, zin, zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags); \
-    break;                                                                                                        \
-  }
+#define CHEB_CASE(K)                                                                                             \
+  case K:                                                                                                        \
+    if (part) {                                                                                                  \
+      const int64_t needed = (n + (SPMM_BS / ROW_G) - 1) / (SPMM_BS / ROW_G);                                    \
+      hipLaunchKernelGGL((k_cheb_small<K, ROW_G, unroll_cheb_part(K), SPMM_BS, waves_cheb_part(K), T>),          \
+                         dim3(cap_xcd(needed, SPMM_MAXBLK)), dim3(SPMM_BS), 0, s, n, rowptr, col, val, dinv, Rv, \
+                         zin, zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags);                                   \
+    } else {                                                                                                     \
+      const int64_t needed = (n + (TPB / ROW_G) - 1) / (TPB / ROW_G);                                            \
+      hipLaunchKernelGGL((k_cheb_small<K, ROW_G, unroll_wide(K), TPB, waves_wide(K), T>),                        \
+                         dim3(cap_xcd(needed, 1 << 30)), dim3(TPB), 0, s, n, rowptr, col, val, dinv, Rv, zin,    \
+                         zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags);                                        \
+    }                                                                                                            \
+    break;
       switch (N) {
         CHEB_CASE(1)
         CHEB_CASE(2)

@@ -280,12 +280,20 @@ __global__ void __launch_bounds__(TPB) k_field(int64_t nt, const int32_t* __rest
 
 // Element entries (10 symmetric local pairs, order (0,0)(0,1)..(3,3)) of
 //   op1 = cK1 K + M_{f1} + cM1 M  and  op2 = cK2 K + M_{f2}
-// for one tet per thread; the mass parts use the 4-point rule.
+// for one tet per thread (the mass parts use the 4-point rule), each written
+// to its slot-order position pos = slot_of[16 t + 4 a + b] (-1: skipped):
+// with TWO the pair (op1, op2) as one 16-byte store at esl2[pos], otherwise
+// op1 alone at esl[pos].
+template <bool TWO>
 __global__ void __launch_bounds__(TPB) k_elem(int64_t nt, const double* __restrict__ geo, double cK1,
                                               const double* __restrict__ f1, double cM1, double cK2,
-                                              const double* __restrict__ f2, double* __restrict__ elem) {
+                                              const double* __restrict__ f2, const int32_t* __restrict__ slot_of,
+                                              double* __restrict__ esl) {
   int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (t >= nt) return;
+  int32_t pos[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) pos[k] = slot_of[16 * t + k];
   const double* G = geo + 16 * t;
   double vol = G[0];
   double g[4][3];
@@ -299,12 +307,11 @@ __global__ void __launch_bounds__(TPB) k_elem(int64_t nt, const double* __restri
     w1[q] = 0.25 * vol * (f1 ? f1[4 * t + q] : 0.0);
     w2[q] = 0.25 * vol * (f2 ? f2[4 * t + q] : 0.0);
   }
-  double e1[10], e2[10];
+  double2* esl2 = reinterpret_cast<double2*>(esl);
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = a; b < 4; ++b) {
-      const int p = a * 4 - (a * (a - 1)) / 2 + (b - a);
       double kv = vol * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2]);
       double m1 = 0.0, m2 = 0.0, mm = 0.0;
 #pragma unroll
@@ -314,34 +321,41 @@ __global__ void __launch_bounds__(TPB) k_elem(int64_t nt, const double* __restri
         m2 += w2[q] * ll;
         mm += 0.25 * vol * ll;
       }
-      e1[p] = cK1 * kv + m1 + cM1 * mm;
-      e2[p] = cK2 * kv + m2;
+      const double e1 = cK1 * kv + m1 + cM1 * mm;
+      const double e2 = cK2 * kv + m2;
+      const int pab = pos[4 * a + b], pba = pos[4 * b + a];
+      if (TWO) {
+        if (pab >= 0) esl2[pab] = make_double2(e1, e2);
+        if (b != a && pba >= 0) esl2[pba] = make_double2(e1, e2);
+      } else {
+        if (pab >= 0) esl[pab] = e1;
+        if (b != a && pba >= 0) esl[pba] = e1;
+      }
     }
-  double* o = elem + 20 * t;
-#pragma unroll
-  for (int p = 0; p < 10; ++p) {
-    o[p] = e1[p];
-    o[10 + p] = e2[p];
-  }
 }
 
-// One thread per CSR slot: the slot's element entries summed in tet order.
-__global__ void __launch_bounds__(TPB) k_slot_gather(int64_t nnz, const int32_t* __restrict__ slot_ptr,
-                                                     const int32_t* __restrict__ slot_src,
-                                                     const double* __restrict__ elem, double* __restrict__ val1,
-                                                     double* __restrict__ val2) {
+// CSR values: each slot's contiguous run of element entries summed in order.
+template <bool TWO>
+__global__ void __launch_bounds__(TPB) k_slot_sum(int64_t nnz, const int32_t* __restrict__ slot_ptr,
+                                                  const double* __restrict__ esl, double* __restrict__ val1,
+                                                  double* __restrict__ val2) {
   int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (j >= nnz) return;
+  const int e0 = slot_ptr[j], e1 = slot_ptr[j + 1];
   double s1 = 0.0, s2 = 0.0;
-  for (int e = slot_ptr[j]; e < slot_ptr[j + 1]; ++e) {
-    int src = slot_src[e];
-    int64_t t = src / 10;
-    int p = src - (int)t * 10;
-    s1 += elem[20 * t + p];
-    if (val2) s2 += elem[20 * t + 10 + p];
+  if (TWO) {
+    const double2* esl2 = reinterpret_cast<const double2*>(esl);
+    for (int e = e0; e < e1; ++e) {
+      const double2 v = esl2[e];
+      s1 += v.x;
+      s2 += v.y;
+    }
+    val1[j] = s1;
+    val2[j] = s2;
+  } else {
+    for (int e = e0; e < e1; ++e) s1 += esl[e];
+    val1[j] = s1;
   }
-  val1[j] = s1;
-  if (val2) val2[j] = s2;
 }
 
 __global__ void __launch_bounds__(TPB) k_diag_inv(int64_t n, const int32_t* __restrict__ diag_slot,
@@ -1081,10 +1095,17 @@ void launch_field(hipStream_t s, int64_t nt, const int32_t* tets, const double* 
   hipLaunchKernelGGL(k_field, dim3(nb(nt)), dim3(TPB), 0, s, nt, tets, nod, v2d, dofv, add1, add2, out);
 }
 void launch_assemble2(hipStream_t s, int64_t nt, int64_t n, int64_t nnz, const double* geo, const int32_t* slot_ptr,
-                      const int32_t* slot_src, const int32_t* diag_slot, double* elem, double cK1, const double* f1,
-                      double cM1, double* val1, double* dinv1, double cK2, const double* f2, double* val2) {
-  hipLaunchKernelGGL(k_elem, dim3(nb(nt)), dim3(TPB), 0, s, nt, geo, cK1, f1, cM1, cK2, f2, elem);
-  hipLaunchKernelGGL(k_slot_gather, dim3(nb(nnz)), dim3(TPB), 0, s, nnz, slot_ptr, slot_src, elem, val1, val2);
+                      const int32_t* slot_of, int64_t ns, const int32_t* diag_slot, double* esl, double cK1,
+                      const double* f1, double cM1, double* val1, double* dinv1, double cK2, const double* f2,
+                      double* val2) {
+  (void)ns;
+  if (val2) {
+    hipLaunchKernelGGL(k_elem<true>, dim3(nb(nt)), dim3(TPB), 0, s, nt, geo, cK1, f1, cM1, cK2, f2, slot_of, esl);
+    hipLaunchKernelGGL(k_slot_sum<true>, dim3(nb(nnz)), dim3(TPB), 0, s, nnz, slot_ptr, esl, val1, val2);
+  } else {
+    hipLaunchKernelGGL(k_elem<false>, dim3(nb(nt)), dim3(TPB), 0, s, nt, geo, cK1, f1, cM1, cK2, f2, slot_of, esl);
+    hipLaunchKernelGGL(k_slot_sum<false>, dim3(nb(nnz)), dim3(TPB), 0, s, nnz, slot_ptr, esl, val1, nullptr);
+  }
   if (dinv1) hipLaunchKernelGGL(k_diag_inv, dim3(nb(n)), dim3(TPB), 0, s, n, diag_slot, val1, dinv1);
 }
 void launch_load(hipStream_t s, int64_t n, int64_t nt, const int32_t* adj_ptr, const int32_t* adj_tet,

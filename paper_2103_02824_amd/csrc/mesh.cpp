@@ -275,20 +275,24 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
     c->adj_ptr[d + 1] = (int32_t)c->adj_tet.size();
   }
   if ((int64_t)c->col.size() >= (1LL << 31)) return fail(c, MLC_ERR_MESH, "too many nonzeros");
-  if (c->nt * 10 >= (1LL << 31)) return fail(c, MLC_ERR_MESH, "too many tets for the slot list");
-  // For every CSR slot (a, b): the element entries (tet t, symmetric local pair
-  // p) that add into it, in increasing tet order. Assembly then sums them with
-  // one thread per slot in this fixed order.
+  if (c->nt * 16 >= (1LL << 31)) return fail(c, MLC_ERR_MESH, "too many tets for the slot list");
+  // For every CSR slot (a, b): the element entries (tet t, local pair) that
+  // add into it, in increasing tet order; slot_of[16 t + 4 a + b] is the
+  // position of entry (a, b) of tet t in that order (-1 when a or b is a
+  // boundary vertex). Assembly writes every element entry to its position and
+  // then sums each slot's contiguous run, in this fixed order.
   {
-    static const int sym[4][4] = {{0, 1, 2, 3}, {1, 4, 5, 6}, {2, 5, 7, 8}, {3, 6, 8, 9}};
     const int64_t nnz = (int64_t)c->col.size();
     std::vector<int32_t> cnt(nnz + 1, 0);
     c->diag_slot.assign(c->n, -1);
+    c->slot_of.assign(16 * c->nt, -1);
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1) {
         c->slot_ptr.assign(nnz + 1, 0);
-        for (int64_t j = 0; j < nnz; ++j) c->slot_ptr[j + 1] = c->slot_ptr[j] + cnt[j];
-        c->slot_src.assign(c->slot_ptr.back(), 0);
+        for (int64_t j = 0; j < nnz; ++j) {
+          if ((int64_t)c->slot_ptr[j] + cnt[j] >= (1LL << 31)) return fail(c, MLC_ERR_MESH, "too many element entries");
+          c->slot_ptr[j + 1] = c->slot_ptr[j] + cnt[j];
+        }
         std::fill(cnt.begin(), cnt.end(), 0);
       }
       for (int64_t t = 0; t < c->nt; ++t) {
@@ -301,7 +305,7 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
           for (int b = 0; b < 4; ++b) {
             if (dd[b] < 0) continue;
             int64_t slot = c->rowptr[dd[a]] + (std::lower_bound(rb, re, dd[b]) - rb);
-            if (pass == 1) c->slot_src[c->slot_ptr[slot] + cnt[slot]] = (int32_t)(t * 10 + sym[a][b]);
+            if (pass == 1) c->slot_of[16 * t + 4 * a + b] = c->slot_ptr[slot] + cnt[slot];
             cnt[slot]++;
             if (a == b) c->diag_slot[dd[a]] = (int32_t)slot;
           }

@@ -47,9 +47,9 @@ struct Dev {
   double* valW = nullptr;       // M_{w0}
   double* valM = nullptr;       // M
   double* valK = nullptr;       // K
-  double* elem = nullptr;       // nt x 20: element entries of two operators
+  double* elem = nullptr;       // element entries of two operators in slot order (2 ns; also load scratch)
   int32_t* slot_ptr = nullptr;  // nnz + 1
-  int32_t* slot_src = nullptr;  // t * 10 + local pair
+  int32_t* slot_of = nullptr;   // nt x 16: slot-order position of element entry (a, b)
   int32_t* diag_slot = nullptr; // n
   double* dinvA = nullptr;      // n
   double* dinvK = nullptr;      // n
@@ -61,6 +61,8 @@ struct Dev {
   double* Q = nullptr;
   double* B = nullptr;
   double* Y = nullptr;          // 4 blocks of n x N
+  double* Yh = nullptr;         // Hartree solver scratch, 4 n (polynomial Z0, Z1, d; coarse-corrected z)
+  double* red2 = nullptr;       // partials of the Gram blocks computed beside the Hartree solve
   // single vectors
   double* w = nullptr;          // nv nodal Hartree potential
   double* g = nullptr;          // nv multipole data (0 inside)
@@ -141,7 +143,7 @@ struct mlc_ctx {
   std::vector<int32_t> adj_ptr, adj_tet, adj_pos;
   std::vector<int8_t> adj_loc;
   std::vector<double> geo;              // nt x 16
-  std::vector<int32_t> slot_ptr, slot_src, diag_slot;  // assembly gather lists
+  std::vector<int32_t> slot_ptr, slot_of, diag_slot;  // assembly lists
   // ---- coarse ---------------------------------------------------------------
   int64_t nH = 0;
   std::vector<int32_t> cv2d, cd2v;
@@ -188,6 +190,8 @@ struct mlc_ctx {
   int cg_graph_pc[3] = {0, 0, 0};      // polynomial degree + 100 with the coarse correction (0: Jacobi)
   int cg_pred[3] = {0, 0, 0};
   hipStream_t cap_stream = nullptr;     // library-owned stream used only to record graphs
+  hipStream_t side = nullptr;           // library-owned stream for work beside the Hartree solve
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // learned initial guess of step 5 and the sample sink that feeds its training
   const mlc_nn* nn = nullptr;
   float* sink_x = nullptr;
@@ -302,9 +306,12 @@ void launch_boundary_g(hipStream_t s, int64_t nbv, const int32_t* bverts, const 
 void launch_field(hipStream_t s, int64_t nt, const int32_t* tets, const double* nod, const int32_t* v2d,
                   const double* dofv, const double* add1, const double* add2, double* out);
 // val1 = cK1 K + M_{f1} + cM1 M, val2 = cK2 K + M_{f2} (optional), dinv1 = 1/diag(val1) (optional)
+// esl: scratch of 2 ns doubles, 16-byte aligned (ns = slot_ptr[nnz], the element entries in slot order;
+// two operators are stored as interleaved pairs).
 void launch_assemble2(hipStream_t s, int64_t nt, int64_t n, int64_t nnz, const double* geo, const int32_t* slot_ptr,
-                      const int32_t* slot_src, const int32_t* diag_slot, double* elem, double cK1, const double* f1,
-                      double cM1, double* val1, double* dinv1, double cK2, const double* f2, double* val2);
+                      const int32_t* slot_of, int64_t ns, const int32_t* diag_slot, double* esl, double cK1,
+                      const double* f1, double cM1, double* val1, double* dinv1, double cK2, const double* f2,
+                      double* val2);
 // b = scale * int f phi_a - l_a, l_a = sum over boundary b of K_ab g_b (gnod may be null);
 // scratch: 8 nt doubles.
 void launch_load(hipStream_t s, int64_t n, int64_t nt, const int32_t* adj_ptr, const int32_t* adj_tet,

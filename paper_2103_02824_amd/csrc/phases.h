@@ -42,6 +42,7 @@ struct StepRun {
 mlc_status phase_fields(StepRun& S);
 mlc_status phase_operators(StepRun& S);
 mlc_status phase_after_solve(StepRun& S);
+mlc_status phase_gram_fixed(StepRun& S, hipStream_t s, double* red);
 mlc_status phase_gram(StepRun& S);
 mlc_status phase_inner(StepRun& S);
 mlc_status phase_recon(StepRun& S);

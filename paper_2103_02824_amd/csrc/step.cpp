@@ -384,8 +384,8 @@ mlc_status phase_operators(StepRun& S) {
   // V_ext + V_xc + g at the quadrature points (A_fix of the inner problems)
   launch_field(s, nt, d.tets, d.g, d.v2d, nullptr, d.vext, d.vxc, d.fld);
   const int64_t nnz = (int64_t)c->col.size();
-  launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 0.5, d.veff, S.sigma, d.valA,
-                   d.dinvA, 0.5, d.fld, d.valF);
+  launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_of, c->slot_ptr.back(), d.diag_slot, d.elem, 0.5, d.veff,
+                   S.sigma, d.valA, d.dinvA, 0.5, d.fld, d.valF);
   if (c->opt.precond == MLC_PC_CHEBYSHEV) launch_gershgorin(s, n, d.rowptr, d.valA, d.dinvA, d.red, d.lmax);
   launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr, nullptr);
   launch_scale_cols_to(s, n, N, d.Q, d.colv, d.B);
@@ -447,9 +447,34 @@ mlc_status phase_after_solve(StepRun& S) {
   return MLC_OK;
 }
 
-// Step 6 continued and Algorithm 3 step 1: M_{w0}, the Gram blocks P^T O U and
-// U^T O U, the Hartree pieces and the coarse-pattern integrals, copied to the
-// host (the caller synchronises before phase_inner).
+// Algorithm 3 step 1, the part that does not involve w0: the Gram blocks
+// P^T O U and U^T O U of O = A_fix, M, K (eqs. Adef, bdef, betadef) and the
+// per-orbital coarse-pattern integrals (eqs. Ah4def, rhsdef), on stream s
+// with partials in red. It may run beside the Hartree solve: it reads U and
+// the fixed operators and writes only its own blocks.
+mlc_status phase_gram_fixed(StepRun& S, hipStream_t s, double* red) {
+  mlc_ctx* c = S.c;
+  auto& d = c->d;
+  const int64_t n = c->n, nH = c->nH, cnt = c->cnt;
+  const int N = c->N;
+  SmallLayout L(nH, N);
+  const double* vals[4] = {d.valF, d.valW, d.valM, d.valK};
+  for (int o : {0, 2, 3}) {
+    double* Yo = d.Y + (int64_t)o * n * N;
+    launch_spmm2(s, n, N, d.rowptr, d.col, vals[o], d.X, Yo, nullptr, nullptr);
+    launch_restrict(s, nH, N, d.PTptr, d.PTidx, d.PTw, Yo, d.small + L.ptF + (int64_t)o * nH * N);
+    launch_gram(s, n, N, d.X, Yo, red);
+    launch_reduce_cols(s, N * N, gram_blocks(n), red, d.small + L.utF + (int64_t)o * N * N);
+  }
+  launch_coarse_orb(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.chat, d.v2d, d.X, N, d.cel_orb);
+  HIPCHK(hipGetLastError());
+  return MLC_OK;
+}
+
+// Step 6 continued and Algorithm 3 step 1 (after phase_gram_fixed): M_{w0},
+// its Gram blocks, the Hartree pieces and the coarse-pattern integrals of the
+// fixed operators and of M_{w0}, copied to the host (the caller synchronises
+// before phase_inner).
 mlc_status phase_gram(StepRun& S) {
   mlc_ctx* c = S.c;
   auto& d = c->d;
@@ -461,8 +486,8 @@ mlc_status phase_gram(StepRun& S) {
   if (c->hartree) {
     if (S.pr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the Hartree problem");
     launch_field(s, nt, d.tets, nullptr, d.v2d, d.w0, nullptr, nullptr, d.fld2);
-    launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_src, d.diag_slot, d.elem, 0.0, d.fld2, 0.0, d.valW,
-                     nullptr, 0.0, nullptr, nullptr);
+    launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_of, c->slot_ptr.back(), d.diag_slot, d.elem, 0.0,
+                     d.fld2, 0.0, d.valW, nullptr, 0.0, nullptr, nullptr);
   } else {
     HIPCHK(hipMemsetAsync(d.w0, 0, sizeof(double) * n, s));
     HIPCHK(hipMemsetAsync(d.lvec, 0, sizeof(double) * n, s));
@@ -471,13 +496,12 @@ mlc_status phase_gram(StepRun& S) {
   }
   S.r.poisson_iters = S.pr.iters;
   S.r.poisson_relres = S.pr.relres;
-  const double* vals[4] = {d.valF, d.valW, d.valM, d.valK};
-  for (int o = 0; o < 4; ++o) {
-    double* Yo = d.Y + (int64_t)o * n * N;
-    launch_spmm2(s, n, N, d.rowptr, d.col, vals[o], d.X, Yo, nullptr, nullptr);
-    launch_restrict(s, nH, N, d.PTptr, d.PTidx, d.PTw, Yo, d.small + L.ptF + (int64_t)o * nH * N);
+  {
+    double* Yo = d.Y + (int64_t)n * N;
+    launch_spmm2(s, n, N, d.rowptr, d.col, d.valW, d.X, Yo, nullptr, nullptr);
+    launch_restrict(s, nH, N, d.PTptr, d.PTidx, d.PTw, Yo, d.small + L.ptF + (int64_t)nH * N);
     launch_gram(s, n, N, d.X, Yo, d.red);
-    launch_reduce_cols(s, N * N, gram_blocks(n), d.red, d.small + L.utF + (int64_t)o * N * N);
+    launch_reduce_cols(s, N * N, gram_blocks(n), d.red, d.small + L.utF + (int64_t)N * N);
   }
   HIPCHK(hipMemsetAsync(d.small + L.d, 0, sizeof(double) * (2 * nH + 8), s));
   if (c->hartree) {
@@ -491,7 +515,6 @@ mlc_status phase_gram(StepRun& S) {
   }
   // coarse-pattern integrals (eqs. Adef, Ah4def, rhsdef, FG)
   launch_coarse_ops(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.chat, d.cgeo, d.fld, d.fld2, d.cel_ops);
-  launch_coarse_orb(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.chat, d.v2d, d.X, N, d.cel_orb);
   HIPCHK(hipEventRecord(S.ev[1], s));
   return S.defer_copies ? MLC_OK : phase_gram_copy(S);
 }
@@ -656,18 +679,31 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   }
   S.r.ir_outer = outer_iters;
   PHASE(phase_after_solve(S));
+  // the w0-independent Gram blocks beside the Hartree solve (which is
+  // latency-bound), on the side stream
+  const bool side = c->hartree && c->side;
+  if (side) {
+    HIPCHK(hipEventRecord(c->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    PHASE(phase_gram_fixed(S, c->side, d.red2));
+    HIPCHK(hipEventRecord(c->ev_join, c->side));
+  } else {
+    PHASE(phase_gram_fixed(S, s, d.red));
+  }
   // step 6: Hartree direction w0, warm-started from the previous step's w0 (zero at bind)
   if (c->hartree) {
     double dummy = 0.0;
     int64_t dn = 0;
-    PolyPC<double> pcK{d.lmax + 1, c->opt.cheb_ratio, c->opt.cheb_degree, {d.Y, d.Y + n}, d.Y + 2 * n,
+    PolyPC<double> pcK{d.lmax + 1, c->opt.cheb_ratio, c->opt.cheb_degree, {d.Yh, d.Yh + n}, d.Yh + 2 * n,
                        d.red + cg_max_blocks()};
-    CoarsePC ccK{d.KHinv, c->nH, d.PTptr, d.PTidx, d.PTw, d.Pk, d.Pw, d.rH, d.eH, d.Y + 3 * n, d.red + cg_max_blocks()};
+    CoarsePC ccK{d.KHinv, c->nH, d.PTptr, d.PTidx, d.PTw, d.Pk, d.Pw, d.rH, d.eH, d.Yh + 3 * n,
+                 d.red + cg_max_blocks()};
     CgArgs<double> pa{d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP, nullptr,
                       c->opt.precond == MLC_PC_CHEBYSHEV ? &pcK : nullptr,
                       c->opt.hartree_coarse && d.KHinv ? &ccK : nullptr};
     PHASE(cg<double>(c, 1, n, 1, pa, c->opt.poisson_rtol, c->opt.cg_maxit, false, &dummy, &dn, &S.pr));
   }
+  if (side) HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
   PHASE(phase_gram(S));
   HIPCHK(hipStreamSynchronize(s));
   PHASE(phase_inner(S));
