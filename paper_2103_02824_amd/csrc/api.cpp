@@ -97,6 +97,7 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->PTw = w.take<double>((int64_t)c->PTw.size());
   d->cgrp_ptr = w.take<int32_t>(cnt + 1);
   d->cgrp_tet = w.take<int32_t>(nt);
+  d->cgrp_dof = w.take<int32_t>(4 * nt);
   d->cgeo = w.take<double>(12 * cnt);
   d->cel_ops = w.take<double>(40 * cnt);
   d->cel_orb = w.take<double>(14 * cnt * N);
@@ -196,6 +197,7 @@ mlc_status upload_and_init(mlc_ctx* c) {
   HIPCHK(up(s, d.PTw, c->PTw));
   HIPCHK(up(s, d.cgrp_ptr, c->cgrp_ptr));
   HIPCHK(up(s, d.cgrp_tet, c->cgrp_tet));
+  HIPCHK(up(s, d.cgrp_dof, c->cgrp_dof));
   HIPCHK(up(s, d.cgeo, c->cgeo));
   HIPCHK(up(s, d.occ, c->occ));
   HIPCHK(up(s, d.RZ, RZ));
@@ -214,7 +216,7 @@ mlc_status upload_and_init(mlc_ctx* c) {
                    d.valM, nullptr, 0.0, nullptr, nullptr);
   launch_gershgorin(s, c->n, d.rowptr, d.valK, d.dinvK, d.red, d.lmax + 1);
   launch_coarse_tri(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.cel_tri);
-  launch_coarse_hats(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.chat);
+  launch_coarse_hats(s, c->cnt, c->nt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.chat);
   if (d.KHinv) {
     // coarse stiffness K_H = P^T K P of the nested P1 spaces (element by element: the coarse hat
     // gradients are constant on a coarse tet), its Cholesky factor and explicit inverse

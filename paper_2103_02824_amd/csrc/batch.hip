@@ -18,6 +18,7 @@
 #include <type_traits>
 
 #include "batch.h"
+#include "row_gather.h"
 
 namespace mlc {
 
@@ -68,6 +69,10 @@ __device__ __forceinline__ void cheb_coef(double lmax, double ratio, int j, doub
 // Rows [r0, r1) of Y = A S for NT <= 8 columns: G lanes per row, every lane
 // strides the row's nonzeros by G and keeps the NT sums in registers. With
 // dot: per-block column sums of S . Y into sd[0..NT).
+// Nonzeros per lane and pass of the tile row gathers (row_gather).
+constexpr int tile_unroll(int NT, int G) { return G >= 8 ? 2 : (NT <= 3 ? 4 : 2); }
+constexpr int tile_cheb_unroll(int NT, int G) { return G >= 8 ? 1 : (NT <= 3 ? 2 : 1); }
+
 template <int NT, int G, typename T>
 __device__ void tile_spmm_small(int64_t r0, int64_t r1, const int32_t* __restrict__ rowptr,
                                 const int32_t* __restrict__ col, const T* __restrict__ val, const T* __restrict__ S,
@@ -83,15 +88,7 @@ __device__ void tile_spmm_small(int64_t r0, int64_t r1, const int32_t* __restric
     T acc[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[c] = T(0);
-    if (r < r1) {
-      int j1 = rowptr[r + 1];
-      for (int j = rowptr[r] + sub; j < j1; j += G) {
-        T a = val[j];
-        const T* xr = S + (int64_t)col[j] * NT;
-#pragma unroll
-        for (int c = 0; c < NT; ++c) acc[c] += a * xr[c];
-      }
-    }
+    if (r < r1) row_gather<NT, G, tile_unroll(NT, G)>(r, sub, rowptr, col, val, S, acc);
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
@@ -171,15 +168,7 @@ __device__ void tile_cheb_small(int64_t r0, int64_t r1, const BProb<T>& D, const
     T acc[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[c] = T(0);
-    if (r < r1) {
-      int j1 = D.rowptr[r + 1];
-      for (int j = D.rowptr[r] + sub; j < j1; j += G) {
-        T a = D.val[j];
-        const T* zr = Zin + (int64_t)D.col[j] * NT;
-#pragma unroll
-        for (int c = 0; c < NT; ++c) acc[c] += a * zr[c];
-      }
-    }
+    if (r < r1) row_gather<NT, G, tile_cheb_unroll(NT, G)>(r, sub, D.rowptr, D.col, D.val, Zin, acc);
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
@@ -296,7 +285,7 @@ __global__ void __launch_bounds__(BS) kb_cheb(const BProb<T>* __restrict__ probs
 // SpMM over all tiles. mode 0 (CG): Q = A P with partials of P.Q, tiles of
 // problems without active columns skip; mode 1: Q = A X, no partials.
 template <int G, typename T>
-__global__ void __launch_bounds__(BS) kb_spmm(const BProb<T>* __restrict__ probs, const int32_t* __restrict__ tile_prob,
+__global__ void __launch_bounds__(BS, 8) kb_spmm(const BProb<T>* __restrict__ probs, const int32_t* __restrict__ tile_prob,
                                               int TR, int NB, int mode, double* __restrict__ part,
                                               const int32_t* __restrict__ flags) {
   __shared__ double sd[BS];

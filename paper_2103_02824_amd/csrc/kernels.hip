@@ -587,13 +587,33 @@ __device__ __forceinline__ double block_sum(double v, double* ws) {
   return (ws[0] + ws[1]) + (ws[2] + ws[3]);
 }
 
+// The same for K values per thread at once (TPB = 256, four waves): every
+// value's wave sum, then one barrier; thread k < K returns the block sum of
+// value k (summed in the order of block_sum), the others 0. ws: 4 K doubles.
+template <int K>
+__device__ __forceinline__ double block_sums(const double (&v)[K], double* ws) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) ws[wid * K + k] = x;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  const double r = t < K ? (ws[t] + ws[K + t]) + (ws[2 * K + t] + ws[3 * K + t]) : 0.0;
+  __syncthreads();  // ws may be reused at once
+  return r;
+}
+
 // Operators: [A_fix = 1/2 K + M_{fA}] [M_{fW}] [M] [K] -> 40 values per coarse
 // tet. One workgroup per coarse tet; threads stride over its fine tets.
 // Per fine tet, in coarse-group order e (fixed per mesh): the four coarse
-// hats of its parent at its four quadrature points, chat[17 e + 4 q + j],
-// and its volume, chat[17 e + 16].
+// hats of its parent at its four quadrature points, chat[(4 q + j) ng + e],
+// and its volume, chat[16 ng + e] (ng = number of fine tets; one array per
+// value, so that consecutive threads read consecutive addresses).
 constexpr int CHAT = 17;
-__global__ void __launch_bounds__(TPB) k_coarse_hats(int64_t cnt, const int32_t* __restrict__ grp_ptr,
+__global__ void __launch_bounds__(TPB) k_coarse_hats(int64_t cnt, int64_t ng, const int32_t* __restrict__ grp_ptr,
                                                      const int32_t* __restrict__ grp_tet,
                                                      const int32_t* __restrict__ tets, const double* __restrict__ geo,
                                                      const double* __restrict__ xyz, const double* __restrict__ cgeo,
@@ -605,14 +625,13 @@ __global__ void __launch_bounds__(TPB) k_coarse_hats(int64_t cnt, const int32_t*
     double Bc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) coarse_bary(cg, xyz, tets[4 * t + a], Bc[a]);
-    double* o = chat + (int64_t)CHAT * e;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const double sj = Bc[0][j] + Bc[1][j] + Bc[2][j] + Bc[3][j];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) o[4 * q + j] = QB * sj + (QA - QB) * Bc[q][j];
+      for (int q = 0; q < 4; ++q) chat[(int64_t)(4 * q + j) * ng + e] = QB * sj + (QA - QB) * Bc[q][j];
     }
-    o[16] = geo[16 * t];
+    chat[16 * ng + e] = geo[16 * t];
   }
 }
 
@@ -627,12 +646,12 @@ __device__ __forceinline__ void coarse_grads(const double* __restrict__ cg, doub
   }
 }
 
-__global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* __restrict__ grp_ptr,
+__global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, int64_t ng, const int32_t* __restrict__ grp_ptr,
                                                     const int32_t* __restrict__ grp_tet,
                                                     const double* __restrict__ chat, const double* __restrict__ cgeo,
                                                     const double* __restrict__ fA, const double* __restrict__ fW,
                                                     double* __restrict__ out) {
-  __shared__ double ws[TPB / 64];
+  __shared__ double ws[4 * 40];
   int64_t C = blockIdx.x;
   double acc[40];
 #pragma unroll
@@ -641,13 +660,12 @@ __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* 
   coarse_grads(cgeo + 12 * C, gc);
   for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
     const int64_t t = grp_tet[e];
-    const double* h = chat + (int64_t)CHAT * e;
-    const double vol = h[16];
+    const double vol = chat[16 * ng + e];
     double pq[4][4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) pq[q][j] = h[4 * q + j];
+      for (int j = 0; j < 4; ++j) pq[q][j] = chat[(int64_t)(4 * q + j) * ng + e];
     double wA[4], wW[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -674,37 +692,32 @@ __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, const int32_t* 
         acc[30 + k] += kv;
       }
   }
-#pragma unroll
-  for (int k = 0; k < 40; ++k) {
-    double v = block_sum(acc[k], ws);
-    if (threadIdx.x == 0) out[40 * C + k] = v;
-  }
+  const double v = block_sums<40>(acc, ws);
+  if (threadIdx.x < 40) out[40 * C + threadIdx.x] = v;
 }
 
 // Per orbital i and coarse tet: the 10 entries (u_i psi_j, psi_m) and the 4
-// entries (u_i^2, psi_j); orbitals two at a time per pass over the fine tets.
+// entries (u_i^2, psi_j); ORB_CHUNK orbitals per pass over the fine tets,
+// whose DoFs come from the per-mesh table grp_dof (group order).
 constexpr int ORB_CHUNK = 2;
-__global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, const int32_t* __restrict__ grp_ptr,
-                                                    const int32_t* __restrict__ grp_tet,
-                                                    const int32_t* __restrict__ tets, const double* __restrict__ chat,
-                                                    const int32_t* __restrict__ v2d, const double* __restrict__ U,
+__global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, int64_t ng, const int32_t* __restrict__ grp_ptr,
+                                                    const int32_t* __restrict__ grp_dof,
+                                                    const double* __restrict__ chat, const double* __restrict__ U,
                                                     int N, double* __restrict__ out) {
-  __shared__ double ws[TPB / 64];
+  __shared__ double ws[4 * ORB_CHUNK * 14];
   int64_t C = blockIdx.x;
   for (int i0 = 0; i0 < N; i0 += ORB_CHUNK) {
     const int nc = N - i0 < ORB_CHUNK ? N - i0 : ORB_CHUNK;
-    double acc[ORB_CHUNK][14];
+    double acc[ORB_CHUNK * 14];
 #pragma unroll
-    for (int o = 0; o < ORB_CHUNK; ++o)
-#pragma unroll
-      for (int k = 0; k < 14; ++k) acc[o][k] = 0.0;
+    for (int k = 0; k < ORB_CHUNK * 14; ++k) acc[k] = 0.0;
     for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
-      const int64_t t = grp_tet[e];
-      const double* h = chat + (int64_t)CHAT * e;
-      const double w = 0.25 * h[16];
-      int dof[4];
+      const int4 dq = reinterpret_cast<const int4*>(grp_dof)[e];
+      const int dof[4] = {dq.x, dq.y, dq.z, dq.w};
+      double h[16];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) dof[a] = v2d[tets[4 * t + a]];
+      for (int k = 0; k < 16; ++k) h[k] = chat[(int64_t)k * ng + e];
+      const double w = 0.25 * chat[16 * ng + e];
 #pragma unroll
       for (int o = 0; o < ORB_CHUNK; ++o) {
         if (o >= nc) continue;
@@ -721,21 +734,14 @@ __global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, const int32_t* 
 #pragma unroll
           for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int m = j; m < 4; ++m) acc[o][j * 4 - (j * (j - 1)) / 2 + (m - j)] += w * uq * ps[j] * ps[m];
+            for (int m = j; m < 4; ++m) acc[14 * o + j * 4 - (j * (j - 1)) / 2 + (m - j)] += w * uq * ps[j] * ps[m];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[o][10 + j] += w * uq * uq * ps[j];
+          for (int j = 0; j < 4; ++j) acc[14 * o + 10 + j] += w * uq * uq * ps[j];
         }
       }
     }
-#pragma unroll
-    for (int o = 0; o < ORB_CHUNK; ++o) {
-      if (o >= nc) continue;
-#pragma unroll
-      for (int k = 0; k < 14; ++k) {
-        double v = block_sum(acc[o][k], ws);
-        if (threadIdx.x == 0) out[14 * (C * N + i0 + o) + k] = v;
-      }
-    }
+    const double v = block_sums<ORB_CHUNK * 14>(acc, ws);
+    if ((int)threadIdx.x < 14 * nc) out[14 * (C * N + i0) + threadIdx.x] = v;
   }
 }
 
@@ -746,7 +752,7 @@ __global__ void __launch_bounds__(TPB) k_coarse_tri(int64_t cnt, const int32_t* 
                                                     const int32_t* __restrict__ tets, const double* __restrict__ geo,
                                                     const double* __restrict__ xyz, const double* __restrict__ cgeo,
                                                     double* __restrict__ out) {
-  __shared__ double ws[TPB / 64];
+  __shared__ double ws[4 * 20];
   int64_t C = blockIdx.x;
   double acc[20];
 #pragma unroll
@@ -773,11 +779,8 @@ __global__ void __launch_bounds__(TPB) k_coarse_tri(int64_t cnt, const int32_t* 
           for (int l = m; l < 4; ++l, ++k) acc[k] += w * ps[j] * ps[m] * ps[l];
     }
   }
-#pragma unroll
-  for (int k = 0; k < 20; ++k) {
-    double v = block_sum(acc[k], ws);
-    if (threadIdx.x == 0) out[20 * C + k] = v;
-  }
+  const double v = block_sums<20>(acc, ws);
+  if (threadIdx.x < 20) out[20 * C + threadIdx.x] = v;
 }
 
 // Phi[a,i] = sum_j Pw[a,j] phiH[Pk[a,j], i] + theta2[i] U[a,i]
@@ -1137,20 +1140,19 @@ void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double*
   else
     hipLaunchKernelGGL(k_gram_wide, dim3(gram_blocks(n)), dim3(TPB), 0, s, n, N, U, Y, partial);
 }
-void launch_coarse_hats(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
+void launch_coarse_hats(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* grp_ptr, const int32_t* grp_tet,
                         const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* chat) {
-  hipLaunchKernelGGL(k_coarse_hats, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, geo, xyz, cgeo,
-                     chat);
+  hipLaunchKernelGGL(k_coarse_hats, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, ng, grp_ptr, grp_tet, tets, geo, xyz,
+                     cgeo, chat);
 }
-void launch_coarse_ops(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
+void launch_coarse_ops(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* grp_ptr, const int32_t* grp_tet,
                        const double* chat, const double* cgeo, const double* fA, const double* fW, double* out) {
-  hipLaunchKernelGGL(k_coarse_ops, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, chat, cgeo, fA, fW,
-                     out);
+  hipLaunchKernelGGL(k_coarse_ops, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, ng, grp_ptr, grp_tet, chat, cgeo, fA,
+                     fW, out);
 }
-void launch_coarse_orb(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
-                       const int32_t* tets, const double* chat, const int32_t* v2d, const double* U, int N,
-                       double* out) {
-  hipLaunchKernelGGL(k_coarse_orb, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, grp_ptr, grp_tet, tets, chat, v2d, U, N,
+void launch_coarse_orb(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* grp_ptr, const int32_t* grp_dof,
+                       const double* chat, const double* U, int N, double* out) {
+  hipLaunchKernelGGL(k_coarse_orb, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, ng, grp_ptr, grp_dof, chat, U, N,
                      out);
 }
 void launch_coarse_tri(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,

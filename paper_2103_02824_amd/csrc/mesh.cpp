@@ -415,6 +415,10 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
     std::vector<int32_t> fill(c->cgrp_ptr.begin(), c->cgrp_ptr.end() - 1);
     for (int64_t t = 0; t < c->nt; ++t) c->cgrp_tet[fill[c->parent[t]]++] = (int32_t)t;
   }
+  // the interior DoFs of every fine tet's vertices in coarse-group order (-1: boundary)
+  c->cgrp_dof.assign(4 * c->nt, -1);
+  for (int64_t e = 0; e < c->nt; ++e)
+    for (int a = 0; a < 4; ++a) c->cgrp_dof[4 * e + a] = c->v2d[c->tets[4 * (int64_t)c->cgrp_tet[e] + a]];
   return MLC_OK;
 }
 

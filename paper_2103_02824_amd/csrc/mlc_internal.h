@@ -82,11 +82,12 @@ struct Dev {
   // coarse grouping
   int32_t* cgrp_ptr = nullptr;  // cnt + 1
   int32_t* cgrp_tet = nullptr;  // nt
+  int32_t* cgrp_dof = nullptr;  // 4 nt: DoFs of the fine tets in coarse-group order (-1: boundary)
   double* cgeo = nullptr;       // cnt x 12
   double* cel_ops = nullptr;    // cnt x 40
   double* cel_orb = nullptr;    // cnt x N x 14
   double* cel_tri = nullptr;    // cnt x 20
-  double* chat = nullptr;       // nt x 17: coarse hats at fine quadrature points, fine volume
+  double* chat = nullptr;       // 17 x nt: coarse hats at fine quadrature points, fine volume
   // small
   double* small = nullptr;      // packed small blocks (see step.cpp)
   double* coarse_in = nullptr;  // phi_H (nH x N), w_H (nH), theta2 (N)
@@ -152,7 +153,7 @@ struct mlc_ctx {
   std::vector<int32_t> PTptr, PTidx;
   std::vector<double> PTw;
   std::vector<int32_t> parent;          // fine tet -> coarse tet
-  std::vector<int32_t> cgrp_ptr, cgrp_tet;
+  std::vector<int32_t> cgrp_ptr, cgrp_tet, cgrp_dof;
   std::vector<double> cgeo;             // cnt x 12
   std::vector<double> cvol;             // coarse tet volumes
   std::vector<double> Pfull_w;          // nv x 4 weights (all fine vertices, coarse vertex ids)
@@ -324,15 +325,15 @@ void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, do
 void launch_restrict(hipStream_t s, int64_t nH, int N, const int32_t* PTptr, const int32_t* PTidx, const double* PTw,
                      const double* Y, double* out);
 void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double* Y, double* partial);
-// chat: per fine tet in coarse-group order, the parent's coarse hats at its
-// quadrature points (16) and its volume (17 doubles; fixed per mesh).
-void launch_coarse_hats(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
+// chat: per fine tet in coarse-group order e, the parent's coarse hats at its
+// quadrature points (16) and its volume: 17 arrays of ng = nt doubles (value
+// k of tet e at k ng + e; fixed per mesh).
+void launch_coarse_hats(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* grp_ptr, const int32_t* grp_tet,
                         const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* chat);
-void launch_coarse_ops(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
+void launch_coarse_ops(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* grp_ptr, const int32_t* grp_tet,
                        const double* chat, const double* cgeo, const double* fA, const double* fW, double* out);
-void launch_coarse_orb(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
-                       const int32_t* tets, const double* chat, const int32_t* v2d, const double* U, int N,
-                       double* out);
+void launch_coarse_orb(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* grp_ptr, const int32_t* grp_dof,
+                       const double* chat, const double* U, int N, double* out);
 void launch_coarse_tri(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
                        const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* out);
 void launch_reconstruct(hipStream_t s, int64_t n, int N, const int32_t* Pk, const double* Pw, const double* phiH,

@@ -466,7 +466,7 @@ mlc_status phase_gram_fixed(StepRun& S, hipStream_t s, double* red) {
     launch_gram(s, n, N, d.X, Yo, red);
     launch_reduce_cols(s, N * N, gram_blocks(n), red, d.small + L.utF + (int64_t)o * N * N);
   }
-  launch_coarse_orb(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.chat, d.v2d, d.X, N, d.cel_orb);
+  launch_coarse_orb(s, cnt, c->nt, d.cgrp_ptr, d.cgrp_dof, d.chat, d.X, N, d.cel_orb);
   HIPCHK(hipGetLastError());
   return MLC_OK;
 }
@@ -514,7 +514,7 @@ mlc_status phase_gram(StepRun& S) {
     launch_reduce_cols(s, 1, elem_blocks(n, 1), d.red, d.small + L.sc + 1);
   }
   // coarse-pattern integrals (eqs. Adef, Ah4def, rhsdef, FG)
-  launch_coarse_ops(s, cnt, d.cgrp_ptr, d.cgrp_tet, d.chat, d.cgeo, d.fld, d.fld2, d.cel_ops);
+  launch_coarse_ops(s, cnt, nt, d.cgrp_ptr, d.cgrp_tet, d.chat, d.cgeo, d.fld, d.fld2, d.cel_ops);
   HIPCHK(hipEventRecord(S.ev[1], s));
   return S.defer_copies ? MLC_OK : phase_gram_copy(S);
 }
