@@ -135,8 +135,10 @@ def main():
     ap.add_argument("--cg-rtol", type=float, default=1e-9)
     ap.add_argument("--precision", choices=["fp64", "fp32ir"], default="fp64",
                     help="step-5 arithmetic: plain FP64 CG, or FP32 CG inside FP64 iterative refinement")
-    ap.add_argument("--precond", choices=["jacobi", "chebyshev"], default="chebyshev",
-                    help="CG preconditioner of the step-5 and Hartree solves")
+    ap.add_argument("--precond", choices=["jacobi", "chebyshev"], default=None,
+                    help="CG preconditioner of the step-5 and Hartree solves (default: chebyshev for one system, "
+                         "jacobi for --workload batch, where the tile SpMM is bandwidth-bound and the polynomial "
+                         "steps cost more than the iterations they save)")
     ap.add_argument("--cheb-degree", type=int, default=8)
     ap.add_argument("--cheb-ratio", type=float, default=100.0)
     ap.add_argument("--hartree-coarse", type=int, default=1, choices=[0, 1],
@@ -153,6 +155,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this size twice (hardware counter calibration)")
     args = ap.parse_args()
+    if args.precond is None:
+        args.precond = "jacobi" if args.workload == "batch" else "chebyshev"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the path shards by orbitals "
               f"across GPUs, which is not run here.", file=sys.stderr)

@@ -279,8 +279,9 @@ mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* til
     }
     b->graph_rt2[kind] = rt2;
   }
-  auto launch_graph = [&](int g) -> mlc_status {
-    if (!graphs[g]) {
+  // every chunk size is captured at the first solve of a kind and shape
+  if (graph && !graphs[0]) {
+    for (int g = 0; g < mlc::CHUNK_GRAPHS; ++g) {
       hipGraph_t gr;
       BCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < (2 << g); ++k)
@@ -290,10 +291,15 @@ mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* til
       hipError_t e = hipGraphInstantiate(&graphs[g], gr, nullptr, nullptr, 0);
       (void)hipGraphDestroy(gr);
       if (e != hipSuccess) {
-        graphs[g] = nullptr;
+        for (int h = 0; h <= g; ++h) {
+          if (graphs[h]) (void)hipGraphExecDestroy(graphs[h]);
+          graphs[h] = nullptr;
+        }
         return bfail(b, MLC_ERR_HIP, "hipGraphInstantiate (batch)");
       }
     }
+  }
+  auto launch_graph = [&](int g) -> mlc_status {
     BCHK(hipGraphLaunch(graphs[g], s));
     return MLC_OK;
   };

@@ -179,8 +179,10 @@ mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs<T>& a, double
     c->cg_graph_rt2[kind] = rt2;
     c->cg_graph_pc[kind] = pcdeg;
   }
-  auto launch_graph = [&](int g) -> mlc_status {
-    if (!graphs[g]) {
+  // every chunk size is captured at the first solve of a kind (a one-time
+  // cost), so that later predicted chunks never wait for an instantiation
+  if (graph && !graphs[0]) {
+    for (int g = 0; g < CHUNK_GRAPHS; ++g) {
       hipGraph_t gr;
       HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < (2 << g); ++k) (void)enqueue_iteration<T>(c, c->cap_stream, n, N, a, rt2, k & 1);
@@ -188,10 +190,15 @@ mlc_status cg(mlc_ctx* c, int kind, int64_t n, int N, const CgArgs<T>& a, double
       hipError_t e = hipGraphInstantiate(&graphs[g], gr, nullptr, nullptr, 0);
       (void)hipGraphDestroy(gr);
       if (e != hipSuccess) {
-        graphs[g] = nullptr;
+        for (int h = 0; h <= g; ++h) {
+          if (graphs[h]) (void)hipGraphExecDestroy(graphs[h]);
+          graphs[h] = nullptr;
+        }
         return hip_fail(c, e, "hipGraphInstantiate");
       }
     }
+  }
+  auto launch_graph = [&](int g) -> mlc_status {
     HIPCHK(hipGraphLaunch(graphs[g], s));
     return MLC_OK;
   };
