@@ -264,7 +264,15 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "detail": {"cg_iters_per_step": cg_its,
+        "detail": {"pcg_throughput": {
+                       "step5_dof_orbital_iterations_per_s":
+                           n * sum(r["cg_iters_sum"] for r in reps) / (1e-3 * sum(r["t_solve_ms"] for r in reps)),
+                       "hartree_dof_iterations_per_s":
+                           n * sum(r["poisson_iters"] for r in reps) / (1e-3 * max(sum(r["t_poisson_ms"] for r in reps),
+                                                                                   1e-9)),
+                       "t_solve_ms_per_step": float(np.mean([r["t_solve_ms"] for r in reps])),
+                       "t_poisson_ms_per_step": float(np.mean([r["t_poisson_ms"] for r in reps]))},
+                   "cg_iters_per_step": cg_its,
                    "poisson_iters_per_step": int(np.mean([r["poisson_iters"] for r in reps])),
                    "inner_ms_per_step": float(np.mean([r["t_inner_ms"] for r in reps])),
                    "inner_iters_per_step": float(np.mean([r["inner_iters"] for r in reps])),

@@ -161,6 +161,8 @@ typedef struct {
   int32_t ir_outer;           /* refinement passes (precision FP32_IR)      */
   int32_t guess_learned_cols; /* columns started from the learned guess (mlc_set_guess) */
   double guess_resid_ratio;   /* max over columns of |b - A x0| / |b - A phi| (x0 = start used) */
+  double t_solve_ms;          /* device: the step-5 solve (0 in a batch: see mlc_batch_report) */
+  double t_poisson_ms;        /* device: the Hartree solve (0 in a batch)   */
 } mlc_step_report;
 
 typedef struct mlc_ctx mlc_ctx;

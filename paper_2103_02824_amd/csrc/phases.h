@@ -18,7 +18,10 @@ struct CgRes {
 struct StepRun {
   mlc_ctx* c;
   mlc_step_report r;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // 0-1 fine stage, 2-3 reconstruction, 4-5 step-5 solve, 6-7 Hartree solve
+  // (4-7 recorded by the single-system step only: solve_timed)
+  hipEvent_t ev[8] = {};
+  bool solve_timed = false;
   double mom[16] = {};
   double colv[2 * MLC_MAX_ORBITALS] = {};
   double sigma = 0.0;

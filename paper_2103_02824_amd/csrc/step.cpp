@@ -345,7 +345,7 @@ mlc_status solve_ir(mlc_ctx* c, int64_t n, int N, bool timed, double* spmm_ms, i
 
 StepRun::StepRun(mlc_ctx* ctx) : c(ctx) { std::memset(&r, 0, sizeof(r)); }
 StepRun::~StepRun() {
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < 8; ++k)
     if (ev[k]) (void)hipEventDestroy(ev[k]);
 }
 
@@ -356,7 +356,7 @@ mlc_status phase_fields(StepRun& S) {
   auto& d = c->d;
   hipStream_t s = c->stream;
   SmallLayout L(c->nH, c->N);
-  for (int k = 0; k < 4; ++k) HIPCHK(hipEventCreate(&S.ev[k]));
+  for (int k = 0; k < 8; ++k) HIPCHK(hipEventCreate(&S.ev[k]));
   HIPCHK(hipEventRecord(S.ev[0], s));
   launch_qp_fields(s, c->nt, d.tets, d.v2d, d.Phi, c->N, d.occ, d.w, d.vext, d.geo, d.qpx, c->xc, c->xalpha, d.vxc,
                    d.exc, d.veff, d.rho, d.red);
@@ -622,6 +622,12 @@ mlc_status phase_finish(StepRun& S, mlc_step_report* rep) {
   S.r.t_fine_ms = ms;
   HIPCHK(hipEventElapsedTime(&ms, S.ev[2], S.ev[3]));
   S.r.t_recon_ms = ms;
+  if (S.solve_timed) {
+    HIPCHK(hipEventElapsedTime(&ms, S.ev[4], S.ev[5]));
+    S.r.t_solve_ms = ms;
+    HIPCHK(hipEventElapsedTime(&ms, S.ev[6], S.ev[7]));
+    S.r.t_poisson_ms = ms;
+  }
   double E = S.tail[3];
   for (int i = 0; i < N; ++i) E += c->occ[i] * S.io.lam[i];
   S.r.energy = E;
@@ -678,12 +684,14 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   const bool cheb = c->opt.precond == MLC_PC_CHEBYSHEV;
   double* rz_part = d.red + (int64_t)cg_max_blocks() * N;
   PolyPC<double> pcA{d.lmax, c->opt.cheb_ratio, c->opt.cheb_degree, {d.Y, d.Y + n * N}, d.Y + 2 * n * N, rz_part};
+  HIPCHK(hipEventRecord(S.ev[4], s));
   if (c->opt.precision == MLC_PREC_FP32_IR) {
     PHASE(solve_ir(c, n, N, timed, &S.r.t_spmm_ms, &S.r.n_spmm, &S.cr, &outer_iters));
   } else {
     CgArgs<double> ca{d.valA, d.dinvA, d.B, d.X, d.R, d.P, d.Q, d.scal, d.flags, nullptr, cheb ? &pcA : nullptr};
     PHASE(cg<double>(c, 0, n, N, ca, c->opt.cg_rtol, c->opt.cg_maxit, timed, &S.r.t_spmm_ms, &S.r.n_spmm, &S.cr));
   }
+  HIPCHK(hipEventRecord(S.ev[5], s));
   S.r.ir_outer = outer_iters;
   PHASE(phase_after_solve(S));
   // the w0-independent Gram blocks beside the Hartree solve (which is
@@ -698,6 +706,7 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
     PHASE(phase_gram_fixed(S, s, d.red));
   }
   // step 6: Hartree direction w0, warm-started from the previous step's w0 (zero at bind)
+  HIPCHK(hipEventRecord(S.ev[6], s));
   if (c->hartree) {
     double dummy = 0.0;
     int64_t dn = 0;
@@ -710,6 +719,8 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
                       c->opt.hartree_coarse && d.KHinv ? &ccK : nullptr};
     PHASE(cg<double>(c, 1, n, 1, pa, c->opt.poisson_rtol, c->opt.cg_maxit, false, &dummy, &dn, &S.pr));
   }
+  HIPCHK(hipEventRecord(S.ev[7], s));
+  S.solve_timed = true;
   if (side) HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
   PHASE(phase_gram(S));
   HIPCHK(hipStreamSynchronize(s));

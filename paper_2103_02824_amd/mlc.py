@@ -78,7 +78,7 @@ class StepReport(C.Structure):
                 ("t_fine_ms", C.c_double), ("t_inner_ms", C.c_double), ("t_recon_ms", C.c_double),
                 ("t_spmm_ms", C.c_double), ("n_spmm", C.c_int64), ("spmm_rows", C.c_int64),
                 ("spmm_cols_sum", C.c_int64), ("ir_outer", C.c_int32), ("guess_learned_cols", C.c_int32),
-                ("guess_resid_ratio", C.c_double)]
+                ("guess_resid_ratio", C.c_double), ("t_solve_ms", C.c_double), ("t_poisson_ms", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -53,6 +53,9 @@ def test_c1_one_step_parity(c1):
     assert relerr(w, ref.state.w) < 1e-6
     assert abs(rep["rho_integral"] - 1.0) < 1e-10
     assert abs(rep["energy"] - ref.energy) < 1e-8
+    # the two solves are timed inside the fine stage
+    assert 0.0 < rep["t_solve_ms"] and 0.0 < rep["t_poisson_ms"]
+    assert rep["t_solve_ms"] + rep["t_poisson_ms"] < rep["t_fine_ms"], rep
 
 
 def test_c1_initial_state(c1):
