@@ -434,9 +434,11 @@ void launch_nn_prepare(hipStream_t s, const NnDev& d) {
 void launch_nn_forward(hipStream_t s, const NnDev& d, const float* X, int64_t m, uint64_t start, uint64_t stride,
                        int64_t M, float* Y) {
   if (m <= 0) return;
+  // at most four blocks per CU: every block stages the weights in LDS once and
+  // its waves then stride over many 16-row tiles
   int64_t tiles = (m + 15) / 16;
   int64_t b = (tiles + 3) / 4;
-  int nb = (int)(b > 4096 ? 4096 : b);
+  int nb = (int)(b > 1024 ? 1024 : b);
   hipLaunchKernelGGL(k_nn_forward, dim3(nb), dim3(BS), 0, s, d, X, m, start, stride, M, Y);
 }
 
