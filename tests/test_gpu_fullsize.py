@@ -1,0 +1,92 @@
+"""The benchmark workload at full size through the C ABI: the 4-atom cluster
+(seed 0, 196 011 DoF x 5 orbitals), one correction step with the benchmark's
+preconditioners (Chebyshev degree 8, coarse-space correction in the Hartree
+CG) and therefore the benchmark's launch shapes.
+
+The checker's own fine stage needs a sparse LU of the Hartree matrix that takes
+minutes at this size, so the library's outputs are checked against the
+checker's independently assembled full-size operators instead (no checker
+solve): the step-5 solutions and the Hartree direction must satisfy the
+checker's systems, the Gram blocks must equal the checker's products with the
+library's U, and the shift and multipole boundary data must match.
+
+Tolerances: the library solves to 1e-12 (step 5) and 1e-13 (Hartree) relative
+residual in its own operators; the checker's operators agree with them to
+rounding (about 1e-15 relative), so residuals in the checker's operators are
+required below 1e-11. Products with a given U: 1e-11 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import hartree as har
+from oracle import xc as xcmod
+from oracle.mlc import Problem
+from oracle.scf import initial_state
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def test_benchmark_cluster_full_size(gpu):
+    from inputs.systems import c2_cluster
+    from paper_2103_02824_amd import mlc
+    print("case 4-atom cluster seed 0, full size: mesh and checker setup", flush=True)
+    S = c2_cluster(0)
+    prob = Problem(S)
+    st0, _ = initial_state(prob, maxit=300)
+    fine = prob.fine
+    opts = mlc.options(cg_rtol=1e-12, poisson_rtol=1e-13, inner_maxit=2, inner_tol=1e-11, shift=1, sigma0=1.0,
+                       precond=mlc.PC_CHEBYSHEV, cheb_degree=8, cheb_ratio=100.0, hartree_coarse=1)
+    ctx = mlc.Context(S, opts)
+    n, N, nH = ctx.n_dof, ctx.N, ctx.n_coarse_dof
+    assert (n, N) == (196011, 5)
+    print("case 4-atom cluster full size: library step", flush=True)
+    ctx.set_state(st0.lam, st0.Phi, st0.w)
+    rep = ctx.correction_step()
+    print(rep, flush=True)
+    assert rep["cg_relres_max"] <= 1e-12 * (1 + 1e-6) and rep["poisson_relres"] <= 1e-13 * (1 + 1e-6)
+
+    # the checker's operators of the input state (steps O1-O4)
+    rho = prob.density_qp(st0.Phi)
+    _, vxc = xcmod.evaluate(S.xc, rho, S.xalpha)
+    g = har.boundary_data(fine, rho)
+    veff = prob.vext_qp + fine.at_qp(st0.w) + vxc
+    sigma = 1.0 - float(veff.min())
+    assert abs(ctx.probe("SIGMA", (1,))[0] - sigma) < 1e-12 * max(1.0, abs(sigma))
+    assert relerr(ctx.probe("G", (ctx.n_vertices,)), g) < 1e-12
+
+    # step 5: U (M-normalised) spans the solution of (A + sigma M) u = (lambda + sigma) M phi column by column
+    A = (0.5 * prob.K + prob.mass_ii(veff) + sigma * prob.M).tocsr()
+    B = (prob.M @ st0.Phi) * (st0.lam + sigma)[None, :]
+    U = ctx.probe("U", (n, N))
+    AU = A @ U
+    for c in range(N):
+        t = float(AU[:, c] @ B[:, c]) / float(AU[:, c] @ AU[:, c])
+        res = np.linalg.norm(B[:, c] - t * AU[:, c]) / np.linalg.norm(B[:, c])
+        assert res < 1e-11, (c, res)
+    assert np.allclose(np.einsum("ai,ai->i", U, prob.M @ U), 1.0, rtol=0, atol=1e-12)
+
+    # step 6: K_II w0 = 4 pi (M rho~)_I - K_IB g_B with rho~ from the library's U
+    rho_t = prob.density_qp(U)
+    b = 4.0 * np.pi * fine.load(rho_t)[fine.interior] - fine.ib(prob.Kfull) @ g[fine.bverts]
+    w0 = ctx.probe("W0", (n,))
+    res = np.linalg.norm(b - prob.K @ w0) / np.linalg.norm(b)
+    assert res < 1e-11, res
+
+    # Gram blocks with the library's U and w0 (Algorithm 3 step 1)
+    Afix = 0.5 * prob.K + prob.mass_ii(prob.vext_qp + vxc + fine.at_qp(g))
+    Mw0 = prob.mass_ii(fine.at_qp(fine.full(w0)))
+    P = prob.P
+    for name, O in (("AFIX", Afix), ("MW0", Mw0), ("M", prob.M), ("K", prob.K)):
+        OU = O @ U
+        e1 = relerr(ctx.probe(f"PT_{name}_U", (nH, N)), P.T @ OU)
+        e2 = relerr(ctx.probe(f"UT_{name}_U", (N, N)), U.T @ OU)
+        print(f"Gram {name}: P^T O U {e1:.1e}, U^T O U {e2:.1e}", flush=True)
+        assert e1 < 1e-11 and e2 < 1e-11, (name, e1, e2)
+
+    # after the step: the density integrates to the electron count
+    assert abs(rep["rho_integral"] - float(np.sum(S.occupations))) < 1e-9
+    ctx.close()
