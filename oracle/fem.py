@@ -126,6 +126,13 @@ def hat_values(fine_xyz, coarse: Mesh):
         best = np.where(better, m, best)
         chosen = np.where(better, t, chosen)
         bary = np.where(better[:, None], l, bary)
+    # points not inside any of the nearest-centroid candidates (long, thin
+    # bisection tets near the nuclei): every coarse tet
+    for a in np.nonzero(best < -1e-10)[0]:
+        l123 = np.einsum("tij,tj->ti", Jinv, fine_xyz[a][None, :] - cP[:, 0])
+        l = np.concatenate([1.0 - l123.sum(axis=1, keepdims=True), l123], axis=1)
+        t = int(np.argmax(l.min(axis=1)))
+        best[a], chosen[a], bary[a] = l[t].min(), t, l[t]
     if np.any(best < -1e-10):
         raise RuntimeError("fine vertex outside the coarse mesh")
     bary = np.where(np.abs(bary) < 1e-14, 0.0, bary)

@@ -90,3 +90,60 @@ def test_benchmark_cluster_full_size(gpu):
     # after the step: the density integrates to the electron count
     assert abs(rep["rho_integral"] - float(np.sum(S.occupations))) < 1e-9
     ctx.close()
+
+
+def test_benchmark_batch_systems_full_size(gpu):
+    """The first two systems of the benchmark's batch of uneven clusters
+    (39 038 and 73 568 vertices, 4 orbitals each), one batched step with the
+    batch benchmark's settings (FP32 CG + FP64 refinement, Jacobi-PCG with the
+    coarse-space correction in the Hartree CG): per system, the step-5
+    solutions and the Hartree direction satisfy the checker's assembled
+    systems and the Gram blocks equal the checker's products."""
+    from inputs.systems import batch_clusters
+    from paper_2103_02824_amd import mlc
+    systems = batch_clusters(2)
+    print(f"case batch systems {[len(S.xyz) for S in systems]} vertices: checker setup", flush=True)
+    probs, states, ctxs = [], [], []
+    opts = mlc.options(cg_rtol=1e-12, poisson_rtol=1e-13, inner_maxit=2, inner_tol=1e-11, shift=1, sigma0=1.0,
+                       precision=mlc.PREC_FP32_IR, ir_inner_rtol=1e-4, hartree_coarse=1)
+    for S in systems:
+        prob = Problem(S)
+        st0, _ = initial_state(prob, maxit=300)
+        ctx = mlc.Context(S, opts)
+        ctx.set_state(st0.lam, st0.Phi, st0.w)
+        probs.append(prob)
+        states.append(st0)
+        ctxs.append(ctx)
+    print("case batch systems: batched step", flush=True)
+    b = mlc.Batch(ctxs)
+    reps, br = b.step()
+    print(br, flush=True)
+    for S, prob, st0, ctx, rep in zip(systems, probs, states, ctxs, reps):
+        fine = prob.fine
+        n, N, nH = ctx.n_dof, ctx.N, ctx.n_coarse_dof
+        assert rep["cg_relres_max"] <= 1e-12 * (1 + 1e-6) and rep["poisson_relres"] <= 1e-13 * (1 + 1e-6)
+        rho = prob.density_qp(st0.Phi)
+        _, vxc = xcmod.evaluate(S.xc, rho, S.xalpha)
+        g = har.boundary_data(fine, rho)
+        veff = prob.vext_qp + fine.at_qp(st0.w) + vxc
+        sigma = 1.0 - float(veff.min())
+        A = (0.5 * prob.K + prob.mass_ii(veff) + sigma * prob.M).tocsr()
+        B = (prob.M @ st0.Phi) * (st0.lam + sigma)[None, :]
+        U = ctx.probe("U", (n, N))
+        AU = A @ U
+        for c in range(N):
+            t = float(AU[:, c] @ B[:, c]) / float(AU[:, c] @ AU[:, c])
+            res = np.linalg.norm(B[:, c] - t * AU[:, c]) / np.linalg.norm(B[:, c])
+            assert res < 1e-11, (n, c, res)
+        rho_t = prob.density_qp(U)
+        bh = 4.0 * np.pi * fine.load(rho_t)[fine.interior] - fine.ib(prob.Kfull) @ g[fine.bverts]
+        w0 = ctx.probe("W0", (n,))
+        res = np.linalg.norm(bh - prob.K @ w0) / np.linalg.norm(bh)
+        assert res < 1e-11, (n, res)
+        OU = prob.M @ U
+        assert relerr(ctx.probe("PT_M_U", (nH, N)), prob.P.T @ OU) < 1e-11
+        assert relerr(ctx.probe("UT_M_U", (N, N)), U.T @ OU) < 1e-11
+        print(f"system n={n}: step-5 and Hartree residuals below 1e-11 in the checker's operators", flush=True)
+    b.close()
+    for c in ctxs:
+        c.close()
