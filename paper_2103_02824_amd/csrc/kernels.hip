@@ -579,17 +579,10 @@ __device__ __forceinline__ void coarse_bary(const double* __restrict__ cg, const
 }
 
 // Block-wide ordered sum of v over the 256 threads; result returned to all.
-__device__ __forceinline__ double block_sum(double v, double* ws) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
-  __syncthreads();
-  return (ws[0] + ws[1]) + (ws[2] + ws[3]);
-}
-
-// The same for K values per thread at once (TPB = 256, four waves): every
-// value's wave sum, then one barrier; thread k < K returns the block sum of
-// value k (summed in the order of block_sum), the others 0. ws: 4 K doubles.
+// Block sums of K values per thread (TPB = 256, four waves): every value's
+// wave sum, then one barrier; thread k < K returns the block sum of value k
+// (the four wave sums added as (w0 + w1) + (w2 + w3)), the others 0.
+// ws: 4 K doubles.
 template <int K>
 __device__ __forceinline__ double block_sums(const double (&v)[K], double* ws) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -612,7 +605,6 @@ __device__ __forceinline__ double block_sums(const double (&v)[K], double* ws) {
 // hats of its parent at its four quadrature points, chat[(4 q + j) ng + e],
 // and its volume, chat[16 ng + e] (ng = number of fine tets; one array per
 // value, so that consecutive threads read consecutive addresses).
-constexpr int CHAT = 17;
 __global__ void __launch_bounds__(TPB) k_coarse_hats(int64_t cnt, int64_t ng, const int32_t* __restrict__ grp_ptr,
                                                      const int32_t* __restrict__ grp_tet,
                                                      const int32_t* __restrict__ tets, const double* __restrict__ geo,
