@@ -112,6 +112,30 @@ def c2_cluster(seed=0):
     return cluster_system(seed, name=f"c2_cluster4_s{seed}")
 
 
+LIH_R = np.array([[-1.0075, 0.0, 0.0], [2.0075, 0.0, 0.0]])   # Li, H (Section 4, first model)
+LIH_Z = np.array([3.0, 1.0])
+
+
+def lih_system(n_base=16, h0=0.08, kappa=0.25, h_min=0.08, name="lih"):
+    """The paper's first model (Section 4): Li (Z = 3) at (-1.0075, 0, 0) and
+    H (Z = 1) at (2.0075, 0, 0), bare Coulomb potential, X-alpha exchange
+    with alpha = 0.77298, box (-6, 6)^3, two doubly occupied orbitals. The
+    coarse mesh is the n_base^3 Kuhn mesh (16^3: 24576 tets, the paper's
+    coarsest mesh); the fine mesh refines it toward the nuclei until the
+    longest edge <= clip(h0 + kappa d, h_min, base edge)."""
+    hm = 12.0 / n_base * math.sqrt(3.0)
+    xyz, tets, cxyz, ctets = graded_mesh(n_base, -6.0, 6.0, LIH_R, h0=h0, kappa=kappa, h_min=h_min, h_max=hm)
+    return System(name=name, R=LIH_R.copy(), Z=LIH_Z.copy(), lo=-6.0, hi=6.0, potential=POT_BARE, n_orbitals=2,
+                  occupations=np.array([2.0, 2.0]), xc=XC_XALPHA, xalpha=0.77298, xyz=xyz, tets=tets, cxyz=cxyz,
+                  ctets=ctets, meta={"n_base": n_base, "h0": h0, "kappa": kappa, "h_min": h_min})
+
+
+def lih_small():
+    """LiH on an 8^3 coarse mesh with a mild grading: small enough for the
+    checker to run whole steps."""
+    return lih_system(n_base=8, h0=0.3, kappa=0.35, h_min=0.3, name="lih_small")
+
+
 def c2_small(seed=0):
     """Same distribution as the 4-atom workload on a coarser grading (about
     1e4 vertices): small enough for the checker to run whole steps."""

@@ -284,6 +284,22 @@ std::vector<double> lowest_eigenvalues(const Tridiag& T, const double* u, double
 
 double border_weight(const Tridiag& T, const double* u, double mu) {
   int64_t n = T.n;
+  // An eigenvalue of K that equals (to rounding) an eigenvalue of T belongs,
+  // in the generic case, to an eigenvector [q; 0] with T q = mu q and q
+  // orthogonal to u: its border weight is zero, and the closed form below,
+  // which assumes T - mu nonsingular, does not apply. T splits exactly into
+  // unreduced blocks when the problem has symmetries (degenerate levels), and
+  // then u can vanish on a whole block. A coupled eigenvalue that lies within
+  // delta of a pole of the secular equation has weight O(sqrt(delta)), so
+  // treating every eigenvalue within delta = 1e-8 scale of the spectrum of T
+  // as decoupled never discards the eigenvalue of largest weight.
+  {
+    double lo, hi = gersh(T, nullptr, 0.0, &lo);
+    double scale = std::max(std::fabs(lo), std::fabs(hi));
+    double pivmin = std::numeric_limits<double>::epsilon() * std::max(scale, 1e-300) * 1e-3;
+    double delta = 1e-8 * scale;
+    if (count_below(T, nullptr, 0.0, mu + delta, pivmin) > count_below(T, nullptr, 0.0, mu - delta, pivmin)) return 0.0;
+  }
   std::vector<double> z(n);
   double tt;
   // z = (T - mu)^{-1} u  (use the bordered solver with r = u, no border)

@@ -1,0 +1,30 @@
+// Test driver for the library's host eigen-solver of the augmented problems
+// (the bordered tridiagonal [[T, u], [u^T, alpha]] of Algorithm 3 step 2):
+// builds T from a dense symmetric C, then reports the k lowest eigenvalues,
+// the border weight of each and the inverse-iteration eigenvector, all in the
+// basis of C.
+#include <cstddef>
+#include <vector>
+
+#include "dense.h"
+
+using namespace mlc::dense;
+
+extern "C" void probe_bordered(const double* C0, const double* uc, double alpha, int n, int k, double* ev_out,
+                               double* w_out, double* Y, double* s_out) {
+  std::vector<double> C(C0, C0 + (std::size_t)n * n);
+  Tridiag Tr;
+  tridiagonalize(C, n, Tr);
+  std::vector<double> u(uc, uc + n), y(n);
+  apply_QT(Tr, u.data());
+  std::vector<double> ev = lowest_eigenvalues(Tr, u.data(), alpha, k);
+  for (int j = 0; j < k; ++j) {
+    ev_out[j] = ev[j];
+    w_out[j] = border_weight(Tr, u.data(), ev[j]);
+    double s;
+    eigenvector(Tr, u.data(), alpha, ev[j], y.data(), &s);
+    apply_Q(Tr, y.data());
+    for (int r = 0; r < n; ++r) Y[(std::size_t)r * k + j] = y[r];
+    s_out[j] = s;
+  }
+}

@@ -338,3 +338,32 @@ def test_two_level_hartree_reaches_the_checker(gpu, case, pc):
     print(f"Hartree CG iterations: without coarse correction {its[0]}, with {its[1]}", flush=True)
     if pc == "jacobi":
         assert its[1] < its[0]
+
+
+@pytest.mark.parametrize("case", ["lih_small", "harmonic"])
+def test_other_models_one_step(gpu, case):
+    """The paper's LiH model (bare Coulomb of two nuclei, X-alpha exchange,
+    Hartree, two doubly occupied orbitals; Section 4) on a small mesh pair,
+    and the harmonic oscillator (no nuclei, no XC, no Hartree; its lowest
+    level and the full degenerate triplet): the fine stage and one whole
+    correction step against the checker. The inner loop is capped at three
+    iterations on both sides (the same iteration, so the same state)."""
+    from inputs.systems import harmonic, lih_small
+    from oracle.mlc import fine_stage
+    from paper_2103_02824_amd import mlc
+    S = lih_small() if case == "lih_small" else harmonic(12, 6, n_orbitals=4)
+    print(f"case {case}: {len(S.xyz)} vertices, N = {S.n_orbitals}", flush=True)
+    prob = Problem(S)
+    st0, _ = initial_state(prob, maxit=300)
+    ctx = mlc.Context(S, mlc.options(**dict(LIB_OPTS, inner_maxit=3)))
+    ctx.set_state(st0.lam, st0.Phi, st0.w)
+    rep = ctx.correction_step()
+    fs = fine_stage(prob, st0, ORA_OPTS)
+    _compare_fine_stage(ctx, prob, fs)
+    ref = correction_step(prob, st0, Options(shift=True, sigma0=1.0, inner_tol=1e-11, inner_maxit=3, n_extra=8))
+    lam, Phi, w, rho = ctx.get_results()
+    assert rep["inner_iters"] == ref.inner_iters, (rep["inner_iters"], ref.inner_iters)
+    assert np.max(np.abs(lam - ref.state.lam)) < 1e-8, (lam, ref.state.lam)
+    assert relerr(rho, ref.rho_nodal) < 1e-6
+    assert abs(rep["rho_integral"] - float(np.sum(S.occupations))) < 1e-9
+    ctx.close()
