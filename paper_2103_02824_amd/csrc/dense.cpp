@@ -282,31 +282,34 @@ std::vector<double> lowest_eigenvalues(const Tridiag& T, const double* u, double
   return ev;
 }
 
-double border_weight(const Tridiag& T, const double* u, double mu) {
-  int64_t n = T.n;
-  // An eigenvalue of K that equals (to rounding) an eigenvalue of T belongs,
-  // in the generic case, to an eigenvector [q; 0] with T q = mu q and q
-  // orthogonal to u: its border weight is zero, and the closed form below,
-  // which assumes T - mu nonsingular, does not apply. T splits exactly into
-  // unreduced blocks when the problem has symmetries (degenerate levels), and
-  // then u can vanish on a whole block. A coupled eigenvalue that lies within
-  // delta of a pole of the secular equation has weight O(sqrt(delta)), so
-  // treating every eigenvalue within delta = 1e-8 scale of the spectrum of T
-  // as decoupled never discards the eigenvalue of largest weight.
-  {
-    double lo, hi = gersh(T, nullptr, 0.0, &lo);
-    double scale = std::max(std::fabs(lo), std::fabs(hi));
-    double pivmin = std::numeric_limits<double>::epsilon() * std::max(scale, 1e-300) * 1e-3;
-    double delta = 1e-8 * scale;
-    if (count_below(T, nullptr, 0.0, mu + delta, pivmin) > count_below(T, nullptr, 0.0, mu - delta, pivmin)) return 0.0;
-  }
+double border_weight(const Tridiag& T, const double* u, double alpha, double mu) {
+  // The closed form takes the eigenvector to be x = [z; -1] with
+  // z = (T - mu)^{-1} u, which holds when mu solves the secular equation
+  // alpha - mu - u^T (T - mu)^{-1} u = 0. An eigenvalue of K that is also an
+  // eigenvalue of T with an eigenvector q orthogonal to u (degenerate or
+  // symmetric spectra) has the eigenvector [q; 0] instead, border weight
+  // zero; there the secular equation does not hold and x is not an
+  // eigenvector. So x is accepted only if its residual |(K - mu) x| / |x| is
+  // below 1e-9 |K| (a coupled eigenpair of weight above ~1e-6 meets it with
+  // orders to spare: its residual is |f'(mu)| |dmu| / |x| ~ |x| eps |K|).
+  const int64_t n = T.n;
   std::vector<double> z(n);
   double tt;
-  // z = (T - mu)^{-1} u  (use the bordered solver with r = u, no border)
   bordered_solve(T, nullptr, 0.0, mu, u, 0.0, z.data(), &tt);
-  double s2 = 0.0;
-  for (int64_t j = 0; j < n; ++j) s2 += z[j] * z[j];
-  return 1.0 / std::sqrt(1.0 + s2);
+  double z2 = 0.0, uz = 0.0, r2 = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    z2 += z[j] * z[j];
+    uz += u[j] * z[j];
+    double r = (T.d[j] - mu) * z[j] - u[j];
+    if (j > 0) r += T.e[j - 1] * z[j - 1];
+    if (j + 1 < n) r += T.e[j] * z[j + 1];
+    r2 += r * r;
+  }
+  const double f = alpha - mu - uz;
+  double lo, hi = gersh(T, u, alpha, &lo);
+  const double knorm = std::max(std::fabs(lo), std::fabs(hi));
+  if (!(std::sqrt((r2 + f * f) / (1.0 + z2)) <= 1e-9 * knorm)) return 0.0;
+  return 1.0 / std::sqrt(1.0 + z2);
 }
 
 void eigenvector(const Tridiag& T, const double* u, double alpha, double mu, double* y, double* s) {

@@ -37,10 +37,12 @@ std::vector<double> lowest_eigenvalues(const Tridiag& T, const double* u, double
 // Eigenvector of K for eigenvalue mu by inverse iteration (normalised).
 // Output: y (n) and s (border coordinate; unused when u is null).
 void eigenvector(const Tridiag& T, const double* u, double alpha, double mu, double* y, double* s);
-// |s| of the normalised eigenvector for eigenvalue mu (border weight), cheap:
-// 1/sqrt(1 + |(T - mu)^{-1} u|^2), and 0 when mu lies within 1e-8 of the
-// spectral scale of an eigenvalue of T (a decoupled eigenvector [q; 0]).
-double border_weight(const Tridiag& T, const double* u, double mu);
+// |s| of the normalised eigenvector of K for eigenvalue mu (border weight),
+// O(n): 1/sqrt(1 + |(T - mu)^{-1} u|^2) when [(T - mu)^{-1} u; -1] is an
+// eigenvector of K to 1e-9 |K| relative residual, and 0 otherwise (mu is then
+// an eigenvalue of T whose eigenvectors are orthogonal to u, as in degenerate
+// or symmetric spectra, and K's eigenvector is [q; 0]).
+double border_weight(const Tridiag& T, const double* u, double alpha, double mu);
 
 }  // namespace dense
 }  // namespace mlc

@@ -224,7 +224,7 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
       int jsel = 0;
       double wbest = -1.0;
       for (int j = 0; j < n_keep; ++j) {
-        double wj = border_weight(Tr, u.data(), ev[j]);
+        double wj = border_weight(Tr, u.data(), alpha, ev[j]);
         if (wj > wbest) {
           wbest = wj;
           jsel = j;

@@ -20,7 +20,7 @@ extern "C" void probe_bordered(const double* C0, const double* uc, double alpha,
   std::vector<double> ev = lowest_eigenvalues(Tr, u.data(), alpha, k);
   for (int j = 0; j < k; ++j) {
     ev_out[j] = ev[j];
-    w_out[j] = border_weight(Tr, u.data(), ev[j]);
+    w_out[j] = border_weight(Tr, u.data(), alpha, ev[j]);
     double s;
     eigenvector(Tr, u.data(), alpha, ev[j], y.data(), &s);
     apply_Q(Tr, y.data());
