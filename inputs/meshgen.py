@@ -19,6 +19,7 @@ from __future__ import annotations
 import itertools
 
 import numpy as np
+from scipy.spatial import cKDTree
 
 # Kuhn subdivision of the unit cube: one tetrahedron per permutation of the
 # axes, x0 = corner (0,0,0), x_{k} = x_{k-1} + e_{perm[k-1]}, x3 = (1,1,1).
@@ -73,6 +74,10 @@ class _Bisector:
         self.mid_keys = np.zeros(0, dtype=np.int64)  # sorted edge keys
         self.mid_ids = np.zeros(0, dtype=np.int64)
         self.key_base = np.int64(1) << np.int64(31)
+        # after a bisection: endpoints of the edges it split and the number of
+        # children it appended (the only places a new hanging edge can be)
+        self.split_ends = None
+        self.n_children = 0
 
     def _key(self, a, b):
         lo = np.minimum(a, b)
@@ -134,6 +139,11 @@ class _Bisector:
             ch2[:, kk + 1:] = Ts[:, kk + 1:]
             c1[s] = ch1
             c2[s] = ch2
+        ends = np.zeros(self.nv, dtype=bool)
+        ends[a] = True
+        ends[b] = True
+        self.split_ends = ends
+        self.n_children = 2 * len(idx)
         newtag = np.where(k > 1, k - 1, 3).astype(np.int8)
         keep = np.ones(len(self.tets), dtype=bool)
         keep[idx] = False
@@ -142,16 +152,30 @@ class _Bisector:
         return len(idx)
 
     def hanging(self):
-        """Mask of tets that own an edge whose midpoint already exists."""
+        """Mask of tets that own an edge whose midpoint already exists.
+
+        Called on a mesh that had no hanging edge before the last bisection:
+        a tet that bisection did not create can then only hang on an edge it
+        split, so only the new children and the tets with a vertex at an end
+        of a split edge are searched."""
         if len(self.mid_keys) == 0:
             return np.zeros(len(self.tets), dtype=bool)
-        T = self.tets
-        hang = np.zeros(len(T), dtype=bool)
+        cand = None
+        if self.split_ends is not None:
+            cand = self.split_ends[self.tets].any(axis=1)
+            cand[len(self.tets) - self.n_children:] = True
+            cand = np.nonzero(cand)[0]
+        T = self.tets if cand is None else self.tets[cand]
+        hang_c = np.zeros(len(T), dtype=bool)
         for (p, q) in ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)):
             keys = self._key(T[:, p], T[:, q])
             pos = np.searchsorted(self.mid_keys, keys)
             pos = np.minimum(pos, len(self.mid_keys) - 1)
-            hang |= self.mid_keys[pos] == keys
+            hang_c |= self.mid_keys[pos] == keys
+        if cand is None:
+            return hang_c
+        hang = np.zeros(len(self.tets), dtype=bool)
+        hang[cand] = hang_c
         return hang
 
     def close(self, max_rounds=1000):
@@ -172,22 +196,23 @@ def _longest_edge(xyz, tets):
     return np.sqrt(h2)
 
 
-def _refine_to(B, C, h0, kappa, h_min, h_max, max_levels=200):
-    for _ in range(max_levels):
+def _refine_to(B, C, h0, kappa, h_min, h_max, max_levels=200, progress=None):
+    tree = cKDTree(np.asarray(C, dtype=np.float64).reshape(-1, 3))
+    for level in range(max_levels):
         X = B.coords()
         cen = X[B.tets].mean(axis=1)
-        d = np.full(len(cen), np.inf)
-        for c in C:
-            d = np.minimum(d, np.linalg.norm(cen - c, axis=1))
+        d, _ = tree.query(cen)  # distance to the nearest centre
         target = np.clip(h0 + kappa * d, h_min, h_max)
         mark = _longest_edge(X, B.tets) > target * (1.0 + 1e-12)
         if not np.any(mark):
             return
         B.bisect(mark)
         B.close()
+        if progress:
+            progress(f"mesh refinement level {level}: {B.nv} vertices, {len(B.tets)} tets")
 
 
-def graded_mesh(n_base, lo, hi, centres, h0, kappa, h_min, h_max=np.inf, coarse=None):
+def graded_mesh(n_base, lo, hi, centres, h0, kappa, h_min, h_max=np.inf, coarse=None, progress=None):
     """Kuhn base mesh refined until every tet satisfies
     longest_edge <= clip(h0 + kappa * d(centroid), h_min, h_max), d = distance
     of the centroid to the nearest centre.
@@ -196,16 +221,17 @@ def graded_mesh(n_base, lo, hi, centres, h0, kappa, h_min, h_max=np.inf, coarse=
     (h0, kappa, h_min, h_max) of a first, milder grading; the fine mesh then
     refines that graded mesh further, so the two meshes stay nested.
     Returns (xyz, tets, coarse_xyz, coarse_tets). Coarse vertices keep their
-    ids in the fine mesh.
+    ids in the fine mesh. progress: optional callable given one line per
+    refinement level (long generations stay visibly alive).
     """
     bxyz, btets = kuhn_mesh(n_base, lo, hi)
     B = _Bisector(bxyz, btets)
     C = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
     if coarse is not None:
-        _refine_to(B, C, *coarse)
+        _refine_to(B, C, *coarse, progress=progress)
     cxyz = B.coords().copy()
     ctets = B.tets.copy()
-    _refine_to(B, C, h0, kappa, h_min, h_max)
+    _refine_to(B, C, h0, kappa, h_min, h_max, progress=progress)
     X = B.coords()
     return X.copy(), B.tets.copy(), cxyz, ctets
 

@@ -87,7 +87,7 @@ def c1_hydrogen():
 
 def cluster_system(seed, n_atoms=4, half_width=3.0, d_min=1.5, box=15.0, rc=0.5,
                    n_base=8, h0=0.12, kappa=0.12, h_min=0.12, h_max=None, name=None,
-                   n_orbitals=None, coarse=(1.4, 0.6, 1.4)):
+                   n_orbitals=None, coarse=(1.4, 0.6, 1.4), progress=None):
     """A seeded cluster with a graded P1 mesh refined toward the nuclei.
 
     Defaults give the 4-atom workload: positions in [-3,3]^3, separation
@@ -100,7 +100,7 @@ def cluster_system(seed, n_atoms=4, half_width=3.0, d_min=1.5, box=15.0, rc=0.5,
     hm = (2 * box) / n_base * math.sqrt(3.0) if h_max is None else h_max
     cg = None if coarse is None else (coarse[0], coarse[1], coarse[2], hm)
     xyz, tets, cxyz, ctets = graded_mesh(n_base, -box, box, R, h0=h0, kappa=kappa, h_min=h_min, h_max=hm,
-                                         coarse=cg)
+                                         coarse=cg, progress=progress)
     return System(name=name or f"cluster{n_atoms}_s{seed}", R=R, Z=Z, lo=-box, hi=box, potential=POT_ERF,
                   rc=rc, n_orbitals=N, occupations=f, xc=XC_LDA, xyz=xyz, tets=tets, cxyz=cxyz,
                   ctets=ctets, meta={"seed": seed, "n_base": n_base, "h0": h0, "kappa": kappa,
@@ -110,6 +110,18 @@ def cluster_system(seed, n_atoms=4, half_width=3.0, d_min=1.5, box=15.0, rc=0.5,
 def c2_cluster(seed=0):
     """4-atom cluster, graded P1 mesh of about 2e5 vertices."""
     return cluster_system(seed, name=f"c2_cluster4_s{seed}")
+
+
+def c3_cluster(seed=0, h=0.101, n_base=12, progress=None):
+    """The 40-atom cluster: positions uniform in [-8,8]^3 with separation
+    >= 1.8, Z in {1..4}, rc = 0.5, box [-25,25]^3, N = ceil(sum Z / 2)
+    orbitals (52 for seed 0). The fine mesh is P1, graded by bisection of the
+    n_base^3 Kuhn base until the longest edge <= clip(h + h d, h, base edge):
+    about 2.0e6 vertices at h = 0.101, a P1 mesh with the DoF count of the
+    P2 mesh such a system would be computed on. The coarse mesh is the base
+    (11^3 interior vertices at n_base = 12)."""
+    return cluster_system(seed, n_atoms=40, half_width=8.0, d_min=1.8, box=25.0, n_base=n_base, h0=h, kappa=h,
+                          h_min=h, coarse=None, name=f"c3_cluster40_s{seed}", progress=progress)
 
 
 LIH_R = np.array([[-1.0075, 0.0, 0.0], [2.0075, 0.0, 0.0]])   # Li, H (Section 4, first model)

@@ -84,6 +84,181 @@ struct RowBlocks {
 
 
 // ---------------------------------------------------------------------------
+// SpMM and fused Chebyshev step for N > 8. A lane owns V consecutive columns
+// (V = 4 for FP32 and V = 2 for FP64 when N is a multiple of V: one 16-byte
+// load per gathered row segment; else V = 1), L lanes share a row (L = the
+// smallest power of two >= N / V, at most 64; with V = 1 and N > 64 a lane
+// also owns the columns 64 further on), so a wavefront works on 64 / L rows
+// at once. BS-thread blocks over XCD-aware row blocks of BS / L rows. A
+// row's column indices and values are read WU at a time (the row's L lanes
+// read the same addresses: one request) and the WU gathers are issued before
+// they are summed, into two accumulators per column; entries past the row end
+// read row r itself with weight zero, so that every chunk issues all its loads
+// at once.
+constexpr int WIDE_BS = 512;
+constexpr int WIDE_MAXBLK = 1024;  // partial producers: at most cg_max_blocks()
+constexpr int WU = 8;
+
+struct WideShape {
+  int V, L, NCH;
+};
+inline WideShape wide_shape(int N, int word) {
+  const int vmax = 16 / word;
+  int V = (vmax >= 4 && N % 4 == 0) ? 4 : (N % 2 == 0 ? 2 : 1);
+  if (V > vmax) V = vmax;
+  const int groups = (N + V - 1) / V;
+  int L = 4;
+  while (L < groups && L < 64) L *= 2;
+  return {V, L, (groups + L - 1) / L};
+}
+// Grid of the N > 8 kernels: one block per 64 rows up to the cap, whatever the
+// layout (the FP32 and FP64 kernels and the consumers of their partials agree
+// on it); blocks past the last row block write zero partials.
+inline int wide_blocks_for(int64_t n) { return cap_xcd((n + 63) / 64, WIDE_MAXBLK); }
+
+template <typename T, int V>
+__device__ __forceinline__ void load_cols(const T* __restrict__ p, T (&o)[V]) {
+  if constexpr (V == 1) {
+    o[0] = p[0];
+  } else if constexpr (V == 2 && sizeof(T) == 8) {
+    const double2 q = *reinterpret_cast<const double2*>(p);
+    o[0] = q.x;
+    o[1] = q.y;
+  } else if constexpr (V == 2) {
+    const float2 q = *reinterpret_cast<const float2*>(p);
+    o[0] = q.x;
+    o[1] = q.y;
+  } else {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    o[0] = q.x;
+    o[1] = q.y;
+    o[2] = q.z;
+    o[3] = q.w;
+  }
+}
+template <typename T, int V>
+__device__ __forceinline__ void store_cols(T* __restrict__ p, const T (&o)[V]) {
+  if constexpr (V == 1) {
+    p[0] = o[0];
+  } else if constexpr (V == 2 && sizeof(T) == 8) {
+    *reinterpret_cast<double2*>(p) = make_double2(o[0], o[1]);
+  } else if constexpr (V == 2) {
+    *reinterpret_cast<float2*>(p) = make_float2(o[0], o[1]);
+  } else {
+    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+// acc[h][v] = (A X)[r, (g + L h) V + v] for the lane's column group g (zero
+// where the group lies past N).
+template <int L, int V, int NCH, typename T>
+__device__ __forceinline__ void row_gather_lanes(int64_t r, int g, int N, const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                 const T* __restrict__ X, T (&acc)[NCH][V]) {
+  T a0[NCH][V], a1[NCH][V];
+#pragma unroll
+  for (int h = 0; h < NCH; ++h)
+#pragma unroll
+    for (int v = 0; v < V; ++v) a0[h][v] = a1[h][v] = T(0);
+  const int j1 = rowptr[r + 1];
+  for (int j = rowptr[r]; j < j1; j += WU) {
+    int k[WU];
+    T w[WU];
+#pragma unroll
+    for (int u = 0; u < WU; ++u) {
+      const bool ok = j + u < j1;
+      k[u] = ok ? col[j + u] : (int)r;
+      w[u] = ok ? val[j + u] : T(0);
+    }
+    T x[WU][NCH][V];
+#pragma unroll
+    for (int u = 0; u < WU; ++u)
+#pragma unroll
+      for (int h = 0; h < NCH; ++h) {
+        const int c = (g + L * h) * V;
+        if (c < N) {
+          load_cols<T, V>(X + (int64_t)k[u] * N + c, x[u][h]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) x[u][h][v] = T(0);
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < WU; u += 2)
+#pragma unroll
+      for (int h = 0; h < NCH; ++h)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          a0[h][v] += w[u] * x[u][h][v];
+          a1[h][v] += w[u + 1] * x[u + 1][h][v];
+        }
+  }
+#pragma unroll
+  for (int h = 0; h < NCH; ++h)
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[h][v] = a0[h][v] + a1[h][v];
+}
+
+// Column sums of dot over the block's BS / L row slots into partial[blk, :].
+template <int L, int V, int NCH, int BS>
+__device__ __forceinline__ void block_cols_lanes(const double (&dot)[NCH][V], int N, double* __restrict__ partial) {
+  __shared__ double sd[BS];
+  const int g = threadIdx.x % L, rl = threadIdx.x / L;
+#pragma unroll
+  for (int h = 0; h < NCH; ++h)
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      __syncthreads();
+      sd[threadIdx.x] = dot[h][v];
+      for (int m = BS / L / 2; m > 0; m >>= 1) {
+        __syncthreads();
+        if (rl < m) sd[threadIdx.x] += sd[threadIdx.x + m * L];
+      }
+      __syncthreads();
+      const int c = (g + L * h) * V + v;
+      if (rl == 0 && c < N) partial[(int64_t)blockIdx.x * N + c] = sd[g];
+    }
+}
+
+// Y = A X; with partial: per-block column sums of X . Y.
+template <int L, int V, int NCH, typename T>
+__global__ void __launch_bounds__(WIDE_BS) k_spmm_rows(int64_t n, int N, const int32_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                       const T* __restrict__ X, T* __restrict__ Y,
+                                                       double* __restrict__ partial, const int32_t* __restrict__ flags) {
+  constexpr int RB = WIDE_BS / L;
+  if (flags && flags[0] == 0) return;
+  const int g = threadIdx.x % L, rl = threadIdx.x / L;
+  double dot[NCH][V];
+#pragma unroll
+  for (int h = 0; h < NCH; ++h)
+#pragma unroll
+    for (int v = 0; v < V; ++v) dot[h][v] = 0.0;
+  const RowBlocks rbk((n + RB - 1) / RB);
+  for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
+    const int64_t r = rb * RB + rl;
+    if (r >= n) continue;
+    T acc[NCH][V];
+    row_gather_lanes<L, V, NCH, T>(r, g, N, rowptr, col, val, X, acc);
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) {
+      const int c = (g + L * h) * V;
+      if (c < N) {
+        const int64_t i = r * N + c;
+        store_cols<T, V>(Y + i, acc[h]);
+        if (partial) {
+          T xo[V];
+          load_cols<T, V>(X + i, xo);
+#pragma unroll
+          for (int v = 0; v < V; ++v) dot[h][v] += (double)acc[h][v] * (double)xo[v];
+        }
+      }
+    }
+  }
+  if (partial) block_cols_lanes<L, V, NCH, WIDE_BS>(dot, N, partial);
+}
+
+// ---------------------------------------------------------------------------
 // Chebyshev polynomial preconditioner z = p(D^-1 A) D^-1 r: the first m steps
 // of the Chebyshev iteration for A z = r from z = 0 with the Jacobi splitting,
 // for eigenvalues of D^-1 A in [lmax / ratio, lmax] (Y. Saad, Iterative
@@ -164,43 +339,6 @@ __global__ void __launch_bounds__(BS, W) k_spmm_small(int64_t n, const int32_t* 
   }
 }
 
-// SpMM for wider blocks (N > 8): thread (row, column), R = 256/N rows per pass,
-// the nonzero loop unrolled by 4 so that four gathers are in flight.
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_spmm_wide(int64_t n, int N, const int32_t* __restrict__ rowptr,
-                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                   const T* __restrict__ X, T* __restrict__ Y,
-                                                   double* __restrict__ partial, const int32_t* __restrict__ flags) {
-  if (flags && flags[0] == 0) return;
-  __shared__ double sd[TPB];
-  const int R = TPB / N;
-  const int t = threadIdx.x;
-  const int rl = t / N, c = t - rl * N;
-  double dot = 0.0;
-  for (int64_t r0 = (int64_t)blockIdx.x * R; r0 < n; r0 += (int64_t)gridDim.x * R) {
-    int64_t r = r0 + rl;
-    if (rl < R && r < n) {
-      int j = rowptr[r], j1 = rowptr[r + 1];
-      T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-      for (; j + 3 < j1; j += 4) {
-        int k0 = col[j], k1 = col[j + 1], k2 = col[j + 2], k3 = col[j + 3];
-        a0 += val[j] * X[(int64_t)k0 * N + c];
-        a1 += val[j + 1] * X[(int64_t)k1 * N + c];
-        a2 += val[j + 2] * X[(int64_t)k2 * N + c];
-        a3 += val[j + 3] * X[(int64_t)k3 * N + c];
-      }
-      for (; j < j1; ++j) a0 += val[j] * X[(int64_t)col[j] * N + c];
-      T acc = (a0 + a1) + (a2 + a3);
-      Y[r * N + c] = acc;
-      if (partial) dot += (double)acc * (double)X[r * N + c];
-    }
-  }
-  if (!partial) return;
-  sd[t] = dot;
-  block_reduce_cols(sd, R, N);
-  if (t < N) partial[(int64_t)blockIdx.x * N + t] = sd[t];
-}
-
 // One Chebyshev step j >= 1 fused with its SpMM (NT <= 8, G lanes per row):
 // w = A Zin; d = cd d + cr D^-1 (R - w); Zout = Zin + d; optional per-block
 // column sums of R . Zout (the r.z of CG after the last step). The row's own
@@ -277,50 +415,64 @@ __global__ void __launch_bounds__(BS, W) k_cheb_small(int64_t n, const int32_t* 
   }
 }
 
-// The same for N > 8: thread (row, column), R = 256/N rows per pass.
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_cheb_wide(int64_t n, int N, const int32_t* __restrict__ rowptr,
-                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                   const T* __restrict__ dinv, const T* __restrict__ R,
-                                                   const T* __restrict__ Zin, T* __restrict__ Zout, T* __restrict__ Dd,
-                                                   const double* __restrict__ lmax, double ratio, int j,
-                                                   double* __restrict__ partial, const int32_t* __restrict__ flags) {
+// The fused Chebyshev step for N > 8 in the same layout: w = A Zin;
+// d = cd d + cr D^-1 (R - w); Zout = Zin + d; optional per-block column sums
+// of R . Zout. The row's own R, d, Zin entries are loaded before the gather.
+template <int L, int V, int NCH, typename T>
+__global__ void __launch_bounds__(WIDE_BS) k_cheb_rows(int64_t n, int N, const int32_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                       const T* __restrict__ dinv, const T* __restrict__ R,
+                                                       const T* __restrict__ Zin, T* __restrict__ Zout,
+                                                       T* __restrict__ Dd, const double* __restrict__ lmax,
+                                                       double ratio, int j, double* __restrict__ partial,
+                                                       const int32_t* __restrict__ flags) {
+  constexpr int RB = WIDE_BS / L;
   if (flags && flags[0] == 0) return;
-  __shared__ double sd[TPB];
   double cdd, crr;
   cheb_coef(*lmax, ratio, j, &cdd, &crr);
   const T cd = (T)cdd, cr = (T)crr;
-  const int Rr = TPB / N;
-  const int t = threadIdx.x;
-  const int rl = t / N, c = t - rl * N;
-  double dot = 0.0;
-  for (int64_t r0 = (int64_t)blockIdx.x * Rr; r0 < n; r0 += (int64_t)gridDim.x * Rr) {
-    int64_t r = r0 + rl;
-    if (rl < Rr && r < n) {
-      int e = rowptr[r], e1 = rowptr[r + 1];
-      T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-      for (; e + 3 < e1; e += 4) {
-        int k0 = col[e], k1 = col[e + 1], k2 = col[e + 2], k3 = col[e + 3];
-        a0 += val[e] * Zin[(int64_t)k0 * N + c];
-        a1 += val[e + 1] * Zin[(int64_t)k1 * N + c];
-        a2 += val[e + 2] * Zin[(int64_t)k2 * N + c];
-        a3 += val[e + 3] * Zin[(int64_t)k3 * N + c];
+  const int g = threadIdx.x % L, rl = threadIdx.x / L;
+  double dot[NCH][V];
+#pragma unroll
+  for (int h = 0; h < NCH; ++h)
+#pragma unroll
+    for (int v = 0; v < V; ++v) dot[h][v] = 0.0;
+  const RowBlocks rbk((n + RB - 1) / RB);
+  for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
+    const int64_t r = rb * RB + rl;
+    if (r >= n) continue;
+    T rv[NCH][V], dv[NCH][V], zv[NCH][V];
+    const T di = dinv[r];
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) {
+      const int c = (g + L * h) * V;
+      if (c < N) {
+        const int64_t i = r * N + c;
+        load_cols<T, V>(R + i, rv[h]);
+        load_cols<T, V>(Dd + i, dv[h]);
+        load_cols<T, V>(Zin + i, zv[h]);
       }
-      for (; e < e1; ++e) a0 += val[e] * Zin[(int64_t)col[e] * N + c];
-      const T w = (a0 + a1) + (a2 + a3);
-      const int64_t i = r * N + c;
-      const T rv = R[i];
-      const T dn = cd * Dd[i] + cr * (dinv[r] * (rv - w));
-      Dd[i] = dn;
-      const T z = Zin[i] + dn;
-      Zout[i] = z;
-      if (partial) dot += (double)rv * (double)z;
+    }
+    T acc[NCH][V];
+    row_gather_lanes<L, V, NCH, T>(r, g, N, rowptr, col, val, Zin, acc);
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) {
+      const int c = (g + L * h) * V;
+      if (c < N) {
+        const int64_t i = r * N + c;
+        T dn[V], z[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          dn[v] = cd * dv[h][v] + cr * (di * (rv[h][v] - acc[h][v]));
+          z[v] = zv[h][v] + dn[v];
+          if (partial) dot[h][v] += (double)rv[h][v] * (double)z[v];
+        }
+        store_cols<T, V>(Dd + i, dn);
+        store_cols<T, V>(Zout + i, z);
+      }
     }
   }
-  if (!partial) return;
-  sd[t] = rl < Rr ? dot : 0.0;
-  block_reduce_cols(sd, Rr, N);
-  if (t < N) partial[(int64_t)blockIdx.x * N + t] = sd[t];
+  if (partial) block_cols_lanes<L, V, NCH, WIDE_BS>(dot, N, partial);
 }
 
 // Gershgorin bound of D^-1 A: per-block maxima of dinv_i sum_j |a_ij|, then
@@ -657,6 +809,38 @@ __global__ void __launch_bounds__(TPB) k_add_f32(int64_t m, const float* __restr
   if (i < m) x[i] += (double)d[i];
 }
 
+// Calls f(tag, grid, block) with tag::L, tag::V, tag::NCH the N > 8 layout of
+// wide_shape(N, sizeof(T)).
+template <int L_, int V_, int NCH_>
+struct WideTag {
+  static constexpr int L = L_, V = V_, NCH = NCH_;
+};
+template <typename T, typename F>
+void wide_launch(hipStream_t, int64_t n, int N, F&& f) {
+  const WideShape w = wide_shape(N, (int)sizeof(T));
+  const dim3 g(wide_blocks_for(n)), b(WIDE_BS);
+  if (w.NCH > 1) {
+    f(WideTag<64, 1, 2>{}, g, b);
+    return;
+  }
+#define WIDE_L(V)                        \
+  switch (w.L) {                         \
+    case 4: f(WideTag<4, V, 1>{}, g, b); break;   \
+    case 8: f(WideTag<8, V, 1>{}, g, b); break;   \
+    case 16: f(WideTag<16, V, 1>{}, g, b); break; \
+    case 32: f(WideTag<32, V, 1>{}, g, b); break; \
+    default: f(WideTag<64, V, 1>{}, g, b);        \
+  }
+  if (w.V == 1) {
+    WIDE_L(1)
+  } else if (w.V == 2) {
+    WIDE_L(2)
+  } else if constexpr (sizeof(T) == 4) {
+    WIDE_L(4)
+  }
+#undef WIDE_L
+}
+
 template <typename T>
 void spmm_any(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val, const T* X,
               T* Y, double* partial, const int32_t* flags) {
@@ -673,11 +857,12 @@ void spmm_any(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int3
     SPMM_CASE(6)
     SPMM_CASE(7)
     SPMM_CASE(8)
-    default: {
-      int64_t R = TPB / N;
-      hipLaunchKernelGGL((k_spmm_wide<T>), dim3(cap((n + R - 1) / R, MAXBLK)), dim3(TPB), 0, s, n, N, rowptr, col,
-                         val, X, Y, partial, flags);
-    }
+    default:
+      wide_launch<T>(s, n, N, [&](auto tag, dim3 g, dim3 b) {
+        using K = decltype(tag);
+        hipLaunchKernelGGL((k_spmm_rows<K::L, K::V, K::NCH, T>), g, b, 0, s, n, N, rowptr, col, val, X, Y, partial,
+                           flags);
+      });
   }
 #undef SPMM_CASE
 }
@@ -690,7 +875,7 @@ int cg_blocks(int64_t n, int N) {
 }
 int spmm_blocks(int64_t n, int N) {
   if (N <= 8) return cap_xcd((n + (SPMM_BS / ROW_G) - 1) / (SPMM_BS / ROW_G), SPMM_MAXBLK);
-  return cg_blocks(n, N);
+  return wide_blocks_for(n);
 }
 int cg_max_blocks() { return MAXBLK; }
 
@@ -822,8 +1007,11 @@ void launch_cheb_steps_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr,
       }
 #undef CHEB_CASE
     } else {
-      hipLaunchKernelGGL((k_cheb_wide<T>), dim3(cg_blocks(n, N)), dim3(TPB), 0, s, n, N, rowptr, col, val, dinv, Rv,
-                         zin, zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags);
+      wide_launch<T>(s, n, N, [&](auto tag, dim3 g, dim3 b) {
+        using K = decltype(tag);
+        hipLaunchKernelGGL((k_cheb_rows<K::L, K::V, K::NCH, T>), g, b, 0, s, n, N, rowptr, col, val, dinv, Rv, zin,
+                           zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags);
+      });
     }
   }
 }

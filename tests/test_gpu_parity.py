@@ -149,6 +149,42 @@ def test_wide_block_twelve_orbitals(gpu):
     ctx.close()
 
 
+_WIDE_REF = {}
+
+
+@pytest.mark.parametrize("case", ["24-chebyshev", "33-jacobi", "52-jacobi", "52-chebyshev", "52-chebyshev-fp32",
+                                  "71-chebyshev"])
+def test_wide_blocks_fine_stage(gpu, case):
+    """The N > 8 kernels on a 23^3-interior mesh (12167 DoF): a lane owns V
+    consecutive columns (V = 2 in FP64 and 4 in FP32 for even and multiple-of-4
+    N, else 1), L = 8..64 lanes share a row, and beyond 64 single columns a lane
+    owns a second chunk (N = 71). Fine-stage parity of the step-5 solutions and
+    every block built from them, with Jacobi (CG SpMM partials) and Chebyshev
+    (fused steps and their r.z partials), in FP64 and FP32 with FP64
+    refinement."""
+    from inputs.systems import tiny_system
+    from oracle.mlc import fine_stage
+    from paper_2103_02824_amd import mlc
+    N = int(case.split("-")[0])
+    if N not in _WIDE_REF:
+        S = tiny_system(n_fine=24, n_coarse=8, box=8.0, nonlinear=False, n_orbitals=N, seed=3)
+        S.occupations = np.ones(N)
+        prob = Problem(S)
+        st0, _ = initial_state(prob)
+        _WIDE_REF[N] = (S, prob, st0, fine_stage(prob, st0, ORA_OPTS))
+    S, prob, st0, fs = _WIDE_REF[N]
+    print(f"case wide N={N} {case}, n_dof={prob.fine.n_dof}", flush=True)
+    extra = dict(precond=mlc.PC_CHEBYSHEV if "chebyshev" in case else mlc.PC_JACOBI, cheb_degree=8, cheb_ratio=100.0)
+    if case.endswith("fp32"):
+        extra["precision"] = mlc.PREC_FP32_IR
+    ctx = mlc.Context(S, mlc.options(**dict(LIB_OPTS, **extra)))
+    ctx.set_state(st0.lam, st0.Phi, st0.w)
+    rep = ctx.correction_step()
+    print(rep, flush=True)
+    _compare_fine_stage(ctx, prob, fs)
+    ctx.close()
+
+
 def test_cluster_fine_stage_five_orbitals(gpu):
     """4-atom cluster on a coarse grading (same distribution as the benchmark
     workload): fine-stage parity for N = 5 (the small-N SpMM path, Hartree
