@@ -97,7 +97,7 @@ struct RowBlocks {
 // at once.
 constexpr int WIDE_BS = 512;
 constexpr int WIDE_MAXBLK = 1024;  // partial producers: at most cg_max_blocks()
-constexpr int WU = 8;
+constexpr int WU = 16;
 
 struct WideShape {
   int V, L, NCH;
@@ -152,7 +152,7 @@ __device__ __forceinline__ void store_cols(T* __restrict__ p, const T (&o)[V]) {
 // acc[h][v] = (A X)[r, (g + L h) V + v] for the lane's column group g (zero
 // where the group lies past N).
 template <int L, int V, int NCH, typename T>
-__device__ __forceinline__ void row_gather_lanes(int64_t r, int g, int N, const int32_t* __restrict__ rowptr,
+__device__ __forceinline__ void row_gather_lanes(int64_t r, int g, int N, int jb, int j1,
                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
                                                  const T* __restrict__ X, T (&acc)[NCH][V]) {
   T a0[NCH][V], a1[NCH][V];
@@ -160,8 +160,7 @@ __device__ __forceinline__ void row_gather_lanes(int64_t r, int g, int N, const 
   for (int h = 0; h < NCH; ++h)
 #pragma unroll
     for (int v = 0; v < V; ++v) a0[h][v] = a1[h][v] = T(0);
-  const int j1 = rowptr[r + 1];
-  for (int j = rowptr[r]; j < j1; j += WU) {
+  for (int j = jb; j < j1; j += WU) {
     int k[WU];
     T w[WU];
 #pragma unroll
@@ -234,12 +233,25 @@ __global__ void __launch_bounds__(WIDE_BS) k_spmm_rows(int64_t n, int N, const i
   for (int h = 0; h < NCH; ++h)
 #pragma unroll
     for (int v = 0; v < V; ++v) dot[h][v] = 0.0;
+  // the next row's pointers are loaded while this row's gathers are in flight
   const RowBlocks rbk((n + RB - 1) / RB);
+  int64_t rn = rbk.first * RB + rl;
+  int jb = 0, je = 0;
+  if (rbk.first < rbk.end && rn < n) {
+    jb = rowptr[rn];
+    je = rowptr[rn + 1];
+  }
   for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
     const int64_t r = rb * RB + rl;
+    const int jr = jb, jr1 = je;
+    rn = (rb + rbk.step) * RB + rl;
+    if (rb + rbk.step < rbk.end && rn < n) {
+      jb = rowptr[rn];
+      je = rowptr[rn + 1];
+    }
     if (r >= n) continue;
     T acc[NCH][V];
-    row_gather_lanes<L, V, NCH, T>(r, g, N, rowptr, col, val, X, acc);
+    row_gather_lanes<L, V, NCH, T>(r, g, N, jr, jr1, col, val, X, acc);
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
       const int c = (g + L * h) * V;
@@ -416,9 +428,11 @@ __global__ void __launch_bounds__(BS, W) k_cheb_small(int64_t n, const int32_t* 
 }
 
 // The fused Chebyshev step for N > 8 in the same layout: w = A Zin;
-// d = cd d + cr D^-1 (R - w); Zout = Zin + d; optional per-block column sums
-// of R . Zout. The row's own R, d, Zin entries are loaded before the gather.
-template <int L, int V, int NCH, typename T>
+// d = cd d + cr D^-1 (R - w); Zout = Zin + d; with PART, per-block column sums
+// of R . Zout into partial (a separate instantiation, so that the steps
+// without them do not hold the sums in registers). The row's own R, d, Zin
+// entries are loaded before the gather.
+template <int L, int V, int NCH, bool PART, typename T>
 __global__ void __launch_bounds__(WIDE_BS) k_cheb_rows(int64_t n, int N, const int32_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ col, const T* __restrict__ val,
                                                        const T* __restrict__ dinv, const T* __restrict__ R,
@@ -437,9 +451,22 @@ __global__ void __launch_bounds__(WIDE_BS) k_cheb_rows(int64_t n, int N, const i
   for (int h = 0; h < NCH; ++h)
 #pragma unroll
     for (int v = 0; v < V; ++v) dot[h][v] = 0.0;
+  // the next row's pointers are loaded while this row's gathers are in flight
   const RowBlocks rbk((n + RB - 1) / RB);
+  int64_t rn = rbk.first * RB + rl;
+  int jb = 0, je = 0;
+  if (rbk.first < rbk.end && rn < n) {
+    jb = rowptr[rn];
+    je = rowptr[rn + 1];
+  }
   for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
     const int64_t r = rb * RB + rl;
+    const int jr = jb, jr1 = je;
+    rn = (rb + rbk.step) * RB + rl;
+    if (rb + rbk.step < rbk.end && rn < n) {
+      jb = rowptr[rn];
+      je = rowptr[rn + 1];
+    }
     if (r >= n) continue;
     T rv[NCH][V], dv[NCH][V], zv[NCH][V];
     const T di = dinv[r];
@@ -454,7 +481,7 @@ __global__ void __launch_bounds__(WIDE_BS) k_cheb_rows(int64_t n, int N, const i
       }
     }
     T acc[NCH][V];
-    row_gather_lanes<L, V, NCH, T>(r, g, N, rowptr, col, val, Zin, acc);
+    row_gather_lanes<L, V, NCH, T>(r, g, N, jr, jr1, col, val, Zin, acc);
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
       const int c = (g + L * h) * V;
@@ -465,14 +492,14 @@ __global__ void __launch_bounds__(WIDE_BS) k_cheb_rows(int64_t n, int N, const i
         for (int v = 0; v < V; ++v) {
           dn[v] = cd * dv[h][v] + cr * (di * (rv[h][v] - acc[h][v]));
           z[v] = zv[h][v] + dn[v];
-          if (partial) dot[h][v] += (double)rv[h][v] * (double)z[v];
+          if constexpr (PART) dot[h][v] += (double)rv[h][v] * (double)z[v];
         }
         store_cols<T, V>(Dd + i, dn);
         store_cols<T, V>(Zout + i, z);
       }
     }
   }
-  if (partial) block_cols_lanes<L, V, NCH, WIDE_BS>(dot, N, partial);
+  if constexpr (PART) block_cols_lanes<L, V, NCH, WIDE_BS>(dot, N, partial);
 }
 
 // Gershgorin bound of D^-1 A: per-block maxima of dinv_i sum_j |a_ij|, then
@@ -1009,8 +1036,12 @@ void launch_cheb_steps_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr,
     } else {
       wide_launch<T>(s, n, N, [&](auto tag, dim3 g, dim3 b) {
         using K = decltype(tag);
-        hipLaunchKernelGGL((k_cheb_rows<K::L, K::V, K::NCH, T>), g, b, 0, s, n, N, rowptr, col, val, dinv, Rv, zin,
-                           zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags);
+        if (part)
+          hipLaunchKernelGGL((k_cheb_rows<K::L, K::V, K::NCH, true, T>), g, b, 0, s, n, N, rowptr, col, val, dinv,
+                             Rv, zin, zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags);
+        else
+          hipLaunchKernelGGL((k_cheb_rows<K::L, K::V, K::NCH, false, T>), g, b, 0, s, n, N, rowptr, col, val, dinv,
+                             Rv, zin, zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags);
       });
     }
   }
