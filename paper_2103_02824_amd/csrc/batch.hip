@@ -120,36 +120,100 @@ __device__ void tile_spmm_small(int64_t r0, int64_t r1, const int32_t* __restric
   __syncthreads();
 }
 
-// Rows [r0, r1) of Y = A S for any N: thread (row, column), R = BS / N rows
-// per pass, four gathers in flight. With dot: column sums into sd[0..N).
-template <typename T>
-__device__ void tile_spmm_wide(int64_t r0, int64_t r1, int N, const int32_t* __restrict__ rowptr,
-                               const int32_t* __restrict__ col, const T* __restrict__ val, const T* __restrict__ S,
-                               T* __restrict__ Y, bool dot, double* sd) {
-  const int R = BS / N;
-  const int rl = threadIdx.x / N, c = threadIdx.x - rl * N;
-  double dp = 0.0;
-  for (int64_t rb = r0; rb < r1; rb += R) {
-    int64_t r = rb + rl;
-    if (rl < R && r < r1) {
-      int j = rowptr[r], j1 = rowptr[r + 1];
-      T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-      for (; j + 3 < j1; j += 4) {
-        int k0 = col[j], k1 = col[j + 1], k2 = col[j + 2], k3 = col[j + 3];
-        a0 += val[j] * S[(int64_t)k0 * N + c];
-        a1 += val[j + 1] * S[(int64_t)k1 * N + c];
-        a2 += val[j + 2] * S[(int64_t)k2 * N + c];
-        a3 += val[j + 3] * S[(int64_t)k3 * N + c];
+// Column sums over the block's BS / L row slots of dot[h][v] (column
+// (g + L h) V + v) into sd[0..N).
+template <int L, int V, int NCH>
+__device__ __forceinline__ void tile_cols_lanes(const double (&dot)[NCH][V], int N, double* sd) {
+  __shared__ double cs[MLC_MAX_ORBITALS];
+  const int g = threadIdx.x % L, rl = threadIdx.x / L;
+#pragma unroll
+  for (int h = 0; h < NCH; ++h)
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      __syncthreads();
+      sd[threadIdx.x] = dot[h][v];
+      for (int m = BS / L / 2; m > 0; m >>= 1) {
+        __syncthreads();
+        if (rl < m) sd[threadIdx.x] += sd[threadIdx.x + m * L];
       }
-      for (; j < j1; ++j) a0 += val[j] * S[(int64_t)col[j] * N + c];
-      T acc = (a0 + a1) + (a2 + a3);
-      Y[r * N + c] = acc;
-      if (dot) dp += (double)acc * (double)S[r * N + c];
+      __syncthreads();
+      const int c = (g + L * h) * V + v;
+      if (rl == 0 && c < N) cs[c] = sd[g];
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < N) sd[threadIdx.x] = cs[threadIdx.x];
+  __syncthreads();
+}
+
+// Rows [r0, r1) of Y = A S for N > 8 in the layout of wide_shape(N,
+// tile_vmax<T>): V columns per lane, L lanes per row, BS / L rows per pass,
+// tile_wu<T> entries per chunk with their gathers issued together (the
+// batched kernels hold every system's path, so they keep the register budget
+// of the small-N tiles: one column per lane; two FP32 columns per lane made
+// the compiler spill the batched Chebyshev kernel). With dot: column sums into
+// sd[0..N).
+template <typename T>
+constexpr int tile_wu() { return sizeof(T) == 8 ? 4 : 8; }
+template <typename T>
+constexpr int tile_vmax() { return 1; }
+template <int L, int V, int NCH, typename T>
+__device__ void tile_spmm_lanes(int64_t r0, int64_t r1, int N, const int32_t* __restrict__ rowptr,
+                                const int32_t* __restrict__ col, const T* __restrict__ val, const T* __restrict__ S,
+                                T* __restrict__ Y, bool dot, double* sd) {
+  constexpr int RB = BS / L;
+  const int g = threadIdx.x % L, rl = threadIdx.x / L;
+  double dp[NCH][V];
+#pragma unroll
+  for (int h = 0; h < NCH; ++h)
+#pragma unroll
+    for (int v = 0; v < V; ++v) dp[h][v] = 0.0;
+  for (int64_t rb = r0; rb < r1; rb += RB) {
+    const int64_t r = rb + rl;
+    if (r >= r1) continue;
+    T acc[NCH][V];
+    row_gather_lanes<L, V, NCH, tile_wu<T>(), T>(r, g, N, rowptr[r], rowptr[r + 1], col, val, S, acc);
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) {
+      const int c = (g + L * h) * V;
+      if (c < N) {
+        const int64_t i = r * N + c;
+        store_cols<T, V>(Y + i, acc[h]);
+        if (dot) {
+          T so[V];
+          load_cols<T, V>(S + i, so);
+#pragma unroll
+          for (int v = 0; v < V; ++v) dp[h][v] += (double)acc[h][v] * (double)so[v];
+        }
+      }
     }
   }
-  if (!dot) return;
-  sd[threadIdx.x] = (rl < R) ? dp : 0.0;
-  reduce_rc(sd, R, N);
+  if (dot) tile_cols_lanes<L, V, NCH>(dp, N, sd);
+}
+
+// Calls f(tag) with the layout of wide_shape(N, tile_vmax<T>()) for N > 8.
+template <typename T, typename F>
+__device__ __forceinline__ void lanes_dispatch(int N, F&& f) {
+  const WideShape w = wide_shape(N, tile_vmax<T>());
+  if (w.NCH > 1) {
+    f(WideTag<64, 1, 2>{});
+    return;
+  }
+#define TILE_L(V)                             \
+  switch (w.L) {                              \
+    case 4: f(WideTag<4, V, 1>{}); break;     \
+    case 8: f(WideTag<8, V, 1>{}); break;     \
+    case 16: f(WideTag<16, V, 1>{}); break;   \
+    case 32: f(WideTag<32, V, 1>{}); break;   \
+    default: f(WideTag<64, V, 1>{});          \
+  }
+  if constexpr (tile_vmax<T>() >= 2) {
+    if (w.V == 2) {
+      TILE_L(2)
+      return;
+    }
+  }
+  TILE_L(1)
+#undef TILE_L
 }
 
 // One Chebyshev step over rows [r0, r1): w = A Zin; d = cd d + cr D^-1 (R - w);
@@ -206,39 +270,53 @@ __device__ void tile_cheb_small(int64_t r0, int64_t r1, const BProb<T>& D, const
   __syncthreads();
 }
 
-template <typename T>
-__device__ void tile_cheb_wide(int64_t r0, int64_t r1, const BProb<T>& D, const T* __restrict__ Zin,
-                               T* __restrict__ Zout, T cd, T cr, bool dot, double* sd) {
+// The Chebyshev step over rows [r0, r1) for N > 8 in the same layout.
+template <int L, int V, int NCH, typename T>
+__device__ void tile_cheb_lanes(int64_t r0, int64_t r1, const BProb<T>& D, const T* __restrict__ Zin,
+                                T* __restrict__ Zout, T cd, T cr, bool dot, double* sd) {
+  constexpr int RB = BS / L;
   const int N = D.N;
-  const int R = BS / N;
-  const int rl = threadIdx.x / N, c = threadIdx.x - rl * N;
-  double dp = 0.0;
-  for (int64_t rb = r0; rb < r1; rb += R) {
-    int64_t r = rb + rl;
-    if (rl < R && r < r1) {
-      int j = D.rowptr[r], j1 = D.rowptr[r + 1];
-      T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-      for (; j + 3 < j1; j += 4) {
-        int k0 = D.col[j], k1 = D.col[j + 1], k2 = D.col[j + 2], k3 = D.col[j + 3];
-        a0 += D.val[j] * Zin[(int64_t)k0 * N + c];
-        a1 += D.val[j + 1] * Zin[(int64_t)k1 * N + c];
-        a2 += D.val[j + 2] * Zin[(int64_t)k2 * N + c];
-        a3 += D.val[j + 3] * Zin[(int64_t)k3 * N + c];
+  const int g = threadIdx.x % L, rl = threadIdx.x / L;
+  double dp[NCH][V];
+#pragma unroll
+  for (int h = 0; h < NCH; ++h)
+#pragma unroll
+    for (int v = 0; v < V; ++v) dp[h][v] = 0.0;
+  for (int64_t rb = r0; rb < r1; rb += RB) {
+    const int64_t r = rb + rl;
+    if (r >= r1) continue;
+    T rv[NCH][V], dv[NCH][V], zv[NCH][V];
+    const T di = D.dinv[r];
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) {
+      const int c = (g + L * h) * V;
+      if (c < N) {
+        const int64_t i = r * N + c;
+        load_cols<T, V>(D.R + i, rv[h]);
+        load_cols<T, V>(D.Dd + i, dv[h]);
+        load_cols<T, V>(Zin + i, zv[h]);
       }
-      for (; j < j1; ++j) a0 += D.val[j] * Zin[(int64_t)D.col[j] * N + c];
-      const T w = (a0 + a1) + (a2 + a3);
-      const int64_t i = r * N + c;
-      const T rv = D.R[i];
-      const T dn = cd * D.Dd[i] + cr * (D.dinv[r] * (rv - w));
-      D.Dd[i] = dn;
-      const T z = Zin[i] + dn;
-      Zout[i] = z;
-      if (dot) dp += (double)rv * (double)z;
+    }
+    T acc[NCH][V];
+    row_gather_lanes<L, V, NCH, tile_wu<T>(), T>(r, g, N, D.rowptr[r], D.rowptr[r + 1], D.col, D.val, Zin, acc);
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) {
+      const int c = (g + L * h) * V;
+      if (c < N) {
+        const int64_t i = r * N + c;
+        T dn[V], z[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          dn[v] = cd * dv[h][v] + cr * (di * (rv[h][v] - acc[h][v]));
+          z[v] = zv[h][v] + dn[v];
+          if (dot) dp[h][v] += (double)rv[h][v] * (double)z[v];
+        }
+        store_cols<T, V>(D.Dd + i, dn);
+        store_cols<T, V>(Zout + i, z);
+      }
     }
   }
-  if (!dot) return;
-  sd[threadIdx.x] = (rl < R) ? dp : 0.0;
-  reduce_rc(sd, R, N);
+  if (dot) tile_cols_lanes<L, V, NCH>(dp, N, sd);
 }
 
 // Chebyshev step j >= 1 over all tiles. Step j reads Z[(j-1)&1] and writes
@@ -277,7 +355,10 @@ __global__ void __launch_bounds__(BS) kb_cheb(const BProb<T>* __restrict__ probs
     CHEB(8)
 #undef CHEB
     default:
-      tile_cheb_wide<T>(r0, r1, D, zin, zout, cd, cr, dot, sd);
+      lanes_dispatch<T>(D.N, [=](auto tag) {
+        using K = decltype(tag);
+        tile_cheb_lanes<K::L, K::V, K::NCH, T>(r0, r1, D, zin, zout, cd, cr, dot, sd);
+      });
   }
   if (dot && (int)threadIdx.x < D.N) rz_part[(int64_t)t * NB + threadIdx.x] = sd[threadIdx.x];
 }
@@ -312,7 +393,10 @@ __global__ void __launch_bounds__(BS, 8) kb_spmm(const BProb<T>* __restrict__ pr
     SMALL(8)
 #undef SMALL
     default:
-      tile_spmm_wide<T>(r0, r1, D.N, D.rowptr, D.col, D.val, S, D.Q, dot, sd);
+      lanes_dispatch<T>(D.N, [=](auto tag) {
+        using K = decltype(tag);
+        tile_spmm_lanes<K::L, K::V, K::NCH, T>(r0, r1, D.N, D.rowptr, D.col, D.val, S, D.Q, dot, sd);
+      });
   }
   if (dot && (int)threadIdx.x < D.N) part[(int64_t)t * NB + threadIdx.x] = sd[threadIdx.x];
 }

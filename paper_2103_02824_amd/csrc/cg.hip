@@ -99,104 +99,10 @@ constexpr int WIDE_BS = 512;
 constexpr int WIDE_MAXBLK = 1024;  // partial producers: at most cg_max_blocks()
 constexpr int WU = 16;
 
-struct WideShape {
-  int V, L, NCH;
-};
-inline WideShape wide_shape(int N, int word) {
-  const int vmax = 16 / word;
-  int V = (vmax >= 4 && N % 4 == 0) ? 4 : (N % 2 == 0 ? 2 : 1);
-  if (V > vmax) V = vmax;
-  const int groups = (N + V - 1) / V;
-  int L = 4;
-  while (L < groups && L < 64) L *= 2;
-  return {V, L, (groups + L - 1) / L};
-}
 // Grid of the N > 8 kernels: one block per 64 rows up to the cap, whatever the
 // layout (the FP32 and FP64 kernels and the consumers of their partials agree
 // on it); blocks past the last row block write zero partials.
 inline int wide_blocks_for(int64_t n) { return cap_xcd((n + 63) / 64, WIDE_MAXBLK); }
-
-template <typename T, int V>
-__device__ __forceinline__ void load_cols(const T* __restrict__ p, T (&o)[V]) {
-  if constexpr (V == 1) {
-    o[0] = p[0];
-  } else if constexpr (V == 2 && sizeof(T) == 8) {
-    const double2 q = *reinterpret_cast<const double2*>(p);
-    o[0] = q.x;
-    o[1] = q.y;
-  } else if constexpr (V == 2) {
-    const float2 q = *reinterpret_cast<const float2*>(p);
-    o[0] = q.x;
-    o[1] = q.y;
-  } else {
-    const float4 q = *reinterpret_cast<const float4*>(p);
-    o[0] = q.x;
-    o[1] = q.y;
-    o[2] = q.z;
-    o[3] = q.w;
-  }
-}
-template <typename T, int V>
-__device__ __forceinline__ void store_cols(T* __restrict__ p, const T (&o)[V]) {
-  if constexpr (V == 1) {
-    p[0] = o[0];
-  } else if constexpr (V == 2 && sizeof(T) == 8) {
-    *reinterpret_cast<double2*>(p) = make_double2(o[0], o[1]);
-  } else if constexpr (V == 2) {
-    *reinterpret_cast<float2*>(p) = make_float2(o[0], o[1]);
-  } else {
-    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
-  }
-}
-
-// acc[h][v] = (A X)[r, (g + L h) V + v] for the lane's column group g (zero
-// where the group lies past N).
-template <int L, int V, int NCH, typename T>
-__device__ __forceinline__ void row_gather_lanes(int64_t r, int g, int N, int jb, int j1,
-                                                 const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                 const T* __restrict__ X, T (&acc)[NCH][V]) {
-  T a0[NCH][V], a1[NCH][V];
-#pragma unroll
-  for (int h = 0; h < NCH; ++h)
-#pragma unroll
-    for (int v = 0; v < V; ++v) a0[h][v] = a1[h][v] = T(0);
-  for (int j = jb; j < j1; j += WU) {
-    int k[WU];
-    T w[WU];
-#pragma unroll
-    for (int u = 0; u < WU; ++u) {
-      const bool ok = j + u < j1;
-      k[u] = ok ? col[j + u] : (int)r;
-      w[u] = ok ? val[j + u] : T(0);
-    }
-    T x[WU][NCH][V];
-#pragma unroll
-    for (int u = 0; u < WU; ++u)
-#pragma unroll
-      for (int h = 0; h < NCH; ++h) {
-        const int c = (g + L * h) * V;
-        if (c < N) {
-          load_cols<T, V>(X + (int64_t)k[u] * N + c, x[u][h]);
-        } else {
-#pragma unroll
-          for (int v = 0; v < V; ++v) x[u][h][v] = T(0);
-        }
-      }
-#pragma unroll
-    for (int u = 0; u < WU; u += 2)
-#pragma unroll
-      for (int h = 0; h < NCH; ++h)
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          a0[h][v] += w[u] * x[u][h][v];
-          a1[h][v] += w[u + 1] * x[u + 1][h][v];
-        }
-  }
-#pragma unroll
-  for (int h = 0; h < NCH; ++h)
-#pragma unroll
-    for (int v = 0; v < V; ++v) acc[h][v] = a0[h][v] + a1[h][v];
-}
 
 // Column sums of dot over the block's BS / L row slots into partial[blk, :].
 template <int L, int V, int NCH, int BS>
@@ -251,7 +157,7 @@ __global__ void __launch_bounds__(WIDE_BS) k_spmm_rows(int64_t n, int N, const i
     }
     if (r >= n) continue;
     T acc[NCH][V];
-    row_gather_lanes<L, V, NCH, T>(r, g, N, jr, jr1, col, val, X, acc);
+    row_gather_lanes<L, V, NCH, WU, T>(r, g, N, jr, jr1, col, val, X, acc);
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
       const int c = (g + L * h) * V;
@@ -481,7 +387,7 @@ __global__ void __launch_bounds__(WIDE_BS) k_cheb_rows(int64_t n, int N, const i
       }
     }
     T acc[NCH][V];
-    row_gather_lanes<L, V, NCH, T>(r, g, N, jr, jr1, col, val, Zin, acc);
+    row_gather_lanes<L, V, NCH, WU, T>(r, g, N, jr, jr1, col, val, Zin, acc);
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
       const int c = (g + L * h) * V;
@@ -838,13 +744,9 @@ __global__ void __launch_bounds__(TPB) k_add_f32(int64_t m, const float* __restr
 
 // Calls f(tag, grid, block) with tag::L, tag::V, tag::NCH the N > 8 layout of
 // wide_shape(N, sizeof(T)).
-template <int L_, int V_, int NCH_>
-struct WideTag {
-  static constexpr int L = L_, V = V_, NCH = NCH_;
-};
 template <typename T, typename F>
 void wide_launch(hipStream_t, int64_t n, int N, F&& f) {
-  const WideShape w = wide_shape(N, (int)sizeof(T));
+  const WideShape w = wide_shape(N, 16 / (int)sizeof(T));
   const dim3 g(wide_blocks_for(n)), b(WIDE_BS);
   if (w.NCH > 1) {
     f(WideTag<64, 1, 2>{}, g, b);
