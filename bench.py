@@ -429,13 +429,18 @@ def run_batch(args):
     print(json.dumps(res), flush=True)
 
 
+# committed rocprofv3 summaries with hardware-counter traffic per workload
+_PROFILES = {("c2", 0, "fp64"): "cg_c2_cluster_fp64.md", ("c3", 0, "fp32ir"): "cg_c3_cluster40_fp32ir.md"}
+
+
 def _traffic(kname, workload, seed, precision):
     """HBM bytes per launch of the roofline kernel from the committed counter summary, or None
-    when that summary was taken on another workload or the kernel source has changed since."""
+    when there is no summary for this workload or the kernel sources have changed since."""
     import hashlib
-    if (workload, seed, precision) != ("c2", 0, "fp64"):
+    name = _PROFILES.get((workload, seed, precision))
+    if name is None:
         return None
-    prof = Path(ROOT) / "profiles" / "cg_c2_cluster_fp64.md"
+    prof = Path(ROOT) / "profiles" / name
     if not prof.exists():
         return None
     for line in prof.read_text().splitlines():
@@ -443,8 +448,8 @@ def _traffic(kname, workload, seed, precision):
             rec = json.loads(line.split(":", 1)[1])
             if rec["kernel"] != kname:
                 continue
-            src = Path(ROOT) / rec["source"]
-            if hashlib.sha256(src.read_bytes()).hexdigest() != rec["source_sha256"]:
+            blob = b"".join((Path(ROOT) / f).read_bytes() for f in rec["sources"])
+            if hashlib.sha256(blob).hexdigest() != rec["sources_sha256"]:
                 return None
             return rec["bytes_per_launch"]
     return None

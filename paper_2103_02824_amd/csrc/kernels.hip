@@ -503,6 +503,45 @@ __global__ void __launch_bounds__(TPB) k_restrict(int64_t nH, int N, const int32
   }
 }
 
+// The restriction for N > 8: lane c of each wavefront owns column c0 + c
+// (c0 = 0, 64, ...), the four wavefronts of the block take interleaved groups
+// of 8 of the coarse row's fine entries (index and weight loads issued
+// together, then the 8 gathered row segments; entries past the end repeat the
+// first with weight zero), and the four wave sums are added in fixed order.
+__global__ void __launch_bounds__(TPB) k_restrict_lanes(int64_t nH, int N, const int32_t* __restrict__ PTptr,
+                                                        const int32_t* __restrict__ PTidx,
+                                                        const double* __restrict__ PTw, const double* __restrict__ Y,
+                                                        double* __restrict__ out) {
+  constexpr int U = 8;
+  __shared__ double ws[TPB / 64][64];
+  const int64_t k = blockIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int e0 = PTptr[k], e1 = PTptr[k + 1];
+  for (int c0 = 0; c0 < N; c0 += 64) {
+    const int c = c0 + lane;
+    double acc = 0.0;
+    for (int e = e0 + U * wid; e < e1; e += U * (TPB / 64)) {
+      int idx[U];
+      double w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = e + u < e1;
+        idx[u] = ok ? PTidx[e + u] : PTidx[e0];
+        w[u] = ok ? PTw[e + u] : 0.0;
+      }
+      double y[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) y[u] = c < N ? Y[(int64_t)idx[u] * N + c] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc += w[u] * y[u];
+    }
+    ws[wid][lane] = acc;
+    __syncthreads();
+    if (wid == 0 && c < N) out[k * N + c] = (ws[0][lane] + ws[1][lane]) + (ws[2][lane] + ws[3][lane]);
+    __syncthreads();
+  }
+}
+
 // Gram block U^T Y (N x N) on the FP64 matrix cores (N <= 16): orbitals are
 // padded to 16, rows are the reduction index. One v_mfma_f64_16x16x4f64 per 4
 // rows: lane l feeds U[row 4q + l/16][orbital l%16] as A (16 x 4, orbital x
@@ -540,6 +579,54 @@ __global__ void __launch_bounds__(TPB) k_gram_mfma(int64_t n, int N, const doubl
     const int o = i * 16 + j;
     partial[(int64_t)blockIdx.x * N * N + p] = (sd[0][o] + sd[1][o]) + (sd[2][o] + sd[3][o]);
   }
+}
+
+// Gram block U^T Y for 16 < N <= 64 on the FP64 matrix cores: the N x N block
+// is TI x TI tiles of 16 x 16 (orbitals padded to 16 TI), each accumulated by
+// the same v_mfma_f64_16x16x4f64 lane layout as k_gram_mfma, all tiles in
+// registers so that U and Y are read once; the block's four waves are summed
+// through LDS one tile at a time into the block's N x N partial.
+template <int TI>
+__global__ void __launch_bounds__(TPB) k_gram_mfma_tiles(int64_t n, int N, const double* __restrict__ U,
+                                                         const double* __restrict__ Y, double* __restrict__ partial) {
+  __shared__ double sd[TPB / 64][16 * 16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int col = lane & 15, rq = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * GRAM_ROWS;
+  const int64_t r1 = r0 + GRAM_ROWS < n ? r0 + GRAM_ROWS : n;
+  f64x4 acc[TI][TI];
+#pragma unroll
+  for (int bi = 0; bi < TI; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < TI; ++bj) acc[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t rb = r0 + 4 * wid; rb < r1; rb += 16) {
+    const int64_t r = rb + rq;
+    double a[TI], b[TI];
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+      const int c = 16 * t + col;
+      const bool ok = r < r1 && c < N;
+      a[t] = ok ? U[r * N + c] : 0.0;
+      b[t] = ok ? Y[r * N + c] : 0.0;
+    }
+#pragma unroll
+    for (int bi = 0; bi < TI; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < TI; ++bj) acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+  }
+#pragma unroll
+  for (int bi = 0; bi < TI; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < TI; ++bj) {
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sd[wid][(rq + 4 * v) * 16 + col] = acc[bi][bj][v];
+      __syncthreads();
+      const int i = 16 * bi + (int)(threadIdx.x >> 4), j = 16 * bj + (int)(threadIdx.x & 15);
+      const int o = threadIdx.x;
+      if (i < N && j < N)
+        partial[(int64_t)blockIdx.x * N * N + (int64_t)i * N + j] = (sd[0][o] + sd[1][o]) + (sd[2][o] + sd[3][o]);
+    }
 }
 
 // Gram block for N > 16: thread (row, j) with the N products per row in a
@@ -1124,13 +1211,23 @@ void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, do
 }
 void launch_restrict(hipStream_t s, int64_t nH, int N, const int32_t* PTptr, const int32_t* PTidx, const double* PTw,
                      const double* Y, double* out) {
-  hipLaunchKernelGGL(k_restrict, dim3((unsigned)nH), dim3(TPB), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
+  if (N > 8)
+    hipLaunchKernelGGL(k_restrict_lanes, dim3((unsigned)nH), dim3(TPB), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
+  else
+    hipLaunchKernelGGL(k_restrict, dim3((unsigned)nH), dim3(TPB), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
 }
 void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double* Y, double* partial) {
+  const dim3 g(gram_blocks(n)), b(TPB);
   if (N <= 16)
-    hipLaunchKernelGGL(k_gram_mfma, dim3(gram_blocks(n)), dim3(TPB), 0, s, n, N, U, Y, partial);
+    hipLaunchKernelGGL(k_gram_mfma, g, b, 0, s, n, N, U, Y, partial);
+  else if (N <= 32)
+    hipLaunchKernelGGL(k_gram_mfma_tiles<2>, g, b, 0, s, n, N, U, Y, partial);
+  else if (N <= 48)
+    hipLaunchKernelGGL(k_gram_mfma_tiles<3>, g, b, 0, s, n, N, U, Y, partial);
+  else if (N <= 64)
+    hipLaunchKernelGGL(k_gram_mfma_tiles<4>, g, b, 0, s, n, N, U, Y, partial);
   else
-    hipLaunchKernelGGL(k_gram_wide, dim3(gram_blocks(n)), dim3(TPB), 0, s, n, N, U, Y, partial);
+    hipLaunchKernelGGL(k_gram_wide, g, b, 0, s, n, N, U, Y, partial);
 }
 void launch_coarse_hats(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* grp_ptr, const int32_t* grp_tet,
                         const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* chat) {
