@@ -448,8 +448,13 @@ def _traffic(kname, workload, seed, precision):
             rec = json.loads(line.split(":", 1)[1])
             if rec["kernel"] != kname:
                 continue
-            blob = b"".join((Path(ROOT) / f).read_bytes() for f in rec["sources"])
-            if hashlib.sha256(blob).hexdigest() != rec["sources_sha256"]:
+            srcs = rec.get("sources", [rec["source"]] if "source" in rec else [])
+            want = rec.get("sources_sha256", rec.get("source_sha256"))
+            try:
+                blob = b"".join((Path(ROOT) / f).read_bytes() for f in srcs)
+            except OSError:
+                return None
+            if not srcs or hashlib.sha256(blob).hexdigest() != want:
                 return None
             return rec["bytes_per_launch"]
     return None
