@@ -80,8 +80,9 @@ def _kernel_name(which, N, word):
         while L < groups and L < 64:
             L *= 2
         nch = -(-groups // L)
-        name = "k_spmm_rows" if "spmm" in which else "k_cheb_rows"
-        return f"{name}<{L}, {V}, {nch}, {t}>"
+        if "spmm" in which:
+            return f"k_spmm_rows<{L}, {V}, {nch}, {t}>"
+        return f"k_cheb_rows<{L}, {V}, {nch}, false, {t}>"  # the steps without the r.z partials
     if "spmm" in which:
         unroll = 4 if N <= 3 else (2 if N <= 6 else 1)
         return f"k_spmm_small<{N}, 4, {unroll}, 1024, {8 if N <= 6 else 4}, {t}>"
