@@ -481,12 +481,24 @@ __global__ void __launch_bounds__(TPB) k_restrict(int64_t nH, int N, const int32
     double acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    for (int e = e0 + (int)threadIdx.x; e < e1; e += TPB) {
-      const double w = PTw[e];
-      const double* y = Y + (int64_t)PTidx[e] * N + c0;
+    // four entries per thread and step, their index and weight loads issued
+    // together, then the four gathers (entries past the end: weight zero)
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += 4 * TPB) {
+      int idx[4];
+      double w[4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < nc) acc[q] += w * y[q];
+      for (int u = 0; u < 4; ++u) {
+        const bool ok = e + u * TPB < e1;
+        idx[u] = ok ? PTidx[e + u * TPB] : PTidx[e];
+        w[u] = ok ? PTw[e + u * TPB] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double* y = Y + (int64_t)idx[u] * N + c0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < nc) acc[q] += w[u] * y[q];
+      }
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -504,23 +516,25 @@ __global__ void __launch_bounds__(TPB) k_restrict(int64_t nH, int N, const int32
 }
 
 // The restriction for N > 8: lane c of each wavefront owns column c0 + c
-// (c0 = 0, 64, ...), the four wavefronts of the block take interleaved groups
-// of 8 of the coarse row's fine entries (index and weight loads issued
-// together, then the 8 gathered row segments; entries past the end repeat the
-// first with weight zero), and the four wave sums are added in fixed order.
-__global__ void __launch_bounds__(TPB) k_restrict_lanes(int64_t nH, int N, const int32_t* __restrict__ PTptr,
+// (c0 = 0, 64, ...), the RW = 16 wavefronts of the block take interleaved
+// groups of 8 of the coarse row's fine entries (a coarse hat spans thousands
+// of fine DoFs; index and weight loads issued together, then the 8 gathered
+// row segments; entries past the end repeat the first with weight zero), and
+// the wave sums are added in fixed order.
+constexpr int RW = 16;
+__global__ void __launch_bounds__(64 * RW) k_restrict_lanes(int64_t nH, int N, const int32_t* __restrict__ PTptr,
                                                         const int32_t* __restrict__ PTidx,
                                                         const double* __restrict__ PTw, const double* __restrict__ Y,
                                                         double* __restrict__ out) {
   constexpr int U = 8;
-  __shared__ double ws[TPB / 64][64];
+  __shared__ double ws[RW][64];
   const int64_t k = blockIdx.x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int e0 = PTptr[k], e1 = PTptr[k + 1];
   for (int c0 = 0; c0 < N; c0 += 64) {
     const int c = c0 + lane;
     double acc = 0.0;
-    for (int e = e0 + U * wid; e < e1; e += U * (TPB / 64)) {
+    for (int e = e0 + U * wid; e < e1; e += U * RW) {
       int idx[U];
       double w[U];
 #pragma unroll
@@ -537,7 +551,12 @@ __global__ void __launch_bounds__(TPB) k_restrict_lanes(int64_t nH, int N, const
     }
     ws[wid][lane] = acc;
     __syncthreads();
-    if (wid == 0 && c < N) out[k * N + c] = (ws[0][lane] + ws[1][lane]) + (ws[2][lane] + ws[3][lane]);
+    if (wid == 0 && c < N) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < RW; ++w) t += ws[w][lane];
+      out[k * N + c] = t;
+    }
     __syncthreads();
   }
 }
@@ -1212,7 +1231,7 @@ void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, do
 void launch_restrict(hipStream_t s, int64_t nH, int N, const int32_t* PTptr, const int32_t* PTidx, const double* PTw,
                      const double* Y, double* out) {
   if (N > 8)
-    hipLaunchKernelGGL(k_restrict_lanes, dim3((unsigned)nH), dim3(TPB), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
+    hipLaunchKernelGGL(k_restrict_lanes, dim3((unsigned)nH), dim3(64 * RW), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
   else
     hipLaunchKernelGGL(k_restrict, dim3((unsigned)nH), dim3(TPB), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
 }
