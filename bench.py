@@ -41,6 +41,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+_HPC = {"same": -1, "jacobi": 0, "chebyshev": 1}  # options.hartree_precond
 
 
 def log(*a):
@@ -153,6 +154,8 @@ def main():
                     help="CG preconditioner of the step-5 and Hartree solves (default: chebyshev for one system, "
                          "jacobi for --workload batch, where the tile SpMM is bandwidth-bound and the polynomial "
                          "steps cost more than the iterations they save)")
+    ap.add_argument("--hartree-precond", choices=["same", "jacobi", "chebyshev"], default="same",
+                    help="preconditioner of the Hartree CG apart from the step-5 solves (default: the same)")
     ap.add_argument("--cheb-degree", type=int, default=8)
     ap.add_argument("--cheb-ratio", type=float, default=100.0)
     ap.add_argument("--hartree-coarse", type=int, default=1, choices=[0, 1],
@@ -199,7 +202,7 @@ def main():
                        inner_tol=args.inner_tol, time_kernels=0, precision=prec,
                        precond=mlc.PC_CHEBYSHEV if args.precond == "chebyshev" else mlc.PC_JACOBI,
                        cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio,
-                       hartree_coarse=args.hartree_coarse)
+                       hartree_coarse=args.hartree_coarse, hartree_precond=_HPC[args.hartree_precond])
     ctx = mlc.Context(S, opts)
     n, N = ctx.n_dof, ctx.N
     nnz = None
@@ -365,8 +368,10 @@ def run_batch(args):
     base = dict(cg_rtol=args.cg_rtol, poisson_rtol=args.cg_rtol, inner_maxit=args.batch_inner_maxit,
                 inner_tol=args.inner_tol)
     pcopt = dict(precond=mlc.PC_CHEBYSHEV if args.precond == "chebyshev" else mlc.PC_JACOBI,
-                 cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio, hartree_coarse=args.hartree_coarse)
-    pcname = args.precond + ("+coarse" if args.hartree_coarse else "")
+                 cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio, hartree_coarse=args.hartree_coarse,
+                 hartree_precond=_HPC[args.hartree_precond])
+    pcname = args.precond + ("" if args.hartree_precond == "same" else f"/hartree-{args.hartree_precond}") + \
+        ("+coarse" if args.hartree_coarse else "")
     out = {}
     states = []
     dof_orb = None

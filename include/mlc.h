@@ -134,6 +134,11 @@ typedef struct {
                            P^T K P factorised on the host once per mesh, its
                            inverse applied on the device) to the preconditioner
                            chosen by precond                                   */
+  int32_t hartree_precond; /* preconditioner of the Hartree CG (step 6): -1 (the
+                           default) takes precond; MLC_PC_JACOBI or
+                           MLC_PC_CHEBYSHEV choose it apart from the step-5
+                           solves (same degree and ratio); a batch requires the
+                           same choice in all its contexts                    */
 } mlc_options;
 
 enum { MLC_PC_JACOBI = 0, MLC_PC_CHEBYSHEV = 1 };

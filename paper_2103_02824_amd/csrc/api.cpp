@@ -434,6 +434,7 @@ void mlc_options_default(mlc_options* o) {
   o->cheb_degree = 4;
   o->cheb_ratio = 30.0;
   o->hartree_coarse = 0;
+  o->hartree_precond = -1;
 }
 
 mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys, const mlc_options* opt,
@@ -460,8 +461,10 @@ mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_sy
       (c->opt.precision != MLC_PREC_FP64 && c->opt.precision != MLC_PREC_FP32_IR) ||
       (c->opt.precision == MLC_PREC_FP32_IR && (!(c->opt.ir_inner_rtol > 0) || c->opt.ir_max_outer < 1)) ||
       (c->opt.precond != MLC_PC_JACOBI && c->opt.precond != MLC_PC_CHEBYSHEV) ||
-      (c->opt.precond == MLC_PC_CHEBYSHEV && (c->opt.cheb_degree < 2 || c->opt.cheb_degree > 16 ||
-                                              !(c->opt.cheb_ratio > 1.0)))) {
+      (c->opt.hartree_precond != -1 && c->opt.hartree_precond != MLC_PC_JACOBI &&
+       c->opt.hartree_precond != MLC_PC_CHEBYSHEV) ||
+      ((c->opt.precond == MLC_PC_CHEBYSHEV || hartree_pc(c->opt) == MLC_PC_CHEBYSHEV) &&
+       (c->opt.cheb_degree < 2 || c->opt.cheb_degree > 16 || !(c->opt.cheb_ratio > 1.0)))) {
     delete c;
     return MLC_ERR_ARG;
   }
@@ -623,7 +626,8 @@ mlc_status mlc_time_kernel(mlc_ctx* c, int32_t which, int32_t reps, double* avg_
   if (!c->has_step) return fail(c, MLC_ERR_STATE, "no correction step has run");
   const bool cheb = which == MLC_KERNEL_CHEB_STEP || which == MLC_KERNEL_HARTREE_CHEB_STEP;
   const bool hart = which >= MLC_KERNEL_HARTREE_SPMM;
-  if (cheb && c->opt.precond != MLC_PC_CHEBYSHEV) return fail(c, MLC_ERR_ARG, "no polynomial preconditioner");
+  if (cheb && (hart ? hartree_pc(c->opt) : c->opt.precond) != MLC_PC_CHEBYSHEV)
+    return fail(c, MLC_ERR_ARG, "no polynomial preconditioner");
   if (hart && !c->hartree) return fail(c, MLC_ERR_ARG, "no Hartree problem");
   auto& d = c->d;
   hipStream_t s = c->stream;

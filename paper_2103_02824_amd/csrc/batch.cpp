@@ -139,7 +139,8 @@ mlc_status upload_shape(mlc_batch* b, int TR) {
     for (int k = 0; k < nt; ++k) tp.push_back(s);
     if (c->hartree) {
       BProb<double> pp{d.rowptr, d.col, d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq,
-                       d.Yh, d.Yh + c->n, d.Yh + 2 * c->n, pc ? d.lmax + 1 : nullptr, c->n, 1, (int32_t)tpP.size(),
+                       d.Yh, d.Yh + c->n, d.Yh + 2 * c->n,
+                       hartree_pc(c->opt) == MLC_PC_CHEBYSHEV ? d.lmax + 1 : nullptr, c->n, 1, (int32_t)tpP.size(),
                        nt, 0};
       hP.push_back(pp);
       for (int k = 0; k < nt; ++k) tpP.push_back(kp);
@@ -251,9 +252,9 @@ struct BRes {
 
 // Batched CG from the current X of every problem; scalars in bs, counts in fl.
 // Ns[p] = columns of problem p. Accumulates iteration counts into out.
-BPoly batch_poly(const mlc_batch* b) {
+BPoly batch_poly(const mlc_batch* b, int kind) {
   const mlc_options& o = b->ctx[0]->opt;
-  if (o.precond != MLC_PC_CHEBYSHEV) return BPoly{0, 1.0, nullptr};
+  if ((kind == 1 ? hartree_pc(o) : o.precond) != MLC_PC_CHEBYSHEV) return BPoly{0, 1.0, nullptr};
   return BPoly{o.cheb_degree, o.cheb_ratio, b->part_rz};
 }
 
@@ -261,7 +262,7 @@ template <typename T>
 mlc_status bcg(mlc_batch* b, int kind, const BProb<T>* probs, const int32_t* tile_prob, int ntiles,
                const std::vector<int>& Ns, double* bs, int32_t* fl, const double* mask_bs, double rtol, int maxit,
                BRes* out, const BCoarseSet* cs = nullptr) {
-  BPoly poly = batch_poly(b);
+  BPoly poly = batch_poly(b, kind);
   if (cs && cs->coarse && !poly.rz_part) poly.rz_part = b->part_rz;  // the coarse term's r.z partials
   hipStream_t s = b->stream;
   const int K = (int)Ns.size();
@@ -499,8 +500,8 @@ mlc_status mlc_batch_create(mlc_ctx* const* ctxs, int32_t count, mlc_batch** out
   for (mlc_ctx* c : b->ctx) {
     if (!c->bound) return MLC_ERR_STATE;
     if (c->opt.precision != b->prec) return MLC_ERR_ARG;
-    if (c->opt.precond != ctxs[0]->opt.precond ||
-        (c->opt.precond == MLC_PC_CHEBYSHEV &&
+    if (c->opt.precond != ctxs[0]->opt.precond || hartree_pc(c->opt) != hartree_pc(ctxs[0]->opt) ||
+        ((c->opt.precond == MLC_PC_CHEBYSHEV || hartree_pc(c->opt) == MLC_PC_CHEBYSHEV) &&
          (c->opt.cheb_degree != ctxs[0]->opt.cheb_degree || c->opt.cheb_ratio != ctxs[0]->opt.cheb_ratio)))
       return MLC_ERR_ARG;
     if (c->opt.hartree_coarse != ctxs[0]->opt.hartree_coarse) return MLC_ERR_ARG;

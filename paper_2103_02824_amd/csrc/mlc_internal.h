@@ -221,6 +221,9 @@ mlc_status probe(mlc_ctx* c, int which, double* out, int64_t count);
 int spmm_rows_per_block(int N);
 
 // Chebyshev polynomial preconditioner of one CG solve (null pointer: Jacobi).
+// Preconditioner of the Hartree CG: hartree_precond, or precond when it is -1.
+inline int hartree_pc(const mlc_options& o) { return o.hartree_precond < 0 ? o.precond : o.hartree_precond; }
+
 template <typename T>
 struct PolyPC {
   const double* lmax;  // device scalar: Gershgorin bound of D^-1 A

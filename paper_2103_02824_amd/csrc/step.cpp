@@ -715,7 +715,7 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
     CoarsePC ccK{d.KHinv, c->nH, d.PTptr, d.PTidx, d.PTw, d.Pk, d.Pw, d.rH, d.eH, d.Yh + 3 * n,
                  d.red + cg_max_blocks()};
     CgArgs<double> pa{d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP, nullptr,
-                      c->opt.precond == MLC_PC_CHEBYSHEV ? &pcK : nullptr,
+                      hartree_pc(c->opt) == MLC_PC_CHEBYSHEV ? &pcK : nullptr,
                       c->opt.hartree_coarse && d.KHinv ? &ccK : nullptr};
     PHASE(cg<double>(c, 1, n, 1, pa, c->opt.poisson_rtol, c->opt.cg_maxit, false, &dummy, &dn, &S.pr));
   }

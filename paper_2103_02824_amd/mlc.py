@@ -63,7 +63,7 @@ class Options(C.Structure):
                 ("reorder", C.c_int32), ("time_kernels", C.c_int32), ("use_graphs", C.c_int32),
                 ("precision", C.c_int32), ("ir_inner_rtol", C.c_double), ("ir_max_outer", C.c_int32),
                 ("precond", C.c_int32), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
-                ("hartree_coarse", C.c_int32)]
+                ("hartree_coarse", C.c_int32), ("hartree_precond", C.c_int32)]
 
 PREC_FP64, PREC_FP32_IR = 0, 1
 PC_JACOBI, PC_CHEBYSHEV = 0, 1

@@ -57,7 +57,8 @@ def _contexts(cases, **kw):
 
 @pytest.mark.parametrize("prec,pc", [("fp64", "jacobi"), ("fp32ir", "jacobi"), ("fp64", "chebyshev"),
                                      ("fp32ir", "chebyshev"), ("fp64", "jacobi+coarse"),
-                                     ("fp64", "chebyshev+coarse"), ("fp32ir", "chebyshev+coarse")])
+                                     ("fp64", "chebyshev+coarse"), ("fp32ir", "chebyshev+coarse"),
+                                     ("fp32ir", "jacobi/hartree-chebyshev+coarse")])
 def test_batch_step_matches_checker(cases, prec, pc):
     from paper_2103_02824_amd import mlc
     kw = {} if prec == "fp64" else dict(precision=mlc.PREC_FP32_IR, ir_inner_rtol=1e-4)
@@ -65,6 +66,8 @@ def test_batch_step_matches_checker(cases, prec, pc):
         kw.update(precond=mlc.PC_CHEBYSHEV, cheb_degree=6, cheb_ratio=100.0)
     if pc.endswith("coarse"):
         kw.update(hartree_coarse=1)
+    if "/hartree-chebyshev" in pc:  # Jacobi for step 5, the polynomial only in the Hartree CG
+        kw.update(hartree_precond=mlc.PC_CHEBYSHEV, cheb_degree=6, cheb_ratio=100.0)
     print(f"case batch of {[c[0] for c in cases]} precision {prec} preconditioner {pc}", flush=True)
     ctxs = _contexts(cases, **kw)
     batch = mlc.Batch(ctxs)
