@@ -152,8 +152,8 @@ def test_wide_block_twelve_orbitals(gpu):
 _WIDE_REF = {}
 
 
-@pytest.mark.parametrize("case", ["24-chebyshev", "33-jacobi", "52-jacobi", "52-chebyshev", "52-chebyshev-fp32",
-                                  "71-chebyshev"])
+@pytest.mark.parametrize("case", ["9-jacobi", "24-chebyshev", "33-jacobi", "52-jacobi", "52-chebyshev",
+                                  "52-chebyshev-fp32", "71-chebyshev", "100-chebyshev-fp32", "128-chebyshev"])
 def test_wide_blocks_fine_stage(gpu, case):
     """The N > 8 kernels on a 23^3-interior mesh (12167 DoF): a lane owns V
     consecutive columns (V = 2 in FP64 and 4 in FP32 for even and multiple-of-4
