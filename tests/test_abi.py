@@ -156,3 +156,33 @@ def test_batch_argument_checks():
     assert not b.value
     assert L.mlc_batch_set_shape(None, 128, 2) == -1
     L.mlc_destroy(h)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes mirror of a C struct in include/mlc.h has the C layout:
+    sizeof and the offset of every field, from a program compiled against the
+    header with g++."""
+    import shutil
+    import subprocess
+    from paper_2103_02824_amd import mlc
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    pairs = {"Mesh": "mlc_mesh", "SystemDesc": "mlc_system", "Options": "mlc_options",
+             "StepReport": "mlc_step_report", "BatchReport": "mlc_batch_report"}
+    lines = ["#include <cstddef>", "#include <cstdio>", f'#include "{ROOT / "include" / "mlc.h"}"', "int main() {"]
+    for py, c in pairs.items():
+        lines.append(f'  std::printf("{py} sizeof %zu\\n", sizeof({c}));')
+        for name, _ in getattr(mlc, py)._fields_:
+            lines.append(f'  std::printf("{py} {name} %zu\\n", offsetof({c}, {name}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.cpp"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["g++", "-std=c++17", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {(a, b): int(v) for a, b, v in (ln.split() for ln in out if ln.strip())}
+    for py in pairs:
+        cls = getattr(mlc, py)
+        assert got[(py, "sizeof")] == C.sizeof(cls), py
+        for name, _ in cls._fields_:
+            assert got[(py, name)] == getattr(cls, name).offset, (py, name)
