@@ -32,7 +32,7 @@ def test_exports_match_header():
     assert declared == set(mlc.EXPORTED)
 
 
-def _create(mlc, L, S, fine_xyz=None, fine_tets=None, coarse_xyz=None, coarse_tets=None, **sysover):
+def _create(mlc, L, S, fine_xyz=None, fine_tets=None, coarse_xyz=None, coarse_tets=None, opts=None, **sysover):
     xyz = np.ascontiguousarray(S.xyz if fine_xyz is None else fine_xyz, dtype=np.float64)
     tets = np.ascontiguousarray(S.tets if fine_tets is None else fine_tets, dtype=np.int32)
     cxyz = np.ascontiguousarray(S.cxyz if coarse_xyz is None else coarse_xyz, dtype=np.float64)
@@ -46,7 +46,7 @@ def _create(mlc, L, S, fine_xyz=None, fine_tets=None, coarse_xyz=None, coarse_te
                         S.xc, S.xalpha, int(S.hartree), S.lo, S.hi)
     for k, v in sysover.items():
         setattr(sd, k, v)
-    o = mlc.options()
+    o = mlc.options() if opts is None else opts
     h = C.c_void_p()
     st = L.mlc_create(C.byref(fine), C.byref(coarse), C.byref(sd), C.byref(o), C.byref(h))
     msg = L.mlc_last_error(h).decode() if h.value else ""
@@ -186,3 +186,19 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(py, "sizeof")] == C.sizeof(cls), py
         for name, _ in cls._fields_:
             assert got[(py, name)] == getattr(cls, name).offset, (py, name)
+
+
+def test_hartree_preconditioner_option_checked():
+    """options.hartree_precond: -1 (take precond), Jacobi or Chebyshev; the
+    polynomial's degree and ratio are checked whenever either solve uses it."""
+    mlc, L = _lib()
+    S = c1_hydrogen()
+    ok = [dict(hartree_precond=-1), dict(hartree_precond=mlc.PC_CHEBYSHEV),
+          dict(precond=mlc.PC_CHEBYSHEV, hartree_precond=mlc.PC_JACOBI)]
+    bad = [dict(hartree_precond=5), dict(hartree_precond=-2),
+           dict(hartree_precond=mlc.PC_CHEBYSHEV, cheb_degree=1),
+           dict(hartree_precond=mlc.PC_CHEBYSHEV, cheb_ratio=0.5)]
+    for kw in ok:
+        assert _create(mlc, L, S, opts=mlc.options(**kw))[0] == 0, kw
+    for kw in bad:
+        assert _create(mlc, L, S, opts=mlc.options(**kw))[0] == -1, kw
