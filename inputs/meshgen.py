@@ -66,7 +66,8 @@ class _Bisector:
     hanging edge by further bisection yields a conforming mesh.
     """
 
-    def __init__(self, xyz, tets):
+    def __init__(self, xyz, tets, full_scan=False):
+        self.full_scan = full_scan  # search every tet for hanging edges (reference behaviour)
         self.xyz = [np.asarray(xyz, dtype=np.float64)]
         self.nv = len(xyz)
         self.tets = np.asarray(tets, dtype=np.int64).copy()
@@ -161,7 +162,7 @@ class _Bisector:
         if len(self.mid_keys) == 0:
             return np.zeros(len(self.tets), dtype=bool)
         cand = None
-        if self.split_ends is not None:
+        if self.split_ends is not None and not self.full_scan:
             cand = self.split_ends[self.tets].any(axis=1)
             cand[len(self.tets) - self.n_children:] = True
             cand = np.nonzero(cand)[0]
@@ -212,7 +213,8 @@ def _refine_to(B, C, h0, kappa, h_min, h_max, max_levels=200, progress=None):
             progress(f"mesh refinement level {level}: {B.nv} vertices, {len(B.tets)} tets")
 
 
-def graded_mesh(n_base, lo, hi, centres, h0, kappa, h_min, h_max=np.inf, coarse=None, progress=None):
+def graded_mesh(n_base, lo, hi, centres, h0, kappa, h_min, h_max=np.inf, coarse=None, progress=None,
+                full_scan=False):
     """Kuhn base mesh refined until every tet satisfies
     longest_edge <= clip(h0 + kappa * d(centroid), h_min, h_max), d = distance
     of the centroid to the nearest centre.
@@ -222,10 +224,12 @@ def graded_mesh(n_base, lo, hi, centres, h0, kappa, h_min, h_max=np.inf, coarse=
     refines that graded mesh further, so the two meshes stay nested.
     Returns (xyz, tets, coarse_xyz, coarse_tets). Coarse vertices keep their
     ids in the fine mesh. progress: optional callable given one line per
-    refinement level (long generations stay visibly alive).
+    refinement level (long generations stay visibly alive). full_scan: search
+    every tet for hanging edges after each bisection (the reference for the
+    restricted search, which must give the same mesh).
     """
     bxyz, btets = kuhn_mesh(n_base, lo, hi)
-    B = _Bisector(bxyz, btets)
+    B = _Bisector(bxyz, btets, full_scan=full_scan)
     C = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
     if coarse is not None:
         _refine_to(B, C, *coarse, progress=progress)

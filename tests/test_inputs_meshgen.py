@@ -1,0 +1,39 @@
+"""The seeded mesh generator: after each bisection it searches for hanging
+edges only around the edges that bisection split. That must give exactly the
+mesh that searching every tet gives, and the result must be a conforming
+nested mesh (every fine tet inside one coarse tet, no hanging edge)."""
+import math
+
+import numpy as np
+import pytest
+
+from inputs.meshgen import graded_mesh
+from inputs.systems import random_cluster
+
+
+@pytest.mark.parametrize("atoms,hw,box,n_base,h,coarse", [
+    (4, 3.0, 15.0, 8, 0.5, (1.4, 0.6, 1.4)),
+    (40, 8.0, 25.0, 12, 0.6, None),
+])
+def test_restricted_hanging_search_gives_the_full_scan_mesh(atoms, hw, box, n_base, h, coarse):
+    R, _ = random_cluster(0, atoms, hw, 1.5 if atoms == 4 else 1.8)
+    hm = 2 * box / n_base * math.sqrt(3.0)
+    cg = None if coarse is None else (*coarse, hm)
+    kw = dict(h0=h, kappa=h, h_min=h, h_max=hm, coarse=cg)
+    fast = graded_mesh(n_base, -box, box, R, **kw)
+    ref = graded_mesh(n_base, -box, box, R, full_scan=True, **kw)
+    for a, b in zip(fast, ref):
+        assert a.shape == b.shape and np.array_equal(a, b)
+    xyz, tets = fast[0], fast[1]
+    # conforming: every edge's midpoint (if a vertex) would make it hanging; each
+    # interior face is shared by exactly two tets
+    faces = np.sort(np.concatenate([tets[:, [0, 1, 2]], tets[:, [0, 1, 3]], tets[:, [0, 2, 3]],
+                                    tets[:, [1, 2, 3]]]), axis=1)
+    _, counts = np.unique(faces, axis=0, return_counts=True)
+    assert counts.max() <= 2
+    on = np.zeros(len(xyz), bool)
+    for ax in range(3):
+        on |= np.isclose(xyz[:, ax], -box) | np.isclose(xyz[:, ax], box)
+    uf, cnt = np.unique(faces, axis=0, return_counts=True)
+    single = uf[cnt == 1]
+    assert np.all(on[single].all(axis=1)), "a face seen once must lie on the box boundary"
