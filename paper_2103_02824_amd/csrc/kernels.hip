@@ -601,50 +601,42 @@ __global__ void __launch_bounds__(TPB) k_gram_mfma(int64_t n, int N, const doubl
 }
 
 // Gram block U^T Y for 16 < N <= 64 on the FP64 matrix cores: the N x N block
-// is TI x TI tiles of 16 x 16 (orbitals padded to 16 TI), each accumulated by
-// the same v_mfma_f64_16x16x4f64 lane layout as k_gram_mfma, all tiles in
-// registers so that U and Y are read once; the block's four waves are summed
-// through LDS one tile at a time into the block's N x N partial.
+// is TI x TI tiles of 16 x 16 (orbitals padded to 16 TI). A block of TI waves
+// takes GRAM_ROWS rows; wave w owns tile row w, so it accumulates its TI tiles
+// (the same v_mfma_f64_16x16x4f64 lane layout as k_gram_mfma) over all the
+// block's rows and writes them to the block's N x N partial directly. Few
+// accumulator registers per wave keep several waves per SIMD in flight.
 template <int TI>
-__global__ void __launch_bounds__(TPB) k_gram_mfma_tiles(int64_t n, int N, const double* __restrict__ U,
-                                                         const double* __restrict__ Y, double* __restrict__ partial) {
-  __shared__ double sd[TPB / 64][16 * 16];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+__global__ void __launch_bounds__(64 * TI) k_gram_mfma_tiles(int64_t n, int N, const double* __restrict__ U,
+                                                             const double* __restrict__ Y,
+                                                             double* __restrict__ partial) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int col = lane & 15, rq = lane >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * GRAM_ROWS;
   const int64_t r1 = r0 + GRAM_ROWS < n ? r0 + GRAM_ROWS : n;
-  f64x4 acc[TI][TI];
+  f64x4 acc[TI];
 #pragma unroll
-  for (int bi = 0; bi < TI; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < TI; ++bj) acc[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t rb = r0 + 4 * wid; rb < r1; rb += 16) {
+  for (int bj = 0; bj < TI; ++bj) acc[bj] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int ca = 16 * w + col;
+  for (int64_t rb = r0; rb < r1; rb += 4) {
     const int64_t r = rb + rq;
-    double a[TI], b[TI];
-#pragma unroll
-    for (int t = 0; t < TI; ++t) {
-      const int c = 16 * t + col;
-      const bool ok = r < r1 && c < N;
-      a[t] = ok ? U[r * N + c] : 0.0;
-      b[t] = ok ? Y[r * N + c] : 0.0;
-    }
-#pragma unroll
-    for (int bi = 0; bi < TI; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < TI; ++bj) acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
-  }
-#pragma unroll
-  for (int bi = 0; bi < TI; ++bi)
+    const bool okr = r < r1;
+    const double a = (okr && ca < N) ? U[r * N + ca] : 0.0;
+    double b[TI];
 #pragma unroll
     for (int bj = 0; bj < TI; ++bj) {
-      __syncthreads();
+      const int c = 16 * bj + col;
+      b[bj] = (okr && c < N) ? Y[r * N + c] : 0.0;
+    }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) sd[wid][(rq + 4 * v) * 16 + col] = acc[bi][bj][v];
-      __syncthreads();
-      const int i = 16 * bi + (int)(threadIdx.x >> 4), j = 16 * bj + (int)(threadIdx.x & 15);
-      const int o = threadIdx.x;
-      if (i < N && j < N)
-        partial[(int64_t)blockIdx.x * N * N + (int64_t)i * N + j] = (sd[0][o] + sd[1][o]) + (sd[2][o] + sd[3][o]);
+    for (int bj = 0; bj < TI; ++bj) acc[bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[bj], acc[bj], 0, 0, 0);
+  }
+#pragma unroll
+  for (int bj = 0; bj < TI; ++bj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * w + rq + 4 * v, j = 16 * bj + col;
+      if (i < N && j < N) partial[(int64_t)blockIdx.x * N * N + (int64_t)i * N + j] = acc[bj][v];
     }
 }
 
@@ -1240,11 +1232,11 @@ void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double*
   if (N <= 16)
     hipLaunchKernelGGL(k_gram_mfma, g, b, 0, s, n, N, U, Y, partial);
   else if (N <= 32)
-    hipLaunchKernelGGL(k_gram_mfma_tiles<2>, g, b, 0, s, n, N, U, Y, partial);
+    hipLaunchKernelGGL(k_gram_mfma_tiles<2>, g, dim3(128), 0, s, n, N, U, Y, partial);
   else if (N <= 48)
-    hipLaunchKernelGGL(k_gram_mfma_tiles<3>, g, b, 0, s, n, N, U, Y, partial);
+    hipLaunchKernelGGL(k_gram_mfma_tiles<3>, g, dim3(192), 0, s, n, N, U, Y, partial);
   else if (N <= 64)
-    hipLaunchKernelGGL(k_gram_mfma_tiles<4>, g, b, 0, s, n, N, U, Y, partial);
+    hipLaunchKernelGGL(k_gram_mfma_tiles<4>, g, dim3(256), 0, s, n, N, U, Y, partial);
   else
     hipLaunchKernelGGL(k_gram_wide, g, b, 0, s, n, N, U, Y, partial);
 }
