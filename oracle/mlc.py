@@ -22,6 +22,13 @@ the design notes):
    u_i has the largest magnitude (M-normalised), ties to the lower
    eigenvalue, sign fixed so that theta2 > 0.
  * The stopping norm of Algorithm 2 step (c) is the H^1 norm.
+ * Algorithm 2 is a fixed-point iteration in the Hartree coefficients
+   x = (w_H, theta1). Run as printed (x_in <- x_out) it oscillates on
+   multi-electron clusters, so by default the next input is chosen by
+   Anderson (Pulay) mixing of the last few (x_in, x_out - x_in) pairs in the
+   energy inner product <a, b> = a^T (V^T K V) b of W_{H,h}; mixing changes
+   only the path, not the fixed point. inner_mix_history = 0 gives the
+   printed iteration.
  * The V_xc term enters with a plus sign throughout.
 """
 from __future__ import annotations
@@ -47,6 +54,8 @@ class Options:
     inner_maxit: int = 500
     n_extra: int = 8
     solver: str = "lu"          # "lu" (exact) or "pcg"
+    inner_mix_history: int = 6  # Anderson history of the inner iteration; 0 = plain (as printed)
+    inner_mix_beta: float = 0.5
     pcg_rtol: float = 1e-13
 
 
@@ -165,8 +174,29 @@ def select_eigenpair(evals, evecs, n_keep):
     return float(evals[j]), x
 
 
-def inner_scf(prob: Problem, fs: dict, opts: Options):
-    """Algorithm 2 with every matrix assembled on the fine mesh."""
+def anderson_next(x_in, F, hist, G, m, beta):
+    """Next input of a fixed-point iteration x -> x + F(x) by Anderson (Pulay)
+    mixing: with the differences dX, dF of the last m+1 inputs and residuals,
+    gamma minimises |F - dF gamma| in the inner product <a, b> = a^T G b, and
+    x_next = (x_in - dX gamma) + beta (F - dF gamma). With no history (first
+    call) it is the damped step x_in + beta F. hist is a list of (x, F) pairs
+    kept by the caller; this call appends the current pair."""
+    hist.append((x_in.copy(), F.copy()))
+    if len(hist) > m + 1:
+        hist.pop(0)
+    if len(hist) == 1:
+        return x_in + beta * F
+    dX = np.array([hist[k + 1][0] - hist[k][0] for k in range(len(hist) - 1)]).T
+    dF = np.array([hist[k + 1][1] - hist[k][1] for k in range(len(hist) - 1)]).T
+    A = dF.T @ G @ dF
+    r = dF.T @ G @ F
+    gam = np.linalg.lstsq(A, r, rcond=1e-12)[0]
+    return (x_in - dX @ gam) + beta * (F - dF @ gam)
+
+
+def inner_scf(prob: Problem, fs: dict, opts: Options, x_start=None):
+    """Algorithm 2 with every matrix assembled on the fine mesh. x_start: the
+    starting Hartree coefficients (w_H, theta1); default (0, 1)."""
     fine = prob.fine
     P = prob.P
     U, w0, g = fs["U"], fs["w0"], fs["g"]
@@ -178,22 +208,27 @@ def inner_scf(prob: Problem, fs: dict, opts: Options):
         V = sp.hstack([P, sp.csr_matrix(w0[:, None])]).tocsr()
         VKV = (V.T @ prob.K @ V).toarray()
         lift = V.T @ (prob.KIB @ g[fine.bverts])
-    wH = np.zeros(NH)
-    th1 = 1.0 if prob.hartree else 0.0
+    # Hartree coefficients x = (w_H, theta1), starting from (0, 1)
+    x_in = np.zeros(NH + 1)
+    x_in[-1] = 1.0 if prob.hartree else 0.0
+    if x_start is not None:
+        x_in = np.array(x_start, dtype=np.float64)
+    hist = []
     Phi_s = U.copy()
     KpM = prob.K + prob.M
     lam = np.zeros(N)
     thetas = np.zeros(N)
     phiH = np.zeros((NH, N))
+    PMP = (P.T @ prob.M @ P).toarray()
     its = 0
     for s in range(opts.inner_maxit):
         its = s + 1
+        wH, th1 = x_in[:-1], float(x_in[-1])
         # (a) N small linear eigenproblems in S_{H,h} = V_H + span{u_i}
         H = Afix + prob.mass_ii(fine.at_qp(prob.Pfull_c @ wH))
         if prob.hartree:
             H = H + th1 * Mw0
         PHP = (P.T @ H @ P).toarray()
-        PMP = (P.T @ prob.M @ P).toarray()
         Phi_new = np.zeros_like(Phi_s)
         for i in range(N):
             u = U[:, i]
@@ -206,18 +241,26 @@ def inner_scf(prob: Problem, fs: dict, opts: Options):
             phiH[:, i] = x[:-1]
             thetas[i] = x[-1]
             Phi_new[:, i] = P @ x[:-1] + x[-1] * u
-        # (b) Hartree problem in W_{H,h}
+        # (b) Hartree problem in W_{H,h} for the new orbitals
         if prob.hartree:
             rho = prob.density_qp(Phi_new)
             rhs = 4.0 * np.pi * (V.T @ fine.load(rho)[fine.interior]) - lift
-            sol = np.linalg.solve(VKV, rhs)
-            wH, th1 = sol[:-1], float(sol[-1])
+            x_out = np.linalg.solve(VKV, rhs)
+        else:
+            x_out = x_in
         # (c) stopping test in the H^1 norm
         D = Phi_new - Phi_s
         diff = float(np.sqrt(np.einsum("ai,ai->", D, KpM @ D)))
         Phi_s = Phi_new
-        if not prob.hartree or diff < opts.inner_tol:
+        if not prob.hartree or diff < opts.inner_tol or s == opts.inner_maxit - 1:
+            x_in = x_out
             break
+        # next Hartree input: as printed (x_out), or mixed
+        if opts.inner_mix_history > 0:
+            x_in = anderson_next(x_in, x_out - x_in, hist, VKV, opts.inner_mix_history, opts.inner_mix_beta)
+        else:
+            x_in = x_out
+    wH, th1 = x_in[:-1].copy(), float(x_in[-1])
     return dict(lam=lam.copy(), Phi=Phi_s, wH=wH, th1=th1, phiH=phiH, theta2=thetas, inner_iters=its,
                 Afix=Afix, Mw0=Mw0, last_diff=diff)
 

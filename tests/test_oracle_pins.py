@@ -417,3 +417,82 @@ def test_algorithm3_pieces_equal_direct_assembly():
 def test_aufbau_occupations():
     assert list(aufbau(5, 3)) == [2, 2, 1]
     assert list(aufbau(10, 6)) == [2, 2, 2, 2, 2, 0]
+
+
+# ---------------------------------------------------------------- energy and the inner iteration
+def test_energy_at_fixed_point_is_kohn_sham_functional():
+    """The reported energy (sum f_i lambda_i minus the double-counting terms
+    -1/2 int w rho and int rho (eps_xc - v_xc)) equals the Kohn-Sham energy
+    functional of Section 2 evaluated term by term at the self-consistent fine
+    solution, which the method leaves unchanged: kinetic 1/2 sum f_i
+    phi_i^T K phi_i, external int V_ext rho, Hartree 1/2 int w rho with w the
+    fine Hartree potential of rho, exchange-correlation int rho eps_xc(rho).
+    A flipped sign or a lost factor in either double-counting term moves the
+    energy by O(1)."""
+    S = tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=True, n_orbitals=2, seed=5)
+    prob = Problem(S)
+    ref = scf(prob.fine, S, tol=1e-13, maxit=400)
+    st = State(lam=ref["lam"].copy(), Phi=ref["Phi"].copy(), w=ref["w"].copy())
+    res = correction_step(prob, st, Options(inner_tol=1e-13))
+    assert np.max(np.abs(res.state.lam - ref["lam"])) < 1e-9     # a fixed point of the step
+    fine = prob.fine
+    rho = prob.density_qp(ref["Phi"])
+    exc, _ = xc.evaluate(S.xc, rho, S.xalpha)
+    f = prob.f
+    kinetic = 0.5 * sum(f[i] * ref["Phi"][:, i] @ (prob.K @ ref["Phi"][:, i]) for i in range(prob.N))
+    e_ext = fine.integrate(prob.vext_qp * rho)
+    e_h = 0.5 * fine.integrate(fine.at_qp(ref["w"]) * rho)
+    e_xc = fine.integrate(rho * exc)
+    E_direct = kinetic + e_ext + e_h + e_xc
+    assert abs(res.energy - E_direct) < 1e-10, (res.energy, E_direct)
+    assert e_h > 0.1 and abs(e_xc) > 0.1                          # both terms matter at this size
+
+
+def test_anderson_mixing_solves_linear_fixed_point():
+    """The mixing rule of the inner iteration, on a linear map x -> A x + b
+    whose plain iteration diverges (spectral radius > 1): with a history of at
+    least the dimension it reaches the fixed point (I - A)^{-1} b in at most
+    dimension + 2 steps (Anderson mixing is then a Krylov method), in any SPD
+    inner product."""
+    from oracle.mlc import anderson_next
+    rng = np.random.default_rng(7)
+    n = 6
+    A = rng.normal(size=(n, n))
+    A = 1.6 * A / np.max(np.abs(np.linalg.eigvals(A)))
+    b = rng.normal(size=n)
+    G = rng.normal(size=(n, n))
+    G = G @ G.T + n * np.eye(n)
+    xstar = np.linalg.solve(np.eye(n) - A, b)
+    x = np.zeros(n)
+    hist = []
+    for _ in range(n + 2):
+        F = A @ x + b - x
+        x = anderson_next(x, F, hist, G, m=n, beta=0.5)
+    assert np.linalg.norm(x - xstar) < 1e-9 * np.linalg.norm(xstar)
+    # plain iteration from the same start diverges
+    y = np.zeros(n)
+    for _ in range(n + 2):
+        y = A @ y + b
+    assert np.linalg.norm(y - xstar) > np.linalg.norm(xstar)
+
+
+def test_mixed_inner_iteration_has_the_printed_fixed_point():
+    """Mixing changes the path of Algorithm 2, not its fixed point: from the
+    converged mixed result, one printed (unmixed) iteration returns the same
+    orbitals and Hartree coefficients."""
+    S = tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=True, n_orbitals=2, seed=5)
+    prob = Problem(S)
+    st0, _ = initial_state(prob)
+    opts = Options(inner_tol=1e-12)
+    fs = fine_stage(prob, st0, opts)
+    mixed = inner_scf(prob, fs, opts)
+    assert mixed["inner_iters"] < opts.inner_maxit
+    one = Options(inner_tol=0.0, inner_maxit=1, inner_mix_history=0)
+    x0 = np.concatenate([mixed["wH"], [mixed["th1"]]])
+    plain = inner_scf(prob, fs, one, x_start=x0)
+    M = prob.M
+    for i in range(prob.N):
+        a, b_ = mixed["Phi"][:, i], plain["Phi"][:, i]
+        assert np.sqrt((a - b_) @ (M @ (a - b_))) < 1e-9
+    assert np.max(np.abs(plain["lam"] - mixed["lam"])) < 1e-10
+    assert abs(plain["th1"] - mixed["th1"]) < 1e-9
