@@ -71,9 +71,13 @@ enum { MLC_POT_ERF = 0,       /* -sum Z_k erf(|x-R_k|/rc)/|x-R_k|             */
 /* Exchange-correlation (Section 4). */
 enum { MLC_XC_NONE = 0, MLC_XC_LDA = 1 /* Slater + Perdew-Zunger 81 */, MLC_XC_XALPHA = 2 };
 
-/* A P1 tetrahedral mesh of the box [box_lo, box_hi]^3 (host arrays).
- * xyz: n_vertices x 3 doubles; tets: n_tets x 4 vertex indices. */
+/* A tetrahedral mesh of the box [box_lo, box_hi] (host arrays, copied by
+ * mlc_create). order: polynomial degree of the Lagrange elements; 1 (linear,
+ * the space V_h of Section 2) is the one implemented, any other value is
+ * rejected with MLC_ERR_ARG. xyz: n_vertices x 3 doubles; tets: n_tets x 4
+ * vertex indices. */
 typedef struct {
+  int32_t order;
   int64_t n_vertices;
   const double* xyz;
   int64_t n_tets;
@@ -94,7 +98,8 @@ typedef struct {
   int32_t xc;                 /* MLC_XC_* */
   double xalpha;              /* alpha of X-alpha (0.77298 in Section 4) */
   int32_t hartree;            /* 1: Hartree term present, 0: absent */
-  double box_lo, box_hi;      /* homogeneous Dirichlet on the box faces */
+  double box_lo[3], box_hi[3];/* the box prod_k [box_lo[k], box_hi[k]]; homogeneous
+                                 Dirichlet data on its faces (Section 4) */
 } mlc_system;
 
 #define MLC_MAX_ORBITALS 128
@@ -139,6 +144,15 @@ typedef struct {
                            MLC_PC_CHEBYSHEV choose it apart from the step-5
                            solves (same degree and ratio); a batch requires the
                            same choice in all its contexts                    */
+  int32_t inner_mix_history; /* Algorithm 2 is a fixed-point iteration in the
+                           Hartree coefficients x = (w_H, theta1); 0 runs it as
+                           printed (next input = the Hartree potential of the
+                           new orbitals); m > 0 chooses the next input by
+                           Anderson (Pulay) mixing of the last m + 1 inputs and
+                           residuals in the energy inner product of W_{H,h}
+                           (same fixed point, converges where the plain
+                           iteration oscillates); 0..16                       */
+  double inner_mix_beta;  /* Anderson damping in (0, 1]                       */
 } mlc_options;
 
 enum { MLC_PC_JACOBI = 0, MLC_PC_CHEBYSHEV = 1 };
@@ -175,7 +189,9 @@ typedef struct mlc_ctx mlc_ctx;
 /* Fill *opt with defaults: cg_rtol 1e-10, cg_maxit 20000, check_every 25,
  * shift 1, sigma0 1, poisson_rtol 1e-12, inner_maxit 500, inner_tol 1e-10,
  * n_extra 8, reorder 1, time_kernels 0, use_graphs 1, precision FP64,
- * ir_inner_rtol 1e-4, ir_max_outer 30. */
+ * ir_inner_rtol 1e-4, ir_max_outer 30, precond Jacobi, cheb_degree 4,
+ * cheb_ratio 30, hartree_coarse 0, hartree_precond -1, inner_mix_history 6,
+ * inner_mix_beta 0.5. */
 void mlc_options_default(mlc_options* opt);
 
 /* Build a context: validates both meshes (positive volumes, indices in range,
@@ -204,17 +220,27 @@ mlc_status mlc_bind(mlc_ctx* ctx, void* dev_workspace, size_t bytes, void* hip_s
  * interpolated to every fine vertex. tol: L1 norm of the density change. */
 mlc_status mlc_initial_state(mlc_ctx* ctx, double tol, int32_t maxit, int32_t* iters);
 
-/* Set (Lambda^l, Phi^l, w^l) from host arrays: lambda[N], phi[n_dof x N]
- * (caller DoF order), w[n_vertices] (nodal Hartree potential, boundary
- * vertices included). */
-mlc_status mlc_set_state(mlc_ctx* ctx, const double* lambda, const double* phi, const double* w);
+/* Set (Lambda^l, Phi^l, w^l), the input of the next outer step (Algorithm 1
+ * step 4): lambda_host[N] on the host; phi_dev[n_dof x N] (caller DoF order)
+ * and w_dev[n_vertices] (nodal Hartree potential, boundary vertices
+ * included) in device memory of the bound GPU, owned by the caller and
+ * read only during the call. The library copies them into its workspace
+ * (reordering Phi on the device) and synchronises the stream. A non-finite
+ * value in any of the three is MLC_ERR_NONFINITE and the previous state is
+ * kept. */
+mlc_status mlc_set_state(mlc_ctx* ctx, const double* lambda_host, const double* phi_dev, const double* w_dev);
 
 /* One outer step (Algorithm 1 steps 5-7). rep may be null. */
 mlc_status mlc_correction_step(mlc_ctx* ctx, mlc_step_report* rep);
 
-/* Copy the current state to host arrays (any may be null): lambda[N],
- * phi[n_dof x N], w[n_vertices], rho[n_vertices] (nodal density). */
-mlc_status mlc_get_results(mlc_ctx* ctx, double* lambda, double* phi, double* w, double* rho);
+/* The current state (Lambda, Phi, rho, w) after the last step (any pointer
+ * may be null): lambda_host[N] on the host; phi_dev[n_dof x N] (caller DoF
+ * order), rho_dev[n_vertices] (nodal density sum f_i phi_i^2) and
+ * w_dev[n_vertices] (nodal Hartree potential) in caller-owned device memory
+ * of the bound GPU, written on the bound stream by device kernels and
+ * copies (no host round trip); the call synchronises the stream before it
+ * returns. */
+mlc_status mlc_get_results(mlc_ctx* ctx, double* lambda_host, double* phi_dev, double* rho_dev, double* w_dev);
 
 /* Intermediate quantities of the last correction step, for checking each part
  * against an independent implementation. Copies `count` doubles into host
@@ -356,7 +382,11 @@ mlc_status mlc_sample_count(const mlc_ctx* ctx, int64_t* rows);
  * mlc_batch_step: one correction step of every system (same results, to
  * rounding order, as mlc_correction_step on each); reports[0..count) as in
  * mlc_correction_step (t_fine_ms and t_recon_ms of a system span the batch's
- * phases); br may be NULL. On error the message names the system. */
+ * phases); br may be NULL. On error the message names the first failing
+ * system. Errors found before the reconstruction (arguments, HIP, CG
+ * breakdown, non-finite augmented solutions) leave every system's state as
+ * it was; MLC_ERR_NOT_CONVERGED updates every system's state to the last
+ * iterate (each system's report is filled), like mlc_correction_step. */
 typedef struct mlc_batch mlc_batch;
 
 typedef struct {

@@ -16,7 +16,9 @@ exactly one base tetrahedron, so the base mesh is a nested coarse mesh.
 """
 from __future__ import annotations
 
+import hashlib
 import itertools
+import os
 
 import numpy as np
 from scipy.spatial import cKDTree
@@ -228,16 +230,39 @@ def graded_mesh(n_base, lo, hi, centres, h0, kappa, h_min, h_max=np.inf, coarse=
     every tet for hanging edges after each bisection (the reference for the
     restricted search, which must give the same mesh).
     """
+    C = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
+    cache = _cache_path(n_base, lo, hi, C, h0, kappa, h_min, h_max, coarse)
+    if cache is not None and os.path.exists(cache):
+        with np.load(cache, allow_pickle=False) as z:
+            return z["xyz"], z["tets"], z["cxyz"], z["ctets"]
     bxyz, btets = kuhn_mesh(n_base, lo, hi)
     B = _Bisector(bxyz, btets, full_scan=full_scan)
-    C = np.asarray(centres, dtype=np.float64).reshape(-1, 3)
     if coarse is not None:
         _refine_to(B, C, *coarse, progress=progress)
     cxyz = B.coords().copy()
     ctets = B.tets.copy()
     _refine_to(B, C, h0, kappa, h_min, h_max, progress=progress)
     X = B.coords()
-    return X.copy(), B.tets.copy(), cxyz, ctets
+    out = (X.copy(), B.tets.copy(), cxyz, ctets)
+    if cache is not None and not full_scan:
+        tmp = cache + ".tmp.npz"
+        np.savez(tmp, xyz=out[0], tets=out[1], cxyz=out[2], ctets=out[3])
+        os.replace(tmp, cache)
+    return out
+
+
+def _cache_path(*params):
+    """File of a generated mesh in the directory named by the environment
+    variable MLC_MESH_CACHE (None when it is unset): generating the largest
+    meshes takes minutes, and a second process on the same machine can load
+    them instead. The name is a hash of every generation parameter."""
+    d = os.environ.get("MLC_MESH_CACHE")
+    if not d:
+        return None
+    os.makedirs(d, exist_ok=True)
+    h = hashlib.sha256(repr([np.asarray(p).tolist() if isinstance(p, np.ndarray) else p
+                             for p in params]).encode()).hexdigest()[:24]
+    return os.path.join(d, f"graded_{h}.npz")
 
 
 def boundary_mask(xyz, lo, hi, tol=1e-12):

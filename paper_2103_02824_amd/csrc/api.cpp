@@ -92,6 +92,13 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->rho_nodal = w.take<double>(nv);
   d->Pk = w.take<int32_t>(4 * n);
   d->Pw = w.take<double>(4 * n);
+  d->rch_seg = w.take<int32_t>((int64_t)c->rch_seg.size());
+  d->rseg_ptr = w.take<int32_t>((int64_t)c->rseg_ptr.size());
+  d->rent_row = w.take<int32_t>((int64_t)c->rent_row.size());
+  d->rent_w = w.take<double>((int64_t)c->rent_w.size());
+  d->kseg_ptr = w.take<int32_t>((int64_t)c->kseg_ptr.size());
+  d->kseg = w.take<int32_t>((int64_t)c->kseg.size());
+  d->rpart = w.take<double>((int64_t)c->kseg.size() * std::max<int64_t>(N, 1));
   d->PTptr = w.take<int32_t>(nH + 1);
   d->PTidx = w.take<int32_t>((int64_t)c->PTidx.size());
   d->PTw = w.take<double>((int64_t)c->PTw.size());
@@ -138,6 +145,8 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->gsel = w.take<double>(4 * N);
   d->gdots = w.take<double>(5 * N);
   d->d2v = w.take<int32_t>(n);
+  d->dof_user = w.take<int32_t>(n);
+  d->chk = w.take<int32_t>(4);
   d->lmax = w.take<double>(2);
   if (c->opt.hartree_coarse && c->hartree) {
     d->KHinv = w.take<double>(nH * nH);
@@ -192,6 +201,12 @@ mlc_status upload_and_init(mlc_ctx* c) {
   HIPCHK(up(s, d.diag_slot, c->diag_slot));
   HIPCHK(up(s, d.Pk, c->Pk));
   HIPCHK(up(s, d.Pw, c->Pw));
+  HIPCHK(up(s, d.rch_seg, c->rch_seg));
+  HIPCHK(up(s, d.rseg_ptr, c->rseg_ptr));
+  HIPCHK(up(s, d.rent_row, c->rent_row));
+  HIPCHK(up(s, d.rent_w, c->rent_w));
+  HIPCHK(up(s, d.kseg_ptr, c->kseg_ptr));
+  HIPCHK(up(s, d.kseg, c->kseg));
   HIPCHK(up(s, d.PTptr, c->PTptr));
   HIPCHK(up(s, d.PTidx, c->PTidx));
   HIPCHK(up(s, d.PTw, c->PTw));
@@ -202,6 +217,7 @@ mlc_status upload_and_init(mlc_ctx* c) {
   HIPCHK(up(s, d.occ, c->occ));
   HIPCHK(up(s, d.RZ, RZ));
   HIPCHK(up(s, d.d2v, c->d2v));
+  HIPCHK(up(s, d.dof_user, c->dof_user));
   HIPCHK(hipMemsetAsync(d.w, 0, sizeof(double) * c->nv, s));
   HIPCHK(hipMemsetAsync(d.g, 0, sizeof(double) * c->nv, s));
   HIPCHK(hipMemsetAsync(d.small, 0, sizeof(double) * small_len(c->nH, c->N), s));
@@ -435,6 +451,8 @@ void mlc_options_default(mlc_options* o) {
   o->cheb_ratio = 30.0;
   o->hartree_coarse = 0;
   o->hartree_precond = -1;
+  o->inner_mix_history = 6;
+  o->inner_mix_beta = 0.5;
 }
 
 mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys, const mlc_options* opt,
@@ -446,7 +464,10 @@ mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_sy
   if (sys->potential < 0 || sys->potential > 2 || sys->xc < 0 || sys->xc > 2) return MLC_ERR_ARG;
   if (sys->n_nuclei < 0 || (sys->n_nuclei > 0 && (!sys->R || !sys->Z))) return MLC_ERR_ARG;
   if (sys->potential != MLC_POT_HARMONIC && sys->n_nuclei == 0) return MLC_ERR_ARG;
-  if (!(sys->box_hi > sys->box_lo)) return MLC_ERR_ARG;
+  for (int k = 0; k < 3; ++k)
+    if (!(sys->box_hi[k] > sys->box_lo[k]) || !std::isfinite(sys->box_lo[k]) || !std::isfinite(sys->box_hi[k]))
+      return MLC_ERR_ARG;
+  if (fine->order != 1 || coarse->order != 1) return MLC_ERR_ARG;
   if (sys->potential == MLC_POT_ERF && !(sys->rc > 0)) return MLC_ERR_ARG;
   for (int i = 0; i < sys->n_orbitals; ++i)
     if (!(sys->occupations[i] >= 0.0) || !std::isfinite(sys->occupations[i])) return MLC_ERR_ARG;
@@ -464,7 +485,9 @@ mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_sy
       (c->opt.hartree_precond != -1 && c->opt.hartree_precond != MLC_PC_JACOBI &&
        c->opt.hartree_precond != MLC_PC_CHEBYSHEV) ||
       ((c->opt.precond == MLC_PC_CHEBYSHEV || hartree_pc(c->opt) == MLC_PC_CHEBYSHEV) &&
-       (c->opt.cheb_degree < 2 || c->opt.cheb_degree > 16 || !(c->opt.cheb_ratio > 1.0)))) {
+       (c->opt.cheb_degree < 2 || c->opt.cheb_degree > 16 || !(c->opt.cheb_ratio > 1.0))) ||
+      c->opt.inner_mix_history < 0 || c->opt.inner_mix_history > 16 ||
+      !(c->opt.inner_mix_beta > 0.0 && c->opt.inner_mix_beta <= 1.0)) {
     delete c;
     return MLC_ERR_ARG;
   }
@@ -479,8 +502,10 @@ mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_sy
   c->xc = sys->xc;
   c->xalpha = sys->xalpha;
   c->hartree = sys->hartree ? 1 : 0;
-  c->lo = sys->box_lo;
-  c->hi = sys->box_hi;
+  for (int k = 0; k < 3; ++k) {
+    c->lo[k] = sys->box_lo[k];
+    c->hi[k] = sys->box_hi[k];
+  }
   mlc_status st = build_mesh(c, fine, coarse);
   if (st != MLC_OK) {
     // keep the message reachable for the caller through a temporary context
@@ -563,19 +588,24 @@ mlc_status mlc_initial_state(mlc_ctx* c, double tol, int32_t maxit, int32_t* ite
   return st;
 }
 
-mlc_status mlc_set_state(mlc_ctx* c, const double* lambda, const double* phi, const double* w) {
-  if (!c || !lambda || !phi || !w) return MLC_ERR_ARG;
+mlc_status mlc_set_state(mlc_ctx* c, const double* lambda, const double* phi_dev, const double* w_dev) {
+  if (!c || !lambda || !phi_dev || !w_dev) return MLC_ERR_ARG;
   if (!c->bound) return fail(c, MLC_ERR_STATE, "mlc_bind first");
   const int N = c->N;
-  std::vector<double> p(c->n * N);
-  for (int64_t a = 0; a < c->n; ++a)
-    for (int i = 0; i < N; ++i) p[a * N + i] = phi[(int64_t)c->dof_user[a] * N + i];
   for (int i = 0; i < N; ++i)
-    if (!std::isfinite(lambda[i])) return fail(c, MLC_ERR_ARG, "non-finite eigenvalue");
-  hipError_t e = hipMemcpyAsync(c->d.Phi, p.data(), sizeof(double) * p.size(), hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->d.w, w, sizeof(double) * c->nv, hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "mlc_set_state upload");
+    if (!std::isfinite(lambda[i])) return fail(c, MLC_ERR_NONFINITE, "non-finite eigenvalue");
+  hipStream_t s = c->stream;
+  auto& d = c->d;
+  // the caller's arrays are checked before anything of the state is overwritten
+  int32_t bad = 0;
+  launch_count_nonfinite(s, c->n * N, phi_dev, c->nv, w_dev, d.chk);
+  HIPCHK(hipMemcpyAsync(&bad, d.chk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (bad) return fail(c, MLC_ERR_NONFINITE, "non-finite value in phi or w");
+  launch_permute_rows(s, c->n, N, d.dof_user, phi_dev, d.Phi, /*gather=*/1);
+  HIPCHK(hipMemcpyAsync(d.w, w_dev, sizeof(double) * c->nv, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
   c->lam.assign(lambda, lambda + N);
   c->has_state = true;
   c->has_step = false;
@@ -588,28 +618,18 @@ mlc_status mlc_correction_step(mlc_ctx* c, mlc_step_report* rep) {
   return fine_stage_and_step(c, rep);
 }
 
-mlc_status mlc_get_results(mlc_ctx* c, double* lambda, double* phi, double* w, double* rho) {
+mlc_status mlc_get_results(mlc_ctx* c, double* lambda, double* phi_dev, double* rho_dev, double* w_dev) {
   if (!c) return MLC_ERR_ARG;
   if (!c->bound || !c->has_state) return fail(c, MLC_ERR_STATE, "no state");
   const int N = c->N;
   hipStream_t s = c->stream;
+  auto& d = c->d;
   if (lambda) std::copy(c->lam.begin(), c->lam.end(), lambda);
-  if (phi) {
-    std::vector<double> h(c->n * N);
-    HIPCHK(hipMemcpyAsync(h.data(), c->d.Phi, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int64_t a = 0; a < c->n; ++a)
-      for (int i = 0; i < N; ++i) phi[(int64_t)c->dof_user[a] * N + i] = h[a * N + i];
-  }
-  if (w) {
-    HIPCHK(hipMemcpyAsync(w, c->d.w, sizeof(double) * c->nv, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-  }
-  if (rho) {
-    launch_rho_nodal(s, c->nv, c->d.v2d, c->d.Phi, N, c->d.occ, c->d.rho_nodal);
-    HIPCHK(hipMemcpyAsync(rho, c->d.rho_nodal, sizeof(double) * c->nv, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-  }
+  if (phi_dev) launch_permute_rows(s, c->n, N, d.dof_user, d.Phi, phi_dev, /*gather=*/0);
+  if (rho_dev) launch_rho_nodal(s, c->nv, d.v2d, d.Phi, N, d.occ, rho_dev);
+  if (w_dev) HIPCHK(hipMemcpyAsync(w_dev, d.w, sizeof(double) * c->nv, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
   return MLC_OK;
 }
 

@@ -674,12 +674,20 @@ mlc_status mlc_batch_step(mlc_batch* b, mlc_step_report* reports, mlc_batch_repo
   for (int i = 0; i < K; ++i)
     if ((st = phase_recon_copy(*runs[i])) != MLC_OK) return sys_fail(b, i, st);
   BCHK(hipStreamSynchronize(s));
-  mlc_status worst = MLC_OK;
+  // every system's device state was rewritten by its reconstruction, so every
+  // system's host state (eigenvalues, coarse coefficients) is brought up to
+  // date before an error is returned; the first failing system is reported
+  mlc_status worst = MLC_OK, first_err = MLC_OK;
+  int first_bad = -1;
   for (int i = 0; i < K; ++i) {
     st = phase_finish(*runs[i], reports ? &reports[i] : nullptr);
-    if (st < 0) return sys_fail(b, i, st);
+    if (st < 0 && first_bad < 0) {
+      first_bad = i;
+      first_err = st;
+    }
     if (st > 0) worst = st;
   }
+  if (first_bad >= 0) return sys_fail(b, first_bad, first_err);
   if (br) {
     std::memset(br, 0, sizeof(*br));
     br->n_systems = K;

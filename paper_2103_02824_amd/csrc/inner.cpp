@@ -86,6 +86,103 @@ void symv(const std::vector<double>& A, int64_t n, const double* x, double* y) {
   for (int64_t i = 0; i < n; ++i) y[i] = dot(&A[i * n], x, n);
 }
 
+// Minimum-norm least-squares solution of the symmetric positive semidefinite
+// system A x = r (order m <= 16) by cyclic Jacobi eigen-decomposition:
+// eigenvalues below 1e-12 of the largest are treated as zero.
+void sym_lstsq(std::vector<double> A, int m, const std::vector<double>& r, std::vector<double>& x) {
+  std::vector<double> V(m * m, 0.0);
+  for (int i = 0; i < m; ++i) V[i * m + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) (i == j ? tot : off) += A[i * m + j] * A[i * m + j];
+    if (off <= 1e-30 * (tot + off) || off == 0.0) break;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        double apq = A[p * m + q];
+        if (apq == 0.0) continue;
+        double th = 0.5 * (A[q * m + q] - A[p * m + p]) / apq;
+        double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < m; ++k) {  // A <- A J
+          double akp = A[k * m + p], akq = A[k * m + q];
+          A[k * m + p] = cs * akp - sn * akq;
+          A[k * m + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < m; ++k) {  // A <- J^T A
+          double apk = A[p * m + k], aqk = A[q * m + k];
+          A[p * m + k] = cs * apk - sn * aqk;
+          A[q * m + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < m; ++k) {
+          double vkp = V[k * m + p], vkq = V[k * m + q];
+          V[k * m + p] = cs * vkp - sn * vkq;
+          V[k * m + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  double emax = 0.0;
+  for (int i = 0; i < m; ++i) emax = std::max(emax, std::fabs(A[i * m + i]));
+  x.assign(m, 0.0);
+  for (int k = 0; k < m; ++k) {
+    double ev = A[k * m + k];
+    if (!(std::fabs(ev) > 1e-12 * emax)) continue;
+    double c = 0.0;
+    for (int i = 0; i < m; ++i) c += V[i * m + k] * r[i];
+    c /= ev;
+    for (int i = 0; i < m; ++i) x[i] += c * V[i * m + k];
+  }
+}
+
+// Anderson (Pulay) mixing of a fixed-point iteration x -> x + F(x): with the
+// differences dX, dF of the last m + 1 inputs and residuals, gamma minimises
+// |F - dF gamma|_G, and the next input is (x - dX gamma) + beta (F - dF gamma);
+// the first call takes the damped step x + beta F. G is applied by the caller
+// (GF = G F) so that the normal equations need no further products with G.
+struct Anderson {
+  int m = 0;
+  double beta = 1.0;
+  std::vector<std::vector<double>> X, F, GF;
+  void next(std::vector<double>& x, const std::vector<double>& f, const std::vector<double>& gf) {
+    X.push_back(x);
+    F.push_back(f);
+    GF.push_back(gf);
+    if ((int)X.size() > m + 1) {
+      X.erase(X.begin());
+      F.erase(F.begin());
+      GF.erase(GF.begin());
+    }
+    const size_t len = x.size();
+    const int k = (int)X.size() - 1;
+    if (k == 0) {
+      for (size_t a = 0; a < len; ++a) x[a] += beta * f[a];
+      return;
+    }
+    std::vector<double> A(k * k), r(k), gam;
+    for (int i = 0; i < k; ++i) {
+      double ri = 0.0;
+      for (size_t a = 0; a < len; ++a) ri += (GF[i + 1][a] - GF[i][a]) * f[a];
+      r[i] = ri;
+      for (int j = 0; j < k; ++j) {
+        double aij = 0.0;
+        for (size_t a = 0; a < len; ++a) aij += (F[i + 1][a] - F[i][a]) * (GF[j + 1][a] - GF[j][a]);
+        A[i * k + j] = aij;
+      }
+    }
+    for (int i = 0; i < k; ++i)  // symmetrise the rounding
+      for (int j = i + 1; j < k; ++j) A[i * k + j] = A[j * k + i] = 0.5 * (A[i * k + j] + A[j * k + i]);
+    sym_lstsq(A, k, r, gam);
+    for (size_t a = 0; a < len; ++a) {
+      double dxg = 0.0, dfg = 0.0;
+      for (int i = 0; i < k; ++i) {
+        dxg += (X[i + 1][a] - X[i][a]) * gam[i];
+        dfg += (F[i + 1][a] - F[i][a]) * gam[i];
+      }
+      x[a] = (x[a] - dxg) + beta * (f[a] - dfg);
+    }
+  }
+};
+
 }  // namespace
 
 // A_{H,2}(w) = sum_m T_{jkm} w_m added into dense A (scale s)
@@ -178,13 +275,31 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
   double th1 = hart ? 1.0 : 0.0;
   std::vector<double> AH, Cm, KpM(nH * nH);
   for (int64_t k = 0; k < nH * nH; ++k) KpM[k] = KHd[k] + MHd[k];
-  std::vector<double> a(nH), Aa(nH), b(nH), u(nH), y(nH), tmp(nH), fH(nH);
+  std::vector<double> tmp(nH), fH(nH);
   Tridiag Tr;
+  // per orbital, fixed in the inner loop: a_i = M_H^{-1} P^T M u_i and the
+  // M-norm^2 of the part of u_i M-orthogonal to V_H, gamma_i - c_i . a_i
+  std::vector<double> aM(nH * N), gpv(N);
+  for (int i = 0; i < N; ++i) {
+    double* ai = &aM[(int64_t)i * nH];
+    for (int64_t k = 0; k < nH; ++k) ai[k] = fb.ptM[k * N + i];
+    forward(L, nH, ai);
+    backward(L, nH, ai);
+    double ca = 0.0;
+    for (int64_t k = 0; k < nH; ++k) ca += fb.ptM[k * N + i] * ai[k];
+    const double gam = fb.utM[i * N + i];
+    gpv[i] = gam - ca;
+    if (!(gpv[i] > 1e-14 * std::fabs(gam))) return fail(c, MLC_ERR_NONFINITE, "auxiliary solution lies in the coarse space");
+  }
   int n_keep = (int)std::min<int64_t>(nH + 1, (int64_t)N + c->opt.n_extra);
   int its = 0;
   double diff = 0.0;
   mlc_status st = MLC_OK;
   int maxit = std::max(1, c->opt.inner_maxit);
+  std::vector<double> xin(nH + 1), xout(nH + 1, 0.0), fres(nH + 1), gres(nH + 1);
+  Anderson mix;
+  mix.m = c->opt.inner_mix_history;
+  mix.beta = c->opt.inner_mix_beta;
   for (int s = 0; s < maxit; ++s) {
     its = s + 1;
     // (a) A_H = A_{H,1} + A_{H,4} + A_{H,2}(w_H) + theta1 A_{H,3}
@@ -195,54 +310,56 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
     }
     congruence(L, AH, nH, Cm);
     tridiagonalize(Cm, nH, Tr);
-    for (int i = 0; i < N; ++i) {
-      // border of orbital i (eqs. bdef, betadef)
-      ah4_apply(i, wH.data(), tmp.data());
-      double beta = fb.utF[i * N + i] + th1 * fb.utW[i * N + i];
-      for (int64_t k = 0; k < nH; ++k) {
-        b[k] = fb.ptF[k * N + i] + (hart ? tmp[k] + th1 * fb.ptW[k * N + i] : 0.0);
-        beta += hart ? rhsv[k * N + i] * wH[k] : 0.0;
-      }
-      double gam = fb.utM[i * N + i];
-      for (int64_t k = 0; k < nH; ++k) a[k] = fb.ptM[k * N + i];
-      forward(L, nH, a.data());
-      backward(L, nH, a.data());  // a = M_H^{-1} c
-      symv(AH, nH, a.data(), Aa.data());
-      double ba = dot(b.data(), a.data(), nH), aAa = dot(a.data(), Aa.data(), nH);
-      double ca = 0.0;
-      for (int64_t k = 0; k < nH; ++k) ca += fb.ptM[k * N + i] * a[k];
-      double gp = gam - ca;
-      double bp = beta - 2.0 * ba + aAa;
-      if (!(gp > 1e-14 * std::fabs(gam))) return fail(c, MLC_ERR_NONFINITE, "auxiliary solution lies in the coarse space");
-      double sg = std::sqrt(gp);
-      for (int64_t k = 0; k < nH; ++k) u[k] = b[k] - Aa[k];
-      forward(L, nH, u.data());
-      for (int64_t k = 0; k < nH; ++k) u[k] /= sg;
-      apply_QT(Tr, u.data());
-      double alpha = bp / gp;
-      std::vector<double> ev = lowest_eigenvalues(Tr, u.data(), alpha, n_keep);
-      int jsel = 0;
-      double wbest = -1.0;
-      for (int j = 0; j < n_keep; ++j) {
-        double wj = border_weight(Tr, u.data(), alpha, ev[j]);
-        if (wj > wbest) {
-          wbest = wj;
-          jsel = j;
+    // the N augmented problems are independent given A_H: one orbital per thread
+    int bad = 0;
+#pragma omp parallel if (N > 1)
+    {
+      std::vector<double> b(nH), Aa(nH), u(nH), y(nH), tmp(nH);
+#pragma omp for schedule(dynamic, 1) reduction(+ : bad)
+      for (int i = 0; i < N; ++i) {
+        const double* ai = &aM[(int64_t)i * nH];
+        // border of orbital i (eqs. bdef, betadef)
+        if (hart) ah4_apply(i, wH.data(), tmp.data());
+        double beta = fb.utF[i * N + i] + th1 * fb.utW[i * N + i];
+        for (int64_t k = 0; k < nH; ++k) {
+          b[k] = fb.ptF[k * N + i] + (hart ? tmp[k] + th1 * fb.ptW[k * N + i] : 0.0);
+          beta += hart ? rhsv[k * N + i] * wH[k] : 0.0;
         }
+        for (int64_t k = 0; k < nH; ++k) Aa[k] = dot(&AH[k * nH], ai, nH);
+        double ba = dot(b.data(), ai, nH), aAa = dot(ai, Aa.data(), nH);
+        const double gp = gpv[i], sg = std::sqrt(gp);
+        double bp = beta - 2.0 * ba + aAa;
+        for (int64_t k = 0; k < nH; ++k) u[k] = b[k] - Aa[k];
+        forward(L, nH, u.data());
+        for (int64_t k = 0; k < nH; ++k) u[k] /= sg;
+        apply_QT(Tr, u.data());
+        double alpha = bp / gp;
+        std::vector<double> ev = lowest_eigenvalues(Tr, u.data(), alpha, n_keep);
+        int jsel = 0;
+        double wbest = -1.0;
+        for (int j = 0; j < n_keep; ++j) {
+          double wj = border_weight(Tr, u.data(), alpha, ev[j]);
+          if (wj > wbest) {
+            wbest = wj;
+            jsel = j;
+          }
+        }
+        double sv;
+        eigenvector(Tr, u.data(), alpha, ev[jsel], y.data(), &sv);
+        if (sv < 0) {
+          sv = -sv;
+          for (int64_t k = 0; k < nH; ++k) y[k] = -y[k];
+        }
+        apply_Q(Tr, y.data());
+        backward(L, nH, y.data());
+        double t2 = sv / sg;
+        for (int64_t k = 0; k < nH; ++k) phiH[k * N + i] = y[k] - t2 * ai[k];
+        theta2[i] = t2;
+        lam[i] = ev[jsel];
+        bad += !std::isfinite(t2) || !std::isfinite(lam[i]);
       }
-      double sv;
-      eigenvector(Tr, u.data(), alpha, ev[jsel], y.data(), &sv);
-      if (sv < 0) {
-        sv = -sv;
-        for (int64_t k = 0; k < nH; ++k) y[k] = -y[k];
-      }
-      apply_Q(Tr, y.data());
-      backward(L, nH, y.data());
-      double t2 = sv / sg;
-      for (int64_t k = 0; k < nH; ++k) phiH[k * N + i] = y[k] - t2 * a[k];
-      theta2[i] = t2;
-      lam[i] = ev[jsel];
     }
+    if (bad) return fail(c, MLC_ERR_NONFINITE, "non-finite solution of an augmented problem");
     // (b) Hartree problem in W_{H,h} (eqs. Hartree_H_h, fH, gdef with the
     //     factor 2, the theta2^2 term and the occupations)
     if (hart) {
@@ -286,8 +403,8 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
       forward(c->h_Kh_chol, nH, r1.data());
       backward(c->h_Kh_chol, nH, r1.data());
       double t1 = (r2 - dot(fb.d.data(), r1.data(), nH)) / schur;
-      for (int64_t k = 0; k < nH; ++k) wH[k] = r1[k] - yd[k] * t1;
-      th1 = t1;
+      for (int64_t k = 0; k < nH; ++k) xout[k] = r1[k] - yd[k] * t1;
+      xout[nH] = t1;
     }
     // (c) ||Phi^{s+1} - Phi^s||_{H^1} in the basis [P, u_i]
     double d2 = 0.0;
@@ -303,8 +420,27 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
     diff = std::sqrt(std::max(d2, 0.0));
     phiH_old = phiH;
     theta2_old = theta2;
-    if (!hart || diff < c->opt.inner_tol) break;
-    if (s == maxit - 1) st = MLC_WARN_INNER_MAXIT;
+    if (!hart) break;
+    const bool done = diff < c->opt.inner_tol;
+    if (!done && s == maxit - 1) st = MLC_WARN_INNER_MAXIT;
+    if (done || s == maxit - 1 || c->opt.inner_mix_history <= 0) {
+      // output (and, unmixed, the next input): the Hartree potential of the new orbitals
+      std::copy(xout.begin(), xout.begin() + nH, wH.begin());
+      th1 = xout[nH];
+      if (done || s == maxit - 1) break;
+      continue;
+    }
+    // next input by Anderson mixing in the energy inner product of W_{H,h}:
+    // G [x_h; x_t] = [K_H x_h + d x_t; d.x_h + zeta x_t]
+    std::copy(wH.begin(), wH.end(), xin.begin());
+    xin[nH] = th1;
+    for (int64_t k = 0; k <= nH; ++k) fres[k] = xout[k] - xin[k];
+    symv(KHd, nH, fres.data(), gres.data());
+    for (int64_t k = 0; k < nH; ++k) gres[k] += fb.d[k] * fres[nH];
+    gres[nH] = dot(fb.d.data(), fres.data(), nH) + fb.zeta * fres[nH];
+    mix.next(xin, fres, gres);
+    std::copy(xin.begin(), xin.begin() + nH, wH.begin());
+    th1 = xin[nH];
   }
   out.lam = lam;
   out.phiH = phiH;

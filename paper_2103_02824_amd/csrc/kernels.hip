@@ -11,6 +11,7 @@
 // run to run. The kernels of this file use no atomics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "mlc_internal.h"
@@ -561,6 +562,61 @@ __global__ void __launch_bounds__(64 * RW) k_restrict_lanes(int64_t nH, int N, c
   }
 }
 
+// Chunked restriction P^T Y. Each block takes one chunk of RESTRICT_CHUNK
+// consecutive fine rows: it copies the chunk's rows of Y (contiguous, RCOL
+// columns at a time) into LDS with coalesced loads, then each wavefront sums
+// the chunk's segments (all entries of one coarse DoF within the chunk, in
+// row order) with a lane per column, reading the rows from LDS. Every row of Y
+// is read from HBM once; the four coarse parents of a row read it from LDS.
+constexpr int RCOL = 64;
+__global__ void __launch_bounds__(TPB) k_restrict_chunks(int64_t n, int N, const int32_t* __restrict__ rch_seg,
+                                                         const int32_t* __restrict__ rseg_ptr,
+                                                         const int32_t* __restrict__ rent_row,
+                                                         const double* __restrict__ rent_w,
+                                                         const double* __restrict__ Y, double* __restrict__ part) {
+  __shared__ double yl[RESTRICT_CHUNK * RCOL];
+  const int64_t r0 = (int64_t)blockIdx.x * RESTRICT_CHUNK;
+  const int nr = (int)(n - r0 < RESTRICT_CHUNK ? n - r0 : RESTRICT_CHUNK);
+  const int s0 = rch_seg[blockIdx.x], s1 = rch_seg[blockIdx.x + 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < N; c0 += RCOL) {
+    const int nc = N - c0 < RCOL ? N - c0 : RCOL;
+    // stage rows r0 .. r0 + nr of columns c0 .. c0 + nc: thread t takes
+    // element (t / nc, t % nc) of the tile, so consecutive threads read
+    // consecutive addresses within a row and the rows follow each other
+    const double* src = Y + r0 * N + c0;
+    for (int t = threadIdx.x; t < nr * nc; t += TPB) {
+      const int r = t / nc, q = t - r * nc;
+      yl[r * RCOL + q] = src[(int64_t)r * N + q];
+    }
+    __syncthreads();
+    for (int g = s0 + wid; g < s1; g += TPB / 64) {
+      const int e0 = rseg_ptr[g], e1 = rseg_ptr[g + 1];
+      double acc = 0.0;
+      if (lane < nc)
+        for (int e = e0; e < e1; ++e) acc += rent_w[e] * yl[rent_row[e] * RCOL + lane];
+      if (lane < nc) part[(int64_t)g * N + c0 + lane] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// out[k, c] = sum of the segment partials of coarse DoF k, in chunk order: one
+// wavefront per coarse DoF, a lane per column.
+__global__ void __launch_bounds__(TPB) k_restrict_sum(int64_t nH, int N, const int32_t* __restrict__ kseg_ptr,
+                                                      const int32_t* __restrict__ kseg,
+                                                      const double* __restrict__ part, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= nH) return;
+  const int j0 = kseg_ptr[k], j1 = kseg_ptr[k + 1];
+  for (int c = lane; c < N; c += 64) {
+    double acc = 0.0;
+    for (int j = j0; j < j1; ++j) acc += part[(int64_t)kseg[j] * N + c];
+    out[k * N + c] = acc;
+  }
+}
+
 // Gram block U^T Y (N x N) on the FP64 matrix cores (N <= 16): orbitals are
 // padded to 16, rows are the reduction index. One v_mfma_f64_16x16x4f64 per 4
 // rows: lane l feeds U[row 4q + l/16][orbital l%16] as A (16 x 4, orbital x
@@ -925,6 +981,42 @@ __global__ void __launch_bounds__(TPB) k_rho_nodal(int64_t nv, const int32_t* __
   rho[v] = s;
 }
 
+// Row permutation of an n x N block (orbital fastest): gather reads row
+// perm[a] of in into row a of out, scatter writes row a of in to row perm[a].
+__global__ void __launch_bounds__(TPB) k_permute_rows(int64_t n, int N, const int32_t* __restrict__ perm,
+                                                      const double* __restrict__ in, double* __restrict__ out,
+                                                      int gather) {
+  int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= n * N) return;
+  int64_t a = t / N;
+  int i = (int)(t - a * N);
+  int64_t pa = perm[a];
+  if (gather)
+    out[t] = in[pa * N + i];
+  else
+    out[pa * N + i] = in[t];
+}
+
+// out[a] = w[d2v[a]]: the interior (DoF) values of a nodal vector.
+__global__ void __launch_bounds__(TPB) k_gather_nodal(int64_t n, const int32_t* __restrict__ d2v,
+                                                      const double* __restrict__ w, double* __restrict__ out) {
+  int64_t a = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (a < n) out[a] = w[d2v[a]];
+}
+
+// Count of non-finite values in two arrays (grid-stride; one atomic per wavefront).
+__global__ void __launch_bounds__(TPB) k_count_nonfinite(int64_t na, const double* __restrict__ a, int64_t nb_,
+                                                         const double* __restrict__ b, int32_t* __restrict__ cnt) {
+  int bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * TPB;
+  for (int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x; t < na + nb_; t += stride) {
+    double v = t < na ? a[t] : b[t - na];
+    bad += !isfinite(v);
+  }
+  for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o);
+  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(cnt, bad);
+}
+
 // Energy pieces per block: [int rho, int (-1/2 w rho + rho (eps_xc(rho) - v_xc^l))]
 __global__ void __launch_bounds__(TPB) k_energy(int64_t nt, const int32_t* __restrict__ tets,
                                                 const int32_t* __restrict__ v2d, const double* __restrict__ Phi,
@@ -1220,6 +1312,16 @@ void launch_reduce_cols(hipStream_t s, int N, int nblk, const double* partial, d
 void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, double* X) {
   hipLaunchKernelGGL(k_normalize_cols, dim3(nb(n * N)), dim3(TPB), 0, s, n * N, N, sc, X);
 }
+void launch_restrict_chunks(hipStream_t s, int64_t n, int64_t nH, int N, const Dev& d, const double* Y,
+                            double* out) {
+  const int64_t nch = (n + RESTRICT_CHUNK - 1) / RESTRICT_CHUNK;
+  if (nch > 0)
+    hipLaunchKernelGGL(k_restrict_chunks, dim3((unsigned)nch), dim3(TPB), 0, s, n, N, d.rch_seg, d.rseg_ptr,
+                       d.rent_row, d.rent_w, Y, d.rpart);
+  if (nH > 0)
+    hipLaunchKernelGGL(k_restrict_sum, dim3((unsigned)((nH + TPB / 64 - 1) / (TPB / 64))), dim3(TPB), 0, s, nH, N,
+                       d.kseg_ptr, d.kseg, d.rpart, out);
+}
 void launch_restrict(hipStream_t s, int64_t nH, int N, const int32_t* PTptr, const int32_t* PTidx, const double* PTw,
                      const double* Y, double* out) {
   if (N > 8)
@@ -1271,6 +1373,21 @@ void launch_hartree_nodal(hipStream_t s, int64_t nv, const int32_t* v2d, const i
 void launch_rho_nodal(hipStream_t s, int64_t nv, const int32_t* v2d, const double* Phi, int N, const double* occ,
                       double* rho) {
   hipLaunchKernelGGL(k_rho_nodal, dim3(nb(nv)), dim3(TPB), 0, s, nv, v2d, Phi, N, occ, rho);
+}
+void launch_permute_rows(hipStream_t s, int64_t n, int N, const int32_t* perm, const double* in, double* out,
+                         int gather) {
+  if (n * N == 0) return;
+  hipLaunchKernelGGL(k_permute_rows, dim3(nb(n * N)), dim3(TPB), 0, s, n, N, perm, in, out, gather);
+}
+void launch_gather_nodal(hipStream_t s, int64_t n, const int32_t* d2v, const double* w, double* out) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_gather_nodal, dim3(nb(n)), dim3(TPB), 0, s, n, d2v, w, out);
+}
+void launch_count_nonfinite(hipStream_t s, int64_t na, const double* a, int64_t nb_, const double* b, int32_t* cnt) {
+  (void)hipMemsetAsync(cnt, 0, sizeof(int32_t), s);
+  int64_t blocks = std::min<int64_t>(nb(na + nb_), 2048);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_count_nonfinite, dim3((unsigned)blocks), dim3(TPB), 0, s, na, a, nb_, b, cnt);
 }
 void launch_energy(hipStream_t s, int64_t nt, const int32_t* tets, const int32_t* v2d, const double* Phi, int N,
                    const double* occ, const double* wnod, const double* vxc_old, const double* geo, int xck,

@@ -24,11 +24,10 @@ uint64_t spread3(uint64_t x) {
   return x;
 }
 
-uint64_t morton(const double* p, double lo, double hi) {
-  double s = (double)((1u << 21) - 1) / (hi - lo);
+uint64_t morton(const double* p, const double lo[3], const double hi[3]) {
   uint64_t c[3];
   for (int k = 0; k < 3; ++k) {
-    double v = (p[k] - lo) * s;
+    double v = (p[k] - lo[k]) * ((double)((1u << 21) - 1) / (hi[k] - lo[k]));
     v = v < 0 ? 0 : (v > (double)((1u << 21) - 1) ? (double)((1u << 21) - 1) : v);
     c[k] = (uint64_t)v;
   }
@@ -63,14 +62,16 @@ double tet_inverse(const double* x0, const double* x1, const double* x2, const d
 struct Locator {
   // uniform bucket grid over the coarse tets' bounding boxes
   int nb = 1;
-  double lo = 0, hi = 1, h = 1;
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1}, h[3] = {1, 1, 1};
   std::vector<int32_t> ptr, ids;
   const std::vector<double>* cgeo = nullptr;
   void build(const mlc_ctx* c) {
-    lo = c->lo;
-    hi = c->hi;
     nb = std::max(1, (int)std::cbrt((double)c->cnt / 4.0));
-    h = (hi - lo) / nb;
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = c->lo[k];
+      hi[k] = c->hi[k];
+      h[k] = (hi[k] - lo[k]) / nb;
+    }
     std::vector<int32_t> cnt((size_t)nb * nb * nb + 1, 0);
     auto cells = [&](int64_t t, int r[6]) {
       double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
@@ -81,9 +82,9 @@ struct Locator {
           mx[k] = std::max(mx[k], v);
         }
       for (int k = 0; k < 3; ++k) {
-        double e = 1e-9 * (hi - lo);
-        r[2 * k] = std::max(0, std::min(nb - 1, (int)std::floor((mn[k] - e - lo) / h)));
-        r[2 * k + 1] = std::max(0, std::min(nb - 1, (int)std::floor((mx[k] + e - lo) / h)));
+        double e = 1e-9 * (hi[k] - lo[k]);
+        r[2 * k] = std::max(0, std::min(nb - 1, (int)std::floor((mn[k] - e - lo[k]) / h[k])));
+        r[2 * k + 1] = std::max(0, std::min(nb - 1, (int)std::floor((mx[k] + e - lo[k]) / h[k])));
       }
     };
     for (int pass = 0; pass < 2; ++pass) {
@@ -109,7 +110,7 @@ struct Locator {
   // coarse tet with the largest minimal barycentric coordinate; returns it in b
   int64_t find(const mlc_ctx* c, const double* p, double b[4], double* best_min) const {
     int ix[3];
-    for (int k = 0; k < 3; ++k) ix[k] = std::max(0, std::min(nb - 1, (int)std::floor((p[k] - lo) / h)));
+    for (int k = 0; k < 3; ++k) ix[k] = std::max(0, std::min(nb - 1, (int)std::floor((p[k] - lo[k]) / h[k])));
     size_t cell = ((size_t)ix[2] * nb + ix[1]) * nb + ix[0];
     int64_t best = -1;
     double bm = -1e300;
@@ -136,14 +137,14 @@ struct Locator {
   }
 };
 
-std::vector<char> boundary_flags(const std::vector<double>& xyz, double lo, double hi) {
+std::vector<char> boundary_flags(const std::vector<double>& xyz, const double lo[3], const double hi[3]) {
   int64_t nv = (int64_t)xyz.size() / 3;
   std::vector<char> on(nv, 0);
-  double tol = 1e-12 * std::max(1.0, std::max(std::fabs(lo), std::fabs(hi)));
   for (int64_t v = 0; v < nv; ++v)
     for (int k = 0; k < 3; ++k) {
+      double tol = 1e-12 * std::max(1.0, std::max(std::fabs(lo[k]), std::fabs(hi[k])));
       double x = xyz[3 * v + k];
-      if (std::fabs(x - lo) <= tol || std::fabs(x - hi) <= tol) on[v] = 1;
+      if (std::fabs(x - lo[k]) <= tol || std::fabs(x - hi[k]) <= tol) on[v] = 1;
     }
   return on;
 }
@@ -385,6 +386,42 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
         c->PTw[fill[k]] = c->Pw[4 * d + s];
         fill[k]++;
       }
+  }
+  {
+    // chunks of RESTRICT_CHUNK consecutive fine rows; in each, the entries
+    // (row, coarse DoF, weight) of its rows sorted by coarse DoF, then row
+    const int64_t RC = RESTRICT_CHUNK;
+    const int64_t nch = (c->n + RC - 1) / RC;
+    c->rch_seg.assign(nch + 1, 0);
+    c->rseg_ptr.assign(1, 0);
+    c->rent_row.clear();
+    c->rent_w.clear();
+    std::vector<int32_t> seg_k;
+    std::vector<std::pair<int32_t, int32_t>> ent;  // (coarse DoF, slot 4 d + s)
+    for (int64_t b = 0; b < nch; ++b) {
+      ent.clear();
+      for (int64_t d = b * RC; d < std::min<int64_t>(c->n, (b + 1) * RC); ++d)
+        for (int s = 0; s < 4; ++s)
+          if (c->Pk[4 * d + s] >= 0) ent.emplace_back(c->Pk[4 * d + s], (int32_t)(4 * d + s));
+      std::sort(ent.begin(), ent.end());
+      for (size_t e = 0; e < ent.size(); ++e) {
+        if (e == 0 || ent[e].first != ent[e - 1].first) {
+          if (e > 0) c->rseg_ptr.push_back((int32_t)c->rent_row.size());
+          seg_k.push_back(ent[e].first);
+        }
+        c->rent_row.push_back((int32_t)(ent[e].second / 4 - b * RC));
+        c->rent_w.push_back(c->Pw[ent[e].second]);
+      }
+      if (!ent.empty()) c->rseg_ptr.push_back((int32_t)c->rent_row.size());
+      c->rch_seg[b + 1] = (int32_t)seg_k.size();
+    }
+    // segments of each coarse DoF, in chunk order
+    c->kseg_ptr.assign(c->nH + 1, 0);
+    for (int32_t k : seg_k) c->kseg_ptr[k + 1]++;
+    for (int64_t k = 0; k < c->nH; ++k) c->kseg_ptr[k + 1] += c->kseg_ptr[k];
+    c->kseg.assign(seg_k.size(), 0);
+    std::vector<int32_t> fill(c->kseg_ptr.begin(), c->kseg_ptr.end() - 1);
+    for (size_t g = 0; g < seg_k.size(); ++g) c->kseg[fill[seg_k[g]]++] = (int32_t)g;
   }
   c->parent.assign(c->nt, -1);
   std::vector<int32_t> gc(c->cnt + 1, 0);

@@ -76,6 +76,16 @@ struct Dev {
   // prolongation
   int32_t* Pk = nullptr;        // n x 4
   double* Pw = nullptr;         // n x 4
+  // chunked restriction P^T Y: fine rows in chunks of RCH; per chunk the
+  // (local row, weight) entries grouped by coarse DoF into segments; per coarse
+  // DoF its segments in chunk order; partial sums per segment (nseg x N)
+  int32_t* rch_seg = nullptr;   // nchunk + 1
+  int32_t* rseg_ptr = nullptr;  // nseg + 1
+  int32_t* rent_row = nullptr;  // nent
+  double* rent_w = nullptr;     // nent
+  int32_t* kseg_ptr = nullptr;  // nH + 1
+  int32_t* kseg = nullptr;      // nseg
+  double* rpart = nullptr;      // nseg x N
   int32_t* PTptr = nullptr;     // nH + 1
   int32_t* PTidx = nullptr;
   double* PTw = nullptr;
@@ -112,6 +122,8 @@ struct Dev {
   double* gsel = nullptr;       // 4N: [learned start used, |r|^2 learned, |r|^2 plain, -]
   double* gdots = nullptr;      // 5N: Galerkin sums of the learned start
   int32_t* d2v = nullptr;       // n: library dof -> vertex
+  int32_t* dof_user = nullptr;  // n: library dof -> caller dof
+  int32_t* chk = nullptr;       // 4: count of non-finite inputs (mlc_set_state)
   double* lmax = nullptr;       // 2: Gershgorin bounds of D^-1 A (step 5) and D^-1 K (Hartree)
   double* KHinv = nullptr;      // nH x nH: inverse of the coarse stiffness (two-level Hartree CG)
   double* rH = nullptr;         // nH: restricted residual
@@ -133,7 +145,8 @@ struct mlc_ctx {
   int32_t n_nuclei = 0;
   std::vector<double> R, Z, occ;
   int32_t potential = 0, xc = 0, hartree = 1, N = 1;
-  double rc = 0.5, omega = 1.0, xalpha = 0.77298, lo = 0, hi = 0;
+  double rc = 0.5, omega = 1.0, xalpha = 0.77298;
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // the box, per axis
   mlc_options opt{};
   // ---- fine DoFs ----------------------------------------------------------
   int64_t n = 0;                        // interior DoFs
@@ -152,6 +165,8 @@ struct mlc_ctx {
   std::vector<double> Pw;
   std::vector<int32_t> PTptr, PTidx;
   std::vector<double> PTw;
+  std::vector<int32_t> rch_seg, rseg_ptr, rent_row, kseg_ptr, kseg;  // chunked restriction (see Dev)
+  std::vector<double> rent_w;
   std::vector<int32_t> parent;          // fine tet -> coarse tet
   std::vector<int32_t> cgrp_ptr, cgrp_tet, cgrp_dof;
   std::vector<double> cgeo;             // cnt x 12
@@ -327,6 +342,11 @@ void launch_reduce_cols(hipStream_t s, int N, int nblk, const double* partial, d
 void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, double* X);
 void launch_restrict(hipStream_t s, int64_t nH, int N, const int32_t* PTptr, const int32_t* PTidx, const double* PTw,
                      const double* Y, double* out);
+// P^T Y (nH x N) through the chunk structure: each chunk of RESTRICT_CHUNK
+// fine rows of Y is read once (into LDS), its segment sums go to part, then
+// the segments of each coarse DoF are summed in chunk order into out.
+constexpr int RESTRICT_CHUNK = 128;
+void launch_restrict_chunks(hipStream_t s, int64_t n, int64_t nH, int N, const Dev& d, const double* Y, double* out);
 void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double* Y, double* partial);
 // chat: per fine tet in coarse-group order e, the parent's coarse hats at its
 // quadrature points (16) and its volume: 17 arrays of ng = nt doubles (value
@@ -345,6 +365,13 @@ void launch_hartree_nodal(hipStream_t s, int64_t nv, const int32_t* v2d, const i
                           const double* wH, double theta1, const double* w0, const double* g, double* w);
 void launch_rho_nodal(hipStream_t s, int64_t nv, const int32_t* v2d, const double* Phi, int N, const double* occ,
                       double* rho);
+// gather = 1: out[a N + i] = in[perm[a] N + i]; gather = 0: out[perm[a] N + i] = in[a N + i]
+void launch_permute_rows(hipStream_t s, int64_t n, int N, const int32_t* perm, const double* in, double* out,
+                         int gather);
+// out[a] = w[d2v[a]] for the n DoFs (interior values of a nodal vector)
+void launch_gather_nodal(hipStream_t s, int64_t n, const int32_t* d2v, const double* w, double* out);
+// cnt[0] = number of non-finite values in a[0..na) and b[0..nb)
+void launch_count_nonfinite(hipStream_t s, int64_t na, const double* a, int64_t nb, const double* b, int32_t* cnt);
 // learned initial guess (kernels.hip)
 void launch_colmax_abs(hipStream_t s, int64_t n, int N, const double* X, double* partial, double* out);
 void launch_features(hipStream_t s, int64_t n, int N, const int32_t* d2v, const double* xyz, const double* w,

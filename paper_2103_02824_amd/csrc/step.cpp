@@ -11,6 +11,12 @@
 
 namespace mlc {
 
+static double box_diagonal(const mlc_ctx* c) {
+  double d2 = 0.0;
+  for (int k = 0; k < 3; ++k) d2 += (c->hi[k] - c->lo[k]) * (c->hi[k] - c->lo[k]);
+  return std::sqrt(d2);
+}
+
 // Offsets into the packed small-block buffer (doubles).
 struct SmallLayout {
   int64_t ptF, ptW, ptM, ptK, utF, utW, utM, utK, d, liftH, sc, mom, ovl, colv, total;
@@ -407,7 +413,7 @@ mlc_status phase_operators(StepRun& S) {
     launch_spmm2(s, n, N, d.rowptr, d.col, d.valA, d.Phi, d.Q, nullptr, nullptr);
     launch_colmax_abs(s, n, N, d.Phi, d.red, d.gscale);
     launch_features(s, n, N, d.d2v, d.xyz, d.w, d.Phi, d.Q, d.B, d.dinvA, d.occ, d.RZ, c->n_nuclei, c->potential,
-                    c->rc, c->omega, c->xc, c->xalpha, std::sqrt(3.0) * (c->hi - c->lo), d.gscale, d.F);
+                    c->rc, c->omega, c->xc, c->xalpha, box_diagonal(c), d.gscale, d.F);
   }
   if (nd) {
     launch_nn_forward(s, *nd, d.F, n * N, 0, 1, n * N, d.Ynn);
@@ -447,6 +453,10 @@ mlc_status phase_after_solve(StepRun& S) {
   launch_reduce_cols(s, N, elem_blocks(n, N), d.red, d.colv + N);
   launch_normalize_cols(s, n, N, d.colv + N, d.X);
   if (c->hartree) {
+    // start of the Hartree CG: the interior values of the current Hartree
+    // potential w^l, the Hartree potential of rho^l (rho~ differs from it by
+    // the step's change of the orbitals; the boundary data are zero inside)
+    launch_gather_nodal(s, n, d.d2v, d.w, d.w0);
     launch_qp_density(s, nt, d.tets, d.v2d, d.X, N, d.occ, d.rhot);
     launch_load(s, n, nt, d.adj_ptr, d.adj_tet, d.adj_loc, d.tets, d.geo, d.rhot, 4.0 * 3.14159265358979323846, d.g,
                 d.v2d, d.elem, d.pb, d.lvec);
@@ -469,7 +479,7 @@ mlc_status phase_gram_fixed(StepRun& S, hipStream_t s, double* red) {
   for (int o : {0, 2, 3}) {
     double* Yo = d.Y + (int64_t)o * n * N;
     launch_spmm2(s, n, N, d.rowptr, d.col, vals[o], d.X, Yo, nullptr, nullptr);
-    launch_restrict(s, nH, N, d.PTptr, d.PTidx, d.PTw, Yo, d.small + L.ptF + (int64_t)o * nH * N);
+    launch_restrict_chunks(s, n, nH, N, d, Yo, d.small + L.ptF + (int64_t)o * nH * N);
     launch_gram(s, n, N, d.X, Yo, red);
     launch_reduce_cols(s, N * N, gram_blocks(n), red, d.small + L.utF + (int64_t)o * N * N);
   }
@@ -506,15 +516,15 @@ mlc_status phase_gram(StepRun& S) {
   {
     double* Yo = d.Y + (int64_t)n * N;
     launch_spmm2(s, n, N, d.rowptr, d.col, d.valW, d.X, Yo, nullptr, nullptr);
-    launch_restrict(s, nH, N, d.PTptr, d.PTidx, d.PTw, Yo, d.small + L.ptF + (int64_t)nH * N);
+    launch_restrict_chunks(s, n, nH, N, d, Yo, d.small + L.ptF + (int64_t)nH * N);
     launch_gram(s, n, N, d.X, Yo, d.red);
     launch_reduce_cols(s, N * N, gram_blocks(n), d.red, d.small + L.utF + (int64_t)N * N);
   }
   HIPCHK(hipMemsetAsync(d.small + L.d, 0, sizeof(double) * (2 * nH + 8), s));
   if (c->hartree) {
     launch_spmm2(s, n, 1, d.rowptr, d.col, d.valK, d.w0, d.pq, nullptr, nullptr);
-    launch_restrict(s, nH, 1, d.PTptr, d.PTidx, d.PTw, d.pq, d.small + L.d);
-    launch_restrict(s, nH, 1, d.PTptr, d.PTidx, d.PTw, d.lvec, d.small + L.liftH);
+    launch_restrict_chunks(s, n, nH, 1, d, d.pq, d.small + L.d);
+    launch_restrict_chunks(s, n, nH, 1, d, d.lvec, d.small + L.liftH);
     launch_coldot(s, n, 1, d.w0, d.pq, d.red);
     launch_reduce_cols(s, 1, elem_blocks(n, 1), d.red, d.small + L.sc + 0);
     launch_coldot(s, n, 1, d.w0, d.lvec, d.red);
@@ -567,6 +577,14 @@ mlc_status phase_inner(StepRun& S) {
   fb.cel_orb = c->last_cel_orb;
   S.ist = inner_loop(c, fb, S.io);
   if (S.ist < 0) return S.ist;
+  // everything the reconstruction writes into the state is checked here, on
+  // the host, before any device write: on failure the state stays as it was
+  bool finite = std::isfinite(S.io.theta1);
+  for (double v : S.io.lam) finite = finite && std::isfinite(v);
+  for (double v : S.io.theta2) finite = finite && std::isfinite(v);
+  for (double v : S.io.phiH) finite = finite && std::isfinite(v);
+  for (double v : S.io.wH) finite = finite && std::isfinite(v);
+  if (!finite) return fail(c, MLC_ERR_NONFINITE, "non-finite result of the augmented problems");
   S.r.inner_iters = S.io.iters;
   S.r.inner_last_diff = S.io.last_diff;
   S.r.t_inner_ms = S.io.ms;
@@ -705,7 +723,7 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   } else {
     PHASE(phase_gram_fixed(S, s, d.red));
   }
-  // step 6: Hartree direction w0, warm-started from the previous step's w0 (zero at bind)
+  // step 6: Hartree direction w0, started from the interior values of w^l (phase_after_solve)
   HIPCHK(hipEventRecord(S.ev[6], s));
   if (c->hartree) {
     double dummy = 0.0;

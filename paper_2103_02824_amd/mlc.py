@@ -45,7 +45,7 @@ class MlcError(RuntimeError):
 
 
 class Mesh(C.Structure):
-    _fields_ = [("n_vertices", C.c_int64), ("xyz", C.POINTER(C.c_double)), ("n_tets", C.c_int64),
+    _fields_ = [("order", C.c_int32), ("n_vertices", C.c_int64), ("xyz", C.POINTER(C.c_double)), ("n_tets", C.c_int64),
                 ("tets", C.POINTER(C.c_int32))]
 
 
@@ -53,7 +53,7 @@ class SystemDesc(C.Structure):
     _fields_ = [("n_nuclei", C.c_int32), ("R", C.POINTER(C.c_double)), ("Z", C.POINTER(C.c_double)),
                 ("potential", C.c_int32), ("rc", C.c_double), ("omega", C.c_double), ("n_orbitals", C.c_int32),
                 ("occupations", C.POINTER(C.c_double)), ("xc", C.c_int32), ("xalpha", C.c_double),
-                ("hartree", C.c_int32), ("box_lo", C.c_double), ("box_hi", C.c_double)]
+                ("hartree", C.c_int32), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3)]
 
 
 class Options(C.Structure):
@@ -63,7 +63,8 @@ class Options(C.Structure):
                 ("reorder", C.c_int32), ("time_kernels", C.c_int32), ("use_graphs", C.c_int32),
                 ("precision", C.c_int32), ("ir_inner_rtol", C.c_double), ("ir_max_outer", C.c_int32),
                 ("precond", C.c_int32), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
-                ("hartree_coarse", C.c_int32), ("hartree_precond", C.c_int32)]
+                ("hartree_coarse", C.c_int32), ("hartree_precond", C.c_int32),
+                ("inner_mix_history", C.c_int32), ("inner_mix_beta", C.c_double)]
 
 PREC_FP64, PREC_FP32_IR = 0, 1
 PC_JACOBI, PC_CHEBYSHEV = 0, 1
@@ -167,6 +168,12 @@ def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+def box3(v):
+    """A box bound as the C double[3]: a scalar for all three axes, or three values."""
+    a = np.broadcast_to(np.asarray(v, dtype=np.float64), (3,))
+    return (C.c_double * 3)(*[float(x) for x in a])
+
+
 def options(**kw):
     o = Options()
     lib().mlc_options_default(C.byref(o))
@@ -193,11 +200,12 @@ class Context:
         Z = np.ascontiguousarray(np.asarray(system.Z, dtype=np.float64).ravel())
         occ = np.ascontiguousarray(np.asarray(system.occupations, dtype=np.float64))
         self._keep += [xyz, tets, cxyz, ctets, R, Z, occ]
-        fine = Mesh(len(xyz), _dp(xyz), len(tets), tets.ctypes.data_as(C.POINTER(C.c_int32)))
-        coarse = Mesh(len(cxyz), _dp(cxyz), len(ctets), ctets.ctypes.data_as(C.POINTER(C.c_int32)))
+        order = int(getattr(system, "order", 1))
+        fine = Mesh(order, len(xyz), _dp(xyz), len(tets), tets.ctypes.data_as(C.POINTER(C.c_int32)))
+        coarse = Mesh(1, len(cxyz), _dp(cxyz), len(ctets), ctets.ctypes.data_as(C.POINTER(C.c_int32)))
         sd = SystemDesc(len(Z), _dp(R), _dp(Z), int(system.potential), float(system.rc), float(system.omega),
                         int(system.n_orbitals), _dp(occ), int(system.xc), float(system.xalpha),
-                        int(bool(system.hartree)), float(system.lo), float(system.hi))
+                        int(bool(system.hartree)), box3(system.lo), box3(system.hi))
         self.opts = opts if opts is not None else options()
         h = C.c_void_p()
         st = L.mlc_create(C.byref(fine), C.byref(coarse), C.byref(sd), C.byref(self.opts), C.byref(h))
@@ -230,12 +238,22 @@ class Context:
         self._chk(lib().mlc_initial_state(self.h, tol, maxit, C.byref(it)))
         return it.value
 
+    def _dev(self, a, shape):
+        """a (NumPy array or torch tensor) as a contiguous float64 tensor of the given shape on the
+        context's device."""
+        import torch
+        t = torch.as_tensor(a, dtype=torch.float64, device=self.device).reshape(shape).contiguous()
+        return t
+
     def set_state(self, lam, Phi, w):
+        """lam: host (N,); Phi (n_dof, N) and w (n_vertices,): NumPy arrays or device tensors
+        (copied to the device first when they are on the host)."""
         lam = np.ascontiguousarray(lam, dtype=np.float64)
-        Phi = np.ascontiguousarray(Phi, dtype=np.float64).reshape(self.n_dof, self.N)
-        w = np.ascontiguousarray(w, dtype=np.float64)
-        assert lam.shape == (self.N,) and w.shape == (self.n_vertices,)
-        self._chk(lib().mlc_set_state(self.h, _dp(lam), _dp(Phi), _dp(w)))
+        assert lam.shape == (self.N,)
+        P = self._dev(Phi, (self.n_dof, self.N))
+        wd = self._dev(w, (self.n_vertices,))
+        self._chk(lib().mlc_set_state(self.h, _dp(lam), C.cast(C.c_void_p(P.data_ptr()), C.POINTER(C.c_double)),
+                                      C.cast(C.c_void_p(wd.data_ptr()), C.POINTER(C.c_double))))
 
     def correction_step(self, allow_warn=True):
         rep = StepReport()
@@ -245,13 +263,21 @@ class Context:
         d["status"] = st
         return d
 
-    def get_results(self):
+    def get_results_device(self):
+        """(lam host NumPy (N,), Phi (n_dof, N), w (n_vertices,), rho (n_vertices,) as device tensors)."""
+        import torch
         lam = np.zeros(self.N)
-        Phi = np.zeros((self.n_dof, self.N))
-        w = np.zeros(self.n_vertices)
-        rho = np.zeros(self.n_vertices)
-        self._chk(lib().mlc_get_results(self.h, _dp(lam), _dp(Phi), _dp(w), _dp(rho)))
+        Phi = torch.empty((self.n_dof, self.N), dtype=torch.float64, device=self.device)
+        w = torch.empty(self.n_vertices, dtype=torch.float64, device=self.device)
+        rho = torch.empty(self.n_vertices, dtype=torch.float64, device=self.device)
+        dp = lambda t: C.cast(C.c_void_p(t.data_ptr()), C.POINTER(C.c_double))
+        self._chk(lib().mlc_get_results(self.h, _dp(lam), dp(Phi), dp(rho), dp(w)))
         return lam, Phi, w, rho
+
+    def get_results(self):
+        """(lam, Phi, w, rho) as host NumPy arrays (copied from the device tensors)."""
+        lam, Phi, w, rho = self.get_results_device()
+        return lam, Phi.cpu().numpy(), w.cpu().numpy(), rho.cpu().numpy()
 
     def probe(self, name, shape):
         out = np.zeros(int(np.prod(shape)))

@@ -32,7 +32,8 @@ def test_exports_match_header():
     assert declared == set(mlc.EXPORTED)
 
 
-def _create(mlc, L, S, fine_xyz=None, fine_tets=None, coarse_xyz=None, coarse_tets=None, opts=None, **sysover):
+def _create(mlc, L, S, fine_xyz=None, fine_tets=None, coarse_xyz=None, coarse_tets=None, opts=None, fine_order=1,
+            **sysover):
     xyz = np.ascontiguousarray(S.xyz if fine_xyz is None else fine_xyz, dtype=np.float64)
     tets = np.ascontiguousarray(S.tets if fine_tets is None else fine_tets, dtype=np.int32)
     cxyz = np.ascontiguousarray(S.cxyz if coarse_xyz is None else coarse_xyz, dtype=np.float64)
@@ -40,12 +41,12 @@ def _create(mlc, L, S, fine_xyz=None, fine_tets=None, coarse_xyz=None, coarse_te
     R = np.ascontiguousarray(S.R.reshape(-1, 3))
     Z = np.ascontiguousarray(S.Z, dtype=np.float64)
     occ = np.ascontiguousarray(S.occupations, dtype=np.float64)
-    fine = mlc.Mesh(len(xyz), mlc._dp(xyz), len(tets), tets.ctypes.data_as(C.POINTER(C.c_int32)))
-    coarse = mlc.Mesh(len(cxyz), mlc._dp(cxyz), len(ctets), ctets.ctypes.data_as(C.POINTER(C.c_int32)))
+    fine = mlc.Mesh(fine_order, len(xyz), mlc._dp(xyz), len(tets), tets.ctypes.data_as(C.POINTER(C.c_int32)))
+    coarse = mlc.Mesh(1, len(cxyz), mlc._dp(cxyz), len(ctets), ctets.ctypes.data_as(C.POINTER(C.c_int32)))
     sd = mlc.SystemDesc(len(Z), mlc._dp(R), mlc._dp(Z), S.potential, S.rc, S.omega, S.n_orbitals, mlc._dp(occ),
-                        S.xc, S.xalpha, int(S.hartree), S.lo, S.hi)
+                        S.xc, S.xalpha, int(S.hartree), mlc.box3(S.lo), mlc.box3(S.hi))
     for k, v in sysover.items():
-        setattr(sd, k, v)
+        setattr(sd, k, mlc.box3(v) if k.startswith("box_") else v)
     o = mlc.options() if opts is None else opts
     h = C.c_void_p()
     st = L.mlc_create(C.byref(fine), C.byref(coarse), C.byref(sd), C.byref(o), C.byref(h))
@@ -99,7 +100,45 @@ def test_rejects_bad_system():
     assert _create(mlc, L, S, n_orbitals=0)[0] == -1
     assert _create(mlc, L, S, xc=7)[0] == -1
     assert _create(mlc, L, S, box_lo=10.0)[0] == -1
+    assert _create(mlc, L, S, box_lo=(-10.0, 10.0, -10.0))[0] == -1   # empty along y
+    assert _create(mlc, L, S, box_hi=(10.0, np.inf, 10.0))[0] == -1
     assert _create(mlc, L, S, rc=0.0)[0] == -1
+
+
+def test_rejects_element_orders_other_than_linear():
+    """mlc_mesh.order: linear Lagrange elements only; 0, 2 and 3 are argument errors."""
+    mlc, L = _lib()
+    S = c1_hydrogen()
+    assert _create(mlc, L, S, fine_order=1)[0] == 0
+    for order in (0, 2, 3):
+        assert _create(mlc, L, S, fine_order=order)[0] == -1, order
+
+
+def test_box_bounds_per_axis():
+    """A box given per axis that differs from the mesh's extent along one axis
+    changes which vertices are boundary vertices, so the DoF count changes:
+    the three bounds are read separately."""
+    mlc, L = _lib()
+    S = c1_hydrogen()
+    st, msg, sizes = _create(mlc, L, S, box_lo=(-10.0, -10.0, -10.0), box_hi=(10.0, 10.0, 10.0))
+    assert st == 0, msg
+    assert sizes[0] == 15 ** 3
+    # x-faces moved outward: the vertices at x = +-10 are interior now
+    st, msg, sizes = _create(mlc, L, S, box_lo=(-11.0, -10.0, -10.0), box_hi=(11.0, 10.0, 10.0))
+    assert st == 0, msg
+    assert sizes[0] == 17 * 15 * 15
+
+
+def test_inner_mixing_options_checked():
+    mlc, L = _lib()
+    S = c1_hydrogen()
+    for kw in (dict(inner_mix_history=0), dict(inner_mix_history=16, inner_mix_beta=1.0)):
+        assert _create(mlc, L, S, opts=mlc.options(**kw))[0] == 0, kw
+    for kw in (dict(inner_mix_history=-1), dict(inner_mix_history=17), dict(inner_mix_beta=0.0),
+               dict(inner_mix_beta=1.5)):
+        assert _create(mlc, L, S, opts=mlc.options(**kw))[0] == -1, kw
+    o = mlc.options()
+    assert (o.inner_mix_history, o.inner_mix_beta) == (6, 0.5)
 
 
 def test_status_strings():
@@ -116,9 +155,10 @@ def test_calls_before_bind_fail_cleanly():
     cxyz = np.ascontiguousarray(S.cxyz)
     ctets = np.ascontiguousarray(S.ctets, dtype=np.int32)
     R, Z, occ = np.zeros(3), np.ones(1), np.ones(1)
-    fine = mlc.Mesh(len(xyz), mlc._dp(xyz), len(tets), tets.ctypes.data_as(C.POINTER(C.c_int32)))
-    coarse = mlc.Mesh(len(cxyz), mlc._dp(cxyz), len(ctets), ctets.ctypes.data_as(C.POINTER(C.c_int32)))
-    sd = mlc.SystemDesc(1, mlc._dp(R), mlc._dp(Z), 0, 0.2, 1.0, 1, mlc._dp(occ), 1, 0.77298, 1, -10.0, 10.0)
+    fine = mlc.Mesh(1, len(xyz), mlc._dp(xyz), len(tets), tets.ctypes.data_as(C.POINTER(C.c_int32)))
+    coarse = mlc.Mesh(1, len(cxyz), mlc._dp(cxyz), len(ctets), ctets.ctypes.data_as(C.POINTER(C.c_int32)))
+    sd = mlc.SystemDesc(1, mlc._dp(R), mlc._dp(Z), 0, 0.2, 1.0, 1, mlc._dp(occ), 1, 0.77298, 1, mlc.box3(-10.0),
+                        mlc.box3(10.0))
     h = C.c_void_p()
     assert L.mlc_create(C.byref(fine), C.byref(coarse), C.byref(sd), None, C.byref(h)) == 0
     rep = mlc.StepReport()
@@ -126,6 +166,7 @@ def test_calls_before_bind_fail_cleanly():
     assert L.mlc_bind(h, None, 0, None) == -4
     lam = np.zeros(1)
     assert L.mlc_get_results(h, mlc._dp(lam), None, None, None) == -9
+    assert L.mlc_set_state(h, mlc._dp(lam), None, None) == -1          # null device pointers
     L.mlc_destroy(h)
 
 
@@ -139,10 +180,10 @@ def test_batch_argument_checks():
             ((S.xyz, np.float64), (S.tets, np.int32), (S.cxyz, np.float64), (S.ctets, np.int32),
              (S.R.reshape(-1, 3), np.float64), (S.Z, np.float64), (S.occupations, np.float64))]
     xyz, tets, cxyz, ctets, R, Z, occ = keep
-    fine = mlc.Mesh(len(xyz), mlc._dp(xyz), len(tets), tets.ctypes.data_as(C.POINTER(C.c_int32)))
-    coarse = mlc.Mesh(len(cxyz), mlc._dp(cxyz), len(ctets), ctets.ctypes.data_as(C.POINTER(C.c_int32)))
+    fine = mlc.Mesh(1, len(xyz), mlc._dp(xyz), len(tets), tets.ctypes.data_as(C.POINTER(C.c_int32)))
+    coarse = mlc.Mesh(1, len(cxyz), mlc._dp(cxyz), len(ctets), ctets.ctypes.data_as(C.POINTER(C.c_int32)))
     sd = mlc.SystemDesc(len(Z), mlc._dp(R), mlc._dp(Z), S.potential, S.rc, S.omega, S.n_orbitals, mlc._dp(occ),
-                        S.xc, S.xalpha, int(S.hartree), S.lo, S.hi)
+                        S.xc, S.xalpha, int(S.hartree), mlc.box3(S.lo), mlc.box3(S.hi))
     o = mlc.options()
     h = C.c_void_p()
     assert L.mlc_create(C.byref(fine), C.byref(coarse), C.byref(sd), C.byref(o), C.byref(h)) == 0

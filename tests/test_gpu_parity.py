@@ -22,6 +22,16 @@ def relerr(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
+def colerr(a, b):
+    """Largest relative 2-norm error over the columns (last axis) of a block, so
+    that a weak column cannot hide behind strong ones."""
+    a = np.asarray(a).reshape(-1, np.shape(a)[-1]) if np.ndim(a) > 1 else np.asarray(a)[:, None]
+    b = np.asarray(b).reshape(a.shape)
+    num = np.linalg.norm(a - b, axis=0)
+    den = np.maximum(np.linalg.norm(b, axis=0), 1e-300)
+    return float(np.max(num / den))
+
+
 @pytest.fixture(scope="module")
 def c1(gpu):
     from paper_2103_02824_amd import mlc
@@ -93,7 +103,7 @@ def _fine_blocks_ref(prob, fs):
 def _compare_fine_stage(ctx, prob, fs, tol_u=1e-8, tol_blk=1e-8):
     nH, N, n = ctx.n_coarse_dof, ctx.N, ctx.n_dof
     U = ctx.probe("U", (n, N))
-    assert relerr(U, fs["U"]) < tol_u
+    assert colerr(U, fs["U"]) < tol_u, colerr(U, fs["U"])
     if prob.hartree:
         assert relerr(ctx.probe("W0", (n,)), fs["w0"]) < tol_u
         assert relerr(ctx.probe("G", (ctx.n_vertices,)), fs["g"]) < 1e-12
@@ -109,6 +119,11 @@ def _compare_fine_stage(ctx, prob, fs, tol_u=1e-8, tol_blk=1e-8):
         # coarse matrices without the u_i dependence are exact to rounding
         tol = 1e-12 if name in ("M_H", "K_H") else tol_blk
         assert relerr(got, ref[name]) < tol, (name, relerr(got, ref[name]))
+        if name.startswith("PT_") or name == "RHS":
+            # per orbital: column i of P^T O u_i (row i of the RHS block)
+            g2 = got if name.startswith("PT_") else got.T
+            r2 = ref[name] if name.startswith("PT_") else ref[name].T
+            assert colerr(g2, r2) < 10 * tol, (name, colerr(g2, r2))
 
 
 def test_tiny_two_orbitals_full_step(gpu):
@@ -382,8 +397,8 @@ def test_other_models_one_step(gpu, case):
     Hartree, two doubly occupied orbitals; Section 4) on a small mesh pair,
     and the harmonic oscillator (no nuclei, no XC, no Hartree; its lowest
     level and the full degenerate triplet): the fine stage and one whole
-    correction step against the checker. The inner loop is capped at three
-    iterations on both sides (the same iteration, so the same state)."""
+    correction step against the checker, with the inner iteration converged
+    on both sides."""
     from inputs.systems import harmonic, lih_small
     from oracle.mlc import fine_stage
     from paper_2103_02824_amd import mlc
@@ -391,15 +406,50 @@ def test_other_models_one_step(gpu, case):
     print(f"case {case}: {len(S.xyz)} vertices, N = {S.n_orbitals}", flush=True)
     prob = Problem(S)
     st0, _ = initial_state(prob, maxit=300)
-    ctx = mlc.Context(S, mlc.options(**dict(LIB_OPTS, inner_maxit=3)))
+    ctx = mlc.Context(S, mlc.options(**LIB_OPTS))
     ctx.set_state(st0.lam, st0.Phi, st0.w)
-    rep = ctx.correction_step()
+    rep = ctx.correction_step(allow_warn=False)
     fs = fine_stage(prob, st0, ORA_OPTS)
     _compare_fine_stage(ctx, prob, fs)
-    ref = correction_step(prob, st0, Options(shift=True, sigma0=1.0, inner_tol=1e-11, inner_maxit=3, n_extra=8))
+    ref = correction_step(prob, st0, ORA_OPTS)
     lam, Phi, w, rho = ctx.get_results()
-    assert rep["inner_iters"] == ref.inner_iters, (rep["inner_iters"], ref.inner_iters)
+    print(f"inner iterations: library {rep['inner_iters']}, checker {ref.inner_iters}", flush=True)
+    assert rep["inner_iters"] < 500 and ref.inner_iters < 500
     assert np.max(np.abs(lam - ref.state.lam)) < 1e-8, (lam, ref.state.lam)
     assert relerr(rho, ref.rho_nodal) < 1e-6
     assert abs(rep["rho_integral"] - float(np.sum(S.occupations))) < 1e-9
+    ctx.close()
+
+
+def test_cluster_whole_steps_converged_inner_loop(gpu):
+    """A multi-orbital cluster (4 atoms, Z = (1, 2, 4, 1), 4 doubly occupied
+    orbitals, LDA + Hartree) over three outer steps, each with the inner
+    iteration converged (Anderson-mixed Algorithm 2 to 1e-11 in H^1, well
+    below its cap) on both sides: eigenvalues to 1e-8 Ha and the density to
+    1e-6 relative L2 after every step, each side continuing from its own
+    state. The orbital overlaps stay small and shrink from step to step."""
+    from inputs.systems import c2_small
+    from paper_2103_02824_amd import mlc
+    S = c2_small(1)
+    prob = Problem(S)
+    print(f"case c2small seed 1, three whole steps, n_dof={prob.fine.n_dof} nH={prob.NH}", flush=True)
+    st, _ = initial_state(prob, maxit=300)
+    ctx = mlc.Context(S, mlc.options(**LIB_OPTS))
+    ctx.set_state(st.lam, st.Phi, st.w)
+    ovl = []
+    for k in range(3):
+        rep = ctx.correction_step(allow_warn=False)
+        ref = correction_step(prob, st, ORA_OPTS)
+        st = ref.state
+        lam, Phi, w, rho = ctx.get_results()
+        print(f"step {k}: lambda {lam}, checker {ref.state.lam}, inner {rep['inner_iters']}/{ref.inner_iters}, "
+              f"overlap {rep['max_offdiag_overlap']:.2e}", flush=True)
+        assert rep["inner_iters"] < 200 and ref.inner_iters < 200
+        assert rep["inner_last_diff"] < 1e-11
+        assert np.max(np.abs(lam - ref.state.lam)) < 1e-8, (lam, ref.state.lam)
+        assert relerr(rho, ref.rho_nodal) < 1e-6
+        assert abs(rep["energy"] - ref.energy) < 1e-7
+        assert abs(rep["max_offdiag_overlap"] - ref.max_offdiag_overlap) < 1e-7
+        ovl.append(rep["max_offdiag_overlap"])
+    assert ovl[-1] < ovl[0] and ovl[-1] < 1e-2, ovl
     ctx.close()
