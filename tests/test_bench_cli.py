@@ -17,7 +17,8 @@ def test_bench_refuses_several_gpus():
 def test_bench_entry_points():
     sys.path.insert(0, str(ROOT))
     import bench
-    for name in ("main", "run_batch", "cpu_baseline", "spmm_bytes", "cheb_bytes", "train_guess_network"):
+    for name in ("main", "run_batch", "cpu_baseline", "cpu_baseline_pcg_rate", "spmm_bytes", "cheb_bytes",
+                 "train_guess_network", "_check_physics"):
         assert callable(getattr(bench, name)), name
     # algorithmic bytes: matrix (values + indices) once, row pointers, X read and Y written
     assert bench.spmm_bytes(10, 30, 2) == 12 * 30 + 4 * 11 + 2 * 8 * 10 * 2
@@ -34,3 +35,20 @@ def test_traffic_lookup_never_raises_and_matches_committed_sources():
     t3 = bench._traffic(bench._kernel_name("cheb_step", 52, 4), "c3", 0, "fp32ir")
     assert t2 is not None and 5e7 < t2 < 1e8, t2
     assert t3 is not None and 1e9 < t3 < 5e9, t3
+
+
+def test_physics_check_exits_on_invalid_results():
+    """A step result with a wrong electron count, an inner loop stopped by its
+    cap or overlapping orbitals ends bench.py with exit status 3; a valid one
+    passes."""
+    import pytest
+    sys.path.insert(0, str(ROOT))
+    import bench
+    ok = {"eigenvalues_sorted": [-1.0, -0.5], "max_offdiag_overlap": 1e-4, "rho_integral": 4.0, "electrons": 4.0,
+          "energy": -3.0, "inner_iters": 12, "inner_last_diff": 1e-11, "inner_converged": True}
+    bench._check_physics(ok, 1e-2, "c2")
+    for change in ({"rho_integral": 3.9}, {"inner_converged": False}, {"max_offdiag_overlap": 0.2},
+                   {"eigenvalues_sorted": [float("nan"), -0.5]}):
+        with pytest.raises(SystemExit) as e:
+            bench._check_physics(dict(ok, **change), 1e-2, "c2")
+        assert e.value.code == 3, change
