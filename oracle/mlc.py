@@ -17,10 +17,11 @@ the design notes):
    the Hartree space is w = g_lift + P w_H + theta1 * w0, with w0 the
    zero-boundary solution of step 6 lifted by g, so (w_H, theta1) = (0, 1)
    is exactly the fine Hartree potential of rho~ (Algorithm 2 start).
- * Step (a) of Algorithm 2 keeps the eigenvector, among the lowest
-   min(N_H+1, N+n_extra) of the augmented pencil, whose coefficient theta2 on
-   u_i has the largest magnitude (M-normalised), ties to the lower
-   eigenvalue, sign fixed so that theta2 > 0.
+ * Step (a) of Algorithm 2 keeps, among the lowest min(N_H+1, N+n_extra)
+   eigenpairs of the augmented pencil, the eigenfunction with the largest
+   component in span{u_i}: the largest |(phi, u_i)_M| (within a repeated
+   eigenvalue, the normalised projection of u_i onto its eigenspace), ties to
+   the lower eigenvalue, sign so that (phi, u_i)_M > 0.
  * The stopping norm of Algorithm 2 step (c) is the H^1 norm.
  * Algorithm 2 is a fixed-point iteration in the Hartree coefficients
    x = (w_H, theta1). Run as printed (x_in <- x_out) it oscillates on
@@ -163,15 +164,29 @@ def augmented_blocks(prob: Problem, U, w0, g, vxc):
     return Afix, Mw0
 
 
-def select_eigenpair(evals, evecs, n_keep):
-    """Algorithm 2 (a): among the lowest n_keep eigenpairs (M-normalised
-    columns) keep the one with the largest |theta2| (last coordinate)."""
-    t = np.abs(evecs[-1, :n_keep])
-    j = int(np.argmax(t))          # first maximum = lower eigenvalue on ties
-    x = evecs[:, j].copy()
-    if x[-1] < 0:
-        x = -x
-    return float(evals[j]), x
+def select_eigenpair(evals, evecs, Mi, n_keep, tol=1e-12):
+    """Algorithm 2 (a): among the lowest n_keep eigenpairs of the augmented
+    pencil (M_i-orthonormal eigenvectors in the basis [P, u_i]), the
+    eigenfunction with the largest component in span{u_i}, that is the
+    largest |(phi, u_i)_M| over unit eigenfunctions phi. Within an eigenvalue
+    of multiplicity above one (eigenvalues equal to tol relative) the maximum
+    is taken by the normalised projection of u_i onto the eigenspace, whose
+    norm is the value. Ties (values equal to 1e-10 relative) go to the lower
+    eigenvalue; the sign makes (phi, u_i)_M positive."""
+    e = Mi[:, -1]                       # (x, u_i)_M = x . M_i[:, -1]: u_i is the last basis function
+    c = evecs[:, :n_keep].T @ e
+    best, j0, k0 = -1.0, 0, 1
+    j = 0
+    while j < n_keep:
+        k = j + 1
+        while k < n_keep and abs(evals[k] - evals[j]) <= tol * max(1.0, abs(evals[j])):
+            k += 1
+        nrm = float(np.linalg.norm(c[j:k]))
+        if nrm > best * (1.0 + 1e-10):
+            best, j0, k0 = nrm, j, k
+        j = k
+    x = evecs[:, j0:k0] @ c[j0:k0] / best
+    return float(evals[j0]), x
 
 
 def anderson_next(x_in, F, hist, G, m, beta):
@@ -237,7 +252,7 @@ def inner_scf(prob: Problem, fs: dict, opts: Options, x_start=None):
             Ki = np.block([[PHP, (P.T @ Hu)[:, None]], [(P.T @ Hu)[None, :], np.array([[u @ Hu]])]])
             Mi = np.block([[PMP, (P.T @ Mu)[:, None]], [(P.T @ Mu)[None, :], np.array([[u @ Mu]])]])
             ev, X = sla.eigh(Ki, Mi, subset_by_index=[0, n_keep - 1])
-            lam[i], x = select_eigenpair(ev, X, n_keep)
+            lam[i], x = select_eigenpair(ev, X, Mi, n_keep)
             phiH[:, i] = x[:-1]
             thetas[i] = x[-1]
             Phi_new[:, i] = P @ x[:-1] + x[-1] * u

@@ -312,6 +312,54 @@ double border_weight(const Tridiag& T, const double* u, double alpha, double mu)
   return 1.0 / std::sqrt(1.0 + z2);
 }
 
+void eigenvector_from(const Tridiag& T, const double* u, double alpha, double mu, const double* y0, double s0,
+                      double* y, double* s) {
+  const int64_t n = T.n;
+  std::vector<double> x(y0, y0 + n), xn(n);
+  double t = u ? s0 : 0.0, tn;
+  const double eps = std::numeric_limits<double>::epsilon();
+  const double mus = mu + eps * std::max(1.0, std::fabs(mu)) * 16.0;
+  for (int it = 0; it < 3; ++it) {
+    double nr = t * t;
+    for (int64_t j = 0; j < n; ++j) nr += x[j] * x[j];
+    nr = std::sqrt(nr);
+    if (!(nr > 0.0)) break;
+    for (int64_t j = 0; j < n; ++j) x[j] /= nr;
+    t /= nr;
+    bordered_solve(T, u, alpha, mus, x.data(), t, xn.data(), &tn);
+    x.swap(xn);
+    t = u ? tn : 0.0;
+  }
+  double nr = t * t;
+  for (int64_t j = 0; j < n; ++j) nr += x[j] * x[j];
+  nr = std::sqrt(nr);
+  for (int64_t j = 0; j < n; ++j) y[j] = nr > 0.0 ? x[j] / nr : 0.0;
+  if (s) *s = nr > 0.0 ? t / nr : 0.0;
+}
+
+int select_projection(const Tridiag& T, const double* u, double alpha, const std::vector<double>& ev,
+                      const double* vy, double vs, double* y, double* s, double* proj) {
+  const int64_t n = T.n;
+  std::vector<double> xy(n);
+  double xs = 0.0, best = -1.0;
+  int jbest = 0;
+  for (int j = 0; j < (int)ev.size(); ++j) {
+    eigenvector_from(T, u, alpha, ev[j], vy, vs, xy.data(), &xs);
+    double p = xs * vs;
+    for (int64_t k = 0; k < n; ++k) p += xy[k] * vy[k];
+    const double ap = std::fabs(p);
+    if (ap > best * (1.0 + 1e-10)) {
+      best = ap;
+      jbest = j;
+      const double sg = p < 0.0 ? -1.0 : 1.0;
+      for (int64_t k = 0; k < n; ++k) y[k] = sg * xy[k];
+      *s = sg * xs;
+    }
+  }
+  *proj = best;
+  return jbest;
+}
+
 void eigenvector(const Tridiag& T, const double* u, double alpha, double mu, double* y, double* s) {
   int64_t n = T.n;
   std::vector<double> x(n), xn(n);

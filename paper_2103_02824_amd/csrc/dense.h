@@ -37,6 +37,19 @@ std::vector<double> lowest_eigenvalues(const Tridiag& T, const double* u, double
 // Eigenvector of K for eigenvalue mu by inverse iteration (normalised).
 // Output: y (n) and s (border coordinate; unused when u is null).
 void eigenvector(const Tridiag& T, const double* u, double alpha, double mu, double* y, double* s);
+// Eigenvector of K for eigenvalue mu by inverse iteration from the start
+// vector [y0; s0] (normalised). Within a repeated eigenvalue the iteration
+// keeps the direction of the start vector's projection onto the eigenspace.
+void eigenvector_from(const Tridiag& T, const double* u, double alpha, double mu, const double* y0, double s0,
+                      double* y, double* s);
+// Algorithm 2 (a) in the coordinates of K: v = [vy; vs] are the coordinates
+// of u_i. Among the eigenvalues ev (ascending) the eigenvector x with the
+// largest |x . v| (the largest component of u_i; within a repeated eigenvalue
+// the normalised projection of v onto its eigenspace), the first of equal
+// values (to 1e-10 relative) winning. Returns its index; y, s: x with
+// x . v > 0; *proj = x . v.
+int select_projection(const Tridiag& T, const double* u, double alpha, const std::vector<double>& ev,
+                      const double* vy, double vs, double* y, double* s, double* proj);
 // |s| of the normalised eigenvector of K for eigenvalue mu (border weight),
 // O(n): 1/sqrt(1 + |(T - mu)^{-1} u|^2) when [(T - mu)^{-1} u; -1] is an
 // eigenvector of K to 1e-9 |K| relative residual, and 0 otherwise (mu is then

@@ -12,8 +12,9 @@
 // Q T Q^T (M_H = L L^T). For orbital i the border (b, beta; c, gamma) is first
 // made M-orthogonal to V_H (a = M_H^{-1} c), which turns the pencil into the
 // standard symmetric problem [[T, u], [u^T, alpha]] of order N_H + 1; its
-// lowest eigenvalues come from bisection on inertia counts and the chosen
-// eigenvector from inverse iteration, both O(N_H) per evaluation.
+// lowest eigenvalues come from bisection on inertia counts, and the kept
+// eigenvector (the largest component in span{u_i}) from inverse iteration
+// started at u_i's coordinates, both O(N_H) per evaluation.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -291,6 +292,17 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
     gpv[i] = gam - ca;
     if (!(gpv[i] > 1e-14 * std::fabs(gam))) return fail(c, MLC_ERR_NONFINITE, "auxiliary solution lies in the coarse space");
   }
+  // L^T a_i: the coarse part of u_i in the M-orthonormal coordinates of V_H
+  std::vector<double> LTa(nH * N, 0.0);
+#pragma omp parallel for schedule(static) if (N > 1)
+  for (int i = 0; i < N; ++i) {
+    const double* ai = &aM[(int64_t)i * nH];
+    double* o = &LTa[(int64_t)i * nH];
+    for (int64_t r = 0; r < nH; ++r) {
+      const double* Lr = &L[r * nH];
+      for (int64_t k = 0; k <= r; ++k) o[k] += Lr[k] * ai[r];
+    }
+  }
   int n_keep = (int)std::min<int64_t>(nH + 1, (int64_t)N + c->opt.n_extra);
   int its = 0;
   double diff = 0.0;
@@ -314,7 +326,7 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
     int bad = 0;
 #pragma omp parallel if (N > 1)
     {
-      std::vector<double> b(nH), Aa(nH), u(nH), y(nH), tmp(nH);
+      std::vector<double> b(nH), Aa(nH), u(nH), y(nH), tmp(nH), vy(nH);
 #pragma omp for schedule(dynamic, 1) reduction(+ : bad)
       for (int i = 0; i < N; ++i) {
         const double* ai = &aM[(int64_t)i * nH];
@@ -335,21 +347,14 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
         apply_QT(Tr, u.data());
         double alpha = bp / gp;
         std::vector<double> ev = lowest_eigenvalues(Tr, u.data(), alpha, n_keep);
-        int jsel = 0;
-        double wbest = -1.0;
-        for (int j = 0; j < n_keep; ++j) {
-          double wj = border_weight(Tr, u.data(), alpha, ev[j]);
-          if (wj > wbest) {
-            wbest = wj;
-            jsel = j;
-          }
-        }
-        double sv;
-        eigenvector(Tr, u.data(), alpha, ev[jsel], y.data(), &sv);
-        if (sv < 0) {
-          sv = -sv;
-          for (int64_t k = 0; k < nH; ++k) y[k] = -y[k];
-        }
+        // (a): the eigenfunction with the largest component in span{u_i}; u_i
+        // has the coordinates [Q^T L^T a_i; sqrt(gamma')] (its coarse part P a_i
+        // and its part M-orthogonal to V_H)
+        std::copy(&LTa[(int64_t)i * nH], &LTa[(int64_t)i * nH] + nH, vy.begin());
+        apply_QT(Tr, vy.data());
+        double sv, pj;
+        const int jsel = select_projection(Tr, u.data(), alpha, ev, vy.data(), sg, y.data(), &sv, &pj);
+        (void)pj;
         apply_Q(Tr, y.data());
         backward(L, nH, y.data());
         double t2 = sv / sg;

@@ -28,3 +28,24 @@ extern "C" void probe_bordered(const double* C0, const double* uc, double alpha,
     s_out[j] = s;
   }
 }
+
+// The selection of Algorithm 2 (a) as the library runs it: the k lowest
+// eigenvalues of [[T, u], [u^T, alpha]] and, among them, the eigenvector with
+// the largest component along v = [vy; vs] (vy in the basis of C). Output:
+// the eigenvalues, the index kept, its eigenvector (y in the basis of C, s)
+// with x . v > 0, and x . v.
+extern "C" int probe_select(const double* C0, const double* uc, double alpha, int n, int k, const double* vyc,
+                            double vs, double* ev_out, double* y_out, double* s_out, double* proj_out) {
+  std::vector<double> C(C0, C0 + (std::size_t)n * n);
+  Tridiag Tr;
+  tridiagonalize(C, n, Tr);
+  std::vector<double> u(uc, uc + n), vy(vyc, vyc + n), y(n);
+  apply_QT(Tr, u.data());
+  apply_QT(Tr, vy.data());
+  std::vector<double> ev = lowest_eigenvalues(Tr, u.data(), alpha, k);
+  for (int j = 0; j < k; ++j) ev_out[j] = ev[j];
+  int j = select_projection(Tr, u.data(), alpha, ev, vy.data(), vs, y.data(), s_out, proj_out);
+  apply_Q(Tr, y.data());
+  for (int r = 0; r < n; ++r) y_out[r] = y[r];
+  return j;
+}

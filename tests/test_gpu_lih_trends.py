@@ -1,0 +1,46 @@
+"""The paper's first model, LiH (Section 4: Li Z = 3 at (-1.0075, 0, 0), H at
+(2.0075, 0, 0), bare Coulomb, X-alpha, box (-6, 6)^3, two doubly occupied
+orbitals), stepped by the library over sixteen outer iterations on the small
+mesh pair, with the inner iteration converged at every step. Reproduced
+qualitatively, not in value (the paper's adaptive meshes and tolerances are
+not given): the inner iteration count falls as the outer iteration
+approaches the ground state, because each inner loop starts from the
+Hartree potential of the newest orbitals (Section 4.1, the table of inner
+and outer iteration numbers for LiH); and the largest overlap between the
+two orbitals, which the method does not orthogonalise, shrinks as the outer
+iteration converges towards the discrete eigenfunctions (the orthogonality
+tables of Section 4.3 report it at 1e-4 to 1e-9 on the final meshes)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_lih_inner_counts_and_orthogonality_over_outer_steps(gpu):
+    from inputs.systems import lih_small
+    from paper_2103_02824_amd import mlc
+    S = lih_small()
+    print(f"case LiH small: {len(S.xyz)} vertices, sixteen outer steps", flush=True)
+    ctx = mlc.Context(S, mlc.options(cg_rtol=1e-11, poisson_rtol=1e-12, inner_tol=1e-10, inner_maxit=300,
+                                     precond=mlc.PC_CHEBYSHEV, cheb_degree=8, cheb_ratio=100.0, hartree_coarse=1))
+    ctx.initial_state(tol=1e-10, maxit=300)
+    inner, ovl, dlam = [], [], []
+    lam_prev = ctx.get_results()[0]
+    for k in range(16):
+        rep = ctx.correction_step(allow_warn=False)
+        lam = ctx.get_results()[0]
+        inner.append(rep["inner_iters"])
+        ovl.append(rep["max_offdiag_overlap"])
+        dlam.append(float(np.max(np.abs(lam - lam_prev))))
+        lam_prev = lam
+        print(f"outer {k + 1}: inner {rep['inner_iters']}, lambda {lam}, |d lambda| {dlam[-1]:.2e}, "
+              f"overlap {ovl[-1]:.2e}, int rho {rep['rho_integral']:.12f}", flush=True)
+        assert abs(rep["rho_integral"] - 4.0) < 1e-9
+    # the paper's pattern: fewer inner iterations as the outer iteration converges
+    assert inner[-1] < inner[0], inner
+    assert all(b <= a + 1 for a, b in zip(inner[1:], inner[2:])), inner   # non-increasing after the first
+    # the outer iteration converges (linearly) and the orbitals become orthogonal
+    assert dlam[-1] < 1e-3 * dlam[0], dlam
+    assert all(b <= 1.001 * a for a, b in zip(ovl[8:], ovl[9:])), ovl
+    assert ovl[-1] < 0.3 * ovl[0], ovl
+    ctx.close()

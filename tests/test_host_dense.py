@@ -1,8 +1,9 @@
 """The library's host eigen-solver for the augmented problems (Algorithm 3
 step 2: per orbital the bordered matrix [[T, u], [u^T, alpha]], its lowest
-eigenvalues by bisection, the eigenpair of largest border weight |theta_2|
-kept), compiled for the CPU with g++ and checked against numpy's dense
-symmetric eigensolver on the same matrix.
+eigenvalues by bisection, the border weights |theta_2| of its eigenvectors,
+and the eigenpair with the largest component along u_i kept), compiled for
+the CPU with g++ and checked against numpy's dense symmetric eigensolver on
+the same matrix and against the checker's selection.
 
 The cases include degenerate spectra: symmetric meshes give coarse operators
 with repeated eigenvalues, and their tridiagonal form can split exactly into
@@ -102,33 +103,45 @@ def test_bordered_eigenpairs_match_dense_eigh(lib, name, C, u, alpha):
     assert np.linalg.norm(y - v) < wtol  # gap to the nearest eigenvalue: 1e-6 in the wide case
 
 
-def test_harmonic_oscillator_augmented_problems_select_as_the_checker(lib):
-    """The augmented problems of one inner iteration of the harmonic
-    oscillator (6^3 coarse mesh, 12^3 fine, four orbitals: the ground state
-    and the degenerate triplet), built by the checker. Symmetry makes many
-    coarse eigenvectors orthogonal to each u_i, so most of the lowest
-    eigenvalues of each augmented problem carry theta_2 = 0. The library's
-    reduction to [[T, u], [u^T, alpha]] (C = L^-1 A_H L^-T with M_H = L L^T,
-    the border made M-orthogonal to V_H: a = M_H^-1 c, gamma' = gamma - c.a)
-    must give the weights |theta_2| sqrt(gamma') of the checker's generalized
-    eigenvectors and select the same eigenpair."""
+def _select(lib, C, u, alpha, k, vy, vs):
+    n = len(u)
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    vy = np.ascontiguousarray(vy, dtype=np.float64)
+    ev = np.zeros(k)
+    y = np.zeros(n)
+    s, pj = ctypes.c_double(), ctypes.c_double()
+    lib.probe_select.restype = ctypes.c_int
+    lib.probe_select.argtypes = [P, P, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, ctypes.c_double, P, P,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    j = lib.probe_select(C.ctypes.data_as(P), u.ctypes.data_as(P), alpha, n, k, vy.ctypes.data_as(P), vs,
+                         ev.ctypes.data_as(P), y.ctypes.data_as(P), ctypes.byref(s), ctypes.byref(pj))
+    return j, ev, y, s.value, pj.value
+
+
+def _augmented_cases(system, n_orbitals_check=None):
+    """The augmented problems of one inner iteration at (w_H, theta1) = (0, 1),
+    built by the checker, with the library's reduction to [[T, u], [u^T,
+    alpha]] in the basis of C = L^-1 A_H L^-T (M_H = L L^T; the border made
+    M-orthogonal to V_H: a = M_H^-1 c, gamma' = gamma - c.a) and the
+    coordinates [L^T a; sqrt(gamma')] of u_i."""
     import scipy.linalg as sla
-    from inputs.systems import harmonic
-    from oracle.mlc import Options, Problem, augmented_blocks, fine_stage, select_eigenpair
+    from oracle.mlc import Options, Problem, augmented_blocks, fine_stage
     from oracle.scf import initial_state
-    S = harmonic(12, 6, n_orbitals=4)
-    prob = Problem(S)
+    prob = Problem(system)
     st0, _ = initial_state(prob, maxit=300)
     fs = fine_stage(prob, st0, Options(shift=True, sigma0=1.0))
     U, P = fs["U"], prob.P
-    H, _ = augmented_blocks(prob, U, fs["w0"], fs["g"], fs["vxc"])
+    H, Mw0 = augmented_blocks(prob, U, fs["w0"], fs["g"], fs["vxc"])
+    if Mw0 is not None:
+        H = H + Mw0
     AH = (P.T @ H @ P).toarray()
     MH = (P.T @ prob.M @ P).toarray()
     n_keep = min(prob.NH + 1, prob.N + 8)
-    Li = np.linalg.inv(np.linalg.cholesky(MH))
+    L = np.linalg.cholesky(MH)
+    Li = np.linalg.inv(L)
     C = Li @ AH @ Li.T
     C = 0.5 * (C + C.T)
-    n_zero = 0
     for i in range(prob.N):
         u = U[:, i]
         Hu, Mu = H @ u, prob.M @ u
@@ -137,14 +150,73 @@ def test_harmonic_oscillator_augmented_problems_select_as_the_checker(lib):
         gp = gam - c @ a
         ub = Li @ (b - AH @ a) / np.sqrt(gp)
         alpha = (beta - 2.0 * b @ a + a @ AH @ a) / gp
-        ev, w, _, _ = _run(lib, C, ub, alpha, n_keep)
         Ki = np.block([[AH, b[:, None]], [b[None, :], np.array([[beta]])]])
         Mi = np.block([[MH, c[:, None]], [c[None, :], np.array([[gam]])]])
         lam, X = sla.eigh(Ki, Mi, subset_by_index=[0, n_keep - 1])
-        theta = np.abs(X[-1, :]) * np.sqrt(gp)
+        yield dict(C=C, ub=ub, alpha=alpha, n_keep=n_keep, gp=gp, a=a, L=L, Li=Li, lam=lam, X=X, Mi=Mi)
+
+
+def test_harmonic_oscillator_augmented_problems_select_as_the_checker(lib):
+    """The augmented problems of one inner iteration of the harmonic
+    oscillator (6^3 coarse mesh, 12^3 fine, four orbitals: the ground state
+    and the degenerate triplet), built by the checker. Symmetry makes many
+    coarse eigenvectors orthogonal to each u_i, so most of the lowest
+    eigenvalues of each augmented problem carry theta_2 = 0. The library's
+    reduction must give the checker's eigenvalues and border weights
+    |theta_2| sqrt(gamma') of its generalized eigenvectors, and its selection
+    (the largest component in span{u_i}) the checker's eigenpair: the same
+    eigenvalue, coarse coefficients and theta_2."""
+    from inputs.systems import harmonic
+    from oracle.mlc import select_eigenpair
+    n_zero = 0
+    for cs in _augmented_cases(harmonic(12, 6, n_orbitals=4)):
+        ev, w, _, _ = _run(lib, cs["C"], cs["ub"], cs["alpha"], cs["n_keep"])
+        lam, X = cs["lam"], cs["X"]
+        theta = np.abs(X[-1, :]) * np.sqrt(cs["gp"])
         assert np.max(np.abs(ev - lam)) < 1e-11 * np.max(np.abs(lam))
-        assert np.max(np.abs(w - theta)) < 1e-10, (i, w, theta)
-        lsel, _ = select_eigenpair(lam, X, n_keep)
-        assert ev[int(np.argmax(w))] == pytest.approx(lsel, abs=1e-11)
+        assert np.max(np.abs(w - theta)) < 1e-10, (w, theta)
         n_zero += int(np.sum(theta < 1e-12))
+        _check_selection(lib, cs, select_eigenpair)
     assert n_zero >= 20  # the symmetric spectrum decouples most candidates
+
+
+def _check_selection(lib, cs, select_eigenpair):
+    sq = np.sqrt(cs["gp"])
+    j, ev, y, s, pj = _select(lib, cs["C"], cs["ub"], cs["alpha"], cs["n_keep"], cs["L"].T @ cs["a"], sq)
+    lsel, x = select_eigenpair(cs["lam"], cs["X"], cs["Mi"], cs["n_keep"])
+    assert ev[j] == pytest.approx(lsel, abs=1e-11 * max(1.0, abs(lsel)))
+    # library eigenvector in coarse coefficients and theta_2: phi = P (L^-T y - theta2 a) + theta2 u
+    t2 = s / sq
+    coarse = cs["Li"].T @ y - t2 * cs["a"]
+    assert abs(t2 - x[-1]) < 1e-8 * max(1.0, abs(x[-1])), (t2, x[-1])
+    assert np.linalg.norm(coarse - x[:-1]) < 1e-8 * max(1.0, np.linalg.norm(x[:-1]))
+    assert pj > 0
+
+
+def test_selection_on_a_nonlinear_cluster_matches_the_checker(lib):
+    """The same comparison on the first inner iteration of a small 4-atom
+    cluster (LDA and Hartree, five orbitals, graded meshes), where the
+    eigenvalues are distinct."""
+    from inputs.systems import c2_small
+    from oracle.mlc import select_eigenpair
+    for cs in _augmented_cases(c2_small(1)):
+        _check_selection(lib, cs, select_eigenpair)
+
+
+def test_selection_prefers_the_component_along_u(lib):
+    """A constructed case that separates the two readings of 'largest
+    component in span{u_i}': a coupled eigenvector with the larger border
+    weight but a small projection onto u against one with a smaller weight
+    and the larger projection. The projection decides."""
+    rng = np.random.default_rng(5)
+    n = 6
+    C = _sym(rng, np.array([0.0, 1.0, 2.0, 3.0, 4.0, 5.0]))
+    u = rng.standard_normal(n) * 0.3
+    alpha = 0.4
+    K = np.block([[C, u[:, None]], [u[None, :], np.array([[alpha]])]])
+    lam, V = np.linalg.eigh(K)
+    v = V[:, 2] * 0.9 + V[:, 0] * np.sqrt(1 - 0.81)          # u_i's coordinates: mostly the third eigenvector
+    j, ev, y, s, pj = _select(lib, C, u, alpha, 4, v[:n], v[n])
+    assert j == 2 and abs(pj - 0.9) < 1e-9
+    # the largest border weight |theta_2| (the other reading) would keep the second eigenvector
+    assert int(np.argmax(np.abs(V[n, :4]))) == 1
