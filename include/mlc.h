@@ -340,6 +340,17 @@ mlc_status mlc_nn_set_params(mlc_nn* nn, const float* theta);
 mlc_status mlc_nn_get_params(mlc_nn* nn, float* theta);
 mlc_status mlc_nn_forward(mlc_nn* nn, const float* x, int64_t rows, float* y);
 mlc_status mlc_nn_loss_grad(mlc_nn* nn, const float* x, const float* t, int64_t rows, double* loss, float* grad);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): mlc_nn_loss_grad
+ * with its scratch (per-block gradient and loss partials, the reduced
+ * gradient and the loss; 9.05 MB) in a device-resident array of the library
+ * instead of the network's workspace. Same arguments, results and errors as
+ * mlc_nn_loss_grad; rows above 2^31 - 1 are MLC_ERR_ARG. It calls no
+ * hipMalloc or hipFree and allocates nothing on the device. Each GPU holds
+ * one copy of the array until the process ends and every call on that GPU
+ * uses it: calls that overlap on one GPU (several streams or threads) race. */
+mlc_status mlc_nn_loss_grad_noalloc(mlc_nn* nn, const float* x, const float* t, int64_t rows, double* loss,
+                                    float* grad);
 mlc_status mlc_nn_adam(mlc_nn* nn, const float* grad, double lr, double beta1, double beta2, double eps);
 mlc_status mlc_nn_train(mlc_nn* nn, const float* x, const float* t, int64_t rows, int32_t steps, int32_t batch,
                         double lr, float* loss_history);

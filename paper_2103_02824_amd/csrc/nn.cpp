@@ -155,6 +155,31 @@ mlc_status mlc_nn_loss_grad(mlc_nn* nn, const float* x, const float* t, int64_t 
   return MLC_OK;
 }
 
+mlc_status mlc_nn_loss_grad_noalloc(mlc_nn* nn, const float* x, const float* t, int64_t rows, double* loss,
+                                    float* grad) {
+  if (!nn || !x || !t || rows < 1 || !loss || !grad) return MLC_ERR_ARG;
+  if (rows > mlc::NN_STATIC_MAX_ROWS)
+    return nfail(nn, MLC_ERR_ARG, "rows above the allocation-free call's limit (2^31 - 1)");
+  mlc_status st = ready(nn);
+  if (st != MLC_OK) return st;
+  hipStream_t s = nn->stream;
+  hipDevice_t dev = -1;  // the GPU the network's stream runs on (the null stream: the current device)
+  if (s)
+    NCHK(hipStreamGetDevice(s, &dev));
+  else
+    NCHK(hipGetDevice(&dev));
+  // the network's parameters and bf16 tables from its workspace; partials,
+  // gradient and loss in the device-resident scratch of this GPU
+  mlc::NnDev d = nn->d;
+  NCHK(mlc::nn_static_scratch(dev, &d));
+  mlc::launch_nn_grad(s, d, x, t, rows, 0, 1, rows, 0);
+  NCHK(hipGetLastError());
+  NCHK(hipMemcpyAsync(grad, d.grad, mlc::NN_NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
+  NCHK(hipMemcpyAsync(loss, d.loss, sizeof(double), hipMemcpyDeviceToHost, s));
+  NCHK(hipStreamSynchronize(s));
+  return MLC_OK;
+}
+
 mlc_status mlc_nn_adam(mlc_nn* nn, const float* grad, double lr, double beta1, double beta2, double eps) {
   if (!nn || !grad || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
     return MLC_ERR_ARG;

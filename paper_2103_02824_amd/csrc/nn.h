@@ -39,6 +39,7 @@ struct NnDev {
 
 constexpr int NN_GRAD_MAX_BLOCKS = 256;
 constexpr int NN_MAX_STEPS = 100000;
+constexpr int64_t NN_STATIC_MAX_ROWS = 2147483647;
 
 // bf16 tables from theta (all of them; zero padding of w1b).
 void launch_nn_prepare(hipStream_t s, const NnDev& d);
@@ -49,6 +50,11 @@ void launch_nn_forward(hipStream_t s, const NnDev& d, const float* X, int64_t m,
 // the loss into d.loss[slot].
 void launch_nn_grad(hipStream_t s, const NnDev& d, const float* X, const float* T, int64_t m, uint64_t start,
                     uint64_t stride, int64_t M, int slot);
+// The allocation-free loss/gradient call's scratch: a device-resident array of
+// nn_static_scratch_bytes() bytes per GPU; sets d->gpart, lpart, grad and loss
+// to its parts on the given device (its address is looked up once per device).
+size_t nn_static_scratch_bytes();
+hipError_t nn_static_scratch(int device, NnDev* d);
 // One Adam step with d.grad; c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t).
 void launch_nn_adam(hipStream_t s, const NnDev& d, float lr, float beta1, float beta2, float eps, float c1, float c2);
 

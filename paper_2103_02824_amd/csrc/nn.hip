@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
+#include <vector>
 
 #include "nn.h"
 
@@ -447,6 +449,53 @@ void launch_nn_grad(hipStream_t s, const NnDev& d, const float* X, const float* 
   int nb = grad_blocks(m);
   hipLaunchKernelGGL(k_nn_grad, dim3(nb), dim3(BS), 0, s, d, X, T, m, start, stride, M);
   hipLaunchKernelGGL(k_nn_reduce, dim3((NN_NPARAM + BS - 1) / BS), dim3(BS), 0, s, d, nb, m, slot);
+}
+
+// ---- device-resident scratch of the allocation-free loss/gradient call ------
+// Per-block gradient partials (NN_GRAD_MAX_BLOCKS x NN_NPARAM floats), loss
+// partials (NN_GRAD_MAX_BLOCKS doubles), the reduced gradient (NN_NPARAM
+// floats) and the loss (one double), each at a 256-byte boundary. Every GPU
+// the library runs on holds one copy until the process ends; calls on one GPU
+// share it.
+namespace {
+constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t SCR_GPART = 0;
+constexpr size_t SCR_LPART = align256(SCR_GPART + sizeof(float) * (size_t)NN_GRAD_MAX_BLOCKS * NN_NPARAM);
+constexpr size_t SCR_GRAD = align256(SCR_LPART + sizeof(double) * NN_GRAD_MAX_BLOCKS);
+constexpr size_t SCR_LOSS = align256(SCR_GRAD + sizeof(float) * NN_NPARAM);
+constexpr size_t SCR_BYTES = align256(SCR_LOSS + sizeof(double));
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[SCR_BYTES];
+
+size_t nn_static_scratch_bytes() { return SCR_BYTES; }
+
+hipError_t nn_static_scratch(int device, NnDev* d) {
+  // the array's address on each device, looked up once per device with that
+  // device current (the host-side name is a stand-in, not a device address)
+  static std::mutex mu;
+  static std::vector<void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((int)addr.size() <= device) addr.resize(device + 1, nullptr);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  char* base = static_cast<char*>(addr[device]);
+  d->gpart = reinterpret_cast<float*>(base + SCR_GPART);
+  d->lpart = reinterpret_cast<double*>(base + SCR_LPART);
+  d->grad = reinterpret_cast<float*>(base + SCR_GRAD);
+  d->loss = reinterpret_cast<double*>(base + SCR_LOSS);
+  return hipSuccess;
 }
 
 void launch_nn_adam(hipStream_t s, const NnDev& d, float lr, float beta1, float beta2, float eps, float c1, float c2) {

@@ -34,7 +34,7 @@ EXPORTED = ["mlc_options_default", "mlc_create", "mlc_sizes", "mlc_workspace_byt
             "mlc_batch_last_error", "mlc_batch_destroy", "mlc_nn_create", "mlc_nn_workspace_bytes", "mlc_nn_bind",
             "mlc_nn_set_params", "mlc_nn_get_params", "mlc_nn_forward", "mlc_nn_loss_grad", "mlc_nn_adam",
             "mlc_nn_train", "mlc_nn_last_error", "mlc_nn_destroy", "mlc_set_guess", "mlc_set_sample_sink",
-            "mlc_sample_count"]
+            "mlc_sample_count", "mlc_nn_loss_grad_noalloc"]
 N_PARAMS = 8833
 
 
@@ -142,6 +142,8 @@ def lib():
     L.mlc_nn_forward.argtypes = [vp, vp, i64, vp]
     L.mlc_nn_loss_grad.argtypes = [vp, vp, vp, i64, P(dbl), fp]
     L.mlc_nn_adam.argtypes = [vp, fp, dbl, dbl, dbl, dbl]
+    L.mlc_nn_loss_grad_noalloc.argtypes = [vp, vp, vp, i64, P(dbl), fp]
+    L.mlc_nn_loss_grad_noalloc.restype = i32
     L.mlc_nn_train.argtypes = [vp, vp, vp, i64, i32, i32, dbl, fp]
     L.mlc_nn_last_error.argtypes = [vp]
     L.mlc_nn_last_error.restype = C.c_char_p
