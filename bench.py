@@ -74,17 +74,21 @@ def make_system(workload, seed):
     raise SystemExit(f"unknown workload {workload}")
 
 
-def cheb_bytes(n, nnz, N, word=8):
-    """Algorithmic bytes of one fused Chebyshev step: the SpMM's matrix and
-    row pointers, the inverse diagonal, Z read once (gathered), R read, the
-    step difference d read and written, Z written."""
-    return (word + 4) * nnz + 4 * (n + 1) + word * n + 5 * word * n * N
+def cheb_bytes(n, nnz, N, word=8, mword=None):
+    """Algorithmic bytes of one interior fused Chebyshev step (the launch
+    mlc_time_kernel replays): the SpMM's matrix (mword bytes per value,
+    default word) and row pointers, the inverse diagonal, the iterate z_{j-1}
+    read once (gathered), R read, z_{j-2} read and z_j written."""
+    mword = word if mword is None else mword
+    return (mword + 4) * nnz + 4 * (n + 1) + word * n + 4 * word * n * N
 
 
-def _kernel_name(which, N, word):
+def _kernel_name(which, N, word, n):
     """Profiler name of the kernel mlc_time_kernel replays: the CG SpMM and
     the Hartree SpMM run the partial-sum shape (1024-thread blocks), the
-    polynomial steps the 256-thread shape of the steps before the last."""
+    polynomial steps the 256-thread shape of the steps before the last. The
+    N > 8 kernels gather through 32-bit offsets when an n x N block spans
+    less than 4 GiB."""
     t = "float" if word == 4 else "double"
     if which in ("hartree_spmm", "hartree_cheb_step"):
         N, t = 1, "double"
@@ -96,13 +100,16 @@ def _kernel_name(which, N, word):
         while L < groups and L < 64:
             L *= 2
         nch = -(-groups // L)
+        o32 = "true" if n * N * word < 2 ** 32 else "false"
         if "spmm" in which:
-            return f"k_spmm_rows<{L}, {V}, {nch}, {t}>"
-        return f"k_cheb_rows<{L}, {V}, {nch}, false, {t}>"  # the steps without the r.z partials
+            return f"k_spmm_rows<{L}, {V}, {nch}, {o32}, {t}>"
+        return f"k_cheb_rows<{L}, {V}, {nch}, false, {o32}, {t}>"  # the steps without the r.z partials
     if "spmm" in which:
         unroll = 4 if N <= 3 else (2 if N <= 6 else 1)
         return f"k_spmm_small<{N}, 4, {unroll}, 1024, {8 if N <= 6 else 4}, {t}>"
-    return f"k_cheb_small<{N}, 4, {4 if N <= 6 else 2}, 256, {8 if N <= 2 else 4}, {t}>"
+    # the matrix-value type: FP32 in the Hartree problem's polynomial steps
+    mt = "float" if which == "hartree_cheb_step" else t
+    return f"k_cheb_small<{N}, 4, {4 if N <= 6 else 2}, 256, {8 if N <= 2 else 4}, {t}, {mt}>"
 
 
 def spmm_bytes(n, nnz, N, word=8):
@@ -222,7 +229,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "batch"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c1", "batch", "learned"],
                     help="c3: 40-atom cluster, 2e6 DoF x 52 orbitals, FP32 CG + FP64 refinement (default); c2: "
                          "4-atom cluster, 2e5 DoF; c1: hydrogen; batch: uneven clusters")
     ap.add_argument("--seed", type=int, default=None, help="cluster seed (default 0 for c3, 1 for c2)")
@@ -267,6 +274,8 @@ def main():
                     help="--workload batch: inner iterations per step (host, reported apart from the GPU time)")
     ap.add_argument("--train-steps", type=int, default=800,
                     help="--workload batch: Adam steps of the learned-guess network")
+    ap.add_argument("--train-systems", type=int, default=60,
+                    help="--workload learned: 4-atom clusters (seeds 1000, ...) whose steps give the training rows")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this size twice (hardware counter calibration)")
     args = ap.parse_args()
@@ -296,6 +305,8 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "learned":
+        return run_learned(args)
     t_all = time.perf_counter()
     log(f"[bench] building workload {args.workload} seed {args.seed}")
     S = make_system(args.workload, args.seed)
@@ -343,13 +354,14 @@ def main():
         cands += [("cheb_step", N, word, (deg - 1) * (it5 + 1)), ("hartree_cheb_step", 1, 8, (deg - 1) * (itp + 1))]
     for which, ncol, w, launches in cands:
         us = ctx.time_kernel(which, n_replay)
-        nbytes = spmm_bytes(n, nnz, ncol, w) if "spmm" in which else cheb_bytes(n, nnz, ncol, w)
+        nbytes = (spmm_bytes(n, nnz, ncol, w) if "spmm" in which else
+                  cheb_bytes(n, nnz, ncol, w, 4 if which == "hartree_cheb_step" else w))
         kern[which] = {"avg_launch_us": round(us, 2), "bytes_per_launch": nbytes,
                        "achieved_GBs": round(nbytes / (us * 1e-6) / 1e9, 1), "launches_per_step": round(launches, 1),
                        "ms_per_step": round(us * launches / 1e3, 3)}
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     kd = kern[dom]
-    kname = _kernel_name(dom, N, word)
+    kname = _kernel_name(dom, N, word, n)
     achieved = kd["achieved_GBs"]
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -503,24 +515,28 @@ def _batch_contexts(systems, mlc, states, **kw):
     return ctxs
 
 
-def train_guess_network(mlc, args, opts):
+def train_guess_network(mlc, args, opts, n_systems=4, steps_per_system=3, stride=1, cap=600000):
     """Samples from the library's own steps on small 4-atom clusters (seeds
-    1000-1003, not in the batch), then GPU training by the library."""
+    1000, 1001, ..., not in the batch), then GPU training by the library."""
     import torch
     from inputs.nn_init import init_params
     from inputs.systems import c2_small
-    cap = 600000
     sx = torch.zeros((cap, 6), dtype=torch.float32, device="cuda")
     st = torch.zeros(cap, dtype=torch.float32, device="cuda")
     rows = 0
-    for seed in range(1000, 1004):
+    t0 = time.perf_counter()
+    for seed in range(1000, 1000 + n_systems):
+        if rows >= cap:
+            break
         ctx = mlc.Context(c2_small(seed), mlc.options(**opts))
         ctx.initial_state(tol=1e-9, maxit=300)
-        ctx.set_sample_sink(sx[rows:], st[rows:], stride=1)
-        for _ in range(3):
+        ctx.set_sample_sink(sx[rows:], st[rows:], stride=stride)
+        for _ in range(steps_per_system):
             ctx.correction_step()
         rows += ctx.sample_count()
         ctx.close()
+        if (seed - 1000) % 10 == 9:
+            log(f"[bench] training samples from {seed - 999} systems: {rows} rows, {time.perf_counter() - t0:.0f} s")
     net = mlc.Network()
     net.set_params(init_params(11, out_scale=0.01))
     t0 = time.perf_counter()
@@ -528,6 +544,62 @@ def train_guess_network(mlc, args, opts):
     log(f"[bench] trained guess network on {rows} rows, {args.train_steps} steps in {time.perf_counter()-t0:.1f} s, "
         f"loss {np.mean(hist[:20]):.3e} -> {np.mean(hist[-20:]):.3e}")
     return net, rows, float(np.mean(hist[:20])), float(np.mean(hist[-20:]))
+
+
+def run_learned(args):
+    """The learned initial guess at the 40-atom workload: the network is
+    trained by the library on rows of its own steps on small 4-atom clusters
+    of the 4-atom distribution (seeds 1000, ...), then the 40-atom step
+    (FP32 CG + FP64 refinement to 1e-9, the benchmark's preconditioners) is
+    run from the interpolated coarse state with the plain start (phi) and
+    with the learned start, alternately; reported: CG iterations, refinement
+    passes and GPU times of each."""
+    import torch
+    from paper_2103_02824_amd import mlc
+    t_all = time.perf_counter()
+    base = dict(cg_rtol=args.cg_rtol, poisson_rtol=args.cg_rtol, inner_maxit=30, inner_tol=args.inner_tol)
+    net, rows, l0, l1 = train_guess_network(mlc, args, base, n_systems=args.train_systems, steps_per_system=2,
+                                            stride=2, cap=4000000)
+    S = make_system("c3", args.seed)
+    opts = _opts(mlc, args, mlc.PREC_FP32_IR, args.precond, args.hartree_coarse)
+    opts.inner_maxit = 6
+    ctx = mlc.Context(S, opts)
+    ctx.initial_state(tol=1e-10, maxit=60)
+    lam0, Phi0, w0, _ = ctx.get_results_device()
+    state0 = (lam0, Phi0.clone(), w0.clone())
+    res = {"plain": [], "learned": []}
+    for k in range(1 + args.steps):
+        for name in ("plain", "learned"):
+            ctx.set_guess(net if name == "learned" else None)
+            ctx.set_state(*state0)
+            rep = ctx.correction_step()
+            log(f"[bench] 40-atom step, {name} start: solve {rep['t_solve_ms']:.2f} ms, fine {rep['t_fine_ms']:.2f} ms, "
+                f"cg {rep['cg_iters_max']} (sum {rep['cg_iters_sum']}), refinement passes {rep['ir_outer']}, "
+                f"learned columns {rep['guess_learned_cols']}, residual ratio {rep['guess_resid_ratio']:.3f}")
+            if k > 0:
+                res[name].append(rep)
+    summary = {}
+    for name, reps in res.items():
+        summary[name] = {"t_fine_ms": float(np.mean([r["t_fine_ms"] + r["t_recon_ms"] for r in reps])),
+                         "t_solve_ms": float(np.mean([r["t_solve_ms"] for r in reps])),
+                         "cg_iters_max": int(reps[-1]["cg_iters_max"]), "cg_iters_sum": int(reps[-1]["cg_iters_sum"]),
+                         "refinement_passes": int(reps[-1]["ir_outer"]),
+                         "learned_cols": int(reps[-1]["guess_learned_cols"]),
+                         "guess_resid_ratio": float(reps[-1]["guess_resid_ratio"])}
+    n, N = ctx.n_dof, ctx.N
+    out = {"metric": "fine-mesh SCF correction step: DoF*orbitals/s and % HBM roofline vs plain FP64",
+           "value": n * N / (summary["learned"]["t_fine_ms"] / 1e3), "unit": "DoF*orbitals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": summary["learned"]["t_fine_ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64-refinement", "data": "synthetic",
+           "config": {"workload": f"40-atom seeded cluster (seed {args.seed}), graded P1 mesh, learned start",
+                      "n_dof": n, "orbitals": N, "training": f"{rows} rows from {args.train_systems} 4-atom clusters"},
+           "roofline": None, "cpu_baseline": None,
+           "detail": dict(summary, training_rows=rows, training_loss=[l0, l1],
+                          speedup_of_learned=summary["plain"]["t_fine_ms"] / summary["learned"]["t_fine_ms"],
+                          total_wall_s=time.perf_counter() - t_all)}
+    ctx.close()
+    net.close()
+    print(json.dumps(out), flush=True)
 
 
 def run_batch(args):

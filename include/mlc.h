@@ -153,7 +153,17 @@ typedef struct {
                            (same fixed point, converges where the plain
                            iteration oscillates); 0..16                       */
   double inner_mix_beta;  /* Anderson damping in (0, 1]                       */
+  int32_t variant;      /* MLC_VARIANT_EIGENPAIRWISE: Algorithm 2 as printed,
+                           one augmented space V_H + span{u_i} per orbital (the
+                           paper's method); MLC_VARIANT_JOINT: the earlier
+                           multilevel correction method it is compared with,
+                           one space V_H + span{u_1..u_N} whose lowest N
+                           eigenpairs are the orbitals (needs the N(N+1)/2
+                           pair integrals (u_j u_l, psi_k) from the fine
+                           mesh; N <= 64)                                      */
 } mlc_options;
+
+enum { MLC_VARIANT_EIGENPAIRWISE = 0, MLC_VARIANT_JOINT = 1 };
 
 enum { MLC_PC_JACOBI = 0, MLC_PC_CHEBYSHEV = 1 };
 
@@ -191,7 +201,7 @@ typedef struct mlc_ctx mlc_ctx;
  * n_extra 8, reorder 1, time_kernels 0, use_graphs 1, precision FP64,
  * ir_inner_rtol 1e-4, ir_max_outer 30, precond Jacobi, cheb_degree 4,
  * cheb_ratio 30, hartree_coarse 0, hartree_precond -1, inner_mix_history 6,
- * inner_mix_beta 0.5. */
+ * inner_mix_beta 0.5, variant MLC_VARIANT_EIGENPAIRWISE. */
 void mlc_options_default(mlc_options* opt);
 
 /* Build a context: validates both meshes (positive volumes, indices in range,

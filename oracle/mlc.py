@@ -57,6 +57,7 @@ class Options:
     solver: str = "lu"          # "lu" (exact) or "pcg"
     inner_mix_history: int = 6  # Anderson history of the inner iteration; 0 = plain (as printed)
     inner_mix_beta: float = 0.5
+    variant: str = "eigenpairwise"  # or "joint": one augmented space for all orbitals
     pcg_rtol: float = 1e-13
 
 
@@ -280,13 +281,74 @@ def inner_scf(prob: Problem, fs: dict, opts: Options, x_start=None):
                 Afix=Afix, Mw0=Mw0, last_diff=diff)
 
 
+def inner_scf_joint(prob: Problem, fs: dict, opts: Options, x_start=None):
+    """The joint-space variant the paper compares against (the earlier
+    multilevel correction method, Section 2): Algorithm 2 with step (a)
+    replaced by one eigenproblem in V_H + span{u_1, ..., u_N} whose lowest N
+    eigenpairs are the new orbitals (M-orthonormal by construction); the
+    Hartree step, the mixing and the stopping test as in inner_scf. The sign
+    of each orbital follows the previous inner iterate ((phi^{s+1},
+    phi^s)_M > 0; the u_i for the first)."""
+    fine = prob.fine
+    P = prob.P
+    U, w0, g = fs["U"], fs["w0"], fs["g"]
+    Afix, Mw0 = augmented_blocks(prob, U, w0, g, fs["vxc"])
+    N, NH = prob.N, prob.NH
+    W = sp.hstack([P, sp.csr_matrix(U)]).tocsr()             # basis [P, u_1..u_N]
+    Mj = (W.T @ prob.M @ W).toarray()
+    KMj = (W.T @ (prob.K + prob.M) @ W).toarray()
+    if prob.hartree:
+        V = sp.hstack([P, sp.csr_matrix(w0[:, None])]).tocsr()
+        VKV = (V.T @ prob.K @ V).toarray()
+        lift = V.T @ (prob.KIB @ g[fine.bverts])
+    x_in = np.zeros(NH + 1)
+    x_in[-1] = 1.0 if prob.hartree else 0.0
+    if x_start is not None:
+        x_in = np.array(x_start, dtype=np.float64)
+    hist = []
+    X_old = np.zeros((NH + N, N))
+    X_old[NH:, :] = np.eye(N)                                # the first iterate: u_i
+    its = 0
+    for s in range(opts.inner_maxit):
+        its = s + 1
+        wH, th1 = x_in[:-1], float(x_in[-1])
+        H = Afix + prob.mass_ii(fine.at_qp(prob.Pfull_c @ wH))
+        if prob.hartree:
+            H = H + th1 * Mw0
+        Kj = (W.T @ H @ W).toarray()
+        lam, X = sla.eigh(Kj, Mj, subset_by_index=[0, N - 1])
+        sgn = np.sign(np.einsum("ai,ai->i", X, Mj @ X_old))
+        X = X * np.where(sgn == 0, 1.0, sgn)[None, :]
+        Phi_new = P @ X[:NH] + U @ X[NH:]
+        if prob.hartree:
+            rho = prob.density_qp(Phi_new)
+            rhs = 4.0 * np.pi * (V.T @ fine.load(rho)[fine.interior]) - lift
+            x_out = np.linalg.solve(VKV, rhs)
+        else:
+            x_out = x_in
+        Dx = X - X_old
+        diff = float(np.sqrt(np.einsum("ai,ai->", Dx, KMj @ Dx)))
+        X_old = X
+        if not prob.hartree or diff < opts.inner_tol or s == opts.inner_maxit - 1:
+            x_in = x_out
+            break
+        if opts.inner_mix_history > 0:
+            x_in = anderson_next(x_in, x_out - x_in, hist, VKV, opts.inner_mix_history, opts.inner_mix_beta)
+        else:
+            x_in = x_out
+    wH, th1 = x_in[:-1].copy(), float(x_in[-1])
+    return dict(lam=lam.copy(), Phi=P @ X_old[:NH] + U @ X_old[NH:], wH=wH, th1=th1, phiH=X_old[:NH].copy(),
+                D=X_old[NH:].copy(), theta2=np.diag(X_old[NH:]).copy(), inner_iters=its, Afix=Afix, Mw0=Mw0,
+                last_diff=diff)
+
+
 def correction_step(prob: Problem, st: State, opts: Options = None) -> StepResult:
     """One outer step l -> l+1 (Algorithm 1 steps 5-7). Outputs follow
     Algorithm 3 step 3: phi_i = phi_{i,H} + theta2_i u_i, and the Hartree
     potential w = g + P w_H + theta1 w0 on every fine vertex."""
     opts = opts or Options()
     fs = fine_stage(prob, st, opts)
-    inn = inner_scf(prob, fs, opts)
+    inn = inner_scf_joint(prob, fs, opts) if opts.variant == "joint" else inner_scf(prob, fs, opts)
     fine = prob.fine
     Phi = inn["Phi"]
     w = fs["g"] + prob.Pfull_c @ inn["wH"] + inn["th1"] * fine.full(fs["w0"])

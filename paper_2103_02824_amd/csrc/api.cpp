@@ -99,6 +99,7 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->kseg_ptr = w.take<int32_t>((int64_t)c->kseg_ptr.size());
   d->kseg = w.take<int32_t>((int64_t)c->kseg.size());
   d->rpart = w.take<double>((int64_t)c->kseg.size() * std::max<int64_t>(N, 1));
+  d->rpartH = w.take<double>((int64_t)c->kseg.size());
   d->PTptr = w.take<int32_t>(nH + 1);
   d->PTidx = w.take<int32_t>((int64_t)c->PTidx.size());
   d->PTw = w.take<double>((int64_t)c->PTw.size());
@@ -108,10 +109,15 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->cgeo = w.take<double>(12 * cnt);
   d->cel_ops = w.take<double>(40 * cnt);
   d->cel_orb = w.take<double>(14 * cnt * N);
+  if (c->opt.variant == MLC_VARIANT_JOINT) {
+    const int64_t npair = N * (N + 1) / 2;
+    d->cel_pairs = w.take<double>(4 * cnt * npair);
+    d->pair_jl = w.take<int32_t>(2 * npair);
+  }
   d->cel_tri = w.take<double>(20 * cnt);
   d->chat = w.take<double>(17 * nt);
   d->small = w.take<double>(small_len(nH, (int)N));
-  d->coarse_in = w.take<double>(nH * N + nH + N);
+  d->coarse_in = w.take<double>(nH * N + nH + N + N * N);
   d->occ = w.take<double>(N);
   d->RZ = w.take<double>(4 * std::max<int64_t>(1, c->n_nuclei));
   d->colv = w.take<double>(2 * N);
@@ -148,6 +154,7 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->dof_user = w.take<int32_t>(n);
   d->chk = w.take<int32_t>(4);
   d->lmax = w.take<double>(2);
+  if (c->hartree && hartree_pc(c->opt) == MLC_PC_CHEBYSHEV) d->valK32 = w.take<float>(nnz);
   if (c->opt.hartree_coarse && c->hartree) {
     d->KHinv = w.take<double>(nH * nH);
     d->rH = w.take<double>(nH);
@@ -218,6 +225,15 @@ mlc_status upload_and_init(mlc_ctx* c) {
   HIPCHK(up(s, d.RZ, RZ));
   HIPCHK(up(s, d.d2v, c->d2v));
   HIPCHK(up(s, d.dof_user, c->dof_user));
+  if (d.pair_jl) {
+    std::vector<int32_t> jl;
+    for (int j = 0; j < c->N; ++j)
+      for (int l = j; l < c->N; ++l) {
+        jl.push_back(j);
+        jl.push_back(l);
+      }
+    HIPCHK(up(s, d.pair_jl, jl));
+  }
   HIPCHK(hipMemsetAsync(d.w, 0, sizeof(double) * c->nv, s));
   HIPCHK(hipMemsetAsync(d.g, 0, sizeof(double) * c->nv, s));
   HIPCHK(hipMemsetAsync(d.small, 0, sizeof(double) * small_len(c->nH, c->N), s));
@@ -231,6 +247,7 @@ mlc_status upload_and_init(mlc_ctx* c) {
   launch_assemble2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_of, ns, d.diag_slot, d.elem, 0.0, nullptr, 1.0,
                    d.valM, nullptr, 0.0, nullptr, nullptr);
   launch_gershgorin(s, c->n, d.rowptr, d.valK, d.dinvK, d.red, d.lmax + 1);
+  if (d.valK32) launch_to_f32(s, nnz, d.valK, d.valK32);
   launch_coarse_tri(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.cel_tri);
   launch_coarse_hats(s, c->cnt, c->nt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.chat);
   if (d.KHinv) {
@@ -453,6 +470,7 @@ void mlc_options_default(mlc_options* o) {
   o->hartree_precond = -1;
   o->inner_mix_history = 6;
   o->inner_mix_beta = 0.5;
+  o->variant = MLC_VARIANT_EIGENPAIRWISE;
 }
 
 mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys, const mlc_options* opt,
@@ -487,6 +505,8 @@ mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_sy
       ((c->opt.precond == MLC_PC_CHEBYSHEV || hartree_pc(c->opt) == MLC_PC_CHEBYSHEV) &&
        (c->opt.cheb_degree < 2 || c->opt.cheb_degree > 16 || !(c->opt.cheb_ratio > 1.0))) ||
       c->opt.inner_mix_history < 0 || c->opt.inner_mix_history > 16 ||
+      (c->opt.variant != MLC_VARIANT_EIGENPAIRWISE && c->opt.variant != MLC_VARIANT_JOINT) ||
+      (c->opt.variant == MLC_VARIANT_JOINT && sys->n_orbitals > 64) ||
       !(c->opt.inner_mix_beta > 0.0 && c->opt.inner_mix_beta <= 1.0)) {
     delete c;
     return MLC_ERR_ARG;
@@ -655,11 +675,13 @@ mlc_status mlc_time_kernel(mlc_ctx* c, int32_t which, int32_t reps, double* avg_
   const int N = hart ? 1 : c->N;
   const bool f32 = !hart && c->opt.precision == MLC_PREC_FP32_IR;
   float* Yf = reinterpret_cast<float*>(d.Y);
-  // one Chebyshev step = a polynomial of degree 2 without the r.z partials:
-  // the launch shape of every step but the last
+  // one interior Chebyshev step (j = 2: both iterate blocks read, the older
+  // one overwritten, no r.z partials): the launch of every step but the first
+  // and the last
   double* Yd = hart ? d.Yh : d.Y;
-  PolyPC<double> pd{hart ? d.lmax + 1 : d.lmax, c->opt.cheb_ratio, 2, {Yd, Yd + n * N}, Yd + 2 * n * N, nullptr};
-  PolyPC<float> pf{d.lmax, c->opt.cheb_ratio, 2, {Yf, Yf + n * N}, Yf + 2 * n * N, nullptr};
+  PolyPC<double> pd{hart ? d.lmax + 1 : d.lmax, c->opt.cheb_ratio, 3, {Yd, Yd + n * N}, nullptr,
+                    hart ? d.valK32 : nullptr};
+  PolyPC<float> pf{d.lmax, c->opt.cheb_ratio, 3, {Yf, Yf + n * N}, nullptr};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -669,17 +691,20 @@ mlc_status mlc_time_kernel(mlc_ctx* c, int32_t which, int32_t reps, double* avg_
   auto one = [&]() {
     if (hart) {
       if (cheb)
-        launch_cheb_steps_t<double>(s, n, 1, d.rowptr, d.col, d.valK, d.dinvK, d.pr, pd, nullptr, nullptr);
+        launch_cheb_step_t<double>(s, n, 1, d.rowptr, d.col, d.valK, d.dinvK, d.pr, pd, 2, pd.Z[1], pd.Z[0], pd.Z[0],
+                                   nullptr, nullptr);
       else
         launch_spmm2(s, n, 1, d.rowptr, d.col, d.valK, d.pp, d.pq, d.red, nullptr);
     } else if (f32) {
       if (cheb)
-        launch_cheb_steps_t<float>(s, n, N, d.rowptr, d.col, d.valA32, d.dinvA32, d.R32, pf, nullptr, nullptr);
+        launch_cheb_step_t<float>(s, n, N, d.rowptr, d.col, d.valA32, d.dinvA32, d.R32, pf, 2, pf.Z[1], pf.Z[0],
+                                  pf.Z[0], nullptr, nullptr);
       else
         launch_spmm2_f32(s, n, N, d.rowptr, d.col, d.valA32, d.P32, d.Q32, d.red, nullptr);
     } else {
       if (cheb)
-        launch_cheb_steps_t<double>(s, n, N, d.rowptr, d.col, d.valA, d.dinvA, d.R, pd, nullptr, nullptr);
+        launch_cheb_step_t<double>(s, n, N, d.rowptr, d.col, d.valA, d.dinvA, d.R, pd, 2, pd.Z[1], pd.Z[0], pd.Z[0],
+                                   nullptr, nullptr);
       else
         launch_spmm2(s, n, N, d.rowptr, d.col, d.valA, d.P, d.Q, d.red, nullptr);
     }

@@ -171,7 +171,7 @@ __device__ void tile_spmm_lanes(int64_t r0, int64_t r1, int N, const int32_t* __
     const int64_t r = rb + rl;
     if (r >= r1) continue;
     T acc[NCH][V];
-    row_gather_lanes<L, V, NCH, tile_wu<T>(), T>(r, g, N, rowptr[r], rowptr[r + 1], col, val, S, acc);
+    row_gather_lanes<L, V, NCH, tile_wu<T>(), false, T>(r, g, N, rowptr[r], rowptr[r + 1], col, val, S, acc);
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
       const int c = (g + L * h) * V;
@@ -298,7 +298,7 @@ __device__ void tile_cheb_lanes(int64_t r0, int64_t r1, const BProb<T>& D, const
       }
     }
     T acc[NCH][V];
-    row_gather_lanes<L, V, NCH, tile_wu<T>(), T>(r, g, N, D.rowptr[r], D.rowptr[r + 1], D.col, D.val, Zin, acc);
+    row_gather_lanes<L, V, NCH, tile_wu<T>(), false, T>(r, g, N, D.rowptr[r], D.rowptr[r + 1], D.col, D.val, Zin, acc);
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
       const int c = (g + L * h) * V;

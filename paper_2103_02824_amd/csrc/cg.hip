@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "mlc_internal.h"
 #include "row_gather.h"
@@ -93,10 +94,17 @@ struct RowBlocks {
 // row's column indices and values are read WU at a time (the row's L lanes
 // read the same addresses: one request) and the WU gathers are issued before
 // they are summed, into two accumulators per column; entries past the row end
-// read row r itself with weight zero, so that every chunk issues all its loads
-// at once.
+// repeat the row's last entry with weight zero, so that every chunk issues all
+// its loads at once, with no branch. Blocks of n N sizeof(T) < 2^32 bytes are
+// gathered through 32-bit offsets (O32).
 constexpr int WIDE_BS = 512;
-constexpr int WIDE_MAXBLK = 1024;  // partial producers: at most cg_max_blocks()
+// Grid cap of the N > 8 kernels: two 512-thread blocks per compute unit
+// (their register use allows two, not more) on 256 compute units, so that
+// every block is resident and the blocks of an XCD sweep its row range
+// together (a larger grid would run in two waves of blocks, each over every
+// other stretch of rows, with fewer neighbouring rows in L2). At most
+// cg_max_blocks(), the partial producers' bound.
+constexpr int WIDE_MAXBLK = 512;
 constexpr int WU = 16;
 
 // Grid of the N > 8 kernels: one block per 64 rows up to the cap, whatever the
@@ -126,7 +134,7 @@ __device__ __forceinline__ void block_cols_lanes(const double (&dot)[NCH][V], in
 }
 
 // Y = A X; with partial: per-block column sums of X . Y.
-template <int L, int V, int NCH, typename T>
+template <int L, int V, int NCH, bool O32, typename T>
 __global__ void __launch_bounds__(WIDE_BS) k_spmm_rows(int64_t n, int N, const int32_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ col, const T* __restrict__ val,
                                                        const T* __restrict__ X, T* __restrict__ Y,
@@ -139,29 +147,28 @@ __global__ void __launch_bounds__(WIDE_BS) k_spmm_rows(int64_t n, int N, const i
   for (int h = 0; h < NCH; ++h)
 #pragma unroll
     for (int v = 0; v < V; ++v) dot[h][v] = 0.0;
-  // the next row's pointers are loaded while this row's gathers are in flight
+  // the next row's pointers are loaded while this row's gathers are in
+  // flight; rows past n are computed as row n - 1 and not stored (no branch
+  // in the loop body)
   const RowBlocks rbk((n + RB - 1) / RB);
   int64_t rn = rbk.first * RB + rl;
-  int jb = 0, je = 0;
-  if (rbk.first < rbk.end && rn < n) {
-    jb = rowptr[rn];
-    je = rowptr[rn + 1];
-  }
+  rn = rn < n ? rn : n - 1;
+  int jb = rowptr[rn], je = rowptr[rn + 1];
   for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
-    const int64_t r = rb * RB + rl;
+    const int64_t r0 = rb * RB + rl;
+    const bool live = r0 < n;
+    const int64_t r = live ? r0 : n - 1;
     const int jr = jb, jr1 = je;
     rn = (rb + rbk.step) * RB + rl;
-    if (rb + rbk.step < rbk.end && rn < n) {
-      jb = rowptr[rn];
-      je = rowptr[rn + 1];
-    }
-    if (r >= n) continue;
+    rn = rn < n ? rn : n - 1;
+    jb = rowptr[rn];
+    je = rowptr[rn + 1];
     T acc[NCH][V];
-    row_gather_lanes<L, V, NCH, WU, T>(r, g, N, jr, jr1, col, val, X, acc);
+    row_gather_lanes<L, V, NCH, WU, O32, T>(r, g, N, jr, jr1, col, val, X, acc);
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
       const int c = (g + L * h) * V;
-      if (c < N) {
+      if (live && c < N) {
         const int64_t i = r * N + c;
         store_cols<T, V>(Y + i, acc[h]);
         if (partial) {
@@ -188,6 +195,10 @@ __global__ void __launch_bounds__(WIDE_BS) k_spmm_rows(int64_t n, int N, const i
 // Its residual polynomial is positive and below one on (0, b], so p is
 // positive there and p(D^-1 A) D^-1 is symmetric positive definite for CG.
 // lmax is a Gershgorin bound of D^-1 A computed on the device.
+// The kernels carry the iterates, not d: with z_j the iterate after step j
+// (z_{-1} = 0) the previous direction is z_{j-1} - z_{j-2}, so step j reads
+// r, z_{j-1} (gathered) and z_{j-2} and writes z_j over z_{j-2}: one block of
+// n x N fewer read and one fewer written per step than with d stored.
 __device__ __forceinline__ double cheb_theta(double lmax, double ratio) { return 0.5 * (lmax + lmax / ratio); }
 __device__ __forceinline__ void cheb_coef(double lmax, double ratio, int j, double* cd, double* cr) {
   const double b = lmax, a = lmax / ratio;
@@ -221,18 +232,29 @@ __global__ void __launch_bounds__(BS, W) k_spmm_small(int64_t n, const int32_t* 
   double dot[NT];
 #pragma unroll
   for (int c = 0; c < NT; ++c) dot[c] = 0.0;
+  // rows past n are computed as row n - 1 and not stored (no branch around
+  // the gather); the next row's pointers are loaded ahead
   const RowBlocks rbk((n + RB - 1) / RB);
+  int64_t rn = rbk.first * RB + rl;
+  rn = rn < n ? rn : n - 1;
+  int jb = rowptr[rn], je = rowptr[rn + 1];
   for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
-    int64_t r = rb * RB + rl;
+    const int64_t r0 = rb * RB + rl;
+    const int64_t r = r0 < n ? r0 : n - 1;
+    const int jr = jb, jr1 = je;
+    rn = (rb + rbk.step) * RB + rl;
+    rn = rn < n ? rn : n - 1;
+    jb = rowptr[rn];
+    je = rowptr[rn + 1];
     T acc[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[c] = T(0);
-    if (r < n) row_gather<NT, G, U>(r, sub, rowptr, col, val, X, acc);
+    row_gather<NT, G, U>(jr, jr1, sub, col, val, X, acc);
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
       for (int off = G / 2; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, G);
-    if (r < n) {
+    if (r0 < n) {
 #pragma unroll
       for (int c = 0; c < NT; ++c)
         if (c % G == sub) {
@@ -258,17 +280,21 @@ __global__ void __launch_bounds__(BS, W) k_spmm_small(int64_t n, const int32_t* 
 }
 
 // One Chebyshev step j >= 1 fused with its SpMM (NT <= 8, G lanes per row):
-// w = A Zin; d = cd d + cr D^-1 (R - w); Zout = Zin + d; optional per-block
-// column sums of R . Zout (the r.z of CG after the last step). The row's own
-// entries of R, d and Zin are loaded before the gather, so that their
-// latency overlaps it.
-template <int NT, int G, int U, int BS, int W, typename T>
+// w = A Zin; Zout = Zin + cd (Zin - Zprev) + cr D^-1 (R - w) with Zprev = 0
+// for j = 1 (Zprev is not read then); optional per-block column sums of
+// R . Zout (the r.z of CG after the last step). Zout may be Zprev (each
+// entry is read before it is written, by the same lane; Zin is the only
+// gathered block). The row's own entries of R, Zprev and Zin are loaded
+// before the gather, so that their latency overlaps it. The matrix values may be a narrower copy (MT = float
+// for FP64 vectors): the polynomial is then that of the rounded matrix, a
+// fixed symmetric positive definite preconditioner all the same.
+template <int NT, int G, int U, int BS, int W, typename T, typename MT = T>
 __global__ void __launch_bounds__(BS, W) k_cheb_small(int64_t n, const int32_t* __restrict__ rowptr,
-                                                      const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                      const int32_t* __restrict__ col, const MT* __restrict__ val,
                                                       const T* __restrict__ dinv, const T* __restrict__ R,
-                                                      const T* __restrict__ Zin, T* __restrict__ Zout,
-                                                      T* __restrict__ Dd, const double* __restrict__ lmax,
-                                                      double ratio, int j, double* __restrict__ partial,
+                                                      const T* __restrict__ Zin, const T* Zprev, T* Zout,
+                                                      const double* __restrict__ lmax, double ratio, int j,
+                                                      double* __restrict__ partial,
                                                       const int32_t* __restrict__ flags) {
   constexpr int RB = BS / G;
   constexpr int NO = (NT + G - 1) / G;  // columns owned by a lane (c = sub + o G)
@@ -282,25 +308,37 @@ __global__ void __launch_bounds__(BS, W) k_cheb_small(int64_t n, const int32_t* 
   double dot[NT];
 #pragma unroll
   for (int c = 0; c < NT; ++c) dot[c] = 0.0;
+  // rows past n are computed as row n - 1 and not stored: no branch around
+  // the gather (and whole lane groups stay active for the shuffles); the next
+  // row's pointers are loaded ahead
   const RowBlocks rbk((n + RB - 1) / RB);
+  int64_t rn = rbk.first * RB + rl;
+  rn = rn < n ? rn : n - 1;
+  int jb = rowptr[rn], je = rowptr[rn + 1];
   for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
-    const int64_t r = rb * RB + rl;
-    if (r >= n) continue;  // whole lane groups: the shuffles below stay within the group
-    T rv[NO], dv[NO], zv[NO];
+    const int64_t r0 = rb * RB + rl;
+    const bool live = r0 < n;
+    const int64_t r = live ? r0 : n - 1;
+    const int jr = jb, jr1 = je;
+    rn = (rb + rbk.step) * RB + rl;
+    rn = rn < n ? rn : n - 1;
+    jb = rowptr[rn];
+    je = rowptr[rn + 1];
+    T rv[NO], pv[NO], zv[NO];
     const T di = dinv[r];
+    // the row's own entries (lanes past NT load the last column; for j = 1
+    // the caller passes Zprev = Zin and the previous iterate is zero)
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
-      const int c = sub + o * G;
-      if (c < NT) {
-        rv[o] = R[r * NT + c];
-        dv[o] = Dd[r * NT + c];
-        zv[o] = Zin[r * NT + c];
-      }
+      const int c = sub + o * G < NT ? sub + o * G : NT - 1;
+      rv[o] = R[r * NT + c];
+      zv[o] = Zin[r * NT + c];
+      pv[o] = Zprev[r * NT + c];
     }
     T acc[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[c] = T(0);
-    row_gather<NT, G, U>(r, sub, rowptr, col, val, Zin, acc);
+    row_gather<NT, G, U>(jr, jr1, sub, col, val, Zin, acc);
 #pragma unroll
     for (int c = 0; c < NT; ++c)
 #pragma unroll
@@ -308,10 +346,9 @@ __global__ void __launch_bounds__(BS, W) k_cheb_small(int64_t n, const int32_t* 
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
       const int c = sub + o * G;
-      if (c < NT) {
-        const T dn = cd * dv[o] + cr * (di * (rv[o] - acc[c]));
-        Dd[r * NT + c] = dn;
-        const T z = zv[o] + dn;
+      if (live && c < NT) {
+        const T dv = j > 1 ? zv[o] - pv[o] : zv[o];
+        const T z = zv[o] + (cd * dv + cr * (di * (rv[o] - acc[c])));
         Zout[r * NT + c] = z;
         if (partial) dot[c] += (double)rv[o] * (double)z;
       }
@@ -334,17 +371,18 @@ __global__ void __launch_bounds__(BS, W) k_cheb_small(int64_t n, const int32_t* 
 }
 
 // The fused Chebyshev step for N > 8 in the same layout: w = A Zin;
-// d = cd d + cr D^-1 (R - w); Zout = Zin + d; with PART, per-block column sums
-// of R . Zout into partial (a separate instantiation, so that the steps
-// without them do not hold the sums in registers). The row's own R, d, Zin
-// entries are loaded before the gather.
-template <int L, int V, int NCH, bool PART, typename T>
+// Zout = Zin + cd (Zin - Zprev) + cr D^-1 (R - w) (Zprev = 0 for j = 1; Zout
+// may be Zprev); with PART, per-block column sums of R . Zout into partial (a
+// separate instantiation, so that the steps without them do not hold the
+// sums in registers). The row's own R, Zprev, Zin entries are loaded before
+// the gather.
+template <int L, int V, int NCH, bool PART, bool O32, typename T>
 __global__ void __launch_bounds__(WIDE_BS) k_cheb_rows(int64_t n, int N, const int32_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ col, const T* __restrict__ val,
                                                        const T* __restrict__ dinv, const T* __restrict__ R,
-                                                       const T* __restrict__ Zin, T* __restrict__ Zout,
-                                                       T* __restrict__ Dd, const double* __restrict__ lmax,
-                                                       double ratio, int j, double* __restrict__ partial,
+                                                       const T* __restrict__ Zin, const T* Zprev, T* Zout,
+                                                       const double* __restrict__ lmax, double ratio, int j,
+                                                       double* __restrict__ partial,
                                                        const int32_t* __restrict__ flags) {
   constexpr int RB = WIDE_BS / L;
   if (flags && flags[0] == 0) return;
@@ -357,52 +395,47 @@ __global__ void __launch_bounds__(WIDE_BS) k_cheb_rows(int64_t n, int N, const i
   for (int h = 0; h < NCH; ++h)
 #pragma unroll
     for (int v = 0; v < V; ++v) dot[h][v] = 0.0;
-  // the next row's pointers are loaded while this row's gathers are in flight
+  // The next row's pointers are loaded while this row's gathers are in
+  // flight. Rows past n (the tail row block) are computed as row n - 1 and
+  // not stored, so the loop body has no branch and its loads need no
+  // conservative waits.
   const RowBlocks rbk((n + RB - 1) / RB);
   int64_t rn = rbk.first * RB + rl;
-  int jb = 0, je = 0;
-  if (rbk.first < rbk.end && rn < n) {
-    jb = rowptr[rn];
-    je = rowptr[rn + 1];
-  }
+  rn = rn < n ? rn : n - 1;
+  int jb = rowptr[rn], je = rowptr[rn + 1];
   for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
-    const int64_t r = rb * RB + rl;
+    const int64_t r0 = rb * RB + rl;
+    const bool live = r0 < n;
+    const int64_t r = live ? r0 : n - 1;
     const int jr = jb, jr1 = je;
     rn = (rb + rbk.step) * RB + rl;
-    if (rb + rbk.step < rbk.end && rn < n) {
-      jb = rowptr[rn];
-      je = rowptr[rn + 1];
-    }
-    if (r >= n) continue;
-    T rv[NCH][V], dv[NCH][V], zv[NCH][V];
+    rn = rn < n ? rn : n - 1;
+    jb = rowptr[rn];
+    je = rowptr[rn + 1];
+    T rv[NCH][V], pv[NCH][V], zv[NCH][V];
     const T di = dinv[r];
+    // the row's own entries (lanes past N load the row's last columns); for
+    // j = 1 the caller passes Zprev = Zin and the previous iterate is zero
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
-      const int c = (g + L * h) * V;
-      if (c < N) {
-        const int64_t i = r * N + c;
-        load_cols<T, V>(R + i, rv[h]);
-        load_cols<T, V>(Dd + i, dv[h]);
-        load_cols<T, V>(Zin + i, zv[h]);
-      }
+      const int64_t i = r * N + lane_col<L, V>(g, h, N);
+      load_cols<T, V>(R + i, rv[h]);
+      load_cols<T, V>(Zin + i, zv[h]);
+      load_cols<T, V>(Zprev + i, pv[h]);
     }
     T acc[NCH][V];
-    row_gather_lanes<L, V, NCH, WU, T>(r, g, N, jr, jr1, col, val, Zin, acc);
+    row_gather_lanes<L, V, NCH, WU, O32, T>(r, g, N, jr, jr1, col, val, Zin, acc);
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
       const int c = (g + L * h) * V;
-      if (c < N) {
-        const int64_t i = r * N + c;
-        T dn[V], z[V];
+      T z[V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          dn[v] = cd * dv[h][v] + cr * (di * (rv[h][v] - acc[h][v]));
-          z[v] = zv[h][v] + dn[v];
-          if constexpr (PART) dot[h][v] += (double)rv[h][v] * (double)z[v];
-        }
-        store_cols<T, V>(Dd + i, dn);
-        store_cols<T, V>(Zout + i, z);
+      for (int v = 0; v < V; ++v) {
+        const T dv = j > 1 ? zv[h][v] - pv[h][v] : zv[h][v];
+        z[v] = zv[h][v] + (cd * dv + cr * (di * (rv[h][v] - acc[h][v])));
+        if constexpr (PART) dot[h][v] += live && c < N ? (double)rv[h][v] * (double)z[v] : 0.0;
       }
+      if (live && c < N) store_cols<T, V>(Zout + r * N + c, z);
     }
   }
   if constexpr (PART) block_cols_lanes<L, V, NCH, WIDE_BS>(dot, N, partial);
@@ -495,7 +528,7 @@ __global__ void __launch_bounds__(TPB) k_cg_init(int64_t n, int N, const T* __re
                                                  const T* __restrict__ AX, const T* __restrict__ dinv,
                                                  T* __restrict__ Rv, T* __restrict__ P,
                                                  double* __restrict__ partial, T* __restrict__ Z0,
-                                                 T* __restrict__ Dd, const double* __restrict__ lmax, double ratio) {
+                                                 const double* __restrict__ lmax, double ratio) {
   __shared__ double sd[TPB];
   const T ith = Z0 ? (T)(1.0 / cheb_theta(*lmax, ratio)) : T(0);
   RC p(N);
@@ -509,10 +542,7 @@ __global__ void __launch_bounds__(TPB) k_cg_init(int64_t n, int N, const T* __re
       T z = dinv[r] * rr;
       Rv[i] = rr;
       P[i] = z;
-      if (Z0) {
-        Z0[i] = z * ith;
-        Dd[i] = z * ith;
-      }
+      if (Z0) Z0[i] = z * ith;
       v[0] += (double)rr * (double)z;
       v[1] += (double)rr * (double)rr;
       v[2] += (double)b * (double)b;
@@ -594,8 +624,8 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int64_t n, int N, const T* __
                                                    const double* __restrict__ pq_part, int nblk_pq,
                                                    const double* __restrict__ scal, const int32_t* __restrict__ flags,
                                                    double* __restrict__ partial, int32_t* __restrict__ brk,
-                                                   T* __restrict__ Z0, T* __restrict__ Dd,
-                                                   const double* __restrict__ lmax, double ratio) {
+                                                   T* __restrict__ Z0, const double* __restrict__ lmax,
+                                                   double ratio) {
   if (flags[0] == 0) return;
   __shared__ double sd[TPB];
   __shared__ double alpha[MLC_MAX_ORBITALS];
@@ -623,11 +653,7 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int64_t n, int N, const T* __
       T rr = Rv[i] - a * Q[i];
       X[i] = x;
       Rv[i] = rr;
-      if (Z0) {
-        T z = dinv[r] * rr * ith;
-        Z0[i] = z;
-        Dd[i] = z;
-      }
+      if (Z0) Z0[i] = dinv[r] * rr * ith;
       v[0] += (double)rr * (double)dinv[r] * (double)rr;
       v[1] += (double)rr * (double)rr;
     }
@@ -742,10 +768,9 @@ __global__ void __launch_bounds__(TPB) k_add_f32(int64_t m, const float* __restr
   if (i < m) x[i] += (double)d[i];
 }
 
-// Calls f(tag, grid, block) with tag::L, tag::V, tag::NCH the N > 8 layout of
-// wide_shape(N, sizeof(T)).
+// The layouts of wide_launch (64-bit gather offsets).
 template <typename T, typename F>
-void wide_launch(hipStream_t, int64_t n, int N, F&& f) {
+void wide_launch_tag(hipStream_t, int64_t n, int N, F&& f) {
   const WideShape w = wide_shape(N, 16 / (int)sizeof(T));
   const dim3 g(wide_blocks_for(n)), b(WIDE_BS);
   if (w.NCH > 1) {
@@ -770,6 +795,18 @@ void wide_launch(hipStream_t, int64_t n, int N, F&& f) {
 #undef WIDE_L
 }
 
+// Calls f(tag, grid, block) with tag::L, tag::V, tag::NCH the N > 8 layout of
+// wide_shape(N, sizeof(T)) and tag::O32 whether an n x N block of T spans
+// less than 4 GiB (32-bit gather offsets).
+template <typename T, typename F>
+void wide_launch(hipStream_t s, int64_t n, int N, F&& f) {
+  if ((uint64_t)n * (uint64_t)N * sizeof(T) < (1ull << 32)) {
+    wide_launch_tag<T>(s, n, N, [&](auto tag, dim3 g, dim3 b) { f(WideTag32<decltype(tag)>{}, g, b); });
+  } else {
+    wide_launch_tag<T>(s, n, N, f);
+  }
+}
+
 template <typename T>
 void spmm_any(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val, const T* X,
               T* Y, double* partial, const int32_t* flags) {
@@ -789,7 +826,7 @@ void spmm_any(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int3
     default:
       wide_launch<T>(s, n, N, [&](auto tag, dim3 g, dim3 b) {
         using K = decltype(tag);
-        hipLaunchKernelGGL((k_spmm_rows<K::L, K::V, K::NCH, T>), g, b, 0, s, n, N, rowptr, col, val, X, Y, partial,
+        hipLaunchKernelGGL((k_spmm_rows<K::L, K::V, K::NCH, K::O32, T>), g, b, 0, s, n, N, rowptr, col, val, X, Y, partial,
                            flags);
       });
   }
@@ -823,7 +860,7 @@ template <typename T>
 void launch_cg_init_t(hipStream_t s, int64_t n, int N, const T* B, const T* AX, const T* dinv, T* Rv, T* P,
                       double* partial, const PolyPC<T>* pc) {
   hipLaunchKernelGGL((k_cg_init<T>), dim3(cg_blocks(n, N)), dim3(TPB), 0, s, n, N, B, AX, dinv, Rv, P, partial,
-                     pc ? pc->Z[0] : (T*)nullptr, pc ? pc->Dd : (T*)nullptr, pc ? pc->lmax : nullptr,
+                     pc ? pc->Z[0] : (T*)nullptr, pc ? pc->lmax : nullptr,
                      pc ? pc->ratio : 1.0);
 }
 void launch_cg_init2(hipStream_t s, int64_t n, int N, const double* B, const double* AX, const double* dinv,
@@ -851,7 +888,7 @@ void launch_cg_update_t(hipStream_t s, int64_t n, int N, const T* dinv, T* X, T*
                         int32_t* brk, const PolyPC<T>* pc) {
   hipLaunchKernelGGL((k_cg_update<T>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, X, Rv, P, Q, pq_part,
                      spmm_blocks(n, N), scal, flags, partial, brk, pc ? pc->Z[0] : (T*)nullptr,
-                     pc ? pc->Dd : (T*)nullptr, pc ? pc->lmax : nullptr, pc ? pc->ratio : 1.0);
+                     pc ? pc->lmax : nullptr, pc ? pc->ratio : 1.0);
 }
 void launch_cg_update_f(hipStream_t s, int64_t n, int N, const double* dinv, double* X, double* Rv, const double* P,
                         const double* Q, const double* pq_part, const double* scal, const int32_t* flags,
@@ -898,54 +935,82 @@ void launch_cg_direction_f32(hipStream_t s, int64_t n, int N, const float* dinv,
   launch_cg_direction_t<float>(s, n, N, dinv, Rv, P, upd_part, scal_in, flags_in, scal_out, flags_out, rtol2, nullptr);
 }
 
-// Chebyshev steps 1..degree-1 from Z[0] and Dd (written by the init or update
-// kernel). Step j reads Z[(j-1)&1] and writes Z[j&1]; the last step writes
-// last_out instead when given, and the r.z partials.
+// Chebyshev step j >= 1: reads Zin (= z_{j-1}) and Zprev (= z_{j-2} for
+// j > 1; for j = 1 pass Zin, whose values are then not used); writes Zout
+// (which may be Zprev) and, when part is given, the r.z partials.
 template <typename T>
-void launch_cheb_steps_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val,
-                         const T* dinv, const T* Rv, const PolyPC<T>& pc, T* last_out, const int32_t* flags) {
-  for (int j = 1; j < pc.degree; ++j) {
-    const bool last = j == pc.degree - 1;
-    const T* zin = pc.Z[(j - 1) & 1];
-    T* zout = last && last_out ? last_out : pc.Z[j & 1];
-    double* part = last ? pc.rz_part : nullptr;
-    if (N <= 8) {
+void launch_cheb_step_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val,
+                        const T* dinv, const T* Rv, const PolyPC<T>& pc, int j, const T* zin, const T* zprev,
+                        T* zout, double* part, const int32_t* flags) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (pc.val32 && N == 1) {
+      // one FP64 column with FP32 matrix values (the Hartree problem's polynomial)
+      if (part) {
+        const int64_t needed = (n + (SPMM_BS / ROW_G) - 1) / (SPMM_BS / ROW_G);
+        hipLaunchKernelGGL((k_cheb_small<1, ROW_G, unroll_cheb_part(1), SPMM_BS, waves_cheb_part(1), T, float>),
+                           dim3(cap_xcd(needed, SPMM_MAXBLK)), dim3(SPMM_BS), 0, s, n, rowptr, col, pc.val32, dinv,
+                           Rv, zin, zprev, zout, pc.lmax, pc.ratio, j, part, flags);
+      } else {
+        const int64_t needed = (n + (TPB / ROW_G) - 1) / (TPB / ROW_G);
+        hipLaunchKernelGGL((k_cheb_small<1, ROW_G, unroll_wide(1), TPB, waves_wide(1), T, float>),
+                           dim3(cap_xcd(needed, 1 << 30)), dim3(TPB), 0, s, n, rowptr, col, pc.val32, dinv, Rv, zin,
+                           zprev, zout, pc.lmax, pc.ratio, j, part, flags);
+      }
+      return;
+    }
+  }
+  if (N <= 8) {
 #define CHEB_CASE(K)                                                                                             \
   case K:                                                                                                        \
     if (part) {                                                                                                  \
       const int64_t needed = (n + (SPMM_BS / ROW_G) - 1) / (SPMM_BS / ROW_G);                                    \
       hipLaunchKernelGGL((k_cheb_small<K, ROW_G, unroll_cheb_part(K), SPMM_BS, waves_cheb_part(K), T>),          \
                          dim3(cap_xcd(needed, SPMM_MAXBLK)), dim3(SPMM_BS), 0, s, n, rowptr, col, val, dinv, Rv, \
-                         zin, zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags);                                   \
+                         zin, zprev, zout, pc.lmax, pc.ratio, j, part, flags);                                   \
     } else {                                                                                                     \
       const int64_t needed = (n + (TPB / ROW_G) - 1) / (TPB / ROW_G);                                            \
       hipLaunchKernelGGL((k_cheb_small<K, ROW_G, unroll_wide(K), TPB, waves_wide(K), T>),                        \
                          dim3(cap_xcd(needed, 1 << 30)), dim3(TPB), 0, s, n, rowptr, col, val, dinv, Rv, zin,    \
-                         zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags);                                        \
+                         zprev, zout, pc.lmax, pc.ratio, j, part, flags);                                        \
     }                                                                                                            \
     break;
-      switch (N) {
-        CHEB_CASE(1)
-        CHEB_CASE(2)
-        CHEB_CASE(3)
-        CHEB_CASE(4)
-        CHEB_CASE(5)
-        CHEB_CASE(6)
-        CHEB_CASE(7)
-        CHEB_CASE(8)
-      }
-#undef CHEB_CASE
-    } else {
-      wide_launch<T>(s, n, N, [&](auto tag, dim3 g, dim3 b) {
-        using K = decltype(tag);
-        if (part)
-          hipLaunchKernelGGL((k_cheb_rows<K::L, K::V, K::NCH, true, T>), g, b, 0, s, n, N, rowptr, col, val, dinv,
-                             Rv, zin, zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags);
-        else
-          hipLaunchKernelGGL((k_cheb_rows<K::L, K::V, K::NCH, false, T>), g, b, 0, s, n, N, rowptr, col, val, dinv,
-                             Rv, zin, zout, pc.Dd, pc.lmax, pc.ratio, j, part, flags);
-      });
+    switch (N) {
+      CHEB_CASE(1)
+      CHEB_CASE(2)
+      CHEB_CASE(3)
+      CHEB_CASE(4)
+      CHEB_CASE(5)
+      CHEB_CASE(6)
+      CHEB_CASE(7)
+      CHEB_CASE(8)
     }
+#undef CHEB_CASE
+  } else {
+    wide_launch<T>(s, n, N, [&](auto tag, dim3 g, dim3 b) {
+      using K = decltype(tag);
+      if (part)
+        hipLaunchKernelGGL((k_cheb_rows<K::L, K::V, K::NCH, true, K::O32, T>), g, b, 0, s, n, N, rowptr, col, val, dinv, Rv,
+                           zin, zprev, zout, pc.lmax, pc.ratio, j, part, flags);
+      else
+        hipLaunchKernelGGL((k_cheb_rows<K::L, K::V, K::NCH, false, K::O32, T>), g, b, 0, s, n, N, rowptr, col, val, dinv, Rv,
+                           zin, zprev, zout, pc.lmax, pc.ratio, j, part, flags);
+    });
+  }
+}
+
+// Chebyshev steps 1..degree-1 from z_0 in Z[0] (written by the init or update
+// kernel): step j reads Z[(j-1)&1] and Z[j&1] and writes Z[j&1]; the last step
+// writes last_out instead when given, and the r.z partials.
+template <typename T>
+void launch_cheb_steps_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val,
+                         const T* dinv, const T* Rv, const PolyPC<T>& pc, T* last_out, const int32_t* flags) {
+  for (int j = 1; j < pc.degree; ++j) {
+    const bool last = j == pc.degree - 1;
+    const T* zin = pc.Z[(j - 1) & 1];
+    T* zprev = pc.Z[j & 1];
+    T* zout = last && last_out ? last_out : zprev;
+    launch_cheb_step_t<T>(s, n, N, rowptr, col, val, dinv, Rv, pc, j, zin, j > 1 ? zprev : zin, zout,
+                          last ? pc.rz_part : nullptr, flags);
   }
 }
 
@@ -985,6 +1050,12 @@ template void launch_cheb_steps_t<double>(hipStream_t, int64_t, int, const int32
                                           const int32_t*);
 template void launch_cheb_steps_t<float>(hipStream_t, int64_t, int, const int32_t*, const int32_t*, const float*,
                                          const float*, const float*, const PolyPC<float>&, float*, const int32_t*);
+template void launch_cheb_step_t<double>(hipStream_t, int64_t, int, const int32_t*, const int32_t*, const double*,
+                                         const double*, const double*, const PolyPC<double>&, int, const double*,
+                                         const double*, double*, double*, const int32_t*);
+template void launch_cheb_step_t<float>(hipStream_t, int64_t, int, const int32_t*, const int32_t*, const float*,
+                                        const float*, const float*, const PolyPC<float>&, int, const float*,
+                                        const float*, float*, double*, const int32_t*);
 
 void launch_to_f32(hipStream_t s, int64_t m, const double* a, float* b) {
   hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((m + TPB - 1) / TPB)), dim3(TPB), 0, s, m, a, b);

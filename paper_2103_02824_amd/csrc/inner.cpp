@@ -458,4 +458,275 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
   return st;
 }
 
+// ---------------------------------------------------------------------------
+// The joint-space variant (the earlier multilevel correction method the paper
+// compares against): Algorithm 2 with step (a) replaced by one eigenproblem in
+// V_H + span{u_1, ..., u_N}, whose lowest N eigenpairs are the new orbitals
+// (M-orthonormal by construction). Every fine-mesh integral comes from the
+// fine stage: the per-orbital pieces of the eigenpairwise form, the full
+// U^T O U blocks, and the pair integrals (u_j u_l, psi_m) that the Hartree
+// term of the u-u block and the density need (the N^2 cross terms).
+mlc_status inner_loop_joint(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
+  using namespace dense;
+  const int64_t nH = c->nH;
+  const int N = c->N;
+  const int64_t m = nH + N;
+  const int hart = c->hartree;
+  const int npair = N * (N + 1) / 2;
+  const TriIndex& ti = tri_index();
+  auto t0 = std::chrono::steady_clock::now();
+
+  std::vector<double> AfixH, G, MH, KH;
+  assemble_dense(c, fb.cel_ops.data(), 40, 0, AfixH);
+  assemble_dense(c, fb.cel_ops.data(), 40, 10, G);
+  if (c->h_Mh_chol.empty()) {
+    assemble_dense(c, fb.cel_ops.data(), 40, 20, MH);
+    assemble_dense(c, fb.cel_ops.data(), 40, 30, KH);
+    c->h_MH = MH;
+    c->h_KH = KH;
+    c->h_Mh_chol = MH;
+    if (!cholesky(c->h_Mh_chol, nH)) return fail(c, MLC_ERR_NONFINITE, "coarse mass matrix not SPD");
+    c->h_Kh_chol = KH;
+    if (!cholesky(c->h_Kh_chol, nH)) return fail(c, MLC_ERR_NONFINITE, "coarse stiffness not SPD");
+  }
+  const std::vector<double>& MHd = c->h_MH;
+  const std::vector<double>& KHd = c->h_KH;
+
+  // coarse-dof vectors of the per-orbital and pair integrals: rhsv[k N + i] =
+  // (u_i^2, psi_k), R[k npair + p] = (u_j u_l, psi_k)
+  std::vector<double> R((size_t)nH * npair, 0.0);
+  for (int64_t C = 0; C < c->cnt; ++C)
+    for (int a = 0; a < 4; ++a) {
+      const int k = c->cv2d[c->ctets[4 * C + a]];
+      if (k < 0) continue;
+      for (int p = 0; p < npair; ++p) R[(int64_t)k * npair + p] += fb.cel_pairs[((int64_t)C * npair + p) * 4 + a];
+    }
+  auto ah4_apply = [&](int i, const double* x, double* y) {  // y = A_h4,i x
+    std::fill(y, y + nH, 0.0);
+    for (int64_t C = 0; C < c->cnt; ++C) {
+      int k[4];
+      for (int a = 0; a < 4; ++a) k[a] = c->cv2d[c->ctets[4 * C + a]];
+      const double* e = &fb.cel_orb[(C * N + i) * 14];
+      for (int a = 0; a < 4; ++a) {
+        if (k[a] < 0) continue;
+        double sacc = 0.0;
+        for (int b = 0; b < 4; ++b)
+          if (k[b] >= 0) sacc += e[sym10(a, b)] * x[k[b]];
+        y[k[a]] += sacc;
+      }
+    }
+  };
+  // Hartree system pieces, as in the eigenpairwise loop
+  std::vector<double> yd(nH, 0.0);
+  double schur = 1.0;
+  if (hart) {
+    for (int64_t k = 0; k < nH; ++k) yd[k] = fb.d[k];
+    forward(c->h_Kh_chol, nH, yd.data());
+    backward(c->h_Kh_chol, nH, yd.data());
+    schur = fb.zeta - dot(fb.d.data(), yd.data(), nH);
+    if (!(schur > 0.0)) return fail(c, MLC_ERR_NONFINITE, "Hartree augmented matrix not SPD");
+  }
+  // the mass and H^1 matrices of the joint basis [P, u_1..u_N] (fixed in the loop)
+  std::vector<double> Mj(m * m, 0.0), KMj(m * m, 0.0);
+  for (int64_t a = 0; a < nH; ++a)
+    for (int64_t b = 0; b < nH; ++b) {
+      Mj[a * m + b] = MHd[a * nH + b];
+      KMj[a * m + b] = KHd[a * nH + b] + MHd[a * nH + b];
+    }
+  for (int64_t k = 0; k < nH; ++k)
+    for (int j = 0; j < N; ++j) {
+      Mj[k * m + nH + j] = Mj[(nH + j) * m + k] = fb.ptM[k * N + j];
+      KMj[k * m + nH + j] = KMj[(nH + j) * m + k] = fb.ptK[k * N + j] + fb.ptM[k * N + j];
+    }
+  for (int j = 0; j < N; ++j)
+    for (int l = 0; l < N; ++l) {
+      Mj[(nH + j) * m + nH + l] = 0.5 * (fb.utM[j * N + l] + fb.utM[l * N + j]);
+      KMj[(nH + j) * m + nH + l] =
+          0.5 * (fb.utK[j * N + l] + fb.utK[l * N + j] + fb.utM[j * N + l] + fb.utM[l * N + j]);
+    }
+  std::vector<double> Lj = Mj;
+  if (!cholesky(Lj, m)) return fail(c, MLC_ERR_NONFINITE, "mass matrix of the joint space not SPD");
+
+  std::vector<double> wH(nH, 0.0), X((size_t)m * N, 0.0), Xold((size_t)m * N, 0.0), lam(N, 0.0);
+  for (int i = 0; i < N; ++i) Xold[(size_t)i * m + nH + i] = 1.0;  // the first iterate: u_i
+  double th1 = hart ? 1.0 : 0.0;
+  std::vector<double> Kj, Cm, tmp(nH), fH(nH), xin(nH + 1), xout(nH + 1, 0.0), fres(nH + 1), gres(nH + 1);
+  std::vector<std::vector<double>> Ah4w(N, std::vector<double>(nH));
+  Tridiag Tr;
+  Anderson mix;
+  mix.m = c->opt.inner_mix_history;
+  mix.beta = c->opt.inner_mix_beta;
+  const int maxit = std::max(1, c->opt.inner_maxit);
+  int its = 0;
+  double diff = 0.0;
+  mlc_status st = MLC_OK;
+  for (int s = 0; s < maxit; ++s) {
+    its = s + 1;
+    // (a) the joint matrix: [[A_H, B], [B^T, E]] with the Hartree input (w_H, theta1)
+    std::vector<double> AH = AfixH;
+    if (hart) {
+      add_trilinear_matrix(c, c->h_tri, wH.data(), 1.0, AH);
+      for (int64_t k = 0; k < nH * nH; ++k) AH[k] += th1 * G[k];
+    }
+    Kj.assign(m * m, 0.0);
+    for (int64_t a = 0; a < nH; ++a)
+      for (int64_t b = 0; b < nH; ++b) Kj[a * m + b] = AH[a * nH + b];
+    for (int j = 0; j < N; ++j) {
+      if (hart) ah4_apply(j, wH.data(), Ah4w[j].data());
+      for (int64_t k = 0; k < nH; ++k) {
+        const double v = fb.ptF[k * N + j] + (hart ? Ah4w[j][k] + th1 * fb.ptW[k * N + j] : 0.0);
+        Kj[k * m + nH + j] = Kj[(nH + j) * m + k] = v;
+      }
+    }
+    for (int j = 0; j < N; ++j)
+      for (int l = j; l < N; ++l) {
+        double v = 0.5 * (fb.utF[j * N + l] + fb.utF[l * N + j]);
+        if (hart) {
+          v += th1 * 0.5 * (fb.utW[j * N + l] + fb.utW[l * N + j]);
+          const int p = pair_index(N, j, l);
+          for (int64_t k = 0; k < nH; ++k) v += wH[k] * R[(int64_t)k * npair + p];
+        }
+        Kj[(nH + j) * m + nH + l] = Kj[(nH + l) * m + nH + j] = v;
+      }
+    // the lowest N eigenpairs: C = L^-1 K L^-T = Q T Q^T, bisection, inverse
+    // iteration (orthogonalised within clusters of equal eigenvalues)
+    congruence(Lj, Kj, m, Cm);
+    tridiagonalize(Cm, m, Tr);
+    std::vector<double> ev = lowest_eigenvalues(Tr, nullptr, 0.0, N);
+    double scale = 0.0;
+    for (int64_t k = 0; k < m; ++k) scale = std::max(scale, std::fabs(Tr.d[k]) + (k + 1 < m ? std::fabs(Tr.e[k]) : 0));
+    std::vector<double> Y((size_t)m * N), y(m);
+    for (int i = 0; i < N; ++i) {
+      std::vector<double> x0(m);
+      for (int64_t k = 0; k < m; ++k) x0[k] = 1.0 + 1e-3 * std::sin(0.7 * (double)k + 1.3 * (double)i);
+      double sv;
+      eigenvector_from(Tr, nullptr, 0.0, ev[i], x0.data(), 0.0, y.data(), &sv);
+      for (int pass = 0; pass < 2; ++pass)
+        for (int k = 0; k < i; ++k) {
+          if (std::fabs(ev[k] - ev[i]) > 1e-8 * std::max(1.0, scale)) continue;
+          const double* yk = &Y[(size_t)k * m];
+          double pr = dot(y.data(), yk, m);
+          for (int64_t q = 0; q < m; ++q) y[q] -= pr * yk[q];
+          double nr = std::sqrt(dot(y.data(), y.data(), m));
+          for (int64_t q = 0; q < m; ++q) y[q] /= nr;
+        }
+      std::copy(y.begin(), y.end(), &Y[(size_t)i * m]);
+    }
+    bool finite = true;
+    for (int i = 0; i < N; ++i) {
+      double* xi = &X[(size_t)i * m];
+      std::copy(&Y[(size_t)i * m], &Y[(size_t)i * m] + m, xi);
+      apply_Q(Tr, xi);
+      backward(Lj, m, xi);
+      // sign of the previous iterate: (phi^{s+1}, phi^s)_M > 0
+      const double* xo = &Xold[(size_t)i * m];
+      double pr = 0.0;
+      for (int64_t a = 0; a < m; ++a) pr += xi[a] * dot(&Mj[a * m], xo, m);
+      if (pr < 0.0)
+        for (int64_t a = 0; a < m; ++a) xi[a] = -xi[a];
+      lam[i] = ev[i];
+      finite = finite && std::isfinite(lam[i]);
+    }
+    if (!finite) return fail(c, MLC_ERR_NONFINITE, "non-finite solution of the joint problem");
+    // (b) Hartree problem for phi_i = P c_i + sum_j d_ji u_j
+    if (hart) {
+      std::fill(fH.begin(), fH.end(), 0.0);
+      double gsum = 0.0;
+      std::vector<double> ph(nH);
+      for (int i = 0; i < N; ++i) {
+        const double f = c->occ[i];
+        if (f == 0.0) continue;
+        const double* xi = &X[(size_t)i * m];
+        const double* di = xi + nH;
+        for (int64_t k = 0; k < nH; ++k) ph[k] = xi[k];
+        for (int64_t C = 0; C < c->cnt; ++C) {  // ((P c_i)^2, psi_k) through the trilinear tensor
+          int k[4];
+          double pl[4];
+          for (int q = 0; q < 4; ++q) {
+            k[q] = c->cv2d[c->ctets[4 * C + q]];
+            pl[q] = k[q] >= 0 ? ph[k[q]] : 0.0;
+          }
+          const double* T = &c->h_tri[20 * C];
+          for (int jj = 0; jj < 4; ++jj) {
+            if (k[jj] < 0) continue;
+            double sacc = 0.0;
+            for (int mm = 0; mm < 4; ++mm)
+              for (int ll = 0; ll < 4; ++ll) sacc += T[ti.idx[jj][mm][ll]] * pl[mm] * pl[ll];
+            fH[k[jj]] += f * sacc;
+          }
+        }
+        symv(G, nH, ph.data(), tmp.data());
+        double g1 = dot(ph.data(), tmp.data(), nH), g2 = 0.0, g3 = 0.0;
+        for (int j = 0; j < N; ++j) {
+          if (di[j] == 0.0) continue;
+          ah4_apply(j, ph.data(), tmp.data());  // (u_j P c_i, psi_k)
+          for (int64_t k = 0; k < nH; ++k) fH[k] += f * 2.0 * di[j] * tmp[k];
+          double pw = 0.0;
+          for (int64_t k = 0; k < nH; ++k) pw += fb.ptW[k * N + j] * ph[k];
+          g2 += di[j] * pw;
+          for (int l = 0; l < N; ++l) {
+            const double dd = di[j] * di[l];
+            const int p = pair_index(N, j, l);
+            for (int64_t k = 0; k < nH; ++k) fH[k] += f * dd * R[(int64_t)k * npair + p];
+            g3 += dd * 0.5 * (fb.utW[j * N + l] + fb.utW[l * N + j]);
+          }
+        }
+        gsum += f * (g1 + 2.0 * g2 + g3);
+      }
+      const double fourpi = 4.0 * 3.14159265358979323846;
+      std::vector<double> r1(nH);
+      for (int64_t k = 0; k < nH; ++k) r1[k] = fourpi * fH[k] - fb.liftH[k];
+      const double r2 = fourpi * gsum - fb.liftT;
+      forward(c->h_Kh_chol, nH, r1.data());
+      backward(c->h_Kh_chol, nH, r1.data());
+      const double t1 = (r2 - dot(fb.d.data(), r1.data(), nH)) / schur;
+      for (int64_t k = 0; k < nH; ++k) xout[k] = r1[k] - yd[k] * t1;
+      xout[nH] = t1;
+    }
+    // (c) ||Phi^{s+1} - Phi^s||_{H^1} in the joint basis
+    double d2 = 0.0;
+    std::vector<double> dx(m);
+    for (int i = 0; i < N; ++i) {
+      for (int64_t a = 0; a < m; ++a) dx[a] = X[(size_t)i * m + a] - Xold[(size_t)i * m + a];
+      for (int64_t a = 0; a < m; ++a) d2 += dx[a] * dot(&KMj[a * m], dx.data(), m);
+    }
+    diff = std::sqrt(std::max(d2, 0.0));
+    Xold = X;
+    if (!hart) break;
+    const bool done = diff < c->opt.inner_tol;
+    if (!done && s == maxit - 1) st = MLC_WARN_INNER_MAXIT;
+    if (done || s == maxit - 1 || c->opt.inner_mix_history <= 0) {
+      std::copy(xout.begin(), xout.begin() + nH, wH.begin());
+      th1 = xout[nH];
+      if (done || s == maxit - 1) break;
+      continue;
+    }
+    std::copy(wH.begin(), wH.end(), xin.begin());
+    xin[nH] = th1;
+    for (int64_t k = 0; k <= nH; ++k) fres[k] = xout[k] - xin[k];
+    symv(KHd, nH, fres.data(), gres.data());
+    for (int64_t k = 0; k < nH; ++k) gres[k] += fb.d[k] * fres[nH];
+    gres[nH] = dot(fb.d.data(), fres.data(), nH) + fb.zeta * fres[nH];
+    mix.next(xin, fres, gres);
+    std::copy(xin.begin(), xin.begin() + nH, wH.begin());
+    th1 = xin[nH];
+  }
+  out.lam = lam;
+  out.phiH.assign((size_t)nH * N, 0.0);
+  out.D.assign((size_t)N * N, 0.0);
+  out.theta2.assign(N, 0.0);
+  for (int i = 0; i < N; ++i) {
+    const double* xi = &Xold[(size_t)i * m];
+    for (int64_t k = 0; k < nH; ++k) out.phiH[k * N + i] = xi[k];
+    for (int j = 0; j < N; ++j) out.D[(size_t)j * N + i] = xi[nH + j];
+    out.theta2[i] = xi[nH + i];
+  }
+  out.wH = wH;
+  out.theta1 = th1;
+  out.iters = its;
+  out.last_diff = diff;
+  out.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
 }  // namespace mlc

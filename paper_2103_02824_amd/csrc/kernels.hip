@@ -467,101 +467,6 @@ __global__ void __launch_bounds__(TPB) k_normalize_cols(int64_t total, int N, co
   X[i] = X[i] / sqrt(s[i % N]);
 }
 
-// out[k, c] = sum_{a in P^T row k} w_a Y[a, c]  (restriction P^T Y, gather form).
-// One block per coarse row: the threads stride over the row's fine entries,
-// then wavefront shuffles and a fixed-order sum of the four waves.
-__global__ void __launch_bounds__(TPB) k_restrict(int64_t nH, int N, const int32_t* __restrict__ PTptr,
-                                                  const int32_t* __restrict__ PTidx, const double* __restrict__ PTw,
-                                                  const double* __restrict__ Y, double* __restrict__ out) {
-  __shared__ double ws[TPB / 64][8];
-  const int64_t k = blockIdx.x;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int e0 = PTptr[k], e1 = PTptr[k + 1];
-  for (int c0 = 0; c0 < N; c0 += 8) {
-    const int nc = N - c0 < 8 ? N - c0 : 8;
-    double acc[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    // four entries per thread and step, their index and weight loads issued
-    // together, then the four gathers (entries past the end: weight zero)
-    for (int e = e0 + (int)threadIdx.x; e < e1; e += 4 * TPB) {
-      int idx[4];
-      double w[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const bool ok = e + u * TPB < e1;
-        idx[u] = ok ? PTidx[e + u * TPB] : PTidx[e];
-        w[u] = ok ? PTw[e + u * TPB] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double* y = Y + (int64_t)idx[u] * N + c0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (q < nc) acc[q] += w[u] * y[q];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      double v = acc[q];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-      if (lane == 0) ws[wid][q] = v;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nc) {
-      const int q = threadIdx.x;
-      out[k * N + c0 + q] = (ws[0][q] + ws[1][q]) + (ws[2][q] + ws[3][q]);
-    }
-    __syncthreads();
-  }
-}
-
-// The restriction for N > 8: lane c of each wavefront owns column c0 + c
-// (c0 = 0, 64, ...), the RW = 16 wavefronts of the block take interleaved
-// groups of 8 of the coarse row's fine entries (a coarse hat spans thousands
-// of fine DoFs; index and weight loads issued together, then the 8 gathered
-// row segments; entries past the end repeat the first with weight zero), and
-// the wave sums are added in fixed order.
-constexpr int RW = 16;
-__global__ void __launch_bounds__(64 * RW) k_restrict_lanes(int64_t nH, int N, const int32_t* __restrict__ PTptr,
-                                                        const int32_t* __restrict__ PTidx,
-                                                        const double* __restrict__ PTw, const double* __restrict__ Y,
-                                                        double* __restrict__ out) {
-  constexpr int U = 8;
-  __shared__ double ws[RW][64];
-  const int64_t k = blockIdx.x;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int e0 = PTptr[k], e1 = PTptr[k + 1];
-  for (int c0 = 0; c0 < N; c0 += 64) {
-    const int c = c0 + lane;
-    double acc = 0.0;
-    for (int e = e0 + U * wid; e < e1; e += U * RW) {
-      int idx[U];
-      double w[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const bool ok = e + u < e1;
-        idx[u] = ok ? PTidx[e + u] : PTidx[e0];
-        w[u] = ok ? PTw[e + u] : 0.0;
-      }
-      double y[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) y[u] = c < N ? Y[(int64_t)idx[u] * N + c] : 0.0;
-#pragma unroll
-      for (int u = 0; u < U; ++u) acc += w[u] * y[u];
-    }
-    ws[wid][lane] = acc;
-    __syncthreads();
-    if (wid == 0 && c < N) {
-      double t = 0.0;
-#pragma unroll
-      for (int w = 0; w < RW; ++w) t += ws[w][lane];
-      out[k * N + c] = t;
-    }
-    __syncthreads();
-  }
-}
-
 // Chunked restriction P^T Y. Each block takes one chunk of RESTRICT_CHUNK
 // consecutive fine rows: it copies the chunk's rows of Y (contiguous, RCOL
 // columns at a time) into LDS with coalesced loads, then each wavefront sums
@@ -569,36 +474,104 @@ __global__ void __launch_bounds__(64 * RW) k_restrict_lanes(int64_t nH, int N, c
 // row order) with a lane per column, reading the rows from LDS. Every row of Y
 // is read from HBM once; the four coarse parents of a row read it from LDS.
 constexpr int RCOL = 64;
+constexpr int RENT_MAX = 4 * RESTRICT_CHUNK;  // entries of one chunk: at most four coarse parents per row
 __global__ void __launch_bounds__(TPB) k_restrict_chunks(int64_t n, int N, const int32_t* __restrict__ rch_seg,
                                                          const int32_t* __restrict__ rseg_ptr,
                                                          const int32_t* __restrict__ rent_row,
                                                          const double* __restrict__ rent_w,
                                                          const double* __restrict__ Y, double* __restrict__ part) {
   __shared__ double yl[RESTRICT_CHUNK * RCOL];
+  __shared__ double ew[RENT_MAX];
+  __shared__ int32_t er[RENT_MAX];
   const int64_t r0 = (int64_t)blockIdx.x * RESTRICT_CHUNK;
   const int nr = (int)(n - r0 < RESTRICT_CHUNK ? n - r0 : RESTRICT_CHUNK);
   const int s0 = rch_seg[blockIdx.x], s1 = rch_seg[blockIdx.x + 1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // the tile's row stride in LDS: N when one tile holds every column (the
+  // chunk's rows of Y are then one contiguous block, copied as such)
+  const int ld = N <= RCOL ? N : RCOL;
+  const int e00 = rseg_ptr[s0], ne = rseg_ptr[s1] - e00;
+  for (int t = threadIdx.x; t < ne; t += TPB) {
+    er[t] = rent_row[e00 + t] * ld;
+    ew[t] = rent_w[e00 + t];
+  }
   for (int c0 = 0; c0 < N; c0 += RCOL) {
     const int nc = N - c0 < RCOL ? N - c0 : RCOL;
-    // stage rows r0 .. r0 + nr of columns c0 .. c0 + nc: thread t takes
-    // element (t / nc, t % nc) of the tile, so consecutive threads read
-    // consecutive addresses within a row and the rows follow each other
-    const double* src = Y + r0 * N + c0;
-    for (int t = threadIdx.x; t < nr * nc; t += TPB) {
-      const int r = t / nc, q = t - r * nc;
-      yl[r * RCOL + q] = src[(int64_t)r * N + q];
+    if (N <= RCOL) {
+      // contiguous copy, four loads in flight per thread
+      const double* src = Y + r0 * N;
+      const int tot = nr * N;
+      for (int t = threadIdx.x; t < tot; t += 4 * TPB) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = t + u * TPB < tot ? src[t + u * TPB] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (t + u * TPB < tot) yl[t + u * TPB] = v[u];
+      }
+    } else {
+      const double* src = Y + r0 * N + c0;
+      for (int r = threadIdx.x / RCOL; r < nr; r += TPB / RCOL) {
+        const int q = threadIdx.x % RCOL;
+        if (q < nc) yl[r * RCOL + q] = src[(int64_t)r * N + q];
+      }
     }
     __syncthreads();
-    for (int g = s0 + wid; g < s1; g += TPB / 64) {
-      const int e0 = rseg_ptr[g], e1 = rseg_ptr[g + 1];
-      double acc = 0.0;
-      if (lane < nc)
-        for (int e = e0; e < e1; ++e) acc += rent_w[e] * yl[rent_row[e] * RCOL + lane];
-      if (lane < nc) part[(int64_t)g * N + c0 + lane] = acc;
-    }
+    if (lane < nc)
+      for (int g = s0 + wid; g < s1; g += TPB / 64) {
+        const int e0 = rseg_ptr[g] - e00, e1 = rseg_ptr[g + 1] - e00;
+        double acc = 0.0;
+        int e = e0;
+        for (; e + 4 <= e1; e += 4) {
+          const double y0 = yl[er[e] + lane], y1 = yl[er[e + 1] + lane], y2 = yl[er[e + 2] + lane],
+                       y3 = yl[er[e + 3] + lane];
+          acc += ew[e] * y0;
+          acc += ew[e + 1] * y1;
+          acc += ew[e + 2] * y2;
+          acc += ew[e + 3] * y3;
+        }
+        for (; e < e1; ++e) acc += ew[e] * yl[er[e] + lane];
+        part[(int64_t)g * N + c0 + lane] = acc;
+      }
     __syncthreads();
   }
+}
+
+// The chunked restriction of one column (N = 1): the chunk's 128 values in
+// LDS, a wavefront per segment with its lanes over the segment's entries and
+// a fixed shuffle tree for the sum.
+__global__ void __launch_bounds__(TPB) k_restrict_chunks1(int64_t n, const int32_t* __restrict__ rch_seg,
+                                                          const int32_t* __restrict__ rseg_ptr,
+                                                          const int32_t* __restrict__ rent_row,
+                                                          const double* __restrict__ rent_w,
+                                                          const double* __restrict__ Y, double* __restrict__ part) {
+  __shared__ double yl[RESTRICT_CHUNK];
+  const int64_t r0 = (int64_t)blockIdx.x * RESTRICT_CHUNK;
+  const int nr = (int)(n - r0 < RESTRICT_CHUNK ? n - r0 : RESTRICT_CHUNK);
+  const int s0 = rch_seg[blockIdx.x], s1 = rch_seg[blockIdx.x + 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int t = threadIdx.x; t < nr; t += TPB) yl[t] = Y[r0 + t];
+  __syncthreads();
+  for (int g = s0 + wid; g < s1; g += TPB / 64) {
+    double acc = 0.0;
+    for (int e = rseg_ptr[g] + lane; e < rseg_ptr[g + 1]; e += 64) acc += rent_w[e] * yl[rent_row[e]];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) part[g] = acc;
+  }
+}
+
+// out[k] = sum of the segment partials of coarse DoF k (N = 1): a wavefront per
+// coarse DoF, its lanes over the segments, a fixed shuffle tree.
+__global__ void __launch_bounds__(TPB) k_restrict_sum1(int64_t nH, const int32_t* __restrict__ kseg_ptr,
+                                                       const int32_t* __restrict__ kseg,
+                                                       const double* __restrict__ part, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= nH) return;
+  double acc = 0.0;
+  for (int j = kseg_ptr[k] + lane; j < kseg_ptr[k + 1]; j += 64) acc += part[kseg[j]];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) out[k] = acc;
 }
 
 // out[k, c] = sum of the segment partials of coarse DoF k, in chunk order: one
@@ -611,8 +584,18 @@ __global__ void __launch_bounds__(TPB) k_restrict_sum(int64_t nH, int N, const i
   if (k >= nH) return;
   const int j0 = kseg_ptr[k], j1 = kseg_ptr[k + 1];
   for (int c = lane; c < N; c += 64) {
+    // four segments' loads in flight, summed in segment order
     double acc = 0.0;
-    for (int j = j0; j < j1; ++j) acc += part[(int64_t)kseg[j] * N + c];
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+      const int64_t g0 = kseg[j], g1 = kseg[j + 1], g2 = kseg[j + 2], g3 = kseg[j + 3];
+      const double p0 = part[g0 * N + c], p1 = part[g1 * N + c], p2 = part[g2 * N + c], p3 = part[g3 * N + c];
+      acc += p0;
+      acc += p1;
+      acc += p2;
+      acc += p3;
+    }
+    for (; j < j1; ++j) acc += part[(int64_t)kseg[j] * N + c];
     out[k * N + c] = acc;
   }
 }
@@ -843,20 +826,98 @@ __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, int64_t ng, con
 }
 
 // Per orbital i and coarse tet: the 10 entries (u_i psi_j, psi_m) and the 4
-// entries (u_i^2, psi_j); ORB_CHUNK orbitals per pass over the fine tets,
-// whose DoFs come from the per-mesh table grp_dof (group order).
-constexpr int ORB_CHUNK = 2;
-__global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, int64_t ng, const int32_t* __restrict__ grp_ptr,
+// entries (u_i^2, psi_j). One block per coarse tet; its fine tets (group
+// order, DoFs from the per-mesh table grp_dof) in tiles of ORB_TILE whose hat
+// values, weights and DoFs are staged in LDS once for all orbitals. Lane l of
+// each wave owns orbital i0 + l (64 orbitals per pass); the block's 4 waves
+// take every 4th tet of the tile (the LDS reads are broadcasts, the U reads of
+// a wave one contiguous row segment). The 4 partial sums per orbital are added
+// in a fixed order.
+constexpr int ORB_TILE = 64;
+__global__ void __launch_bounds__(256) k_coarse_orb(int64_t cnt, int64_t ng, const int32_t* __restrict__ grp_ptr,
                                                     const int32_t* __restrict__ grp_dof,
                                                     const double* __restrict__ chat, const double* __restrict__ U,
                                                     int N, double* __restrict__ out) {
-  __shared__ double ws[4 * ORB_CHUNK * 14];
-  int64_t C = blockIdx.x;
-  for (int i0 = 0; i0 < N; i0 += ORB_CHUNK) {
-    const int nc = N - i0 < ORB_CHUNK ? N - i0 : ORB_CHUNK;
-    double acc[ORB_CHUNK * 14];
+  __shared__ double sh[ORB_TILE * 17];
+  __shared__ int32_t sdof[ORB_TILE * 4];
+  __shared__ double red[3 * 14 * 64];
+  const int64_t C = blockIdx.x;
+  const int lane = threadIdx.x & 63, slot = threadIdx.x >> 6;
+  const int e0 = grp_ptr[C], e1 = grp_ptr[C + 1];
+  for (int i0 = 0; i0 < N; i0 += 64) {
+    const int i = i0 + lane;
+    const int ic = i < N ? i : N - 1;  // lanes past N repeat the last orbital (never stored)
+    double acc[14];
 #pragma unroll
-    for (int k = 0; k < ORB_CHUNK * 14; ++k) acc[k] = 0.0;
+    for (int k = 0; k < 14; ++k) acc[k] = 0.0;
+    for (int t0 = e0; t0 < e1; t0 += ORB_TILE) {
+      const int ne = e1 - t0 < ORB_TILE ? e1 - t0 : ORB_TILE;
+      __syncthreads();
+      for (int k = threadIdx.x; k < 17 * ne; k += 256) {
+        const int q = k / ne, t = k - q * ne;
+        sh[t * 17 + q] = chat[(int64_t)q * ng + t0 + t];
+      }
+      for (int k = threadIdx.x; k < 4 * ne; k += 256) sdof[k] = grp_dof[4 * (int64_t)t0 + k];
+      __syncthreads();
+      for (int t = slot; t < ne; t += 4) {
+        const double* h = sh + t * 17;
+        const double w = 0.25 * h[16];
+        double u[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int dof = sdof[4 * t + a];
+          const double v = U[(int64_t)(dof >= 0 ? dof : 0) * N + ic];
+          u[a] = dof >= 0 ? v : 0.0;
+        }
+        const double us = u[0] + u[1] + u[2] + u[3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double uq = QB * us + (QA - QB) * u[q];
+          const double wu = w * uq;
+          double ps[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) ps[j] = h[4 * q + j];
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int m = j; m < 4; ++m) acc[j * 4 - (j * (j - 1)) / 2 + (m - j)] += wu * ps[j] * ps[m];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[10 + j] += wu * uq * ps[j];
+        }
+      }
+    }
+    // the partial sums of waves 1..3 through LDS, added by wave 0 in slot order
+    __syncthreads();
+    if (slot > 0)
+#pragma unroll
+      for (int k = 0; k < 14; ++k) red[((slot - 1) * 14 + k) * 64 + lane] = acc[k];
+    __syncthreads();
+    if (slot == 0 && i < N) {
+#pragma unroll
+      for (int k = 0; k < 14; ++k) {
+        const double v = ((acc[k] + red[k * 64 + lane]) + red[(14 + k) * 64 + lane]) + red[(28 + k) * 64 + lane];
+        out[14 * (C * N + i) + k] = v;
+      }
+    }
+  }
+}
+
+// Joint-space variant: per coarse tet and orbital pair (j <= l) the 4 entries
+// (u_j u_l, psi_m) over the coarse tet's vertices m; PAIR_CHUNK pairs per pass
+// over the fine tets (pairs in the order (0,0), (0,1), ..., (0,N-1), (1,1), ...).
+constexpr int PAIR_CHUNK = 4;
+__global__ void __launch_bounds__(TPB) k_coarse_pairs(int64_t cnt, int64_t ng, const int32_t* __restrict__ grp_ptr,
+                                                      const int32_t* __restrict__ grp_dof,
+                                                      const double* __restrict__ chat, const double* __restrict__ U,
+                                                      int N, const int32_t* __restrict__ pair_jl, int npair,
+                                                      double* __restrict__ out) {
+  __shared__ double ws[4 * PAIR_CHUNK * 4];
+  const int64_t C = blockIdx.x;
+  for (int p0 = 0; p0 < npair; p0 += PAIR_CHUNK) {
+    const int np = npair - p0 < PAIR_CHUNK ? npair - p0 : PAIR_CHUNK;
+    double acc[PAIR_CHUNK * 4];
+#pragma unroll
+    for (int k = 0; k < PAIR_CHUNK * 4; ++k) acc[k] = 0.0;
     for (int e = grp_ptr[C] + threadIdx.x; e < grp_ptr[C + 1]; e += TPB) {
       const int4 dq = reinterpret_cast<const int4*>(grp_dof)[e];
       const int dof[4] = {dq.x, dq.y, dq.z, dq.w};
@@ -865,30 +926,48 @@ __global__ void __launch_bounds__(TPB) k_coarse_orb(int64_t cnt, int64_t ng, con
       for (int k = 0; k < 16; ++k) h[k] = chat[(int64_t)k * ng + e];
       const double w = 0.25 * chat[16 * ng + e];
 #pragma unroll
-      for (int o = 0; o < ORB_CHUNK; ++o) {
-        if (o >= nc) continue;
-        double u[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) u[a] = dof[a] >= 0 ? U[(int64_t)dof[a] * N + i0 + o] : 0.0;
-        const double us = u[0] + u[1] + u[2] + u[3];
+      for (int o = 0; o < PAIR_CHUNK; ++o) {
+        if (o >= np) continue;
+        const int jj = pair_jl[2 * (p0 + o)], ll = pair_jl[2 * (p0 + o) + 1];
+        double a[4], b[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const double uq = QB * us + (QA - QB) * u[q];
-          double ps[4];
+          a[q] = dof[q] >= 0 ? U[(int64_t)dof[q] * N + jj] : 0.0;
+          b[q] = dof[q] >= 0 ? U[(int64_t)dof[q] * N + ll] : 0.0;
+        }
+        const double as = a[0] + a[1] + a[2] + a[3], bs = b[0] + b[1] + b[2] + b[3];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) ps[j] = h[4 * q + j];
+        for (int q = 0; q < 4; ++q) {
+          const double aq = QB * as + (QA - QB) * a[q], bq = QB * bs + (QA - QB) * b[q];
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int m = j; m < 4; ++m) acc[14 * o + j * 4 - (j * (j - 1)) / 2 + (m - j)] += w * uq * ps[j] * ps[m];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[14 * o + 10 + j] += w * uq * uq * ps[j];
+          for (int m = 0; m < 4; ++m) acc[4 * o + m] += w * aq * bq * h[4 * q + m];
         }
       }
     }
-    const double v = block_sums<ORB_CHUNK * 14>(acc, ws);
-    if ((int)threadIdx.x < 14 * nc) out[14 * (C * N + i0) + threadIdx.x] = v;
+    const double v = block_sums<PAIR_CHUNK * 4>(acc, ws);
+    if ((int)threadIdx.x < 4 * np) out[4 * (C * npair + p0) + threadIdx.x] = v;
   }
+}
+
+// Joint-space reconstruction: Phi[a, i] = sum_s Pw[a, s] C[Pk[a, s], i] + sum_j U[a, j] D[j, i]
+// (C: N_H x N coarse coefficients, D: N x N coefficients of the u_j).
+__global__ void __launch_bounds__(TPB) k_reconstruct_joint(int64_t n, int N, const int32_t* __restrict__ Pk,
+                                                           const double* __restrict__ Pw,
+                                                           const double* __restrict__ Cc, const double* __restrict__ D,
+                                                           const double* __restrict__ U, double* __restrict__ Phi) {
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= n * N) return;
+  const int64_t a = t / N;
+  const int i = (int)(t - a * N);
+  double v = 0.0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = Pk[4 * a + s];
+    if (k >= 0) v += Pw[4 * a + s] * Cc[(int64_t)k * N + i];
+  }
+  const double* ua = U + a * N;
+  for (int j = 0; j < N; ++j) v += ua[j] * D[j * N + i];
+  Phi[t] = v;
 }
 
 // Trilinear tensor T_jkm = int psi_j psi_k psi_m (fine quadrature), 20 entries
@@ -1313,21 +1392,22 @@ void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, do
   hipLaunchKernelGGL(k_normalize_cols, dim3(nb(n * N)), dim3(TPB), 0, s, n * N, N, sc, X);
 }
 void launch_restrict_chunks(hipStream_t s, int64_t n, int64_t nH, int N, const Dev& d, const double* Y,
-                            double* out) {
+                            double* out, double* part) {
   const int64_t nch = (n + RESTRICT_CHUNK - 1) / RESTRICT_CHUNK;
+  if (!part) part = d.rpart;
+  const dim3 gs((unsigned)((nH + TPB / 64 - 1) / (TPB / 64)));
+  if (N == 1) {
+    if (nch > 0)
+      hipLaunchKernelGGL(k_restrict_chunks1, dim3((unsigned)nch), dim3(TPB), 0, s, n, d.rch_seg, d.rseg_ptr,
+                         d.rent_row, d.rent_w, Y, part);
+    if (nH > 0) hipLaunchKernelGGL(k_restrict_sum1, gs, dim3(TPB), 0, s, nH, d.kseg_ptr, d.kseg, part, out);
+    return;
+  }
   if (nch > 0)
     hipLaunchKernelGGL(k_restrict_chunks, dim3((unsigned)nch), dim3(TPB), 0, s, n, N, d.rch_seg, d.rseg_ptr,
-                       d.rent_row, d.rent_w, Y, d.rpart);
+                       d.rent_row, d.rent_w, Y, part);
   if (nH > 0)
-    hipLaunchKernelGGL(k_restrict_sum, dim3((unsigned)((nH + TPB / 64 - 1) / (TPB / 64))), dim3(TPB), 0, s, nH, N,
-                       d.kseg_ptr, d.kseg, d.rpart, out);
-}
-void launch_restrict(hipStream_t s, int64_t nH, int N, const int32_t* PTptr, const int32_t* PTidx, const double* PTw,
-                     const double* Y, double* out) {
-  if (N > 8)
-    hipLaunchKernelGGL(k_restrict_lanes, dim3((unsigned)nH), dim3(64 * RW), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
-  else
-    hipLaunchKernelGGL(k_restrict, dim3((unsigned)nH), dim3(TPB), 0, s, nH, N, PTptr, PTidx, PTw, Y, out);
+    hipLaunchKernelGGL(k_restrict_sum, gs, dim3(TPB), 0, s, nH, N, d.kseg_ptr, d.kseg, part, out);
 }
 void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double* Y, double* partial) {
   const dim3 g(gram_blocks(n)), b(TPB);
@@ -1354,8 +1434,17 @@ void launch_coarse_ops(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* gr
 }
 void launch_coarse_orb(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* grp_ptr, const int32_t* grp_dof,
                        const double* chat, const double* U, int N, double* out) {
-  hipLaunchKernelGGL(k_coarse_orb, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, ng, grp_ptr, grp_dof, chat, U, N,
+  hipLaunchKernelGGL(k_coarse_orb, dim3((unsigned)cnt), dim3(256), 0, s, cnt, ng, grp_ptr, grp_dof, chat, U, N,
                      out);
+}
+void launch_coarse_pairs(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* grp_ptr, const int32_t* grp_dof,
+                         const double* chat, const double* U, int N, const int32_t* pair_jl, int npair, double* out) {
+  hipLaunchKernelGGL(k_coarse_pairs, dim3((unsigned)cnt), dim3(TPB), 0, s, cnt, ng, grp_ptr, grp_dof, chat, U, N,
+                     pair_jl, npair, out);
+}
+void launch_reconstruct_joint(hipStream_t s, int64_t n, int N, const int32_t* Pk, const double* Pw, const double* Cc,
+                              const double* D, const double* U, double* Phi) {
+  hipLaunchKernelGGL(k_reconstruct_joint, dim3(nb(n * N)), dim3(TPB), 0, s, n, N, Pk, Pw, Cc, D, U, Phi);
 }
 void launch_coarse_tri(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
                        const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* out) {

@@ -86,6 +86,7 @@ struct Dev {
   int32_t* kseg_ptr = nullptr;  // nH + 1
   int32_t* kseg = nullptr;      // nseg
   double* rpart = nullptr;      // nseg x N
+  double* rpartH = nullptr;     // nseg: the Hartree CG's coarse correction (beside the Gram blocks)
   int32_t* PTptr = nullptr;     // nH + 1
   int32_t* PTidx = nullptr;
   double* PTw = nullptr;
@@ -97,6 +98,8 @@ struct Dev {
   double* cel_ops = nullptr;    // cnt x 40
   double* cel_orb = nullptr;    // cnt x N x 14
   double* cel_tri = nullptr;    // cnt x 20
+  double* cel_pairs = nullptr;  // joint variant: cnt x npair x 4, (u_j u_l, psi_m)
+  int32_t* pair_jl = nullptr;   // joint variant: the pairs (j <= l), 2 x npair
   double* chat = nullptr;       // 17 x nt: coarse hats at fine quadrature points, fine volume
   // small
   double* small = nullptr;      // packed small blocks (see step.cpp)
@@ -125,6 +128,7 @@ struct Dev {
   int32_t* dof_user = nullptr;  // n: library dof -> caller dof
   int32_t* chk = nullptr;       // 4: count of non-finite inputs (mlc_set_state)
   double* lmax = nullptr;       // 2: Gershgorin bounds of D^-1 A (step 5) and D^-1 K (Hartree)
+  float* valK32 = nullptr;      // nnz: K in FP32 for the Hartree CG's polynomial steps
   double* KHinv = nullptr;      // nH x nH: inverse of the coarse stiffness (two-level Hartree CG)
   double* rH = nullptr;         // nH: restricted residual
   double* eH = nullptr;         // nH: coarse correction
@@ -192,7 +196,7 @@ struct mlc_ctx {
   std::vector<double> last_theta2, last_phiH, last_wH;
   double last_theta1 = 0.0, last_sigma = 0.0;
   std::vector<double> last_small;       // packed small blocks of the fine stage
-  std::vector<double> last_cel_ops, last_cel_orb;
+  std::vector<double> last_cel_ops, last_cel_orb, last_cel_pairs;
   int64_t small_len = 0;
   std::string err;
   // timing of the dominant kernel
@@ -244,9 +248,9 @@ struct PolyPC {
   const double* lmax;  // device scalar: Gershgorin bound of D^-1 A
   double ratio;        // interval [lmax / ratio, lmax]
   int degree;          // >= 2
-  T* Z[2];             // ping-pong blocks, n x N each
-  T* Dd;               // n x N
+  T* Z[2];             // ping-pong blocks of the iterates, n x N each
   double* rz_part;     // per-block r.z partials of the last step (spmm_blocks(n, N) x N)
+  const float* val32 = nullptr;  // optional FP32 copy of the matrix values for the steps (FP64, one column)
 };
 template <typename T>
 void launch_cg_init_t(hipStream_t s, int64_t n, int N, const T* B, const T* AX, const T* dinv, T* Rv, T* P,
@@ -262,6 +266,10 @@ void launch_cg_direction_t(hipStream_t s, int64_t n, int N, const T* dinv, const
 template <typename T>
 void launch_cheb_steps_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val,
                          const T* dinv, const T* Rv, const PolyPC<T>& pc, T* last_out, const int32_t* flags);
+template <typename T>
+void launch_cheb_step_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val,
+                        const T* dinv, const T* Rv, const PolyPC<T>& pc, int j, const T* zin, const T* zprev,
+                        T* zout, double* part, const int32_t* flags);
 void launch_cg_start2(hipStream_t s, int64_t n, int N, const double* partial, double rtol2, const double* mask,
                       double* scal, int32_t* flags, const double* rz_part);
 // Direction with an explicit preconditioned residual Zl and its r.z partials
@@ -340,13 +348,13 @@ void launch_scale_cols_to(hipStream_t s, int64_t n, int N, const double* X, cons
 void launch_coldot(hipStream_t s, int64_t n, int N, const double* X, const double* Y, double* partial);
 void launch_reduce_cols(hipStream_t s, int N, int nblk, const double* partial, double* out);
 void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, double* X);
-void launch_restrict(hipStream_t s, int64_t nH, int N, const int32_t* PTptr, const int32_t* PTidx, const double* PTw,
-                     const double* Y, double* out);
 // P^T Y (nH x N) through the chunk structure: each chunk of RESTRICT_CHUNK
 // fine rows of Y is read once (into LDS), its segment sums go to part, then
 // the segments of each coarse DoF are summed in chunk order into out.
 constexpr int RESTRICT_CHUNK = 128;
-void launch_restrict_chunks(hipStream_t s, int64_t n, int64_t nH, int N, const Dev& d, const double* Y, double* out);
+// part: the segment partials (nseg x N; null: d.rpart)
+void launch_restrict_chunks(hipStream_t s, int64_t n, int64_t nH, int N, const Dev& d, const double* Y, double* out,
+                            double* part = nullptr);
 void launch_gram(hipStream_t s, int64_t n, int N, const double* U, const double* Y, double* partial);
 // chat: per fine tet in coarse-group order e, the parent's coarse hats at its
 // quadrature points (16) and its volume: 17 arrays of ng = nt doubles (value
@@ -357,6 +365,12 @@ void launch_coarse_ops(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* gr
                        const double* chat, const double* cgeo, const double* fA, const double* fW, double* out);
 void launch_coarse_orb(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* grp_ptr, const int32_t* grp_dof,
                        const double* chat, const double* U, int N, double* out);
+// joint-space variant: (u_j u_l, psi_m) per coarse tet and pair, 4 values each (out: cnt x npair x 4)
+void launch_coarse_pairs(hipStream_t s, int64_t cnt, int64_t ng, const int32_t* grp_ptr, const int32_t* grp_dof,
+                         const double* chat, const double* U, int N, const int32_t* pair_jl, int npair, double* out);
+// Phi = P C + U D (C: nH x N, D: N x N, both row-major)
+void launch_reconstruct_joint(hipStream_t s, int64_t n, int N, const int32_t* Pk, const double* Pw, const double* Cc,
+                              const double* D, const double* U, double* Phi);
 void launch_coarse_tri(hipStream_t s, int64_t cnt, const int32_t* grp_ptr, const int32_t* grp_tet,
                        const int32_t* tets, const double* geo, const double* xyz, const double* cgeo, double* out);
 void launch_reconstruct(hipStream_t s, int64_t n, int N, const int32_t* Pk, const double* Pw, const double* phiH,

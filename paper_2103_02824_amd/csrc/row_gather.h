@@ -10,22 +10,26 @@ namespace mlc {
 // acc[c] += sum over this lane's nonzeros of row r (every G-th from
 // rowptr[r] + sub) of a_rj X[j][c]; U nonzeros per pass have their column
 // and value loads issued together, then their gathers. Entries past the row
-// end read row r itself with a zero weight (the same terms in the same order
-// as a plain loop, since adding +0 changes nothing).
-template <int NT, int G, int U, typename T>
-__device__ __forceinline__ void row_gather(int64_t r, int sub, const int32_t* __restrict__ rowptr,
-                                           const int32_t* __restrict__ col, const T* __restrict__ val,
-                                           const T* __restrict__ X, T (&acc)[NT]) {
-  const int j1 = rowptr[r + 1];
-  for (int j = rowptr[r] + sub; j < j1; j += G * U) {
+// end repeat the row's last entry with a zero weight (the same terms in the
+// same order as a plain loop, since adding +0 changes nothing), so every load
+// is in bounds and issued unconditionally: no branch inside the pass, and all
+// U gathers are in flight at once.
+// The matrix values may be stored in a narrower type VT than the vectors (T):
+// each value is widened before its product.
+// (jb, j1: the row's entry range, loaded by the caller.)
+template <int NT, int G, int U, typename VT, typename T>
+__device__ __forceinline__ void row_gather(int jb, int j1, int sub, const int32_t* __restrict__ col,
+                                           const VT* __restrict__ val, const T* __restrict__ X, T (&acc)[NT]) {
+  for (int j = jb + sub; j < j1; j += G * U) {
     int cc[U];
     T vv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = j + u * G;
-      const bool ok = e < j1;
-      cc[u] = ok ? col[e] : (int)r;
-      vv[u] = ok ? val[e] : T(0);
+      const uint32_t ec = (uint32_t)(e < j1 ? e : j1 - 1);
+      cc[u] = col[ec];
+      const T a = (T)val[ec];
+      vv[u] = e < j1 ? a : T(0);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -34,6 +38,12 @@ __device__ __forceinline__ void row_gather(int64_t r, int sub, const int32_t* __
       for (int c = 0; c < NT; ++c) acc[c] += vv[u] * xr[c];
     }
   }
+}
+template <int NT, int G, int U, typename VT, typename T>
+__device__ __forceinline__ void row_gather(int64_t r, int sub, const int32_t* __restrict__ rowptr,
+                                           const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                           const T* __restrict__ X, T (&acc)[NT]) {
+  row_gather<NT, G, U>(rowptr[r], rowptr[r + 1], sub, col, val, X, acc);
 }
 
 // Layout of the kernels for N > 8 orbitals: a lane owns V consecutive columns
@@ -53,6 +63,12 @@ __host__ __device__ inline WideShape wide_shape(int N, int vmax) {
 template <int L_, int V_, int NCH_>
 struct WideTag {
   static constexpr int L = L_, V = V_, NCH = NCH_;
+  static constexpr bool O32 = false;
+};
+// the same layout with 32-bit gather offsets
+template <typename Tag>
+struct WideTag32 : Tag {
+  static constexpr bool O32 = true;
 };
 
 template <typename T, int V>
@@ -88,37 +104,55 @@ __device__ __forceinline__ void store_cols(T* __restrict__ p, const T (&o)[V]) {
   }
 }
 
-// acc[h][v] = (A X)[r, (g + L h) V + v] for the lane's column group g (zero
-// where the group lies past N).
-template <int L, int V, int NCH, int WU, typename T>
+// Column offset of the lane's group h, clamped into the row: lanes whose
+// group lies past N read the row's last V columns (their sums are never
+// stored), so that the loads need no branch.
+template <int L, int V>
+__device__ __forceinline__ int lane_col(int g, int h, int N) {
+  const int c = (g + L * h) * V;
+  return c < N ? c : N - V;
+}
+
+// acc[h][v] = (A X)[r, lane_col(g, h) + v] for the lane's column group g
+// (meaningful where the group lies within N). The WU column indices and
+// values of a pass are loaded unconditionally (entries past the row end
+// repeat its last entry with weight zero), then the WU gathers: no branch
+// inside the pass, so all of them are in flight together. With O32 (the
+// caller guarantees n N sizeof(T) < 2^32) the gathers address X by a 32-bit
+// byte offset from its base: one register per address instead of two.
+template <int L, int V, int NCH, int WU, bool O32, typename T>
 __device__ __forceinline__ void row_gather_lanes(int64_t r, int g, int N, int jb, int j1,
                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
                                                  const T* __restrict__ X, T (&acc)[NCH][V]) {
   T a0[NCH][V], a1[NCH][V];
+  int coff[NCH];
 #pragma unroll
-  for (int h = 0; h < NCH; ++h)
+  for (int h = 0; h < NCH; ++h) {
+    coff[h] = lane_col<L, V>(g, h, N);
 #pragma unroll
     for (int v = 0; v < V; ++v) a0[h][v] = a1[h][v] = T(0);
+  }
+  const uint32_t rowb = (uint32_t)N * (uint32_t)sizeof(T);
   for (int j = jb; j < j1; j += WU) {
     int k[WU];
     T w[WU];
 #pragma unroll
     for (int u = 0; u < WU; ++u) {
-      const bool ok = j + u < j1;
-      k[u] = ok ? col[j + u] : (int)r;
-      w[u] = ok ? val[j + u] : T(0);
+      const uint32_t e = (uint32_t)(j + u < j1 ? j + u : j1 - 1);
+      k[u] = col[e];
+      const T a = val[e];
+      w[u] = j + u < j1 ? a : T(0);
     }
     T x[WU][NCH][V];
 #pragma unroll
     for (int u = 0; u < WU; ++u)
 #pragma unroll
       for (int h = 0; h < NCH; ++h) {
-        const int c = (g + L * h) * V;
-        if (c < N) {
-          load_cols<T, V>(X + (int64_t)k[u] * N + c, x[u][h]);
+        if constexpr (O32) {
+          const uint32_t off = (uint32_t)k[u] * rowb + (uint32_t)coff[h] * (uint32_t)sizeof(T);
+          load_cols<T, V>(reinterpret_cast<const T*>(reinterpret_cast<const char*>(X) + off), x[u][h]);
         } else {
-#pragma unroll
-          for (int v = 0; v < V; ++v) x[u][h][v] = T(0);
+          load_cols<T, V>(X + (int64_t)k[u] * N + coff[h], x[u][h]);
         }
       }
 #pragma unroll

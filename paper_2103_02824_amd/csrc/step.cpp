@@ -94,7 +94,7 @@ void enqueue_precond(mlc_ctx* c, hipStream_t s, int64_t n, int N, const CgArgs<T
   if constexpr (std::is_same<T, double>::value) {
     if (a.cc) {
       const CoarsePC& cc = *a.cc;
-      launch_restrict(s, cc.nH, 1, cc.PTptr, cc.PTidx, cc.PTw, a.R, cc.rH);
+      launch_restrict_chunks(s, n, cc.nH, 1, d, a.R, cc.rH, d.rpartH);
       launch_dense_mv(s, cc.nH, cc.KHinv, cc.rH, cc.eH);
       double* zout = start ? a.P : (a.pc ? const_cast<double*>(*Zl) : cc.Z);
       launch_zcoarse(s, n, a.dinv, a.R, a.pc ? *Zl : nullptr, cc.Pk, cc.Pw, cc.eH, zout, cc.rz_part);
@@ -307,7 +307,7 @@ mlc_status solve_ir(mlc_ctx* c, int64_t n, int N, bool timed, double* spmm_ms, i
     launch_to_f32(s, n * N, d.R, d.B32);
     HIPCHK(hipMemsetAsync(d.X32, 0, sizeof(float) * n * N, s));
     float* Yf = reinterpret_cast<float*>(d.Y);
-    PolyPC<float> pcF{d.lmax, c->opt.cheb_ratio, c->opt.cheb_degree, {Yf, Yf + n * N}, Yf + 2 * n * N,
+    PolyPC<float> pcF{d.lmax, c->opt.cheb_ratio, c->opt.cheb_degree, {Yf, Yf + n * N},
                       d.red + (int64_t)cg_max_blocks() * N};
     CgArgs<float> fa{d.valA32, d.dinvA32, d.B32, d.X32, d.R32, d.P32, d.Q32, d.scal32, d.flags32, d.scal,
                      c->opt.precond == MLC_PC_CHEBYSHEV ? &pcF : nullptr};
@@ -484,6 +484,8 @@ mlc_status phase_gram_fixed(StepRun& S, hipStream_t s, double* red) {
     launch_reduce_cols(s, N * N, gram_blocks(n), red, d.small + L.utF + (int64_t)o * N * N);
   }
   launch_coarse_orb(s, cnt, c->nt, d.cgrp_ptr, d.cgrp_dof, d.chat, d.X, N, d.cel_orb);
+  if (d.cel_pairs) launch_coarse_pairs(s, cnt, c->nt, d.cgrp_ptr, d.cgrp_dof, d.chat, d.X, N, d.pair_jl, N * (N + 1) / 2,
+                                       d.cel_pairs);
   HIPCHK(hipGetLastError());
   return MLC_OK;
 }
@@ -549,6 +551,11 @@ mlc_status phase_gram_copy(StepRun& S) {
   HIPCHK(hipMemcpyAsync(c->last_small.data(), d.small, sizeof(double) * L.total, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(c->last_cel_ops.data(), d.cel_ops, sizeof(double) * 40 * cnt, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(c->last_cel_orb.data(), d.cel_orb, sizeof(double) * 14 * cnt * N, hipMemcpyDeviceToHost, s));
+  if (d.cel_pairs) {
+    c->last_cel_pairs.resize(4 * cnt * (N * (N + 1) / 2));
+    HIPCHK(hipMemcpyAsync(c->last_cel_pairs.data(), d.cel_pairs, sizeof(double) * c->last_cel_pairs.size(),
+                          hipMemcpyDeviceToHost, s));
+  }
   if (S.guess) HIPCHK(hipMemcpyAsync(S.gsel, d.gsel, sizeof(double) * 4 * N, hipMemcpyDeviceToHost, s));
   return MLC_OK;
 }
@@ -575,7 +582,12 @@ mlc_status phase_inner(StepRun& S) {
   fb.liftT = h[L.sc + 1];
   fb.cel_ops = c->last_cel_ops;
   fb.cel_orb = c->last_cel_orb;
-  S.ist = inner_loop(c, fb, S.io);
+  if (c->opt.variant == MLC_VARIANT_JOINT) {
+    fb.cel_pairs = c->last_cel_pairs;
+    S.ist = inner_loop_joint(c, fb, S.io);
+  } else {
+    S.ist = inner_loop(c, fb, S.io);
+  }
   if (S.ist < 0) return S.ist;
   // everything the reconstruction writes into the state is checked here, on
   // the host, before any device write: on failure the state stays as it was
@@ -584,6 +596,7 @@ mlc_status phase_inner(StepRun& S) {
   for (double v : S.io.theta2) finite = finite && std::isfinite(v);
   for (double v : S.io.phiH) finite = finite && std::isfinite(v);
   for (double v : S.io.wH) finite = finite && std::isfinite(v);
+  for (double v : S.io.D) finite = finite && std::isfinite(v);
   if (!finite) return fail(c, MLC_ERR_NONFINITE, "non-finite result of the augmented problems");
   S.r.inner_iters = S.io.iters;
   S.r.inner_last_diff = S.io.last_diff;
@@ -602,13 +615,18 @@ mlc_status phase_recon(StepRun& S) {
   const int64_t n = c->n, nt = c->nt, nH = c->nH, nv = c->nv;
   const int N = c->N;
   SmallLayout L(nH, N);
-  S.cin.assign(nH * N + nH + N, 0.0);
+  const bool joint = c->opt.variant == MLC_VARIANT_JOINT;
+  S.cin.assign(nH * N + nH + N + (joint ? N * N : 0), 0.0);
   std::copy(S.io.phiH.begin(), S.io.phiH.end(), S.cin.begin());
   std::copy(S.io.wH.begin(), S.io.wH.end(), S.cin.begin() + nH * N);
   std::copy(S.io.theta2.begin(), S.io.theta2.end(), S.cin.begin() + nH * N + nH);
+  if (joint) std::copy(S.io.D.begin(), S.io.D.end(), S.cin.begin() + nH * N + nH + N);
   HIPCHK(hipMemcpyAsync(d.coarse_in, S.cin.data(), sizeof(double) * S.cin.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipEventRecord(S.ev[2], s));
-  launch_reconstruct(s, n, N, d.Pk, d.Pw, d.coarse_in, d.coarse_in + nH * N + nH, d.X, d.Phi);
+  if (joint)
+    launch_reconstruct_joint(s, n, N, d.Pk, d.Pw, d.coarse_in, d.coarse_in + nH * N + nH + N, d.X, d.Phi);
+  else
+    launch_reconstruct(s, n, N, d.Pk, d.Pw, d.coarse_in, d.coarse_in + nH * N + nH, d.X, d.Phi);
   launch_hartree_nodal(s, nv, d.v2d, d.Pk, d.Pw, d.coarse_in + nH * N, S.io.theta1, d.w0, d.g, d.w);
   launch_rho_nodal(s, nv, d.v2d, d.Phi, N, d.occ, d.rho_nodal);
   launch_energy(s, nt, d.tets, d.v2d, d.Phi, N, d.occ, d.w, d.vxc, d.geo, c->xc, c->xalpha, d.red);
@@ -701,7 +719,7 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   int outer_iters = 0;
   const bool cheb = c->opt.precond == MLC_PC_CHEBYSHEV;
   double* rz_part = d.red + (int64_t)cg_max_blocks() * N;
-  PolyPC<double> pcA{d.lmax, c->opt.cheb_ratio, c->opt.cheb_degree, {d.Y, d.Y + n * N}, d.Y + 2 * n * N, rz_part};
+  PolyPC<double> pcA{d.lmax, c->opt.cheb_ratio, c->opt.cheb_degree, {d.Y, d.Y + n * N}, rz_part};
   HIPCHK(hipEventRecord(S.ev[4], s));
   if (c->opt.precision == MLC_PREC_FP32_IR) {
     PHASE(solve_ir(c, n, N, timed, &S.r.t_spmm_ms, &S.r.n_spmm, &S.cr, &outer_iters));
@@ -728,8 +746,8 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   if (c->hartree) {
     double dummy = 0.0;
     int64_t dn = 0;
-    PolyPC<double> pcK{d.lmax + 1, c->opt.cheb_ratio, c->opt.cheb_degree, {d.Yh, d.Yh + n}, d.Yh + 2 * n,
-                       d.red + cg_max_blocks()};
+    PolyPC<double> pcK{d.lmax + 1, c->opt.cheb_ratio, c->opt.cheb_degree, {d.Yh, d.Yh + n},
+                       d.red + cg_max_blocks(), d.valK32};
     CoarsePC ccK{d.KHinv, c->nH, d.PTptr, d.PTidx, d.PTw, d.Pk, d.Pw, d.rH, d.eH, d.Yh + 3 * n,
                  d.red + cg_max_blocks()};
     CgArgs<double> pa{d.valK, d.dinvK, d.pb, d.w0, d.pr, d.pp, d.pq, d.scalP, d.flagsP, nullptr,

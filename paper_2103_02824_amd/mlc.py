@@ -64,10 +64,11 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("ir_inner_rtol", C.c_double), ("ir_max_outer", C.c_int32),
                 ("precond", C.c_int32), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("hartree_coarse", C.c_int32), ("hartree_precond", C.c_int32),
-                ("inner_mix_history", C.c_int32), ("inner_mix_beta", C.c_double)]
+                ("inner_mix_history", C.c_int32), ("inner_mix_beta", C.c_double), ("variant", C.c_int32)]
 
 PREC_FP64, PREC_FP32_IR = 0, 1
 PC_JACOBI, PC_CHEBYSHEV = 0, 1
+VARIANT_EIGENPAIRWISE, VARIANT_JOINT = 0, 1
 KERNELS = {"cg_spmm": 0, "cheb_step": 1, "hartree_spmm": 2, "hartree_cheb_step": 3}
 
 

@@ -243,3 +243,11 @@ def test_hartree_preconditioner_option_checked():
         assert _create(mlc, L, S, opts=mlc.options(**kw))[0] == 0, kw
     for kw in bad:
         assert _create(mlc, L, S, opts=mlc.options(**kw))[0] == -1, kw
+
+
+def test_variant_option_checked():
+    mlc, L = _lib()
+    S = c1_hydrogen()
+    assert _create(mlc, L, S, opts=mlc.options(variant=mlc.VARIANT_JOINT))[0] == 0
+    assert _create(mlc, L, S, opts=mlc.options(variant=2))[0] == -1
+    assert mlc.options().variant == mlc.VARIANT_EIGENPAIRWISE

@@ -453,3 +453,37 @@ def test_cluster_whole_steps_converged_inner_loop(gpu):
         ovl.append(rep["max_offdiag_overlap"])
     assert ovl[-1] < ovl[0] and ovl[-1] < 1e-2, ovl
     ctx.close()
+
+
+@pytest.mark.parametrize("case", ["tiny2", "lih_small", "c2small1"])
+def test_joint_variant_matches_the_checker(gpu, case):
+    """The joint-space variant (one augmented space V_H + span{u_1..u_N}, its
+    lowest N eigenpairs; the pair integrals (u_j u_l, psi_k) from the fine
+    stage, the dense joint problem on the host) against the checker's
+    direct fine-mesh evaluation: two whole steps with the inner iteration
+    converged; eigenvalues to 1e-8, the density to 1e-6 relative L2, the
+    orbitals M-orthonormal to 1e-10 (the subspace, not each orbital: compared
+    through the density and the projector P Phi Phi^T M)."""
+    from inputs.systems import c2_small, lih_small, tiny_system
+    from paper_2103_02824_amd import mlc
+    S = {"tiny2": lambda: tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=True, n_orbitals=2, seed=7),
+         "lih_small": lih_small, "c2small1": lambda: c2_small(1)}[case]()
+    prob = Problem(S)
+    print(f"case {case} joint variant, n_dof={prob.fine.n_dof} nH={prob.NH} N={prob.N}", flush=True)
+    st, _ = initial_state(prob, maxit=300)
+    ctx = mlc.Context(S, mlc.options(**dict(LIB_OPTS, variant=mlc.VARIANT_JOINT)))
+    ctx.set_state(st.lam, st.Phi, st.w)
+    opts = Options(shift=True, sigma0=1.0, inner_tol=1e-11, inner_maxit=500, n_extra=8, variant="joint")
+    for k in range(2):
+        rep = ctx.correction_step(allow_warn=False)
+        ref = correction_step(prob, st, opts)
+        st = ref.state
+        lam, Phi, w, rho = ctx.get_results()
+        print(f"step {k}: lambda {lam} checker {ref.state.lam}, inner {rep['inner_iters']}/{ref.inner_iters}, "
+              f"overlap {rep['max_offdiag_overlap']:.1e}", flush=True)
+        assert np.max(np.abs(lam - ref.state.lam)) < 1e-8, (lam, ref.state.lam)
+        assert relerr(rho, ref.rho_nodal) < 1e-6
+        assert rep["max_offdiag_overlap"] < 1e-10
+        proj = Phi @ (Phi.T @ (prob.M @ Phi))
+        assert np.linalg.norm(proj - ref.state.Phi @ (ref.state.Phi.T @ (prob.M @ Phi))) < 1e-7 * np.linalg.norm(proj)
+    ctx.close()

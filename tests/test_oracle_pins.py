@@ -496,3 +496,37 @@ def test_mixed_inner_iteration_has_the_printed_fixed_point():
         assert np.sqrt((a - b_) @ (M @ (a - b_))) < 1e-9
     assert np.max(np.abs(plain["lam"] - mixed["lam"])) < 1e-10
     assert abs(plain["th1"] - mixed["th1"]) < 1e-9
+
+
+# ---------------------------------------------------------------- the joint-space variant
+def test_joint_variant_linear_case_converges_to_dense_eigensolve():
+    """The comparison method (one augmented space V_H + span{u_1..u_N} for all
+    orbitals): with no Hartree and no XC its steps reach the lowest N
+    eigenpairs of the fine pencil (dense eigh), and its orbitals are
+    M-orthonormal at every step."""
+    S = tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=False, n_orbitals=3, seed=3)
+    prob = Problem(S)
+    A = (0.5 * prob.K + prob.mass_ii(prob.vext_qp)).toarray()
+    ev, _ = sla.eigh(A, prob.M.toarray())
+    st, _ = initial_state(prob)
+    for _ in range(120):
+        res = correction_step(prob, st, Options(variant="joint"))
+        st = res.state
+        G = st.Phi.T @ (prob.M @ st.Phi)
+        assert np.max(np.abs(G - np.eye(3))) < 1e-12
+    assert np.max(np.abs(st.lam - ev[:3])) < 1e-10, (st.lam, ev[:3])
+
+
+def test_joint_variant_exact_eigenpairs_are_a_fixed_point():
+    """Starting from exact fine eigenpairs, the joint space contains them, and
+    its lowest N Ritz pairs are those eigenpairs."""
+    S = tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=False, n_orbitals=2, seed=3)
+    prob = Problem(S)
+    A = (0.5 * prob.K + prob.mass_ii(prob.vext_qp)).toarray()
+    ev, V = sla.eigh(A, prob.M.toarray())
+    st = State(lam=ev[:2].copy(), Phi=V[:, :2].copy(), w=np.zeros(prob.fine.nv))
+    res = correction_step(prob, st, Options(variant="joint"))
+    assert np.max(np.abs(res.state.lam - ev[:2])) < 1e-12
+    for i in range(2):
+        s = np.sign(res.state.Phi[:, i] @ prob.M @ V[:, i])
+        assert np.linalg.norm(s * res.state.Phi[:, i] - V[:, i]) < 1e-9
