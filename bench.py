@@ -101,9 +101,9 @@ def _kernel_name(which, N, word, n):
             L *= 2
         nch = -(-groups // L)
         o32 = "true" if n * N * word < 2 ** 32 else "false"
-        if "spmm" in which:
-            return f"k_spmm_rows<{L}, {V}, {nch}, {o32}, {t}>"
-        return f"k_cheb_rows<{L}, {V}, {nch}, false, {o32}, {t}>"  # the steps without the r.z partials
+        if "spmm" in which:  # the CG SpMM with its p.q partials: 512-thread blocks
+            return f"k_spmm_rows<{L}, {V}, {nch}, {o32}, 512, {t}>"
+        return f"k_cheb_rows<{L}, {V}, {nch}, false, {o32}, 256, {t}>"  # the steps without the r.z partials
     if "spmm" in which:
         unroll = 4 if N <= 3 else (2 if N <= 6 else 1)
         return f"k_spmm_small<{N}, 4, {unroll}, 1024, {8 if N <= 6 else 4}, {t}>"
@@ -265,9 +265,9 @@ def main():
                     help="largest accepted off-diagonal orbital overlap after a step (default 1e-2 for c1/c2; "
                          "1.0 for c3, whose 12^3 coarse space does not resolve 52 cluster orbitals)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=4,
+    ap.add_argument("--cpu-iters", type=int, default=20,
                     help="c3 cpu baseline: Jacobi-PCG iterations of the checker timed on --cpu-cols columns")
-    ap.add_argument("--cpu-cols", type=int, default=4)
+    ap.add_argument("--cpu-cols", type=int, default=8)
     ap.add_argument("--batch-systems", type=int, default=12,
                     help="--workload batch: number of uneven clusters stepped together")
     ap.add_argument("--batch-inner-maxit", type=int, default=4,

@@ -322,8 +322,10 @@ mlc_status mlc_time_kernel(mlc_ctx* ctx, int32_t which, int32_t reps, double* av
  * then starts from x0_i = a phi_i + b delta_i, the minimiser of the energy
  * J(x) = 1/2 x.Ax - b.x over span{phi_i, delta_i} (a 2 x 2 solve per
  * column), which is never farther from the solution in the A-norm than
- * phi_i; phi_i stays the fallback where the 2 x 2 system is singular or J
- * does not drop. Products run in BF16 on the matrix cores with FP32 accumulation;
+ * phi_i; phi_i stays the start where the 2 x 2 system is singular, where J
+ * does not drop, or where the minimiser's residual |b - A x0| exceeds phi_i's
+ * (CG's stopping test is on the residual, which a start closer in the A-norm
+ * can still raise). Products run in BF16 on the matrix cores with FP32 accumulation;
  * master weights, Adam moments and the loss are FP32/FP64.
  * Parameter packing (floats): W1 (64 x 6, out x in), b1 (64), W2 (64 x 64),
  * b2, W3 (64 x 64), b3, W4 (64), b4 (1).

@@ -202,7 +202,10 @@ def targets(U, Phi, s):
 def galerkin_start(A, B, Phi, D):
     """Per column the minimiser of J over span{phi, delta}; returns x0, the
     per-column flags (True where the combination is used) and the
-    coefficients (a, b)."""
+    coefficients (a, b). phi is kept where the 2 x 2 system is singular, where
+    J does not drop, or where the minimiser's residual |b - A x0| exceeds
+    phi's (a start closer in the A-norm can still carry a larger residual,
+    and CG's stopping test is on the residual)."""
     Phi, D, B = np.asarray(Phi), np.asarray(D), np.asarray(B)
     AP, AD = A @ Phi, A @ D
     X = Phi.copy()
@@ -218,7 +221,9 @@ def galerkin_start(A, B, Phi, D):
         b = (G[0, 0] * r[1] - G[1, 0] * r[0]) / det
         j_phi = 0.5 * G[0, 0] - r[0]
         j_new = 0.5 * (a * a * G[0, 0] + 2 * a * b * G[0, 1] + b * b * G[1, 1]) - (a * r[0] + b * r[1])
-        if j_new < j_phi:
+        res_new = np.linalg.norm(B[:, c] - (a * AP[:, c] + b * AD[:, c]))
+        res_phi = np.linalg.norm(B[:, c] - AP[:, c])
+        if j_new < j_phi and res_new <= res_phi:
             X[:, c] = a * Phi[:, c] + b * D[:, c]
             used[c] = True
             coef[c] = (a, b)

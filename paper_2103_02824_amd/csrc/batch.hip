@@ -665,9 +665,12 @@ __global__ void __launch_bounds__(BS) kb_direction(const BProb<T>* __restrict__ 
   if constexpr (std::is_same<T, double>::value) {
     if (cs && degree < 2) Zl = cs[p].Zc;  // coarse correction on top of Jacobi
   }
-  for (int64_t i = r0 * N + threadIdx.x; i < r1 * N; i += BS) {
-    int64_t r = i / N;
-    int c = (int)(i - r * N);
+  // tile-local 32-bit indices (no 64-bit division per entry)
+  const int m = (int)((r1 - r0) * N);
+  for (int li = threadIdx.x; li < m; li += BS) {
+    const int lr = li / N;
+    const int c = li - lr * N;
+    const int64_t r = r0 + lr, i = r0 * N + li;
     D.P[i] = (Zl ? Zl[i] : D.dinv[r] * D.R[i]) + beta[c] * D.P[i];
   }
 }

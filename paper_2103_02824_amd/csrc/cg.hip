@@ -36,6 +36,7 @@ constexpr int SPMM_BS = 1024;      // CG SpMM block size (16 waves per block)
 // slower, because the blocks past the first round run on a half-empty chip.
 constexpr int SPMM_MAXBLK = 512;
 constexpr int VEC_MAXBLK = 512;    // update / direction grid cap
+constexpr int UPD_UR = 4;          // row passes per loop trip of the V-column update / direction
 constexpr int NXCD = 8;            // XCDs of the chip, each with its own L2
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -97,20 +98,31 @@ struct RowBlocks {
 // repeat the row's last entry with weight zero, so that every chunk issues all
 // its loads at once, with no branch. Blocks of n N sizeof(T) < 2^32 bytes are
 // gathered through 32-bit offsets (O32).
-constexpr int WIDE_BS = 512;
-// Grid cap of the N > 8 kernels: two 512-thread blocks per compute unit
-// (their register use allows two, not more) on 256 compute units, so that
-// every block is resident and the blocks of an XCD sweep its row range
-// together (a larger grid would run in two waves of blocks, each over every
-// other stretch of rows, with fewer neighbouring rows in L2). At most
-// cg_max_blocks(), the partial producers' bound.
-constexpr int WIDE_MAXBLK = 512;
-constexpr int WU = 16;
+// Launch shapes, from a standalone harness on the 40-atom matrix (2.0M rows,
+// bimodal row lengths 7..27) at N = 52: the gathers are bound by the vector
+// memory instructions they issue (each covers 64 / L rows; a pass of WU
+// entries costs WU of them whatever the rows' lengths), so the kernels take
+// WU = 8 entries per pass in FP32 (-8% against 16) and 4 in FP64 (-15%), and
+// the launches without partial sums run 256-thread blocks on up to 256
+// blocks per XCD. The producers of per-block partial sums (CG SpMM, last
+// polynomial step) keep 512-thread blocks on a grid of at most 512, because
+// every consumer block re-reads all partials.
+constexpr int WIDE_BS = 512;       // partial producers
+constexpr int WIDE_MAXBLK = 512;   // at most cg_max_blocks()
+constexpr int WIDE_BS_PLAIN = 256;
+constexpr int WIDE_MAXBLK_PLAIN = 2048;
+template <typename T>
+constexpr int wide_wu() { return sizeof(T) == 4 ? 8 : 4; }
 
-// Grid of the N > 8 kernels: one block per 64 rows up to the cap, whatever the
-// layout (the FP32 and FP64 kernels and the consumers of their partials agree
-// on it); blocks past the last row block write zero partials.
+// Grid of the N > 8 partial producers: one block per 64 rows up to the cap,
+// whatever the layout (the FP32 and FP64 kernels and the consumers of their
+// partials agree on it); blocks past the last row block write zero partials.
 inline int wide_blocks_for(int64_t n) { return cap_xcd((n + 63) / 64, WIDE_MAXBLK); }
+// Grid of the other N > 8 launches: one block per row block of BS / L rows up to the cap.
+inline int wide_plain_blocks(int64_t n, int L) {
+  const int64_t rb = WIDE_BS_PLAIN / L;
+  return cap_xcd((n + rb - 1) / rb, WIDE_MAXBLK_PLAIN);
+}
 
 // Column sums of dot over the block's BS / L row slots into partial[blk, :].
 template <int L, int V, int NCH, int BS>
@@ -134,12 +146,12 @@ __device__ __forceinline__ void block_cols_lanes(const double (&dot)[NCH][V], in
 }
 
 // Y = A X; with partial: per-block column sums of X . Y.
-template <int L, int V, int NCH, bool O32, typename T>
-__global__ void __launch_bounds__(WIDE_BS) k_spmm_rows(int64_t n, int N, const int32_t* __restrict__ rowptr,
+template <int L, int V, int NCH, bool O32, int BS, typename T>
+__global__ void __launch_bounds__(BS) k_spmm_rows(int64_t n, int N, const int32_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ col, const T* __restrict__ val,
                                                        const T* __restrict__ X, T* __restrict__ Y,
                                                        double* __restrict__ partial, const int32_t* __restrict__ flags) {
-  constexpr int RB = WIDE_BS / L;
+  constexpr int RB = BS / L;
   if (flags && flags[0] == 0) return;
   const int g = threadIdx.x % L, rl = threadIdx.x / L;
   double dot[NCH][V];
@@ -164,7 +176,7 @@ __global__ void __launch_bounds__(WIDE_BS) k_spmm_rows(int64_t n, int N, const i
     jb = rowptr[rn];
     je = rowptr[rn + 1];
     T acc[NCH][V];
-    row_gather_lanes<L, V, NCH, WU, O32, T>(r, g, N, jr, jr1, col, val, X, acc);
+    row_gather_lanes<L, V, NCH, wide_wu<T>(), O32, T>(r, g, N, jr, jr1, col, val, X, acc);
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
       const int c = (g + L * h) * V;
@@ -180,7 +192,7 @@ __global__ void __launch_bounds__(WIDE_BS) k_spmm_rows(int64_t n, int N, const i
       }
     }
   }
-  if (partial) block_cols_lanes<L, V, NCH, WIDE_BS>(dot, N, partial);
+  if (partial) block_cols_lanes<L, V, NCH, BS>(dot, N, partial);
 }
 
 // ---------------------------------------------------------------------------
@@ -370,21 +382,107 @@ __global__ void __launch_bounds__(BS, W) k_cheb_small(int64_t n, const int32_t* 
   }
 }
 
+// The fused Chebyshev step for one column (the Hartree problem and other
+// N = 1 systems), the same arithmetic as k_cheb_small<1>: each group of G
+// lanes takes R2 consecutive rows whose entries are interleaved in one pass
+// loop (U entries per lane and row per pass, all loads of a pass issued
+// together), so a wavefront has R2 times as many loads in flight as with
+// one row per group. A one-column step is latency-bound: each row is a chain
+// of row pointers, column indices and gathers.
+template <int G, int U, int BS, int W, int R2, typename T, typename MT>
+__global__ void __launch_bounds__(BS, W) k_cheb_one(int64_t n, const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col, const MT* __restrict__ val,
+                                                    const T* __restrict__ dinv, const T* __restrict__ R,
+                                                    const T* __restrict__ Zin, const T* Zprev, T* Zout,
+                                                    const double* __restrict__ lmax, double ratio, int j,
+                                                    double* __restrict__ partial, const int32_t* __restrict__ flags) {
+  constexpr int RB = BS / G * R2;  // rows per block pass
+  if (flags && flags[0] == 0) return;
+  __shared__ double sd[BS / 64];
+  double cdd, crr;
+  cheb_coef(*lmax, ratio, j, &cdd, &crr);
+  const T cd = (T)cdd, cr = (T)crr;
+  const int sub = threadIdx.x % G, rl = threadIdx.x / G;
+  double dot = 0.0;
+  const RowBlocks rbk((n + RB - 1) / RB);
+  for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
+    // rows past n are computed as row n - 1 and not stored
+    int64_t r[R2];
+    bool live[R2];
+    int jb[R2], je[R2];
+    T rv[R2], zv[R2], pv[R2], di[R2], acc[R2];
+    int len = 0;
+#pragma unroll
+    for (int k = 0; k < R2; ++k) {
+      const int64_t r0 = rb * RB + (int64_t)rl * R2 + k;
+      live[k] = r0 < n;
+      r[k] = live[k] ? r0 : n - 1;
+      jb[k] = rowptr[r[k]];
+      je[k] = rowptr[r[k] + 1];
+      rv[k] = R[r[k]];
+      zv[k] = Zin[r[k]];
+      pv[k] = Zprev[r[k]];  // for j = 1 the caller passes Zprev = Zin (not used)
+      di[k] = dinv[r[k]];
+      acc[k] = T(0);
+      len = max(len, je[k] - jb[k]);
+    }
+    for (int o = sub; o < len; o += G * U) {
+      int cc[R2][U];
+      T vv[R2][U];
+#pragma unroll
+      for (int k = 0; k < R2; ++k)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = jb[k] + o + u * G;
+          const uint32_t ec = (uint32_t)(e < je[k] ? e : je[k] - 1);
+          cc[k][u] = col[ec];
+          const T a = (T)val[ec];
+          vv[k][u] = e < je[k] ? a : T(0);
+        }
+#pragma unroll
+      for (int k = 0; k < R2; ++k)
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[k] += vv[k][u] * Zin[cc[k][u]];
+    }
+#pragma unroll
+    for (int k = 0; k < R2; ++k) {
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, G);
+      if (live[k] && sub == 0) {
+        const T dv = j > 1 ? zv[k] - pv[k] : zv[k];
+        const T z = zv[k] + (cd * dv + cr * (di[k] * (rv[k] - acc[k])));
+        Zout[r[k]] = z;
+        if (partial) dot += (double)rv[k] * (double)z;
+      }
+    }
+  }
+  if (!partial) return;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const double v = wave_sum(dot);
+  if (lane == 0) sd[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < BS / 64; ++w) s += sd[w];
+    partial[blockIdx.x] = s;
+  }
+}
+
 // The fused Chebyshev step for N > 8 in the same layout: w = A Zin;
 // Zout = Zin + cd (Zin - Zprev) + cr D^-1 (R - w) (Zprev = 0 for j = 1; Zout
 // may be Zprev); with PART, per-block column sums of R . Zout into partial (a
 // separate instantiation, so that the steps without them do not hold the
 // sums in registers). The row's own R, Zprev, Zin entries are loaded before
 // the gather.
-template <int L, int V, int NCH, bool PART, bool O32, typename T>
-__global__ void __launch_bounds__(WIDE_BS) k_cheb_rows(int64_t n, int N, const int32_t* __restrict__ rowptr,
+template <int L, int V, int NCH, bool PART, bool O32, int BS, typename T>
+__global__ void __launch_bounds__(BS) k_cheb_rows(int64_t n, int N, const int32_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ col, const T* __restrict__ val,
                                                        const T* __restrict__ dinv, const T* __restrict__ R,
                                                        const T* __restrict__ Zin, const T* Zprev, T* Zout,
                                                        const double* __restrict__ lmax, double ratio, int j,
                                                        double* __restrict__ partial,
                                                        const int32_t* __restrict__ flags) {
-  constexpr int RB = WIDE_BS / L;
+  constexpr int RB = BS / L;
   if (flags && flags[0] == 0) return;
   double cdd, crr;
   cheb_coef(*lmax, ratio, j, &cdd, &crr);
@@ -424,7 +522,7 @@ __global__ void __launch_bounds__(WIDE_BS) k_cheb_rows(int64_t n, int N, const i
       load_cols<T, V>(Zprev + i, pv[h]);
     }
     T acc[NCH][V];
-    row_gather_lanes<L, V, NCH, WU, O32, T>(r, g, N, jr, jr1, col, val, Zin, acc);
+    row_gather_lanes<L, V, NCH, wide_wu<T>(), O32, T>(r, g, N, jr, jr1, col, val, Zin, acc);
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
       const int c = (g + L * h) * V;
@@ -438,7 +536,7 @@ __global__ void __launch_bounds__(WIDE_BS) k_cheb_rows(int64_t n, int N, const i
       if (live && c < N) store_cols<T, V>(Zout + r * N + c, z);
     }
   }
-  if constexpr (PART) block_cols_lanes<L, V, NCH, WIDE_BS>(dot, N, partial);
+  if constexpr (PART) block_cols_lanes<L, V, NCH, BS>(dot, N, partial);
 }
 
 // Gershgorin bound of D^-1 A: per-block maxima of dinv_i sum_j |a_ij|, then
@@ -666,10 +764,108 @@ __global__ void __launch_bounds__(TPB) k_cg_update(int64_t n, int N, const T* __
   }
 }
 
+// The update for N > 8 with N a multiple of V = 16 / sizeof(T): a thread owns V
+// consecutive columns of a row (one 16-byte access per block and row; N / V
+// threads per row, TPB / (N / V) rows per block pass); the block's column
+// sums go through LDS as R x N and are added row-halving.
+template <typename T, int V>
+__global__ void __launch_bounds__(TPB) k_cg_update_v(int64_t n, int N, const T* __restrict__ dinv,
+                                                     T* __restrict__ X, T* __restrict__ Rv,
+                                                     const T* __restrict__ P, const T* __restrict__ Q,
+                                                     const double* __restrict__ pq_part, int nblk_pq,
+                                                     const double* __restrict__ scal,
+                                                     const int32_t* __restrict__ flags, double* __restrict__ partial,
+                                                     int32_t* __restrict__ brk, T* __restrict__ Z0,
+                                                     const double* __restrict__ lmax, double ratio) {
+  if (flags[0] == 0) return;
+  __shared__ double sd[2][TPB * V];
+  __shared__ double alpha[MLC_MAX_ORBITALS];
+  const T ith = Z0 ? (T)(1.0 / cheb_theta(*lmax, ratio)) : T(0);
+  sum_partials(pq_part, nblk_pq, N, alpha);
+  if ((int)threadIdx.x < N) {
+    int c = threadIdx.x;
+    double pq = alpha[c];
+    bool act = scal[C_ACT * N + c] != 0.0;
+    if (act && !(pq > 0.0)) {
+      if (blockIdx.x == 0) brk[0] = 1;
+      act = false;
+    }
+    alpha[c] = act ? scal[C_RZ * N + c] / pq : 0.0;
+  }
+  __syncthreads();
+  const int Qn = N / V, R = TPB / Qn;
+  const int rl = threadIdx.x / Qn, c0 = (threadIdx.x - rl * Qn) * V;
+  const bool lane_on = rl < R;
+  T a[V];
+  double v0[V], v1[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    a[v] = lane_on ? (T)alpha[c0 + v] : T(0);
+    v0[v] = v1[v] = 0.0;
+  }
+  // UPD_UR row passes per loop trip, their loads issued together (the grid is
+  // small, since every consumer block re-reads all partials)
+  for (int64_t rq = (int64_t)blockIdx.x * R * UPD_UR; rq < n; rq += (int64_t)gridDim.x * R * UPD_UR) {
+    T x[UPD_UR][V], pp[UPD_UR][V], rr[UPD_UR][V], qq[UPD_UR][V];
+    T di[UPD_UR];
+#pragma unroll
+    for (int k = 0; k < UPD_UR; ++k) {
+      const int64_t r = rq + k * R + rl;
+      if (lane_on && r < n) {
+        const int64_t i = r * N + c0;
+        load_cols<T, V>(X + i, x[k]);
+        load_cols<T, V>(P + i, pp[k]);
+        load_cols<T, V>(Rv + i, rr[k]);
+        load_cols<T, V>(Q + i, qq[k]);
+        di[k] = dinv[r];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < UPD_UR; ++k) {
+      const int64_t r = rq + k * R + rl;
+      if (lane_on && r < n) {
+        const int64_t i = r * N + c0;
+        T z[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          x[k][v] += a[v] * pp[k][v];
+          rr[k][v] -= a[v] * qq[k][v];
+          z[v] = di[k] * rr[k][v] * ith;
+          v0[v] += (double)rr[k][v] * (double)di[k] * (double)rr[k][v];
+          v1[v] += (double)rr[k][v] * (double)rr[k][v];
+        }
+        store_cols<T, V>(X + i, x[k]);
+        store_cols<T, V>(Rv + i, rr[k]);
+        if (Z0) store_cols<T, V>(Z0 + i, z);
+      }
+    }
+  }
+  if (lane_on)
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      sd[0][rl * N + c0 + v] = v0[v];
+      sd[1][rl * N + c0 + v] = v1[v];
+    }
+  for (int m = R; m > 1;) {
+    const int h = (m + 1) >> 1;
+    __syncthreads();
+    for (int t = threadIdx.x; t < (m - h) * N; t += TPB) {
+      sd[0][t] += sd[0][t + h * N];
+      sd[1][t] += sd[1][t + h * N];
+    }
+    m = h;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < N; c += TPB) {
+    partial[((int64_t)blockIdx.x * 2 + 0) * N + c] = sd[0][c];
+    partial[((int64_t)blockIdx.x * 2 + 1) * N + c] = sd[1][c];
+  }
+}
+
 // beta_c = rz'_c / rz_c and the test ||r||^2 <= rtol^2 ||b||^2 from the update
 // partials; P = Dinv R + beta P. Block 0 writes the next scalars (the other
 // buffer) and the active count.
-template <typename T>
+template <typename T, int V>
 __global__ void __launch_bounds__(TPB) k_cg_direction(int64_t n, int N, const T* __restrict__ dinv,
                                                       const T* __restrict__ Rv, T* __restrict__ P,
                                                       const double* __restrict__ upd_part, int nblk_upd,
@@ -713,11 +909,41 @@ __global__ void __launch_bounds__(TPB) k_cg_direction(int64_t n, int N, const T*
     for (int c = 0; c < N; ++c) nact += still[c] != 0.0;
     flags_out[0] = nact;
   }
-  int64_t total = n * N;
-  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < total; i += (int64_t)gridDim.x * TPB) {
-    int64_t r = i / N;
-    int c = (int)(i - r * N);
-    P[i] = (Zl ? Zl[i] : dinv[r] * Rv[i]) + (T)beta[c] * P[i];
+  // the rows in the update's layout: V consecutive columns per thread (no
+  // 64-bit division per entry)
+  const int Qn = N / V, R = TPB / Qn;
+  const int rl = threadIdx.x / Qn, c0 = (threadIdx.x - rl * Qn) * V;
+  const bool lane_on = rl < R;
+  T b[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) b[v] = lane_on ? (T)beta[c0 + v] : T(0);
+  for (int64_t rq = (int64_t)blockIdx.x * R * UPD_UR; rq < n; rq += (int64_t)gridDim.x * R * UPD_UR) {
+    T z[UPD_UR][V], pp[UPD_UR][V];
+#pragma unroll
+    for (int k = 0; k < UPD_UR; ++k) {
+      const int64_t r = rq + k * R + rl;
+      if (lane_on && r < n) {
+        const int64_t i = r * N + c0;
+        if (Zl) {
+          load_cols<T, V>(Zl + i, z[k]);
+        } else {
+          load_cols<T, V>(Rv + i, z[k]);
+          const T di = dinv[r];
+#pragma unroll
+          for (int v = 0; v < V; ++v) z[k][v] *= di;
+        }
+        load_cols<T, V>(P + i, pp[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < UPD_UR; ++k) {
+      const int64_t r = rq + k * R + rl;
+      if (lane_on && r < n) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) pp[k][v] = z[k][v] + b[v] * pp[k][v];
+        store_cols<T, V>(P + r * N + c0, pp[k]);
+      }
+    }
   }
 }
 
@@ -755,6 +981,19 @@ void spmm_small(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* 
 
 int vec_blocks(int64_t n, int N) {
   int64_t R = TPB / N;
+  return cap((n + R - 1) / R, VEC_MAXBLK);
+}
+// columns per thread of the update and direction kernels, and their grid
+// (UPD_UR row passes per loop trip)
+template <typename T>
+inline int upd_v(int N) {
+  constexpr int V = 16 / (int)sizeof(T);
+  return (N > 8 && N % V == 0) ? V : 1;
+}
+template <typename T>
+inline int upd_blocks(int64_t n, int N) {
+  const int V = upd_v<T>(N);
+  const int64_t R = (int64_t)(TPB / (N / V)) * (V > 1 ? UPD_UR : 1);
   return cap((n + R - 1) / R, VEC_MAXBLK);
 }
 
@@ -826,8 +1065,13 @@ void spmm_any(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int3
     default:
       wide_launch<T>(s, n, N, [&](auto tag, dim3 g, dim3 b) {
         using K = decltype(tag);
-        hipLaunchKernelGGL((k_spmm_rows<K::L, K::V, K::NCH, K::O32, T>), g, b, 0, s, n, N, rowptr, col, val, X, Y, partial,
-                           flags);
+        if (partial)
+          hipLaunchKernelGGL((k_spmm_rows<K::L, K::V, K::NCH, K::O32, WIDE_BS, T>), g, b, 0, s, n, N, rowptr, col, val,
+                             X, Y, partial, flags);
+        else
+          hipLaunchKernelGGL((k_spmm_rows<K::L, K::V, K::NCH, K::O32, WIDE_BS_PLAIN, T>),
+                             dim3(wide_plain_blocks(n, K::L)), dim3(WIDE_BS_PLAIN), 0, s, n, N, rowptr, col, val, X, Y,
+                             partial, flags);
       });
   }
 #undef SPMM_CASE
@@ -886,9 +1130,15 @@ template <typename T>
 void launch_cg_update_t(hipStream_t s, int64_t n, int N, const T* dinv, T* X, T* Rv, const T* P, const T* Q,
                         const double* pq_part, const double* scal, const int32_t* flags, double* partial,
                         int32_t* brk, const PolyPC<T>* pc) {
-  hipLaunchKernelGGL((k_cg_update<T>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, X, Rv, P, Q, pq_part,
-                     spmm_blocks(n, N), scal, flags, partial, brk, pc ? pc->Z[0] : (T*)nullptr,
-                     pc ? pc->lmax : nullptr, pc ? pc->ratio : 1.0);
+  constexpr int VV = 16 / (int)sizeof(T);
+  if (upd_v<T>(N) == VV)
+    hipLaunchKernelGGL((k_cg_update_v<T, VV>), dim3(upd_blocks<T>(n, N)), dim3(TPB), 0, s, n, N, dinv, X, Rv, P, Q,
+                       pq_part, spmm_blocks(n, N), scal, flags, partial, brk, pc ? pc->Z[0] : (T*)nullptr,
+                       pc ? pc->lmax : nullptr, pc ? pc->ratio : 1.0);
+  else
+    hipLaunchKernelGGL((k_cg_update<T>), dim3(upd_blocks<T>(n, N)), dim3(TPB), 0, s, n, N, dinv, X, Rv, P, Q, pq_part,
+                       spmm_blocks(n, N), scal, flags, partial, brk, pc ? pc->Z[0] : (T*)nullptr,
+                       pc ? pc->lmax : nullptr, pc ? pc->ratio : 1.0);
 }
 void launch_cg_update_f(hipStream_t s, int64_t n, int N, const double* dinv, double* X, double* Rv, const double* P,
                         const double* Q, const double* pq_part, const double* scal, const int32_t* flags,
@@ -905,8 +1155,15 @@ template <typename T>
 void launch_cg_direction_z(hipStream_t s, int64_t n, int N, const T* dinv, const T* Rv, T* P, const double* upd_part,
                            const double* scal_in, const int32_t* flags_in, double* scal_out, int32_t* flags_out,
                            double rtol2, const double* rz_part, const T* Zl) {
-  hipLaunchKernelGGL((k_cg_direction<T>), dim3(vec_blocks(n, N)), dim3(TPB), 0, s, n, N, dinv, Rv, P, upd_part,
-                     vec_blocks(n, N), scal_in, flags_in, scal_out, flags_out, rtol2, rz_part, spmm_blocks(n, N), Zl);
+  constexpr int VV = 16 / (int)sizeof(T);
+  if (upd_v<T>(N) == VV)
+    hipLaunchKernelGGL((k_cg_direction<T, VV>), dim3(upd_blocks<T>(n, N)), dim3(TPB), 0, s, n, N, dinv, Rv, P,
+                       upd_part, upd_blocks<T>(n, N), scal_in, flags_in, scal_out, flags_out, rtol2, rz_part,
+                       spmm_blocks(n, N), Zl);
+  else
+    hipLaunchKernelGGL((k_cg_direction<T, 1>), dim3(upd_blocks<T>(n, N)), dim3(TPB), 0, s, n, N, dinv, Rv, P,
+                       upd_part, upd_blocks<T>(n, N), scal_in, flags_in, scal_out, flags_out, rtol2, rz_part,
+                       spmm_blocks(n, N), Zl);
 }
 template <typename T>
 void launch_cg_direction_t(hipStream_t s, int64_t n, int N, const T* dinv, const T* Rv, T* P, const double* upd_part,
@@ -942,22 +1199,33 @@ template <typename T>
 void launch_cheb_step_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val,
                         const T* dinv, const T* Rv, const PolyPC<T>& pc, int j, const T* zin, const T* zprev,
                         T* zout, double* part, const int32_t* flags) {
-  if constexpr (std::is_same<T, double>::value) {
-    if (pc.val32 && N == 1) {
-      // one FP64 column with FP32 matrix values (the Hartree problem's polynomial)
+  if (N == 1) {
+    // one column: two rows per lane group (k_cheb_one); the partial producer keeps the grid its consumers
+    // expect (spmm_blocks(n, 1))
+    auto one = [&](auto mt, const auto* v) {
+      using MT = decltype(mt);
       if (part) {
         const int64_t needed = (n + (SPMM_BS / ROW_G) - 1) / (SPMM_BS / ROW_G);
-        hipLaunchKernelGGL((k_cheb_small<1, ROW_G, unroll_cheb_part(1), SPMM_BS, waves_cheb_part(1), T, float>),
-                           dim3(cap_xcd(needed, SPMM_MAXBLK)), dim3(SPMM_BS), 0, s, n, rowptr, col, pc.val32, dinv,
-                           Rv, zin, zprev, zout, pc.lmax, pc.ratio, j, part, flags);
-      } else {
-        const int64_t needed = (n + (TPB / ROW_G) - 1) / (TPB / ROW_G);
-        hipLaunchKernelGGL((k_cheb_small<1, ROW_G, unroll_wide(1), TPB, waves_wide(1), T, float>),
-                           dim3(cap_xcd(needed, 1 << 30)), dim3(TPB), 0, s, n, rowptr, col, pc.val32, dinv, Rv, zin,
+        hipLaunchKernelGGL((k_cheb_one<ROW_G, unroll_cheb_part(1), SPMM_BS, 4, 2, T, MT>),
+                           dim3(cap_xcd(needed, SPMM_MAXBLK)), dim3(SPMM_BS), 0, s, n, rowptr, col, v, dinv, Rv, zin,
                            zprev, zout, pc.lmax, pc.ratio, j, part, flags);
+      } else {
+        constexpr int RB1 = TPB / ROW_G * 2;
+        const int64_t needed = (n + RB1 - 1) / RB1;
+        hipLaunchKernelGGL((k_cheb_one<ROW_G, unroll_wide(1), TPB, 4, 2, T, MT>),
+                           dim3(cap_xcd(needed, 1 << 30)), dim3(TPB), 0, s, n, rowptr, col, v, dinv, Rv, zin, zprev,
+                           zout, pc.lmax, pc.ratio, j, part, flags);
       }
-      return;
+    };
+    if constexpr (std::is_same<T, double>::value) {
+      if (pc.val32) {
+        // one FP64 column with FP32 matrix values (the Hartree problem's polynomial)
+        one(float(0), pc.val32);
+        return;
+      }
     }
+    one(T(0), val);
+    return;
   }
   if (N <= 8) {
 #define CHEB_CASE(K)                                                                                             \
@@ -989,10 +1257,11 @@ void launch_cheb_step_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr, 
     wide_launch<T>(s, n, N, [&](auto tag, dim3 g, dim3 b) {
       using K = decltype(tag);
       if (part)
-        hipLaunchKernelGGL((k_cheb_rows<K::L, K::V, K::NCH, true, K::O32, T>), g, b, 0, s, n, N, rowptr, col, val, dinv, Rv,
-                           zin, zprev, zout, pc.lmax, pc.ratio, j, part, flags);
+        hipLaunchKernelGGL((k_cheb_rows<K::L, K::V, K::NCH, true, K::O32, WIDE_BS, T>), g, b, 0, s, n, N, rowptr, col,
+                           val, dinv, Rv, zin, zprev, zout, pc.lmax, pc.ratio, j, part, flags);
       else
-        hipLaunchKernelGGL((k_cheb_rows<K::L, K::V, K::NCH, false, K::O32, T>), g, b, 0, s, n, N, rowptr, col, val, dinv, Rv,
+        hipLaunchKernelGGL((k_cheb_rows<K::L, K::V, K::NCH, false, K::O32, WIDE_BS_PLAIN, T>),
+                           dim3(wide_plain_blocks(n, K::L)), dim3(WIDE_BS_PLAIN), 0, s, n, N, rowptr, col, val, dinv, Rv,
                            zin, zprev, zout, pc.lmax, pc.ratio, j, part, flags);
     });
   }

@@ -830,10 +830,12 @@ __global__ void __launch_bounds__(TPB) k_coarse_ops(int64_t cnt, int64_t ng, con
 // order, DoFs from the per-mesh table grp_dof) in tiles of ORB_TILE whose hat
 // values, weights and DoFs are staged in LDS once for all orbitals. Lane l of
 // each wave owns orbital i0 + l (64 orbitals per pass); the block's 4 waves
-// take every 4th tet of the tile (the LDS reads are broadcasts, the U reads of
-// a wave one contiguous row segment). The 4 partial sums per orbital are added
-// in a fixed order.
+// take every 4th tet of the tile, ORB_BATCH tets at a time (the LDS reads are
+// broadcasts, the U reads of a wave one contiguous row segment each, all of a
+// batch in flight together). The 4 partial sums per orbital are added in a
+// fixed order.
 constexpr int ORB_TILE = 64;
+constexpr int ORB_BATCH = 4;
 __global__ void __launch_bounds__(256) k_coarse_orb(int64_t cnt, int64_t ng, const int32_t* __restrict__ grp_ptr,
                                                     const int32_t* __restrict__ grp_dof,
                                                     const double* __restrict__ chat, const double* __restrict__ U,
@@ -859,30 +861,40 @@ __global__ void __launch_bounds__(256) k_coarse_orb(int64_t cnt, int64_t ng, con
       }
       for (int k = threadIdx.x; k < 4 * ne; k += 256) sdof[k] = grp_dof[4 * (int64_t)t0 + k];
       __syncthreads();
-      for (int t = slot; t < ne; t += 4) {
-        const double* h = sh + t * 17;
-        const double w = 0.25 * h[16];
-        double u[4];
+      // ORB_BATCH tets per wave at a time: their U values are loaded together
+      // (tets past the tile repeat the last one with weight zero)
+      for (int t0 = slot; t0 < ne; t0 += 4 * ORB_BATCH) {
+        double u[ORB_BATCH][4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const int dof = sdof[4 * t + a];
-          const double v = U[(int64_t)(dof >= 0 ? dof : 0) * N + ic];
-          u[a] = dof >= 0 ? v : 0.0;
+        for (int b = 0; b < ORB_BATCH; ++b) {
+          const int t = t0 + 4 * b < ne ? t0 + 4 * b : ne - 1;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const int dof = sdof[4 * t + a];
+            const double v = U[(int64_t)(dof >= 0 ? dof : 0) * N + ic];
+            u[b][a] = dof >= 0 ? v : 0.0;
+          }
         }
-        const double us = u[0] + u[1] + u[2] + u[3];
+#pragma unroll 1
+        for (int b = 0; b < ORB_BATCH; ++b) {
+          const int t = t0 + 4 * b < ne ? t0 + 4 * b : ne - 1;
+          const double* h = sh + t * 17;
+          const double w = t0 + 4 * b < ne ? 0.25 * h[16] : 0.0;
+          const double us = u[b][0] + u[b][1] + u[b][2] + u[b][3];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double uq = QB * us + (QA - QB) * u[q];
-          const double wu = w * uq;
-          double ps[4];
+          for (int q = 0; q < 4; ++q) {
+            const double uq = QB * us + (QA - QB) * u[b][q];
+            const double wu = w * uq;
+            double ps[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) ps[j] = h[4 * q + j];
+            for (int j = 0; j < 4; ++j) ps[j] = h[4 * q + j];
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int m = j; m < 4; ++m) acc[j * 4 - (j * (j - 1)) / 2 + (m - j)] += wu * ps[j] * ps[m];
+              for (int m = j; m < 4; ++m) acc[j * 4 - (j * (j - 1)) / 2 + (m - j)] += wu * ps[j] * ps[m];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[10 + j] += wu * uq * ps[j];
+            for (int j = 0; j < 4; ++j) acc[10 + j] += wu * uq * ps[j];
+          }
         }
       }
     }
@@ -1270,36 +1282,52 @@ __device__ __forceinline__ bool galerkin_coef(const double* g, int N, int c, dou
   return true;
 }
 
-// X = a phi + b delta per column (X holds delta on entry); per-block column
-// sums of |b - A x0|^2 and |b - A phi|^2 (A x0 = a A phi + b A delta).
-__global__ void __launch_bounds__(TPB) k_guess_combine(int64_t n, int N, int R, const double* __restrict__ Phi,
-                                                       const double* __restrict__ AP, const double* __restrict__ AD,
-                                                       const double* __restrict__ B, const double* __restrict__ g,
-                                                       double* __restrict__ X, double* __restrict__ used,
-                                                       double* __restrict__ partial) {
+// Per-block column sums of |b - A x0|^2 (x0 the span minimiser, phi where it
+// is not defined) and |b - A phi|^2 (A x0 = a A phi + b A delta).
+__global__ void __launch_bounds__(TPB) k_guess_resid(int64_t n, int N, int R, const double* __restrict__ AP,
+                                                     const double* __restrict__ AD, const double* __restrict__ B,
+                                                     const double* __restrict__ g, double* __restrict__ partial) {
   __shared__ double sd[TPB];
   int t = threadIdx.x;
   int rl = t / N, c = t - rl * N;
   int64_t r = (int64_t)blockIdx.x * R + rl;
   double v[2] = {0.0, 0.0};
-  if (rl < R) {
+  if (rl < R && r < n) {
     double a, b;
-    bool u = galerkin_coef(g, N, c, &a, &b);
-    if (blockIdx.x == 0 && rl == 0) used[c] = u ? 1.0 : 0.0;
-    if (r < n) {
-      int64_t q = r * N + c;
-      X[q] = u ? a * Phi[q] + b * X[q] : Phi[q];
-      double el = B[q] - (a * AP[q] + b * AD[q]);
-      double ep = B[q] - AP[q];
-      v[0] = el * el;
-      v[1] = ep * ep;
-    }
+    galerkin_coef(g, N, c, &a, &b);
+    int64_t q = r * N + c;
+    double el = B[q] - (a * AP[q] + b * AD[q]);
+    double ep = B[q] - AP[q];
+    v[0] = el * el;
+    v[1] = ep * ep;
   }
   for (int k = 0; k < 2; ++k) {
     __syncthreads();
     sd[t] = v[k];
     block_reduce_cols(sd, R, N);
     if (t < N) partial[(int64_t)blockIdx.x * 2 * N + k * N + t] = sd[t];
+  }
+}
+
+// X = a phi + b delta per column where the span minimiser is defined, lowers J
+// and its residual does not exceed phi's; X = phi elsewhere (X holds delta on
+// entry). sel: [used (N), |b - A x0|^2 (N), |b - A phi|^2 (N), |b - A X|^2 of
+// the start taken (N)]; the middle two are read, block 0 writes the others.
+__global__ void __launch_bounds__(TPB) k_guess_apply(int64_t n, int N, int R, const double* __restrict__ Phi,
+                                                     const double* __restrict__ g, double* __restrict__ sel,
+                                                     double* __restrict__ X) {
+  int t = threadIdx.x;
+  int rl = t / N, c = t - rl * N;
+  if (rl >= R) return;
+  double a, b;
+  const bool ok = galerkin_coef(g, N, c, &a, &b) && sel[N + c] <= sel[2 * N + c];
+  if (blockIdx.x == 0 && rl == 0) {
+    sel[c] = ok ? 1.0 : 0.0;
+    sel[3 * N + c] = ok ? sel[N + c] : sel[2 * N + c];
+  }
+  for (int64_t r = (int64_t)blockIdx.x * R + rl; r < n; r += (int64_t)gridDim.x * R) {
+    int64_t q = r * N + c;
+    X[q] = ok ? a * Phi[q] + b * X[q] : Phi[q];
   }
 }
 
@@ -1508,8 +1536,9 @@ void launch_guess_galerkin(hipStream_t s, int64_t n, int N, const double* Phi, c
   int nbk = elem_blocks(n, N);
   hipLaunchKernelGGL(k_guess_dots, dim3(nbk), dim3(TPB), 0, s, n, N, R, Phi, X, AP, AD, B, partial);
   hipLaunchKernelGGL(k_reduce_cols, dim3(5 * N), dim3(TPB), 0, s, 5 * N, nbk, partial, gdots);
-  hipLaunchKernelGGL(k_guess_combine, dim3(nbk), dim3(TPB), 0, s, n, N, R, Phi, AP, AD, B, gdots, X, gsel, partial);
+  hipLaunchKernelGGL(k_guess_resid, dim3(nbk), dim3(TPB), 0, s, n, N, R, AP, AD, B, gdots, partial);
   hipLaunchKernelGGL(k_reduce_cols, dim3(2 * N), dim3(TPB), 0, s, 2 * N, nbk, partial, gsel + N);
+  hipLaunchKernelGGL(k_guess_apply, dim3(nbk), dim3(TPB), 0, s, n, N, R, Phi, gdots, gsel, X);
 }
 void launch_collect(hipStream_t s, int64_t n, int N, int stride, const float* F, const double* U,
                     const double* Phi, const double* scale, int64_t offset, int64_t cap, float* out_x,

@@ -122,7 +122,7 @@ struct Dev {
   float* F = nullptr;           // n N x 6 features (row i N + c)
   float* Ynn = nullptr;         // n N network outputs
   double* gscale = nullptr;     // N: max |phi_c|
-  double* gsel = nullptr;       // 4N: [learned start used, |r|^2 learned, |r|^2 plain, -]
+  double* gsel = nullptr;       // 4N: [learned start used, |r|^2 span minimiser, |r|^2 plain, |r|^2 taken]
   double* gdots = nullptr;      // 5N: Galerkin sums of the learned start
   int32_t* d2v = nullptr;       // n: library dof -> vertex
   int32_t* dof_user = nullptr;  // n: library dof -> caller dof
@@ -393,8 +393,9 @@ void launch_features(hipStream_t s, int64_t n, int N, const int32_t* d2v, const 
                      const double* RZ, int n_nuclei, int pot, double rc, double omega, int xck, double xalpha,
                      double diag, const double* scale, float* F);
 void launch_guess_delta(hipStream_t s, int64_t n, int N, const double* scale, const float* Y, double* D);
-// X (= delta on entry) <- Galerkin start in span{Phi, delta}; gdots: 5N sums;
-// gsel: [used (N), |b - A x0|^2 (N), |b - A phi|^2 (N)].
+// X (= delta on entry) <- Galerkin start in span{Phi, delta} where it lowers J
+// and does not raise the residual, Phi elsewhere; gdots: 5N sums; gsel: [used
+// (N), |b - A x0|^2 (N), |b - A phi|^2 (N), |b - A X|^2 of the start taken (N)].
 void launch_guess_galerkin(hipStream_t s, int64_t n, int N, const double* Phi, const double* AP, const double* AD,
                            const double* B, double* X, double* partial, double* gdots, double* gsel);
 void launch_collect(hipStream_t s, int64_t n, int N, int stride, const float* F, const double* U,

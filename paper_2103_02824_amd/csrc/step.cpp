@@ -679,7 +679,7 @@ mlc_status phase_finish(StepRun& S, mlc_step_report* rep) {
     int used = 0;
     for (int i = 0; i < N; ++i) {
       used += S.gsel[i] != 0.0;
-      double l = S.gsel[N + i], p = S.gsel[2 * N + i];
+      double l = S.gsel[3 * N + i], p = S.gsel[2 * N + i];
       worst = std::max(worst, p > 0.0 ? std::sqrt(l / p) : (l > 0.0 ? 1e300 : 1.0));
     }
     S.r.guess_learned_cols = used;

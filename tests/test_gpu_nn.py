@@ -86,10 +86,6 @@ def test_adam_steps_match_checker(net):
         assert np.max(np.abs(got - ref) / (1.0 + np.abs(ref))) < 1e-6
 
 
-def ctx_N(S):
-    return int(S.n_orbitals)
-
-
 def _tiny():
     from inputs.systems import tiny_system
     return tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=True, n_orbitals=2, seed=7)
@@ -161,9 +157,10 @@ def test_training_lowers_loss_and_guess_gain_on_unseen_cluster(net):
     4-atom distribution, GPU training by the library's kernels, then one
     unseen cluster stepped from the same state with and without the learned
     start. Reported: loss decrease, CG iterations and the initial residual
-    ratio; required: the loss falls, the solves reach the same answer, and
-    CG from the learned start (never farther from the solution in the A-norm)
-    needs at most two iterations more per orbital."""
+    ratio; required: the loss falls, the solves reach the same answer, the
+    learned start's initial residual is nowhere above the plain start's (it
+    is taken only where it lowers the energy without raising the residual),
+    and CG from it needs no more iterations than from phi."""
     import torch
     from inputs.systems import c2_small
     from paper_2103_02824_amd import mlc
@@ -202,6 +199,9 @@ def test_training_lowers_loss_and_guess_gain_on_unseen_cluster(net):
           f"learned {learned['cg_iters_max']} (sum {learned['cg_iters_sum']}), learned columns "
           f"{learned['guess_learned_cols']}, residual ratio {learned['guess_resid_ratio']:.3f}", flush=True)
     assert relerr(res[True][1], res[False][1]) < 1e-6
-    # the start is the energy minimiser over a span containing phi: never worse in the A-norm, so CG from
-    # it needs at most a few iterations more (the residual test is not the A-norm) and usually fewer
-    assert learned["cg_iters_sum"] <= plain["cg_iters_sum"] + 2 * ctx_N(S)
+    # the start is taken only where it lowers the energy and does not raise the residual: its initial
+    # residual never exceeds the plain start's, column by column
+    assert learned["guess_resid_ratio"] <= 1.0 + 1e-12
+    # no regression in CG iterations (on this cluster the network's starts raise the residual in every
+    # column, so phi is kept throughout: the same iterations as the plain start)
+    assert learned["cg_iters_sum"] <= plain["cg_iters_sum"]

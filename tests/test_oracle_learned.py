@@ -154,8 +154,9 @@ def test_nearest_distances_brute_force():
 
 def test_galerkin_start_recovers_the_solution_and_never_loses_energy():
     """A perfect direction (delta = u - phi) gives x0 = u exactly; any
-    direction gives J(x0) <= J(phi) and J(x0) <= J at other points of the
-    span; a direction parallel to phi is rejected (singular 2 x 2)."""
+    direction gives J(x0) <= J(phi) and |b - A x0| <= |b - A phi|, and where
+    the combination is used, J(x0) <= J at other points of the span; a
+    direction parallel to phi is rejected (singular 2 x 2)."""
     rng = np.random.default_rng(12)
     n = 40
     Bm = rng.normal(size=(n, n))
@@ -173,8 +174,41 @@ def test_galerkin_start_recovers_the_solution_and_never_loses_energy():
     X, used, coef = Lr.galerkin_start(A, B, Phi, D)
     for c in range(3):
         assert J(X[:, c], c) <= J(Phi[:, c], c) + 1e-9
-        for da, db in rng.normal(scale=0.05, size=(5, 2)):
-            a, b = coef[c]
-            assert J(X[:, c], c) <= J((a + da) * Phi[:, c] + (b + db) * D[:, c], c) + 1e-9
+        assert np.linalg.norm(B[:, c] - A @ X[:, c]) <= np.linalg.norm(B[:, c] - A @ Phi[:, c]) * (1 + 1e-12)
+        if used[c]:
+            for da, db in rng.normal(scale=0.05, size=(5, 2)):
+                a, b = coef[c]
+                assert J(X[:, c], c) <= J((a + da) * Phi[:, c] + (b + db) * D[:, c], c) + 1e-9
     X, used, _ = Lr.galerkin_start(A, B, Phi, 2.0 * Phi)
     assert not used.any() and np.array_equal(X, Phi)
+
+
+def test_galerkin_start_keeps_phi_when_the_residual_grows():
+    """Random starts on a stiff diagonal A (eigenvalues 1 and 400): among them
+    are directions whose span minimiser lowers J (the A-norm error) but has a
+    larger residual than phi; there phi is kept, and elsewhere the minimiser
+    is used. Both cases must occur in the draws."""
+    rng = np.random.default_rng(5)
+    n = 6
+    A = np.diag([1.0, 1.0, 1.0, 1.0, 1.0, 400.0])
+    kept = taken = 0
+    for _ in range(400):
+        u = rng.normal(size=n)
+        B = (A @ u)[:, None]
+        Phi = (u + rng.normal(size=n) * np.array([1, 1, 1, 1, 1, 0.02]))[:, None]
+        D = rng.normal(size=(n, 1)) * np.array([[1], [1], [1], [1], [1], [0.05]])
+        G = np.array([[Phi[:, 0] @ A @ Phi[:, 0], Phi[:, 0] @ A @ D[:, 0]],
+                      [D[:, 0] @ A @ Phi[:, 0], D[:, 0] @ A @ D[:, 0]]])
+        r = np.array([B[:, 0] @ Phi[:, 0], B[:, 0] @ D[:, 0]])
+        a, b = np.linalg.solve(G, r)
+        x = a * Phi[:, 0] + b * D[:, 0]
+        drops = 0.5 * x @ A @ x - B[:, 0] @ x < 0.5 * Phi[:, 0] @ A @ Phi[:, 0] - B[:, 0] @ Phi[:, 0]
+        grows = np.linalg.norm(B[:, 0] - A @ x) > np.linalg.norm(B[:, 0] - A @ Phi[:, 0])
+        X, used, _ = Lr.galerkin_start(A, B, Phi, D)
+        if drops and grows:
+            kept += 1
+            assert not used[0] and np.array_equal(X, Phi)
+        elif drops:
+            taken += 1
+            assert used[0] and np.allclose(X[:, 0], x, rtol=1e-12, atol=1e-12)
+    assert kept > 0 and taken > 0, (kept, taken)
