@@ -161,6 +161,9 @@ typedef struct {
                            eigenpairs are the orbitals (needs the N(N+1)/2
                            pair integrals (u_j u_l, psi_k) from the fine
                            mesh; N <= 64)                                      */
+  int32_t estimator;    /* 1: mlc_create builds the fine mesh's face
+                           neighbours for mlc_estimate (host time and 20 bytes
+                           of workspace per fine tet); 0 (default): off       */
 } mlc_options;
 
 enum { MLC_VARIANT_EIGENPAIRWISE = 0, MLC_VARIANT_JOINT = 1 };
@@ -308,6 +311,62 @@ mlc_status mlc_probe(mlc_ctx* ctx, int32_t which, double* out, int64_t count);
  * step-6 kernels (MLC_ERR_ARG otherwise); reps in 1..100000. */
 enum { MLC_KERNEL_CG_SPMM = 0, MLC_KERNEL_CHEB_STEP, MLC_KERNEL_HARTREE_SPMM, MLC_KERNEL_HARTREE_CHEB_STEP };
 mlc_status mlc_time_kernel(mlc_ctx* ctx, int32_t which, int32_t reps, double* avg_us);
+
+/* ---- Adaptive loop: estimate, mark, refine, transfer ------------------------
+ * Algorithm 1 steps 1-3 and 9 around the correction step: the residual a
+ * posteriori estimator of Section 2 on each fine tet T,
+ *   eta^2(T) = h_T^2 ||R_T||^2_{0,T} + sum over interior faces e of T of h_e ||J_e||^2_{0,e},
+ *   R_T = ((V_eff - lambda_i) phi_i)_i (the Laplacian of a P1 function vanishes
+ *   inside T), J_e = (1/2 grad phi_i|T+ . nu+ + 1/2 grad phi_i|T- . nu-)_i,
+ * with h_T, h_e the longest edges of T and e, V_eff of the current state, the
+ * element norm by the 4-point rule of the assembly, and the norms of the
+ * vectors over orbitals the sums of their squares; Doerfler marking; conforming
+ * refinement of the marked tets by tagged (Maubach) bisection; the transfer of
+ * nodal values (a new vertex is an edge midpoint: the mean of its ends).
+ *
+ * mlc_estimate: eta^2 of the context's current state for every fine tet, into
+ *   the caller's device array eta2 (nt doubles, in the caller's tet order);
+ *   asynchronous on the context's stream (it recomputes V_eff of the state at
+ *   the quadrature points). Needs options.estimator = 1 at mlc_create and a
+ *   state (MLC_ERR_STATE otherwise); MLC_ERR_ARG for a null pointer.
+ * mlc_mark_dorfler: host arrays. marked[t] = 1 for the smallest set M of tets,
+ *   taken in decreasing order of eta2 (ties by index), with sum_M eta2 >=
+ *   theta sum eta2, 0 elsewhere; *count = |M|. theta in (0, 1]; MLC_ERR_ARG
+ *   for bad arguments or a negative or non-finite eta2.
+ * mlc_refine: host. Bisects the marked tets of (xyz, tets) once each and then
+ *   every tet with a hanging edge until the mesh is conforming. Tets carry a
+ *   refinement tag (tags, nt int8; 3 for a Kuhn-ordered initial mesh whose
+ *   tets list x0, x1, x2, x3 with x0-x3 the cube diagonal) that selects the
+ *   edge to bisect: tag k cuts edge x0-xk into (x0..x_{k-1}, z, x_{k+1}..x3) and
+ *   (x1..x_k, z, x_{k+1}..x3), both tagged k - 1 (3 after 1). The result is
+ *   written to out (mlc_refine_result, owned by the library until
+ *   mlc_refine_free): new vertices are appended after the old ones; each
+ *   comes with the two ends of the edge it bisects (parents, 2 per new vertex),
+ *   in batches (batch_ptr) whose parents all precede the batch.
+ * mlc_transfer_vertices: device. values (nv_new x ncols, row-major, caller's
+ *   device memory) holds the old vertices' values in its first nv_old rows;
+ *   the rows of the new vertices are filled batch by batch with the means of
+ *   their parents' rows. parents_dev: the refinement's parents copied to the
+ *   device (2 x (nv_new - nv_old) int64); batch_ptr: host, nbatch + 1 offsets.
+ *   Asynchronous on the given stream. */
+mlc_status mlc_estimate(mlc_ctx* ctx, double* eta2_dev);
+mlc_status mlc_mark_dorfler(const double* eta2, int64_t nt, double theta, uint8_t* marked, int64_t* count);
+typedef struct {
+  int64_t nv, nt;          /* the refined mesh's vertex and tet counts */
+  const double* xyz;       /* nv x 3 */
+  const int32_t* tets;     /* nt x 4 */
+  const int8_t* tags;      /* nt */
+  int64_t n_new;           /* nv - the old vertex count */
+  const int64_t* parents;  /* n_new x 2: edge ends of each new vertex */
+  int32_t nbatch;
+  const int64_t* batch_ptr;/* nbatch + 1 offsets into the new vertices */
+  void* internal;
+} mlc_refine_result;
+mlc_status mlc_refine(int64_t nv, const double* xyz, int64_t nt, const int32_t* tets, const int8_t* tags,
+                      const uint8_t* marked, mlc_refine_result* out);
+void mlc_refine_free(mlc_refine_result* r);
+mlc_status mlc_transfer_vertices(int64_t nv_old, int64_t nv_new, const int64_t* parents_dev, int32_t nbatch,
+                                 const int64_t* batch_ptr, int32_t ncols, double* values_dev, void* hip_stream);
 
 /* ---- Learned initial guess of step 5 ----------------------------------------
  * Extension of the method (the paper starts every step-5 problem from the

@@ -81,6 +81,7 @@ class _Bisector:
         # children it appended (the only places a new hanging edge can be)
         self.split_ends = None
         self.n_children = 0
+        self.parents = []  # (lo, hi) edge of each created vertex, in creation (id) order
 
     def _key(self, a, b):
         lo = np.minimum(a, b)
@@ -116,6 +117,7 @@ class _Bisector:
             newxyz = 0.5 * (X[lo] + X[hi])
             new_ids = self.nv + np.arange(len(new_keys), dtype=np.int64)
             self.nv += len(new_keys)
+            self.parents.append(np.stack([lo, hi], axis=1))
             self.xyz.append(newxyz)
             mids[~found] = new_ids[inv]
             allk = np.concatenate([self.mid_keys, new_keys])
@@ -188,6 +190,45 @@ class _Bisector:
                 return
             self.bisect(h)
         raise RuntimeError("bisection closure did not terminate")
+
+
+class AdaptiveMesh:
+    """A conforming tetrahedral mesh refined step by step by tagged bisection
+    of marked tets plus the closure that removes hanging edges (the refinement
+    of an adaptive loop). Mesh data only: after each refine(), xyz and tets
+    describe the new mesh and new_parents holds, for each vertex created by
+    that refine() in id order, the two ends of the edge it bisects."""
+
+    def __init__(self, xyz, tets):
+        self._b = _Bisector(xyz, tets)
+        self.new_parents = np.zeros((0, 2), dtype=np.int64)
+
+    @classmethod
+    def kuhn(cls, n, lo, hi):
+        return cls(*kuhn_mesh(n, lo, hi))
+
+    @property
+    def xyz(self):
+        return self._b.coords()
+
+    @property
+    def tets(self):
+        return self._b.tets
+
+    def refine(self, marked):
+        """Bisect the marked tets once (marked: boolean mask over the current
+        tets), then close the mesh."""
+        marked = np.asarray(marked, dtype=bool)
+        if marked.shape != (len(self._b.tets),):
+            raise ValueError("marked must be a mask over the current tets")
+        nv0 = self._b.nv
+        start = len(self._b.parents)
+        self._b.bisect(marked)
+        self._b.close()
+        par = self._b.parents[start:]
+        self.new_parents = np.concatenate(par, axis=0) if par else np.zeros((0, 2), dtype=np.int64)
+        assert len(self.new_parents) == self._b.nv - nv0
+        return self
 
 
 def _longest_edge(xyz, tets):

@@ -160,6 +160,10 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
     d->rH = w.take<double>(nH);
     d->eH = w.take<double>(nH);
   }
+  if (c->opt.estimator) {
+    d->nbr = w.take<int32_t>(4 * nt);
+    d->tord = w.take<int32_t>(nt);
+  }
   return w.off + 256;
 }
 
@@ -225,6 +229,10 @@ mlc_status upload_and_init(mlc_ctx* c) {
   HIPCHK(up(s, d.RZ, RZ));
   HIPCHK(up(s, d.d2v, c->d2v));
   HIPCHK(up(s, d.dof_user, c->dof_user));
+  if (d.nbr) {
+    HIPCHK(up(s, d.nbr, c->nbr));
+    HIPCHK(up(s, d.tord, c->tord));
+  }
   if (d.pair_jl) {
     std::vector<int32_t> jl;
     for (int j = 0; j < c->N; ++j)
@@ -471,6 +479,7 @@ void mlc_options_default(mlc_options* o) {
   o->inner_mix_history = 6;
   o->inner_mix_beta = 0.5;
   o->variant = MLC_VARIANT_EIGENPAIRWISE;
+  o->estimator = 0;
 }
 
 mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys, const mlc_options* opt,
@@ -507,6 +516,7 @@ mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_sy
       c->opt.inner_mix_history < 0 || c->opt.inner_mix_history > 16 ||
       (c->opt.variant != MLC_VARIANT_EIGENPAIRWISE && c->opt.variant != MLC_VARIANT_JOINT) ||
       (c->opt.variant == MLC_VARIANT_JOINT && sys->n_orbitals > 64) ||
+      (c->opt.estimator != 0 && c->opt.estimator != 1) ||
       !(c->opt.inner_mix_beta > 0.0 && c->opt.inner_mix_beta <= 1.0)) {
     delete c;
     return MLC_ERR_ARG;
@@ -657,6 +667,36 @@ mlc_status mlc_probe(mlc_ctx* c, int32_t which, double* out, int64_t count) {
   if (!c || !out) return MLC_ERR_ARG;
   if (!c->has_step) return fail(c, MLC_ERR_STATE, "no correction step has run");
   return probe(c, which, out, count);
+}
+
+mlc_status mlc_estimate(mlc_ctx* c, double* eta2) {
+  if (!c || !eta2) return MLC_ERR_ARG;
+  if (!c->bound || !c->has_state) return fail(c, MLC_ERR_STATE, "bind and set a state first");
+  if (!c->opt.estimator) return fail(c, MLC_ERR_STATE, "created without options.estimator");
+  auto& d = c->d;
+  hipStream_t s = c->stream;
+  // V_eff of the current state at the quadrature points, then eta^2 per tet
+  launch_qp_fields(s, c->nt, d.tets, d.v2d, d.Phi, c->N, d.occ, d.w, d.vext, d.geo, d.qpx, c->xc, c->xalpha, d.vxc,
+                   d.exc, d.veff, d.rho, d.red);
+  HIPCHK(hipMemcpyAsync(d.colv, c->lam.data(), sizeof(double) * c->N, hipMemcpyHostToDevice, s));
+  launch_estimate(s, c->nt, c->N, d.tets, d.v2d, d.Phi, d.colv, d.veff, d.geo, d.xyz, d.nbr, d.tord, eta2);
+  HIPCHK(hipGetLastError());
+  return MLC_OK;
+}
+
+mlc_status mlc_transfer_vertices(int64_t nv_old, int64_t nv_new, const int64_t* parents, int32_t nbatch,
+                                 const int64_t* batch_ptr, int32_t ncols, double* values, void* stream) {
+  if (nv_old < 1 || nv_new < nv_old || nbatch < 0 || ncols < 1 || !values || (nv_new > nv_old && !parents) ||
+      (nbatch > 0 && !batch_ptr))
+    return MLC_ERR_ARG;
+  if (nbatch > 0 && (batch_ptr[0] != 0 || batch_ptr[nbatch] != nv_new - nv_old)) return MLC_ERR_ARG;
+  for (int32_t b = 0; b < nbatch; ++b)
+    if (batch_ptr[b + 1] < batch_ptr[b]) return MLC_ERR_ARG;
+  if (nbatch == 0 && nv_new != nv_old) return MLC_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  for (int32_t b = 0; b < nbatch; ++b)
+    launch_transfer(s, batch_ptr[b + 1] - batch_ptr[b], batch_ptr[b], nv_old, parents, ncols, values);
+  return hipGetLastError() == hipSuccess ? MLC_OK : MLC_ERR_HIP;
 }
 
 mlc_status mlc_time_kernel(mlc_ctx* c, int32_t which, int32_t reps, double* avg_us) {

@@ -382,92 +382,6 @@ __global__ void __launch_bounds__(BS, W) k_cheb_small(int64_t n, const int32_t* 
   }
 }
 
-// The fused Chebyshev step for one column (the Hartree problem and other
-// N = 1 systems), the same arithmetic as k_cheb_small<1>: each group of G
-// lanes takes R2 consecutive rows whose entries are interleaved in one pass
-// loop (U entries per lane and row per pass, all loads of a pass issued
-// together), so a wavefront has R2 times as many loads in flight as with
-// one row per group. A one-column step is latency-bound: each row is a chain
-// of row pointers, column indices and gathers.
-template <int G, int U, int BS, int W, int R2, typename T, typename MT>
-__global__ void __launch_bounds__(BS, W) k_cheb_one(int64_t n, const int32_t* __restrict__ rowptr,
-                                                    const int32_t* __restrict__ col, const MT* __restrict__ val,
-                                                    const T* __restrict__ dinv, const T* __restrict__ R,
-                                                    const T* __restrict__ Zin, const T* Zprev, T* Zout,
-                                                    const double* __restrict__ lmax, double ratio, int j,
-                                                    double* __restrict__ partial, const int32_t* __restrict__ flags) {
-  constexpr int RB = BS / G * R2;  // rows per block pass
-  if (flags && flags[0] == 0) return;
-  __shared__ double sd[BS / 64];
-  double cdd, crr;
-  cheb_coef(*lmax, ratio, j, &cdd, &crr);
-  const T cd = (T)cdd, cr = (T)crr;
-  const int sub = threadIdx.x % G, rl = threadIdx.x / G;
-  double dot = 0.0;
-  const RowBlocks rbk((n + RB - 1) / RB);
-  for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
-    // rows past n are computed as row n - 1 and not stored
-    int64_t r[R2];
-    bool live[R2];
-    int jb[R2], je[R2];
-    T rv[R2], zv[R2], pv[R2], di[R2], acc[R2];
-    int len = 0;
-#pragma unroll
-    for (int k = 0; k < R2; ++k) {
-      const int64_t r0 = rb * RB + (int64_t)rl * R2 + k;
-      live[k] = r0 < n;
-      r[k] = live[k] ? r0 : n - 1;
-      jb[k] = rowptr[r[k]];
-      je[k] = rowptr[r[k] + 1];
-      rv[k] = R[r[k]];
-      zv[k] = Zin[r[k]];
-      pv[k] = Zprev[r[k]];  // for j = 1 the caller passes Zprev = Zin (not used)
-      di[k] = dinv[r[k]];
-      acc[k] = T(0);
-      len = max(len, je[k] - jb[k]);
-    }
-    for (int o = sub; o < len; o += G * U) {
-      int cc[R2][U];
-      T vv[R2][U];
-#pragma unroll
-      for (int k = 0; k < R2; ++k)
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int e = jb[k] + o + u * G;
-          const uint32_t ec = (uint32_t)(e < je[k] ? e : je[k] - 1);
-          cc[k][u] = col[ec];
-          const T a = (T)val[ec];
-          vv[k][u] = e < je[k] ? a : T(0);
-        }
-#pragma unroll
-      for (int k = 0; k < R2; ++k)
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc[k] += vv[k][u] * Zin[cc[k][u]];
-    }
-#pragma unroll
-    for (int k = 0; k < R2; ++k) {
-#pragma unroll
-      for (int off = G / 2; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, G);
-      if (live[k] && sub == 0) {
-        const T dv = j > 1 ? zv[k] - pv[k] : zv[k];
-        const T z = zv[k] + (cd * dv + cr * (di[k] * (rv[k] - acc[k])));
-        Zout[r[k]] = z;
-        if (partial) dot += (double)rv[k] * (double)z;
-      }
-    }
-  }
-  if (!partial) return;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const double v = wave_sum(dot);
-  if (lane == 0) sd[wid] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < BS / 64; ++w) s += sd[w];
-    partial[blockIdx.x] = s;
-  }
-}
-
 // The fused Chebyshev step for N > 8 in the same layout: w = A Zin;
 // Zout = Zin + cd (Zin - Zprev) + cr D^-1 (R - w) (Zprev = 0 for j = 1; Zout
 // may be Zprev); with PART, per-block column sums of R . Zout into partial (a
@@ -1199,33 +1113,22 @@ template <typename T>
 void launch_cheb_step_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr, const int32_t* col, const T* val,
                         const T* dinv, const T* Rv, const PolyPC<T>& pc, int j, const T* zin, const T* zprev,
                         T* zout, double* part, const int32_t* flags) {
-  if (N == 1) {
-    // one column: two rows per lane group (k_cheb_one); the partial producer keeps the grid its consumers
-    // expect (spmm_blocks(n, 1))
-    auto one = [&](auto mt, const auto* v) {
-      using MT = decltype(mt);
+  if constexpr (std::is_same<T, double>::value) {
+    if (pc.val32 && N == 1) {
+      // one FP64 column with FP32 matrix values (the Hartree problem's polynomial)
       if (part) {
         const int64_t needed = (n + (SPMM_BS / ROW_G) - 1) / (SPMM_BS / ROW_G);
-        hipLaunchKernelGGL((k_cheb_one<ROW_G, unroll_cheb_part(1), SPMM_BS, 4, 2, T, MT>),
-                           dim3(cap_xcd(needed, SPMM_MAXBLK)), dim3(SPMM_BS), 0, s, n, rowptr, col, v, dinv, Rv, zin,
-                           zprev, zout, pc.lmax, pc.ratio, j, part, flags);
+        hipLaunchKernelGGL((k_cheb_small<1, ROW_G, unroll_cheb_part(1), SPMM_BS, waves_cheb_part(1), T, float>),
+                           dim3(cap_xcd(needed, SPMM_MAXBLK)), dim3(SPMM_BS), 0, s, n, rowptr, col, pc.val32, dinv,
+                           Rv, zin, zprev, zout, pc.lmax, pc.ratio, j, part, flags);
       } else {
-        constexpr int RB1 = TPB / ROW_G * 2;
-        const int64_t needed = (n + RB1 - 1) / RB1;
-        hipLaunchKernelGGL((k_cheb_one<ROW_G, unroll_wide(1), TPB, 4, 2, T, MT>),
-                           dim3(cap_xcd(needed, 1 << 30)), dim3(TPB), 0, s, n, rowptr, col, v, dinv, Rv, zin, zprev,
-                           zout, pc.lmax, pc.ratio, j, part, flags);
+        const int64_t needed = (n + (TPB / ROW_G) - 1) / (TPB / ROW_G);
+        hipLaunchKernelGGL((k_cheb_small<1, ROW_G, unroll_wide(1), TPB, waves_wide(1), T, float>),
+                           dim3(cap_xcd(needed, 1 << 30)), dim3(TPB), 0, s, n, rowptr, col, pc.val32, dinv, Rv, zin,
+                           zprev, zout, pc.lmax, pc.ratio, j, part, flags);
       }
-    };
-    if constexpr (std::is_same<T, double>::value) {
-      if (pc.val32) {
-        // one FP64 column with FP32 matrix values (the Hartree problem's polynomial)
-        one(float(0), pc.val32);
-        return;
-      }
+      return;
     }
-    one(T(0), val);
-    return;
   }
   if (N <= 8) {
 #define CHEB_CASE(K)                                                                                             \

@@ -1331,6 +1331,110 @@ __global__ void __launch_bounds__(TPB) k_guess_apply(int64_t n, int N, int R, co
   }
 }
 
+// eta^2 of each fine tet for the residual estimator of the adaptive loop:
+// h_T^2 sum_i sum_q |T|/4 ((V_eff(q) - lambda_i) phi_i(q))^2 plus, for each
+// face a (opposite vertex a) with a tet t' on its other side,
+// h_e |e| sum_i J_i^2 with J_i = 1/2 (grad phi_i|t - grad phi_i|t') . nu,
+// nu = -grad lambda_a / |grad lambda_a| the outward normal, |e| = 3 |t|
+// |grad lambda_a|, h_e the face's longest edge. One thread per tet, the
+// orbitals in a loop; written at the caller's index of the tet.
+__global__ void __launch_bounds__(TPB) k_estimate(int64_t nt, int N, const int32_t* __restrict__ tets,
+                                                  const int32_t* __restrict__ v2d, const double* __restrict__ Phi,
+                                                  const double* __restrict__ lam, const double* __restrict__ veff,
+                                                  const double* __restrict__ geo, const double* __restrict__ xyz,
+                                                  const int32_t* __restrict__ nbr, const int32_t* __restrict__ tord,
+                                                  double* __restrict__ eta2) {
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= nt) return;
+  int vt[4], dof[4];
+  double x[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    vt[a] = tets[4 * t + a];
+    dof[a] = v2d[vt[a]];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x[a][k] = xyz[3 * (int64_t)vt[a] + k];
+  }
+  const double* G = geo + 16 * t;
+  const double vol = G[0];
+  double h2 = 0.0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = a + 1; b < 4; ++b) {
+      double e2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) e2 += (x[a][k] - x[b][k]) * (x[a][k] - x[b][k]);
+      h2 = fmax(h2, e2);
+    }
+  // faces: outward normal, h_e |e| (0 on the boundary), the neighbour's DoFs and gradients
+  double nu[4][3], wf[4];
+  int64_t tn[4];
+  for (int a = 0; a < 4; ++a) {
+    const int32_t o = nbr[4 * t + a];
+    tn[a] = o;
+    const double g0 = G[1 + 3 * a], g1 = G[2 + 3 * a], g2 = G[3 + 3 * a];
+    const double gn = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+    nu[a][0] = -g0 / gn;
+    nu[a][1] = -g1 / gn;
+    nu[a][2] = -g2 / gn;
+    double he2 = 0.0;
+    for (int b = 0; b < 4; ++b)
+      for (int c = b + 1; c < 4; ++c) {
+        if (b == a || c == a) continue;
+        double e2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) e2 += (x[b][k] - x[c][k]) * (x[b][k] - x[c][k]);
+        he2 = fmax(he2, e2);
+      }
+    wf[a] = o >= 0 ? sqrt(he2) * 3.0 * vol * gn : 0.0;
+  }
+  double elem = 0.0, face = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double u[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) u[a] = dof[a] >= 0 ? Phi[(int64_t)dof[a] * N + i] : 0.0;
+    const double us = u[0] + u[1] + u[2] + u[3];
+    const double li = lam[i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double r = (veff[4 * t + q] - li) * (QB * us + (QA - QB) * u[q]);
+      elem += 0.25 * vol * r * r;
+    }
+    double g[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) g[k] += u[a] * G[1 + 3 * a + k];
+    for (int a = 0; a < 4; ++a) {
+      if (tn[a] < 0) continue;
+      const int64_t o = tn[a];
+      const double* Go = geo + 16 * o;
+      double go[3] = {0.0, 0.0, 0.0};
+      for (int b = 0; b < 4; ++b) {
+        const int db = v2d[tets[4 * o + b]];
+        const double ub = db >= 0 ? Phi[(int64_t)db * N + i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) go[k] += ub * Go[1 + 3 * b + k];
+      }
+      const double J = 0.5 * ((g[0] - go[0]) * nu[a][0] + (g[1] - go[1]) * nu[a][1] + (g[2] - go[2]) * nu[a][2]);
+      face += wf[a] * J * J;
+    }
+  }
+  eta2[tord[t]] = h2 * elem + face;
+}
+
+// Nodal values of the vertices one bisection batch created: the mean of the
+// two ends of each one's edge (rows of ncols values).
+__global__ void __launch_bounds__(TPB) k_transfer(int64_t m, int64_t first, int64_t nv_old,
+                                                  const int64_t* __restrict__ parents, int ncols,
+                                                  double* __restrict__ values) {
+  const int64_t id = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (id >= m * ncols) return;
+  const int64_t j = first + id / ncols;
+  const int c = (int)(id - (id / ncols) * ncols);
+  const int64_t lo = parents[2 * j], hi = parents[2 * j + 1];
+  values[(nv_old + j) * ncols + c] = 0.5 * (values[lo * ncols + c] + values[hi * ncols + c]);
+}
+
 // Sample rows of every stride-th DoF: features and (u - phi)/s.
 __global__ void __launch_bounds__(TPB) k_collect(int64_t n, int N, int stride, const float* __restrict__ F,
                                                  const double* __restrict__ U, const double* __restrict__ Phi,
@@ -1539,6 +1643,16 @@ void launch_guess_galerkin(hipStream_t s, int64_t n, int N, const double* Phi, c
   hipLaunchKernelGGL(k_guess_resid, dim3(nbk), dim3(TPB), 0, s, n, N, R, AP, AD, B, gdots, partial);
   hipLaunchKernelGGL(k_reduce_cols, dim3(2 * N), dim3(TPB), 0, s, 2 * N, nbk, partial, gsel + N);
   hipLaunchKernelGGL(k_guess_apply, dim3(nbk), dim3(TPB), 0, s, n, N, R, Phi, gdots, gsel, X);
+}
+void launch_estimate(hipStream_t s, int64_t nt, int N, const int32_t* tets, const int32_t* v2d, const double* Phi,
+                     const double* lam, const double* veff, const double* geo, const double* xyz, const int32_t* nbr,
+                     const int32_t* tord, double* eta2) {
+  hipLaunchKernelGGL(k_estimate, dim3(nb(nt)), dim3(TPB), 0, s, nt, N, tets, v2d, Phi, lam, veff, geo, xyz, nbr, tord,
+                     eta2);
+}
+void launch_transfer(hipStream_t s, int64_t m, int64_t first, int64_t nv_old, const int64_t* parents, int ncols,
+                     double* values) {
+  if (m > 0) hipLaunchKernelGGL(k_transfer, dim3(nb(m * ncols)), dim3(TPB), 0, s, m, first, nv_old, parents, ncols, values);
 }
 void launch_collect(hipStream_t s, int64_t n, int N, int stride, const float* F, const double* U,
                     const double* Phi, const double* scale, int64_t offset, int64_t cap, float* out_x,

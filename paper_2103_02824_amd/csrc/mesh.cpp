@@ -184,6 +184,44 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
   c->tets.resize(4 * c->nt);
   for (int64_t t = 0; t < c->nt; ++t)
     for (int a = 0; a < 4; ++a) c->tets[4 * t + a] = tin[4 * tord[t] + a];
+  if (c->opt.estimator) {
+    // the caller's tet order, and for each face (opposite vertex a) the tet
+    // on its other side: faces sorted by their vertex triple, equal triples
+    // adjacent
+    c->tord.resize(c->nt);
+    for (int64_t t = 0; t < c->nt; ++t) c->tord[t] = (int32_t)tord[t];
+    struct Face {
+      int32_t v[3];
+      int32_t id;  // 4 t + a
+    };
+    std::vector<Face> fs(4 * c->nt);
+    for (int64_t t = 0; t < c->nt; ++t)
+      for (int a = 0; a < 4; ++a) {
+        Face& f = fs[4 * t + a];
+        int k = 0;
+        for (int b = 0; b < 4; ++b)
+          if (b != a) f.v[k++] = c->tets[4 * t + b];
+        std::sort(f.v, f.v + 3);
+        f.id = (int32_t)(4 * t + a);
+      }
+    std::sort(fs.begin(), fs.end(), [](const Face& x, const Face& y) {
+      if (x.v[0] != y.v[0]) return x.v[0] < y.v[0];
+      if (x.v[1] != y.v[1]) return x.v[1] < y.v[1];
+      if (x.v[2] != y.v[2]) return x.v[2] < y.v[2];
+      return x.id < y.id;
+    });
+    c->nbr.assign(4 * c->nt, -1);
+    for (size_t i = 0; i + 1 < fs.size(); ++i) {
+      const Face &x = fs[i], &y = fs[i + 1];
+      if (x.v[0] == y.v[0] && x.v[1] == y.v[1] && x.v[2] == y.v[2]) {
+        if (i + 2 < fs.size() && fs[i + 2].v[0] == x.v[0] && fs[i + 2].v[1] == x.v[1] && fs[i + 2].v[2] == x.v[2])
+          return fail(c, MLC_ERR_MESH, "a face is shared by more than two fine tets");
+        c->nbr[x.id] = y.id / 4;
+        c->nbr[y.id] = x.id / 4;
+        ++i;
+      }
+    }
+  }
 
   // ---- geometry ---------------------------------------------------------------
   c->geo.assign(16 * c->nt, 0.0);

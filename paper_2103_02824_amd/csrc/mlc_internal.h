@@ -100,6 +100,8 @@ struct Dev {
   double* cel_tri = nullptr;    // cnt x 20
   double* cel_pairs = nullptr;  // joint variant: cnt x npair x 4, (u_j u_l, psi_m)
   int32_t* pair_jl = nullptr;   // joint variant: the pairs (j <= l), 2 x npair
+  int32_t* nbr = nullptr;       // estimator: nt x 4, tet across the face opposite vertex a (-1: boundary)
+  int32_t* tord = nullptr;      // estimator: the caller's index of each (Morton-ordered) tet
   double* chat = nullptr;       // 17 x nt: coarse hats at fine quadrature points, fine volume
   // small
   double* small = nullptr;      // packed small blocks (see step.cpp)
@@ -161,6 +163,8 @@ struct mlc_ctx {
   std::vector<int32_t> adj_ptr, adj_tet, adj_pos;
   std::vector<int8_t> adj_loc;
   std::vector<double> geo;              // nt x 16
+  std::vector<int32_t> tord;            // caller's index of each library tet (estimator option)
+  std::vector<int32_t> nbr;             // nt x 4 face neighbours (estimator option)
   std::vector<int32_t> slot_ptr, slot_of, diag_slot;  // assembly lists
   // ---- coarse ---------------------------------------------------------------
   int64_t nH = 0;
@@ -393,6 +397,11 @@ void launch_features(hipStream_t s, int64_t n, int N, const int32_t* d2v, const 
                      const double* RZ, int n_nuclei, int pot, double rc, double omega, int xck, double xalpha,
                      double diag, const double* scale, float* F);
 void launch_guess_delta(hipStream_t s, int64_t n, int N, const double* scale, const float* Y, double* D);
+void launch_estimate(hipStream_t s, int64_t nt, int N, const int32_t* tets, const int32_t* v2d, const double* Phi,
+                     const double* lam, const double* veff, const double* geo, const double* xyz, const int32_t* nbr,
+                     const int32_t* tord, double* eta2);
+void launch_transfer(hipStream_t s, int64_t m, int64_t first, int64_t nv_old, const int64_t* parents, int ncols,
+                     double* values);
 // X (= delta on entry) <- Galerkin start in span{Phi, delta} where it lowers J
 // and does not raise the residual, Phi elsewhere; gdots: 5N sums; gsel: [used
 // (N), |b - A x0|^2 (N), |b - A phi|^2 (N), |b - A X|^2 of the start taken (N)].

@@ -34,7 +34,8 @@ EXPORTED = ["mlc_options_default", "mlc_create", "mlc_sizes", "mlc_workspace_byt
             "mlc_batch_last_error", "mlc_batch_destroy", "mlc_nn_create", "mlc_nn_workspace_bytes", "mlc_nn_bind",
             "mlc_nn_set_params", "mlc_nn_get_params", "mlc_nn_forward", "mlc_nn_loss_grad", "mlc_nn_adam",
             "mlc_nn_train", "mlc_nn_last_error", "mlc_nn_destroy", "mlc_set_guess", "mlc_set_sample_sink",
-            "mlc_sample_count", "mlc_nn_loss_grad_noalloc"]
+            "mlc_sample_count", "mlc_nn_loss_grad_noalloc", "mlc_estimate", "mlc_mark_dorfler", "mlc_refine",
+            "mlc_refine_free", "mlc_transfer_vertices"]
 N_PARAMS = 8833
 
 
@@ -64,7 +65,8 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("ir_inner_rtol", C.c_double), ("ir_max_outer", C.c_int32),
                 ("precond", C.c_int32), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("hartree_coarse", C.c_int32), ("hartree_precond", C.c_int32),
-                ("inner_mix_history", C.c_int32), ("inner_mix_beta", C.c_double), ("variant", C.c_int32)]
+                ("inner_mix_history", C.c_int32), ("inner_mix_beta", C.c_double), ("variant", C.c_int32),
+                ("estimator", C.c_int32)]
 
 PREC_FP64, PREC_FP32_IR = 0, 1
 PC_JACOBI, PC_CHEBYSHEV = 0, 1
@@ -97,6 +99,13 @@ class BatchReport(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
 
 
+class RefineResult(C.Structure):
+    _fields_ = [("nv", C.c_int64), ("nt", C.c_int64), ("xyz", C.POINTER(C.c_double)),
+                ("tets", C.POINTER(C.c_int32)), ("tags", C.POINTER(C.c_int8)), ("n_new", C.c_int64),
+                ("parents", C.POINTER(C.c_int64)), ("nbatch", C.c_int32), ("batch_ptr", C.POINTER(C.c_int64)),
+                ("internal", C.c_void_p)]
+
+
 def lib():
     """Load libmlc.so (raises if it has not been built)."""
     global _lib
@@ -119,6 +128,16 @@ def lib():
     L.mlc_probe.argtypes = [vp, i32, P(dbl), i64]
     L.mlc_time_kernel.argtypes = [vp, i32, i32, P(dbl)]
     L.mlc_time_kernel.restype = i32
+    L.mlc_estimate.argtypes = [vp, vp]
+    L.mlc_estimate.restype = i32
+    L.mlc_mark_dorfler.argtypes = [P(dbl), i64, dbl, P(C.c_uint8), P(i64)]
+    L.mlc_mark_dorfler.restype = i32
+    L.mlc_refine.argtypes = [i64, P(dbl), i64, P(i32), P(C.c_int8), P(C.c_uint8), P(RefineResult)]
+    L.mlc_refine.restype = i32
+    L.mlc_refine_free.argtypes = [P(RefineResult)]
+    L.mlc_refine_free.restype = None
+    L.mlc_transfer_vertices.argtypes = [i64, i64, vp, i32, P(i64), i32, vp, vp]
+    L.mlc_transfer_vertices.restype = i32
     L.mlc_status_string.argtypes = [i32]
     L.mlc_status_string.restype = C.c_char_p
     L.mlc_last_error.argtypes = [vp]
@@ -308,6 +327,15 @@ class Context:
         self._chk(lib().mlc_sample_count(self.h, C.byref(r)))
         return r.value
 
+    def estimate(self):
+        """eta^2 of the current state per fine tet (the residual estimator of
+        the adaptive loop), a device tensor in the caller's tet order; needs
+        options(estimator=1)."""
+        import torch
+        eta2 = torch.empty(self.n_tets, dtype=torch.float64, device=self.device)
+        self._chk(lib().mlc_estimate(self.h, C.c_void_p(eta2.data_ptr())))
+        return eta2
+
     def time_kernel(self, which="cg_spmm", reps=50):
         """Mean launch time (us) of one solver kernel replayed back to back:
         cg_spmm, cheb_step, hartree_spmm, hartree_cheb_step."""
@@ -325,6 +353,61 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def mark_dorfler(eta2, theta):
+    """Doerfler set of eta2 (host array): (boolean mask, count)."""
+    e = np.ascontiguousarray(eta2, dtype=np.float64)
+    m = np.zeros(len(e), dtype=np.uint8)
+    k = C.c_int64()
+    st = lib().mlc_mark_dorfler(_dp(e), len(e), float(theta), m.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(k))
+    if st != MLC_OK:
+        raise MlcError(st, "mlc_mark_dorfler")
+    return m.astype(bool), k.value
+
+
+def refine(xyz, tets, tags, marked):
+    """Bisect the marked tets and close the mesh (mlc_refine). Returns a dict
+    of NumPy copies: xyz, tets, tags, parents (n_new x 2) and batch_ptr."""
+    X = np.ascontiguousarray(xyz, dtype=np.float64)
+    T = np.ascontiguousarray(tets, dtype=np.int32)
+    G = np.ascontiguousarray(tags, dtype=np.int8)
+    M = np.ascontiguousarray(marked, dtype=np.uint8)
+    r = RefineResult()
+    st = lib().mlc_refine(len(X), _dp(X), len(T), T.ctypes.data_as(C.POINTER(C.c_int32)),
+                          G.ctypes.data_as(C.POINTER(C.c_int8)), M.ctypes.data_as(C.POINTER(C.c_uint8)),
+                          C.byref(r))
+    if st != MLC_OK:
+        raise MlcError(st, "mlc_refine")
+    try:
+        out = {"xyz": np.ctypeslib.as_array(r.xyz, shape=(r.nv, 3)).copy(),
+               "tets": np.ctypeslib.as_array(r.tets, shape=(r.nt, 4)).copy(),
+               "tags": np.ctypeslib.as_array(r.tags, shape=(r.nt,)).copy(),
+               "parents": (np.ctypeslib.as_array(r.parents, shape=(r.n_new, 2)).copy() if r.n_new
+                           else np.zeros((0, 2), dtype=np.int64)),
+               "batch_ptr": np.ctypeslib.as_array(r.batch_ptr, shape=(r.nbatch + 1,)).copy()}
+    finally:
+        lib().mlc_refine_free(C.byref(r))
+    return out
+
+
+def transfer_vertices(values, nv_old, parents, batch_ptr, stream=None):
+    """Fill the new vertices' rows of values (device tensor, nv_new x ncols,
+    float64, the first nv_old rows holding the old values) with the means of
+    their parents' rows, batch by batch (mlc_transfer_vertices)."""
+    import torch
+    assert values.dtype == torch.float64 and values.is_contiguous()
+    v2 = values.reshape(values.shape[0], -1)
+    par = torch.as_tensor(np.ascontiguousarray(parents, dtype=np.int64).reshape(-1), device=values.device)
+    bp = np.ascontiguousarray(batch_ptr, dtype=np.int64)
+    s = stream if stream is not None else torch.cuda.current_stream(values.device)
+    st = lib().mlc_transfer_vertices(int(nv_old), int(v2.shape[0]), C.c_void_p(par.data_ptr()), len(bp) - 1,
+                                     bp.ctypes.data_as(C.POINTER(C.c_int64)), int(v2.shape[1]),
+                                     C.c_void_p(v2.data_ptr()), C.c_void_p(s.cuda_stream))
+    if st != MLC_OK:
+        raise MlcError(st, "mlc_transfer_vertices")
+    s.synchronize()  # keeps par alive until the kernels have read it
+    return values
 
 
 class Batch:
