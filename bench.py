@@ -274,8 +274,10 @@ def main():
                     help="--workload batch: inner iterations per step (host, reported apart from the GPU time)")
     ap.add_argument("--train-steps", type=int, default=800,
                     help="--workload batch: Adam steps of the learned-guess network")
-    ap.add_argument("--train-systems", type=int, default=60,
+    ap.add_argument("--train-systems", type=int, default=125,
                     help="--workload learned: 4-atom clusters (seeds 1000, ...) whose steps give the training rows")
+    ap.add_argument("--train-steps-per-system", type=int, default=4,
+                    help="--workload learned: correction steps sampled per training cluster (125 x 4 = 500 solves)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this size twice (hardware counter calibration)")
     args = ap.parse_args()
@@ -558,8 +560,8 @@ def run_learned(args):
     from paper_2103_02824_amd import mlc
     t_all = time.perf_counter()
     base = dict(cg_rtol=args.cg_rtol, poisson_rtol=args.cg_rtol, inner_maxit=30, inner_tol=args.inner_tol)
-    net, rows, l0, l1 = train_guess_network(mlc, args, base, n_systems=args.train_systems, steps_per_system=2,
-                                            stride=2, cap=4000000)
+    net, rows, l0, l1 = train_guess_network(mlc, args, base, n_systems=args.train_systems,
+                                            steps_per_system=args.train_steps_per_system, stride=2, cap=8000000)
     S = make_system("c3", args.seed)
     opts = _opts(mlc, args, mlc.PREC_FP32_IR, args.precond, args.hartree_coarse)
     opts.inner_maxit = 6
@@ -592,7 +594,9 @@ def run_learned(args):
            "steps": args.steps, "warmup": 1, "ms_per_step": summary["learned"]["t_fine_ms"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64-refinement", "data": "synthetic",
            "config": {"workload": f"40-atom seeded cluster (seed {args.seed}), graded P1 mesh, learned start",
-                      "n_dof": n, "orbitals": N, "training": f"{rows} rows from {args.train_systems} 4-atom clusters"},
+                      "n_dof": n, "orbitals": N,
+                      "training": f"{rows} rows from {args.train_systems * args.train_steps_per_system} solves "
+                                  f"({args.train_systems} 4-atom clusters x {args.train_steps_per_system} steps)"},
            "roofline": None, "cpu_baseline": None,
            "detail": dict(summary, training_rows=rows, training_loss=[l0, l1],
                           speedup_of_learned=summary["plain"]["t_fine_ms"] / summary["learned"]["t_fine_ms"],
