@@ -37,6 +37,7 @@ class System:
     xc: int = XC_LDA
     xalpha: float = 0.77298
     hartree: bool = True
+    order: int = 1           # fine-space elements: 1 = P1 (the paper's), 2 = P2
     # meshes
     xyz: np.ndarray = None
     tets: np.ndarray = None
@@ -174,15 +175,15 @@ def harmonic(n_fine, n_coarse, box=6.0, n_orbitals=4, omega=1.0):
                   xyz=xyz, tets=tets, cxyz=cxyz, ctets=ctets)
 
 
-def tiny_system(n_fine=4, n_coarse=2, box=4.0, nonlinear=True, n_orbitals=2, seed=3):
-    """A few-hundred-DoF mesh for brute-force checks."""
+def tiny_system(n_fine=4, n_coarse=2, box=4.0, nonlinear=True, n_orbitals=2, seed=3, order=1):
+    """A few-hundred-DoF mesh for brute-force checks (order 2: P2 on the same mesh)."""
     R, Z = random_cluster(seed, 2, 1.0, 1.0, z_choices=(1, 2))
     xyz, tets = kuhn_mesh(n_fine, -box, box)
     cxyz, ctets = kuhn_mesh(n_coarse, -box, box)
     ne = float(Z.sum())
     return System(name=f"tiny_{n_fine}", R=R, Z=Z, lo=-box, hi=box, potential=POT_ERF, rc=0.5,
                   n_orbitals=n_orbitals, occupations=aufbau(ne, n_orbitals),
-                  xc=XC_LDA if nonlinear else XC_NONE, hartree=nonlinear,
+                  xc=XC_LDA if nonlinear else XC_NONE, hartree=nonlinear, order=order,
                   xyz=xyz, tets=tets, cxyz=cxyz, ctets=ctets)
 
 

@@ -9,6 +9,7 @@ with NumPy/SciPy (sparse assembly, ``splu``, dense ``eigh``).
 
 Modules
   fem        P1 spaces, the 4-point quadrature, assembly, prolongation
+  fem2       P2 spaces (the quadratic extension), the 27-point conical rule
   xc         LDA (Slater + PZ81) and X-alpha from their energy densities
   potentials external potentials
   hartree    multipole Dirichlet data and the Poisson solve

@@ -62,7 +62,10 @@ def interior_faces(mesh: Mesh):
 
 def estimator(mesh: Mesh, lam, Phi_full, veff_qp):
     """eta^2 per tet for the eigenpairs (lam, Phi_full) (Phi_full: values at
-    every vertex, zero on the boundary) and V_eff at the quadrature points."""
+    every vertex, zero on the boundary) and V_eff at the quadrature points.
+    Written for the P1 space (no Laplacian term in the element residual)."""
+    if getattr(mesh, "order", 1) != 1:
+        raise ValueError("the estimator is written for P1 elements")
     lam = np.asarray(lam, dtype=np.float64)
     Phi_full = np.asarray(Phi_full, dtype=np.float64).reshape(mesh.nv, -1)
     hT = tet_diameters(mesh)

@@ -26,6 +26,8 @@ WQ = np.full(4, 0.25)  # weights relative to |T|
 class Mesh:
     """A tetrahedral mesh with its interior (Dirichlet-free) vertex numbering."""
 
+    order = 1
+
     def __init__(self, xyz, tets, lo, hi):
         self.xyz = np.asarray(xyz, dtype=np.float64)
         self.tets = np.asarray(tets, dtype=np.int64)
@@ -141,8 +143,21 @@ def hat_values(fine_xyz, coarse: Mesh):
     return sp.coo_matrix((bary.ravel(), (rows, cols)), shape=(nf, coarse.nv)).tocsr()
 
 
+def make_mesh(xyz, tets, lo, hi, order=1):
+    """The P1 space (order 1) or the P2 space (order 2, fem2.MeshP2) on a mesh."""
+    if order == 1:
+        return Mesh(xyz, tets, lo, hi)
+    if order == 2:
+        from .fem2 import MeshP2
+        return MeshP2(xyz, tets, lo, hi)
+    raise ValueError("element order must be 1 or 2")
+
+
 def prolongation(fine: Mesh, coarse: Mesh):
-    """Returns (P_full (fine nv x coarse nv), P (fine dof x coarse dof))."""
+    """Returns (P_full (fine nv x coarse nv), P (fine dof x coarse dof)).
+    The coarse space is P1; on a P2 fine space the rows are the fine nodes
+    (vertices and edge midpoints), where the coarse hats' values are again
+    their exact P2 coefficients (a coarse hat is linear on every fine tet)."""
     Pf = hat_values(fine.xyz, coarse)
     P = Pf[fine.interior][:, coarse.interior].tocsr()
     P.eliminate_zeros()

@@ -43,7 +43,7 @@ from scipy.sparse.linalg import splu
 
 from . import hartree as har
 from . import xc as xcmod
-from .fem import Mesh, prolongation
+from .fem import Mesh, make_mesh, prolongation
 from .potentials import v_ext
 
 
@@ -85,7 +85,7 @@ class Problem:
 
     def __init__(self, system):
         self.sys = system
-        self.fine = Mesh(system.xyz, system.tets, system.lo, system.hi)
+        self.fine = make_mesh(system.xyz, system.tets, system.lo, system.hi, getattr(system, "order", 1))
         self.coarse = Mesh(system.cxyz, system.ctets, system.lo, system.hi)
         self.Pfull, self.P = prolongation(self.fine, self.coarse)
         self.Pfull_c = self.Pfull[:, self.coarse.interior].tocsr()   # coarse dof -> all fine vertices

@@ -27,7 +27,7 @@ def scf(mesh: Mesh, system, tol=1e-11, maxit=400, beta=0.5, hist=6, verbose=Fals
     K, M, KIB = mesh.ii(Kf), mesh.ii(mesh.mass()), mesh.ib(Kf)
     vext = v_ext(mesh.qp, system.R, system.Z, system.potential, system.rc, system.omega)
     nonlinear = system.hartree or system.xc != 0
-    rho_in = np.zeros((mesh.nt, 4))
+    rho_in = np.zeros_like(mesh.qw)
     w = np.zeros(mesh.nv)
     X_hist, F_hist = [], []
     ip = lambda a, b: float(np.sum(mesh.qw * a * b))

@@ -380,11 +380,14 @@ def test_augmented_problem_upper_bound_linear():
     assert np.all(res.state.lam >= ev[:2] - 1e-12)
 
 
-def test_algorithm3_pieces_equal_direct_assembly():
+@pytest.mark.parametrize("order", [1, 2])
+def test_algorithm3_pieces_equal_direct_assembly(order):
     """Algorithm 3 step 1 decomposition vs the direct fine assembly of the
     augmented matrices and of the Hartree right-hand side, at arbitrary inner
-    iterates (the expansion keeps 2 theta2 and theta2^2 and the occupations)."""
-    S = tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=True, n_orbitals=2, seed=7)
+    iterates (the expansion keeps 2 theta2 and theta2^2 and the occupations);
+    on P1 and on P2 fine spaces."""
+    S = tiny_system(n_fine=8 if order == 1 else 4, n_coarse=4, box=5.0, nonlinear=True, n_orbitals=2, seed=7,
+                    order=order)
     prob = Problem(S)
     st, _ = initial_state(prob)
     fs = fine_stage(prob, st, Options())
