@@ -33,9 +33,12 @@
  *     the context runs on and passes it to mlc_bind(), together with the HIP
  *     stream all work is enqueued on. The workspace must outlive the context's
  *     use of it. Calls that return host data synchronise that stream.
- *   - DoF numbering seen by callers: the fine (coarse) degrees of freedom are
- *     the vertices of the fine (coarse) mesh that do not lie on the box
- *     boundary, in increasing vertex index. Orbital blocks are row-major
+ *   - Nodes and DoF numbering seen by callers: the nodes of a P1 mesh are its
+ *     vertices; those of a P2 fine mesh (order 2) are its vertices followed by
+ *     one node per edge at the edge's midpoint, edges in increasing
+ *     (lo, hi) vertex-index order. The fine (coarse) degrees of freedom are
+ *     the nodes of the fine (coarse) mesh that do not lie on the box
+ *     boundary, in increasing node index. Orbital blocks are row-major
  *     n_dof x N (orbital index fastest). Internally the library reorders the
  *     fine DoFs for memory locality and undoes it on output.
  *   - One context is used from one host thread at a time.
@@ -72,10 +75,13 @@ enum { MLC_POT_ERF = 0,       /* -sum Z_k erf(|x-R_k|/rc)/|x-R_k|             */
 enum { MLC_XC_NONE = 0, MLC_XC_LDA = 1 /* Slater + Perdew-Zunger 81 */, MLC_XC_XALPHA = 2 };
 
 /* A tetrahedral mesh of the box [box_lo, box_hi] (host arrays, copied by
- * mlc_create). order: polynomial degree of the Lagrange elements; 1 (linear,
- * the space V_h of Section 2) is the one implemented, any other value is
- * rejected with MLC_ERR_ARG. xyz: n_vertices x 3 doubles; tets: n_tets x 4
- * vertex indices. */
+ * mlc_create). order: polynomial degree of the Lagrange elements: 1 (linear,
+ * the space V_h of Section 2) or, for the fine mesh only, 2 (quadratic: the
+ * same construction with P2 polynomials per tet, 10 nodes, integrals by a
+ * degree-5 27-point rule); any other value, or a coarse mesh of order 2, is
+ * MLC_ERR_ARG. The coarse space is P1, a subspace of the fine P1 or P2 space
+ * on nested meshes. xyz: n_vertices x 3 doubles; tets: n_tets x 4 vertex
+ * indices (the library derives the P2 edge nodes itself). */
 typedef struct {
   int32_t order;
   int64_t n_vertices;
@@ -160,10 +166,11 @@ typedef struct {
                            one space V_H + span{u_1..u_N} whose lowest N
                            eigenpairs are the orbitals (needs the N(N+1)/2
                            pair integrals (u_j u_l, psi_k) from the fine
-                           mesh; N <= 64)                                      */
+                           mesh; N <= 64; P1 fine meshes only)                 */
   int32_t estimator;    /* 1: mlc_create builds the fine mesh's face
                            neighbours for mlc_estimate (host time and 20 bytes
-                           of workspace per fine tet); 0 (default): off       */
+                           of workspace per fine tet; P1 fine meshes only);
+                           0 (default): off                                    */
 } mlc_options;
 
 enum { MLC_VARIANT_EIGENPAIRWISE = 0, MLC_VARIANT_JOINT = 1 };
@@ -215,7 +222,8 @@ void mlc_options_default(mlc_options* opt);
 mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys,
                       const mlc_options* opt, mlc_ctx** out);
 
-/* Sizes: fine interior DoFs, coarse interior DoFs, fine vertices, N. */
+/* Sizes: fine interior DoFs, coarse interior DoFs, fine nodes (the length of
+ * every nodal array below: the vertices for P1, vertices and edges for P2), N. */
 mlc_status mlc_sizes(const mlc_ctx* ctx, int64_t* n_dof, int64_t* n_coarse_dof, int64_t* n_vertices,
                      int32_t* n_orbitals);
 
@@ -235,7 +243,7 @@ mlc_status mlc_initial_state(mlc_ctx* ctx, double tol, int32_t maxit, int32_t* i
 
 /* Set (Lambda^l, Phi^l, w^l), the input of the next outer step (Algorithm 1
  * step 4): lambda_host[N] on the host; phi_dev[n_dof x N] (caller DoF order)
- * and w_dev[n_vertices] (nodal Hartree potential, boundary vertices
+ * and w_dev[n_vertices] (nodal Hartree potential, boundary nodes
  * included) in device memory of the bound GPU, owned by the caller and
  * read only during the call. The library copies them into its workspace
  * (reordering Phi on the device) and synchronises the stream. A non-finite
@@ -261,7 +269,7 @@ mlc_status mlc_get_results(mlc_ctx* ctx, double* lambda_host, double* phi_dev, d
  *   MLC_PROBE_U        n_dof x N   u_i after M-normalisation (step 5)
  *   MLC_PROBE_W0       n_dof       zero-boundary Hartree direction (step 6)
  *   MLC_PROBE_G        n_vertices  multipole Dirichlet data (0 inside)
- *   MLC_PROBE_VXC_QP   4 n_tets    V_xc(rho^l) at quadrature points
+ *   MLC_PROBE_VXC_QP   nq n_tets   V_xc(rho^l) at quadrature points (nq = 4 for P1, 27 for P2)
  *   MLC_PROBE_PT_AFIX_U, _PT_MW0_U, _PT_M_U, _PT_K_U   N_H x N   P^T O u_i
  *   MLC_PROBE_UT_AFIX_U, _UT_MW0_U, _UT_M_U, _UT_K_U   N x N     U^T O U
  *   MLC_PROBE_HARTREE_D   N_H + 2  [P^T K w0, w0^T K w0, w0^T l] (l = K_IB g_B)

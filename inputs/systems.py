@@ -113,16 +113,22 @@ def c2_cluster(seed=0):
     return cluster_system(seed, name=f"c2_cluster4_s{seed}")
 
 
-def c3_cluster(seed=0, h=0.101, n_base=12, progress=None):
+def c3_cluster(seed=0, h=None, n_base=12, order=1, progress=None):
     """The 40-atom cluster: positions uniform in [-8,8]^3 with separation
     >= 1.8, Z in {1..4}, rc = 0.5, box [-25,25]^3, N = ceil(sum Z / 2)
-    orbitals (52 for seed 0). The fine mesh is P1, graded by bisection of the
-    n_base^3 Kuhn base until the longest edge <= clip(h + h d, h, base edge):
-    about 2.0e6 vertices at h = 0.101, a P1 mesh with the DoF count of the
-    P2 mesh such a system would be computed on. The coarse mesh is the base
+    orbitals (52 for seed 0). The fine mesh is graded by bisection of the
+    n_base^3 Kuhn base until the longest edge <= clip(h + h d, h, base edge).
+    order 2 (the workload's P2 space): h = 0.199 by default, about 2.8e5
+    vertices and 2.0e6 P2 DoFs. order 1: h = 0.101 by default, about 2.0e6
+    vertices, a P1 mesh with the same DoF count. The coarse mesh is the base
     (11^3 interior vertices at n_base = 12)."""
-    return cluster_system(seed, n_atoms=40, half_width=8.0, d_min=1.8, box=25.0, n_base=n_base, h0=h, kappa=h,
-                          h_min=h, coarse=None, name=f"c3_cluster40_s{seed}", progress=progress)
+    if h is None:
+        h = 0.199 if order == 2 else 0.101
+    S = cluster_system(seed, n_atoms=40, half_width=8.0, d_min=1.8, box=25.0, n_base=n_base, h0=h, kappa=h,
+                       h_min=h, coarse=None, name=f"c3_cluster40_s{seed}" + ("_p2" if order == 2 else ""),
+                       progress=progress)
+    S.order = order
+    return S
 
 
 LIH_R = np.array([[-1.0075, 0.0, 0.0], [2.0075, 0.0, 0.0]])   # Li, H (Section 4, first model)

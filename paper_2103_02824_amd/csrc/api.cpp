@@ -42,24 +42,25 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   Carver w{base};
   const int64_t n = c->n, nt = c->nt, nv = c->nv, nH = c->nH, N = c->N, cnt = c->cnt;
   const int64_t nnz = (int64_t)c->col.size(), nadj = (int64_t)c->adj_tet.size();
-  d->tets = w.take<int32_t>(4 * nt);
+  const int64_t ne = c->ne, nqt = c->nq * nt;
+  d->tets = w.take<int32_t>(ne * nt);
   d->v2d = w.take<int32_t>(nv);
   d->xyz = w.take<double>(3 * nv);
   d->geo = w.take<double>(16 * nt);
-  d->qpx = w.take<double>(12 * nt);
-  d->vext = w.take<double>(4 * nt);
-  d->vxc = w.take<double>(4 * nt);
-  d->exc = w.take<double>(4 * nt);
-  d->veff = w.take<double>(4 * nt);
-  d->rho = w.take<double>(4 * nt);
-  d->fld = w.take<double>(4 * nt);
-  d->fld2 = w.take<double>(4 * nt);
-  d->rhot = w.take<double>(4 * nt);
+  d->qpx = w.take<double>(3 * nqt);
+  if (c->order == 2) d->qtab = w.take<double>(P2_TAB);
+  d->vext = w.take<double>(nqt);
+  d->vxc = w.take<double>(nqt);
+  d->exc = w.take<double>(nqt);
+  d->veff = w.take<double>(nqt);
+  d->rho = w.take<double>(nqt);
+  d->fld = w.take<double>(nqt);
+  d->fld2 = w.take<double>(nqt);
+  d->rhot = w.take<double>(nqt);
   d->rowptr = w.take<int32_t>(n + 1);
   d->col = w.take<int32_t>(nnz);
   d->adj_ptr = w.take<int32_t>(n + 1);
   d->adj_tet = w.take<int32_t>(nadj);
-  d->adj_pos = w.take<int32_t>(4 * nadj);
   d->adj_loc = w.take<int8_t>(nadj);
   d->bverts = w.take<int32_t>((int64_t)c->bverts.size());
   d->valA = w.take<double>(nnz);
@@ -67,9 +68,9 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->valW = w.take<double>(nnz);
   d->valM = w.take<double>(nnz);
   d->valK = w.take<double>(nnz);
-  d->elem = w.take<double>(std::max<int64_t>(2 * (int64_t)c->slot_ptr.back(), 8 * nt));
+  d->elem = w.take<double>(std::max<int64_t>(2 * (int64_t)c->slot_ptr.back(), 2 * ne * nt));
   d->slot_ptr = w.take<int32_t>(nnz + 1);
-  d->slot_of = w.take<int32_t>(16 * nt);
+  d->slot_of = w.take<int32_t>(ne * ne * nt);
   d->diag_slot = w.take<int32_t>(n);
   d->dinvA = w.take<double>(n);
   d->dinvK = w.take<double>(n);
@@ -105,7 +106,7 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->PTw = w.take<double>((int64_t)c->PTw.size());
   d->cgrp_ptr = w.take<int32_t>(cnt + 1);
   d->cgrp_tet = w.take<int32_t>(nt);
-  d->cgrp_dof = w.take<int32_t>(4 * nt);
+  d->cgrp_dof = w.take<int32_t>(ne * nt);
   d->cgeo = w.take<double>(12 * cnt);
   d->cel_ops = w.take<double>(40 * cnt);
   d->cel_orb = w.take<double>(14 * cnt * N);
@@ -115,7 +116,7 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
     d->pair_jl = w.take<int32_t>(2 * npair);
   }
   d->cel_tri = w.take<double>(20 * cnt);
-  d->chat = w.take<double>(17 * nt);
+  d->chat = w.take<double>((4 * c->nq + 1) * nt);
   d->small = w.take<double>(small_len(nH, (int)N));
   d->coarse_in = w.take<double>(nH * N + nH + N + N * N);
   d->occ = w.take<double>(N);
@@ -182,13 +183,18 @@ static hipError_t up(hipStream_t s, T* dst, const std::vector<T>& src) {
 mlc_status upload_and_init(mlc_ctx* c) {
   auto& d = c->d;
   hipStream_t s = c->stream;
-  std::vector<double> qpx(12 * c->nt);
+  // quadrature points: barycentric combinations of each tet's vertices (its first 4 nodes)
+  const int nq = c->nq, ne = c->ne;
+  std::vector<double> qpx(3 * nq * c->nt);
   for (int64_t t = 0; t < c->nt; ++t)
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < nq; ++q)
       for (int k = 0; k < 3; ++k) {
         double v = 0.0;
-        for (int j = 0; j < 4; ++j) v += (q == j ? QA : QB) * c->xyz[3 * (int64_t)c->tets[4 * t + j] + k];
-        qpx[12 * t + 3 * q + k] = v;
+        for (int j = 0; j < 4; ++j) {
+          const double lq = c->order == 2 ? c->qtab[P2_T_L + 4 * q + j] : (q == j ? QA : QB);
+          v += lq * c->xyz[3 * (int64_t)c->tets[ne * t + j] + k];
+        }
+        qpx[3 * (nq * t + q) + k] = v;
       }
   std::vector<double> RZ(4 * std::max(1, c->n_nuclei), 0.0);
   for (int k = 0; k < c->n_nuclei; ++k) {
@@ -200,11 +206,11 @@ mlc_status upload_and_init(mlc_ctx* c) {
   HIPCHK(up(s, d.xyz, c->xyz));
   HIPCHK(up(s, d.geo, c->geo));
   HIPCHK(up(s, d.qpx, qpx));
+  if (d.qtab) HIPCHK(up(s, d.qtab, c->qtab));
   HIPCHK(up(s, d.rowptr, c->rowptr));
   HIPCHK(up(s, d.col, c->col));
   HIPCHK(up(s, d.adj_ptr, c->adj_ptr));
   HIPCHK(up(s, d.adj_tet, c->adj_tet));
-  HIPCHK(up(s, d.adj_pos, c->adj_pos));
   HIPCHK(up(s, d.adj_loc, c->adj_loc));
   HIPCHK(up(s, d.bverts, c->bverts));
   HIPCHK(up(s, d.slot_ptr, c->slot_ptr));
@@ -247,17 +253,29 @@ mlc_status upload_and_init(mlc_ctx* c) {
   HIPCHK(hipMemsetAsync(d.small, 0, sizeof(double) * small_len(c->nH, c->N), s));
   HIPCHK(hipMemsetAsync(d.w0, 0, sizeof(double) * c->n, s));
   // fixed quantities: V_ext at the quadrature points, K, M, coarse trilinear tensor
-  launch_vext(s, c->nt, d.qpx, d.RZ, c->n_nuclei, c->potential, c->rc, c->omega, d.vext);
+  launch_vext(s, nq * c->nt, d.qpx, d.RZ, c->n_nuclei, c->potential, c->rc, c->omega, d.vext);
   const int64_t nnz = (int64_t)c->col.size();
   const int64_t ns = c->slot_ptr.back();
-  launch_assemble2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_of, ns, d.diag_slot, d.elem, 1.0, nullptr, 0.0,
-                   d.valK, d.dinvK, 0.0, nullptr, d.valM);
-  launch_assemble2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_of, ns, d.diag_slot, d.elem, 0.0, nullptr, 1.0,
-                   d.valM, nullptr, 0.0, nullptr, nullptr);
+  if (c->order == 2) {
+    launch_assemble2_p2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_of, d.diag_slot, d.elem, 1.0, nullptr, 0.0,
+                        d.valK, d.dinvK, 0.0, nullptr, d.valM, d.qtab);
+    launch_assemble2_p2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_of, d.diag_slot, d.elem, 0.0, nullptr, 1.0,
+                        d.valM, nullptr, 0.0, nullptr, nullptr, d.qtab);
+  } else {
+    launch_assemble2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_of, ns, d.diag_slot, d.elem, 1.0, nullptr, 0.0,
+                     d.valK, d.dinvK, 0.0, nullptr, d.valM);
+    launch_assemble2(s, c->nt, c->n, nnz, d.geo, d.slot_ptr, d.slot_of, ns, d.diag_slot, d.elem, 0.0, nullptr, 1.0,
+                     d.valM, nullptr, 0.0, nullptr, nullptr);
+  }
   launch_gershgorin(s, c->n, d.rowptr, d.valK, d.dinvK, d.red, d.lmax + 1);
   if (d.valK32) launch_to_f32(s, nnz, d.valK, d.valK32);
-  launch_coarse_tri(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.cel_tri);
-  launch_coarse_hats(s, c->cnt, c->nt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.chat);
+  if (c->order == 2) {
+    launch_coarse_tri_p2(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.qtab, d.cel_tri);
+    launch_coarse_hats_p2(s, c->cnt, c->nt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.qtab, d.chat);
+  } else {
+    launch_coarse_tri(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.cel_tri);
+    launch_coarse_hats(s, c->cnt, c->nt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.chat);
+  }
   if (d.KHinv) {
     // coarse stiffness K_H = P^T K P of the nested P1 spaces (element by element: the coarse hat
     // gradients are constant on a coarse tet), its Cholesky factor and explicit inverse
@@ -332,9 +350,9 @@ mlc_status probe(mlc_ctx* c, int which, double* out, int64_t count) {
       HIPCHK(hipStreamSynchronize(s));
       return MLC_OK;
     case MLC_PROBE_VXC_QP: {
-      if ((st = need(4 * nt))) return st;
+      if ((st = need(c->nq * nt))) return st;
       // library tet order -> caller tet order is not tracked; return per library tet
-      HIPCHK(hipMemcpyAsync(out, d.vxc, sizeof(double) * 4 * nt, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(out, d.vxc, sizeof(double) * c->nq * nt, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       return MLC_OK;
     }
@@ -494,7 +512,7 @@ mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_sy
   for (int k = 0; k < 3; ++k)
     if (!(sys->box_hi[k] > sys->box_lo[k]) || !std::isfinite(sys->box_lo[k]) || !std::isfinite(sys->box_hi[k]))
       return MLC_ERR_ARG;
-  if (fine->order != 1 || coarse->order != 1) return MLC_ERR_ARG;
+  if ((fine->order != 1 && fine->order != 2) || coarse->order != 1) return MLC_ERR_ARG;
   if (sys->potential == MLC_POT_ERF && !(sys->rc > 0)) return MLC_ERR_ARG;
   for (int i = 0; i < sys->n_orbitals; ++i)
     if (!(sys->occupations[i] >= 0.0) || !std::isfinite(sys->occupations[i])) return MLC_ERR_ARG;
@@ -517,6 +535,7 @@ mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_sy
       (c->opt.variant != MLC_VARIANT_EIGENPAIRWISE && c->opt.variant != MLC_VARIANT_JOINT) ||
       (c->opt.variant == MLC_VARIANT_JOINT && sys->n_orbitals > 64) ||
       (c->opt.estimator != 0 && c->opt.estimator != 1) ||
+      (fine->order == 2 && (c->opt.estimator != 0 || c->opt.variant == MLC_VARIANT_JOINT)) ||
       !(c->opt.inner_mix_beta > 0.0 && c->opt.inner_mix_beta <= 1.0)) {
     delete c;
     return MLC_ERR_ARG;

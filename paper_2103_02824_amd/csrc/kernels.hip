@@ -15,6 +15,7 @@
 #include <cstdint>
 
 #include "mlc_internal.h"
+#include "pointwise.h"
 
 namespace mlc {
 
@@ -39,73 +40,11 @@ __device__ __forceinline__ void block_reduce_cols(double* sd, int R, int N) {
 }
 
 // ---------------------------------------------------------------------------
-// Exchange-correlation: LDA = Slater exchange + Perdew-Zunger 1981 correlation
-// with the constants printed in Section 4; V_xc = eps + rho d eps/d rho in the
-// closed forms eps_x * 4/3 and, for correlation,
-//   r_s >= 1: v_c = eps_c (1 + 7/6 b1 sqrt(rs) + 4/3 b2 rs) / (1 + b1 sqrt(rs) + b2 rs)
-//   r_s <  1: v_c = A ln rs + (B - A/3) + (2/3) C rs ln rs + (2D - C)/3 rs.
-// X-alpha: v = -3/2 alpha (3 rho / pi)^(1/3), eps = 3/4 v.
-__device__ __forceinline__ void xc_point(int kind, double xalpha, double rho, double* eps, double* v) {
-  if (kind == 0 || !(rho > 1e-30)) {
-    *eps = 0.0;
-    *v = 0.0;
-    return;
-  }
-  const double pi = 3.14159265358979323846;
-  double c13 = cbrt(rho);
-  if (kind == 2) {
-    double vv = -1.5 * xalpha * cbrt(3.0 / pi) * c13;
-    *v = vv;
-    *eps = 0.75 * vv;
-    return;
-  }
-  double ex = -0.75 * cbrt(3.0 / pi) * c13;
-  double vx = ex * (4.0 / 3.0);
-  double rs = cbrt(3.0 / (4.0 * pi * rho));
-  double ec, vc;
-  if (rs >= 1.0) {
-    const double g = -0.1423, b1 = 1.0529, b2 = 0.3334;
-    double sq = sqrt(rs);
-    double den = 1.0 + b1 * sq + b2 * rs;
-    ec = g / den;
-    vc = ec * (1.0 + (7.0 / 6.0) * b1 * sq + (4.0 / 3.0) * b2 * rs) / den;
-  } else {
-    const double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
-    double lr = log(rs);
-    ec = A * lr + B + C * rs * lr + D * rs;
-    vc = A * lr + (B - A / 3.0) + (2.0 / 3.0) * C * rs * lr + ((2.0 * D - C) / 3.0) * rs;
-  }
-  *eps = ex + ec;
-  *v = vx + vc;
-}
-
-// ---------------------------------------------------------------------------
-// V_ext at a point: -sum Z erf(r/rc)/r (its r -> 0 limit -2Z/(sqrt(pi) rc)),
-// the bare -sum Z/r, or the harmonic 1/2 omega^2 |x|^2.
-__device__ __forceinline__ double vext_point(double x, double y, double z, int n_nuclei, const double* __restrict__ RZ,
-                                             int kind, double rc, double omega) {
-  if (kind == 2) return 0.5 * omega * omega * (x * x + y * y + z * z);
-  double v = 0.0;
-  for (int k = 0; k < n_nuclei; ++k) {
-    double dx = x - RZ[4 * k], dy = y - RZ[4 * k + 1], dz = z - RZ[4 * k + 2], Zk = RZ[4 * k + 3];
-    double r = sqrt(dx * dx + dy * dy + dz * dz);
-    if (kind == 1) {
-      v -= Zk / r;
-    } else {
-      if (r < 1e-12)
-        v -= Zk * 1.12837916709551257390 / rc;
-      else
-        v -= Zk * erf(r / rc) / r;
-    }
-  }
-  return v;
-}
-
-__global__ void __launch_bounds__(TPB) k_vext(int64_t nt, const double* __restrict__ qpx, int n_nuclei,
+__global__ void __launch_bounds__(TPB) k_vext(int64_t npts, const double* __restrict__ qpx, int n_nuclei,
                                               const double* __restrict__ RZ, int kind, double rc,
                                               double omega, double* __restrict__ vext) {
   int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (i >= nt * 4) return;
+  if (i >= npts) return;
   vext[i] = vext_point(qpx[3 * i], qpx[3 * i + 1], qpx[3 * i + 2], n_nuclei, RZ, kind, rc, omega);
 }
 
@@ -406,7 +345,8 @@ __global__ void __launch_bounds__(TPB) k_load_elem(int64_t nt, const int32_t* __
   }
 }
 
-__global__ void __launch_bounds__(TPB) k_load_gather(int64_t n, const int32_t* __restrict__ adj_ptr,
+// (ne: nodes per tet; the element pass wrote 2 ne values per tet)
+__global__ void __launch_bounds__(TPB) k_load_gather(int64_t n, int ne, const int32_t* __restrict__ adj_ptr,
                                                      const int32_t* __restrict__ adj_tet,
                                                      const int8_t* __restrict__ adj_loc, const double* __restrict__ e,
                                                      double* __restrict__ b, double* __restrict__ lvec) {
@@ -414,9 +354,9 @@ __global__ void __launch_bounds__(TPB) k_load_gather(int64_t n, const int32_t* _
   if (a >= n) return;
   double load = 0.0, lift = 0.0;
   for (int k = adj_ptr[a]; k < adj_ptr[a + 1]; ++k) {
-    int64_t o = 8 * (int64_t)adj_tet[k] + adj_loc[k];
+    int64_t o = 2 * ne * (int64_t)adj_tet[k] + adj_loc[k];
     load += e[o];
-    lift += e[o + 4];
+    lift += e[o + ne];
   }
   b[a] = load - lift;
   if (lvec) lvec[a] = lift;
@@ -706,36 +646,6 @@ __global__ void __launch_bounds__(TPB) k_gram_wide(int64_t n, int N, const doubl
 // psi_j = sum_a Bc[a][j] phi_a with Bc the coarse barycentrics of the fine
 // vertices). Results are 4x4 symmetric blocks in coarse local numbering,
 // stored as the 10 entries (j<=k) in order (0,0)(0,1)(0,2)(0,3)(1,1)...(3,3).
-__device__ __forceinline__ void coarse_bary(const double* __restrict__ cg, const double* __restrict__ xyz, int v,
-                                            double b[4]) {
-  double dx = xyz[3 * v] - cg[0], dy = xyz[3 * v + 1] - cg[1], dz = xyz[3 * v + 2] - cg[2];
-  b[1] = cg[3] * dx + cg[4] * dy + cg[5] * dz;
-  b[2] = cg[6] * dx + cg[7] * dy + cg[8] * dz;
-  b[3] = cg[9] * dx + cg[10] * dy + cg[11] * dz;
-  b[0] = 1.0 - b[1] - b[2] - b[3];
-}
-
-// Block-wide ordered sum of v over the 256 threads; result returned to all.
-// Block sums of K values per thread (TPB = 256, four waves): every value's
-// wave sum, then one barrier; thread k < K returns the block sum of value k
-// (the four wave sums added as (w0 + w1) + (w2 + w3)), the others 0.
-// ws: 4 K doubles.
-template <int K>
-__device__ __forceinline__ double block_sums(const double (&v)[K], double* ws) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double x = v[k];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    if (lane == 0) ws[wid * K + k] = x;
-  }
-  __syncthreads();
-  const int t = threadIdx.x;
-  const double r = t < K ? (ws[t] + ws[K + t]) + (ws[2 * K + t] + ws[3 * K + t]) : 0.0;
-  __syncthreads();  // ws may be reused at once
-  return r;
-}
-
 // Operators: [A_fix = 1/2 K + M_{fA}] [M_{fW}] [M] [K] -> 40 values per coarse
 // tet. One workgroup per coarse tet; threads stride over its fine tets.
 // Per fine tet, in coarse-group order e (fixed per mesh): the four coarse
@@ -1462,9 +1372,9 @@ int elem_blocks(int64_t n, int N) { return (int)((n + spmm_rows_per_block(N) - 1
 int qp_blocks(int64_t nt) { return (int)nb(nt); }
 int gram_blocks(int64_t n) { return (int)((n + GRAM_ROWS - 1) / GRAM_ROWS); }
 
-void launch_vext(hipStream_t s, int64_t nt, const double* qpx, const double* RZ, int n_nuclei, int kind,
+void launch_vext(hipStream_t s, int64_t npts, const double* qpx, const double* RZ, int n_nuclei, int kind,
                  double rc, double omega, double* vext) {
-  hipLaunchKernelGGL(k_vext, dim3(nb(nt * 4)), dim3(TPB), 0, s, nt, qpx, n_nuclei, RZ, kind, rc, omega, vext);
+  hipLaunchKernelGGL(k_vext, dim3(nb(npts)), dim3(TPB), 0, s, npts, qpx, n_nuclei, RZ, kind, rc, omega, vext);
 }
 void launch_qp_density(hipStream_t s, int64_t nt, const int32_t* tets, const int32_t* v2d, const double* X, int N,
                        const double* occ, double* rho_out) {
@@ -1508,7 +1418,21 @@ void launch_load(hipStream_t s, int64_t n, int64_t nt, const int32_t* adj_ptr, c
                  const int8_t* adj_loc, const int32_t* tets, const double* geo, const double* f_qp, double scale,
                  const double* gnod, const int32_t* v2d, double* scratch, double* b, double* lvec) {
   hipLaunchKernelGGL(k_load_elem, dim3(nb(nt)), dim3(TPB), 0, s, nt, tets, geo, f_qp, scale, gnod, v2d, scratch);
-  hipLaunchKernelGGL(k_load_gather, dim3(nb(n)), dim3(TPB), 0, s, n, adj_ptr, adj_tet, adj_loc, scratch, b, lvec);
+  launch_load_gather(s, n, 4, adj_ptr, adj_tet, adj_loc, scratch, b, lvec);
+}
+void launch_load_gather(hipStream_t s, int64_t n, int ne, const int32_t* adj_ptr, const int32_t* adj_tet,
+                        const int8_t* adj_loc, const double* scratch, double* b, double* lvec) {
+  hipLaunchKernelGGL(k_load_gather, dim3(nb(n)), dim3(TPB), 0, s, n, ne, adj_ptr, adj_tet, adj_loc, scratch, b, lvec);
+}
+void launch_slot_sum(hipStream_t s, int64_t nnz, const int32_t* slot_ptr, const double* esl, double* val1,
+                     double* val2) {
+  if (val2)
+    hipLaunchKernelGGL(k_slot_sum<true>, dim3(nb(nnz)), dim3(TPB), 0, s, nnz, slot_ptr, esl, val1, val2);
+  else
+    hipLaunchKernelGGL(k_slot_sum<false>, dim3(nb(nnz)), dim3(TPB), 0, s, nnz, slot_ptr, esl, val1, nullptr);
+}
+void launch_diag_inv(hipStream_t s, int64_t n, const int32_t* diag_slot, const double* val, double* dinv) {
+  hipLaunchKernelGGL(k_diag_inv, dim3(nb(n)), dim3(TPB), 0, s, n, diag_slot, val, dinv);
 }
 void launch_scale_cols_to(hipStream_t s, int64_t n, int N, const double* X, const double* sc, double* Y) {
   hipLaunchKernelGGL(k_scale_cols_to, dim3(nb(n * N)), dim3(TPB), 0, s, n * N, N, X, sc, Y);

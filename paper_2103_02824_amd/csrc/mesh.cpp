@@ -1,4 +1,5 @@
-// Host-side mesh preparation (once per mesh pair): interior DoF numbering,
+// Host-side mesh preparation (once per mesh pair): the fine nodes (P1: the
+// vertices; P2: the vertices and edge midpoints), interior DoF numbering,
 // locality ordering, element geometry, CSR pattern, row adjacency for the
 // row-wise assembly kernel, the prolongation P (coarse hat functions at the
 // fine vertices: the spaces are nested, Section 3.2) and the grouping of fine
@@ -153,22 +154,60 @@ std::vector<char> boundary_flags(const std::vector<double>& xyz, const double lo
 
 mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) {
   // ---- copy and validate ------------------------------------------------------
-  c->nv = fine->n_vertices;
+  c->order = fine->order;
+  c->ne = c->order == 2 ? P2_NE : 4;
+  c->nq = c->order == 2 ? P2_NQ : 4;
+  const int NEL = c->ne;
+  c->nvert = fine->n_vertices;
   c->nt = fine->n_tets;
   c->cnv = coarse->n_vertices;
   c->cnt = coarse->n_tets;
-  if (c->nv < 4 || c->nt < 1 || c->cnv < 4 || c->cnt < 1) return fail(c, MLC_ERR_MESH, "empty mesh");
-  if (c->nv >= (1LL << 31) || c->nt * 4 >= (1LL << 31)) return fail(c, MLC_ERR_MESH, "mesh too large for int32 indices");
-  c->xyz.assign(fine->xyz, fine->xyz + 3 * c->nv);
+  if (c->nvert < 4 || c->nt < 1 || c->cnv < 4 || c->cnt < 1) return fail(c, MLC_ERR_MESH, "empty mesh");
+  if (c->nvert >= (1LL << 31) || c->nt * NEL * NEL >= (1LL << 31))
+    return fail(c, MLC_ERR_MESH, "mesh too large for int32 indices");
+  c->xyz.assign(fine->xyz, fine->xyz + 3 * c->nvert);
   c->cxyz.assign(coarse->xyz, coarse->xyz + 3 * c->cnv);
   std::vector<int32_t> tin(fine->tets, fine->tets + 4 * c->nt);
   c->ctets.assign(coarse->tets, coarse->tets + 4 * c->cnt);
   for (int64_t i = 0; i < 4 * c->nt; ++i)
-    if (tin[i] < 0 || tin[i] >= c->nv) return fail(c, MLC_ERR_MESH, "fine tet index out of range");
+    if (tin[i] < 0 || tin[i] >= c->nvert) return fail(c, MLC_ERR_MESH, "fine tet index out of range");
   for (int64_t i = 0; i < 4 * c->cnt; ++i)
     if (c->ctets[i] < 0 || c->ctets[i] >= c->cnv) return fail(c, MLC_ERR_MESH, "coarse tet index out of range");
-  for (int64_t i = 0; i < 3 * c->nv; ++i)
+  for (int64_t i = 0; i < 3 * c->nvert; ++i)
     if (!std::isfinite(c->xyz[i])) return fail(c, MLC_ERR_MESH, "non-finite fine coordinate");
+
+  // ---- fine nodes: the vertices, and for P2 one node per edge at its midpoint,
+  // edges in increasing (lo, hi) vertex order; element node lists in caller tet order
+  std::vector<int32_t> tel;
+  if (c->order == 2) {
+    static const int EDGE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    const uint64_t NV = (uint64_t)c->nvert;
+    std::vector<uint64_t> ek(6 * c->nt);
+    for (int64_t t = 0; t < c->nt; ++t)
+      for (int e = 0; e < 6; ++e) {
+        const uint64_t a = (uint64_t)tin[4 * t + EDGE[e][0]], b = (uint64_t)tin[4 * t + EDGE[e][1]];
+        ek[6 * t + e] = std::min(a, b) * NV + std::max(a, b);
+      }
+    std::vector<uint64_t> edges(ek);
+    std::sort(edges.begin(), edges.end());
+    edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+    if (c->nvert + (int64_t)edges.size() >= (1LL << 31)) return fail(c, MLC_ERR_MESH, "mesh too large for int32 indices");
+    for (uint64_t k : edges) {
+      const int64_t a = (int64_t)(k / NV), b = (int64_t)(k % NV);
+      for (int x = 0; x < 3; ++x) c->xyz.push_back(0.5 * (c->xyz[3 * a + x] + c->xyz[3 * b + x]));
+    }
+    tel.resize(P2_NE * c->nt);
+    for (int64_t t = 0; t < c->nt; ++t) {
+      for (int a = 0; a < 4; ++a) tel[P2_NE * t + a] = tin[4 * t + a];
+      for (int e = 0; e < 6; ++e)
+        tel[P2_NE * t + 4 + e] =
+            (int32_t)(c->nvert + (std::lower_bound(edges.begin(), edges.end(), ek[6 * t + e]) - edges.begin()));
+    }
+    p2_tables(c->qtab);
+  } else {
+    tel = tin;
+  }
+  c->nv = (int64_t)c->xyz.size() / 3;
 
   // ---- fine tets: locality order by Morton code of the centroid -------------
   std::vector<uint64_t> key(c->nt);
@@ -181,10 +220,10 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
   std::vector<int64_t> tord(c->nt);
   std::iota(tord.begin(), tord.end(), 0);
   if (c->opt.reorder) std::stable_sort(tord.begin(), tord.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
-  c->tets.resize(4 * c->nt);
+  c->tets.resize(NEL * c->nt);
   for (int64_t t = 0; t < c->nt; ++t)
-    for (int a = 0; a < 4; ++a) c->tets[4 * t + a] = tin[4 * tord[t] + a];
-  if (c->opt.estimator) {
+    for (int a = 0; a < NEL; ++a) c->tets[NEL * t + a] = tel[NEL * tord[t] + a];
+  if (c->opt.estimator && c->order == 1) {
     // the caller's tet order, and for each face (opposite vertex a) the tet
     // on its other side: faces sorted by their vertex triple, equal triples
     // adjacent
@@ -227,7 +266,7 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
   c->geo.assign(16 * c->nt, 0.0);
   for (int64_t t = 0; t < c->nt; ++t) {
     const double* x[4];
-    for (int a = 0; a < 4; ++a) x[a] = &c->xyz[3 * (int64_t)c->tets[4 * t + a]];
+    for (int a = 0; a < 4; ++a) x[a] = &c->xyz[3 * (int64_t)c->tets[NEL * t + a]];
     double Ji[9];
     double det = tet_inverse(x[0], x[1], x[2], x[3], Ji);
     double vol = std::fabs(det) / 6.0;
@@ -249,7 +288,7 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
     if (!on[v]) interior.push_back((int32_t)v);
     else c->bverts.push_back((int32_t)v);
   c->n = (int64_t)interior.size();
-  if (c->n == 0) return fail(c, MLC_ERR_MESH, "fine mesh has no interior vertex");
+  if (c->n == 0) return fail(c, MLC_ERR_MESH, "fine mesh has no interior node");
   std::vector<int64_t> dord(c->n);
   std::iota(dord.begin(), dord.end(), 0);
   if (c->opt.reorder) {
@@ -267,29 +306,28 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
     c->dof_user[d] = (int32_t)dord[d];
   }
 
-  // ---- vertex -> tets, CSR pattern, assembly adjacency ---------------------------
-  std::vector<int32_t> vt_ptr(c->nv + 1, 0), vt(4 * c->nt);
-  for (int64_t i = 0; i < 4 * c->nt; ++i) vt_ptr[c->tets[i] + 1]++;
+  // ---- node -> tets, CSR pattern, assembly adjacency ------------------------------
+  std::vector<int32_t> vt_ptr(c->nv + 1, 0), vt(NEL * c->nt);
+  for (int64_t i = 0; i < NEL * c->nt; ++i) vt_ptr[c->tets[i] + 1]++;
   for (int64_t v = 0; v < c->nv; ++v) vt_ptr[v + 1] += vt_ptr[v];
   {
     std::vector<int32_t> fill(vt_ptr.begin(), vt_ptr.end() - 1);
     for (int64_t t = 0; t < c->nt; ++t)
-      for (int a = 0; a < 4; ++a) vt[fill[c->tets[4 * t + a]]++] = (int32_t)t;
+      for (int a = 0; a < NEL; ++a) vt[fill[c->tets[NEL * t + a]]++] = (int32_t)t;
   }
   c->rowptr.assign(c->n + 1, 0);
   c->col.clear();
   c->adj_ptr.assign(c->n + 1, 0);
   c->adj_tet.clear();
   c->adj_loc.clear();
-  c->adj_pos.clear();
   std::vector<int32_t> nbr;
   for (int64_t d = 0; d < c->n; ++d) {
     int32_t v = c->d2v[d];
     nbr.clear();
     for (int32_t e = vt_ptr[v]; e < vt_ptr[v + 1]; ++e) {
       int64_t t = vt[e];
-      for (int a = 0; a < 4; ++a) {
-        int32_t dd = c->v2d[c->tets[4 * t + a]];
+      for (int a = 0; a < NEL; ++a) {
+        int32_t dd = c->v2d[c->tets[NEL * t + a]];
         if (dd >= 0) nbr.push_back(dd);
       }
     }
@@ -300,31 +338,24 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
     for (int32_t e = vt_ptr[v]; e < vt_ptr[v + 1]; ++e) {
       int64_t t = vt[e];
       int la = -1;
-      for (int a = 0; a < 4; ++a)
-        if (c->tets[4 * t + a] == v) la = a;
+      for (int a = 0; a < NEL; ++a)
+        if (c->tets[NEL * t + a] == v) la = a;
       c->adj_tet.push_back((int32_t)t);
       c->adj_loc.push_back((int8_t)la);
-      for (int b = 0; b < 4; ++b) {
-        int32_t dd = c->v2d[c->tets[4 * t + b]];
-        int32_t pos = -1;
-        if (dd >= 0) pos = (int32_t)(std::lower_bound(nbr.begin(), nbr.end(), dd) - nbr.begin());
-        c->adj_pos.push_back(pos);
-      }
     }
     c->adj_ptr[d + 1] = (int32_t)c->adj_tet.size();
   }
   if ((int64_t)c->col.size() >= (1LL << 31)) return fail(c, MLC_ERR_MESH, "too many nonzeros");
-  if (c->nt * 16 >= (1LL << 31)) return fail(c, MLC_ERR_MESH, "too many tets for the slot list");
   // For every CSR slot (a, b): the element entries (tet t, local pair) that
-  // add into it, in increasing tet order; slot_of[16 t + 4 a + b] is the
+  // add into it, in increasing tet order; slot_of[ne^2 t + ne a + b] is the
   // position of entry (a, b) of tet t in that order (-1 when a or b is a
-  // boundary vertex). Assembly writes every element entry to its position and
+  // boundary node). Assembly writes every element entry to its position and
   // then sums each slot's contiguous run, in this fixed order.
   {
     const int64_t nnz = (int64_t)c->col.size();
     std::vector<int32_t> cnt(nnz + 1, 0);
     c->diag_slot.assign(c->n, -1);
-    c->slot_of.assign(16 * c->nt, -1);
+    c->slot_of.assign((int64_t)NEL * NEL * c->nt, -1);
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1) {
         c->slot_ptr.assign(nnz + 1, 0);
@@ -335,16 +366,16 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
         std::fill(cnt.begin(), cnt.end(), 0);
       }
       for (int64_t t = 0; t < c->nt; ++t) {
-        int32_t dd[4];
-        for (int a = 0; a < 4; ++a) dd[a] = c->v2d[c->tets[4 * t + a]];
-        for (int a = 0; a < 4; ++a) {
+        int32_t dd[P2_NE];
+        for (int a = 0; a < NEL; ++a) dd[a] = c->v2d[c->tets[NEL * t + a]];
+        for (int a = 0; a < NEL; ++a) {
           if (dd[a] < 0) continue;
           const int32_t* rb = &c->col[c->rowptr[dd[a]]];
           const int32_t* re = &c->col[c->rowptr[dd[a] + 1]];
-          for (int b = 0; b < 4; ++b) {
+          for (int b = 0; b < NEL; ++b) {
             if (dd[b] < 0) continue;
             int64_t slot = c->rowptr[dd[a]] + (std::lower_bound(rb, re, dd[b]) - rb);
-            if (pass == 1) c->slot_of[16 * t + 4 * a + b] = c->slot_ptr[slot] + cnt[slot];
+            if (pass == 1) c->slot_of[(int64_t)NEL * NEL * t + NEL * a + b] = c->slot_ptr[slot] + cnt[slot];
             cnt[slot]++;
             if (a == b) c->diag_slot[dd[a]] = (int32_t)slot;
           }
@@ -386,7 +417,7 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
   for (int64_t v = 0; v < c->nv; ++v) {
     double b[4], bm;
     int64_t t = loc.find(c, &c->xyz[3 * v], b, &bm);
-    if (t < 0 || bm < -1e-9) return fail(c, MLC_ERR_NOT_NESTED, "fine vertex outside the coarse mesh");
+    if (t < 0 || bm < -1e-9) return fail(c, MLC_ERR_NOT_NESTED, "fine node outside the coarse mesh");
     for (int a = 0; a < 4; ++a) {
       double w = std::fabs(b[a]) < 1e-13 ? 0.0 : b[a];
       c->Pfull_k[4 * v + a] = w != 0.0 ? c->ctets[4 * t + a] : -1;
@@ -466,14 +497,14 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
   for (int64_t t = 0; t < c->nt; ++t) {
     double p[3] = {0, 0, 0};
     for (int a = 0; a < 4; ++a)
-      for (int k = 0; k < 3; ++k) p[k] += 0.25 * c->xyz[3 * (int64_t)c->tets[4 * t + a] + k];
+      for (int k = 0; k < 3; ++k) p[k] += 0.25 * c->xyz[3 * (int64_t)c->tets[NEL * t + a] + k];
     double b[4], bm;
     int64_t C = loc.find(c, p, b, &bm);
     if (C < 0 || bm < -1e-9) return fail(c, MLC_ERR_NOT_NESTED, "fine tet outside the coarse mesh");
     // every vertex of the fine tet must lie in the parent (nested refinement)
     const double* g = &c->cgeo[12 * C];
     for (int a = 0; a < 4; ++a) {
-      const double* x = &c->xyz[3 * (int64_t)c->tets[4 * t + a]];
+      const double* x = &c->xyz[3 * (int64_t)c->tets[NEL * t + a]];
       double dx = x[0] - g[0], dy = x[1] - g[1], dz = x[2] - g[2];
       double l1 = g[3] * dx + g[4] * dy + g[5] * dz, l2 = g[6] * dx + g[7] * dy + g[8] * dz;
       double l3 = g[9] * dx + g[10] * dy + g[11] * dz;
@@ -490,10 +521,10 @@ mlc_status build_mesh(mlc_ctx* c, const mlc_mesh* fine, const mlc_mesh* coarse) 
     std::vector<int32_t> fill(c->cgrp_ptr.begin(), c->cgrp_ptr.end() - 1);
     for (int64_t t = 0; t < c->nt; ++t) c->cgrp_tet[fill[c->parent[t]]++] = (int32_t)t;
   }
-  // the interior DoFs of every fine tet's vertices in coarse-group order (-1: boundary)
-  c->cgrp_dof.assign(4 * c->nt, -1);
+  // the interior DoFs of every fine tet's nodes in coarse-group order (-1: boundary)
+  c->cgrp_dof.assign((int64_t)NEL * c->nt, -1);
   for (int64_t e = 0; e < c->nt; ++e)
-    for (int a = 0; a < 4; ++a) c->cgrp_dof[4 * e + a] = c->v2d[c->tets[4 * (int64_t)c->cgrp_tet[e] + a]];
+    for (int a = 0; a < NEL; ++a) c->cgrp_dof[NEL * e + a] = c->v2d[c->tets[NEL * (int64_t)c->cgrp_tet[e] + a]];
   return MLC_OK;
 }
 

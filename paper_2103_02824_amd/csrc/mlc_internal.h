@@ -10,6 +10,7 @@
 
 #include "../../include/mlc.h"
 #include "chunks.h"
+#include "p2.h"
 
 namespace mlc {
 
@@ -21,11 +22,12 @@ constexpr double QB = 0.13819660112501051518;  // (5 - sqrt 5) / 20
 // Device sub-buffers carved out of the caller's workspace.
 struct Dev {
   // fine mesh (library orders)
-  int32_t* tets = nullptr;      // nt x 4 fine vertex ids
+  int32_t* tets = nullptr;      // nt x ne fine node ids (ne = 4 for P1, 10 for P2)
   int32_t* v2d = nullptr;       // nv: vertex -> dof or -1
   double* xyz = nullptr;        // nv x 3
   double* geo = nullptr;        // nt x 16: vol, grad lambda_0..3 (12), pad
-  double* qpx = nullptr;        // nt x 4 x 3 quadrature point coordinates
+  double* qpx = nullptr;        // nt x nq x 3 quadrature point coordinates (fields below: nt x nq)
+  double* qtab = nullptr;       // P2 reference tables (p2.h), order 2 only
   double* vext = nullptr;       // nt x 4
   double* vxc = nullptr;        // nt x 4   V_xc(rho^l)
   double* exc = nullptr;        // nt x 4
@@ -38,7 +40,6 @@ struct Dev {
   int32_t* col = nullptr;       // nnz
   int32_t* adj_ptr = nullptr;   // n + 1
   int32_t* adj_tet = nullptr;   // nadj
-  int32_t* adj_pos = nullptr;   // nadj x 4
   int8_t* adj_loc = nullptr;    // nadj
   int32_t* bverts = nullptr;    // boundary vertex ids
   // operators on the interior CSR pattern
@@ -144,9 +145,12 @@ struct Options {
 
 struct mlc_ctx {
   // ---- inputs -------------------------------------------------------------
-  int64_t nv = 0, nt = 0, cnv = 0, cnt = 0;
-  std::vector<double> xyz, cxyz;        // library vertex order (= caller order)
-  std::vector<int32_t> tets;            // library tet order (Morton by centroid)
+  int64_t nv = 0, nt = 0, cnv = 0, cnt = 0;   // nv: fine nodes (P1: the vertices)
+  int32_t order = 1, ne = 4, nq = 4;    // element order, nodes and quadrature points per fine tet
+  int64_t nvert = 0;                    // fine vertices (the first nvert nodes)
+  std::vector<double> qtab;             // P2 reference tables (order 2)
+  std::vector<double> xyz, cxyz;        // fine nodes in caller order (vertices, then P2 edge midpoints)
+  std::vector<int32_t> tets;            // nt x ne node ids, library tet order (Morton by centroid)
   std::vector<int32_t> ctets;
   int32_t n_nuclei = 0;
   std::vector<double> R, Z, occ;
@@ -160,7 +164,7 @@ struct mlc_ctx {
   std::vector<int32_t> dof_user;        // library dof -> caller dof index
   std::vector<int32_t> bverts;
   std::vector<int32_t> rowptr, col;
-  std::vector<int32_t> adj_ptr, adj_tet, adj_pos;
+  std::vector<int32_t> adj_ptr, adj_tet;
   std::vector<int8_t> adj_loc;
   std::vector<double> geo;              // nt x 16
   std::vector<int32_t> tord;            // caller's index of each library tet (estimator option)
@@ -323,7 +327,8 @@ int elem_blocks(int64_t n, int N);
 int qp_blocks(int64_t nt);
 int gram_blocks(int64_t n);
 int nmom();
-void launch_vext(hipStream_t s, int64_t nt, const double* qpx, const double* RZ, int n_nuclei, int kind,
+// V_ext at npts points (nt x number of quadrature points per tet)
+void launch_vext(hipStream_t s, int64_t npts, const double* qpx, const double* RZ, int n_nuclei, int kind,
                  double rc, double omega, double* vext);
 void launch_qp_density(hipStream_t s, int64_t nt, const int32_t* tets, const int32_t* v2d, const double* X, int N,
                        const double* occ, double* rho_out);
@@ -348,6 +353,13 @@ void launch_assemble2(hipStream_t s, int64_t nt, int64_t n, int64_t nnz, const d
 void launch_load(hipStream_t s, int64_t n, int64_t nt, const int32_t* adj_ptr, const int32_t* adj_tet,
                  const int8_t* adj_loc, const int32_t* tets, const double* geo, const double* f_qp, double scale,
                  const double* gnod, const int32_t* v2d, double* scratch, double* b, double* lvec);
+// the DoF pass of the load vector (ne nodes per tet, 2 ne element values per tet in scratch)
+void launch_load_gather(hipStream_t s, int64_t n, int ne, const int32_t* adj_ptr, const int32_t* adj_tet,
+                        const int8_t* adj_loc, const double* scratch, double* b, double* lvec);
+// CSR values from the element entries in slot order; dinv = 1 / diagonal
+void launch_slot_sum(hipStream_t s, int64_t nnz, const int32_t* slot_ptr, const double* esl, double* val1,
+                     double* val2);
+void launch_diag_inv(hipStream_t s, int64_t n, const int32_t* diag_slot, const double* val, double* dinv);
 void launch_scale_cols_to(hipStream_t s, int64_t n, int N, const double* X, const double* sc, double* Y);
 void launch_coldot(hipStream_t s, int64_t n, int N, const double* X, const double* Y, double* partial);
 void launch_reduce_cols(hipStream_t s, int N, int nblk, const double* partial, double* out);

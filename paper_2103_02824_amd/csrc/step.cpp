@@ -364,8 +364,12 @@ mlc_status phase_fields(StepRun& S) {
   SmallLayout L(c->nH, c->N);
   for (int k = 0; k < 8; ++k) HIPCHK(hipEventCreate(&S.ev[k]));
   HIPCHK(hipEventRecord(S.ev[0], s));
-  launch_qp_fields(s, c->nt, d.tets, d.v2d, d.Phi, c->N, d.occ, d.w, d.vext, d.geo, d.qpx, c->xc, c->xalpha, d.vxc,
-                   d.exc, d.veff, d.rho, d.red);
+  if (c->order == 2)
+    launch_qp_fields_p2(s, c->nt, d.tets, d.v2d, d.Phi, c->N, d.occ, d.w, d.vext, d.geo, d.qpx, c->xc, c->xalpha,
+                        d.qtab, d.vxc, d.exc, d.veff, d.rho, d.red);
+  else
+    launch_qp_fields(s, c->nt, d.tets, d.v2d, d.Phi, c->N, d.occ, d.w, d.vext, d.geo, d.qpx, c->xc, c->xalpha, d.vxc,
+                     d.exc, d.veff, d.rho, d.red);
   launch_reduce_rows(s, d.red, qp_blocks(c->nt), nmom(), 1, d.small + L.mom);
   return S.defer_copies ? MLC_OK : phase_fields_copy(S);
 }
@@ -395,10 +399,16 @@ mlc_status phase_operators(StepRun& S) {
   if (c->hartree && S.mom[0] > 0.0)
     launch_boundary_g(s, (int64_t)c->bverts.size(), d.bverts, d.xyz, d.small + L.mom, d.g);
   // V_ext + V_xc + g at the quadrature points (A_fix of the inner problems)
-  launch_field(s, nt, d.tets, d.g, d.v2d, nullptr, d.vext, d.vxc, d.fld);
   const int64_t nnz = (int64_t)c->col.size();
-  launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_of, c->slot_ptr.back(), d.diag_slot, d.elem, 0.5, d.veff,
-                   S.sigma, d.valA, d.dinvA, 0.5, d.fld, d.valF);
+  if (c->order == 2) {
+    launch_field_p2(s, nt, d.tets, d.g, d.v2d, nullptr, d.vext, d.vxc, d.qtab, d.fld);
+    launch_assemble2_p2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_of, d.diag_slot, d.elem, 0.5, d.veff, S.sigma,
+                        d.valA, d.dinvA, 0.5, d.fld, d.valF, d.qtab);
+  } else {
+    launch_field(s, nt, d.tets, d.g, d.v2d, nullptr, d.vext, d.vxc, d.fld);
+    launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_of, c->slot_ptr.back(), d.diag_slot, d.elem, 0.5,
+                     d.veff, S.sigma, d.valA, d.dinvA, 0.5, d.fld, d.valF);
+  }
   if (c->opt.precond == MLC_PC_CHEBYSHEV) launch_gershgorin(s, n, d.rowptr, d.valA, d.dinvA, d.red, d.lmax);
   launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr, nullptr);
   launch_scale_cols_to(s, n, N, d.Q, d.colv, d.B);
@@ -457,9 +467,15 @@ mlc_status phase_after_solve(StepRun& S) {
     // potential w^l, the Hartree potential of rho^l (rho~ differs from it by
     // the step's change of the orbitals; the boundary data are zero inside)
     launch_gather_nodal(s, n, d.d2v, d.w, d.w0);
-    launch_qp_density(s, nt, d.tets, d.v2d, d.X, N, d.occ, d.rhot);
-    launch_load(s, n, nt, d.adj_ptr, d.adj_tet, d.adj_loc, d.tets, d.geo, d.rhot, 4.0 * 3.14159265358979323846, d.g,
-                d.v2d, d.elem, d.pb, d.lvec);
+    if (c->order == 2) {
+      launch_qp_density_p2(s, nt, d.tets, d.v2d, d.X, N, d.occ, d.qtab, d.rhot);
+      launch_load_p2(s, n, nt, d.adj_ptr, d.adj_tet, d.adj_loc, d.tets, d.geo, d.rhot, 4.0 * 3.14159265358979323846,
+                     d.g, d.v2d, d.qtab, d.elem, d.pb, d.lvec);
+    } else {
+      launch_qp_density(s, nt, d.tets, d.v2d, d.X, N, d.occ, d.rhot);
+      launch_load(s, n, nt, d.adj_ptr, d.adj_tet, d.adj_loc, d.tets, d.geo, d.rhot, 4.0 * 3.14159265358979323846,
+                  d.g, d.v2d, d.elem, d.pb, d.lvec);
+    }
   }
   return MLC_OK;
 }
@@ -483,7 +499,10 @@ mlc_status phase_gram_fixed(StepRun& S, hipStream_t s, double* red) {
     launch_gram(s, n, N, d.X, Yo, red);
     launch_reduce_cols(s, N * N, gram_blocks(n), red, d.small + L.utF + (int64_t)o * N * N);
   }
-  launch_coarse_orb(s, cnt, c->nt, d.cgrp_ptr, d.cgrp_dof, d.chat, d.X, N, d.cel_orb);
+  if (c->order == 2)
+    launch_coarse_orb_p2(s, cnt, c->nt, d.cgrp_ptr, d.cgrp_dof, d.chat, d.X, N, d.qtab, d.cel_orb);
+  else
+    launch_coarse_orb(s, cnt, c->nt, d.cgrp_ptr, d.cgrp_dof, d.chat, d.X, N, d.cel_orb);
   if (d.cel_pairs) launch_coarse_pairs(s, cnt, c->nt, d.cgrp_ptr, d.cgrp_dof, d.chat, d.X, N, d.pair_jl, N * (N + 1) / 2,
                                        d.cel_pairs);
   HIPCHK(hipGetLastError());
@@ -504,13 +523,19 @@ mlc_status phase_gram(StepRun& S) {
   const int64_t nnz = (int64_t)c->col.size();
   if (c->hartree) {
     if (S.pr.breakdown) return fail(c, MLC_ERR_BREAKDOWN, "CG breakdown in the Hartree problem");
-    launch_field(s, nt, d.tets, nullptr, d.v2d, d.w0, nullptr, nullptr, d.fld2);
-    launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_of, c->slot_ptr.back(), d.diag_slot, d.elem, 0.0,
-                     d.fld2, 0.0, d.valW, nullptr, 0.0, nullptr, nullptr);
+    if (c->order == 2) {
+      launch_field_p2(s, nt, d.tets, nullptr, d.v2d, d.w0, nullptr, nullptr, d.qtab, d.fld2);
+      launch_assemble2_p2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_of, d.diag_slot, d.elem, 0.0, d.fld2, 0.0,
+                          d.valW, nullptr, 0.0, nullptr, nullptr, d.qtab);
+    } else {
+      launch_field(s, nt, d.tets, nullptr, d.v2d, d.w0, nullptr, nullptr, d.fld2);
+      launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_of, c->slot_ptr.back(), d.diag_slot, d.elem, 0.0,
+                       d.fld2, 0.0, d.valW, nullptr, 0.0, nullptr, nullptr);
+    }
   } else {
     HIPCHK(hipMemsetAsync(d.w0, 0, sizeof(double) * n, s));
     HIPCHK(hipMemsetAsync(d.lvec, 0, sizeof(double) * n, s));
-    HIPCHK(hipMemsetAsync(d.fld2, 0, sizeof(double) * 4 * nt, s));
+    HIPCHK(hipMemsetAsync(d.fld2, 0, sizeof(double) * c->nq * nt, s));
     HIPCHK(hipMemsetAsync(d.valW, 0, sizeof(double) * nnz, s));
   }
   S.r.poisson_iters = S.pr.iters;
@@ -533,7 +558,10 @@ mlc_status phase_gram(StepRun& S) {
     launch_reduce_cols(s, 1, elem_blocks(n, 1), d.red, d.small + L.sc + 1);
   }
   // coarse-pattern integrals (eqs. Adef, Ah4def, rhsdef, FG)
-  launch_coarse_ops(s, cnt, nt, d.cgrp_ptr, d.cgrp_tet, d.chat, d.cgeo, d.fld, d.fld2, d.cel_ops);
+  if (c->order == 2)
+    launch_coarse_ops_p2(s, cnt, nt, d.cgrp_ptr, d.cgrp_tet, d.chat, d.cgeo, d.fld, d.fld2, d.qtab, d.cel_ops);
+  else
+    launch_coarse_ops(s, cnt, nt, d.cgrp_ptr, d.cgrp_tet, d.chat, d.cgeo, d.fld, d.fld2, d.cel_ops);
   HIPCHK(hipEventRecord(S.ev[1], s));
   return S.defer_copies ? MLC_OK : phase_gram_copy(S);
 }
@@ -629,7 +657,10 @@ mlc_status phase_recon(StepRun& S) {
     launch_reconstruct(s, n, N, d.Pk, d.Pw, d.coarse_in, d.coarse_in + nH * N + nH, d.X, d.Phi);
   launch_hartree_nodal(s, nv, d.v2d, d.Pk, d.Pw, d.coarse_in + nH * N, S.io.theta1, d.w0, d.g, d.w);
   launch_rho_nodal(s, nv, d.v2d, d.Phi, N, d.occ, d.rho_nodal);
-  launch_energy(s, nt, d.tets, d.v2d, d.Phi, N, d.occ, d.w, d.vxc, d.geo, c->xc, c->xalpha, d.red);
+  if (c->order == 2)
+    launch_energy_p2(s, nt, d.tets, d.v2d, d.Phi, N, d.occ, d.w, d.vxc, d.geo, c->xc, c->xalpha, d.qtab, d.red);
+  else
+    launch_energy(s, nt, d.tets, d.v2d, d.Phi, N, d.occ, d.w, d.vxc, d.geo, c->xc, c->xalpha, d.red);
   launch_reduce_rows(s, d.red, qp_blocks(nt), 2, 0, d.small + L.sc + 2);
   launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr, nullptr);
   launch_gram(s, n, N, d.Phi, d.Q, d.red);

@@ -105,13 +105,24 @@ def test_rejects_bad_system():
     assert _create(mlc, L, S, rc=0.0)[0] == -1
 
 
-def test_rejects_element_orders_other_than_linear():
-    """mlc_mesh.order: linear Lagrange elements only; 0, 2 and 3 are argument errors."""
+def test_element_orders_linear_and_quadratic():
+    """mlc_mesh.order: 1 (P1) and 2 (P2) on the fine mesh; 0 and 3 are
+    argument errors, and so is a coarse mesh of order 2 (the coarse space is
+    P1). On P2 the nodes are the vertices plus one per edge, the DoFs the
+    nodes off the box faces: the checker's P2 space has the same counts. P2
+    with the estimator option or the joint variant is an argument error."""
+    from oracle.fem2 import MeshP2
     mlc, L = _lib()
     S = c1_hydrogen()
     assert _create(mlc, L, S, fine_order=1)[0] == 0
-    for order in (0, 2, 3):
+    for order in (0, 3):
         assert _create(mlc, L, S, fine_order=order)[0] == -1, order
+    st, msg, sizes = _create(mlc, L, S, fine_order=2)
+    assert st == 0, msg
+    m = MeshP2(S.xyz, S.tets, S.lo, S.hi)
+    assert sizes[0] == m.n_dof and sizes[2] == m.nv and sizes[0] == 31 ** 3
+    assert _create(mlc, L, S, fine_order=2, opts=mlc.options(estimator=1))[0] == -1
+    assert _create(mlc, L, S, fine_order=2, opts=mlc.options(variant=mlc.VARIANT_JOINT))[0] == -1
 
 
 def test_box_bounds_per_axis():
