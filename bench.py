@@ -63,14 +63,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_system(workload, seed):
+def make_system(workload, seed, order=1):
     from inputs.systems import c1_hydrogen, c2_cluster, c3_cluster
     if workload == "c1":
         return c1_hydrogen()
     if workload == "c2":
         return c2_cluster(seed)
     if workload == "c3":
-        return c3_cluster(seed, progress=lambda m: log(f"[bench] {m}"))
+        return c3_cluster(seed, order=order, progress=lambda m: log(f"[bench] {m}"))
     raise SystemExit(f"unknown workload {workload}")
 
 
@@ -197,7 +197,8 @@ def _opts(mlc, args, precision, precond, hartree_coarse):
                        inner_tol=args.inner_tol, time_kernels=0, precision=precision,
                        precond=mlc.PC_CHEBYSHEV if precond == "chebyshev" else mlc.PC_JACOBI,
                        cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio,
-                       hartree_coarse=hartree_coarse, hartree_precond=_HPC[args.hartree_precond])
+                       hartree_coarse=hartree_coarse, hartree_precond=_HPC[args.hartree_precond],
+                       ir_inner_rtol=args.ir_inner_rtol)
 
 
 def _timed_steps(ctx, state, n_warm, n_timed, label, reset):
@@ -233,6 +234,9 @@ def main():
                     help="c3: 40-atom cluster, 2e6 DoF x 52 orbitals, FP32 CG + FP64 refinement (default); c2: "
                          "4-atom cluster, 2e5 DoF; c1: hydrogen; batch: uneven clusters")
     ap.add_argument("--seed", type=int, default=None, help="cluster seed (default 0 for c3, 1 for c2)")
+    ap.add_argument("--order", type=int, default=2, choices=[1, 2],
+                    help="--workload c3: fine-space elements, 2 = P2 (2.0e6 DoFs on 2.8e5 vertices, the "
+                         "default), 1 = P1 (2.0e6 vertices)")
     ap.add_argument("--cg-rtol", type=float, default=1e-9)
     ap.add_argument("--precision", choices=["fp64", "fp32ir"], default=None,
                     help="step-5 arithmetic: plain FP64 CG, or FP32 CG inside FP64 iterative refinement "
@@ -243,8 +247,13 @@ def main():
                          "steps cost more than the iterations they save)")
     ap.add_argument("--hartree-precond", choices=["same", "jacobi", "chebyshev"], default="same",
                     help="preconditioner of the Hartree CG apart from the step-5 solves (default: the same)")
-    ap.add_argument("--cheb-degree", type=int, default=8)
-    ap.add_argument("--cheb-ratio", type=float, default=100.0)
+    ap.add_argument("--cheb-degree", type=int, default=None,
+                    help="Chebyshev degree (default 16 on the P2 40-atom workload, 8 otherwise)")
+    ap.add_argument("--cheb-ratio", type=float, default=None,
+                    help="Chebyshev interval [lmax/ratio, lmax] (default 300 on the P2 40-atom workload, 100 "
+                         "otherwise)")
+    ap.add_argument("--ir-inner-rtol", type=float, default=1e-4,
+                    help="FP32 CG tolerance of each refinement pass (relative to the pass's residual)")
     ap.add_argument("--hartree-coarse", type=int, default=1, choices=[0, 1],
                     help="add the exact coarse-space correction to the Hartree CG preconditioner")
     ap.add_argument("--inner-maxit", type=int, default=None,
@@ -281,6 +290,11 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this size twice (hardware counter calibration)")
     args = ap.parse_args()
+    p2 = args.workload == "c3" and args.order == 2
+    if args.cheb_degree is None:
+        args.cheb_degree = 16 if p2 else 8
+    if args.cheb_ratio is None:
+        args.cheb_ratio = 300.0 if p2 else 100.0
     if args.precond is None:
         args.precond = "jacobi" if args.workload == "batch" else "chebyshev"
     if args.precision is None:
@@ -311,7 +325,7 @@ def main():
         return run_learned(args)
     t_all = time.perf_counter()
     log(f"[bench] building workload {args.workload} seed {args.seed}")
-    S = make_system(args.workload, args.seed)
+    S = make_system(args.workload, args.seed, args.order)
     prec = mlc.PREC_FP32_IR if args.precision == "fp32ir" else mlc.PREC_FP64
     ctx = mlc.Context(S, _opts(mlc, args, prec, args.precond, args.hartree_coarse))
     n, N = ctx.n_dof, ctx.N
@@ -343,7 +357,7 @@ def main():
     # stream between two HIP events (per-launch events inside the solve would add dispatch overhead
     # to every launch); the one with the largest time per step (mean launch time x launches per
     # step) is the dominant kernel
-    nnz = int(np.sum(_row_nnz(S, ctx)))
+    nnz = int(ctx.probe("PATTERN", (3,))[0])
     word = 4 if args.precision == "fp32ir" else 8
     n_replay = 200
     cheb = args.precond == "chebyshev"
@@ -367,7 +381,8 @@ def main():
     achieved = kd["achieved_GBs"]
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": _traffic(kname, args.workload, args.seed, args.precision),
+            "traffic": _traffic(kname, args.workload, args.seed, args.precision,
+                                args.order if args.workload == "c3" else 1),
             "kernel": kname, "bytes_per_launch": kd["bytes_per_launch"], "avg_launch_us": kd["avg_launch_us"],
             "launches_timed": n_replay, "all_kernels": kern}
     # the plain FP64 GPU path on the same input state: FP64 Jacobi-PCG, no coarse correction
@@ -396,7 +411,7 @@ def main():
         log(f"[bench] cpu baseline: {cpu['sample']}")
     cg_its = int(np.mean([r["cg_iters_max"] for r in reps]))
     workload_name = {"c2": f"4-atom seeded cluster (seed {args.seed}), graded P1 mesh",
-                     "c3": f"40-atom seeded cluster (seed {args.seed}), graded P1 mesh",
+                     "c3": f"40-atom seeded cluster (seed {args.seed}), graded P{args.order} mesh",
                      "c1": "hydrogen Z=1 rc=0.2, 16^3 Kuhn P1 mesh"}[args.workload]
     out = {
         "metric": "fine-mesh SCF correction step: DoF*orbitals/s and % HBM roofline vs plain FP64",
@@ -452,11 +467,11 @@ def cpu_baseline_pcg_rate(S, ctx, args, plain):
     per step (its step-5 and Hartree Jacobi-PCG iterations), the CPU doing the
     same iterations."""
     import os
-    from oracle.fem import Mesh
+    from oracle.fem import make_mesh
     from oracle.pcg import jacobi_pcg
     from oracle.potentials import v_ext
     t0 = time.perf_counter()
-    fine = Mesh(S.xyz, S.tets, S.lo, S.hi)
+    fine = make_mesh(S.xyz, S.tets, S.lo, S.hi, getattr(S, "order", 1))
     Kf = fine.stiffness()
     vq = v_ext(fine.qp, S.R, S.Z, S.potential, S.rc, S.omega)
     sigma = 1.0 - float(vq.min())
@@ -689,14 +704,15 @@ def run_batch(args):
 
 
 # committed rocprofv3 summaries with hardware-counter traffic per workload
-_PROFILES = {("c2", 0, "fp64"): "cg_c2_cluster_fp64.md", ("c3", 0, "fp32ir"): "cg_c3_cluster40_fp32ir.md"}
+_PROFILES = {("c2", 0, "fp64", 1): "cg_c2_cluster_fp64.md", ("c3", 0, "fp32ir", 1): "cg_c3_cluster40_fp32ir.md",
+             ("c3", 0, "fp32ir", 2): "cg_c3_cluster40_p2_fp32ir.md"}
 
 
-def _traffic(kname, workload, seed, precision):
+def _traffic(kname, workload, seed, precision, order=1):
     """HBM bytes per launch of the roofline kernel from the committed counter summary, or None
     when there is no summary for this workload or the kernel sources have changed since."""
     import hashlib
-    name = _PROFILES.get((workload, seed, precision))
+    name = _PROFILES.get((workload, seed, precision, order))
     if name is None:
         return None
     prof = Path(ROOT) / "profiles" / name
@@ -717,22 +733,6 @@ def _traffic(kname, workload, seed, precision):
                 return None
             return rec["bytes_per_launch"]
     return None
-
-
-def _row_nnz(S, ctx):
-    # nonzeros of the interior CSR pattern, counted from the mesh (same rule as the library)
-    from collections import defaultdict
-    tets = np.asarray(S.tets)
-    lo, hi = S.lo, S.hi
-    xyz = np.asarray(S.xyz)
-    tol = 1e-12 * max(1.0, abs(lo), abs(hi))
-    onb = np.zeros(len(xyz), bool)
-    for ax in range(3):
-        onb |= (np.abs(xyz[:, ax] - lo) <= tol) | (np.abs(xyz[:, ax] - hi) <= tol)
-    e = np.concatenate([tets[:, [a, b]] for a in range(4) for b in range(4)])
-    e = e[~onb[e[:, 0]] & ~onb[e[:, 1]]]
-    key = e[:, 0].astype(np.int64) * len(xyz) + e[:, 1]
-    return np.array([len(np.unique(key))])
 
 
 if __name__ == "__main__":

@@ -283,6 +283,8 @@ mlc_status mlc_get_results(mlc_ctx* ctx, double* lambda_host, double* phi_dev, d
  *   MLC_PROBE_FEATURES n_dof x N x 6   learned-guess features (row dof, orbital)
  *   MLC_PROBE_NN_OUT   n_dof x N       network outputs of the last guess
  *   MLC_PROBE_GUESS_SCALE N            s_c = max |phi_c| of the last guess
+ *   MLC_PROBE_PATTERN  3                [nonzeros of the interior CSR pattern,
+ *                                        nodes per fine tet, quadrature points per fine tet]
  */
 enum {
   MLC_PROBE_U = 0, MLC_PROBE_W0, MLC_PROBE_G, MLC_PROBE_VXC_QP,
@@ -292,7 +294,7 @@ enum {
   MLC_PROBE_AFIX_H, MLC_PROBE_MW0_H, MLC_PROBE_M_H, MLC_PROBE_K_H,
   MLC_PROBE_AH4, MLC_PROBE_RHS, MLC_PROBE_THETA2, MLC_PROBE_PHI_H, MLC_PROBE_WH,
   MLC_PROBE_SIGMA,
-  MLC_PROBE_FEATURES, MLC_PROBE_NN_OUT, MLC_PROBE_GUESS_SCALE,
+  MLC_PROBE_FEATURES, MLC_PROBE_NN_OUT, MLC_PROBE_GUESS_SCALE, MLC_PROBE_PATTERN,
   MLC_PROBE_COUNT
 };
 mlc_status mlc_probe(mlc_ctx* ctx, int32_t which, double* out, int64_t count);

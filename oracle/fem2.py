@@ -143,13 +143,18 @@ class MeshP2:
         return np.einsum("qac,tcx->tqax", DQ, self.grad)
 
     def stiffness(self):
-        G = self.grad_qp()
-        elem = np.einsum("tq,tqax,tqbx->tab", self.qw, G, G)
+        """K_ab = |T| sum_q W_q grad phi_a(q) . grad phi_b(q). With
+        grad phi_a = sum_c D[q,a,c] grad lambda_c (grad lambda constant on T)
+        the sum is |T| sum_{c,d} S[a,b,c,d] (grad lambda_c . grad lambda_d),
+        S = sum_q W_q D[q,a,c] D[q,b,d] the same for every tet."""
+        S = np.einsum("q,qac,qbd->abcd", WQ2, DQ, DQ)
+        gl = np.matmul(self.grad, self.grad.transpose(0, 2, 1))           # (nt, 4, 4)
+        elem = self.vol[:, None, None] * (gl.reshape(self.nt, 16) @ S.reshape(100, 16).T).reshape(self.nt, 10, 10)
         return self._coo(elem)
 
     def mass(self, f_qp=None):
         f = np.ones_like(self.qw) if f_qp is None else f_qp
-        elem = np.einsum("tq,qa,qb->tab", self.qw * f, BQ, BQ)
+        elem = np.einsum("tq,qa,qb->tab", self.qw * f, BQ, BQ, optimize=True)
         return self._coo(elem)
 
     def load(self, f_qp):

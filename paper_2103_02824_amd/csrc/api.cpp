@@ -461,6 +461,12 @@ mlc_status probe(mlc_ctx* c, int which, double* out, int64_t count) {
       HIPCHK(hipMemcpyAsync(out, d.gscale, sizeof(double) * N, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       return MLC_OK;
+    case MLC_PROBE_PATTERN:
+      if ((st = need(3))) return st;
+      out[0] = (double)c->col.size();
+      out[1] = c->ne;
+      out[2] = c->nq;
+      return MLC_OK;
     default:
       return fail(c, MLC_ERR_ARG, "unknown probe");
   }
