@@ -171,6 +171,12 @@ typedef struct {
                            neighbours for mlc_estimate (host time and 20 bytes
                            of workspace per fine tet; P1 fine meshes only);
                            0 (default): off                                    */
+  int32_t cheb_lanczos; /* upper end of the Chebyshev interval: 0 (default)
+                           the Gershgorin bound of D^-1 A; m in 2..64:
+                           min(Gershgorin, 1.1 x the largest Ritz value of m
+                           Lanczos steps on D^-1 A in the D inner product,
+                           from a fixed pseudo-random start), for A + sigma M
+                           every step and for K once at mlc_bind              */
 } mlc_options;
 
 enum { MLC_VARIANT_EIGENPAIRWISE = 0, MLC_VARIANT_JOINT = 1 };
@@ -285,6 +291,7 @@ mlc_status mlc_get_results(mlc_ctx* ctx, double* lambda_host, double* phi_dev, d
  *   MLC_PROBE_GUESS_SCALE N            s_c = max |phi_c| of the last guess
  *   MLC_PROBE_PATTERN  3                [nonzeros of the interior CSR pattern,
  *                                        nodes per fine tet, quadrature points per fine tet]
+ *   MLC_PROBE_LMAX     2                upper ends of the Chebyshev intervals [step 5, Hartree]
  */
 enum {
   MLC_PROBE_U = 0, MLC_PROBE_W0, MLC_PROBE_G, MLC_PROBE_VXC_QP,
@@ -295,6 +302,7 @@ enum {
   MLC_PROBE_AH4, MLC_PROBE_RHS, MLC_PROBE_THETA2, MLC_PROBE_PHI_H, MLC_PROBE_WH,
   MLC_PROBE_SIGMA,
   MLC_PROBE_FEATURES, MLC_PROBE_NN_OUT, MLC_PROBE_GUESS_SCALE, MLC_PROBE_PATTERN,
+  MLC_PROBE_LMAX,
   MLC_PROBE_COUNT
 };
 mlc_status mlc_probe(mlc_ctx* ctx, int32_t which, double* out, int64_t count);

@@ -155,6 +155,7 @@ size_t workspace_layout(mlc_ctx* c, char* base, Dev* d) {
   d->dof_user = w.take<int32_t>(n);
   d->chk = w.take<int32_t>(4);
   d->lmax = w.take<double>(2);
+  d->lanc = w.take<double>(2 * 64 + 4);
   if (c->hartree && hartree_pc(c->opt) == MLC_PC_CHEBYSHEV) d->valK32 = w.take<float>(nnz);
   if (c->opt.hartree_coarse && c->hartree) {
     d->KHinv = w.take<double>(nH * nH);
@@ -268,6 +269,9 @@ mlc_status upload_and_init(mlc_ctx* c) {
                      d.valM, nullptr, 0.0, nullptr, nullptr);
   }
   launch_gershgorin(s, c->n, d.rowptr, d.valK, d.dinvK, d.red, d.lmax + 1);
+  if (c->opt.cheb_lanczos)
+    launch_lanczos_lmax(s, c->n, d.rowptr, d.col, d.valK, d.dinvK, c->opt.cheb_lanczos, 1.1, d.Y, d.red, d.lanc,
+                        d.lmax + 1);
   if (d.valK32) launch_to_f32(s, nnz, d.valK, d.valK32);
   if (c->order == 2) {
     launch_coarse_tri_p2(s, c->cnt, d.cgrp_ptr, d.cgrp_tet, d.tets, d.geo, d.xyz, d.cgeo, d.qtab, d.cel_tri);
@@ -461,6 +465,11 @@ mlc_status probe(mlc_ctx* c, int which, double* out, int64_t count) {
       HIPCHK(hipMemcpyAsync(out, d.gscale, sizeof(double) * N, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       return MLC_OK;
+    case MLC_PROBE_LMAX:
+      if ((st = need(2))) return st;
+      HIPCHK(hipMemcpyAsync(out, d.lmax, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      return MLC_OK;
     case MLC_PROBE_PATTERN:
       if ((st = need(3))) return st;
       out[0] = (double)c->col.size();
@@ -504,6 +513,7 @@ void mlc_options_default(mlc_options* o) {
   o->inner_mix_beta = 0.5;
   o->variant = MLC_VARIANT_EIGENPAIRWISE;
   o->estimator = 0;
+  o->cheb_lanczos = 0;
 }
 
 mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys, const mlc_options* opt,
@@ -541,6 +551,7 @@ mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_sy
       (c->opt.variant != MLC_VARIANT_EIGENPAIRWISE && c->opt.variant != MLC_VARIANT_JOINT) ||
       (c->opt.variant == MLC_VARIANT_JOINT && sys->n_orbitals > 64) ||
       (c->opt.estimator != 0 && c->opt.estimator != 1) ||
+      (c->opt.cheb_lanczos != 0 && (c->opt.cheb_lanczos < 2 || c->opt.cheb_lanczos > 64)) ||
       (fine->order == 2 && (c->opt.estimator != 0 || c->opt.variant == MLC_VARIANT_JOINT)) ||
       !(c->opt.inner_mix_beta > 0.0 && c->opt.inner_mix_beta <= 1.0)) {
     delete c;

@@ -1055,6 +1055,108 @@ __global__ void __launch_bounds__(TPB) k_energy(int64_t nt, const int32_t* __res
   }
 }
 
+// ---------------------------------------------------------------------------
+// Lanczos estimate of lambda_max(D^-1 A) for the Chebyshev interval. D^-1 A is
+// self-adjoint in <x, y>_D = sum_i x_i y_i / dinv_i; m Lanczos steps from a
+// fixed pseudo-random start give the tridiagonal T_m, whose largest
+// eigenvalue (a Ritz value, at most lambda_max) is found by bisection on
+// Sturm counts. The bound used is min(Gershgorin, safety x that Ritz value).
+// Block partial sums are added in a fixed order (one reduction kernel).
+constexpr int LZ_BLOCKS = 1024;
+__device__ __forceinline__ void lz_block_sum(double v, double* __restrict__ partial) {
+  __shared__ double sd[TPB];
+  sd[threadIdx.x] = v;
+  for (int h = TPB / 2; h > 0; h >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < h) sd[threadIdx.x] += sd[threadIdx.x + h];
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sd[0];
+}
+
+// v_i = a pseudo-random value in [-1, 1) (multiplicative hash of i); partial <v, v>_D.
+__global__ void __launch_bounds__(TPB) k_lz_init(int64_t n, const double* __restrict__ dinv, double* __restrict__ v,
+                                                 double* __restrict__ partial) {
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    const uint32_t h = (uint32_t)((uint64_t)(i + 1) * 2654435761ull);
+    const double x = (double)h * (2.0 / 4294967296.0) - 1.0;
+    v[i] = x;
+    acc += x * x / dinv[i];
+  }
+  lz_block_sum(acc, partial);
+}
+// v /= sqrt(nrm2[0])
+__global__ void __launch_bounds__(TPB) k_lz_scale(int64_t n, const double* __restrict__ nrm2, double* __restrict__ v) {
+  const double sc = nrm2[0] > 0.0 ? 1.0 / sqrt(nrm2[0]) : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) v[i] *= sc;
+}
+// w = D^-1 y - beta v_prev (beta = sqrt(beta2[0]), 0 at the first step); partial <w, v>_D.
+__global__ void __launch_bounds__(TPB) k_lz_alpha(int64_t n, const double* __restrict__ dinv,
+                                                  const double* __restrict__ y, const double* __restrict__ v,
+                                                  const double* __restrict__ vprev, const double* __restrict__ beta2,
+                                                  double* __restrict__ w, double* __restrict__ partial) {
+  const double beta = beta2 ? sqrt(fmax(beta2[0], 0.0)) : 0.0;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    const double wi = dinv[i] * y[i] - beta * vprev[i];
+    w[i] = wi;
+    acc += wi * v[i] / dinv[i];
+  }
+  lz_block_sum(acc, partial);
+}
+// w -= alpha v; partial <w, w>_D.
+__global__ void __launch_bounds__(TPB) k_lz_orth(int64_t n, const double* __restrict__ dinv,
+                                                 const double* __restrict__ alpha, const double* __restrict__ v,
+                                                 double* __restrict__ w, double* __restrict__ partial) {
+  const double a = alpha[0];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    const double wi = w[i] - a * v[i];
+    w[i] = wi;
+    acc += wi * wi / dinv[i];
+  }
+  lz_block_sum(acc, partial);
+}
+// v_prev = v; v = w / beta (0 when beta vanishes: an invariant subspace was found).
+__global__ void __launch_bounds__(TPB) k_lz_next(int64_t n, const double* __restrict__ beta2,
+                                                 const double* __restrict__ w, double* __restrict__ v,
+                                                 double* __restrict__ vprev) {
+  const double b2 = beta2[0];
+  const double sc = b2 > 1e-300 ? 1.0 / sqrt(b2) : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    vprev[i] = v[i];
+    v[i] = w[i] * sc;
+  }
+}
+// Largest eigenvalue of T (diagonal alpha[0..m), off-diagonal sqrt(beta2[1..m))) by bisection on the
+// number of eigenvalues below x (Sturm sequence of the LDL^T pivots); lmax[0] = min(lmax[0], safety x it).
+__global__ void k_lz_eig(int m, const double* __restrict__ alpha, const double* __restrict__ beta2, double safety,
+                         double* __restrict__ lmax) {
+  if (threadIdx.x != 0) return;
+  double lo = 1e300, hi = -1e300;
+  for (int j = 0; j < m; ++j) {
+    const double bl = j > 0 ? sqrt(fmax(beta2[j], 0.0)) : 0.0, br = j + 1 < m ? sqrt(fmax(beta2[j + 1], 0.0)) : 0.0;
+    lo = fmin(lo, alpha[j] - bl - br);
+    hi = fmax(hi, alpha[j] + bl + br);
+  }
+  if (!(hi > lo) || !(hi < 1e300)) return;
+  for (int it = 0; it < 200; ++it) {
+    const double x = 0.5 * (lo + hi);
+    int below = 0;
+    double q = alpha[0] - x;
+    if (q < 0.0) ++below;
+    for (int j = 1; j < m; ++j) {
+      if (q == 0.0) q = 1e-300;
+      q = (alpha[j] - x) - fmax(beta2[j], 0.0) / q;
+      if (q < 0.0) ++below;
+    }
+    if (below == m) hi = x;  // every eigenvalue below x
+    else lo = x;
+  }
+  const double est = safety * hi;
+  if (est > 0.0 && est < lmax[0]) lmax[0] = est;
+}
+
 inline unsigned nb(int64_t work) { return (unsigned)((work + TPB - 1) / TPB); }
 
 // ---------------------------------------------------------------------------
@@ -1443,6 +1545,27 @@ void launch_coldot(hipStream_t s, int64_t n, int N, const double* X, const doubl
 }
 void launch_reduce_cols(hipStream_t s, int N, int nblk, const double* partial, double* out) {
   hipLaunchKernelGGL(k_reduce_cols, dim3(N), dim3(TPB), 0, s, N, nblk, partial, out);
+}
+void launch_lanczos_lmax(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                         const double* dinv, int m, double safety, double* work, double* partial, double* scal,
+                         double* lmax) {
+  if (m < 2 || n < 2) return;
+  const int g = (int)std::min<int64_t>(LZ_BLOCKS, std::max<int64_t>(1, (n + TPB - 1) / TPB));
+  double *v = work, *vprev = work + n, *w = work + 2 * n;
+  double *alpha = scal, *beta2 = scal + m + 1;  // beta2[j]: squared norm after step j - 1 (beta2[0] unused)
+  hipLaunchKernelGGL(k_lz_init, dim3(g), dim3(TPB), 0, s, n, dinv, v, partial);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(TPB), 0, s, 1, g, partial, beta2);
+  hipLaunchKernelGGL(k_lz_scale, dim3(g), dim3(TPB), 0, s, n, beta2, v);
+  for (int j = 0; j < m; ++j) {
+    launch_spmm2(s, n, 1, rowptr, col, val, v, w, nullptr, nullptr);
+    hipLaunchKernelGGL(k_lz_alpha, dim3(g), dim3(TPB), 0, s, n, dinv, w, v, vprev, j > 0 ? beta2 + j : nullptr, w,
+                       partial);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(TPB), 0, s, 1, g, partial, alpha + j);
+    hipLaunchKernelGGL(k_lz_orth, dim3(g), dim3(TPB), 0, s, n, dinv, alpha + j, v, w, partial);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(TPB), 0, s, 1, g, partial, beta2 + j + 1);
+    if (j + 1 < m) hipLaunchKernelGGL(k_lz_next, dim3(g), dim3(TPB), 0, s, n, beta2 + j + 1, w, v, vprev);
+  }
+  hipLaunchKernelGGL(k_lz_eig, dim3(1), dim3(64), 0, s, m, alpha, beta2, safety, lmax);
 }
 void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, double* X) {
   hipLaunchKernelGGL(k_normalize_cols, dim3(nb(n * N)), dim3(TPB), 0, s, n * N, N, sc, X);

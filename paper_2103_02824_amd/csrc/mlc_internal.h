@@ -130,7 +130,8 @@ struct Dev {
   int32_t* d2v = nullptr;       // n: library dof -> vertex
   int32_t* dof_user = nullptr;  // n: library dof -> caller dof
   int32_t* chk = nullptr;       // 4: count of non-finite inputs (mlc_set_state)
-  double* lmax = nullptr;       // 2: Gershgorin bounds of D^-1 A (step 5) and D^-1 K (Hartree)
+  double* lmax = nullptr;       // 2: upper ends of the Chebyshev intervals of D^-1 A (step 5) and D^-1 K (Hartree)
+  double* lanc = nullptr;       // 2 x 64 + 4: Lanczos coefficients of the lmax estimate
   float* valK32 = nullptr;      // nnz: K in FP32 for the Hartree CG's polynomial steps
   double* KHinv = nullptr;      // nH x nH: inverse of the coarse stiffness (two-level Hartree CG)
   double* rH = nullptr;         // nH: restricted residual
@@ -363,6 +364,11 @@ void launch_diag_inv(hipStream_t s, int64_t n, const int32_t* diag_slot, const d
 void launch_scale_cols_to(hipStream_t s, int64_t n, int N, const double* X, const double* sc, double* Y);
 void launch_coldot(hipStream_t s, int64_t n, int N, const double* X, const double* Y, double* partial);
 void launch_reduce_cols(hipStream_t s, int N, int nblk, const double* partial, double* out);
+// lmax[0] = min(lmax[0], safety x the largest Ritz value of m Lanczos steps on D^-1 A in the D inner
+// product); work: 3n doubles; partial: ceil(n / 256) (at most 1024) doubles; scal: 2m + 2 doubles.
+void launch_lanczos_lmax(hipStream_t s, int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                         const double* dinv, int m, double safety, double* work, double* partial, double* scal,
+                         double* lmax);
 void launch_normalize_cols(hipStream_t s, int64_t n, int N, const double* sc, double* X);
 // P^T Y (nH x N) through the chunk structure: each chunk of RESTRICT_CHUNK
 // fine rows of Y is read once (into LDS), its segment sums go to part, then

@@ -409,7 +409,11 @@ mlc_status phase_operators(StepRun& S) {
     launch_assemble2(s, nt, n, nnz, d.geo, d.slot_ptr, d.slot_of, c->slot_ptr.back(), d.diag_slot, d.elem, 0.5,
                      d.veff, S.sigma, d.valA, d.dinvA, 0.5, d.fld, d.valF);
   }
-  if (c->opt.precond == MLC_PC_CHEBYSHEV) launch_gershgorin(s, n, d.rowptr, d.valA, d.dinvA, d.red, d.lmax);
+  if (c->opt.precond == MLC_PC_CHEBYSHEV) {
+    launch_gershgorin(s, n, d.rowptr, d.valA, d.dinvA, d.red, d.lmax);
+    if (c->opt.cheb_lanczos)
+      launch_lanczos_lmax(s, n, d.rowptr, d.col, d.valA, d.dinvA, c->opt.cheb_lanczos, 1.1, d.Y, d.red, d.lanc, d.lmax);
+  }
   launch_spmm2(s, n, N, d.rowptr, d.col, d.valM, d.Phi, d.Q, nullptr, nullptr);
   launch_scale_cols_to(s, n, N, d.Q, d.colv, d.B);
   HIPCHK(hipMemcpyAsync(d.X, d.Phi, sizeof(double) * n * N, hipMemcpyDeviceToDevice, s));

@@ -24,7 +24,7 @@ STATUS = {0: "MLC_OK", -1: "MLC_ERR_ARG", -2: "MLC_ERR_MESH", -3: "MLC_ERR_NOT_N
 
 PROBES = ["U", "W0", "G", "VXC_QP", "PT_AFIX_U", "PT_MW0_U", "PT_M_U", "PT_K_U", "UT_AFIX_U", "UT_MW0_U",
           "UT_M_U", "UT_K_U", "HARTREE_D", "AFIX_H", "MW0_H", "M_H", "K_H", "AH4", "RHS", "THETA2", "PHI_H",
-          "WH", "SIGMA", "FEATURES", "NN_OUT", "GUESS_SCALE", "PATTERN"]
+          "WH", "SIGMA", "FEATURES", "NN_OUT", "GUESS_SCALE", "PATTERN", "LMAX"]
 PROBE_ID = {name: i for i, name in enumerate(PROBES)}
 
 EXPORTED = ["mlc_options_default", "mlc_create", "mlc_sizes", "mlc_workspace_bytes", "mlc_bind",
@@ -66,7 +66,7 @@ class Options(C.Structure):
                 ("precond", C.c_int32), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("hartree_coarse", C.c_int32), ("hartree_precond", C.c_int32),
                 ("inner_mix_history", C.c_int32), ("inner_mix_beta", C.c_double), ("variant", C.c_int32),
-                ("estimator", C.c_int32)]
+                ("estimator", C.c_int32), ("cheb_lanczos", C.c_int32)]
 
 PREC_FP64, PREC_FP32_IR = 0, 1
 PC_JACOBI, PC_CHEBYSHEV = 0, 1

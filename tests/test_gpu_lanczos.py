@@ -1,0 +1,57 @@
+"""The Lanczos estimate of the Chebyshev interval's upper end (option
+cheb_lanczos) against the checker: the library's lambda_max for the step-5
+operator A + sigma M and for K lies between the true largest eigenvalue of
+D^-1 A (the checker's operator, dense symmetric eigensolve of
+D^-1/2 A D^-1/2) and min(Gershgorin, 1.1 x lambda_max), so the polynomial
+preconditioner stays positive definite; and a step with it reaches the
+checker's results, on P1 and P2 spaces."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from inputs.systems import tiny_system
+from oracle.mlc import Problem, correction_step, fine_stage
+from oracle.scf import initial_state
+from test_gpu_parity import LIB_OPTS, ORA_OPTS, relerr
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "tiny2": lambda: tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=True, n_orbitals=2, seed=7),
+    "p2_nested": lambda: tiny_system(n_fine=6, n_coarse=3, box=5.0, nonlinear=True, n_orbitals=2, seed=7, order=2),
+}
+
+
+def _bounds(A):
+    A = A.toarray()
+    d = np.diag(A)
+    s = 1.0 / np.sqrt(d)
+    lmax = sla.eigvalsh(A * s[:, None] * s[None, :])[-1]
+    gersh = np.max(np.sum(np.abs(A), axis=1) / d)
+    return lmax, gersh
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_lanczos_upper_end_and_step(gpu, case):
+    from paper_2103_02824_amd import mlc
+    S = CASES[case]()
+    prob = Problem(S)
+    st0, _ = initial_state(prob)
+    ctx = mlc.Context(S, mlc.options(**dict(LIB_OPTS, precond=mlc.PC_CHEBYSHEV, cheb_degree=8, cheb_ratio=100.0,
+                                            cheb_lanczos=24, hartree_coarse=1)))
+    ctx.set_state(st0.lam, st0.Phi, st0.w)
+    ctx.correction_step()
+    lm = ctx.probe("LMAX", (2,))
+    fs = fine_stage(prob, st0, ORA_OPTS)
+    for got, A in ((lm[0], fs["A"] + fs["sigma"] * prob.M), (lm[1], prob.K)):
+        lmax, gersh = _bounds(A)
+        print(f"case {case}: library {got:.6f}, true lambda_max {lmax:.6f}, Gershgorin {gersh:.6f}", flush=True)
+        assert lmax * (1 - 1e-9) <= got <= min(gersh * (1 + 1e-6), 1.1 * lmax * (1 + 1e-9))
+        if 1.1 * lmax < 0.99 * gersh:
+            assert got < 0.99 * gersh     # the estimate, not the Gershgorin bound, was taken
+    ref = correction_step(prob, st0, ORA_OPTS)
+    assert relerr(ctx.probe("U", (ctx.n_dof, ctx.N)), ref.inter["fine"]["U"]) < 1e-8
+    lam, Phi, w, rho = ctx.get_results()
+    assert np.max(np.abs(lam - ref.state.lam)) < 1e-8, (lam, ref.state.lam)
+    assert relerr(rho, ref.rho_nodal) < 1e-6
+    ctx.close()
