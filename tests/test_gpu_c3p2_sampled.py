@@ -1,7 +1,7 @@
 """The 40-atom workload on its P2 space at full size (about 2.0e6 P2 DoFs x
 52 orbitals on a graded mesh of 2.8e5 vertices; FP32 CG inside FP64
-refinement, Chebyshev degree 16 over [lmax/300, lmax]: the benchmark's
-launch configuration),
+refinement, Chebyshev degree 16 over [lmax/300, lmax] with lmax from 16
+Lanczos steps: the benchmark's launch configuration),
 checked on sampled outputs as the P1 case is. For each sampled DoF (a vertex
 or an edge node) the checker assembles its row of (A + sigma M) and of M on
 the patch of tets that contain the node, with its own P2 elements
@@ -34,7 +34,7 @@ def _c3p2_step():
     S = c3_cluster(0, order=2, progress=lambda m: print(m, flush=True))
     opts = mlc.options(cg_rtol=1e-12, poisson_rtol=1e-12, inner_maxit=1, inner_tol=1e-9, shift=1, sigma0=1.0,
                        precision=mlc.PREC_FP32_IR, precond=mlc.PC_CHEBYSHEV, cheb_degree=16, cheb_ratio=300.0,
-                       hartree_coarse=1)
+                       cheb_lanczos=16, hartree_coarse=1)
     ctx = mlc.Context(S, opts)
     n, N = ctx.n_dof, ctx.N
     print(f"case 40-atom P2: n_dof={n} nodes={ctx.n_vertices} N={N}", flush=True)
