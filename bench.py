@@ -198,7 +198,8 @@ def _opts(mlc, args, precision, precond, hartree_coarse):
                        precond=mlc.PC_CHEBYSHEV if precond == "chebyshev" else mlc.PC_JACOBI,
                        cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio,
                        hartree_coarse=hartree_coarse, hartree_precond=_HPC[args.hartree_precond],
-                       ir_inner_rtol=args.ir_inner_rtol, cheb_lanczos=args.cheb_lanczos)
+                       ir_inner_rtol=args.ir_inner_rtol, cheb_lanczos=args.cheb_lanczos,
+                       hartree_cheb_degree=args.hartree_cheb_degree, hartree_cheb_ratio=args.hartree_cheb_ratio)
 
 
 def _timed_steps(ctx, state, n_warm, n_timed, label, reset):
@@ -255,6 +256,12 @@ def main():
     ap.add_argument("--cheb-lanczos", type=int, default=None,
                     help="Lanczos steps for the Chebyshev interval's upper end (0: the Gershgorin bound; default "
                          "16 on the P2 40-atom workload, 0 otherwise)")
+    ap.add_argument("--hartree-cheb-degree", type=int, default=None,
+                    help="the Hartree CG's polynomial degree (0: --cheb-degree; default 8 on the 40-atom workload, "
+                         "0 otherwise)")
+    ap.add_argument("--hartree-cheb-ratio", type=float, default=None,
+                    help="the Hartree CG's interval ratio (0: --cheb-ratio; default 300 on the 40-atom workload, "
+                         "0 otherwise)")
     ap.add_argument("--ir-inner-rtol", type=float, default=1e-4,
                     help="FP32 CG tolerance of each refinement pass (relative to the pass's residual)")
     ap.add_argument("--hartree-coarse", type=int, default=1, choices=[0, 1],
@@ -300,6 +307,10 @@ def main():
         args.cheb_ratio = 300.0 if p2 else 100.0
     if args.cheb_lanczos is None:
         args.cheb_lanczos = 16 if p2 else 0
+    if args.hartree_cheb_degree is None:
+        args.hartree_cheb_degree = 8 if args.workload == "c3" else 0
+    if args.hartree_cheb_ratio is None:
+        args.hartree_cheb_ratio = 300.0 if args.workload == "c3" else 0.0
     if args.precond is None:
         args.precond = "jacobi" if args.workload == "batch" else "chebyshev"
     if args.precision is None:
@@ -431,7 +442,9 @@ def main():
                    "preconditioner": ("Jacobi" if args.precond == "jacobi" else
                                       f"Chebyshev degree {args.cheb_degree} over [lmax/{args.cheb_ratio:g}, lmax], lmax "
                                       + (f"from {args.cheb_lanczos} Lanczos steps" if args.cheb_lanczos else
-                                         "the Gershgorin bound"))
+                                         "the Gershgorin bound")
+                                      + (f"; Hartree CG degree {args.hartree_cheb_degree or args.cheb_degree} over "
+                                         f"[lmax/{args.hartree_cheb_ratio or args.cheb_ratio:g}, lmax]"))
                    + (" + coarse-space correction (Hartree)" if args.hartree_coarse else ""),
                    "timed_step": ("outer step l=0 -> 1 of Algorithm 1 from the interpolated coarse Kohn-Sham "
                                   "state, repeated (state reset on the device before each step)" if reset else

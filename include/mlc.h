@@ -177,6 +177,10 @@ typedef struct {
                            Lanczos steps on D^-1 A in the D inner product,
                            from a fixed pseudo-random start), for A + sigma M
                            every step and for K once at mlc_bind              */
+  int32_t hartree_cheb_degree; /* the Hartree CG's polynomial degree (2..16);
+                                  0 (default): cheb_degree                    */
+  double hartree_cheb_ratio;   /* its interval ratio (> 1); 0 (default):
+                                  cheb_ratio                                  */
 } mlc_options;
 
 enum { MLC_VARIANT_EIGENPAIRWISE = 0, MLC_VARIANT_JOINT = 1 };

@@ -514,6 +514,8 @@ void mlc_options_default(mlc_options* o) {
   o->variant = MLC_VARIANT_EIGENPAIRWISE;
   o->estimator = 0;
   o->cheb_lanczos = 0;
+  o->hartree_cheb_degree = 0;
+  o->hartree_cheb_ratio = 0.0;
 }
 
 mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_system* sys, const mlc_options* opt,
@@ -552,6 +554,8 @@ mlc_status mlc_create(const mlc_mesh* fine, const mlc_mesh* coarse, const mlc_sy
       (c->opt.variant == MLC_VARIANT_JOINT && sys->n_orbitals > 64) ||
       (c->opt.estimator != 0 && c->opt.estimator != 1) ||
       (c->opt.cheb_lanczos != 0 && (c->opt.cheb_lanczos < 2 || c->opt.cheb_lanczos > 64)) ||
+      (c->opt.hartree_cheb_degree != 0 && (c->opt.hartree_cheb_degree < 2 || c->opt.hartree_cheb_degree > 16)) ||
+      !(c->opt.hartree_cheb_ratio == 0.0 || c->opt.hartree_cheb_ratio > 1.0) ||
       (fine->order == 2 && (c->opt.estimator != 0 || c->opt.variant == MLC_VARIANT_JOINT)) ||
       !(c->opt.inner_mix_beta > 0.0 && c->opt.inner_mix_beta <= 1.0)) {
     delete c;
@@ -755,7 +759,7 @@ mlc_status mlc_time_kernel(mlc_ctx* c, int32_t which, int32_t reps, double* avg_
   // one overwritten, no r.z partials): the launch of every step but the first
   // and the last
   double* Yd = hart ? d.Yh : d.Y;
-  PolyPC<double> pd{hart ? d.lmax + 1 : d.lmax, c->opt.cheb_ratio, 3, {Yd, Yd + n * N}, nullptr,
+  PolyPC<double> pd{hart ? d.lmax + 1 : d.lmax, hart ? hartree_ratio(c->opt) : c->opt.cheb_ratio, 3, {Yd, Yd + n * N}, nullptr,
                     hart ? d.valK32 : nullptr};
   PolyPC<float> pf{d.lmax, c->opt.cheb_ratio, 3, {Yf, Yf + n * N}, nullptr};
   hipEvent_t e0, e1;

@@ -255,6 +255,7 @@ struct BRes {
 BPoly batch_poly(const mlc_batch* b, int kind) {
   const mlc_options& o = b->ctx[0]->opt;
   if ((kind == 1 ? hartree_pc(o) : o.precond) != MLC_PC_CHEBYSHEV) return BPoly{0, 1.0, nullptr};
+  if (kind == 1) return BPoly{hartree_deg(o), hartree_ratio(o), b->part_rz};
   return BPoly{o.cheb_degree, o.cheb_ratio, b->part_rz};
 }
 
@@ -502,7 +503,9 @@ mlc_status mlc_batch_create(mlc_ctx* const* ctxs, int32_t count, mlc_batch** out
     if (c->opt.precision != b->prec) return MLC_ERR_ARG;
     if (c->opt.precond != ctxs[0]->opt.precond || hartree_pc(c->opt) != hartree_pc(ctxs[0]->opt) ||
         ((c->opt.precond == MLC_PC_CHEBYSHEV || hartree_pc(c->opt) == MLC_PC_CHEBYSHEV) &&
-         (c->opt.cheb_degree != ctxs[0]->opt.cheb_degree || c->opt.cheb_ratio != ctxs[0]->opt.cheb_ratio)))
+         (c->opt.cheb_degree != ctxs[0]->opt.cheb_degree || c->opt.cheb_ratio != ctxs[0]->opt.cheb_ratio ||
+          hartree_deg(c->opt) != hartree_deg(ctxs[0]->opt) ||
+          hartree_ratio(c->opt) != hartree_ratio(ctxs[0]->opt))))
       return MLC_ERR_ARG;
     if (c->opt.hartree_coarse != ctxs[0]->opt.hartree_coarse) return MLC_ERR_ARG;
     b->NB = std::max(b->NB, (int)c->N);

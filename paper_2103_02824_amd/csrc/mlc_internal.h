@@ -251,6 +251,8 @@ int spmm_rows_per_block(int N);
 // Chebyshev polynomial preconditioner of one CG solve (null pointer: Jacobi).
 // Preconditioner of the Hartree CG: hartree_precond, or precond when it is -1.
 inline int hartree_pc(const mlc_options& o) { return o.hartree_precond < 0 ? o.precond : o.hartree_precond; }
+inline int hartree_deg(const mlc_options& o) { return o.hartree_cheb_degree > 0 ? o.hartree_cheb_degree : o.cheb_degree; }
+inline double hartree_ratio(const mlc_options& o) { return o.hartree_cheb_ratio > 0 ? o.hartree_cheb_ratio : o.cheb_ratio; }
 
 template <typename T>
 struct PolyPC {

@@ -781,7 +781,7 @@ mlc_status fine_stage_and_step(mlc_ctx* c, mlc_step_report* rep) {
   if (c->hartree) {
     double dummy = 0.0;
     int64_t dn = 0;
-    PolyPC<double> pcK{d.lmax + 1, c->opt.cheb_ratio, c->opt.cheb_degree, {d.Yh, d.Yh + n},
+    PolyPC<double> pcK{d.lmax + 1, hartree_ratio(c->opt), hartree_deg(c->opt), {d.Yh, d.Yh + n},
                        d.red + cg_max_blocks(), d.valK32};
     CoarsePC ccK{d.KHinv, c->nH, d.PTptr, d.PTidx, d.PTw, d.Pk, d.Pw, d.rH, d.eH, d.Yh + 3 * n,
                  d.red + cg_max_blocks()};

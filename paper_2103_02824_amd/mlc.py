@@ -66,7 +66,8 @@ class Options(C.Structure):
                 ("precond", C.c_int32), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("hartree_coarse", C.c_int32), ("hartree_precond", C.c_int32),
                 ("inner_mix_history", C.c_int32), ("inner_mix_beta", C.c_double), ("variant", C.c_int32),
-                ("estimator", C.c_int32), ("cheb_lanczos", C.c_int32)]
+                ("estimator", C.c_int32), ("cheb_lanczos", C.c_int32),
+                ("hartree_cheb_degree", C.c_int32), ("hartree_cheb_ratio", C.c_double)]
 
 PREC_FP64, PREC_FP32_IR = 0, 1
 PC_JACOBI, PC_CHEBYSHEV = 0, 1

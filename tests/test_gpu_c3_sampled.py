@@ -63,10 +63,10 @@ def _c3_step():
     from inputs.systems import c3_cluster
     from paper_2103_02824_amd import mlc
     print("case 40-atom cluster seed 0, full size: mesh", flush=True)
-    S = c3_cluster(0, progress=lambda m: print(m, flush=True))
+    S = c3_cluster(0, order=1, progress=lambda m: print(m, flush=True))
     opts = mlc.options(cg_rtol=1e-12, poisson_rtol=1e-12, inner_maxit=1, inner_tol=1e-9, shift=1, sigma0=1.0,
                        precision=mlc.PREC_FP32_IR, precond=mlc.PC_CHEBYSHEV, cheb_degree=8, cheb_ratio=100.0,
-                       hartree_coarse=1)
+                       hartree_cheb_degree=8, hartree_cheb_ratio=300.0, hartree_coarse=1)
     ctx = mlc.Context(S, opts)
     n, N = ctx.n_dof, ctx.N
     assert (n, N) == (2004523, 52)

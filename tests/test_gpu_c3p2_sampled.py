@@ -34,7 +34,7 @@ def _c3p2_step():
     S = c3_cluster(0, order=2, progress=lambda m: print(m, flush=True))
     opts = mlc.options(cg_rtol=1e-12, poisson_rtol=1e-12, inner_maxit=1, inner_tol=1e-9, shift=1, sigma0=1.0,
                        precision=mlc.PREC_FP32_IR, precond=mlc.PC_CHEBYSHEV, cheb_degree=16, cheb_ratio=300.0,
-                       cheb_lanczos=16, hartree_coarse=1)
+                       cheb_lanczos=16, hartree_cheb_degree=8, hartree_cheb_ratio=300.0, hartree_coarse=1)
     ctx = mlc.Context(S, opts)
     n, N = ctx.n_dof, ctx.N
     print(f"case 40-atom P2: n_dof={n} nodes={ctx.n_vertices} N={N}", flush=True)

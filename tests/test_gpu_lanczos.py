@@ -1,4 +1,4 @@
-"""The Lanczos estimate of the Chebyshev interval's upper end (option
+"""The Chebyshev preconditioner's options. The Lanczos estimate of the interval's upper end (option
 cheb_lanczos) against the checker: the library's lambda_max for the step-5
 operator A + sigma M and for K lies between the true largest eigenvalue of
 D^-1 A (the checker's operator, dense symmetric eigensolve of
@@ -55,3 +55,27 @@ def test_lanczos_upper_end_and_step(gpu, case):
     assert np.max(np.abs(lam - ref.state.lam)) < 1e-8, (lam, ref.state.lam)
     assert relerr(rho, ref.rho_nodal) < 1e-6
     ctx.close()
+
+
+def test_hartree_polynomial_options(gpu):
+    """hartree_cheb_degree / hartree_cheb_ratio set the Hartree CG's polynomial
+    apart from step 5's: the Hartree iteration count changes, the step-5 count
+    does not, and the results still match the checker."""
+    from paper_2103_02824_amd import mlc
+    S = CASES["tiny2"]()
+    prob = Problem(S)
+    st0, _ = initial_state(prob)
+    base = dict(LIB_OPTS, precond=mlc.PC_CHEBYSHEV, cheb_degree=8, cheb_ratio=100.0, hartree_coarse=1)
+    reps = []
+    for extra in ({}, dict(hartree_cheb_degree=3, hartree_cheb_ratio=20.0)):
+        ctx = mlc.Context(S, mlc.options(**dict(base, **extra)))
+        ctx.set_state(st0.lam, st0.Phi, st0.w)
+        reps.append(ctx.correction_step())
+        lam, Phi, w, rho = ctx.get_results()
+        ctx.close()
+    ref = correction_step(prob, st0, ORA_OPTS)
+    assert np.max(np.abs(lam - ref.state.lam)) < 1e-8 and relerr(rho, ref.rho_nodal) < 1e-6
+    print(f"Hartree iterations {reps[0]['poisson_iters']} -> {reps[1]['poisson_iters']}, step 5 "
+          f"{reps[0]['cg_iters_max']} -> {reps[1]['cg_iters_max']}", flush=True)
+    assert reps[1]["poisson_iters"] > reps[0]["poisson_iters"]
+    assert reps[1]["cg_iters_max"] == reps[0]["cg_iters_max"]
