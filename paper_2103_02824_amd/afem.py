@@ -27,11 +27,14 @@ def interior_vertices(xyz, lo, hi):
 
 
 def adapt(system, opts=None, theta=0.4, levels=3, steps=1, state=None, tags=None, init=(1e-10, 200),
-          progress=None):
+          progress=None, tol=None):
     """Run `levels` meshes of the adaptive loop from system's fine mesh.
 
     opts: library options (estimator is switched on); theta: Doerfler
-    parameter (0.4 in Section 4); steps: correction steps per mesh; state:
+    parameter (0.4 in Section 4); steps: correction steps per mesh, or with
+    tol the most steps per mesh, stopping once the eigenvalues change by less
+    than tol between two steps (the outer iteration of Algorithm 1 run to
+    convergence on each mesh, as the iteration counts of Section 4 are); state:
     optional (lam, Phi, w) on the first mesh (host arrays or device tensors;
     else mlc_initial_state with init = (tol, maxit)); tags: bisection tags of
     the first mesh's tets (default 3, right for a Kuhn-ordered mesh).
@@ -51,11 +54,21 @@ def adapt(system, opts=None, theta=0.4, levels=3, steps=1, state=None, tags=None
         ctx.set_state(*state)
     out = []
     for lev in range(levels):
-        reps = [ctx.correction_step() for _ in range(steps)]
+        reps = []
+        lam_prev = ctx.get_results()[0] if tol is not None else None
+        for _ in range(steps):
+            reps.append(ctx.correction_step())
+            if tol is not None:
+                lam_now = ctx.get_results()[0]
+                done = float(np.max(np.abs(lam_now - lam_prev))) < tol
+                lam_prev = lam_now
+                if done:
+                    break
         eta2 = ctx.estimate().cpu().numpy()
         lam, Phi, w, _ = ctx.get_results_device()
         rec = {"level": lev, "n_dof": ctx.n_dof, "n_tets": ctx.n_tets, "lam": lam.copy(),
-               "eta": float(np.sqrt(eta2.sum())), "reports": reps, "marked": 0}
+               "eta": float(np.sqrt(eta2.sum())), "reports": reps, "marked": 0, "outer": len(reps),
+               "inner": [int(r["inner_iters"]) for r in reps]}
         out.append(rec)
         if progress:
             progress(rec)

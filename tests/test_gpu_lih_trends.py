@@ -44,3 +44,35 @@ def test_lih_inner_counts_and_orthogonality_over_outer_steps(gpu):
     assert all(b <= 1.001 * a for a, b in zip(ovl[8:], ovl[9:])), ovl
     assert ovl[-1] < 0.3 * ovl[0], ovl
     ctx.close()
+
+
+def test_lih_on_the_adaptive_loop(gpu):
+    """LiH through the adaptive loop (Algorithm 1 with the residual estimator,
+    Doerfler marking theta = 0.4, bisection, transfer; Section 4's first
+    model), from a 16^3 Kuhn fine mesh over an 8^3 coarse one, five correction
+    steps per mesh: over eight meshes the estimate falls at every level, the
+    mesh grows around the nuclei, the lowest eigenvalue falls (the finer
+    spaces resolve the Li core), and the electron count holds."""
+    from inputs.meshgen import kuhn_mesh
+    from inputs.systems import LIH_R, LIH_Z, POT_BARE, XC_XALPHA, System
+    from paper_2103_02824_amd import afem, mlc
+    xyz, tets = kuhn_mesh(16, -6.0, 6.0)
+    cxyz, ctets = kuhn_mesh(8, -6.0, 6.0)
+    S = System(name="lih_kuhn", R=LIH_R.copy(), Z=LIH_Z.copy(), lo=-6.0, hi=6.0, potential=POT_BARE,
+               n_orbitals=2, occupations=np.array([2.0, 2.0]), xc=XC_XALPHA, xalpha=0.77298,
+               xyz=xyz, tets=tets, cxyz=cxyz, ctets=ctets)
+    opts = mlc.options(cg_rtol=1e-11, poisson_rtol=1e-12, inner_tol=1e-10, inner_maxit=300,
+                       precond=mlc.PC_CHEBYSHEV, cheb_degree=8, cheb_ratio=100.0, hartree_coarse=1)
+    print("case LiH on the adaptive loop: 16^3 / 8^3 Kuhn, eight meshes", flush=True)
+    recs, ctx = afem.adapt(S, opts, theta=0.4, levels=8, steps=5,
+                           progress=lambda r: print(f"level {r['level']}: dof {r['n_dof']}, lambda {r['lam']}, "
+                                                    f"eta {r['eta']:.4e}, inner {r['inner']}", flush=True))
+    ctx.close()
+    eta = [r["eta"] for r in recs]
+    dof = [r["n_dof"] for r in recs]
+    lam1 = [float(np.min(r["lam"])) for r in recs]
+    assert all(b < a for a, b in zip(eta, eta[1:])), eta
+    assert all(b >= a for a, b in zip(dof, dof[1:])) and dof[-1] > dof[0], dof
+    assert lam1[-1] < lam1[0] - 0.1, lam1
+    for r in recs:
+        assert abs(r["reports"][-1]["rho_integral"] - 4.0) < 1e-9
