@@ -3,9 +3,10 @@
 step (step-5 solutions per column, Hartree direction, boundary data, Gram
 blocks, coarse-pattern integrals), then eigenvalues, density and energy, on
 a P2 space over the coarse mesh itself and over a refinement of it; the
-initial state; whole steps in a row; and the FP32 + Chebyshev configuration
-of the large workloads. Tolerances as for P1: eigenvalues 1e-8 Ha, density
-1e-6 relative L2, blocks 1e-8 at CG tolerance 1e-12."""
+initial state; whole steps in a row; the FP32 + Chebyshev configuration of
+the large workloads; and P2 systems in a batch beside a P1 one. Tolerances
+as for P1: eigenvalues 1e-8 Ha, density 1e-6 relative L2, blocks 1e-8 at CG
+tolerance 1e-12."""
 import numpy as np
 import pytest
 
@@ -104,3 +105,34 @@ def test_p2_fp32_refinement_with_chebyshev(gpu):
     assert np.max(np.abs(lam - ref.state.lam)) < 1e-8, (lam, ref.state.lam)
     assert relerr(rho, ref.rho_nodal) < 1e-6
     ctx.close()
+
+
+def test_p2_systems_in_a_batch(gpu):
+    """A batch mixing two P2 systems and a P1 one (mlc_batch_*: the batched
+    CG over every system's rows, the other phases per system with their own
+    element kernels) reaches each system's checker results."""
+    from paper_2103_02824_amd import mlc
+    systems = [CASES["same_mesh"](), CASES["nested"](),
+               tiny_system(n_fine=8, n_coarse=4, box=5.0, nonlinear=True, n_orbitals=2, seed=7)]
+    kw = dict(LIB_OPTS, precision=mlc.PREC_FP32_IR, ir_inner_rtol=1e-4, precond=mlc.PC_CHEBYSHEV, cheb_degree=6,
+              cheb_ratio=100.0, hartree_coarse=1)
+    refs, ctxs = [], []
+    for S in systems:
+        prob = Problem(S)
+        st0, _ = initial_state(prob)
+        refs.append(correction_step(prob, st0, ORA_OPTS))
+        ctx = mlc.Context(S, mlc.options(**kw))
+        ctx.set_state(st0.lam, st0.Phi, st0.w)
+        ctxs.append(ctx)
+    print("case batch of two P2 systems and one P1 system", flush=True)
+    batch = mlc.Batch(ctxs)
+    reps, br = batch.step()
+    for S, ctx, rep, ref in zip(systems, ctxs, reps, refs):
+        assert rep["cg_relres_max"] <= 1e-12 * (1 + 1e-6)
+        assert relerr(ctx.probe("U", (ctx.n_dof, ctx.N)), ref.inter["fine"]["U"]) < 1e-8
+        lam, Phi, w, rho = ctx.get_results()
+        assert np.max(np.abs(lam - ref.state.lam)) < 1e-8, (S.order, lam, ref.state.lam)
+        assert relerr(rho, ref.rho_nodal) < 1e-6
+    batch.close()
+    for c in ctxs:
+        c.close()
