@@ -114,16 +114,24 @@ __device__ __forceinline__ int lane_col(int g, int h, int N) {
 }
 
 // acc[h][v] = (A X)[r, lane_col(g, h) + v] for the lane's column group g
-// (meaningful where the group lies within N). The WU column indices and
-// values of a pass are loaded unconditionally (entries past the row end
-// repeat its last entry with weight zero), then the WU gathers: no branch
-// inside the pass, so all of them are in flight together. With O32 (the
-// caller guarantees n N sizeof(T) < 2^32) the gathers address X by a 32-bit
-// byte offset from its base: one register per address instead of two.
+// (meaningful where the group lies within N). The row's L lanes load its
+// column indices and values cooperatively, CH = max(L, WU) entries per
+// chunk (lane g takes entries g, g + L, ...; entries past the row end repeat
+// its last entry with weight zero), and pass them to each other with
+// width-L shuffles: one load instruction per L entries instead of one per
+// entry. Each sub-pass then issues the WU gathers of WU entries with no
+// branch inside, so all of them are in flight together; sub-passes wholly
+// past the row end are skipped (the same for the row's L lanes). With O32
+// (the caller guarantees n N sizeof(T) < 2^32) the gathers address X by a
+// 32-bit byte offset from its base: one register per address instead of two.
+// The L lanes of a row are consecutive lanes of one wavefront, L dividing 64.
 template <int L, int V, int NCH, int WU, bool O32, typename T>
 __device__ __forceinline__ void row_gather_lanes(int64_t r, int g, int N, int jb, int j1,
                                                  const int32_t* __restrict__ col, const T* __restrict__ val,
                                                  const T* __restrict__ X, T (&acc)[NCH][V]) {
+  constexpr int CH = L > WU ? L : WU;   // entries per cooperative chunk
+  constexpr int PER = CH / L;           // entries each lane loads per chunk
+  static_assert(CH % L == 0 && CH % WU == 0, "chunk must hold whole lane rounds and sub-passes");
   T a0[NCH][V], a1[NCH][V];
   int coff[NCH];
 #pragma unroll
@@ -133,37 +141,49 @@ __device__ __forceinline__ void row_gather_lanes(int64_t r, int g, int N, int jb
     for (int v = 0; v < V; ++v) a0[h][v] = a1[h][v] = T(0);
   }
   const uint32_t rowb = (uint32_t)N * (uint32_t)sizeof(T);
-  for (int j = jb; j < j1; j += WU) {
-    int k[WU];
-    T w[WU];
+  for (int j = jb; j < j1; j += CH) {
+    int kl[PER];
+    T wl[PER];
 #pragma unroll
-    for (int u = 0; u < WU; ++u) {
-      const uint32_t e = (uint32_t)(j + u < j1 ? j + u : j1 - 1);
-      k[u] = col[e];
+    for (int i = 0; i < PER; ++i) {
+      const int e0 = j + g + L * i;
+      const uint32_t e = (uint32_t)(e0 < j1 ? e0 : j1 - 1);
+      kl[i] = col[e];
       const T a = val[e];
-      w[u] = j + u < j1 ? a : T(0);
+      wl[i] = e0 < j1 ? a : T(0);
     }
-    T x[WU][NCH][V];
 #pragma unroll
-    for (int u = 0; u < WU; ++u)
+    for (int p = 0; p < CH; p += WU) {
+      if (j + p >= j1) break;
+      int k[WU];
+      T w[WU];
 #pragma unroll
-      for (int h = 0; h < NCH; ++h) {
-        if constexpr (O32) {
-          const uint32_t off = (uint32_t)k[u] * rowb + (uint32_t)coff[h] * (uint32_t)sizeof(T);
-          load_cols<T, V>(reinterpret_cast<const T*>(reinterpret_cast<const char*>(X) + off), x[u][h]);
-        } else {
-          load_cols<T, V>(X + (int64_t)k[u] * N + coff[h], x[u][h]);
-        }
+      for (int u = 0; u < WU; ++u) {
+        k[u] = __shfl(kl[(p + u) / L], (p + u) % L, L);
+        w[u] = __shfl(wl[(p + u) / L], (p + u) % L, L);
       }
+      T x[WU][NCH][V];
 #pragma unroll
-    for (int u = 0; u < WU; u += 2)
+      for (int u = 0; u < WU; ++u)
 #pragma unroll
-      for (int h = 0; h < NCH; ++h)
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          a0[h][v] += w[u] * x[u][h][v];
-          a1[h][v] += w[u + 1] * x[u + 1][h][v];
+        for (int h = 0; h < NCH; ++h) {
+          if constexpr (O32) {
+            const uint32_t off = (uint32_t)k[u] * rowb + (uint32_t)coff[h] * (uint32_t)sizeof(T);
+            load_cols<T, V>(reinterpret_cast<const T*>(reinterpret_cast<const char*>(X) + off), x[u][h]);
+          } else {
+            load_cols<T, V>(X + (int64_t)k[u] * N + coff[h], x[u][h]);
+          }
         }
+#pragma unroll
+      for (int u = 0; u < WU; u += 2)
+#pragma unroll
+        for (int h = 0; h < NCH; ++h)
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            a0[h][v] += w[u] * x[u][h][v];
+            a1[h][v] += w[u + 1] * x[u + 1][h][v];
+          }
+    }
   }
 #pragma unroll
   for (int h = 0; h < NCH; ++h)
