@@ -378,12 +378,13 @@ def main():
     n_replay = 200
     cheb = args.precond == "chebyshev"
     deg = args.cheb_degree if cheb else 1
+    hdeg = (args.hartree_cheb_degree or deg) if cheb else 1   # 0 = the step-5 polynomial's degree
     it5 = float(np.mean([r["cg_iters_max"] for r in reps]))
     itp = float(np.mean([r["poisson_iters"] for r in reps]))
     kern = {}
     cands = [("cg_spmm", N, word, it5 + 2), ("hartree_spmm", 1, 8, itp + 2)]
     if cheb:
-        cands += [("cheb_step", N, word, (deg - 1) * (it5 + 1)), ("hartree_cheb_step", 1, 8, (deg - 1) * (itp + 1))]
+        cands += [("cheb_step", N, word, (deg - 1) * (it5 + 1)), ("hartree_cheb_step", 1, 8, (hdeg - 1) * (itp + 1))]
     for which, ncol, w, launches in cands:
         us = ctx.time_kernel(which, n_replay)
         nbytes = (spmm_bytes(n, nnz, ncol, w) if "spmm" in which else
