@@ -382,6 +382,75 @@ __global__ void __launch_bounds__(BS, W) k_cheb_small(int64_t n, const int32_t* 
   }
 }
 
+// One Chebyshev step j >= 1 for a single FP64 column with FP32 matrix values
+// (the Hartree problem's polynomial steps that produce no partial sums), in
+// a streaming layout: a one-wavefront block owns 64 consecutive rows, one
+// lane per row, and reads the rows' contiguous run of nonzeros [A, B) in
+// windows of S1_WIN entries, lane t taking entries t, t + 64, ... of the
+// window: every column-index and value load is one contiguous 256-byte
+// request, against 16 separate rows' segments with four lanes per row. Each
+// lane writes its products a_e x_{col e} to LDS, and after the barrier each
+// row's lane sums the products of its own entries that fall in the window, in
+// entry order. Entries past B in the last window load entry B - 1 and store a
+// zero product, so every load is in bounds. Rows past n (the last block)
+// own no entries and are not stored. Zout may be Zprev (each row's entry is
+// read before it is written, by its own lane).
+constexpr int S1_WIN = 512;
+__global__ void __launch_bounds__(64, 8) k_cheb_stream1(int64_t n, const int32_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const float* __restrict__ val,
+                                                        const double* __restrict__ dinv,
+                                                        const double* __restrict__ R,
+                                                        const double* __restrict__ Zin, const double* Zprev,
+                                                        double* Zout, const double* __restrict__ lmax, double ratio,
+                                                        int j, const int32_t* __restrict__ flags) {
+  __shared__ double prod[S1_WIN];
+  if (flags && flags[0] == 0) return;
+  double cd, cr;
+  cheb_coef(*lmax, ratio, j, &cd, &cr);
+  const int lane = threadIdx.x;
+  const RowBlocks rbk((n + 63) / 64);
+  for (int64_t rb = rbk.first; rb < rbk.end; rb += rbk.step) {
+    const int64_t r0 = rb * 64;
+    const int64_t r = r0 + lane;
+    const bool live = r < n;
+    const int64_t rr = live ? r : n - 1;
+    const int A = rowptr[r0];
+    const int B = rowptr[r0 + 64 < n ? r0 + 64 : n];
+    const int rs = live ? rowptr[rr] : B;
+    const int re = live ? rowptr[rr + 1] : B;
+    const double di = dinv[rr], rv = R[rr], zv = Zin[rr], pv = Zprev[rr];
+    double s = 0.0;
+    for (int wa = A; wa < B; wa += S1_WIN) {
+      const int we = wa + S1_WIN < B ? wa + S1_WIN : B;
+      int c[S1_WIN / 64];
+      float a[S1_WIN / 64];
+#pragma unroll
+      for (int k = 0; k < S1_WIN / 64; ++k) {
+        const int e = wa + lane + 64 * k;
+        const int ec = e < we ? e : we - 1;
+        c[k] = col[ec];
+        const float av = val[ec];
+        a[k] = e < we ? av : 0.0f;
+      }
+      double x[S1_WIN / 64];
+#pragma unroll
+      for (int k = 0; k < S1_WIN / 64; ++k) x[k] = Zin[c[k]];
+#pragma unroll
+      for (int k = 0; k < S1_WIN / 64; ++k) prod[lane + 64 * k] = (double)a[k] * x[k];
+      __syncthreads();
+      const int lo = (rs > wa ? rs : wa) - wa;
+      const int hi = (re < we ? re : we) - wa;
+      for (int t = lo; t < hi; ++t) s += prod[t];
+      __syncthreads();
+    }
+    if (live) {
+      const double dv = j > 1 ? zv - pv : zv;
+      Zout[r] = zv + (cd * dv + cr * (di * (rv - s)));
+    }
+  }
+}
+
 // The fused Chebyshev step for N > 8 in the same layout: w = A Zin;
 // Zout = Zin + cd (Zin - Zprev) + cr D^-1 (R - w) (Zprev = 0 for j = 1; Zout
 // may be Zprev); with PART, per-block column sums of R . Zout into partial (a
@@ -1122,10 +1191,8 @@ void launch_cheb_step_t(hipStream_t s, int64_t n, int N, const int32_t* rowptr, 
                            dim3(cap_xcd(needed, SPMM_MAXBLK)), dim3(SPMM_BS), 0, s, n, rowptr, col, pc.val32, dinv,
                            Rv, zin, zprev, zout, pc.lmax, pc.ratio, j, part, flags);
       } else {
-        const int64_t needed = (n + (TPB / ROW_G) - 1) / (TPB / ROW_G);
-        hipLaunchKernelGGL((k_cheb_small<1, ROW_G, unroll_wide(1), TPB, waves_wide(1), T, float>),
-                           dim3(cap_xcd(needed, 1 << 30)), dim3(TPB), 0, s, n, rowptr, col, pc.val32, dinv, Rv, zin,
-                           zprev, zout, pc.lmax, pc.ratio, j, part, flags);
+        hipLaunchKernelGGL(k_cheb_stream1, dim3(cap_xcd((n + 63) / 64, 1 << 30)), dim3(64), 0, s, n, rowptr, col,
+                           pc.val32, dinv, Rv, zin, zprev, zout, pc.lmax, pc.ratio, j, flags);
       }
       return;
     }
