@@ -47,23 +47,67 @@ void backward(const std::vector<double>& L, int64_t n, double* x) {
   }
 }
 
+namespace {
+
+// forward() on nb <= B right-hand sides at once, stored interleaved
+// (X[k B + b] is entry k of right-hand side b): each row of L is read once
+// for all of them instead of once per right-hand side. Every right-hand side
+// takes the same operations in the same order as forward(), so the results
+// are the same.
+template <int B>
+void forward_block(const std::vector<double>& L, int64_t n, double* X, int nb) {
+  for (int64_t i = 0; i < n; ++i) {
+    const double* Li = &L[i * n];
+    double s[B];
+    for (int b = 0; b < B; ++b) s[b] = X[i * B + b];
+    for (int64_t k = 0; k < i; ++k) {
+      const double lk = Li[k];
+      const double* xk = &X[k * B];
+      for (int b = 0; b < B; ++b) s[b] -= lk * xk[b];
+    }
+    for (int b = 0; b < B; ++b) X[i * B + b] = s[b] / Li[i];
+  }
+  (void)nb;
+}
+
+constexpr int CONG_B = 16;  // right-hand sides per pass over L
+
+}  // namespace
+
 void congruence(const std::vector<double>& L, const std::vector<double>& A, int64_t n, std::vector<double>& C) {
-  // X = L^{-1} A: column j of A (= row j, A symmetric) solved into row j of Xt
+  const int64_t nblk = (n + CONG_B - 1) / CONG_B;
+  // X = L^{-1} A: column j of A (= row j, A symmetric) solved into row j of Xt,
+  // CONG_B columns per pass (the unused slots of the last pass hold zeros)
   std::vector<double> Xt(n * n);
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t j = 0; j < n; ++j) {
-    double* x = &Xt[j * n];
-    for (int64_t i = 0; i < n; ++i) x[i] = A[j * n + i];
-    forward(L, n, x);
+#pragma omp parallel
+  {
+    std::vector<double> X(n * CONG_B);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+      const int64_t j0 = blk * CONG_B;
+      const int nb = (int)std::min<int64_t>(CONG_B, n - j0);
+      for (int64_t i = 0; i < n; ++i)
+        for (int b = 0; b < CONG_B; ++b) X[i * CONG_B + b] = b < nb ? A[(j0 + b) * n + i] : 0.0;
+      forward_block<CONG_B>(L, n, X.data(), nb);
+      for (int b = 0; b < nb; ++b)
+        for (int64_t i = 0; i < n; ++i) Xt[(j0 + b) * n + i] = X[i * CONG_B + b];
+    }
   }
   // C = L^{-1} X^T: column j of X^T = row j of X = column j of Xt
   C.assign(n * n, 0.0);
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t j = 0; j < n; ++j) {
-    std::vector<double> x(n);
-    for (int64_t i = 0; i < n; ++i) x[i] = Xt[i * n + j];
-    forward(L, n, x.data());
-    for (int64_t i = 0; i < n; ++i) C[j * n + i] = x[i];
+#pragma omp parallel
+  {
+    std::vector<double> X(n * CONG_B);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+      const int64_t j0 = blk * CONG_B;
+      const int nb = (int)std::min<int64_t>(CONG_B, n - j0);
+      for (int64_t i = 0; i < n; ++i)
+        for (int b = 0; b < CONG_B; ++b) X[i * CONG_B + b] = b < nb ? Xt[i * n + j0 + b] : 0.0;
+      forward_block<CONG_B>(L, n, X.data(), nb);
+      for (int b = 0; b < nb; ++b)
+        for (int64_t i = 0; i < n; ++i) C[(j0 + b) * n + i] = X[i * CONG_B + b];
+    }
   }
   // symmetrise against rounding
 #pragma omp parallel for schedule(static)

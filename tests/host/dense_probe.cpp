@@ -49,3 +49,13 @@ extern "C" int probe_select(const double* C0, const double* uc, double alpha, in
   for (int r = 0; r < n; ++r) y_out[r] = y[r];
   return j;
 }
+
+// C = L^{-1} A L^{-T} with L the Cholesky factor of M (the pencil reduction
+// of every inner iteration); returns 0 when M is not positive definite.
+extern "C" int probe_congruence(const double* M0, const double* A0, int n, double* C_out) {
+  std::vector<double> L(M0, M0 + (std::size_t)n * n), A(A0, A0 + (std::size_t)n * n), C;
+  if (!cholesky(L, n)) return 0;
+  congruence(L, A, n, C);
+  for (std::size_t i = 0; i < (std::size_t)n * n; ++i) C_out[i] = C[i];
+  return 1;
+}

@@ -220,3 +220,27 @@ def test_selection_prefers_the_component_along_u(lib):
     assert j == 2 and abs(pj - 0.9) < 1e-9
     # the largest border weight |theta_2| (the other reading) would keep the second eigenvector
     assert int(np.argmax(np.abs(V[n, :4]))) == 1
+
+
+@pytest.mark.parametrize("n", [1, 5, 16, 17, 40, 75])
+def test_congruence_matches_triangular_solves(lib, n):
+    """The reduction C = L^-1 A L^-T of the pencil (A_H, M_H) with M_H = L L^T,
+    computed several right-hand sides per pass over L (orders that are not a
+    multiple of the block width included), against numpy's Cholesky and
+    triangular solves."""
+    rng = np.random.default_rng(100 + n)
+    R = rng.standard_normal((n, n))
+    M = R @ R.T / n + np.eye(n)
+    A = rng.standard_normal((n, n))
+    A = 0.5 * (A + A.T)
+    C = np.zeros((n, n))
+    lib.probe_congruence.restype = ctypes.c_int
+    ok = lib.probe_congruence(np.ascontiguousarray(M).ctypes.data_as(P), np.ascontiguousarray(A).ctypes.data_as(P),
+                              ctypes.c_int(n), C.ctypes.data_as(P))
+    assert ok == 1
+    L = np.linalg.cholesky(M)
+    X = np.linalg.solve(L, A)
+    ref = np.linalg.solve(L, X.T)
+    ref = 0.5 * (ref + ref.T)
+    assert np.array_equal(C, C.T)
+    assert np.max(np.abs(C - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
