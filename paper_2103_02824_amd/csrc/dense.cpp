@@ -119,6 +119,15 @@ void congruence(const std::vector<double>& L, const std::vector<double>& A, int6
     }
 }
 
+// Householder reduction, one column k at a time: v from column k below the
+// diagonal, p = tau C22 v, w = p - (tau/2)(p.v) v, C22 -= v w^T + w v^T.
+// The rank-2 update of column k is applied row by row in the same pass that
+// forms the next column's product C22 v: first the next column itself is
+// brought up to date (it defines the next reflector), then each row of the
+// trailing matrix is updated and, while it is in cache, multiplied by the
+// next v. Every element receives the same operations in the same order as
+// with separate passes (update, then product), so the result is the same;
+// the trailing matrix is streamed twice per column instead of three times.
 void tridiagonalize(std::vector<double>& C, int64_t n, Tridiag& T) {
   T.n = n;
   T.V.assign(n * n, 0.0);
@@ -126,8 +135,24 @@ void tridiagonalize(std::vector<double>& C, int64_t n, Tridiag& T) {
   T.d.assign(n, 0.0);
   T.e.assign(n > 1 ? n - 1 : 0, 0.0);
   std::vector<double> v(n), p(n);
+  // pending rank-2 update of rows and columns q0..n-1: C[r][c] -= xu[r-q0] wu[c-q0] + wu[r-q0] xu[c-q0]
+  std::vector<double> xu(n), wu(n);
+  bool pending = false;
+  int64_t q0 = 0;
+  // apply the pending update to row r, columns c0..n-1
+  auto update_row = [&](int64_t r, int64_t c0) {
+    double* Cr = &C[r * n];
+    const double xi = xu[r - q0], wi = wu[r - q0];
+    for (int64_t c = c0; c < n; ++c) Cr[c] -= xi * wu[c - q0] + wi * xu[c - q0];
+  };
   for (int64_t k = 0; k + 2 < n; ++k) {
     int64_t m = n - k - 1;  // trailing size
+    // column k (rows k..n-1) brought up to date
+    if (pending)
+      for (int64_t r = k; r < n; ++r) {
+        const int64_t i = r - q0;
+        C[r * n + k] -= xu[i] * wu[0] + wu[i] * xu[0];
+      }
     double* x = &v[k + 1];
     double nrm2 = 0.0;
     for (int64_t i = 0; i < m; ++i) {
@@ -139,37 +164,77 @@ void tridiagonalize(std::vector<double>& C, int64_t n, Tridiag& T) {
     if (nrm == 0.0) {
       T.e[k] = 0.0;
       T.tau[k] = 0.0;
+      // no reflector: finish the pending update of rows k..n-1
+      if (pending) {
+#pragma omp parallel for schedule(static) if (m > 128)
+        for (int64_t r = k; r < n; ++r) update_row(r, k + 1);
+        pending = false;
+      }
       continue;
     }
     double alpha = x[0] >= 0 ? -nrm : nrm;  // e_k
     x[0] -= alpha;                          // v = x - alpha e1
-    double vv = nrm2 - 2.0 * alpha * (x[0] + alpha) + alpha * alpha;
     // vv = |x - alpha e1|^2 computed directly for safety
-    vv = 0.0;
+    double vv = 0.0;
     for (int64_t i = 0; i < m; ++i) vv += x[i] * x[i];
     double tau = 2.0 / vv;
     T.e[k] = alpha;
     T.tau[k] = tau;
     for (int64_t i = 0; i < m; ++i) T.V[k * n + k + 1 + i] = x[i];
-    // p = tau * C22 v
+    // the pending update of row k (columns k+1..), then of each trailing row
+    // together with p = tau * C22 v
+    // (four rows at a time: their sums are independent chains, each in its
+    // own order, so they overlap in the floating-point pipeline)
+    if (pending) update_row(k, k + 1);
+    const int64_t m4 = (m + 3) / 4;
 #pragma omp parallel for schedule(static) if (m > 128)
-    for (int64_t i = 0; i < m; ++i) {
-      const double* Ci = &C[(k + 1 + i) * n + k + 1];
-      double s = 0.0;
-      for (int64_t j = 0; j < m; ++j) s += Ci[j] * x[j];
-      p[k + 1 + i] = tau * s;
+    for (int64_t i4 = 0; i4 < m4; ++i4) {
+      const int64_t i0 = 4 * i4;
+      if (i0 + 4 <= m) {
+        if (pending)
+          for (int64_t i = i0; i < i0 + 4; ++i) update_row(k + 1 + i, k + 1);
+        const double* C0 = &C[(k + 1 + i0) * n + k + 1];
+        const double* C1 = C0 + n;
+        const double* C2 = C1 + n;
+        const double* C3 = C2 + n;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int64_t j = 0; j < m; ++j) {
+          const double xj = x[j];
+          s0 += C0[j] * xj;
+          s1 += C1[j] * xj;
+          s2 += C2[j] * xj;
+          s3 += C3[j] * xj;
+        }
+        p[k + 1 + i0] = tau * s0;
+        p[k + 2 + i0] = tau * s1;
+        p[k + 3 + i0] = tau * s2;
+        p[k + 4 + i0] = tau * s3;
+      } else {
+        for (int64_t i = i0; i < m; ++i) {
+          if (pending) update_row(k + 1 + i, k + 1);
+          const double* Ci = &C[(k + 1 + i) * n + k + 1];
+          double s = 0.0;
+          for (int64_t j = 0; j < m; ++j) s += Ci[j] * x[j];
+          p[k + 1 + i] = tau * s;
+        }
+      }
     }
     double pv = 0.0;
     for (int64_t i = 0; i < m; ++i) pv += p[k + 1 + i] * x[i];
     double h = 0.5 * tau * pv;
     for (int64_t i = 0; i < m; ++i) p[k + 1 + i] -= h * x[i];  // w
-    const double* w = &p[k + 1];
-#pragma omp parallel for schedule(static) if (m > 128)
+    // this column's update (rows and columns k+1..n-1) becomes the pending one
+    q0 = k + 1;
     for (int64_t i = 0; i < m; ++i) {
-      double* Ci = &C[(k + 1 + i) * n + k + 1];
-      double xi = x[i], wi = w[i];
-      for (int64_t j = 0; j < m; ++j) Ci[j] -= xi * w[j] + wi * x[j];
+      xu[i] = x[i];
+      wu[i] = p[k + 1 + i];
     }
+    pending = true;
+  }
+  if (pending) {
+    const int64_t k0 = q0;
+#pragma omp parallel for schedule(static) if (n - k0 > 128)
+    for (int64_t r = k0; r < n; ++r) update_row(r, k0);
   }
   if (n >= 2) {
     T.d[n - 2] = C[(n - 2) * n + n - 2];
