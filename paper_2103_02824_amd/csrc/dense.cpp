@@ -391,6 +391,119 @@ std::vector<double> lowest_eigenvalues(const Tridiag& T, const double* u, double
   return ev;
 }
 
+namespace {
+
+constexpr int GROUP_P = 4;
+
+// count_below for GROUP_P problems at once (the same operations per problem)
+void count_below_group(const Tridiag& T, const double* const* u, const double* alpha, const double* mu,
+                       const double* pivmin, int64_t* cnt) {
+  const int64_t n = T.n;
+  int64_t c[GROUP_P];
+  double dprev[GROUP_P], wprev[GROUP_P], schur[GROUP_P];
+  for (int q = 0; q < GROUP_P; ++q) {
+    c[q] = 0;
+    dprev[q] = 1.0;
+    wprev[q] = 0.0;
+    schur[q] = alpha[q] - mu[q];
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    for (int q = 0; q < GROUP_P; ++q) {
+      double dj = T.d[j] - mu[q];
+      double wj = u[q][j];
+      if (j > 0) {
+        double ej = T.e[j - 1];
+        dj -= ej * ej / dprev[q];
+        wj -= ej / dprev[q] * wprev[q];
+      }
+      if (std::fabs(dj) < pivmin[q]) dj = -pivmin[q];
+      if (dj < 0) ++c[q];
+      schur[q] -= wj * wj / dj;
+      dprev[q] = dj;
+      wprev[q] = wj;
+    }
+  }
+  for (int q = 0; q < GROUP_P; ++q) cnt[q] = c[q] + (schur[q] < 0 ? 1 : 0);
+}
+
+// the bisection of lowest_eigenvalues as a state machine: next() gives the
+// next point to count at (false once all k eigenvalues are found), feed()
+// takes its count
+struct Bisection {
+  double a0, b0, eps, scale, pivmin, a, b;
+  int k, j, it;
+  std::vector<double>* ev;
+  void start() {
+    a = j > 0 ? std::max(a0, (*ev)[j - 1] - 4 * eps * scale) : a0;
+    b = b0;
+    it = 0;
+  }
+  bool next(double* m) {
+    while (j < k) {
+      const double mm = 0.5 * (a + b);
+      if (it >= 200 || b - a <= 2.0 * eps * std::max(std::fabs(a), std::fabs(b)) + 1e-300 || mm == a || mm == b) {
+        (*ev)[j] = 0.5 * (a + b);
+        if (++j < k) start();
+        continue;
+      }
+      *m = mm;
+      return true;
+    }
+    return false;
+  }
+  void feed(double m, int64_t cnt) {
+    if (cnt > j)
+      b = m;
+    else
+      a = m;
+    ++it;
+  }
+};
+
+}  // namespace
+
+void lowest_eigenvalues_group(const Tridiag& T, int P, const double* const* u, const double* alpha, int k,
+                              std::vector<double>* ev) {
+  Bisection B[GROUP_P];
+  for (int q = 0; q < P; ++q) {
+    double lo, hi = gersh(T, u[q], alpha[q], &lo);
+    Bisection& s = B[q];
+    s.eps = std::numeric_limits<double>::epsilon();
+    s.scale = std::max(std::fabs(lo), std::fabs(hi));
+    s.pivmin = s.eps * std::max(s.scale, 1e-300) * 1e-3;
+    s.a0 = lo - 1e-12 * s.scale - 1e-300;
+    s.b0 = hi + 1e-12 * s.scale;
+    s.k = k;
+    s.j = 0;
+    s.ev = &ev[q];
+    ev[q].assign(k, 0.0);
+    if (k > 0) s.start();
+  }
+  for (;;) {
+    double m[GROUP_P], mu[GROUP_P], pv[GROUP_P], al[GROUP_P];
+    const double* uu[GROUP_P];
+    bool need[GROUP_P];
+    int live = -1;
+    for (int q = 0; q < GROUP_P; ++q) {
+      need[q] = q < P && B[q].next(&m[q]);
+      if (need[q]) live = q;
+    }
+    if (live < 0) break;
+    // slots without a pending count repeat a live one (their counts are not used)
+    for (int q = 0; q < GROUP_P; ++q) {
+      const int r = need[q] ? q : live;
+      uu[q] = u[r];
+      al[q] = alpha[r];
+      mu[q] = m[r];
+      pv[q] = B[r].pivmin;
+    }
+    int64_t cnt[GROUP_P];
+    count_below_group(T, uu, al, mu, pv, cnt);
+    for (int q = 0; q < GROUP_P; ++q)
+      if (need[q]) B[q].feed(m[q], cnt[q]);
+  }
+}
+
 double border_weight(const Tridiag& T, const double* u, double alpha, double mu) {
   // The closed form takes the eigenvector to be x = [z; -1] with
   // z = (T - mu)^{-1} u, which holds when mu solves the secular equation

@@ -34,6 +34,12 @@ void apply_Q(const Tridiag& T, double* x);   // x <- Q x
 // n+1; u may be null for plain T of order n) by bisection on inertia counts.
 // Returns the k lowest eigenvalues in ascending order.
 std::vector<double> lowest_eigenvalues(const Tridiag& T, const double* u, double alpha, int k);
+// The same for P <= 4 bordered problems that share T (borders u[q], corners
+// alpha[q], all non-null), their bisections advanced together so that their
+// inertia counts, each a chain of dependent divisions, overlap: ev[q] is
+// exactly what lowest_eigenvalues(T, u[q], alpha[q], k) returns.
+void lowest_eigenvalues_group(const Tridiag& T, int P, const double* const* u, const double* alpha, int k,
+                              std::vector<double>* ev);
 // Eigenvector of K for eigenvalue mu by inverse iteration (normalised).
 // Output: y (n) and s (border coordinate; unused when u is null).
 void eigenvector(const Tridiag& T, const double* u, double alpha, double mu, double* y, double* s);

@@ -309,6 +309,10 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
   mlc_status st = MLC_OK;
   int maxit = std::max(1, c->opt.inner_maxit);
   std::vector<double> xin(nH + 1), xout(nH + 1, 0.0), fres(nH + 1), gres(nH + 1);
+  // per orbital, within one inner iteration: border in the tridiagonal basis,
+  // corner entry, lowest eigenvalues
+  std::vector<double> Ub(nH * N), alphab(N);
+  std::vector<std::vector<double>> evb(N);
   Anderson mix;
   mix.m = c->opt.inner_mix_history;
   mix.beta = c->opt.inner_mix_beta;
@@ -322,14 +326,21 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
     }
     congruence(L, AH, nH, Cm);
     tridiagonalize(Cm, nH, Tr);
-    // the N augmented problems are independent given A_H: one orbital per thread
+    // the N augmented problems are independent given A_H. Three passes over
+    // the orbitals: their borders (one orbital per thread), the bisections
+    // for their lowest eigenvalues (GROUP orbitals per thread, their inertia
+    // counts advanced together), then the selection and reconstruction (one
+    // orbital per thread); each orbital's arithmetic is that of one pass.
+    constexpr int GROUP = 4;
+    const int ngroup = (N + GROUP - 1) / GROUP;
     int bad = 0;
 #pragma omp parallel if (N > 1)
     {
-      std::vector<double> b(nH), Aa(nH), u(nH), y(nH), tmp(nH), vy(nH);
-#pragma omp for schedule(dynamic, 1) reduction(+ : bad)
+      std::vector<double> b(nH), Aa(nH), y(nH), tmp(nH), vy(nH);
+#pragma omp for schedule(dynamic, 1)
       for (int i = 0; i < N; ++i) {
         const double* ai = &aM[(int64_t)i * nH];
+        double* u = &Ub[(int64_t)i * nH];
         // border of orbital i (eqs. bdef, betadef)
         if (hart) ah4_apply(i, wH.data(), tmp.data());
         double beta = fb.utF[i * N + i] + th1 * fb.utW[i * N + i];
@@ -342,18 +353,32 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
         const double gp = gpv[i], sg = std::sqrt(gp);
         double bp = beta - 2.0 * ba + aAa;
         for (int64_t k = 0; k < nH; ++k) u[k] = b[k] - Aa[k];
-        forward(L, nH, u.data());
+        forward(L, nH, u);
         for (int64_t k = 0; k < nH; ++k) u[k] /= sg;
-        apply_QT(Tr, u.data());
-        double alpha = bp / gp;
-        std::vector<double> ev = lowest_eigenvalues(Tr, u.data(), alpha, n_keep);
+        apply_QT(Tr, u);
+        alphab[i] = bp / gp;
+      }
+#pragma omp for schedule(dynamic, 1)
+      for (int g = 0; g < ngroup; ++g) {
+        const int i0 = g * GROUP, P = std::min(GROUP, N - i0);
+        const double* up[GROUP];
+        for (int q = 0; q < P; ++q) up[q] = &Ub[(int64_t)(i0 + q) * nH];
+        lowest_eigenvalues_group(Tr, P, up, &alphab[i0], n_keep, &evb[i0]);
+      }
+#pragma omp for schedule(dynamic, 1) reduction(+ : bad)
+      for (int i = 0; i < N; ++i) {
+        const double* ai = &aM[(int64_t)i * nH];
+        const double* u = &Ub[(int64_t)i * nH];
+        const double sg = std::sqrt(gpv[i]);
+        const double alpha = alphab[i];
+        const std::vector<double>& ev = evb[i];
         // (a): the eigenfunction with the largest component in span{u_i}; u_i
         // has the coordinates [Q^T L^T a_i; sqrt(gamma')] (its coarse part P a_i
         // and its part M-orthogonal to V_H)
         std::copy(&LTa[(int64_t)i * nH], &LTa[(int64_t)i * nH] + nH, vy.begin());
         apply_QT(Tr, vy.data());
         double sv, pj;
-        const int jsel = select_projection(Tr, u.data(), alpha, ev, vy.data(), sg, y.data(), &sv, &pj);
+        const int jsel = select_projection(Tr, u, alpha, ev, vy.data(), sg, y.data(), &sv, &pj);
         (void)pj;
         apply_Q(Tr, y.data());
         backward(L, nH, y.data());

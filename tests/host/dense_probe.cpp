@@ -59,3 +59,28 @@ extern "C" int probe_congruence(const double* M0, const double* A0, int n, doubl
   for (std::size_t i = 0; i < (std::size_t)n * n; ++i) C_out[i] = C[i];
   return 1;
 }
+
+// lowest_eigenvalues_group on P problems sharing T (from C) against P
+// separate lowest_eigenvalues calls: ev_group and ev_single, P x k each.
+extern "C" void probe_group(const double* C0, int n, int P, const double* U, const double* alpha, int k,
+                            double* ev_group, double* ev_single) {
+  std::vector<double> C(C0, C0 + (std::size_t)n * n);
+  Tridiag Tr;
+  tridiagonalize(C, n, Tr);
+  std::vector<std::vector<double>> Ut(P, std::vector<double>(n));
+  std::vector<const double*> up(P);
+  for (int q = 0; q < P; ++q) {
+    for (int i = 0; i < n; ++i) Ut[q][i] = U[(std::size_t)q * n + i];
+    apply_QT(Tr, Ut[q].data());
+    up[q] = Ut[q].data();
+  }
+  std::vector<std::vector<double>> evg(P);
+  lowest_eigenvalues_group(Tr, P, up.data(), alpha, k, evg.data());
+  for (int q = 0; q < P; ++q) {
+    std::vector<double> evs = lowest_eigenvalues(Tr, up[q], alpha[q], k);
+    for (int j = 0; j < k; ++j) {
+      ev_group[(std::size_t)q * k + j] = evg[q][j];
+      ev_single[(std::size_t)q * k + j] = evs[j];
+    }
+  }
+}

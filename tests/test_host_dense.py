@@ -244,3 +244,27 @@ def test_congruence_matches_triangular_solves(lib, n):
     ref = 0.5 * (ref + ref.T)
     assert np.array_equal(C, C.T)
     assert np.max(np.abs(C - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("name,C,u,alpha", list(_cases()), ids=lambda v: v if isinstance(v, str) else "")
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+def test_grouped_bisection_equals_separate_calls(lib, name, C, u, alpha, P):
+    """The bisections of several orbitals' bordered problems advanced together
+    (their inertia counts interleaved) give exactly the eigenvalues of separate
+    calls, bit for bit, and those match the dense eigensolver."""
+    n, k = len(u), 12
+    rng = np.random.default_rng(P)
+    U = np.stack([u * (1.0 + 0.1 * q) + (0.0 if name == "split_uncoupled_block" else 0.01 * q)
+                  * rng.standard_normal(n) for q in range(P)])
+    al = np.array([alpha + 0.05 * q for q in range(P)])
+    evg, evs = np.zeros(P * k), np.zeros(P * k)
+    lib.probe_group(np.ascontiguousarray(C).ctypes.data_as(P_), ctypes.c_int(n), ctypes.c_int(P),
+                    np.ascontiguousarray(U).ctypes.data_as(P_), al.ctypes.data_as(P_), ctypes.c_int(k),
+                    evg.ctypes.data_as(P_), evs.ctypes.data_as(P_))
+    assert np.array_equal(evg, evs)
+    for q in range(P):
+        lam, _ = _dense(C, U[q], al[q])
+        assert np.max(np.abs(evg[q * k:(q + 1) * k] - lam[:k])) < 1e-12 * np.max(np.abs(lam))
+
+
+P_ = ctypes.POINTER(ctypes.c_double)
