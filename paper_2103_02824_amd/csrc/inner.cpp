@@ -313,6 +313,12 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
   // corner entry, lowest eigenvalues
   std::vector<double> Ub(nH * N), alphab(N);
   std::vector<std::vector<double>> evb(N);
+  // Hartree right-hand side: coarse DoF of each tet vertex (-1 on the
+  // boundary), and each orbital's addends
+  std::vector<int> hs_dof(hart ? 4 * c->cnt : 0);
+  for (int64_t C = 0; C < (hart ? c->cnt : 0); ++C)
+    for (int q = 0; q < 4; ++q) hs_dof[4 * C + q] = c->cv2d[c->ctets[4 * C + q]];
+  std::vector<double> hs_tet(hart ? (int64_t)N * c->cnt * 4 : 0), hs_dofv(hart ? nH * N : 0), hs_g(N);
   Anderson mix;
   mix.m = c->opt.inner_mix_history;
   mix.beta = c->opt.inner_mix_beta;
@@ -393,38 +399,56 @@ mlc_status inner_loop(mlc_ctx* c, const FineBlocks& fb, InnerOut& out) {
     // (b) Hartree problem in W_{H,h} (eqs. Hartree_H_h, fH, gdef with the
     //     factor 2, the theta2^2 term and the occupations)
     if (hart) {
+      // each orbital's addends in parallel (its trilinear terms per coarse tet
+      // and vertex, its A_h4 and rhs terms per coarse DoF, its scalar), then
+      // added into fH and gsum in orbital order, as one pass would
+#pragma omp parallel if (N > 1)
+      {
+        std::vector<double> ph(nH), tq(nH);
+#pragma omp for schedule(dynamic, 1)
+        for (int i = 0; i < N; ++i) {
+          double f = c->occ[i];
+          if (f == 0.0) continue;
+          for (int64_t k = 0; k < nH; ++k) ph[k] = phiH[k * N + i];
+          double t2 = theta2[i];
+          double* sa = &hs_tet[(int64_t)i * c->cnt * 4];
+          // (phi_H^2, psi_j) through the trilinear tensor
+          for (int64_t C = 0; C < c->cnt; ++C) {
+            const int* k = &hs_dof[4 * C];
+            double pl[4];
+            for (int q = 0; q < 4; ++q) pl[q] = k[q] >= 0 ? ph[k[q]] : 0.0;
+            const double* T = &c->h_tri[20 * C];
+            for (int j = 0; j < 4; ++j) {
+              if (k[j] < 0) continue;
+              double sacc = 0.0;
+              for (int m = 0; m < 4; ++m)
+                for (int l = 0; l < 4; ++l) sacc += T[ti.idx[j][m][l]] * pl[m] * pl[l];
+              sa[4 * C + j] = f * sacc;
+            }
+          }
+          ah4_apply(i, ph.data(), tq.data());
+          double* so = &hs_dofv[(int64_t)i * nH];
+          for (int64_t k = 0; k < nH; ++k) so[k] = f * (2.0 * t2 * tq[k] + t2 * t2 * rhsv[k * N + i]);
+          symv(G, nH, ph.data(), tq.data());
+          double g1 = dot(ph.data(), tq.data(), nH);
+          double g2 = 0.0;
+          for (int64_t k = 0; k < nH; ++k) g2 += fb.ptW[k * N + i] * ph[k];
+          hs_g[i] = f * (g1 + 2.0 * t2 * g2 + t2 * t2 * fb.utW[i * N + i]);
+        }
+      }
       std::fill(fH.begin(), fH.end(), 0.0);
       double gsum = 0.0;
-      std::vector<double> ph(nH);
       for (int i = 0; i < N; ++i) {
-        double f = c->occ[i];
-        if (f == 0.0) continue;
-        for (int64_t k = 0; k < nH; ++k) ph[k] = phiH[k * N + i];
-        double t2 = theta2[i];
-        // (phi_H^2, psi_j) through the trilinear tensor
-        for (int64_t C = 0; C < c->cnt; ++C) {
-          int k[4];
-          double pl[4];
-          for (int q = 0; q < 4; ++q) {
-            k[q] = c->cv2d[c->ctets[4 * C + q]];
-            pl[q] = k[q] >= 0 ? ph[k[q]] : 0.0;
-          }
-          const double* T = &c->h_tri[20 * C];
+        if (c->occ[i] == 0.0) continue;
+        const double* sa = &hs_tet[(int64_t)i * c->cnt * 4];
+        for (int64_t C = 0; C < c->cnt; ++C)
           for (int j = 0; j < 4; ++j) {
-            if (k[j] < 0) continue;
-            double sacc = 0.0;
-            for (int m = 0; m < 4; ++m)
-              for (int l = 0; l < 4; ++l) sacc += T[ti.idx[j][m][l]] * pl[m] * pl[l];
-            fH[k[j]] += f * sacc;
+            const int k = hs_dof[4 * C + j];
+            if (k >= 0) fH[k] += sa[4 * C + j];
           }
-        }
-        ah4_apply(i, ph.data(), tmp.data());
-        for (int64_t k = 0; k < nH; ++k) fH[k] += f * (2.0 * t2 * tmp[k] + t2 * t2 * rhsv[k * N + i]);
-        symv(G, nH, ph.data(), tmp.data());
-        double g1 = dot(ph.data(), tmp.data(), nH);
-        double g2 = 0.0;
-        for (int64_t k = 0; k < nH; ++k) g2 += fb.ptW[k * N + i] * ph[k];
-        gsum += f * (g1 + 2.0 * t2 * g2 + t2 * t2 * fb.utW[i * N + i]);
+        const double* so = &hs_dofv[(int64_t)i * nH];
+        for (int64_t k = 0; k < nH; ++k) fH[k] += so[k];
+        gsum += hs_g[i];
       }
       const double fourpi = 4.0 * 3.14159265358979323846;
       std::vector<double> r1(nH);
